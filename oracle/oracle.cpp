@@ -1,0 +1,1014 @@
+// Plain, slow, single-threaded FP64 oracle of the SteepGS hot path.
+//
+// TEST INFRASTRUCTURE ONLY.  Nothing in the product path may call, link or
+// load this file; only the tests, the smoke check and the CPU-baseline leg of
+// the benchmark do.  It shares no code, header, table or constant with the
+// GPU library.
+//
+// What it computes (paper: "Steepest Descent Density Control for Compact 3D
+// Gaussian Splatting", arXiv 2505.05587):
+//   * the Gaussian primitive of Sec. 3, Eq. (sigma_3D): position p, covariance
+//     from a quaternion and per-axis scales, opacity o, SH colour;
+//   * its projection Pi (Sec. 3, Eq. (sigma_2D) and the footnote on Pi): the
+//     mean maps through the camera, the covariance through the local affine
+//     map P Sigma P^T;
+//   * the front-to-back alpha blend of Eq. (alpha_blend), nearest first, over
+//     the Gaussians whose screen-space footprint covers the pixel's tile;
+//   * the L1 photometric loss of Eq. (loss), one mean per view, summed over
+//     views;
+//   * exact derivatives of that loss.  The blend's own derivative w.r.t. each
+//     alpha is the product rule written out (suffix sums); every other
+//     derivative comes from forward-mode dual numbers, so no hand-derived
+//     chain rule appears here;
+//   * the splitting matrix of Theorem 1, S_i = sum over views and pixels of
+//     dL/dalpha_i(x) * Hessian_p alpha_i(x), with the Hessian of Sec. 4.4 and
+//     App. C.4 (P, Pi(Sigma) and colour held fixed w.r.t. p);
+//   * its eigen-decomposition by cyclic Jacobi rotations (the paper uses the
+//     closed trigonometric root formula of App. A.3; this oracle uses a
+//     different method on purpose);
+//   * Steepest Density Control (Theorem 2, Algorithm 1): split iff
+//     lambda_min < eps_split into p +/- eps * v_min, each child with half the
+//     parent's opacity, other attributes copied.
+//
+// Parameter layout, planar [F][n]: p(3), log-scale(3), quaternion (w,x,y,z)(4),
+// opacity logit(1), SH coefficients 3*(d+1)^2 (row 11 + 3*k + channel).
+//
+// Built with -O2 -ffp-contract=off so that every double operation rounds
+// exactly as written.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------------------
+// inputs
+
+struct Cam {
+  double R[9];  // world->camera rotation, row-major
+  double t[3];
+  double fx, fy, cx, cy;
+  int W, H, model;  // model 0: pinhole, 1: orthographic
+  int tiles_x, tiles_y;
+  int64_t tile_offset;   // global id of this view's first tile
+  int64_t pixel_offset;  // index of this view's first pixel in packed images
+};
+
+struct Opts {
+  int tw, th;
+  double near_z, radius_sigmas, dilation, guard;
+  double alpha_min, alpha_max, t_min;
+  double bg[3];
+};
+
+Opts read_opts(const double* o) {
+  Opts r;
+  r.tw = (int)o[0];
+  r.th = (int)o[1];
+  r.near_z = o[2];
+  r.radius_sigmas = o[3];
+  r.dilation = o[4];
+  r.guard = o[5];
+  r.alpha_min = o[6];
+  r.alpha_max = o[7];
+  r.t_min = o[8];
+  r.bg[0] = o[9];
+  r.bg[1] = o[10];
+  r.bg[2] = o[11];
+  return r;
+}
+
+std::vector<Cam> read_cams(const float* cf, const int32_t* ci, int V, const Opts& opt) {
+  std::vector<Cam> cams(V);
+  int64_t toff = 0, poff = 0;
+  for (int v = 0; v < V; ++v) {
+    Cam& c = cams[v];
+    for (int k = 0; k < 9; ++k) c.R[k] = cf[16 * v + k];
+    for (int k = 0; k < 3; ++k) c.t[k] = cf[16 * v + 9 + k];
+    c.fx = cf[16 * v + 12];
+    c.fy = cf[16 * v + 13];
+    c.cx = cf[16 * v + 14];
+    c.cy = cf[16 * v + 15];
+    c.W = ci[3 * v + 0];
+    c.H = ci[3 * v + 1];
+    c.model = ci[3 * v + 2];
+    c.tiles_x = (c.W + opt.tw - 1) / opt.tw;
+    c.tiles_y = (c.H + opt.th - 1) / opt.th;
+    c.tile_offset = toff;
+    c.pixel_offset = poff;
+    toff += (int64_t)c.tiles_x * c.tiles_y;
+    poff += (int64_t)c.W * c.H;
+  }
+  return cams;
+}
+
+int num_params(int deg) { return 11 + 3 * (deg + 1) * (deg + 1); }
+
+// ---------------------------------------------------------------------------
+// forward-mode dual numbers: value plus N partial derivatives
+
+template <int N>
+struct Dual {
+  double v;
+  double d[N];
+  Dual() : v(0.0) { std::memset(d, 0, sizeof(d)); }
+  Dual(double x) : v(x) { std::memset(d, 0, sizeof(d)); }  // NOLINT: constants promote
+};
+
+template <int N> Dual<N> operator+(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r(a.v + b.v);
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] + b.d[k];
+  return r;
+}
+template <int N> Dual<N> operator-(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r(a.v - b.v);
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] - b.d[k];
+  return r;
+}
+template <int N> Dual<N> operator-(const Dual<N>& a) {
+  Dual<N> r(-a.v);
+  for (int k = 0; k < N; ++k) r.d[k] = -a.d[k];
+  return r;
+}
+template <int N> Dual<N> operator*(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r(a.v * b.v);
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+  return r;
+}
+template <int N> Dual<N> operator/(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r(a.v / b.v);
+  for (int k = 0; k < N; ++k) r.d[k] = (a.d[k] * b.v - a.v * b.d[k]) / (b.v * b.v);
+  return r;
+}
+template <int N> Dual<N> operator+(const Dual<N>& a, double b) { return a + Dual<N>(b); }
+template <int N> Dual<N> operator+(double a, const Dual<N>& b) { return Dual<N>(a) + b; }
+template <int N> Dual<N> operator-(const Dual<N>& a, double b) { return a - Dual<N>(b); }
+template <int N> Dual<N> operator-(double a, const Dual<N>& b) { return Dual<N>(a) - b; }
+template <int N> Dual<N> operator*(const Dual<N>& a, double b) { return a * Dual<N>(b); }
+template <int N> Dual<N> operator*(double a, const Dual<N>& b) { return Dual<N>(a) * b; }
+template <int N> Dual<N> operator/(const Dual<N>& a, double b) { return a / Dual<N>(b); }
+template <int N> Dual<N> operator/(double a, const Dual<N>& b) { return Dual<N>(a) / b; }
+
+template <int N> Dual<N> exp(const Dual<N>& a) {
+  Dual<N> r(std::exp(a.v));
+  for (int k = 0; k < N; ++k) r.d[k] = r.v * a.d[k];
+  return r;
+}
+template <int N> Dual<N> sqrt(const Dual<N>& a) {
+  Dual<N> r(std::sqrt(a.v));
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] / (2.0 * r.v);
+  return r;
+}
+
+double val(double x) { return x; }
+template <int N> double val(const Dual<N>& x) { return x.v; }
+
+double sqrt_(double x) { return std::sqrt(x); }
+template <int N> Dual<N> sqrt_(const Dual<N>& x) { return sqrt(x); }
+double exp_(double x) { return std::exp(x); }
+template <int N> Dual<N> exp_(const Dual<N>& x) { return exp(x); }
+
+// clamp to [lo, hi]; a clamped value is a constant (zero derivative)
+template <class T> T clamp_(const T& x, double lo, double hi) {
+  if (val(x) < lo) return T(lo);
+  if (val(x) > hi) return T(hi);
+  return x;
+}
+
+// ---------------------------------------------------------------------------
+// real spherical harmonics from the associated Legendre functions
+// (Condon-Shortley phase), index k = l*l + l + m, m = -l..l.
+//   Y_l0  = K_l0 P_l^0(z)
+//   Y_lm  = sqrt(2) K_lm P_l^m(cos t) cos(m phi)   (m > 0)
+//   Y_l-m = sqrt(2) K_lm P_l^m(cos t) sin(m phi)   (m > 0)
+// With Q_l^m = P_l^m / (1 - z^2)^(m/2) and, on the unit sphere,
+// sin^m(t) e^{i m phi} = (x + i y)^m, every term is a polynomial in x, y, z.
+
+double factorial(int k) {
+  double f = 1.0;
+  for (int i = 2; i <= k; ++i) f *= i;
+  return f;
+}
+
+template <class T>
+void sh_basis(int deg, const T& x, const T& y, const T& z, T* Y) {
+  T Q[4][4];
+  for (int m = 0; m <= deg; ++m) {
+    double dfact = 1.0;  // (2m-1)!!
+    for (int i = 2 * m - 1; i > 1; i -= 2) dfact *= i;
+    Q[m][m] = T(((m % 2) ? -1.0 : 1.0) * dfact);
+    if (m + 1 <= deg) Q[m + 1][m] = z * (double)(2 * m + 1) * Q[m][m];
+    for (int l = m + 2; l <= deg; ++l)
+      Q[l][m] = ((double)(2 * l - 1) * z * Q[l - 1][m] - (double)(l + m - 1) * Q[l - 2][m]) /
+                (double)(l - m);
+  }
+  T re[4], im[4];
+  re[0] = T(1.0);
+  im[0] = T(0.0);
+  for (int m = 1; m <= deg; ++m) {
+    re[m] = re[m - 1] * x - im[m - 1] * y;
+    im[m] = re[m - 1] * y + im[m - 1] * x;
+  }
+  for (int l = 0; l <= deg; ++l) {
+    for (int m = 0; m <= l; ++m) {
+      double K = std::sqrt((2.0 * l + 1.0) / (4.0 * kPi) * factorial(l - m) / factorial(l + m));
+      if (m == 0) {
+        Y[l * l + l] = K * Q[l][0];
+      } else {
+        Y[l * l + l + m] = std::sqrt(2.0) * K * Q[l][m] * re[m];
+        Y[l * l + l - m] = std::sqrt(2.0) * K * Q[l][m] * im[m];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// one Gaussian through one camera
+
+template <class T>
+struct Proj {
+  bool visible = false;
+  T mx, my;          // projected mean Pi(p), pixels
+  T A00, A01, A11;   // conic: inverse of the 2D covariance Pi(Sigma) (+ dilation)
+  T o;               // opacity
+  T rgb[3];          // view-dependent colour, clamped at 0
+  double depth = 0;  // camera-space z
+  double rgb_raw[3] = {0, 0, 0};
+  int rect[4] = {0, 0, -1, -1};  // tile x0, y0, x1, y1 (inclusive)
+};
+
+template <class T>
+void project(const T* th, int deg, const Cam& cam, const Opts& opt, Proj<T>& out) {
+  out.visible = false;
+  // covariance from quaternion (w,x,y,z) and scales: Sigma = R diag(s^2) R^T
+  T qn = sqrt_(th[6] * th[6] + th[7] * th[7] + th[8] * th[8] + th[9] * th[9]);
+  T w = th[6] / qn, x = th[7] / qn, y = th[8] / qn, z = th[9] / qn;
+  T Rq[3][3] = {{1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y)},
+                {2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x)},
+                {2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)}};
+  T s2[3];
+  for (int k = 0; k < 3; ++k) {
+    T s = exp_(th[3 + k]);
+    s2[k] = s * s;
+  }
+  T Sig[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) Sig[a][b] = Rq[a][0] * s2[0] * Rq[b][0] + Rq[a][1] * s2[1] * Rq[b][1] + Rq[a][2] * s2[2] * Rq[b][2];
+  out.o = 1.0 / (1.0 + exp_(-th[10]));
+
+  // camera space
+  T pc[3];
+  for (int r = 0; r < 3; ++r)
+    pc[r] = cam.R[3 * r + 0] * th[0] + cam.R[3 * r + 1] * th[1] + cam.R[3 * r + 2] * th[2] + cam.t[r];
+  out.depth = val(pc[2]);
+  if (!(out.depth > opt.near_z)) return;
+
+  // projected mean and the local affine map J (pinhole: Jacobian of the
+  // perspective division at the frustum-guarded point)
+  T J[2][3];
+  if (cam.model == 0) {
+    out.mx = cam.fx * (pc[0] / pc[2]) + cam.cx;
+    out.my = cam.fy * (pc[1] / pc[2]) + cam.cy;
+    T gx = pc[0] / pc[2], gy = pc[1] / pc[2];
+    if (opt.guard > 0.0) {
+      double limx = opt.guard * (0.5 * cam.W / cam.fx);
+      double limy = opt.guard * (0.5 * cam.H / cam.fy);
+      gx = clamp_(gx, -limx, limx);
+      gy = clamp_(gy, -limy, limy);
+    }
+    J[0][0] = cam.fx / pc[2];
+    J[0][1] = T(0.0);
+    J[0][2] = -(cam.fx * gx) / pc[2];
+    J[1][0] = T(0.0);
+    J[1][1] = cam.fy / pc[2];
+    J[1][2] = -(cam.fy * gy) / pc[2];
+  } else {
+    out.mx = cam.fx * pc[0] + cam.cx;
+    out.my = cam.fy * pc[1] + cam.cy;
+    J[0][0] = T(cam.fx);
+    J[0][1] = T(0.0);
+    J[0][2] = T(0.0);
+    J[1][0] = T(0.0);
+    J[1][1] = T(cam.fy);
+    J[1][2] = T(0.0);
+  }
+  // P = J W (2x3), Pi(Sigma) = P Sigma P^T + dilation * I
+  T P[2][3];
+  for (int a = 0; a < 2; ++a)
+    for (int c = 0; c < 3; ++c) P[a][c] = J[a][0] * cam.R[0 + c] + J[a][1] * cam.R[3 + c] + J[a][2] * cam.R[6 + c];
+  T S2[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      T acc(0.0);
+      for (int c = 0; c < 3; ++c)
+        for (int d = 0; d < 3; ++d) acc = acc + P[a][c] * Sig[c][d] * P[b][d];
+      S2[a][b] = acc;
+    }
+  S2[0][0] = S2[0][0] + opt.dilation;
+  S2[1][1] = S2[1][1] + opt.dilation;
+  T det = S2[0][0] * S2[1][1] - S2[0][1] * S2[1][0];
+  if (!(val(det) > 0.0)) return;
+  out.A00 = S2[1][1] / det;
+  out.A01 = -S2[0][1] / det;
+  out.A11 = S2[0][0] / det;
+
+  // footprint: radius_sigmas standard deviations along the major axis, in
+  // whole pixels; tiles whose pixel span meets [m - r, m + r]
+  double a = val(S2[0][0]), b = val(S2[0][1]), c = val(S2[1][1]);
+  double half = 0.5 * (a - c);
+  double lam = 0.5 * (a + c) + std::sqrt(half * half + b * b);
+  double r = std::ceil(opt.radius_sigmas * std::sqrt(lam));
+  double mxv = val(out.mx), myv = val(out.my);
+  double x0 = std::floor((mxv - r) / opt.tw), x1 = std::floor((mxv + r) / opt.tw);
+  double y0 = std::floor((myv - r) / opt.th), y1 = std::floor((myv + r) / opt.th);
+  x0 = std::max(x0, 0.0);
+  y0 = std::max(y0, 0.0);
+  x1 = std::min(x1, (double)(cam.tiles_x - 1));
+  y1 = std::min(y1, (double)(cam.tiles_y - 1));
+  if (x0 > x1 || y0 > y1) return;
+  out.rect[0] = (int)x0;
+  out.rect[1] = (int)y0;
+  out.rect[2] = (int)x1;
+  out.rect[3] = (int)y1;
+
+  // colour: SH evaluated at the unit direction from the camera centre
+  double campos[3];
+  for (int k = 0; k < 3; ++k) campos[k] = -(cam.R[0 + k] * cam.t[0] + cam.R[3 + k] * cam.t[1] + cam.R[6 + k] * cam.t[2]);
+  T dx = th[0] - campos[0], dy = th[1] - campos[1], dz = th[2] - campos[2];
+  T dn = sqrt_(dx * dx + dy * dy + dz * dz);
+  dx = dx / dn;
+  dy = dy / dn;
+  dz = dz / dn;
+  T Y[16];
+  sh_basis(deg, dx, dy, dz, Y);
+  int nb = (deg + 1) * (deg + 1);
+  for (int ch = 0; ch < 3; ++ch) {
+    T acc(0.0);
+    for (int k = 0; k < nb; ++k) acc = acc + th[11 + 3 * k + ch] * Y[k];
+    acc = acc + 0.5;
+    out.rgb_raw[ch] = val(acc);
+    out.rgb[ch] = (val(acc) < 0.0) ? T(0.0) : acc;
+  }
+  out.visible = true;
+}
+
+// alpha of a projected Gaussian at pixel (u,v) before the alpha_max clamp
+template <class T>
+T alpha_raw(const T& mx, const T& my, const T& A00, const T& A01, const T& A11, const T& o, double u, double v) {
+  T dx = u - mx, dy = v - my;
+  T power = -0.5 * (A00 * dx * dx + 2.0 * A01 * dx * dy + A11 * dy * dy);
+  return o * exp_(power);
+}
+
+// Hessian of alpha w.r.t. the projected mean (Sec. 4.4, App. C.4):
+//   alpha * (A d d^T A - A),  d = x - Pi(p)
+void alpha_hessian_mu(double mx, double my, double A00, double A01, double A11, double o, double u, double v,
+                      double H[3]) {
+  double a = alpha_raw(mx, my, A00, A01, A11, o, u, v);
+  double dx = u - mx, dy = v - my;
+  double Adx = A00 * dx + A01 * dy, Ady = A01 * dx + A11 * dy;
+  H[0] = a * (Adx * Adx - A00);
+  H[1] = a * (Adx * Ady - A01);
+  H[2] = a * (Ady * Ady - A11);
+}
+
+// ---------------------------------------------------------------------------
+// one view: projected records and per-tile depth-ordered lists
+
+struct View {
+  const Cam* cam;
+  const Opts* opt;
+  int n;
+  std::vector<Proj<double>> rec;
+  std::vector<std::vector<int>> tiles;  // Gaussian ids per tile, ordered by (depth_f32 bits, id)
+};
+
+uint32_t depth_bits(double z) {
+  float f = (float)z;  // round to nearest even
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  return u;
+}
+
+void load_theta(const float* params, int64_t n, int deg, int64_t i, double* th) {
+  int F = num_params(deg);
+  for (int f = 0; f < F; ++f) th[f] = params[(int64_t)f * n + i];
+}
+
+void build_view(const float* params, int64_t n, int deg, const Cam& cam, const Opts& opt, View& view) {
+  view.cam = &cam;
+  view.opt = &opt;
+  view.n = (int)n;
+  view.rec.assign(n, Proj<double>());
+  double th[59];
+  for (int64_t i = 0; i < n; ++i) {
+    load_theta(params, n, deg, i, th);
+    project(th, deg, cam, opt, view.rec[i]);
+  }
+  view.tiles.assign((size_t)cam.tiles_x * cam.tiles_y, std::vector<int>());
+  for (int64_t i = 0; i < n; ++i) {
+    const Proj<double>& p = view.rec[i];
+    if (!p.visible) continue;
+    for (int ty = p.rect[1]; ty <= p.rect[3]; ++ty)
+      for (int tx = p.rect[0]; tx <= p.rect[2]; ++tx) view.tiles[(size_t)ty * cam.tiles_x + tx].push_back((int)i);
+  }
+  for (auto& lst : view.tiles)
+    std::stable_sort(lst.begin(), lst.end(), [&](int a, int b) {
+      return depth_bits(view.rec[a].depth) < depth_bits(view.rec[b].depth);
+    });
+}
+
+// ---------------------------------------------------------------------------
+// per-pixel blend (Eq. alpha_blend, front to back)
+
+struct Contrib {
+  int g;
+  double a, T;
+  bool clamped;
+};
+
+struct Pixel {
+  double C[3];
+  double T_final;
+  std::vector<Contrib> list;
+  int listed;  // how many entries of the tile list were examined (incl. the stopping one)
+  bool ambig;  // a cut-off decision within the ambiguity band
+};
+
+constexpr double kAlphaBand = 1e-5;  // relative band around alpha_min / alpha_max
+constexpr double kTBand = 1e-4;      // relative band around t_min
+
+void blend_pixel(const View& view, int u, int v, Pixel& px) {
+  const Cam& cam = *view.cam;
+  const Opts& opt = *view.opt;
+  const std::vector<int>& lst = view.tiles[(size_t)(v / opt.th) * cam.tiles_x + (u / opt.tw)];
+  double T = 1.0;
+  px.C[0] = px.C[1] = px.C[2] = 0.0;
+  px.list.clear();
+  px.ambig = false;
+  px.listed = (int)lst.size();
+  for (size_t j = 0; j < lst.size(); ++j) {
+    const Proj<double>& g = view.rec[lst[j]];
+    double a = alpha_raw(g.mx, g.my, g.A00, g.A01, g.A11, g.o, (double)u, (double)v);
+    bool clamped = false;
+    if (opt.alpha_max < 1.0 && std::fabs(a - opt.alpha_max) <= kAlphaBand * opt.alpha_max) px.ambig = true;
+    if (a > opt.alpha_max) {
+      a = opt.alpha_max;
+      clamped = true;
+    }
+    if (opt.alpha_min > 0.0 && std::fabs(a - opt.alpha_min) <= kAlphaBand * opt.alpha_min) px.ambig = true;
+    if (a < opt.alpha_min) continue;
+    double Tn = T * (1.0 - a);
+    if (opt.t_min > 0.0 && std::fabs(Tn - opt.t_min) <= kTBand * opt.t_min) px.ambig = true;
+    if (Tn < opt.t_min) {
+      px.listed = (int)j + 1;
+      break;
+    }
+    for (int ch = 0; ch < 3; ++ch) px.C[ch] += g.rgb[ch] * a * T;
+    px.list.push_back({lst[j], a, T, clamped});
+    T = Tn;
+  }
+  for (int ch = 0; ch < 3; ++ch) px.C[ch] += T * opt.bg[ch];
+  px.T_final = T;
+}
+
+// per (Gaussian, view) accumulators of the pixel backward
+struct Grad2D {
+  double g[9];  // dL/d(mx, my, A00, A01, A11, o, r, g, b)
+  double H[3];  // sum_x dL/dalpha * Hessian_mu alpha: xx, xy, yy
+};
+
+// Exact reverse sweep of one pixel given dL/dC.  Accumulates into acc[g]
+// for every contributing Gaussian g with want[g] set (want == nullptr: all).
+void backward_pixel(const View& view, int u, int v, const Pixel& px, const double dLdC[3],
+                    std::vector<Grad2D>& acc, const std::vector<uint8_t>* want) {
+  const Opts& opt = *view.opt;
+  double R[3];  // sum of the colour behind the current entry, background included
+  for (int ch = 0; ch < 3; ++ch) R[ch] = px.T_final * opt.bg[ch];
+  for (int k = (int)px.list.size() - 1; k >= 0; --k) {
+    const Contrib& c = px.list[k];
+    const Proj<double>& g = view.rec[c.g];
+    double dLda = 0.0;
+    for (int ch = 0; ch < 3; ++ch) dLda += dLdC[ch] * (g.rgb[ch] * c.T - R[ch] / (1.0 - c.a));
+    for (int ch = 0; ch < 3; ++ch) R[ch] += g.rgb[ch] * c.a * c.T;
+    if (want && !(*want)[c.g]) continue;
+    Grad2D& A = acc[c.g];
+    for (int ch = 0; ch < 3; ++ch) A.g[6 + ch] += c.a * c.T * dLdC[ch];
+    if (c.clamped) continue;  // alpha = alpha_max: constant in (mean, conic, opacity)
+    Dual<6> in[6];
+    double vals[6] = {g.mx, g.my, g.A00, g.A01, g.A11, g.o};
+    for (int k2 = 0; k2 < 6; ++k2) {
+      in[k2] = Dual<6>(vals[k2]);
+      in[k2].d[k2] = 1.0;
+    }
+    Dual<6> a = alpha_raw(in[0], in[1], in[2], in[3], in[4], in[5], (double)u, (double)v);
+    for (int k2 = 0; k2 < 6; ++k2) A.g[k2] += dLda * a.d[k2];
+    double H[3];
+    alpha_hessian_mu(g.mx, g.my, g.A00, g.A01, g.A11, g.o, (double)u, (double)v, H);
+    for (int k2 = 0; k2 < 3; ++k2) A.H[k2] += dLda * H[k2];
+  }
+}
+
+// Jacobian of the 9 projected quantities w.r.t. the F parameters of Gaussian i
+template <int F>
+bool jacobian(const float* params, int64_t n, int deg, int64_t i, const Cam& cam, const Opts& opt, double J[9][59]) {
+  double th[59];
+  load_theta(params, n, deg, i, th);
+  Dual<F> td[F];
+  for (int f = 0; f < F; ++f) {
+    td[f] = Dual<F>(th[f]);
+    td[f].d[f] = 1.0;
+  }
+  Proj<Dual<F>> pr;
+  project(td, deg, cam, opt, pr);
+  if (!pr.visible) return false;
+  const Dual<F>* outs[9] = {&pr.mx, &pr.my, &pr.A00, &pr.A01, &pr.A11, &pr.o, &pr.rgb[0], &pr.rgb[1], &pr.rgb[2]};
+  for (int r = 0; r < 9; ++r)
+    for (int f = 0; f < F; ++f) J[r][f] = outs[r]->d[f];
+  return true;
+}
+
+bool jacobian_any(const float* params, int64_t n, int deg, int64_t i, const Cam& cam, const Opts& opt, double J[9][59]) {
+  switch (deg) {
+    case 0: return jacobian<14>(params, n, deg, i, cam, opt, J);
+    case 1: return jacobian<23>(params, n, deg, i, cam, opt, J);
+    case 2: return jacobian<38>(params, n, deg, i, cam, opt, J);
+    default: return jacobian<59>(params, n, deg, i, cam, opt, J);
+  }
+}
+
+// lift the per-view accumulators of Gaussian i to parameter space:
+// grads += J^T g2d, S += P^T H P with P = d Pi(p) / dp (rows 0-1, columns 0-2)
+void lift(const float* params, int64_t n, int deg, int64_t i, const Cam& cam, const Opts& opt, const Grad2D& acc,
+          double* grad_i /*[F] stride gstride*/, int64_t gstride, double* S_i /*[9] stride sstride*/, int64_t sstride) {
+  double J[9][59];
+  if (!jacobian_any(params, n, deg, i, cam, opt, J)) return;
+  int F = num_params(deg);
+  for (int f = 0; f < F; ++f) {
+    double s = 0.0;
+    for (int r = 0; r < 9; ++r) s += acc.g[r] * J[r][f];
+    grad_i[f * gstride] += s;
+  }
+  double H[2][2] = {{acc.H[0], acc.H[1]}, {acc.H[1], acc.H[2]}};
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      double s = 0.0;
+      for (int x = 0; x < 2; ++x)
+        for (int y = 0; y < 2; ++y) s += J[x][a] * H[x][y] * J[y][b];
+      S_i[(3 * a + b) * sstride] += s;
+    }
+}
+
+double sgn(double x) { return (x > 0.0) - (x < 0.0); }
+
+// ---------------------------------------------------------------------------
+// symmetric 3x3 eigen-decomposition by cyclic Jacobi rotations
+
+void jacobi_eigh(const double Ain[9], double lam[3], double vec[9] /* columns = eigenvectors */) {
+  double A[3][3], Vm[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      A[a][b] = 0.5 * (Ain[3 * a + b] + Ain[3 * b + a]);
+      Vm[a][b] = (a == b) ? 1.0 : 0.0;
+    }
+  double norm = 0.0;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) norm += A[a][b] * A[a][b];
+  norm = std::sqrt(norm);
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = std::sqrt(2.0 * (A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2]));
+    if (off <= 1e-15 * norm || off == 0.0) break;
+    const int pairs[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    for (auto& pq : pairs) {
+      int p = pq[0], q = pq[1];
+      if (A[p][q] == 0.0) continue;
+      // rotation angle that zeroes A[p][q]
+      double theta = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+      double t = (theta >= 0.0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+      double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+      double G[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+      G[p][p] = c;
+      G[q][q] = c;
+      G[p][q] = s;
+      G[q][p] = -s;
+      double B[3][3], C[3][3];
+      for (int a = 0; a < 3; ++a)  // B = G^T A
+        for (int b = 0; b < 3; ++b) B[a][b] = G[0][a] * A[0][b] + G[1][a] * A[1][b] + G[2][a] * A[2][b];
+      for (int a = 0; a < 3; ++a)  // A = B G
+        for (int b = 0; b < 3; ++b) A[a][b] = B[a][0] * G[0][b] + B[a][1] * G[1][b] + B[a][2] * G[2][b];
+      for (int a = 0; a < 3; ++a)  // V = V G
+        for (int b = 0; b < 3; ++b) C[a][b] = Vm[a][0] * G[0][b] + Vm[a][1] * G[1][b] + Vm[a][2] * G[2][b];
+      std::memcpy(Vm, C, sizeof(C));
+    }
+  }
+  int idx[3] = {0, 1, 2};
+  std::sort(idx, idx + 3, [&](int a, int b) { return A[a][a] < A[b][b]; });
+  for (int k = 0; k < 3; ++k) {
+    lam[k] = A[idx[k]][idx[k]];
+    double col[3] = {Vm[0][idx[k]], Vm[1][idx[k]], Vm[2][idx[k]]};
+    // canonical sign: the largest-magnitude component is positive (ties: lowest index)
+    int big = 0;
+    for (int r = 1; r < 3; ++r)
+      if (std::fabs(col[r]) > std::fabs(col[big])) big = r;
+    double sg = col[big] < 0.0 ? -1.0 : 1.0;
+    for (int r = 0; r < 3; ++r) vec[3 * r + k] = sg * col[r];
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+// C interface (ctypes).  Arrays are plain host memory; shapes in comments.
+// cam_f: [V][16] = R(9) t(3) fx fy cx cy; cam_i: [V][3] = W H model;
+// opts: [12] = tile_w tile_h near radius_sigmas dilation guard alpha_min
+//              alpha_max t_min bg0 bg1 bg2.
+// Returns 0 on success, nonzero on bad arguments.
+
+extern "C" {
+
+int orc_num_params(int deg) { return num_params(deg); }
+
+// Per (view, Gaussian) projected record, rows of rec[V*n][12]:
+// mx my A00 A01 A11 o r g b depth raw_r raw_g ... (raw_b in rec2)
+// rect[V*n][4] (x0 y0 x1 y1 inclusive), tiles[V*n], depth_bits[V*n], visible[V*n]
+int orc_project(const float* params, int64_t n, int deg, const float* cam_f, const int32_t* cam_i, int V,
+                const double* opts, double* rec /*[V*n][13]*/, int32_t* rect /*[V*n][4]*/,
+                uint32_t* tiles /*[V*n]*/, uint32_t* dbits /*[V*n]*/, uint8_t* visible /*[V*n]*/) {
+  if (n < 0 || V <= 0 || deg < 0 || deg > 3) return 1;
+  Opts opt = read_opts(opts);
+  std::vector<Cam> cams = read_cams(cam_f, cam_i, V, opt);
+  double th[59];
+  for (int v = 0; v < V; ++v)
+    for (int64_t i = 0; i < n; ++i) {
+      load_theta(params, n, deg, i, th);
+      Proj<double> p;
+      project(th, deg, cams[v], opt, p);
+      int64_t r = (int64_t)v * n + i;
+      double* o = rec + 13 * r;
+      o[0] = p.mx; o[1] = p.my; o[2] = p.A00; o[3] = p.A01; o[4] = p.A11; o[5] = p.o;
+      o[6] = p.rgb[0]; o[7] = p.rgb[1]; o[8] = p.rgb[2]; o[9] = p.depth;
+      o[10] = p.rgb_raw[0]; o[11] = p.rgb_raw[1]; o[12] = p.rgb_raw[2];
+      for (int k = 0; k < 4; ++k) rect[4 * r + k] = p.rect[k];
+      visible[r] = p.visible ? 1 : 0;
+      tiles[r] = p.visible ? (uint32_t)((p.rect[2] - p.rect[0] + 1) * (p.rect[3] - p.rect[1] + 1)) : 0u;
+      dbits[r] = p.visible ? depth_bits(p.depth) : 0u;
+    }
+  return 0;
+}
+
+// Instance list: one (key, value) per (visible Gaussian, overlapped tile),
+// emitted view by view, Gaussian by Gaussian, tiles row-major;
+// key = global_tile << 32 | depth_f32 bits, value = v*n + i; stable sort by
+// key; ranges[t] = [begin, end) of tile t (0,0 if empty).
+// Call with keys == nullptr to get the count in *count.
+int orc_sort(const float* params, int64_t n, int deg, const float* cam_f, const int32_t* cam_i, int V,
+             const double* opts, uint64_t* count, uint64_t* keys, uint32_t* vals, uint32_t* ranges /*[Tt][2]*/) {
+  if (n < 0 || V <= 0 || deg < 0 || deg > 3) return 1;
+  Opts opt = read_opts(opts);
+  std::vector<Cam> cams = read_cams(cam_f, cam_i, V, opt);
+  std::vector<std::pair<uint64_t, uint32_t>> inst;
+  double th[59];
+  for (int v = 0; v < V; ++v)
+    for (int64_t i = 0; i < n; ++i) {
+      load_theta(params, n, deg, i, th);
+      Proj<double> p;
+      project(th, deg, cams[v], opt, p);
+      if (!p.visible) continue;
+      uint64_t db = depth_bits(p.depth);
+      for (int ty = p.rect[1]; ty <= p.rect[3]; ++ty)
+        for (int tx = p.rect[0]; tx <= p.rect[2]; ++tx) {
+          uint64_t tile = (uint64_t)cams[v].tile_offset + (uint64_t)ty * cams[v].tiles_x + tx;
+          inst.push_back({(tile << 32) | db, (uint32_t)((int64_t)v * n + i)});
+        }
+    }
+  *count = inst.size();
+  if (!keys) return 0;
+  std::stable_sort(inst.begin(), inst.end(),
+                   [](const std::pair<uint64_t, uint32_t>& a, const std::pair<uint64_t, uint32_t>& b) { return a.first < b.first; });
+  int64_t Tt = cams.back().tile_offset + (int64_t)cams.back().tiles_x * cams.back().tiles_y;
+  for (int64_t t = 0; t < 2 * Tt; ++t) ranges[t] = 0;
+  for (size_t k = 0; k < inst.size(); ++k) {
+    keys[k] = inst[k].first;
+    vals[k] = inst[k].second;
+    uint64_t t = inst[k].first >> 32;
+    if (k == 0 || (inst[k - 1].first >> 32) != t) ranges[2 * t] = (uint32_t)k;
+    if (k + 1 == inst.size() || (inst[k + 1].first >> 32) != t) ranges[2 * t + 1] = (uint32_t)(k + 1);
+  }
+  return 0;
+}
+
+// Full forward + backward.  Outputs (nullable unless stated):
+//   image [packed 3*Px], T_final [Px], n_used [Px] (contributing count),
+//   pix_ambig [Px], loss [V] (needs target), grads [F][n] (+=), S [9][n] (+=),
+//   g2d [V*n][9] and H2d [V*n][3] per-view accumulators, gauss_ambig [n].
+// sign_band: |C - target| below it marks the pixel ambiguous.
+int orc_forward_backward(const float* params, int64_t n, int deg, const float* cam_f, const int32_t* cam_i, int V,
+                         const double* opts, const float* target, double sign_band, double* image, double* T_final,
+                         int32_t* n_used, uint8_t* pix_ambig, double* loss, double* grads, double* S, double* g2d,
+                         double* H2d, uint8_t* gauss_ambig) {
+  if (n < 0 || V <= 0 || deg < 0 || deg > 3) return 1;
+  Opts opt = read_opts(opts);
+  std::vector<Cam> cams = read_cams(cam_f, cam_i, V, opt);
+  int F = num_params(deg);
+  if (gauss_ambig)
+    for (int64_t i = 0; i < n; ++i) gauss_ambig[i] = 0;
+  for (int v = 0; v < V; ++v) {
+    const Cam& cam = cams[v];
+    View view;
+    build_view(params, n, deg, cam, opt, view);
+    std::vector<Grad2D> acc(n);
+    for (auto& a : acc) std::memset(&a, 0, sizeof(a));
+    double inv = 1.0 / (3.0 * cam.W * cam.H);
+    double lsum = 0.0;
+    Pixel px;
+    for (int y = 0; y < cam.H; ++y)
+      for (int x = 0; x < cam.W; ++x) {
+        int64_t pid = cam.pixel_offset + (int64_t)y * cam.W + x;
+        blend_pixel(view, x, y, px);
+        if (image)
+          for (int ch = 0; ch < 3; ++ch) image[3 * cam.pixel_offset + (int64_t)ch * cam.W * cam.H + (int64_t)y * cam.W + x] = px.C[ch];
+        if (T_final) T_final[pid] = px.T_final;
+        if (n_used) n_used[pid] = (int32_t)px.list.size();
+        bool amb = px.ambig;
+        if (!target) {
+          if (pix_ambig) pix_ambig[pid] = amb;
+          continue;
+        }
+        double dLdC[3];
+        for (int ch = 0; ch < 3; ++ch) {
+          double tg = target[3 * cam.pixel_offset + (int64_t)ch * cam.W * cam.H + (int64_t)y * cam.W + x];
+          double diff = px.C[ch] - tg;
+          lsum += std::fabs(diff);
+          dLdC[ch] = sgn(diff) * inv;
+          if (std::fabs(diff) < sign_band) amb = true;
+        }
+        if (pix_ambig) pix_ambig[pid] = amb;
+        if (amb && gauss_ambig) {
+          const std::vector<int>& lst = view.tiles[(size_t)(y / opt.th) * cam.tiles_x + (x / opt.tw)];
+          for (int j = 0; j < px.listed; ++j) gauss_ambig[lst[j]] = 1;
+        }
+        backward_pixel(view, x, y, px, dLdC, acc, nullptr);
+      }
+    if (!target) continue;
+    if (loss) loss[v] = lsum * inv;
+    for (int64_t i = 0; i < n; ++i) {
+      int64_t r = (int64_t)v * n + i;
+      if (g2d)
+        for (int k = 0; k < 9; ++k) g2d[9 * r + k] = acc[i].g[k];
+      if (H2d)
+        for (int k = 0; k < 3; ++k) H2d[3 * r + k] = acc[i].H[k];
+      if (!view.rec[i].visible) continue;
+      bool any = false;
+      for (int k = 0; k < 9; ++k) any |= acc[i].g[k] != 0.0;
+      if (!any || (!grads && !S)) continue;
+      static thread_local std::vector<double> gtmp, stmp;
+      gtmp.assign(F, 0.0);
+      stmp.assign(9, 0.0);
+      lift(params, n, deg, i, cam, opt, acc[i], gtmp.data(), 1, stmp.data(), 1);
+      if (grads)
+        for (int f = 0; f < F; ++f) grads[(int64_t)f * n + i] += gtmp[f];
+      if (S)
+        for (int k = 0; k < 9; ++k) S[(int64_t)k * n + i] += stmp[k];
+    }
+  }
+  (void)F;
+  return 0;
+}
+
+// Loss only (sum over views of the per-view mean L1), for finite differences.
+double orc_loss(const float* params, int64_t n, int deg, const float* cam_f, const int32_t* cam_i, int V,
+                const double* opts, const float* target) {
+  Opts opt = read_opts(opts);
+  std::vector<Cam> cams = read_cams(cam_f, cam_i, V, opt);
+  double total = 0.0;
+  for (int v = 0; v < V; ++v) {
+    const Cam& cam = cams[v];
+    View view;
+    build_view(params, n, deg, cam, opt, view);
+    Pixel px;
+    double lsum = 0.0;
+    for (int y = 0; y < cam.H; ++y)
+      for (int x = 0; x < cam.W; ++x) {
+        blend_pixel(view, x, y, px);
+        for (int ch = 0; ch < 3; ++ch)
+          lsum += std::fabs(px.C[ch] - target[3 * cam.pixel_offset + (int64_t)ch * cam.W * cam.H + (int64_t)y * cam.W + x]);
+      }
+    total += lsum / (3.0 * cam.W * cam.H);
+  }
+  return total;
+}
+
+// Colour and final transmittance of sampled pixels (global packed pixel ids).
+int orc_render_pixels(const float* params, int64_t n, int deg, const float* cam_f, const int32_t* cam_i, int V,
+                      const double* opts, const int64_t* pix, int64_t npix, double* rgb /*[npix][3]*/,
+                      double* T_final, uint8_t* ambig) {
+  Opts opt = read_opts(opts);
+  std::vector<Cam> cams = read_cams(cam_f, cam_i, V, opt);
+  for (int v = 0; v < V; ++v) {
+    const Cam& cam = cams[v];
+    bool any = false;
+    for (int64_t k = 0; k < npix; ++k) any |= (pix[k] >= cam.pixel_offset && pix[k] < cam.pixel_offset + (int64_t)cam.W * cam.H);
+    if (!any) continue;
+    View view;
+    build_view(params, n, deg, cam, opt, view);
+    Pixel px;
+    for (int64_t k = 0; k < npix; ++k) {
+      int64_t local = pix[k] - cam.pixel_offset;
+      if (local < 0 || local >= (int64_t)cam.W * cam.H) continue;
+      int x = (int)(local % cam.W), y = (int)(local / cam.W);
+      blend_pixel(view, x, y, px);
+      for (int ch = 0; ch < 3; ++ch) rgb[3 * k + ch] = px.C[ch];
+      if (T_final) T_final[k] = px.T_final;
+      if (ambig) ambig[k] = px.ambig;
+    }
+  }
+  return 0;
+}
+
+// Gradients and splitting matrices of sampled Gaussians only: every pixel of
+// every tile the sampled Gaussian touches is blended in full, its L1
+// gradient formed, and the reverse sweep credited to the sampled Gaussians.
+// grads [ns][F], S [ns][9], ambig [ns].
+int orc_grads_sampled(const float* params, int64_t n, int deg, const float* cam_f, const int32_t* cam_i, int V,
+                      const double* opts, const float* target, double sign_band, const int64_t* gids, int64_t ns,
+                      double* grads, double* S, uint8_t* ambig) {
+  Opts opt = read_opts(opts);
+  std::vector<Cam> cams = read_cams(cam_f, cam_i, V, opt);
+  int F = num_params(deg);
+  std::vector<uint8_t> want(n, 0);
+  for (int64_t k = 0; k < ns; ++k) want[gids[k]] = 1;
+  for (int64_t k = 0; k < ns; ++k) {
+    ambig[k] = 0;
+    for (int f = 0; f < F; ++f) grads[k * F + f] = 0.0;
+    for (int q = 0; q < 9; ++q) S[k * 9 + q] = 0.0;
+  }
+  std::vector<uint8_t> gamb(n, 0);
+  for (int v = 0; v < V; ++v) {
+    const Cam& cam = cams[v];
+    View view;
+    build_view(params, n, deg, cam, opt, view);
+    std::vector<uint8_t> tile_needed((size_t)cam.tiles_x * cam.tiles_y, 0);
+    for (int64_t k = 0; k < ns; ++k) {
+      const Proj<double>& p = view.rec[gids[k]];
+      if (!p.visible) continue;
+      for (int ty = p.rect[1]; ty <= p.rect[3]; ++ty)
+        for (int tx = p.rect[0]; tx <= p.rect[2]; ++tx) tile_needed[(size_t)ty * cam.tiles_x + tx] = 1;
+    }
+    std::vector<Grad2D> acc(n);
+    for (auto& a : acc) std::memset(&a, 0, sizeof(a));
+    double inv = 1.0 / (3.0 * cam.W * cam.H);
+    Pixel px;
+    for (int ty = 0; ty < cam.tiles_y; ++ty)
+      for (int tx = 0; tx < cam.tiles_x; ++tx) {
+        if (!tile_needed[(size_t)ty * cam.tiles_x + tx]) continue;
+        for (int y = ty * opt.th; y < std::min(cam.H, (ty + 1) * opt.th); ++y)
+          for (int x = tx * opt.tw; x < std::min(cam.W, (tx + 1) * opt.tw); ++x) {
+            blend_pixel(view, x, y, px);
+            double dLdC[3];
+            bool amb = px.ambig;
+            for (int ch = 0; ch < 3; ++ch) {
+              double tg = target[3 * cam.pixel_offset + (int64_t)ch * cam.W * cam.H + (int64_t)y * cam.W + x];
+              double diff = px.C[ch] - tg;
+              dLdC[ch] = sgn(diff) * inv;
+              if (std::fabs(diff) < sign_band) amb = true;
+            }
+            if (amb) {
+              const std::vector<int>& lst = view.tiles[(size_t)ty * cam.tiles_x + tx];
+              for (int j = 0; j < px.listed; ++j) gamb[lst[j]] = 1;
+            }
+            backward_pixel(view, x, y, px, dLdC, acc, &want);
+          }
+      }
+    for (int64_t k = 0; k < ns; ++k) {
+      int64_t i = gids[k];
+      if (!view.rec[i].visible) continue;
+      lift(params, n, deg, i, cam, opt, acc[i], grads + k * F, 1, S + k * 9, 1);
+    }
+  }
+  for (int64_t k = 0; k < ns; ++k) ambig[k] = gamb[gids[k]];
+  return 0;
+}
+
+// Loss after splitting Gaussian i into two offspring at p +/- eps*delta with
+// weights 1/2 that share the parent's slot in every blend (the replacement of
+// sigma_i by sum_j w_j sigma_j of Sec. 4.1); other parameters unchanged.
+double orc_loss_merged_split(const float* params, int64_t n, int deg, const float* cam_f, const int32_t* cam_i, int V,
+                             const double* opts, const float* target, int64_t gi, const double* delta, double eps) {
+  Opts opt = read_opts(opts);
+  std::vector<Cam> cams = read_cams(cam_f, cam_i, V, opt);
+  double total = 0.0;
+  double th[59], thp[59], thm[59];
+  load_theta(params, n, deg, gi, th);
+  std::memcpy(thp, th, sizeof(th));
+  std::memcpy(thm, th, sizeof(th));
+  for (int k = 0; k < 3; ++k) {
+    thp[k] = th[k] + eps * delta[k];
+    thm[k] = th[k] - eps * delta[k];
+  }
+  for (int v = 0; v < V; ++v) {
+    const Cam& cam = cams[v];
+    View view;
+    build_view(params, n, deg, cam, opt, view);
+    Proj<double> cp, cm;
+    project(thp, deg, cam, opt, cp);
+    project(thm, deg, cam, opt, cm);
+    double lsum = 0.0;
+    for (int y = 0; y < cam.H; ++y)
+      for (int x = 0; x < cam.W; ++x) {
+        const std::vector<int>& lst = view.tiles[(size_t)(y / opt.th) * cam.tiles_x + (x / opt.tw)];
+        double T = 1.0, C[3] = {0, 0, 0};
+        for (size_t j = 0; j < lst.size(); ++j) {
+          const Proj<double>& g = view.rec[lst[j]];
+          double a, rgb[3];
+          if (lst[j] == gi) {
+            a = 0.0;
+            for (int ch = 0; ch < 3; ++ch) rgb[ch] = g.rgb[ch];
+            if (cp.visible) a += 0.5 * alpha_raw(cp.mx, cp.my, cp.A00, cp.A01, cp.A11, cp.o, (double)x, (double)y);
+            if (cm.visible) a += 0.5 * alpha_raw(cm.mx, cm.my, cm.A00, cm.A01, cm.A11, cm.o, (double)x, (double)y);
+          } else {
+            a = alpha_raw(g.mx, g.my, g.A00, g.A01, g.A11, g.o, (double)x, (double)y);
+            for (int ch = 0; ch < 3; ++ch) rgb[ch] = g.rgb[ch];
+          }
+          if (a > opt.alpha_max) a = opt.alpha_max;
+          if (a < opt.alpha_min) continue;
+          double Tn = T * (1.0 - a);
+          if (Tn < opt.t_min) break;
+          for (int ch = 0; ch < 3; ++ch) C[ch] += rgb[ch] * a * T;
+          T = Tn;
+        }
+        for (int ch = 0; ch < 3; ++ch) {
+          C[ch] += T * opt.bg[ch];
+          lsum += std::fabs(C[ch] - target[3 * cam.pixel_offset + (int64_t)ch * cam.W * cam.H + (int64_t)y * cam.W + x]);
+        }
+      }
+    total += lsum / (3.0 * cam.W * cam.H);
+  }
+  return total;
+}
+
+// Real SH basis at m unit directions: out[m][(deg+1)^2]
+void orc_sh_basis(int deg, const double* dirs, int64_t m, double* out) {
+  int nb = (deg + 1) * (deg + 1);
+  for (int64_t k = 0; k < m; ++k) sh_basis(deg, dirs[3 * k], dirs[3 * k + 1], dirs[3 * k + 2], out + k * nb);
+}
+
+// alpha (before clamping) and its mean-Hessian at a pixel
+double orc_alpha(const double* g6, double u, double v) { return alpha_raw(g6[0], g6[1], g6[2], g6[3], g6[4], g6[5], u, v); }
+void orc_alpha_hessian(const double* g6, double u, double v, double* H3) {
+  alpha_hessian_mu(g6[0], g6[1], g6[2], g6[3], g6[4], g6[5], u, v, H3);
+}
+
+// Symmetric eigen-decomposition of m matrices S[m][9] (row-major 3x3):
+// lam[m][3] ascending, vec[m][9] with eigenvectors in columns (canonical sign).
+void orc_eigh(const double* S, int64_t m, double* lam, double* vec) {
+  for (int64_t k = 0; k < m; ++k) jacobi_eigh(S + 9 * k, lam + 3 * k, vec + 9 * k);
+}
+
+// Steepest Density Control over all Gaussians.  S is [9][n] (row-major 3x3 per
+// Gaussian, any scale); s_scale multiplies it first (Algorithm 1 averages the
+// accumulated matrix over the densification interval).  out_params is
+// [F][out_cap] doubles; returns n_out (or -1 if out_cap is too small, with
+// *needed set).  lam_min [n], vmin [3][n], split [n].
+int64_t orc_densify(const float* params, int64_t n, int deg, const double* S, double s_scale, double eps,
+                    double eps_split, double* out_params, int64_t out_cap, double* lam_min, double* vmin,
+                    uint8_t* split, int64_t* needed) {
+  int F = num_params(deg);
+  std::vector<int64_t> off(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    double M[9], lam[3], vec[9];
+    for (int k = 0; k < 9; ++k) M[k] = s_scale * S[(int64_t)k * n + i];
+    jacobi_eigh(M, lam, vec);
+    lam_min[i] = lam[0];
+    for (int r = 0; r < 3; ++r) vmin[(int64_t)r * n + i] = vec[3 * r + 0];
+    split[i] = lam[0] < eps_split ? 1 : 0;
+    off[i + 1] = off[i] + 1 + split[i];
+  }
+  *needed = off[n];
+  if (off[n] > out_cap) return -1;
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t o = off[i];
+    for (int f = 0; f < F; ++f) {
+      double x = params[(int64_t)f * n + i];
+      out_params[(int64_t)f * out_cap + o] = x;
+      if (split[i]) out_params[(int64_t)f * out_cap + o + 1] = x;
+    }
+    if (!split[i]) continue;
+    for (int k = 0; k < 3; ++k) {
+      double p = params[(int64_t)k * n + i], d = vmin[(int64_t)k * n + i];
+      out_params[(int64_t)k * out_cap + o] = p + eps * d;
+      out_params[(int64_t)k * out_cap + o + 1] = p - eps * d;
+    }
+    double op = 1.0 / (1.0 + std::exp(-(double)params[(int64_t)10 * n + i]));
+    double oh = 0.5 * op;
+    double logit = std::log(oh / (1.0 - oh));
+    out_params[(int64_t)10 * out_cap + o] = logit;
+    out_params[(int64_t)10 * out_cap + o + 1] = logit;
+  }
+  return off[n];
+}
+
+}  // extern "C"

@@ -1,0 +1,253 @@
+"""ctypes front end of the FP64 CPU oracle (``oracle.cpp``).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by the
+CPU-baseline leg of the benchmark.  The product path never imports it.
+
+Inputs come from :mod:`paper_2505_05587_amd.scenes` (seeded generators);
+every function returns numpy arrays in float64 (or the integer types of the
+instance list).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "oracle.cpp")
+LIB = os.path.join(HERE, "liboracle.so")
+
+_c_f32 = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+_c_f64 = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+_c_i32 = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+_c_i64 = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+_c_u32 = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
+_c_u64 = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
+_c_u8 = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (plain FP64, no FMA contraction)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+                               "-fno-fast-math", "-o", tmp, SRC])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = C.CDLL(LIB)
+        common = [_c_f32, C.c_int64, C.c_int, _c_f32, _c_i32, C.c_int, _c_f64]
+        L.orc_project.argtypes = common + [_c_f64, _c_i32, _c_u32, _c_u32, _c_u8]
+        L.orc_project.restype = C.c_int
+        L.orc_sort.argtypes = common + [C.POINTER(C.c_uint64), C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_sort.restype = C.c_int
+        L.orc_forward_backward.argtypes = common + [C.c_void_p, C.c_double] + [C.c_void_p] * 10
+        L.orc_forward_backward.restype = C.c_int
+        L.orc_loss.argtypes = common + [_c_f32]
+        L.orc_loss.restype = C.c_double
+        L.orc_render_pixels.argtypes = common + [_c_i64, C.c_int64, _c_f64, _c_f64, _c_u8]
+        L.orc_render_pixels.restype = C.c_int
+        L.orc_grads_sampled.argtypes = common + [_c_f32, C.c_double, _c_i64, C.c_int64, _c_f64, _c_f64, _c_u8]
+        L.orc_grads_sampled.restype = C.c_int
+        L.orc_loss_merged_split.argtypes = common + [_c_f32, C.c_int64, _c_f64, C.c_double]
+        L.orc_loss_merged_split.restype = C.c_double
+        L.orc_sh_basis.argtypes = [C.c_int, _c_f64, C.c_int64, _c_f64]
+        L.orc_sh_basis.restype = None
+        L.orc_alpha.argtypes = [_c_f64, C.c_double, C.c_double]
+        L.orc_alpha.restype = C.c_double
+        L.orc_alpha_hessian.argtypes = [_c_f64, C.c_double, C.c_double, _c_f64]
+        L.orc_alpha_hessian.restype = None
+        L.orc_eigh.argtypes = [_c_f64, C.c_int64, _c_f64, _c_f64]
+        L.orc_eigh.restype = None
+        L.orc_densify.argtypes = [_c_f32, C.c_int64, C.c_int, _c_f64, C.c_double, C.c_double, C.c_double, _c_f64,
+                                  C.c_int64, _c_f64, _c_f64, _c_u8, C.POINTER(C.c_int64)]
+        L.orc_densify.restype = C.c_int64
+        L.orc_num_params.argtypes = [C.c_int]
+        L.orc_num_params.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+# ----------------------------------------------------------------------------
+# argument marshalling
+
+
+def cam_arrays(cams):
+    V = cams.V
+    cf = np.zeros((V, 16), np.float32)
+    cf[:, 0:9] = np.asarray(cams.R, np.float32).reshape(V, 9)
+    cf[:, 9:12] = np.asarray(cams.t, np.float32)
+    cf[:, 12] = cams.fx
+    cf[:, 13] = cams.fy
+    cf[:, 14] = cams.cx
+    cf[:, 15] = cams.cy
+    ci = np.stack([cams.width, cams.height, cams.model], axis=1).astype(np.int32)
+    return np.ascontiguousarray(cf), np.ascontiguousarray(ci)
+
+
+def opts_array(opts):
+    bg = opts.get("bg", (0.0, 0.0, 0.0))
+    return np.array([opts["tile_w"], opts["tile_h"], opts["near_z"], opts["radius_sigmas"], opts["dilation"],
+                     opts["frustum_guard"], opts["alpha_min"], opts["alpha_max"], opts["t_min"],
+                     bg[0], bg[1], bg[2]], np.float64)
+
+
+def _common(params, sh_degree, cams, opts):
+    params = np.ascontiguousarray(params, np.float32)
+    cf, ci = cam_arrays(cams)
+    return [params, params.shape[1], sh_degree, cf, ci, cams.V, opts_array(opts)]
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def total_tiles(cams, opts):
+    tx = (cams.width.astype(np.int64) + opts["tile_w"] - 1) // opts["tile_w"]
+    ty = (cams.height.astype(np.int64) + opts["tile_h"] - 1) // opts["tile_h"]
+    return int((tx * ty).sum())
+
+
+# ----------------------------------------------------------------------------
+# entry points
+
+
+def project(params, sh_degree, cams, opts):
+    args = _common(params, sh_degree, cams, opts)
+    m = cams.V * args[1]
+    rec = np.zeros((m, 13), np.float64)
+    rect = np.zeros((m, 4), np.int32)
+    tiles = np.zeros(m, np.uint32)
+    dbits = np.zeros(m, np.uint32)
+    vis = np.zeros(m, np.uint8)
+    assert lib().orc_project(*args, rec, rect, tiles, dbits, vis) == 0
+    return dict(mean=rec[:, 0:2], conic=rec[:, 2:5], opacity=rec[:, 5], rgb=rec[:, 6:9], depth=rec[:, 9],
+                rgb_raw=rec[:, 10:13], rect=rect, tiles=tiles, depth_bits=dbits, visible=vis.astype(bool))
+
+
+def sort(params, sh_degree, cams, opts):
+    args = _common(params, sh_degree, cams, opts)
+    cnt = C.c_uint64(0)
+    assert lib().orc_sort(*args, C.byref(cnt), None, None, None) == 0
+    K = cnt.value
+    keys = np.zeros(max(K, 1), np.uint64)
+    vals = np.zeros(max(K, 1), np.uint32)
+    ranges = np.zeros((total_tiles(cams, opts), 2), np.uint32)
+    assert lib().orc_sort(*args, C.byref(cnt), _ptr(keys), _ptr(vals), _ptr(ranges)) == 0
+    return keys[:K], vals[:K], ranges
+
+
+def forward_backward(params, sh_degree, cams, opts, target=None, sign_band=1e-5, per_view=False):
+    args = _common(params, sh_degree, cams, opts)
+    n = args[1]
+    F = params.shape[0]
+    Px = cams.total_pixels()
+    image = np.zeros(3 * Px, np.float64)
+    T = np.zeros(Px, np.float64)
+    used = np.zeros(Px, np.int32)
+    pamb = np.zeros(Px, np.uint8)
+    out = dict(image=image, T_final=T, n_used=used, pix_ambig=pamb)
+    tgt = None if target is None else np.ascontiguousarray(target, np.float32)
+    loss = grads = S = g2d = H2d = gamb = None
+    if tgt is not None:
+        loss = np.zeros(cams.V, np.float64)
+        grads = np.zeros((F, n), np.float64)
+        S = np.zeros((9, n), np.float64)
+        gamb = np.zeros(n, np.uint8)
+        if per_view:
+            g2d = np.zeros((cams.V * n, 9), np.float64)
+            H2d = np.zeros((cams.V * n, 3), np.float64)
+    rc = lib().orc_forward_backward(*args, _ptr(tgt), float(sign_band), _ptr(image), _ptr(T), _ptr(used),
+                                    _ptr(pamb), _ptr(loss), _ptr(grads), _ptr(S), _ptr(g2d), _ptr(H2d), _ptr(gamb))
+    assert rc == 0
+    out["pix_ambig"] = pamb.astype(bool)
+    if tgt is not None:
+        out.update(loss=loss, grads=grads, S=S, gauss_ambig=gamb.astype(bool))
+        if per_view:
+            out.update(g2d=g2d, H2d=H2d)
+    return out
+
+
+def loss(params, sh_degree, cams, opts, target):
+    args = _common(params, sh_degree, cams, opts)
+    return lib().orc_loss(*args, np.ascontiguousarray(target, np.float32))
+
+
+def render_pixels(params, sh_degree, cams, opts, pixel_ids):
+    args = _common(params, sh_degree, cams, opts)
+    pix = np.ascontiguousarray(pixel_ids, np.int64)
+    rgb = np.zeros((len(pix), 3), np.float64)
+    T = np.zeros(len(pix), np.float64)
+    amb = np.zeros(len(pix), np.uint8)
+    assert lib().orc_render_pixels(*args, pix, len(pix), rgb, T, amb) == 0
+    return rgb, T, amb.astype(bool)
+
+
+def grads_sampled(params, sh_degree, cams, opts, target, gids, sign_band=1e-5):
+    args = _common(params, sh_degree, cams, opts)
+    g = np.ascontiguousarray(gids, np.int64)
+    F = params.shape[0]
+    grads = np.zeros((len(g), F), np.float64)
+    S = np.zeros((len(g), 9), np.float64)
+    amb = np.zeros(len(g), np.uint8)
+    rc = lib().orc_grads_sampled(*args, np.ascontiguousarray(target, np.float32), float(sign_band), g, len(g),
+                                 grads, S, amb)
+    assert rc == 0
+    return grads, S, amb.astype(bool)
+
+
+def loss_merged_split(params, sh_degree, cams, opts, target, gi, delta, eps):
+    args = _common(params, sh_degree, cams, opts)
+    return lib().orc_loss_merged_split(*args, np.ascontiguousarray(target, np.float32), int(gi),
+                                       np.ascontiguousarray(delta, np.float64), float(eps))
+
+
+def sh_basis(deg, dirs):
+    dirs = np.ascontiguousarray(dirs, np.float64).reshape(-1, 3)
+    out = np.zeros((dirs.shape[0], (deg + 1) ** 2), np.float64)
+    lib().orc_sh_basis(deg, dirs, dirs.shape[0], out)
+    return out
+
+
+def alpha(g6, u, v):
+    return lib().orc_alpha(np.ascontiguousarray(g6, np.float64), float(u), float(v))
+
+
+def alpha_hessian(g6, u, v):
+    H = np.zeros(3, np.float64)
+    lib().orc_alpha_hessian(np.ascontiguousarray(g6, np.float64), float(u), float(v), H)
+    return np.array([[H[0], H[1]], [H[1], H[2]]])
+
+
+def eigh(S):
+    S = np.ascontiguousarray(np.asarray(S, np.float64).reshape(-1, 9))
+    lam = np.zeros((S.shape[0], 3), np.float64)
+    vec = np.zeros((S.shape[0], 9), np.float64)
+    lib().orc_eigh(S, S.shape[0], lam, vec)
+    return lam, vec.reshape(-1, 3, 3)
+
+
+def densify(params, sh_degree, S9, s_scale, eps, eps_split, out_cap=None):
+    params = np.ascontiguousarray(params, np.float32)
+    F, n = params.shape
+    S9 = np.ascontiguousarray(S9, np.float64).reshape(9, n)
+    cap = 2 * n if out_cap is None else out_cap
+    out = np.zeros((F, max(cap, 1)), np.float64)
+    lam = np.zeros(n, np.float64)
+    vmin = np.zeros((3, n), np.float64)
+    split = np.zeros(n, np.uint8)
+    need = C.c_int64(0)
+    n_out = lib().orc_densify(params, n, sh_degree, S9, float(s_scale), float(eps), float(eps_split), out, cap,
+                              lam, vmin, split, C.byref(need))
+    return dict(n_out=int(n_out), needed=int(need.value), params=out[:, :max(n_out, 0)], lambda_min=lam,
+                vmin=vmin, split=split.astype(bool))

@@ -1,0 +1,140 @@
+"""Pins of the oracle's blend (Eq. alpha_blend), tile gathering, depth order
+and L1 loss (Eq. loss): brute force on tiny inputs and closed forms."""
+import numpy as np
+import pytest
+
+from paper_2505_05587_amd import scenes
+from tests.helpers import ortho_camera, pack_params, tiny_scene
+
+
+def _brute_image(pr, cams, opts, n):
+    """Per pixel: every visible Gaussian whose tile rectangle holds the
+    pixel's tile, ordered by (float32 depth, index), composited front to
+    back with the cut-offs.  Plain Python loops."""
+    W, H = int(cams.width[0]), int(cams.height[0])
+    tw, th = opts["tile_w"], opts["tile_h"]
+    img = np.zeros((3, H, W))
+    Tf = np.zeros((H, W))
+    used = np.zeros((H, W), np.int64)
+    for y in range(H):
+        for x in range(W):
+            tx, ty = x // tw, y // th
+            cand = [i for i in range(n) if pr["visible"][i] and pr["rect"][i][0] <= tx <= pr["rect"][i][2]
+                    and pr["rect"][i][1] <= ty <= pr["rect"][i][3]]
+            cand.sort(key=lambda i: (np.float32(pr["depth"][i]), i))
+            T, C, k = 1.0, np.zeros(3), 0
+            for i in cand:
+                (mx, my), (a, b, c), o = pr["mean"][i], pr["conic"][i], pr["opacity"][i]
+                dx, dy = x - mx, y - my
+                al = min(opts["alpha_max"], o * np.exp(-0.5 * (a * dx * dx + 2 * b * dx * dy + c * dy * dy)))
+                if al < opts["alpha_min"]:
+                    continue
+                if T * (1 - al) < opts["t_min"]:
+                    break
+                C += pr["rgb"][i] * al * T
+                T *= 1 - al
+                k += 1
+            img[:, y, x] = C + T * np.asarray(opts["bg"])
+            Tf[y, x] = T
+            used[y, x] = k
+    return img, Tf, used
+
+
+@pytest.mark.parametrize("mode", ["3dgs", "smooth"])
+@pytest.mark.parametrize("model", [0, 1])
+def test_blend_matches_brute_force(oracle, mode, model):
+    P, cams, target = tiny_scene(20 + model, 40, 40, model=model, log_scale_mu=-2.0)
+    opts = scenes.opts(mode, bg=(0.1, 0.2, 0.3))
+    pr = oracle.project(P, 0, cams, opts)
+    out = oracle.forward_backward(P, 0, cams, opts)
+    img, Tf, used = _brute_image(pr, cams, opts, P.shape[1])
+    np.testing.assert_allclose(out["image"].reshape(3, 40, 40), img, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(out["T_final"].reshape(40, 40), Tf, rtol=1e-12, atol=1e-300)
+    np.testing.assert_array_equal(out["n_used"].reshape(40, 40), used)
+
+
+def test_single_gaussian_closed_form(oracle):
+    # one Gaussian, affine camera: C = c*alpha + (1-alpha)*bg with
+    # alpha = min(alpha_max, o * exp(-1/2 d^T Pi(Sigma)^-1 d))
+    cams = ortho_camera(32, scale=10.0)
+    P = pack_params([[0.1, -0.2, 0.0]], [[-1.0, -1.5, -2.0]], [[0.9, 0.1, -0.3, 0.2]], [2.5],
+                    [[0.4, -0.3, 0.1]], 0)
+    opts = scenes.opts("3dgs", radius_sigmas=1e3, dilation=0.0, bg=(0.25, 0.5, 0.75))
+    out = oracle.forward_backward(P, 0, cams, opts)
+    from scipy.spatial.transform import Rotation
+    q = P[6:10, 0].astype(np.float64)
+    rot = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+    s = np.exp(P[3:6, 0].astype(np.float64))
+    Rc = cams.R[0].astype(np.float64)
+    Pm = 10.0 * Rc[:2]
+    S2 = Pm @ rot @ np.diag(s * s) @ rot.T @ Pm.T
+    A = np.linalg.inv(S2)
+    mu = Pm @ P[0:3, 0].astype(np.float64) + 10.0 * cams.t[0, :2].astype(np.float64) + 16.0
+    o = 1 / (1 + np.exp(-np.float64(P[10, 0])))
+    rgb = P[11:14, 0].astype(np.float64) * (0.5 / np.sqrt(np.pi)) + 0.5
+    bg = np.array([0.25, 0.5, 0.75])
+    ys, xs = np.mgrid[0:32, 0:32]
+    d = np.stack([xs - mu[0], ys - mu[1]], -1)
+    al = np.minimum(0.99, o * np.exp(-0.5 * np.einsum("...i,ij,...j->...", d, A, d)))
+    keep = al >= 1 / 255
+    al = np.where(keep, al, 0.0)
+    expect = rgb[:, None, None] * al + (1 - al) * bg[:, None, None]
+    np.testing.assert_allclose(out["image"].reshape(3, 32, 32), expect, rtol=1e-11, atol=1e-14)
+
+
+def test_front_to_back_order_and_ties(oracle):
+    # Two overlapping Gaussians: the nearer one is composited first
+    # (T_i multiplies over the nearer entries, Eq. alpha_blend); equal depth
+    # falls back to index order.
+    cams = ortho_camera(16, scale=4.0)
+    base = dict(log_scales=[[-0.5] * 3, [-0.5] * 3], quats=[[1, 0, 0, 0]] * 2, logits=[0.0, 1.0],
+                sh=[[1.0, 0.0, 0.0], [0.0, 1.0, 0.0]])
+    opts = scenes.opts("smooth", radius_sigmas=1e3)
+
+    def render(z0, z1):
+        P = pack_params([[0, 0, z0], [0, 0, z1]], base["log_scales"], base["quats"], base["logits"], base["sh"], 0)
+        pr = oracle.project(P, 0, cams, opts)
+        out = oracle.forward_backward(P, 0, cams, opts)
+        return pr, out["image"].reshape(3, 16, 16)[:, 8, 8]
+
+    # camera at z=5 looking down -z: larger world z is nearer
+    pr, c = render(0.5, -0.5)
+    a0 = pr["opacity"][0] * np.exp(-0.5 * 0.0)
+    x = np.array([8.0, 8.0]) - pr["mean"][0]
+    a0 = pr["opacity"][0] * np.exp(-0.5 * x @ np.array([[pr["conic"][0][0], pr["conic"][0][1]], [pr["conic"][0][1], pr["conic"][0][2]]]) @ x)
+    x1 = np.array([8.0, 8.0]) - pr["mean"][1]
+    a1 = pr["opacity"][1] * np.exp(-0.5 * x1 @ np.array([[pr["conic"][1][0], pr["conic"][1][1]], [pr["conic"][1][1], pr["conic"][1][2]]]) @ x1)
+    np.testing.assert_allclose(c, pr["rgb"][0] * a0 + pr["rgb"][1] * a1 * (1 - a0), rtol=1e-12)
+    pr2, c2 = render(-0.5, 0.5)
+    np.testing.assert_allclose(c2, pr2["rgb"][1] * a1 + pr2["rgb"][0] * a0 * (1 - a1), rtol=1e-12)
+    pr3, c3 = render(0.0, 0.0)   # tie: index 0 first
+    np.testing.assert_allclose(c3, pr3["rgb"][0] * a0 + pr3["rgb"][1] * a1 * (1 - a0), rtol=1e-12)
+
+
+def test_loss_is_sum_of_per_view_means(oracle):
+    rng = np.random.default_rng(30)
+    P = scenes.uniform_gaussians(rng, 80, log_scale_mu=-2.5)
+    cams = scenes.make_cameras([(0, 0, 3.0), (2.0, 1.0, 2.0)], [(24, 16), (20, 28)])
+    target = scenes.uniform_target(rng, cams)
+    opts = scenes.opts("3dgs")
+    out = oracle.forward_backward(P, 0, cams, opts, target)
+    offs = cams.pixel_offsets()
+    total = 0.0
+    for v in range(2):
+        npx = int(cams.width[v] * cams.height[v])
+        sl = slice(3 * offs[v], 3 * offs[v] + 3 * npx)
+        per = np.abs(out["image"][sl] - target[sl].astype(np.float64)).mean()
+        assert out["loss"][v] == pytest.approx(per, rel=1e-12)
+        total += per
+    assert oracle.loss(P, 0, cams, opts, target) == pytest.approx(total, rel=1e-12)
+
+
+def test_sampled_pixels_match_full_render(oracle):
+    P, cams, target = tiny_scene(31, 60, 48, sh_degree=2)
+    opts = scenes.opts("3dgs")
+    full = oracle.forward_backward(P, 2, cams, opts)
+    pix = np.array([0, 5, 47, 48 * 20 + 7, 48 * 48 - 1])
+    rgb, T, _ = oracle.render_pixels(P, 2, cams, opts, pix)
+    img = full["image"].reshape(3, -1)
+    np.testing.assert_array_equal(rgb, img[:, pix].T)
+    np.testing.assert_array_equal(T, full["T_final"][pix])

@@ -1,0 +1,170 @@
+"""Pins of the oracle's Gaussian primitive and projection (Sec. 3, Eqs.
+sigma_3D and sigma_2D, footnote on Pi) against closed forms and library
+routines."""
+import math
+
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+from scipy.special import expit, sph_harm_y
+
+from paper_2505_05587_amd import scenes
+from tests.helpers import ortho_camera, pack_params, pinhole_camera
+
+
+def _rand_gauss(rng, n, deg=0, spread=0.5):
+    means = rng.uniform(-spread, spread, size=(n, 3))
+    ls = rng.normal(-2.5, 0.4, size=(n, 3))
+    q = rng.normal(size=(n, 4))
+    logit = rng.normal(size=n)
+    sh = rng.normal(0, 0.3, size=(n, (deg + 1) ** 2 * 3))
+    return means, ls, q, logit, sh
+
+
+def _covariance_scipy(P, i):
+    q = P[6:10, i].astype(np.float64)
+    rot = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()  # scipy: scalar last
+    s = np.exp(P[3:6, i].astype(np.float64))
+    return rot @ np.diag(s * s) @ rot.T
+
+
+def _sigma2d_from_conic(pr, r):
+    a, b, c = pr["conic"][r]
+    return np.linalg.inv(np.array([[a, b], [b, c]]))
+
+
+def test_affine_camera_covariance_is_P_Sigma_PT(oracle):
+    # footnote on Pi: for Pi(x) = P x + b, Pi(Sigma) = P Sigma P^T
+    rng = np.random.default_rng(10)
+    P = pack_params(*_rand_gauss(rng, 20), 0)
+    cams = scenes.make_cameras([(1.0, 2.0, 4.0)], [(64, 64)], model=1, ortho_scale=20.0)
+    opts = scenes.opts("smooth", dilation=0.0, radius_sigmas=1e3)
+    pr = oracle.project(P, 0, cams, opts)
+    Rc = cams.R[0].astype(np.float64)
+    Pm = cams.fx[0] * Rc[:2, :]
+    for i in range(20):
+        S3 = _covariance_scipy(P, i)
+        np.testing.assert_allclose(_sigma2d_from_conic(pr, i), Pm @ S3 @ Pm.T, rtol=1e-9, atol=0)
+        # mean maps through the affine camera
+        pc = Rc @ P[0:3, i].astype(np.float64) + cams.t[0].astype(np.float64)
+        np.testing.assert_allclose(pr["mean"][i], cams.fx[0] * pc[:2] + np.array([cams.cx[0], cams.cy[0]]),
+                                   rtol=1e-13)
+        assert pr["depth"][i] == pytest.approx(pc[2], rel=1e-14)
+
+
+def test_pinhole_covariance_uses_local_affine_map(oracle):
+    # Pinhole: Pi is replaced by its local affine approximation at p, so
+    # Pi(Sigma) = P Sigma P^T with P the Jacobian of the projected mean
+    # (finite differences here), plus the dilation on the diagonal.
+    rng = np.random.default_rng(11)
+    n = 12
+    means = np.round(rng.uniform(-0.3, 0.3, size=(n, 3)) * 64) / 64
+    g = _rand_gauss(rng, n)
+    P = pack_params(means, g[1], g[2], g[3], g[4], 0)
+    cams = pinhole_camera(64, pos=(0.0, 0.0, 3.0))
+    dil = 0.3
+    opts = scenes.opts("smooth", dilation=dil, radius_sigmas=1e3)
+    base = oracle.project(P, 0, cams, opts)
+    h = 2.0 ** -14
+    for i in range(n):
+        Jfd = np.zeros((2, 3))
+        for k in range(3):
+            Pp, Pm = P.copy(), P.copy()
+            Pp[k, i] += h
+            Pm[k, i] -= h
+            assert Pp[k, i] - P[k, i] == np.float32(h)
+            Jfd[:, k] = (oracle.project(Pp, 0, cams, opts)["mean"][i] - oracle.project(Pm, 0, cams, opts)["mean"][i]) / (2 * h)
+        S3 = _covariance_scipy(P, i)
+        expect = Jfd @ S3 @ Jfd.T + dil * np.eye(2)
+        np.testing.assert_allclose(_sigma2d_from_conic(base, i), expect, rtol=2e-7)
+        # pinhole mean: perspective division
+        pc = cams.R[0].astype(np.float64) @ P[0:3, i].astype(np.float64) + cams.t[0].astype(np.float64)
+        np.testing.assert_allclose(base["mean"][i], [cams.fx[0] * pc[0] / pc[2] + cams.cx[0],
+                                                     cams.fy[0] * pc[1] / pc[2] + cams.cy[0]], rtol=1e-14)
+
+
+def test_opacity_and_dc_colour(oracle):
+    rng = np.random.default_rng(12)
+    g = _rand_gauss(rng, 10)
+    P = pack_params(*g, 0)
+    cams = pinhole_camera(32)
+    pr = oracle.project(P, 0, cams, scenes.opts("3dgs", radius_sigmas=1e3))
+    np.testing.assert_allclose(pr["opacity"], expit(P[10].astype(np.float64)), rtol=1e-15)
+    y00 = 1.0 / (2.0 * math.sqrt(math.pi))
+    raw = P[11:14].T.astype(np.float64) * y00 + 0.5
+    np.testing.assert_allclose(pr["rgb_raw"], raw, rtol=1e-14)
+    np.testing.assert_allclose(pr["rgb"], np.maximum(raw, 0.0), rtol=1e-14)
+
+
+def _fibonacci_dirs(m):
+    k = np.arange(m) + 0.5
+    z = 1 - 2 * k / m
+    phi = np.pi * (1 + 5 ** 0.5) * k
+    r = np.sqrt(1 - z * z)
+    return np.stack([r * np.cos(phi), r * np.sin(phi), z], axis=1)
+
+
+def test_sh_basis_matches_scipy_complex_harmonics(oracle):
+    # real SH (Condon-Shortley phase): sqrt(2) Re / Im of the complex Y_l^|m|
+    dirs = _fibonacci_dirs(200)
+    Y = oracle.sh_basis(3, dirs)
+    theta = np.arccos(np.clip(dirs[:, 2], -1, 1))
+    phi = np.arctan2(dirs[:, 1], dirs[:, 0])
+    for l in range(4):
+        for m in range(-l, l + 1):
+            c = sph_harm_y(l, abs(m), theta, phi)
+            ref = c.real if m == 0 else math.sqrt(2) * (c.real if m > 0 else c.imag)
+            np.testing.assert_allclose(Y[:, l * l + l + m], ref, atol=1e-13)
+
+
+def test_sh_basis_orthonormal_on_sphere(oracle):
+    # Gauss-Legendre in cos(theta) x uniform phi integrates degree <= 6 products exactly
+    x, w = np.polynomial.legendre.leggauss(12)
+    nphi = 16
+    phi = (np.arange(nphi) + 0.5) * 2 * np.pi / nphi
+    Z, PH = np.meshgrid(x, phi, indexing="ij")
+    W = np.repeat(w[:, None], nphi, axis=1) * (2 * np.pi / nphi)
+    r = np.sqrt(1 - Z ** 2)
+    dirs = np.stack([r * np.cos(PH), r * np.sin(PH), Z], axis=-1).reshape(-1, 3)
+    Y = oracle.sh_basis(3, dirs)
+    G = (Y * W.reshape(-1, 1)).T @ Y
+    np.testing.assert_allclose(G, np.eye(16), atol=1e-12)
+
+
+def test_sh_colour_is_basis_dot_coefficients(oracle):
+    rng = np.random.default_rng(13)
+    g = _rand_gauss(rng, 8, deg=3)
+    P = pack_params(*g, 3)
+    cams = pinhole_camera(32, pos=(0.5, -0.2, 3.0))
+    pr = oracle.project(P, 3, cams, scenes.opts("3dgs", radius_sigmas=1e3))
+    Rc, t = cams.R[0].astype(np.float64), cams.t[0].astype(np.float64)
+    campos = -Rc.T @ t
+    for i in range(8):
+        d = P[0:3, i].astype(np.float64) - campos
+        d /= np.linalg.norm(d)
+        Y = oracle.sh_basis(3, d)[0]
+        coef = P[11:, i].astype(np.float64).reshape(16, 3)
+        np.testing.assert_allclose(pr["rgb_raw"][i], Y @ coef + 0.5, rtol=1e-13, atol=1e-15)
+
+
+def test_cull_and_footprint(oracle):
+    # behind the near plane -> culled; footprint covers radius_sigmas * sqrt(lambda_max)
+    rng = np.random.default_rng(14)
+    g = list(_rand_gauss(rng, 40, spread=1.0))
+    g[0][:5, 2] = 4.0   # behind the camera at z = 3
+    P = pack_params(*g, 0)
+    cams = pinhole_camera(64)
+    opts = scenes.opts("3dgs")
+    pr = oracle.project(P, 0, cams, opts)
+    assert not pr["visible"][:5].any()
+    for i in np.nonzero(pr["visible"])[0]:
+        S2 = _sigma2d_from_conic(pr, i)
+        r = math.ceil(3.0 * math.sqrt(np.linalg.eigvalsh(S2).max()))
+        mx, my = pr["mean"][i]
+        x0, y0, x1, y1 = pr["rect"][i]
+        for tx in range(4):
+            for ty in range(4):
+                hit = (tx * 16 <= mx + r) and ((tx + 1) * 16 > mx - r) and (ty * 16 <= my + r) and ((ty + 1) * 16 > my - r)
+                assert hit == (x0 <= tx <= x1 and y0 <= ty <= y1)
+        assert pr["tiles"][i] == (x1 - x0 + 1) * (y1 - y0 + 1)
+        assert pr["depth_bits"][i] == np.float32(pr["depth"][i]).view(np.uint32)

@@ -1,0 +1,164 @@
+"""Pins of the oracle's eigen-decomposition (App. A.3), Steepest Density
+Control (Theorem 2, Algorithm 1) and instance sort."""
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy.special import expit
+
+from paper_2505_05587_amd import scenes
+from tests.helpers import tiny_scene
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_eigh_closed_form_cases(oracle):
+    cases = json.load(open(os.path.join(GOLDEN, "eigen_closed_form.json")))["cases"]
+    for c in cases:
+        A = np.array(c["A"], np.float64)
+        lam, vec = oracle.eigh(A[None])
+        np.testing.assert_allclose(lam[0], c["eigenvalues"], atol=1e-13)
+        if "v_min" in c:
+            np.testing.assert_allclose(vec[0][:, 0], c["v_min"], atol=1e-13)
+
+
+def test_eigh_matches_lapack_on_random_symmetric(oracle):
+    rng = np.random.default_rng(50)
+    B = rng.normal(size=(10000, 3, 3)) * np.exp(rng.normal(0, 3, size=(10000, 1, 1)))
+    S = B + np.swapaxes(B, 1, 2)
+    lam, vec = oracle.eigh(S)
+    ref = np.linalg.eigvalsh(S)
+    scale = np.abs(ref).max(axis=1, keepdims=True)
+    assert (np.abs(lam - ref) <= 1e-13 * scale).all()
+    # residual and orthonormality of the eigenvector columns
+    res = np.einsum("kij,kjl->kil", S, vec) - vec * lam[:, None, :]
+    assert (np.linalg.norm(res, axis=1) <= 1e-12 * scale).all()
+    np.testing.assert_allclose(np.einsum("kji,kjl->kil", vec, vec), np.broadcast_to(np.eye(3), S.shape), atol=1e-12)
+    # canonical sign: the largest-magnitude component of v_min is positive
+    v = vec[:, :, 0]
+    assert (v[np.arange(len(v)), np.abs(v).argmax(axis=1)] > 0).all()
+
+
+def test_smith_trigonometric_roots_agree(oracle):
+    # App. A.3: A = p B + q I, q = tr(A)/3, p = sqrt(tr((A - qI)^2)/6),
+    # beta = 2 cos(acos(det(B)/2)/3 + 2 k pi / 3); the smallest root is k = 1.
+    rng = np.random.default_rng(51)
+    B0 = rng.normal(size=(2000, 3, 3))
+    S = B0 + np.swapaxes(B0, 1, 2)
+    lam, _ = oracle.eigh(S)
+    q = np.trace(S, axis1=1, axis2=2) / 3
+    Aq = S - q[:, None, None] * np.eye(3)
+    p = np.sqrt(np.einsum("kij,kji->k", Aq, Aq) / 6)
+    detB = np.linalg.det(Aq / p[:, None, None])
+    phi = np.arccos(np.clip(detB / 2, -1, 1)) / 3
+    roots = np.stack([q + 2 * p * np.cos(phi + 2 * k * np.pi / 3) for k in range(3)], 1)
+    np.testing.assert_allclose(np.sort(roots, 1), lam, atol=1e-9 * np.abs(lam).max())
+    np.testing.assert_allclose(roots[:, 1], lam[:, 0], atol=1e-9 * np.abs(lam).max())
+
+
+def _random_S(rng, n):
+    B = rng.normal(size=(n, 3, 3))
+    S = B + np.swapaxes(B, 1, 2)
+    S[: n // 4] = np.einsum("kij,kjl->kil", B[: n // 4], np.swapaxes(B[: n // 4], 1, 2))  # PSD: no split
+    return S
+
+
+def test_densify_rule_and_layout(oracle):
+    # Theorem 2 / Algorithm 1: split iff lambda_min < eps_split into
+    # (p + eps v_min, o/2) and (p - eps v_min, o/2); others untouched.
+    rng = np.random.default_rng(52)
+    n = 500
+    P = scenes.clustered_gaussians(rng, n, 20, sh_degree=1)
+    S = _random_S(rng, n)
+    S9 = S.reshape(n, 9).T.copy()
+    eps, eps_split = 0.01, -1e-6
+    out = oracle.densify(P, 1, S9, 1.0, eps, eps_split)
+    lam, vec = oracle.eigh(S)
+    np.testing.assert_allclose(out["lambda_min"], lam[:, 0])
+    split = lam[:, 0] < eps_split
+    np.testing.assert_array_equal(out["split"], split)
+    assert out["n_out"] == n + split.sum()
+    assert split[: n // 4].sum() == 0 and split.sum() > n // 2
+    Q = out["params"]
+    o = 0
+    for i in range(n):
+        if not split[i]:
+            np.testing.assert_array_equal(Q[:, o], P[:, i].astype(np.float64))
+            o += 1
+            continue
+        a, b = Q[:, o], Q[:, o + 1]
+        p = P[0:3, i].astype(np.float64)
+        np.testing.assert_allclose(0.5 * (a[0:3] + b[0:3]), p, rtol=1e-15, atol=1e-15)
+        np.testing.assert_allclose(0.5 * (a[0:3] - b[0:3]), eps * vec[i][:, 0], rtol=1e-12, atol=1e-15)
+        for c in (a, b):
+            assert expit(c[10]) == pytest.approx(0.5 * expit(np.float64(P[10, i])), rel=1e-13)
+            np.testing.assert_array_equal(c[3:10], P[3:10, i].astype(np.float64))
+            np.testing.assert_array_equal(c[11:], P[11:, i].astype(np.float64))
+        o += 2
+    assert o == out["n_out"]
+
+
+def test_densify_scale_and_threshold(oracle):
+    # S is averaged over the interval before the test (Algorithm 1); a positive
+    # scale does not change the split set at eps_split = 0, the threshold does
+    rng = np.random.default_rng(53)
+    n = 300
+    P = scenes.uniform_gaussians(rng, n)
+    S9 = _random_S(rng, n).reshape(n, 9).T.copy()
+    a = oracle.densify(P, 0, S9, 1.0, 0.01, 0.0)
+    b = oracle.densify(P, 0, S9, 1.0 / 100.0, 0.01, 0.0)
+    np.testing.assert_array_equal(a["split"], b["split"])
+    np.testing.assert_allclose(b["lambda_min"], a["lambda_min"] / 100.0, rtol=1e-12, atol=1e-15)
+    c = oracle.densify(P, 0, S9, 1.0, 0.01, -1e9)
+    assert c["n_out"] == n and not c["split"].any()
+    small = oracle.densify(P, 0, S9, 1.0, 0.01, 0.0, out_cap=n)
+    assert small["n_out"] == -1 and small["needed"] == a["n_out"]
+
+
+def test_instance_sort_properties(oracle):
+    # view-dependent depth sort per tile (Sec. 3, Rasterization): keys are
+    # tile | depth, non-decreasing, each visible Gaussian appears once per
+    # covered tile, ranges partition the list.  Re-emitted here from the
+    # projection and re-sorted with numpy's stable sort.
+    P, cams, _ = tiny_scene(54, 300, 64, sh_degree=0)
+    cams = scenes.make_cameras([(0, 0, 3.0), (1.5, 0.5, 2.5)], [(64, 48), (40, 72)])
+    opts = scenes.opts("3dgs")
+    keys, vals, ranges = oracle.sort(P, 0, cams, opts)
+    pr = oracle.project(P, 0, cams, opts)
+    n = P.shape[1]
+    assert (np.diff(keys.astype(np.uint64)) >= 0).all() if len(keys) > 1 else True
+    assert len(keys) == int(pr["tiles"].sum())
+    em_k, em_v = [], []
+    tile_off = 0
+    for v in range(cams.V):
+        tx = (int(cams.width[v]) + 15) // 16
+        ty = (int(cams.height[v]) + 15) // 16
+        for i in range(n):
+            r = v * n + i
+            if not pr["visible"][r]:
+                continue
+            x0, y0, x1, y1 = pr["rect"][r]
+            for yy in range(y0, y1 + 1):
+                for xx in range(x0, x1 + 1):
+                    em_k.append(((tile_off + yy * tx + xx) << 32) | int(pr["depth_bits"][r]))
+                    em_v.append(r)
+        tile_off += tx * ty
+    em_k = np.array(em_k, np.uint64)
+    em_v = np.array(em_v, np.uint32)
+    order = np.argsort(em_k, kind="stable")
+    np.testing.assert_array_equal(keys, em_k[order])
+    np.testing.assert_array_equal(vals, em_v[order])
+    assert ranges.shape[0] == tile_off
+    covered = np.zeros(len(keys), np.int64)
+    for t in range(tile_off):
+        b, e = ranges[t]
+        assert (keys[b:e] >> np.uint64(32) == t).all()
+        covered[b:e] += 1
+    assert (covered == 1).all()
+
+
+def test_paper_constants_fixture():
+    c = json.load(open(os.path.join(GOLDEN, "paper_constants.json")))
+    assert c["eps_split"]["value"] == -1e-6
+    assert c["offspring_weight"]["value"] == 0.5 and c["offspring_count"]["value"] == 2
