@@ -1,0 +1,209 @@
+/*
+ * steepgs.h -- C ABI of the SteepGS hot path on AMD Instinct MI355X (gfx950).
+ *
+ * Paper: "Steepest Descent Density Control for Compact 3D Gaussian
+ * Splatting" (arXiv 2505.05587).  The five stages are
+ *
+ *   steepgs_project          Sec. 3, Eq. (sigma_3D), Eq. (sigma_2D) and the
+ *                            footnote on Pi: each Gaussian through each camera.
+ *   steepgs_sort             Sec. 3 "Rasterization": view-dependent depth order,
+ *                            grouped by screen tile.
+ *   steepgs_render_fwd       Sec. 3, Eq. (alpha_blend), front-to-back; Eq. (loss)
+ *                            L1 value when a target is given.
+ *   steepgs_render_bwd_split Sec. 4.4 and Theorem 1: backward of the blend and the
+ *                            per-Gaussian splitting matrix
+ *                            S_i += sum_x dL/dalpha_i(x) * Hessian_p alpha_i(x),
+ *                            with the Hessian of Sec. 4.4 / App. C.4.
+ *   steepgs_densify          Theorem 2, Algorithm 1, App. A.3: smallest
+ *                            eigenpair of each 3x3 S_i, split iff
+ *                            lambda_min < eps_split into p +/- eps v_min with
+ *                            half the opacity each.
+ *
+ * General conventions
+ *   - Every pointer named d_* is device memory owned by the caller.  The
+ *     library never allocates, frees or keeps device memory between calls;
+ *     scratch space comes from the caller's workspace (see
+ *     steepgs_workspace_size).  Host pointers are read during the call only.
+ *   - `stream` is a hipStream_t.  Calls only enqueue work on it: no host
+ *     synchronisation, no device allocation and no memset nodes, so every call
+ *     may be captured into a HIP graph.  Calls that overlap on one workspace
+ *     race.
+ *   - Return value: STEEPGS_OK, or an error detected on the host before any
+ *     work is enqueued (bad argument, launch failure).  Failures that depend on
+ *     data (instance or output capacity) are written to *d_status on the
+ *     device together with the size that would have been needed.
+ *   - Floating point is IEEE fp32 storage; projection, eigensolve and the
+ *     projection backward compute in fp64, the rasterizer in fp32.
+ *
+ * Gaussian parameters: one planar float32 array [F][n] (row stride n),
+ *   rows 0-2 position p, 3-5 log-scales, 6-9 quaternion (w,x,y,z) (normalised
+ *   inside), 10 opacity logit, 11.. SH coefficients: row 11 + 3*k + channel,
+ *   basis k = l*l + l + m of the real spherical harmonics (Condon-Shortley
+ *   phase), F = 11 + 3*(d+1)^2 for SH degree d in 0..3.
+ *   covariance = R(q) diag(exp(2*log_scale)) R(q)^T, opacity = sigmoid(logit),
+ *   colour = max(0, sum_k sh_k Y_k(dir) + 1/2), dir = unit(p - camera centre).
+ */
+#ifndef STEEPGS_H
+#define STEEPGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  STEEPGS_OK = 0,
+  STEEPGS_ERR_INVALID_ARG = 1, /* null pointer, bad size, unsupported option */
+  STEEPGS_ERR_CAPACITY = 2,    /* (device status) an output buffer was too small */
+  STEEPGS_ERR_HIP = 3,         /* a HIP launch or runtime call failed */
+  STEEPGS_ERR_WORKSPACE = 4    /* workspace smaller than steepgs_workspace_size() */
+} steepgs_status;
+
+#define STEEPGS_ROW_MEAN 0
+#define STEEPGS_ROW_LOG_SCALE 3
+#define STEEPGS_ROW_QUAT 6
+#define STEEPGS_ROW_OPACITY 10
+#define STEEPGS_ROW_SH 11
+#define STEEPGS_NUM_PARAMS(d) (11 + 3 * ((d) + 1) * ((d) + 1))
+
+/* One camera (96 bytes).  World->camera x_c = R x + t, camera looks down +z,
+ * x right, y down.  model 0 (pinhole): u = fx x_c/z_c + cx, v = fy y_c/z_c + cy;
+ * model 1 (orthographic): u = fx x_c + cx, v = fy y_c + cy.  Pixel (u, v)
+ * (integers) is sampled at the image point (u, v).  tiles_x, tiles_y,
+ * tile_offset and pixel_offset place the view in the batch and are filled by
+ * steepgs_layout_cameras. */
+typedef struct {
+  float R[9]; /* row-major */
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+  int32_t model;
+  int32_t tiles_x, tiles_y;
+  int32_t tile_offset;  /* global id of the view's first tile */
+  int64_t pixel_offset; /* index of the view's first pixel in packed images */
+} steepgs_camera;
+
+/* Raster conventions (host struct, read at call time).  alpha_min = 0,
+ * alpha_max = 1, t_min = 0 gives the cut-off free "smooth" blend.
+ *   alpha = min(alpha_max, o * exp(-1/2 d^T A d)); entries with alpha < alpha_min
+ *   are skipped; a pixel stops before the entry that would take its
+ *   transmittance below t_min.
+ *   footprint radius = ceil(radius_sigmas * sqrt(lambda_max(Pi(Sigma)))) pixels;
+ *   dilation is added to the diagonal of Pi(Sigma); frustum_guard > 0 clamps
+ *   x_c/z_c, y_c/z_c to +/- frustum_guard * half-image-size / focal inside the
+ *   pinhole Jacobian; Gaussians with z_c <= near_z are culled. */
+typedef struct {
+  int32_t tile_w, tile_h; /* supported: 16x16, 16x8, 8x8 */
+  float near_z;
+  float radius_sigmas;
+  float dilation;
+  float frustum_guard;
+  float alpha_min, alpha_max, t_min;
+  float bg[3];
+} steepgs_opts;
+
+/* Projected record of one (view, Gaussian) pair, 48 bytes.  Index r = v*n + i.
+ * conic = (a, b, c) with A = [[a, b], [b, c]] = Pi(Sigma)^-1.  rect packs the
+ * inclusive tile rectangle: rect_lo = x0 | y0 << 16, rect_hi = x1 | y1 << 16.
+ * A culled pair has opacity 0 and tiles_touched 0. */
+typedef struct {
+  float mean_x, mean_y;
+  float conic_a, conic_b;
+  float conic_c, opacity;
+  float rgb[3];
+  float depth; /* camera-space z */
+  uint32_t rect_lo, rect_hi;
+} steepgs_splat;
+
+/* Fill tiles_x/tiles_y/tile_offset/pixel_offset of V host cameras for the
+ * tile shape of `opts`; returns the totals.  Host only. */
+steepgs_status steepgs_layout_cameras(steepgs_camera* cams, int32_t V, const steepgs_opts* opts,
+                                      int64_t* total_pixels, int32_t* total_tiles);
+
+/* Workspace (device bytes) each stage needs.  stage: 1 sort, 2 render_fwd,
+ * 3 render_bwd_split, 4 densify (project needs none).  n = Gaussians, V =
+ * views, capacity = instance capacity of the sort. */
+size_t steepgs_workspace_size(int32_t stage, int64_t n, int32_t V, uint64_t capacity, int32_t total_tiles);
+
+/* Stage 1 -- projection (Sec. 3, Eqs. sigma_3D / sigma_2D).
+ * In:  d_params [F][n], d_cams [V] (device copy of laid-out cameras).
+ * Out: d_splats [V*n], d_tiles_touched [V*n] (tiles in the rectangle, 0 if
+ *      culled).  Discrete outcomes (culling, footprint, depth) are computed in
+ *      fp64 in a fixed operation order. */
+steepgs_status steepgs_project(const float* d_params, int64_t n, int32_t sh_degree, const steepgs_camera* d_cams,
+                               int32_t V, const steepgs_opts* opts, steepgs_splat* d_splats,
+                               uint32_t* d_tiles_touched, void* stream);
+
+/* Stage 2 -- instance list (Sec. 3 "Rasterization": sort by view-dependent
+ * depth).  One instance per (visible pair, covered tile); 64-bit key
+ * global_tile << 32 | float bits of depth; value r = v*n + i; sorted by key,
+ * ties by r (the order of emission view, Gaussian, row-major tile).
+ * Out: d_vals [capacity] sorted values; d_keys [capacity] (nullable) sorted
+ *      keys; d_tile_ranges [total_tiles][2] = [begin, end) ((0,0) if empty);
+ *      *d_num_instances = K.  If K > capacity, *d_status = STEEPGS_ERR_CAPACITY,
+ *      *d_num_instances holds K and the outputs are not written.  *d_status is
+ *      set to 0 otherwise. */
+steepgs_status steepgs_sort(const steepgs_splat* d_splats, const uint32_t* d_tiles_touched, int64_t n, int32_t V,
+                            const steepgs_camera* d_cams, const steepgs_opts* opts, int32_t total_tiles,
+                            uint64_t* d_keys, uint32_t* d_vals, uint64_t capacity, uint32_t* d_tile_ranges,
+                            uint64_t* d_num_instances, int32_t* d_status, void* d_ws, size_t ws_bytes,
+                            void* stream);
+
+/* Stage 3 -- forward blend (Eq. alpha_blend), all V views in one persistent
+ * launch.  Out: d_image packed per view as [3][H][W] planes (offset
+ * 3*pixel_offset), d_T_final [total_pixels], d_n_contrib [total_pixels]
+ * (entries of the tile list up to and including the last contributor).
+ * d_target (nullable, same layout as d_image): when given, d_loss[V] receives
+ * the per-view mean absolute error of Eq. (loss) (overwritten). */
+steepgs_status steepgs_render_fwd(const steepgs_splat* d_splats, int64_t n, const uint32_t* d_vals,
+                                  const uint32_t* d_tile_ranges, const steepgs_camera* d_cams, int32_t V,
+                                  const steepgs_opts* opts, int32_t total_tiles, int64_t total_pixels,
+                                  const float* d_target, float* d_image, float* d_T_final, uint32_t* d_n_contrib,
+                                  float* d_loss, void* d_ws, size_t ws_bytes, void* stream);
+
+/* Stage 4 -- backward of the blend and the projection, and the splitting
+ * matrices (Theorem 1; Sec. 4.4).  Loss gradient per pixel: d_dL_dimage when
+ * non-null, else the L1 loss of Eq. (loss) against d_target (sum over views
+ * of the per-view mean).  Accumulates (+=, caller zeroes):
+ *   d_grads [F][n]  dL/dparams,
+ *   d_S     [6][n]  S_i summed over views and pixels, entries xx xy xz yy yz zz,
+ *                   with Hessian_p alpha = alpha P^T (A d d^T A - A) P, P the
+ *                   Jacobian of the projected mean w.r.t. p, held fixed with
+ *                   Pi(Sigma) and colour (App. C.4).
+ * d_grad2d (nullable) [9][V*n] receives the per-pair gradients w.r.t.
+ * (mean_x, mean_y, conic a, b, c, opacity, r, g, b) (overwritten). */
+steepgs_status steepgs_render_bwd_split(const float* d_params, int64_t n, int32_t sh_degree,
+                                        const steepgs_camera* d_cams, int32_t V, const steepgs_opts* opts,
+                                        const steepgs_splat* d_splats, const uint32_t* d_tiles_touched,
+                                        const uint32_t* d_vals, const uint32_t* d_tile_ranges, int32_t total_tiles,
+                                        int64_t total_pixels, const float* d_image, const float* d_T_final,
+                                        const uint32_t* d_n_contrib, const float* d_dL_dimage,
+                                        const float* d_target, float* d_grads, float* d_S, float* d_grad2d,
+                                        void* d_ws, size_t ws_bytes, void* stream);
+
+/* Stage 5 -- Steepest Density Control (Theorem 2; Algorithm 1; App. A.3).
+ * S' = s_scale * S (Algorithm 1 averages over the interval); smallest
+ * eigenpair by the trigonometric root formula in fp64; split iff
+ * lambda_min < eps_split.  Output layout: exclusive scan of m_i in {1, 2}:
+ * d_out [F][out_capacity] row stride out_capacity; an unsplit Gaussian is
+ * copied to out[off_i]; a split one writes (p + eps v_min, o/2) to off_i and
+ * (p - eps v_min, o/2) to off_i + 1 (opacity halved in [0,1], logit re-derived;
+ * other rows copied).  *d_n_out = n + #splits.  d_lambda_min [n], d_vmin [3][n]
+ * (unit, largest-magnitude component positive), d_split [n] (nullable each).
+ * If n + #splits > out_capacity: *d_status = STEEPGS_ERR_CAPACITY, *d_n_out holds
+ * the needed size and d_out is not written. */
+steepgs_status steepgs_densify(const float* d_params, int64_t n, int32_t sh_degree, const float* d_S, float s_scale,
+                               float eps, float eps_split, float* d_out, int64_t out_capacity, int64_t* d_n_out,
+                               float* d_lambda_min, float* d_vmin, uint8_t* d_split, int32_t* d_status, void* d_ws,
+                               size_t ws_bytes, void* stream);
+
+const char* steepgs_status_string(steepgs_status s);
+const char* steepgs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STEEPGS_H */

@@ -437,6 +437,7 @@ struct Pixel {
   std::vector<Contrib> list;
   int listed;  // how many entries of the tile list were examined (incl. the stopping one)
   bool ambig;  // a cut-off decision within the ambiguity band
+  std::vector<int> amb_ids;  // entries whose own cut-off decision is within the band
 };
 
 constexpr double kAlphaBand = 1e-5;  // relative band around alpha_min / alpha_max
@@ -449,21 +450,30 @@ void blend_pixel(const View& view, int u, int v, Pixel& px) {
   double T = 1.0;
   px.C[0] = px.C[1] = px.C[2] = 0.0;
   px.list.clear();
+  px.amb_ids.clear();
   px.ambig = false;
   px.listed = (int)lst.size();
   for (size_t j = 0; j < lst.size(); ++j) {
     const Proj<double>& g = view.rec[lst[j]];
     double a = alpha_raw(g.mx, g.my, g.A00, g.A01, g.A11, g.o, (double)u, (double)v);
     bool clamped = false;
-    if (opt.alpha_max < 1.0 && std::fabs(a - opt.alpha_max) <= kAlphaBand * opt.alpha_max) px.ambig = true;
+    bool amb = false;
+    if (opt.alpha_max < 1.0 && std::fabs(a - opt.alpha_max) <= kAlphaBand * opt.alpha_max) amb = true;
     if (a > opt.alpha_max) {
       a = opt.alpha_max;
       clamped = true;
     }
-    if (opt.alpha_min > 0.0 && std::fabs(a - opt.alpha_min) <= kAlphaBand * opt.alpha_min) px.ambig = true;
+    if (opt.alpha_min > 0.0 && std::fabs(a - opt.alpha_min) <= kAlphaBand * opt.alpha_min) amb = true;
+    if (amb) {
+      px.ambig = true;
+      px.amb_ids.push_back(lst[j]);
+    }
     if (a < opt.alpha_min) continue;
     double Tn = T * (1.0 - a);
-    if (opt.t_min > 0.0 && std::fabs(Tn - opt.t_min) <= kTBand * opt.t_min) px.ambig = true;
+    if (opt.t_min > 0.0 && std::fabs(Tn - opt.t_min) <= kTBand * opt.t_min) {
+      px.ambig = true;
+      px.amb_ids.push_back(lst[j]);
+    }
     if (Tn < opt.t_min) {
       px.listed = (int)j + 1;
       break;
@@ -564,6 +574,13 @@ void lift(const float* params, int64_t n, int deg, int64_t i, const Cam& cam, co
 }
 
 double sgn(double x) { return (x > 0.0) - (x < 0.0); }
+
+// A flipped decision in a pixel can change the gradient of that pixel's
+// contributors and of the entry whose decision flipped; mark those.
+void mark_affected(const Pixel& px, uint8_t* flags) {
+  for (const Contrib& c : px.list) flags[c.g] = 1;
+  for (int g : px.amb_ids) flags[g] = 1;
+}
 
 // ---------------------------------------------------------------------------
 // symmetric 3x3 eigen-decomposition by cyclic Jacobi rotations
@@ -747,10 +764,7 @@ int orc_forward_backward(const float* params, int64_t n, int deg, const float* c
           if (std::fabs(diff) < sign_band) amb = true;
         }
         if (pix_ambig) pix_ambig[pid] = amb;
-        if (amb && gauss_ambig) {
-          const std::vector<int>& lst = view.tiles[(size_t)(y / opt.th) * cam.tiles_x + (x / opt.tw)];
-          for (int j = 0; j < px.listed; ++j) gauss_ambig[lst[j]] = 1;
-        }
+        if (amb && gauss_ambig) mark_affected(px, gauss_ambig);
         backward_pixel(view, x, y, px, dLdC, acc, nullptr);
       }
     if (!target) continue;
@@ -876,10 +890,7 @@ int orc_grads_sampled(const float* params, int64_t n, int deg, const float* cam_
               dLdC[ch] = sgn(diff) * inv;
               if (std::fabs(diff) < sign_band) amb = true;
             }
-            if (amb) {
-              const std::vector<int>& lst = view.tiles[(size_t)ty * cam.tiles_x + tx];
-              for (int j = 0; j < px.listed; ++j) gamb[lst[j]] = 1;
-            }
+            if (amb) mark_affected(px, gamb.data());
             backward_pixel(view, x, y, px, dLdC, acc, &want);
           }
       }

@@ -1,0 +1,229 @@
+// Stage 5: Steepest Density Control (Theorem 2, Algorithm 1) with the
+// closed-form 3x3 eigensolve of App. A.3.
+//
+// Kernel 1, one thread per Gaussian: S' = s_scale * S, smallest eigenpair by
+// the trigonometric root formula (fp64), split flag lambda_min < eps_split.
+// An exclusive scan of the flags places the output: Gaussian i lands at
+// i + (#splits before i), a split one occupies two slots.  Kernel 2 scatters
+// the parent, or the two offspring p +/- eps v_min with opacity o/2 (the
+// logit re-derived) and every other attribute copied.
+#include "common.h"
+#include "scan.h"
+
+namespace sg {
+
+// smallest eigenpair of a symmetric 3x3 matrix given as xx xy xz yy yz zz
+SG_DEV void eig3_min(const double s[6], double& lam_min, double v[3]) {
+  const double a00 = s[0], a01 = s[1], a02 = s[2], a11 = s[3], a12 = s[4], a22 = s[5];
+  const double q = (a00 + a11 + a22) / 3.0;
+  const double b00 = a00 - q, b11 = a11 - q, b22 = a22 - q;
+  const double p2 = b00 * b00 + b11 * b11 + b22 * b22 + 2.0 * (a01 * a01 + a02 * a02 + a12 * a12);
+  v[0] = 1.0;
+  v[1] = 0.0;
+  v[2] = 0.0;
+  if (!(p2 > 0.0)) {  // A = q I: every vector is an eigenvector
+    lam_min = q;
+    return;
+  }
+  const double p = sqrt(p2 / 6.0);
+  const double ip = 1.0 / p;
+  // B = (A - q I) / p;  det(B) / 2 = cos(3 theta)
+  const double c00 = b00 * ip, c11 = b11 * ip, c22 = b22 * ip, c01 = a01 * ip, c02 = a02 * ip, c12 = a12 * ip;
+  const double detB = c00 * (c11 * c22 - c12 * c12) - c01 * (c01 * c22 - c12 * c02) + c02 * (c01 * c12 - c11 * c02);
+  double r = 0.5 * detB;
+  r = r < -1.0 ? -1.0 : (r > 1.0 ? 1.0 : r);
+  const double phi = acos(r) / 3.0;
+  // roots q + 2 p cos(phi + 2 k pi / 3); k = 1 is the smallest
+  lam_min = q + 2.0 * p * cos(phi + 2.0943951023931957);  // 2 pi / 3
+  // eigenvector: null direction of A - lambda I from the largest row cross product
+  const double r0[3] = {a00 - lam_min, a01, a02};
+  const double r1[3] = {a01, a11 - lam_min, a12};
+  const double r2[3] = {a02, a12, a22 - lam_min};
+  double c[3][3];
+  const double* rows[3][2] = {{r0, r1}, {r0, r2}, {r1, r2}};
+  double best = -1.0;
+  int bi = 0;
+  for (int k = 0; k < 3; ++k) {
+    const double* u = rows[k][0];
+    const double* w = rows[k][1];
+    c[k][0] = u[1] * w[2] - u[2] * w[1];
+    c[k][1] = u[2] * w[0] - u[0] * w[2];
+    c[k][2] = u[0] * w[1] - u[1] * w[0];
+    const double nn = c[k][0] * c[k][0] + c[k][1] * c[k][1] + c[k][2] * c[k][2];
+    if (nn > best) {
+      best = nn;
+      bi = k;
+    }
+  }
+  const double scale2 = p2 * p2;  // |A - q I|^4 sets the scale of a cross product's square norm
+  if (best > 1e-24 * scale2) {
+    const double inv = 1.0 / sqrt(best);
+    for (int k = 0; k < 3; ++k) v[k] = c[bi][k] * inv;
+  } else {
+    // lambda_min repeated: A - lambda I has rank <= 1; any unit vector
+    // orthogonal to its largest row is an eigenvector
+    const double* rr[3] = {r0, r1, r2};
+    int br = 0;
+    double bn = -1.0;
+    for (int k = 0; k < 3; ++k) {
+      const double nn = rr[k][0] * rr[k][0] + rr[k][1] * rr[k][1] + rr[k][2] * rr[k][2];
+      if (nn > bn) {
+        bn = nn;
+        br = k;
+      }
+    }
+    if (bn > 1e-24 * p2) {
+      const double* u = rr[br];
+      int ax = 0;  // axis least aligned with u
+      if (fabs(u[1]) < fabs(u[ax])) ax = 1;
+      if (fabs(u[2]) < fabs(u[ax])) ax = 2;
+      const double e[3] = {ax == 0 ? 1.0 : 0.0, ax == 1 ? 1.0 : 0.0, ax == 2 ? 1.0 : 0.0};
+      double t[3] = {u[1] * e[2] - u[2] * e[1], u[2] * e[0] - u[0] * e[2], u[0] * e[1] - u[1] * e[0]};
+      const double inv = 1.0 / sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+      for (int k = 0; k < 3; ++k) v[k] = t[k] * inv;
+    }
+  }
+  // canonical sign: largest-magnitude component positive (ties: lowest index)
+  int big = 0;
+  if (fabs(v[1]) > fabs(v[big])) big = 1;
+  if (fabs(v[2]) > fabs(v[big])) big = 2;
+  if (v[big] < 0.0) {
+    v[0] = -v[0];
+    v[1] = -v[1];
+    v[2] = -v[2];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_densify_eig(const float* __restrict__ S, int64_t n, float s_scale,
+                                                     float eps_split, float* __restrict__ lam_out,
+                                                     float* __restrict__ v_out, uint32_t* __restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s[6];
+  for (int k = 0; k < 6; ++k) s[k] = (double)s_scale * (double)S[k * n + i];
+  double lam, v[3];
+  eig3_min(s, lam, v);
+  lam_out[i] = (float)lam;
+  for (int k = 0; k < 3; ++k) v_out[k * n + i] = (float)v[k];
+  flag[i] = (lam < (double)eps_split) ? 1u : 0u;
+}
+
+struct LoadFlags {
+  const uint32_t* f;
+  SG_DEV uint32_t operator()(int64_t i) const { return f[i]; }
+};
+
+__global__ void k_densify_total(const uint32_t* __restrict__ total, int64_t n, int64_t cap, int64_t* __restrict__ n_out,
+                                int32_t* __restrict__ status) {
+  const int64_t need = n + (int64_t)*total;
+  *n_out = need;
+  *status = need > cap ? (int32_t)STEEPGS_ERR_CAPACITY : (int32_t)STEEPGS_OK;
+}
+
+__global__ void __launch_bounds__(256) k_densify_scatter(const float* __restrict__ params, int64_t n, int F,
+                                                         const uint32_t* __restrict__ flag,
+                                                         const uint32_t* __restrict__ before,
+                                                         const float* __restrict__ vmin, float eps,
+                                                         float* __restrict__ out, int64_t cap,
+                                                         const int32_t* __restrict__ status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || *status != STEEPGS_OK) return;
+  const int64_t o = i + (int64_t)before[i];
+  const bool split = flag[i] != 0u;
+  for (int f = 0; f < F; ++f) {
+    const float x = params[(int64_t)f * n + i];
+    out[(int64_t)f * cap + o] = x;
+    if (split) out[(int64_t)f * cap + o + 1] = x;
+  }
+  if (!split) return;
+  for (int k = 0; k < 3; ++k) {
+    const double p = params[(int64_t)k * n + i];
+    const double d = (double)eps * (double)vmin[k * n + i];
+    out[(int64_t)k * cap + o] = (float)(p + d);
+    out[(int64_t)k * cap + o + 1] = (float)(p - d);
+  }
+  // opacity halved in [0, 1]; stored as a logit
+  const double op = 1.0 / (1.0 + exp(-(double)params[(int64_t)STEEPGS_ROW_OPACITY * n + i]));
+  const double half = 0.5 * op;
+  const float logit = (float)log(half / (1.0 - half));
+  out[(int64_t)STEEPGS_ROW_OPACITY * cap + o] = logit;
+  out[(int64_t)STEEPGS_ROW_OPACITY * cap + o + 1] = logit;
+}
+
+struct DensWs {
+  float* lam;
+  float* vmin;
+  uint32_t* flag;
+  uint32_t* before;
+  uint32_t* partials;
+};
+
+static size_t densify_layout(void* base, int64_t n, DensWs& w) {
+  Carver c(base);
+  w.lam = c.take<float>(n);
+  w.vmin = c.take<float>(3 * n);
+  w.flag = c.take<uint32_t>(n);
+  w.before = c.take<uint32_t>(n);
+  w.partials = c.take<uint32_t>(scan_partials_count(n) + 1);
+  return c.used + 256;
+}
+
+size_t densify_workspace(int64_t n) {
+  DensWs w;
+  return densify_layout(nullptr, n, w);
+}
+
+__global__ void k_copy_f32(const float* __restrict__ a, float* __restrict__ b, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) b[i] = a[i];
+}
+
+__global__ void k_flag_u8(const uint32_t* __restrict__ f, uint8_t* __restrict__ o, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) o[i] = (uint8_t)f[i];
+}
+
+__global__ void k_densify_empty(int64_t* n_out, int32_t* status) {
+  *n_out = 0;
+  *status = STEEPGS_OK;
+}
+
+}  // namespace sg
+
+using namespace sg;
+
+extern "C" steepgs_status steepgs_densify(const float* d_params, int64_t n, int32_t sh_degree, const float* d_S,
+                                          float s_scale, float eps, float eps_split, float* d_out,
+                                          int64_t out_capacity, int64_t* d_n_out, float* d_lambda_min, float* d_vmin,
+                                          uint8_t* d_split, int32_t* d_status, void* d_ws, size_t ws_bytes,
+                                          void* stream) {
+  if (n < 0 || sh_degree < 0 || sh_degree > 3 || out_capacity < 0 || !d_n_out || !d_status)
+    return STEEPGS_ERR_INVALID_ARG;
+  if (n >= (int64_t)1 << 31) return STEEPGS_ERR_INVALID_ARG;
+  hipStream_t st = as_stream(stream);
+  if (n == 0) {
+    hipLaunchKernelGGL(k_densify_empty, dim3(1), dim3(1), 0, st, d_n_out, d_status);
+    SG_TRY_LAUNCH();
+    return STEEPGS_OK;
+  }
+  if (!d_params || !d_S || (out_capacity > 0 && !d_out)) return STEEPGS_ERR_INVALID_ARG;
+  DensWs w;
+  const size_t need = densify_layout(nullptr, n, w);
+  if (!d_ws || ws_bytes < need) return STEEPGS_ERR_WORKSPACE;
+  densify_layout(d_ws, n, w);
+  const int F = STEEPGS_NUM_PARAMS(sh_degree);
+  const unsigned nb = (unsigned)ceil_div(n, 256);
+  hipLaunchKernelGGL(k_densify_eig, dim3(nb), dim3(256), 0, st, d_S, n, s_scale, eps_split, w.lam, w.vmin, w.flag);
+  if (exclusive_scan<LoadFlags, uint32_t, uint32_t>(LoadFlags{w.flag}, n, w.before, w.partials, st) != hipSuccess)
+    return STEEPGS_ERR_HIP;
+  hipLaunchKernelGGL(k_densify_total, dim3(1), dim3(1), 0, st, w.partials + scan_partials_count(n), n, out_capacity,
+                     d_n_out, d_status);
+  if (out_capacity > 0)
+    hipLaunchKernelGGL(k_densify_scatter, dim3(nb), dim3(256), 0, st, d_params, n, F, w.flag, w.before, w.vmin, eps,
+                       d_out, out_capacity, d_status);
+  if (d_lambda_min) hipLaunchKernelGGL(k_copy_f32, dim3(nb), dim3(256), 0, st, w.lam, d_lambda_min, n);
+  if (d_vmin) hipLaunchKernelGGL(k_copy_f32, dim3((unsigned)ceil_div(3 * n, 256)), dim3(256), 0, st, w.vmin, d_vmin, 3 * n);
+  if (d_split) hipLaunchKernelGGL(k_flag_u8, dim3(nb), dim3(256), 0, st, w.flag, d_split, n);
+  SG_TRY_LAUNCH();
+  return STEEPGS_OK;
+}

@@ -1,0 +1,141 @@
+// Stage 1: projection of every Gaussian through every camera (Sec. 3,
+// Eqs. sigma_3D and sigma_2D).  One thread per Gaussian loops over the V
+// views, so the parameters are read from HBM once per batch, not once per
+// view.
+#include "projection.h"
+
+namespace sg {
+
+__global__ void __launch_bounds__(256) k_project(const float* __restrict__ params, int64_t n, int deg,
+                                                 const steepgs_camera* __restrict__ cams, int V, steepgs_opts opt,
+                                                 steepgs_splat* __restrict__ out, uint32_t* __restrict__ tiles) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Gauss g;
+  load_gauss(params, n, i, g);
+  for (int v = 0; v < V; ++v) {
+    CamD cam;
+    load_cam(cams[v], cam);
+    ViewProj pv;
+    const int64_t r = (int64_t)v * n + i;
+    steepgs_splat s;
+    uint32_t count = 0;
+    if (project_view(g, params, n, i, deg, cam, opt, pv, true)) {
+      s.mean_x = (float)pv.mx;
+      s.mean_y = (float)pv.my;
+      s.conic_a = (float)pv.A00;
+      s.conic_b = (float)pv.A01;
+      s.conic_c = (float)pv.A11;
+      s.opacity = (float)g.o;
+      s.rgb[0] = (float)pv.rgb[0];
+      s.rgb[1] = (float)pv.rgb[1];
+      s.rgb[2] = (float)pv.rgb[2];
+      s.depth = (float)pv.pc[2];
+      s.rect_lo = (uint32_t)pv.rect[0] | ((uint32_t)pv.rect[1] << 16);
+      s.rect_hi = (uint32_t)pv.rect[2] | ((uint32_t)pv.rect[3] << 16);
+      count = (uint32_t)((pv.rect[2] - pv.rect[0] + 1) * (pv.rect[3] - pv.rect[1] + 1));
+    } else {
+      s.mean_x = s.mean_y = 0.f;
+      s.conic_a = s.conic_b = s.conic_c = 0.f;
+      s.opacity = 0.f;
+      s.rgb[0] = s.rgb[1] = s.rgb[2] = 0.f;
+      s.depth = 0.f;
+      s.rect_lo = 1u;  // x0 = 1 > x1 = 0: empty
+      s.rect_hi = 0u;
+    }
+    // three 16-byte stores
+    float4* dst = reinterpret_cast<float4*>(out + r);
+    const float4* src = reinterpret_cast<const float4*>(&s);
+    dst[0] = src[0];
+    dst[1] = src[1];
+    dst[2] = src[2];
+    tiles[r] = count;
+  }
+}
+
+}  // namespace sg
+
+using namespace sg;
+
+extern "C" steepgs_status steepgs_project(const float* d_params, int64_t n, int32_t sh_degree,
+                                          const steepgs_camera* d_cams, int32_t V, const steepgs_opts* opts,
+                                          steepgs_splat* d_splats, uint32_t* d_tiles_touched, void* stream) {
+  if (n < 0 || V <= 0 || sh_degree < 0 || sh_degree > 3 || !opts_ok(opts)) return STEEPGS_ERR_INVALID_ARG;
+  if (n == 0) return STEEPGS_OK;
+  if (!d_params || !d_cams || !d_splats || !d_tiles_touched) return STEEPGS_ERR_INVALID_ARG;
+  if ((int64_t)V * n >= (int64_t)UINT32_MAX) return STEEPGS_ERR_INVALID_ARG;  // record ids are 32-bit
+  const int threads = 256;
+  hipLaunchKernelGGL(k_project, dim3((unsigned)ceil_div(n, threads)), dim3(threads), 0, as_stream(stream), d_params,
+                     n, sh_degree, d_cams, V, *opts, d_splats, d_tiles_touched);
+  SG_TRY_LAUNCH();
+  return STEEPGS_OK;
+}
+
+extern "C" steepgs_status steepgs_layout_cameras(steepgs_camera* cams, int32_t V, const steepgs_opts* opts,
+                                                 int64_t* total_pixels, int32_t* total_tiles) {
+  if (!cams || V <= 0 || !opts_ok(opts)) return STEEPGS_ERR_INVALID_ARG;
+  int64_t poff = 0, toff = 0;
+  for (int v = 0; v < V; ++v) {
+    steepgs_camera& c = cams[v];
+    if (c.width <= 0 || c.height <= 0 || c.width > 65535 * 8 || c.height > 65535 * 8) return STEEPGS_ERR_INVALID_ARG;
+    if (c.model != 0 && c.model != 1) return STEEPGS_ERR_INVALID_ARG;
+    c.tiles_x = (c.width + opts->tile_w - 1) / opts->tile_w;
+    c.tiles_y = (c.height + opts->tile_h - 1) / opts->tile_h;
+    c.tile_offset = (int32_t)toff;
+    c.pixel_offset = poff;
+    toff += (int64_t)c.tiles_x * c.tiles_y;
+    poff += (int64_t)c.width * c.height;
+    if (toff >= (int64_t)1 << 31) return STEEPGS_ERR_INVALID_ARG;
+  }
+  if (total_pixels) *total_pixels = poff;
+  if (total_tiles) *total_tiles = (int32_t)toff;
+  return STEEPGS_OK;
+}
+
+extern "C" const char* steepgs_status_string(steepgs_status s) {
+  switch (s) {
+    case STEEPGS_OK: return "ok";
+    case STEEPGS_ERR_INVALID_ARG: return "invalid argument";
+    case STEEPGS_ERR_CAPACITY: return "output capacity exceeded";
+    case STEEPGS_ERR_HIP: return "HIP runtime error";
+    case STEEPGS_ERR_WORKSPACE: return "workspace too small";
+  }
+  return "unknown status";
+}
+
+extern "C" const char* steepgs_version(void) { return "steepgs-gfx950 0.1"; }
+
+namespace sg {
+int device_cu_count() {
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cache[dev] == 0) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    cache[dev] = cus;
+  }
+  return cache[dev];
+}
+}  // namespace sg
+
+namespace sg {
+size_t sort_workspace(int64_t m, uint64_t cap);
+size_t render_fwd_workspace();
+size_t render_bwd_workspace(int64_t m);
+size_t densify_workspace(int64_t n);
+}  // namespace sg
+
+extern "C" size_t steepgs_workspace_size(int32_t stage, int64_t n, int32_t V, uint64_t capacity,
+                                         int32_t total_tiles) {
+  (void)total_tiles;
+  if (n < 0 || V < 0) return 0;
+  const int64_t m = (int64_t)V * n;
+  switch (stage) {
+    case 1: return sg::sort_workspace(m, capacity);
+    case 2: return sg::render_fwd_workspace();
+    case 3: return sg::render_bwd_workspace(m);
+    case 4: return sg::densify_workspace(n);
+    default: return 0;
+  }
+}

@@ -1,0 +1,270 @@
+// fp64 projection of one Gaussian through one camera (Sec. 3: Eq. sigma_3D,
+// Eq. sigma_2D and the footnote on Pi).  Used by the projection kernel and,
+// to recompute the same quantities, by the projection backward.
+//
+// Every operation that decides something discrete (culling, footprint
+// radius, tile rectangle, depth key, colour clamp) is evaluated in fp64 with
+// contraction disabled and a fixed operation order, so the decisions are
+// reproducible from the fp32 inputs.
+#pragma once
+
+#include "common.h"
+
+namespace sg {
+
+// Real spherical harmonics, Condon-Shortley phase, index k = l*l + l + m,
+// written as polynomials on the unit sphere.  Normalisation constants:
+constexpr double kSH0 = 0.28209479177387814;   // sqrt(1/(4 pi))
+constexpr double kSH1 = 0.4886025119029199;    // sqrt(3/(4 pi))
+constexpr double kSH2a = 1.0925484305920792;   // sqrt(15/pi) / 2
+constexpr double kSH2b = 0.31539156525252005;  // sqrt(5/pi) / 4
+constexpr double kSH2c = 0.5462742152960396;   // sqrt(15/pi) / 4
+constexpr double kSH3a = 0.5900435899266435;   // sqrt(35/(2 pi)) / 4
+constexpr double kSH3b = 2.890611442640554;    // sqrt(105/pi) / 2
+constexpr double kSH3c = 0.4570457994644658;   // sqrt(21/(2 pi)) / 4
+constexpr double kSH3d = 0.3731763325901154;   // sqrt(7/pi) / 4
+constexpr double kSH3e = 1.445305721320277;    // sqrt(105/pi) / 4
+
+SG_DEV void sh_eval(int deg, double x, double y, double z, double* Y) {
+  Y[0] = kSH0;
+  if (deg < 1) return;
+  Y[1] = -kSH1 * y;
+  Y[2] = kSH1 * z;
+  Y[3] = -kSH1 * x;
+  if (deg < 2) return;
+  const double xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = kSH2a * x * y;
+  Y[5] = -kSH2a * y * z;
+  Y[6] = kSH2b * (2.0 * zz - xx - yy);
+  Y[7] = -kSH2a * x * z;
+  Y[8] = kSH2c * (xx - yy);
+  if (deg < 3) return;
+  Y[9] = -kSH3a * y * (3.0 * xx - yy);
+  Y[10] = kSH3b * x * y * z;
+  Y[11] = -kSH3c * y * (4.0 * zz - xx - yy);
+  Y[12] = kSH3d * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
+  Y[13] = -kSH3c * x * (4.0 * zz - xx - yy);
+  Y[14] = kSH3e * z * (xx - yy);
+  Y[15] = -kSH3a * x * (xx - 3.0 * yy);
+}
+
+// g += sum_k w_k * grad_(x,y,z) Y_k   (polynomial gradient; the caller
+// projects it onto the sphere's tangent plane)
+SG_DEV void sh_grad(int deg, double x, double y, double z, const double* w, double g[3]) {
+  if (deg < 1) return;
+  g[1] += -kSH1 * w[1];
+  g[2] += kSH1 * w[2];
+  g[0] += -kSH1 * w[3];
+  if (deg < 2) return;
+  const double xx = x * x, yy = y * y, zz = z * z;
+  g[0] += kSH2a * y * w[4];
+  g[1] += kSH2a * x * w[4];
+  g[1] += -kSH2a * z * w[5];
+  g[2] += -kSH2a * y * w[5];
+  g[0] += -2.0 * kSH2b * x * w[6];
+  g[1] += -2.0 * kSH2b * y * w[6];
+  g[2] += 4.0 * kSH2b * z * w[6];
+  g[0] += -kSH2a * z * w[7];
+  g[2] += -kSH2a * x * w[7];
+  g[0] += 2.0 * kSH2c * x * w[8];
+  g[1] += -2.0 * kSH2c * y * w[8];
+  if (deg < 3) return;
+  // Y9 = -a (3 x^2 y - y^3)
+  g[0] += -kSH3a * 6.0 * x * y * w[9];
+  g[1] += -kSH3a * (3.0 * xx - 3.0 * yy) * w[9];
+  // Y10 = b x y z
+  g[0] += kSH3b * y * z * w[10];
+  g[1] += kSH3b * x * z * w[10];
+  g[2] += kSH3b * x * y * w[10];
+  // Y11 = -c (4 y z^2 - x^2 y - y^3)
+  g[0] += kSH3c * 2.0 * x * y * w[11];
+  g[1] += -kSH3c * (4.0 * zz - xx - 3.0 * yy) * w[11];
+  g[2] += -kSH3c * 8.0 * y * z * w[11];
+  // Y12 = d (2 z^3 - 3 x^2 z - 3 y^2 z)
+  g[0] += -kSH3d * 6.0 * x * z * w[12];
+  g[1] += -kSH3d * 6.0 * y * z * w[12];
+  g[2] += kSH3d * (6.0 * zz - 3.0 * xx - 3.0 * yy) * w[12];
+  // Y13 = -c (4 x z^2 - x^3 - x y^2)
+  g[0] += -kSH3c * (4.0 * zz - 3.0 * xx - yy) * w[13];
+  g[1] += kSH3c * 2.0 * x * y * w[13];
+  g[2] += -kSH3c * 8.0 * x * z * w[13];
+  // Y14 = e (x^2 z - y^2 z)
+  g[0] += kSH3e * 2.0 * x * z * w[14];
+  g[1] += -kSH3e * 2.0 * y * z * w[14];
+  g[2] += kSH3e * (xx - yy) * w[14];
+  // Y15 = -a (x^3 - 3 x y^2)
+  g[0] += -kSH3a * (3.0 * xx - 3.0 * yy) * w[15];
+  g[1] += kSH3a * 6.0 * x * y * w[15];
+}
+
+// view-independent part of a Gaussian
+struct Gauss {
+  double p[3];
+  double qw, qx, qy, qz, qn;  // unit quaternion and the input's norm
+  double R[3][3];             // rotation of the unit quaternion
+  double s[3];                // scales
+  double Sig[3][3];           // R diag(s^2) R^T
+  double o;                   // opacity
+};
+
+SG_DEV void load_gauss(const float* __restrict__ params, int64_t n, int64_t i, Gauss& g) {
+#pragma clang fp contract(off)
+  for (int k = 0; k < 3; ++k) g.p[k] = (double)params[(STEEPGS_ROW_MEAN + k) * n + i];
+  const double w0 = params[(STEEPGS_ROW_QUAT + 0) * n + i], x0 = params[(STEEPGS_ROW_QUAT + 1) * n + i];
+  const double y0 = params[(STEEPGS_ROW_QUAT + 2) * n + i], z0 = params[(STEEPGS_ROW_QUAT + 3) * n + i];
+  g.qn = sqrt(w0 * w0 + x0 * x0 + y0 * y0 + z0 * z0);
+  const double w = w0 / g.qn, x = x0 / g.qn, y = y0 / g.qn, z = z0 / g.qn;
+  g.qw = w;
+  g.qx = x;
+  g.qy = y;
+  g.qz = z;
+  g.R[0][0] = 1.0 - 2.0 * (y * y + z * z);
+  g.R[0][1] = 2.0 * (x * y - w * z);
+  g.R[0][2] = 2.0 * (x * z + w * y);
+  g.R[1][0] = 2.0 * (x * y + w * z);
+  g.R[1][1] = 1.0 - 2.0 * (x * x + z * z);
+  g.R[1][2] = 2.0 * (y * z - w * x);
+  g.R[2][0] = 2.0 * (x * z - w * y);
+  g.R[2][1] = 2.0 * (y * z + w * x);
+  g.R[2][2] = 1.0 - 2.0 * (x * x + y * y);
+  double s2[3];
+  for (int k = 0; k < 3; ++k) {
+    g.s[k] = exp((double)params[(STEEPGS_ROW_LOG_SCALE + k) * n + i]);
+    s2[k] = g.s[k] * g.s[k];
+  }
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      g.Sig[a][b] = g.R[a][0] * s2[0] * g.R[b][0] + g.R[a][1] * s2[1] * g.R[b][1] + g.R[a][2] * s2[2] * g.R[b][2];
+  g.o = 1.0 / (1.0 + exp(-(double)params[STEEPGS_ROW_OPACITY * n + i]));
+}
+
+// camera in fp64
+struct CamD {
+  double R[9], t[3], fx, fy, cx, cy;
+  int W, H, model, tiles_x, tiles_y;
+};
+
+SG_DEV void load_cam(const steepgs_camera& c, CamD& d) {
+  for (int k = 0; k < 9; ++k) d.R[k] = c.R[k];
+  for (int k = 0; k < 3; ++k) d.t[k] = c.t[k];
+  d.fx = c.fx;
+  d.fy = c.fy;
+  d.cx = c.cx;
+  d.cy = c.cy;
+  d.W = c.width;
+  d.H = c.height;
+  d.model = c.model;
+  d.tiles_x = c.tiles_x;
+  d.tiles_y = c.tiles_y;
+}
+
+// per (Gaussian, view) quantities
+struct ViewProj {
+  double pc[3];
+  double mx, my;
+  double gx, gy;          // x/z and y/z after the frustum guard
+  bool gx_free, gy_free;  // guard inactive (derivative passes)
+  double J[2][3];         // Jacobian of the projection (guarded), or the affine map
+  double P[2][3];         // J W
+  double S2[2][2];        // Pi(Sigma) + dilation
+  double det;
+  double A00, A01, A11;  // conic
+  int rect[4];
+  double dir[3], dlen;  // unit direction from the camera centre and its length
+  double Y[16];
+  double raw[3], rgb[3];
+};
+
+// Returns false when culled.  With want_colour the SH colour is evaluated.
+SG_DEV bool project_view(const Gauss& g, const float* __restrict__ params, int64_t n, int64_t i, int deg,
+                         const CamD& cam, const steepgs_opts& opt, ViewProj& v, bool want_colour) {
+#pragma clang fp contract(off)
+  for (int r = 0; r < 3; ++r)
+    v.pc[r] = cam.R[3 * r + 0] * g.p[0] + cam.R[3 * r + 1] * g.p[1] + cam.R[3 * r + 2] * g.p[2] + cam.t[r];
+  if (!(v.pc[2] > (double)opt.near_z)) return false;
+  if (cam.model == 0) {
+    v.mx = cam.fx * (v.pc[0] / v.pc[2]) + cam.cx;
+    v.my = cam.fy * (v.pc[1] / v.pc[2]) + cam.cy;
+    v.gx = v.pc[0] / v.pc[2];
+    v.gy = v.pc[1] / v.pc[2];
+    v.gx_free = v.gy_free = true;
+    const double guard = opt.frustum_guard;
+    if (guard > 0.0) {
+      const double limx = guard * (0.5 * cam.W / cam.fx);
+      const double limy = guard * (0.5 * cam.H / cam.fy);
+      if (v.gx < -limx) { v.gx = -limx; v.gx_free = false; }
+      if (v.gx > limx) { v.gx = limx; v.gx_free = false; }
+      if (v.gy < -limy) { v.gy = -limy; v.gy_free = false; }
+      if (v.gy > limy) { v.gy = limy; v.gy_free = false; }
+    }
+    v.J[0][0] = cam.fx / v.pc[2];
+    v.J[0][1] = 0.0;
+    v.J[0][2] = -(cam.fx * v.gx) / v.pc[2];
+    v.J[1][0] = 0.0;
+    v.J[1][1] = cam.fy / v.pc[2];
+    v.J[1][2] = -(cam.fy * v.gy) / v.pc[2];
+  } else {
+    v.mx = cam.fx * v.pc[0] + cam.cx;
+    v.my = cam.fy * v.pc[1] + cam.cy;
+    v.gx = v.gy = 0.0;
+    v.gx_free = v.gy_free = false;
+    v.J[0][0] = cam.fx;
+    v.J[0][1] = 0.0;
+    v.J[0][2] = 0.0;
+    v.J[1][0] = 0.0;
+    v.J[1][1] = cam.fy;
+    v.J[1][2] = 0.0;
+  }
+  for (int a = 0; a < 2; ++a)
+    for (int c = 0; c < 3; ++c) v.P[a][c] = v.J[a][0] * cam.R[0 + c] + v.J[a][1] * cam.R[3 + c] + v.J[a][2] * cam.R[6 + c];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      double acc = 0.0;
+      for (int c = 0; c < 3; ++c)
+        for (int d = 0; d < 3; ++d) acc = acc + v.P[a][c] * g.Sig[c][d] * v.P[b][d];
+      v.S2[a][b] = acc;
+    }
+  v.S2[0][0] = v.S2[0][0] + (double)opt.dilation;
+  v.S2[1][1] = v.S2[1][1] + (double)opt.dilation;
+  v.det = v.S2[0][0] * v.S2[1][1] - v.S2[0][1] * v.S2[1][0];
+  if (!(v.det > 0.0)) return false;
+  v.A00 = v.S2[1][1] / v.det;
+  v.A01 = -v.S2[0][1] / v.det;
+  v.A11 = v.S2[0][0] / v.det;
+
+  const double a = v.S2[0][0], b = v.S2[0][1], c = v.S2[1][1];
+  const double half = 0.5 * (a - c);
+  const double lam = 0.5 * (a + c) + sqrt(half * half + b * b);
+  const double r = ceil((double)opt.radius_sigmas * sqrt(lam));
+  const double tw = opt.tile_w, th = opt.tile_h;
+  double x0 = floor((v.mx - r) / tw), x1 = floor((v.mx + r) / tw);
+  double y0 = floor((v.my - r) / th), y1 = floor((v.my + r) / th);
+  x0 = fmax(x0, 0.0);
+  y0 = fmax(y0, 0.0);
+  x1 = fmin(x1, (double)(cam.tiles_x - 1));
+  y1 = fmin(y1, (double)(cam.tiles_y - 1));
+  if (x0 > x1 || y0 > y1) return false;
+  v.rect[0] = (int)x0;
+  v.rect[1] = (int)y0;
+  v.rect[2] = (int)x1;
+  v.rect[3] = (int)y1;
+
+  if (!want_colour) return true;
+  double campos[3];
+  for (int k = 0; k < 3; ++k) campos[k] = -(cam.R[0 + k] * cam.t[0] + cam.R[3 + k] * cam.t[1] + cam.R[6 + k] * cam.t[2]);
+  double d[3] = {g.p[0] - campos[0], g.p[1] - campos[1], g.p[2] - campos[2]};
+  v.dlen = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  for (int k = 0; k < 3; ++k) v.dir[k] = d[k] / v.dlen;
+  sh_eval(deg, v.dir[0], v.dir[1], v.dir[2], v.Y);
+  const int nb = (deg + 1) * (deg + 1);
+  for (int ch = 0; ch < 3; ++ch) {
+    double acc = 0.0;
+    for (int k = 0; k < nb; ++k) acc = acc + (double)params[(STEEPGS_ROW_SH + 3 * k + ch) * n + i] * v.Y[k];
+    acc = acc + 0.5;
+    v.raw[ch] = acc;
+    v.rgb[ch] = acc < 0.0 ? 0.0 : acc;
+  }
+  return true;
+}
+
+}  // namespace sg

@@ -1,0 +1,104 @@
+// Device-wide exclusive prefix sum (reduce, scan partials, scan) used by the
+// instance sort and by densification.  Sizes are host-known; nothing here
+// reads a device count.
+#pragma once
+
+#include "common.h"
+
+namespace sg {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;  // elements per block
+
+// exclusive scan over the 256 threads of a block; returns the block total
+template <class T>
+SG_DEV T block_exclusive_scan(T x, T* lds /*[kScanThreads/64 + 1]*/, T& total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  T inc = x;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    T y = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += y;
+  }
+  if (lane == 63) lds[wave] = inc;
+  __syncthreads();
+  T wave_off = 0, tot = 0;
+  for (int w = 0; w < kScanThreads / 64; ++w) {
+    if (w < wave) wave_off += lds[w];
+    tot += lds[w];
+  }
+  __syncthreads();
+  total = tot;
+  return wave_off + inc - x;
+}
+
+template <class Load, class Acc>
+__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(Load in, int64_t N, Acc* __restrict__ partials) {
+  __shared__ Acc lds[kScanThreads / 64 + 1];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  Acc s = 0;
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < N) s += (Acc)in(base + k);
+  Acc total;
+  block_exclusive_scan<Acc>(s, lds, total);
+  if (threadIdx.x == 0) partials[blockIdx.x] = total;
+}
+
+// single block: in-place exclusive scan of `count` partials; grand total to *total_out
+template <class Acc>
+__global__ void __launch_bounds__(kScanThreads) k_scan_partials(Acc* __restrict__ partials, int64_t count,
+                                                                  Acc* __restrict__ total_out) {
+  __shared__ Acc lds[kScanThreads / 64 + 1];
+  const int64_t per = (count + kScanThreads - 1) / kScanThreads;
+  const int64_t b = (int64_t)threadIdx.x * per;
+  Acc s = 0;
+  for (int64_t k = 0; k < per; ++k)
+    if (b + k < count) s += partials[b + k];
+  Acc total;
+  Acc run = block_exclusive_scan<Acc>(s, lds, total);
+  for (int64_t k = 0; k < per; ++k)
+    if (b + k < count) {
+      Acc x = partials[b + k];
+      partials[b + k] = run;
+      run += x;
+    }
+  if (threadIdx.x == 0 && total_out) *total_out = total;
+}
+
+template <class Load, class Acc, class Out>
+__global__ void __launch_bounds__(kScanThreads) k_scan_final(Load in, int64_t N, const Acc* __restrict__ partials,
+                                                               Out* __restrict__ out) {
+  __shared__ Acc lds[kScanThreads / 64 + 1];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  Acc v[kScanItems];
+  Acc s = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = (base + k < N) ? (Acc)in(base + k) : Acc(0);
+    s += v[k];
+  }
+  Acc total;
+  Acc run = block_exclusive_scan<Acc>(s, lds, total) + partials[blockIdx.x];
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < N) {
+      out[base + k] = (Out)run;
+      run += v[k];
+    }
+}
+
+inline size_t scan_partials_count(int64_t N) { return (size_t)ceil_div(N > 0 ? N : 1, kScanTile); }
+
+// Enqueue an exclusive scan of N elements read through `in` into `out`;
+// `partials` holds scan_partials_count(N) + 1 accumulators; the grand total
+// is left in partials[scan_partials_count(N)].
+template <class Load, class Acc, class Out>
+hipError_t exclusive_scan(Load in, int64_t N, Out* out, Acc* partials, hipStream_t st) {
+  const int64_t nb = (int64_t)scan_partials_count(N);
+  hipLaunchKernelGGL((k_scan_reduce<Load, Acc>), dim3((unsigned)nb), dim3(kScanThreads), 0, st, in, N, partials);
+  hipLaunchKernelGGL((k_scan_partials<Acc>), dim3(1), dim3(kScanThreads), 0, st, partials, nb, partials + nb);
+  hipLaunchKernelGGL((k_scan_final<Load, Acc, Out>), dim3((unsigned)nb), dim3(kScanThreads), 0, st, in, N, partials,
+                     out);
+  return hipGetLastError();
+}
+
+}  // namespace sg

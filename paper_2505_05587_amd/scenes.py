@@ -315,6 +315,12 @@ OPTS_SMOOTH = dict(OPTS_3DGS, alpha_min=0.0, alpha_max=1.0, t_min=0.0)
 
 
 def opts(mode="3dgs", **over):
+    """Raster options; real values are rounded to float32 so that a float32
+    consumer and a float64 consumer see the same numbers."""
     base = dict(OPTS_3DGS if mode == "3dgs" else OPTS_SMOOTH)
     base.update(over)
+    for k, v in list(base.items()):
+        if isinstance(v, float):
+            base[k] = float(np.float32(v))
+    base["bg"] = tuple(float(np.float32(x)) for x in base["bg"])
     return base

@@ -1,0 +1,153 @@
+"""GPU parity: every stage of the HIP path against the FP64 oracle on the same
+seeded inputs, through the C ABI.
+
+Bars: projected records within fp32 rounding of the oracle's fp64 values, and
+culling / rectangles / depth bits bit-exact; instance keys, values and tile
+ranges bit-exact; image within 1e-5 abs + 1e-4 rel; gradients and S_i within
+1e-3 of the reference norm per Gaussian and parameter group plus 1e-6 of the
+largest; lambda_min signs equal where |lambda_min| > 1e-4 |S_i|.  Pixels and
+Gaussians whose result hinges on a cut-off decision within its fp32 band
+(alpha_min, alpha_max, t_min, sign of C - target) are excluded, as the oracle
+flags them.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2505_05587_amd import scenes
+from tests.gpu_common import (assert_group_close, assert_S_close, expand_pixel_mask, image_close, run_gpu,
+                              scene_small)
+
+pytestmark = pytest.mark.gpu
+
+KINDS = ["plain_small", "sh3_pinhole", "multiview", "ortho"]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2505_05587_amd import _lib
+    _lib.lib()
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("mode", ["3dgs", "smooth"])
+def test_project_and_sort(oracle, kind, mode):
+    P, deg, cams, target = scene_small(kind)
+    opts = scenes.opts(mode)
+    print(f"\n[case] project+sort kind={kind} mode={mode} n={P.shape[1]} V={cams.V}", flush=True)
+    g = run_gpu(P, deg, cams, opts, want_keys=True)
+    pr = oracle.project(P, deg, cams, opts)
+    vis = pr["visible"]
+    np.testing.assert_array_equal(g["tiles"] > 0, vis)
+    np.testing.assert_array_equal(g["tiles"], pr["tiles"])
+    sp = g["splats"]
+    rect_lo = sp[:, 10].view(np.uint32)
+    rect_hi = sp[:, 11].view(np.uint32)
+    rect = np.stack([rect_lo & 0xFFFF, rect_lo >> 16, rect_hi & 0xFFFF, rect_hi >> 16], 1).astype(np.int32)
+    np.testing.assert_array_equal(rect[vis], pr["rect"][vis])
+    np.testing.assert_array_equal(sp[vis, 9].view(np.uint32), pr["depth_bits"][vis])
+    np.testing.assert_allclose(sp[vis, 0:2], pr["mean"][vis], rtol=2e-7, atol=1e-5)
+    np.testing.assert_allclose(sp[vis, 2:5], pr["conic"][vis], rtol=2e-6, atol=1e-12)
+    np.testing.assert_allclose(sp[vis, 5], pr["opacity"][vis], rtol=2e-7)
+    np.testing.assert_allclose(sp[vis, 6:9], pr["rgb"][vis], rtol=2e-6, atol=1e-7)
+    keys, vals, ranges = oracle.sort(P, deg, cams, opts)
+    assert g["K"] == len(keys)
+    np.testing.assert_array_equal(g["vals"], vals)
+    np.testing.assert_array_equal(g["keys"], keys)
+    np.testing.assert_array_equal(g["ranges"], ranges)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("mode", ["3dgs", "smooth"])
+def test_forward_backward(oracle, kind, mode):
+    P, deg, cams, target = scene_small(kind)
+    opts = scenes.opts(mode)
+    print(f"\n[case] fwd+bwd kind={kind} mode={mode} n={P.shape[1]} V={cams.V}", flush=True)
+    g = run_gpu(P, deg, cams, opts, target=target)
+    ref = oracle.forward_backward(P, deg, cams, opts, target)
+    pix_amb = ref["pix_ambig"]
+    assert pix_amb.mean() < 1e-3 or mode == "3dgs" and pix_amb.mean() < 5e-3
+    ok = image_close(g["image"], ref["image"], expand_pixel_mask(pix_amb, cams))
+    assert ok.all(), f"{(~ok).sum()} image values out of tolerance"
+    okT = np.abs(g["T_final"] - ref["T_final"]) <= 1e-5 + 1e-4 * ref["T_final"]
+    assert (okT | pix_amb).all()
+    np.testing.assert_allclose(g["loss"], ref["loss"], rtol=1e-4)
+    gamb = ref["gauss_ambig"]
+    assert gamb.mean() < 0.1
+    assert_group_close(g["grads"], ref["grads"], gamb, what=f"{kind}/{mode}")
+    assert_S_close(g["S6"], ref["S"], gamb)
+
+
+def test_densify_matches_oracle(oracle):
+    rng = np.random.default_rng(7)
+    n = 20000
+    P = scenes.clustered_gaussians(rng, n, 100, sh_degree=3)
+    B = rng.normal(size=(n, 3, 3)) * np.exp(rng.normal(0, 2, size=(n, 1, 1)))
+    S = (B + np.swapaxes(B, 1, 2)).astype(np.float32)
+    S[: n // 5] = np.einsum("kij,kjl->kil", B[: n // 5], np.swapaxes(B[: n // 5], 1, 2))
+    S[n // 5: n // 5 + 50] = 0.0                         # never seen: no split
+    S[n // 5 + 50: n // 5 + 100] = np.eye(3) * -2.0      # repeated eigenvalue
+    S6 = np.stack([S[:, 0, 0], S[:, 0, 1], S[:, 0, 2], S[:, 1, 1], S[:, 1, 2], S[:, 2, 2]]).astype(np.float32)
+    S9 = S.reshape(n, 9).T.astype(np.float64)
+    eps, eps_split, s_scale = np.float32(0.01), np.float32(-1e-6), np.float32(0.5)
+    ref = oracle.densify(P, 3, S9, float(s_scale), float(eps), float(eps_split))
+    from paper_2505_05587_amd import pipeline
+    dev = torch.device("cuda", 0)
+    out = pipeline.densify(torch.from_numpy(P).to(dev), 3, torch.from_numpy(np.ascontiguousarray(S6)).to(dev),
+                           float(s_scale), float(eps), float(eps_split))
+    lam = out["lambda_min"].cpu().numpy().astype(np.float64)
+    Sn = np.linalg.norm(S9 * float(s_scale), axis=0)
+    sure = np.abs(ref["lambda_min"]) > 1e-4 * Sn
+    np.testing.assert_array_equal((lam < eps_split)[sure], ref["split"][sure])
+    np.testing.assert_allclose(lam, ref["lambda_min"], atol=1e-6 * Sn.max(), rtol=1e-5)
+    split_g = out["split"].cpu().numpy().astype(bool)
+    assert out["n_out"] == n + split_g.sum()
+    # eigenvectors where lambda_min is separated from the middle eigenvalue
+    lam3, _ = oracle.eigh(S9.T.reshape(n, 3, 3) * float(s_scale))
+    gap = lam3[:, 1] - lam3[:, 0] > 1e-3 * Sn
+    v = out["vmin"].cpu().numpy().astype(np.float64)
+    cos = np.abs(np.sum(v * ref["vmin"], axis=0))
+    assert (cos[gap] >= 1 - 1e-3).all()
+    if (split_g == ref["split"]).all():
+        got = out["params"].cpu().numpy().astype(np.float64)
+        assert got.shape == ref["params"].shape
+        np.testing.assert_allclose(got[3:10], ref["params"][3:10], rtol=0, atol=0)
+        np.testing.assert_allclose(got[11:], ref["params"][11:], rtol=0, atol=0)
+        np.testing.assert_allclose(got[0:3], ref["params"][0:3], rtol=1e-6, atol=1e-6)
+        np.testing.assert_allclose(got[10], ref["params"][10], rtol=1e-5, atol=1e-6)
+    # capacity overflow reports the needed size
+    small = pipeline.densify(torch.from_numpy(P).to(dev), 3, torch.from_numpy(np.ascontiguousarray(S6)).to(dev),
+                             float(s_scale), float(eps), float(eps_split), out_capacity=n)
+    assert small["status"] == 2 and small["n_out"] == out["n_out"]
+
+
+def test_sort_capacity_overflow_and_retry(oracle):
+    P, deg, cams, target = scene_small("plain_small")
+    opts = scenes.opts("3dgs")
+    from paper_2505_05587_amd import pipeline
+    dev = torch.device("cuda", 0)
+    cb = pipeline.CameraBatch(cams, opts, dev)
+    ras = pipeline.Rasterizer(cb, deg, capacity=16)
+    fs = ras.forward(torch.from_numpy(P).to(dev))
+    keys, vals, ranges = oracle.sort(P, deg, cams, opts)
+    assert fs.K == len(keys) and ras.capacity >= len(keys)
+    np.testing.assert_array_equal(ras.vals[: fs.K].cpu().numpy().view(np.uint32), vals)
+
+
+def test_all_culled_and_empty(oracle):
+    from paper_2505_05587_amd import pipeline
+    dev = torch.device("cuda", 0)
+    rng = np.random.default_rng(3)
+    P = scenes.uniform_gaussians(rng, 50)
+    P[2] = 10.0  # all behind the camera at z = 3
+    cams = scenes.make_cameras([(0, 0, 3.0)], [(40, 24)])
+    opts = scenes.opts("3dgs", bg=(0.2, 0.4, 0.6))
+    cb = pipeline.CameraBatch(cams, opts, dev)
+    ras = pipeline.Rasterizer(cb, 0, capacity=8)
+    fs = ras.forward(torch.from_numpy(P).to(dev))
+    assert fs.K == 0
+    img = fs.image.cpu().numpy().reshape(3, 24, 40)
+    np.testing.assert_allclose(img, np.broadcast_to(np.array([0.2, 0.4, 0.6], np.float32)[:, None, None], img.shape))
+    ref = oracle.forward_backward(P, 0, cams, opts)
+    np.testing.assert_allclose(fs.image.cpu().numpy(), ref["image"], rtol=1e-6)
