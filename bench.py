@@ -1,0 +1,252 @@
+#!/usr/bin/env python3
+"""Benchmark of the SteepGS hot path on one MI355X.
+
+Workload (default): 1,000,000 clustered Gaussians (SH degree 3), 16 views of
+mixed resolution -- the batched densification step.  A step is one pass of
+project -> sort -> forward with fused L1 -> backward with splitting matrices
+-> Steepest Density Control over the whole batch.
+
+The timed region replays the HIP-graph-captured batched step K times
+(inputs resident in HBM).  The same step issued per view (V = 1 calls, S
+accumulated, then one densification) is timed beside it.  A second pass of K
+eager steps records HIP events around every kernel of interest (on the
+stream it is launched on) for the per-stage breakdown and the roofline of the
+dominant kernel.  The CPU baseline times the FP64 oracle on one view and
+scales it to the step.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "ms per fwd+bwd+split step, 1M Gaussians×16 views; batched vs per-view speedup"
+PEAK_HBM_GBS = 8000.0
+# fp32 vector peak without packed-FP32 instructions: 256 CU x 4 SIMD x 16 lanes
+# x 2 flop (FMA) x 2.4 GHz
+PEAK_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def say(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="batched_16")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-per-view", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--eps", type=float, default=1e-3)
+    return ap.parse_args()
+
+
+def time_region(fn, steps, torch):
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    return a.elapsed_time(b) / steps, wall
+
+
+def kernel_times(step, steps, torch, L):
+    """K eager steps with HIP events around each timed kernel; returns
+    {name: [ms per launch]}"""
+    events = {}
+    for w in range(len(L.TIMER_NAMES)):
+        st = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+        en = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+        for e in st + en:
+            e.record()  # creates the underlying event
+        events[w] = (st, en)
+    torch.cuda.synchronize()
+    for w, (st, en) in events.items():
+        L.steepgs_set_kernel_timer(w, st, en)
+    try:
+        for _ in range(steps):
+            step.run()
+        torch.cuda.synchronize()
+    finally:
+        for w in events:
+            L.steepgs_set_kernel_timer(w, [], [])
+    return {L.TIMER_NAMES[w]: [s.elapsed_time(e) for s, e in zip(st, en)] for w, (st, en) in events.items()}
+
+
+def cpu_baseline(scene, opts):
+    """The oracle as it stands on one view of the workload (full Gaussian set),
+    scaled to the 16-view step, plus its densification over all Gaussians."""
+    import numpy as np
+    from oracle import oracle as O
+    V = scene.cams.V
+    px = scene.cams.pixels()
+    v = int(np.argmin(np.abs(px - px.mean())))  # the view closest to the mean resolution
+    c1 = scene.cams.subset([v])
+    tg = scene.target_view(v).reshape(-1)
+    t0 = time.perf_counter()
+    r = O.forward_backward(scene.params, scene.sh_degree, c1, opts, tg)
+    t_view = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.densify(scene.params, scene.sh_degree, r["S"], 1.0, 1e-3, -1e-6)
+    t_dens = time.perf_counter() - t0
+    ms = (t_view * px.sum() / px[v] + t_dens) * 1e3
+    return {"value": round(ms, 1), "unit": "ms/step", "cores": 1, "kind": "oracle",
+            "sample": f"view {v} ({int(scene.cams.width[v])}x{int(scene.cams.height[v])}) of {V}, all "
+                      f"{scene.n} Gaussians, fwd+bwd+S in {t_view:.1f} s scaled by total/view pixels "
+                      f"({px.sum() / px[v]:.2f}x), plus densification of all Gaussians ({t_dens:.1f} s)"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (views would shard across GPUs with one "
+              "all-reduce of gradients and splitting matrices; not implemented). Run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2505_05587_amd import _lib as L
+    from paper_2505_05587_amd import scenes
+    from paper_2505_05587_amd.pipeline import CameraBatch
+    from paper_2505_05587_amd.step import BatchedStep, PerViewStep
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    say(f"device {torch.cuda.get_device_name(0)}; generating {args.workload}")
+    t0 = time.perf_counter()
+    scene = scenes.make(args.workload)
+    opts = scenes.opts("3dgs")
+    say(f"scene ready in {time.perf_counter() - t0:.1f} s: n={scene.n} V={scene.cams.V} px={scene.cams.total_pixels()}")
+    P = torch.from_numpy(scene.params).to(dev)
+    target = torch.from_numpy(scene.target).to(dev)
+    cams = CameraBatch(scene.cams, opts, dev)
+
+    step = BatchedStep(P, scene.sh_degree, cams, target, eps=args.eps, eps_split=-1e-6)
+    K = step.prepare()
+    say(f"instances K={K} tiles={cams.total_tiles}")
+    for _ in range(max(args.warmup, 1)):
+        step.run()
+    new_params = step.check()
+    n_out = new_params.shape[1]
+    loss = float(step.loss.sum())
+    step.ras.render(target, count_used=True)
+    pairs = int(step.ras.n_contrib.to(torch.int64).sum())
+    contrib = int(step.ras.n_used.to(torch.int64).sum())
+    visible = int((step.ras.tiles > 0).sum())
+    say(f"warm: loss={loss:.5f} n_out={n_out} pairs={pairs} contributors={contrib} visible={visible}")
+
+    use_graph = not args.no_graph
+    if use_graph:
+        try:
+            step.capture()
+            step.replay()
+            torch.cuda.synchronize()
+            step.check()
+        except Exception as e:  # graph capture is an optimisation; the eager step is the same work
+            say(f"graph capture failed ({e}); timing eager steps")
+            use_graph = False
+    fn = step.replay if use_graph else step.run
+    say(f"timing {args.steps} batched steps ({'graph' if use_graph else 'eager'})")
+    ms_batched, wall_batched = time_region(fn, args.steps, torch)
+    step.check()
+    say(f"batched: {ms_batched:.3f} ms/step (host wall {wall_batched:.3f})")
+
+    say("per-kernel events over eager steps")
+    kt = kernel_times(step, args.steps, torch, L)
+    stages = {k: float(np.mean(v)) for k, v in kt.items()}
+    say("stages ms: " + ", ".join(f"{k}={v:.3f}" for k, v in stages.items()))
+
+    per_view = None
+    if not args.no_per_view:
+        step.graph = None
+        pv = PerViewStep(P, scene.sh_degree, scene.cams, opts, target, eps=args.eps, eps_split=-1e-6)
+        pv.prepare()
+        for _ in range(max(args.warmup, 1)):
+            pv.run()
+        pv.check()
+        say(f"timing {args.steps} per-view steps")
+        per_view, _ = time_region(pv.run, args.steps, torch)
+        pv.check()
+        say(f"per-view: {per_view:.3f} ms/step")
+        del pv
+        torch.cuda.empty_cache()
+
+    # roofline of the dominant kernel
+    n, V, F = scene.n, scene.cams.V, scene.params.shape[0]
+    Px = cams.total_pixels
+    dom = max((k for k in stages if k != "sort"), key=lambda k: stages[k])
+    models = {
+        # fp32 flops per examined (pixel, entry) pair and per contributing pair
+        "render_fwd": ("alu", pairs * 15 + contrib * 10),
+        "render_bwd": ("alu", pairs * 15 + contrib * 50),
+        # compulsory HBM bytes
+        "project": ("hbm", n * 4 * F + V * n * 52),
+        "proj_bwd": ("hbm", n * 4 * F + V * n * (4 + 36) + n * 4 * F * 2 + n * 24 * 2),
+        "densify": ("hbm", n * 24 + n * 4 * 5),
+    }
+    bound, work = models[dom]
+    t_s = stages[dom] * 1e-3
+    if bound == "hbm":
+        achieved = work / t_s / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None}
+    else:
+        achieved = work / t_s / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_NONPACKED_TFLOPS, 1),
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4), "traffic": None}
+    roof["kernel"] = dom
+    roof["ms"] = round(stages[dom], 4)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        say("CPU baseline: oracle on one view")
+        cpu = cpu_baseline(scene, opts)
+        say(f"cpu baseline {cpu['value']} ms/step")
+
+    out = {
+        "metric": METRIC,
+        "value": round(ms_batched, 4),
+        "unit": "ms/step",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_batched, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "gaussians": n, "views": V, "pixels": Px, "sh_degree": scene.sh_degree,
+                   "resolutions": [f"{w}x{h}" for w, h in zip(cams.widths, cams.heights)],
+                   "tile": f"{opts['tile_w']}x{opts['tile_h']}", "graph": use_graph, "eps_split": -1e-6},
+        "per_view_ms_per_step": None if per_view is None else round(per_view, 4),
+        "speedup_batched_vs_per_view": None if per_view is None else round(per_view / ms_batched, 3),
+        "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+        "counts": {"instances": K, "visible_pairs": visible, "examined_pairs": pairs, "contributing_pairs": contrib,
+                   "n_out": n_out, "loss": round(loss, 6)},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -155,13 +155,14 @@ steepgs_status steepgs_sort(const steepgs_splat* d_splats, const uint32_t* d_til
  * launch.  Out: d_image packed per view as [3][H][W] planes (offset
  * 3*pixel_offset), d_T_final [total_pixels], d_n_contrib [total_pixels]
  * (entries of the tile list up to and including the last contributor).
+ * d_n_used (nullable) [total_pixels]: number of entries blended into the pixel.
  * d_target (nullable, same layout as d_image): when given, d_loss[V] receives
  * the per-view mean absolute error of Eq. (loss) (overwritten). */
 steepgs_status steepgs_render_fwd(const steepgs_splat* d_splats, int64_t n, const uint32_t* d_vals,
                                   const uint32_t* d_tile_ranges, const steepgs_camera* d_cams, int32_t V,
                                   const steepgs_opts* opts, int32_t total_tiles, int64_t total_pixels,
                                   const float* d_target, float* d_image, float* d_T_final, uint32_t* d_n_contrib,
-                                  float* d_loss, void* d_ws, size_t ws_bytes, void* stream);
+                                  uint32_t* d_n_used, float* d_loss, void* d_ws, size_t ws_bytes, void* stream);
 
 /* Stage 4 -- backward of the blend and the projection, and the splitting
  * matrices (Theorem 1; Sec. 4.4).  Loss gradient per pixel: d_dL_dimage when
@@ -198,6 +199,22 @@ steepgs_status steepgs_densify(const float* d_params, int64_t n, int32_t sh_degr
                                float eps, float eps_split, float* d_out, int64_t out_capacity, int64_t* d_n_out,
                                float* d_lambda_min, float* d_vmin, uint8_t* d_split, int32_t* d_status, void* d_ws,
                                size_t ws_bytes, void* stream);
+
+/* Profiling hook.  When set for kernel `which` (STEEPGS_TIMER_*), every
+ * later launch of that kernel records start_events[i] immediately before and
+ * stop_events[i] immediately after it on the launch's stream, i = 0, 1, ...
+ * cycling through `count` caller-owned hipEvent_t handles, so a caller can time
+ * a kernel live inside a run.  count = 0 clears it.  Host-side process-global
+ * setting; not thread-safe; never allocates. */
+#define STEEPGS_TIMER_PROJECT 0    /* projection kernel */
+#define STEEPGS_TIMER_SORT 1       /* whole instance-sort stage */
+#define STEEPGS_TIMER_RENDER_FWD 2 /* forward raster kernel */
+#define STEEPGS_TIMER_RENDER_BWD 3 /* backward raster kernel */
+#define STEEPGS_TIMER_PROJ_BWD 4   /* projection backward + splitting-matrix lift */
+#define STEEPGS_TIMER_DENSIFY 5    /* eigensolve kernel of densification */
+#define STEEPGS_TIMER_COUNT 6
+steepgs_status steepgs_set_kernel_timer(int32_t which, void* const* start_events, void* const* stop_events,
+                                        int32_t count);
 
 const char* steepgs_status_string(steepgs_status s);
 const char* steepgs_version(void);

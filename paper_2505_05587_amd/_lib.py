@@ -63,7 +63,9 @@ def lib():
         L.steepgs_project.argtypes = [vp, i64, i32, vp, i32, C.POINTER(Opts), vp, vp, vp]
         L.steepgs_sort.argtypes = [vp, vp, i64, i32, vp, C.POINTER(Opts), i32, vp, vp, u64, vp, vp, vp, vp, sz, vp]
         L.steepgs_render_fwd.argtypes = [vp, i64, vp, vp, vp, i32, C.POINTER(Opts), i32, i64, vp, vp, vp, vp, vp,
-                                         vp, sz, vp]
+                                         vp, vp, sz, vp]
+        L.steepgs_set_kernel_timer.argtypes = [i32, vp, vp, i32]
+        L.steepgs_set_kernel_timer.restype = C.c_int
         L.steepgs_render_bwd_split.argtypes = [vp, i64, i32, vp, i32, C.POINTER(Opts), vp, vp, vp, vp, i32, i64,
                                                vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.steepgs_densify.argtypes = [vp, i64, i32, vp, f32, f32, f32, vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]
@@ -134,11 +136,27 @@ def steepgs_sort(splats, tiles_touched, n, V, d_cams, opts, total_tiles, keys, v
 
 
 def steepgs_render_fwd(splats, n, vals, tile_ranges, d_cams, V, opts, total_tiles, total_pixels, target, image,
-                       T_final, n_contrib, loss, ws, stream=None):
+                       T_final, n_contrib, n_used, loss, ws, stream=None):
     _check("steepgs_render_fwd",
            lib().steepgs_render_fwd(_p(splats), n, _p(vals), _p(tile_ranges), _p(d_cams), V, C.byref(opts),
                                     total_tiles, total_pixels, _p(target), _p(image), _p(T_final), _p(n_contrib),
-                                    _p(loss), _p(ws), ws.numel() * ws.element_size(), _stream(stream)))
+                                    _p(n_used), _p(loss), _p(ws), ws.numel() * ws.element_size(),
+                                    _stream(stream)))
+
+
+TIMER_PROJECT, TIMER_SORT, TIMER_RENDER_FWD, TIMER_RENDER_BWD, TIMER_PROJ_BWD, TIMER_DENSIFY = range(6)
+TIMER_NAMES = ["project", "sort", "render_fwd", "render_bwd", "proj_bwd", "densify"]
+
+
+def steepgs_set_kernel_timer(which, start_events, stop_events):
+    """start_events / stop_events: lists of torch.cuda.Event (already created)
+    or raw hipEvent_t handles; empty lists clear the timer."""
+    def handle(e):
+        return e.cuda_event if hasattr(e, "cuda_event") else int(e)
+    cnt = len(start_events)
+    arr_s = (C.c_void_p * max(cnt, 1))(*[handle(e) for e in start_events])
+    arr_e = (C.c_void_p * max(cnt, 1))(*[handle(e) for e in stop_events])
+    _check("steepgs_set_kernel_timer", lib().steepgs_set_kernel_timer(which, arr_s, arr_e, cnt))
 
 
 def steepgs_render_bwd_split(params, n, sh_degree, d_cams, V, opts, splats, tiles_touched, vals, tile_ranges,

@@ -36,6 +36,27 @@ inline bool opts_ok(const steepgs_opts* o) {
 // compute units of the current device (cached per device id)
 int device_cu_count();
 
+// optional launch timing (see steepgs_set_kernel_timer)
+struct KernelTimer {
+  hipEvent_t starts[1024];
+  hipEvent_t stops[1024];
+  int count = 0;
+  int next = 0;
+};
+KernelTimer* kernel_timers();
+
+inline void timer_begin(int which, hipStream_t st) {
+  KernelTimer& t = kernel_timers()[which];
+  if (t.count > 0) hipEventRecord(t.starts[t.next], st);
+}
+inline void timer_end(int which, hipStream_t st) {
+  KernelTimer& t = kernel_timers()[which];
+  if (t.count > 0) {
+    hipEventRecord(t.stops[t.next], st);
+    t.next = (t.next + 1) % t.count;
+  }
+}
+
 // workspace carving: 256-byte aligned bump allocator over the caller's buffer
 struct Carver {
   char* base;

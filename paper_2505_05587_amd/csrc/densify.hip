@@ -213,7 +213,9 @@ extern "C" steepgs_status steepgs_densify(const float* d_params, int64_t n, int3
   densify_layout(d_ws, n, w);
   const int F = STEEPGS_NUM_PARAMS(sh_degree);
   const unsigned nb = (unsigned)ceil_div(n, 256);
+  timer_begin(STEEPGS_TIMER_DENSIFY, st);
   hipLaunchKernelGGL(k_densify_eig, dim3(nb), dim3(256), 0, st, d_S, n, s_scale, eps_split, w.lam, w.vmin, w.flag);
+  timer_end(STEEPGS_TIMER_DENSIFY, st);
   if (exclusive_scan<LoadFlags, uint32_t, uint32_t>(LoadFlags{w.flag}, n, w.before, w.partials, st) != hipSuccess)
     return STEEPGS_ERR_HIP;
   hipLaunchKernelGGL(k_densify_total, dim3(1), dim3(1), 0, st, w.partials + scan_partials_count(n), n, out_capacity,

@@ -65,8 +65,10 @@ extern "C" steepgs_status steepgs_project(const float* d_params, int64_t n, int3
   if (!d_params || !d_cams || !d_splats || !d_tiles_touched) return STEEPGS_ERR_INVALID_ARG;
   if ((int64_t)V * n >= (int64_t)UINT32_MAX) return STEEPGS_ERR_INVALID_ARG;  // record ids are 32-bit
   const int threads = 256;
+  timer_begin(STEEPGS_TIMER_PROJECT, as_stream(stream));
   hipLaunchKernelGGL(k_project, dim3((unsigned)ceil_div(n, threads)), dim3(threads), 0, as_stream(stream), d_params,
                      n, sh_degree, d_cams, V, *opts, d_splats, d_tiles_touched);
+  timer_end(STEEPGS_TIMER_PROJECT, as_stream(stream));
   SG_TRY_LAUNCH();
   return STEEPGS_OK;
 }
@@ -106,6 +108,11 @@ extern "C" const char* steepgs_status_string(steepgs_status s) {
 extern "C" const char* steepgs_version(void) { return "steepgs-gfx950 0.1"; }
 
 namespace sg {
+KernelTimer* kernel_timers() {
+  static KernelTimer timers[STEEPGS_TIMER_COUNT];
+  return timers;
+}
+
 int device_cu_count() {
   static int cache[64] = {0};
   int dev = 0;
@@ -138,4 +145,18 @@ extern "C" size_t steepgs_workspace_size(int32_t stage, int64_t n, int32_t V, ui
     case 4: return sg::densify_workspace(n);
     default: return 0;
   }
+}
+
+extern "C" steepgs_status steepgs_set_kernel_timer(int32_t which, void* const* start_events,
+                                                   void* const* stop_events, int32_t count) {
+  if (which < 0 || which >= STEEPGS_TIMER_COUNT || count < 0 || count > 1024) return STEEPGS_ERR_INVALID_ARG;
+  if (count > 0 && (!start_events || !stop_events)) return STEEPGS_ERR_INVALID_ARG;
+  sg::KernelTimer& t = sg::kernel_timers()[which];
+  for (int i = 0; i < count; ++i) {
+    t.starts[i] = reinterpret_cast<hipEvent_t>(start_events[i]);
+    t.stops[i] = reinterpret_cast<hipEvent_t>(stop_events[i]);
+  }
+  t.count = count;
+  t.next = 0;
+  return STEEPGS_OK;
 }

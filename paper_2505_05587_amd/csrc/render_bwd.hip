@@ -389,6 +389,7 @@ extern "C" steepgs_status steepgs_render_bwd_split(const float* d_params, int64_
                      9 * m);
   const int grid = (int)std::min<int64_t>(total_tiles, (int64_t)device_cu_count() * 8);
   const steepgs_opts& o = *opts;
+  timer_begin(STEEPGS_TIMER_RENDER_BWD, st);
   if (o.tile_w == 16 && o.tile_h == 16)
     launch_bwd<16, 16>(grid, st, d_splats, d_vals, d_tile_ranges, d_cams, V, o, total_tiles, d_image, d_T_final,
                        d_n_contrib, d_dL_dimage, d_target, g2d, m, queue);
@@ -398,8 +399,11 @@ extern "C" steepgs_status steepgs_render_bwd_split(const float* d_params, int64_
   else
     launch_bwd<8, 8>(grid, st, d_splats, d_vals, d_tile_ranges, d_cams, V, o, total_tiles, d_image, d_T_final,
                      d_n_contrib, d_dL_dimage, d_target, g2d, m, queue);
+  timer_end(STEEPGS_TIMER_RENDER_BWD, st);
+  timer_begin(STEEPGS_TIMER_PROJ_BWD, st);
   hipLaunchKernelGGL(k_proj_bwd, dim3((unsigned)ceil_div(n, 128)), dim3(128), 0, st, d_params, n, sh_degree, d_cams, V,
                      o, d_tiles_touched, g2d, d_grads, d_S);
+  timer_end(STEEPGS_TIMER_PROJ_BWD, st);
   SG_TRY_LAUNCH();
   return STEEPGS_OK;
 }

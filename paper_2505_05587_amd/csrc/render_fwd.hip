@@ -18,7 +18,7 @@ __global__ void __launch_bounds__(TW* TH) k_render_fwd(const steepgs_splat* __re
                                                       steepgs_opts opt, int total_tiles,
                                                       const float* __restrict__ target, float* __restrict__ image,
                                                       float* __restrict__ T_final, uint32_t* __restrict__ n_contrib,
-                                                      float* __restrict__ loss, uint32_t* __restrict__ queue) {
+                                                      uint32_t* __restrict__ n_used, float* __restrict__ loss, uint32_t* __restrict__ queue) {
   constexpr int NT = TW * TH;
   __shared__ float s_mx[NT], s_my[NT], s_a[NT], s_b[NT], s_c[NT], s_o[NT], s_r[NT], s_g[NT], s_bl[NT];
   __shared__ float s_red[NT / 64];
@@ -47,7 +47,7 @@ __global__ void __launch_bounds__(TW* TH) k_render_fwd(const steepgs_splat* __re
     const uint32_t begin = ranges[2 * tile], end = ranges[2 * tile + 1];
     const float fx = (float)px, fy = (float)py;
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
-    uint32_t last = 0;
+    uint32_t last = 0, used = 0;
     bool done = !inside;
     for (uint32_t b0 = begin; b0 < end; b0 += NT) {
       if (__builtin_amdgcn_readfirstlane(__syncthreads_count(done)) == NT) break;
@@ -83,6 +83,7 @@ __global__ void __launch_bounds__(TW* TH) k_render_fwd(const steepgs_splat* __re
           C2 += s_bl[j] * w;
           T = Tn;
           last = b0 - begin + (uint32_t)j + 1u;
+          ++used;
         }
       }
     }
@@ -97,6 +98,7 @@ __global__ void __launch_bounds__(TW* TH) k_render_fwd(const steepgs_splat* __re
       img[2 * plane] = o2;
       T_final[p] = T;
       n_contrib[p] = last;
+      if (n_used) n_used[p] = used;
       if (target) {
         const float* tg = target + 3 * pix_off + (int64_t)py * W + px;
         err = fabsf(o0 - tg[0]) + fabsf(o1 - tg[plane]) + fabsf(o2 - tg[2 * plane]);
@@ -131,9 +133,9 @@ template <int TW, int TH>
 static void launch_fwd(int grid, hipStream_t st, const steepgs_splat* splats, const uint32_t* vals,
                        const uint32_t* ranges, const steepgs_camera* cams, int V, const steepgs_opts& opt,
                        int total_tiles, const float* target, float* image, float* T_final, uint32_t* n_contrib,
-                       float* loss, uint32_t* queue) {
+                       uint32_t* n_used, float* loss, uint32_t* queue) {
   hipLaunchKernelGGL((k_render_fwd<TW, TH>), dim3(grid), dim3(TW * TH), 0, st, splats, vals, ranges, cams, V, opt,
-                     total_tiles, target, image, T_final, n_contrib, loss, queue);
+                     total_tiles, target, image, T_final, n_contrib, n_used, loss, queue);
 }
 
 }  // namespace sg
@@ -144,7 +146,8 @@ extern "C" steepgs_status steepgs_render_fwd(const steepgs_splat* d_splats, int6
                                              const uint32_t* d_tile_ranges, const steepgs_camera* d_cams, int32_t V,
                                              const steepgs_opts* opts, int32_t total_tiles, int64_t total_pixels,
                                              const float* d_target, float* d_image, float* d_T_final,
-                                             uint32_t* d_n_contrib, float* d_loss, void* d_ws, size_t ws_bytes,
+                                             uint32_t* d_n_contrib, uint32_t* d_n_used, float* d_loss, void* d_ws,
+                                             size_t ws_bytes,
                                              void* stream) {
   if (n < 0 || V <= 0 || total_tiles <= 0 || total_pixels <= 0 || !opts_ok(opts)) return STEEPGS_ERR_INVALID_ARG;
   if (!d_tile_ranges || !d_cams || !d_image || !d_T_final || !d_n_contrib) return STEEPGS_ERR_INVALID_ARG;
@@ -156,15 +159,17 @@ extern "C" steepgs_status steepgs_render_fwd(const steepgs_splat* d_splats, int6
   if (d_target) hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)ceil_div(V, 64)), dim3(64), 0, st, d_loss, (int64_t)V);
   const int grid = (int)std::min<int64_t>(total_tiles, (int64_t)device_cu_count() * 8);
   const steepgs_opts& o = *opts;
+  timer_begin(STEEPGS_TIMER_RENDER_FWD, st);
   if (o.tile_w == 16 && o.tile_h == 16)
     launch_fwd<16, 16>(grid, st, d_splats, d_vals, d_tile_ranges, d_cams, V, o, total_tiles, d_target, d_image,
-                       d_T_final, d_n_contrib, d_loss, queue);
+                       d_T_final, d_n_contrib, d_n_used, d_loss, queue);
   else if (o.tile_w == 16 && o.tile_h == 8)
     launch_fwd<16, 8>(grid, st, d_splats, d_vals, d_tile_ranges, d_cams, V, o, total_tiles, d_target, d_image,
-                      d_T_final, d_n_contrib, d_loss, queue);
+                      d_T_final, d_n_contrib, d_n_used, d_loss, queue);
   else
     launch_fwd<8, 8>(grid, st, d_splats, d_vals, d_tile_ranges, d_cams, V, o, total_tiles, d_target, d_image,
-                     d_T_final, d_n_contrib, d_loss, queue);
+                     d_T_final, d_n_contrib, d_n_used, d_loss, queue);
+  timer_end(STEEPGS_TIMER_RENDER_FWD, st);
   SG_TRY_LAUNCH();
   return STEEPGS_OK;
 }

@@ -262,11 +262,13 @@ extern "C" steepgs_status steepgs_sort(const steepgs_splat* d_splats, const uint
   const size_t need = sort_layout(nullptr, m, capacity, w);
   if (!d_ws || ws_bytes < need) return STEEPGS_ERR_WORKSPACE;
   sort_layout(d_ws, m, capacity, w);
+  timer_begin(STEEPGS_TIMER_SORT, st);
   hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)ceil_div(2 * (int64_t)total_tiles, 256)), dim3(256), 0, st,
                      d_tile_ranges, 0u, 2 * (int64_t)total_tiles);
   if (m == 0) {
     hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, d_num_instances, (uint64_t)0);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, st, reinterpret_cast<uint32_t*>(d_status), 0u, (int64_t)1);
+    timer_end(STEEPGS_TIMER_SORT, st);
     SG_TRY_LAUNCH();
     return STEEPGS_OK;
   }
@@ -307,6 +309,7 @@ extern "C" steepgs_status steepgs_sort(const steepgs_splat* d_splats, const uint
       hipLaunchKernelGGL(k_keys64, dim3(2048), dim3(256), 0, st, w.tkA, d_vals, d_splats, d_num_instances, capacity,
                          d_keys);
   }
+  timer_end(STEEPGS_TIMER_SORT, st);
   SG_TRY_LAUNCH();
   return STEEPGS_OK;
 }

@@ -91,6 +91,7 @@ class Rasterizer:
         self.image = torch.empty(3 * Px, dtype=torch.float32, device=self.dev)
         self.T_final = torch.empty(Px, dtype=torch.float32, device=self.dev)
         self.n_contrib = torch.empty(Px, dtype=torch.int32, device=self.dev)
+        self.n_used = None
         self.loss = torch.zeros(cams.V, dtype=torch.float32, device=self.dev)
         self.grad2d = None
 
@@ -135,15 +136,19 @@ class Rasterizer:
             self._ensure(n, int(K * 1.25) + 1024)
         raise RuntimeError("instance capacity could not be satisfied")
 
-    def render(self, target: torch.Tensor | None = None):
+    def render(self, target: torch.Tensor | None = None, count_used: bool = False):
+        if count_used and self.n_used is None:
+            self.n_used = torch.empty(self.cams.total_pixels, dtype=torch.int32, device=self.dev)
         L.steepgs_render_fwd(self.splats, self.n, self.vals, self.ranges, self.cams.dev, self.cams.V, self.cams.opts,
                              self.cams.total_tiles, self.cams.total_pixels, target, self.image, self.T_final,
-                             self.n_contrib, self.loss if target is not None else None, self.ws_fwd)
+                             self.n_contrib, self.n_used if count_used else None,
+                             self.loss if target is not None else None, self.ws_fwd)
 
-    def forward(self, params: torch.Tensor, target: torch.Tensor | None = None, want_keys=False) -> ForwardState:
+    def forward(self, params: torch.Tensor, target: torch.Tensor | None = None, want_keys=False,
+                count_used=False) -> ForwardState:
         self.project(params)
         K = self.sort(want_keys)
-        self.render(target)
+        self.render(target, count_used)
         return ForwardState(K, self.image, self.T_final, self.n_contrib, self.loss if target is not None else None)
 
     def backward(self, params: torch.Tensor, grads: torch.Tensor, S: torch.Tensor, target=None, dL_dimage=None,

@@ -62,7 +62,9 @@ def test_bad_arguments_rejected_on_host():
                             None) == L.ERR_INVALID_ARG
     fake = C.c_void_p(0x1000)
     assert lib.steepgs_render_fwd(fake, 10, fake, fake, fake, 1, C.byref(o), 4, 64, None, fake, fake, fake, None,
-                                  None, 0, None) == L.ERR_WORKSPACE
+                                  None, None, 0, None) == L.ERR_WORKSPACE
+    assert lib.steepgs_set_kernel_timer(9, None, None, 0) == L.ERR_INVALID_ARG
+    assert lib.steepgs_set_kernel_timer(0, None, None, 0) == L.OK
     assert lib.steepgs_densify(None, 10, 0, None, 1.0, 0.01, 0.0, None, 0, None, None, None, None, None, None, 0,
                                None) == L.ERR_INVALID_ARG
     assert lib.steepgs_status_string(2) == b"output capacity exceeded"

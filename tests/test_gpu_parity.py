@@ -72,6 +72,7 @@ def test_forward_backward(oracle, kind, mode):
     assert ok.all(), f"{(~ok).sum()} image values out of tolerance"
     okT = np.abs(g["T_final"] - ref["T_final"]) <= 1e-5 + 1e-4 * ref["T_final"]
     assert (okT | pix_amb).all()
+    np.testing.assert_array_equal(g["n_used"][~pix_amb], ref["n_used"][~pix_amb])
     np.testing.assert_allclose(g["loss"], ref["loss"], rtol=1e-4)
     gamb = ref["gauss_ambig"]
     assert gamb.mean() < 0.1
