@@ -30,7 +30,7 @@ inline bool opts_ok(const steepgs_opts* o) {
   const bool tile_ok = (o->tile_w == 16 && o->tile_h == 16) || (o->tile_w == 16 && o->tile_h == 8) ||
                        (o->tile_w == 8 && o->tile_h == 8);
   return tile_ok && o->radius_sigmas > 0.f && o->alpha_max > 0.f && o->alpha_max <= 1.f && o->alpha_min >= 0.f &&
-         o->t_min >= 0.f && o->t_min < 1.f && o->near_z > 0.f && o->dilation >= 0.f;
+         o->t_min >= 0.f && o->t_min < 1.f && o->near_z > 0.f && o->dilation >= 0.f && o->alpha_max >= o->alpha_min;
 }
 
 // compute units of the current device (cached per device id)
@@ -101,12 +101,51 @@ SG_DEV int view_of_tile(const steepgs_camera* __restrict__ cams, int V, int tile
 //   alpha = min(alpha_max, o * exp(-1/2 d^T A d)),  d = x - mean.
 // The forward and backward raster kernels evaluate it with this one routine
 // so that both see bit-identical values.
-struct SplatLDS {
-  float mx, my, ca, cb, cc, o;
-};
-
 SG_DEV float splat_power(float dx, float dy, float a, float b, float c) {
   return -0.5f * (a * dx * dx + c * dy * dy) - b * dx * dy;
+}
+
+// Half-extents of the region where alpha >= alpha_min: the ellipse
+// d^T A d <= 2 ln(o / alpha_min), whose x half-width is sqrt(tau (A^-1)_xx).
+// Widened by 1% and 1/16 pixel so a test against it is conservative for the
+// fp32 evaluation of alpha; empty (negative) when o <= alpha_min; unbounded
+// when alpha_min = 0.
+SG_DEV void cutoff_extent(float a, float b, float c, float o, float alpha_min, float& ex, float& ey) {
+  if (!(alpha_min > 0.f)) {
+    ex = ey = INFINITY;
+    return;
+  }
+  if (!(o > alpha_min)) {
+    ex = ey = -INFINITY;
+    return;
+  }
+  const float tau = 2.f * __logf(o / alpha_min);
+  const float det = a * c - b * b;
+  ex = sqrtf(tau * c / det) * 1.01f + 0.0625f;
+  ey = sqrtf(tau * a / det) * 1.01f + 0.0625f;
+}
+
+// wave-wide sum with DPP row operations; the total is returned to every lane
+#define SG_DPP(v, ctrl, rmask) \
+  __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, (v)), (ctrl), (rmask), 0xf, false))
+SG_DEV float wave_sum_dpp(float v) {
+  v += SG_DPP(v, 0xb1, 0xf);   // quad_perm [1,0,3,2]
+  v += SG_DPP(v, 0x4e, 0xf);   // quad_perm [2,3,0,1]
+  v += SG_DPP(v, 0x141, 0xf);  // row_half_mirror: sums of 8
+  v += SG_DPP(v, 0x140, 0xf);  // row_mirror: sums of 16
+  v += SG_DPP(v, 0x142, 0xa);  // row_bcast:15 into rows 1 and 3: sums of 32
+  v += SG_DPP(v, 0x143, 0xc);  // row_bcast:31 into rows 2 and 3: lane 63 holds the total
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+
+// largest value over the wave
+SG_DEV uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const uint32_t o = (uint32_t)__shfl_xor((int)v, off, kWave);
+    v = o > v ? o : v;
+  }
+  return v;
 }
 
 }  // namespace sg

@@ -25,76 +25,78 @@ constexpr double kSH3c = 0.4570457994644658;   // sqrt(21/(2 pi)) / 4
 constexpr double kSH3d = 0.3731763325901154;   // sqrt(7/pi) / 4
 constexpr double kSH3e = 1.445305721320277;    // sqrt(105/pi) / 4
 
-SG_DEV void sh_eval(int deg, double x, double y, double z, double* Y) {
-  Y[0] = kSH0;
+template <class T>
+SG_DEV void sh_eval(int deg, T x, T y, T z, T* Y) {
+  Y[0] = T(kSH0);
   if (deg < 1) return;
-  Y[1] = -kSH1 * y;
-  Y[2] = kSH1 * z;
-  Y[3] = -kSH1 * x;
+  Y[1] = T(-kSH1) * y;
+  Y[2] = T(kSH1) * z;
+  Y[3] = T(-kSH1) * x;
   if (deg < 2) return;
-  const double xx = x * x, yy = y * y, zz = z * z;
-  Y[4] = kSH2a * x * y;
-  Y[5] = -kSH2a * y * z;
-  Y[6] = kSH2b * (2.0 * zz - xx - yy);
-  Y[7] = -kSH2a * x * z;
-  Y[8] = kSH2c * (xx - yy);
+  const T xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = T(kSH2a) * x * y;
+  Y[5] = T(-kSH2a) * y * z;
+  Y[6] = T(kSH2b) * (T(2) * zz - xx - yy);
+  Y[7] = T(-kSH2a) * x * z;
+  Y[8] = T(kSH2c) * (xx - yy);
   if (deg < 3) return;
-  Y[9] = -kSH3a * y * (3.0 * xx - yy);
-  Y[10] = kSH3b * x * y * z;
-  Y[11] = -kSH3c * y * (4.0 * zz - xx - yy);
-  Y[12] = kSH3d * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
-  Y[13] = -kSH3c * x * (4.0 * zz - xx - yy);
-  Y[14] = kSH3e * z * (xx - yy);
-  Y[15] = -kSH3a * x * (xx - 3.0 * yy);
+  Y[9] = T(-kSH3a) * y * (T(3) * xx - yy);
+  Y[10] = T(kSH3b) * x * y * z;
+  Y[11] = T(-kSH3c) * y * (T(4) * zz - xx - yy);
+  Y[12] = T(kSH3d) * z * (T(2) * zz - T(3) * xx - T(3) * yy);
+  Y[13] = T(-kSH3c) * x * (T(4) * zz - xx - yy);
+  Y[14] = T(kSH3e) * z * (xx - yy);
+  Y[15] = T(-kSH3a) * x * (xx - T(3) * yy);
 }
 
 // g += sum_k w_k * grad_(x,y,z) Y_k   (polynomial gradient; the caller
 // projects it onto the sphere's tangent plane)
-SG_DEV void sh_grad(int deg, double x, double y, double z, const double* w, double g[3]) {
+template <class T>
+SG_DEV void sh_grad(int deg, T x, T y, T z, const T* w, T g[3]) {
   if (deg < 1) return;
-  g[1] += -kSH1 * w[1];
-  g[2] += kSH1 * w[2];
-  g[0] += -kSH1 * w[3];
+  g[1] += T(-kSH1) * w[1];
+  g[2] += T(kSH1) * w[2];
+  g[0] += T(-kSH1) * w[3];
   if (deg < 2) return;
-  const double xx = x * x, yy = y * y, zz = z * z;
-  g[0] += kSH2a * y * w[4];
-  g[1] += kSH2a * x * w[4];
-  g[1] += -kSH2a * z * w[5];
-  g[2] += -kSH2a * y * w[5];
-  g[0] += -2.0 * kSH2b * x * w[6];
-  g[1] += -2.0 * kSH2b * y * w[6];
-  g[2] += 4.0 * kSH2b * z * w[6];
-  g[0] += -kSH2a * z * w[7];
-  g[2] += -kSH2a * x * w[7];
-  g[0] += 2.0 * kSH2c * x * w[8];
-  g[1] += -2.0 * kSH2c * y * w[8];
+  const T xx = x * x, yy = y * y, zz = z * z;
+  g[0] += T(kSH2a) * y * w[4];
+  g[1] += T(kSH2a) * x * w[4];
+  g[1] += T(-kSH2a) * z * w[5];
+  g[2] += T(-kSH2a) * y * w[5];
+  g[0] += T(-2.0 * kSH2b) * x * w[6];
+  g[1] += T(-2.0 * kSH2b) * y * w[6];
+  g[2] += T(4.0 * kSH2b) * z * w[6];
+  g[0] += T(-kSH2a) * z * w[7];
+  g[2] += T(-kSH2a) * x * w[7];
+  g[0] += T(2.0 * kSH2c) * x * w[8];
+  g[1] += T(-2.0 * kSH2c) * y * w[8];
   if (deg < 3) return;
   // Y9 = -a (3 x^2 y - y^3)
-  g[0] += -kSH3a * 6.0 * x * y * w[9];
-  g[1] += -kSH3a * (3.0 * xx - 3.0 * yy) * w[9];
+  g[0] += T(-6.0 * kSH3a) * x * y * w[9];
+  g[1] += T(-kSH3a) * (T(3) * xx - T(3) * yy) * w[9];
   // Y10 = b x y z
-  g[0] += kSH3b * y * z * w[10];
-  g[1] += kSH3b * x * z * w[10];
-  g[2] += kSH3b * x * y * w[10];
+  g[0] += T(kSH3b) * y * z * w[10];
+  g[1] += T(kSH3b) * x * z * w[10];
+  g[2] += T(kSH3b) * x * y * w[10];
   // Y11 = -c (4 y z^2 - x^2 y - y^3)
-  g[0] += kSH3c * 2.0 * x * y * w[11];
-  g[1] += -kSH3c * (4.0 * zz - xx - 3.0 * yy) * w[11];
-  g[2] += -kSH3c * 8.0 * y * z * w[11];
+  g[0] += T(2.0 * kSH3c) * x * y * w[11];
+  g[1] += T(-kSH3c) * (T(4) * zz - xx - T(3) * yy) * w[11];
+  g[2] += T(-8.0 * kSH3c) * y * z * w[11];
   // Y12 = d (2 z^3 - 3 x^2 z - 3 y^2 z)
-  g[0] += -kSH3d * 6.0 * x * z * w[12];
-  g[1] += -kSH3d * 6.0 * y * z * w[12];
-  g[2] += kSH3d * (6.0 * zz - 3.0 * xx - 3.0 * yy) * w[12];
+  g[0] += T(-6.0 * kSH3d) * x * z * w[12];
+  g[1] += T(-6.0 * kSH3d) * y * z * w[12];
+  g[2] += T(kSH3d) * (T(6) * zz - T(3) * xx - T(3) * yy) * w[12];
   // Y13 = -c (4 x z^2 - x^3 - x y^2)
-  g[0] += -kSH3c * (4.0 * zz - 3.0 * xx - yy) * w[13];
-  g[1] += kSH3c * 2.0 * x * y * w[13];
-  g[2] += -kSH3c * 8.0 * x * z * w[13];
+  g[0] += T(-kSH3c) * (T(4) * zz - T(3) * xx - yy) * w[13];
+  g[1] += T(2.0 * kSH3c) * x * y * w[13];
+  g[2] += T(-8.0 * kSH3c) * x * z * w[13];
   // Y14 = e (x^2 z - y^2 z)
-  g[0] += kSH3e * 2.0 * x * z * w[14];
-  g[1] += -kSH3e * 2.0 * y * z * w[14];
-  g[2] += kSH3e * (xx - yy) * w[14];
+  g[0] += T(2.0 * kSH3e) * x * z * w[14];
+  g[1] += T(-2.0 * kSH3e) * y * z * w[14];
+  g[2] += T(kSH3e) * (xx - yy) * w[14];
   // Y15 = -a (x^3 - 3 x y^2)
-  g[0] += -kSH3a * (3.0 * xx - 3.0 * yy) * w[15];
-  g[1] += kSH3a * 6.0 * x * y * w[15];
+  g[0] += T(-kSH3a) * (T(3) * xx - T(3) * yy) * w[15];
+  g[1] += T(6.0 * kSH3a) * x * y * w[15];
 }
 
 // view-independent part of a Gaussian
@@ -255,7 +257,7 @@ SG_DEV bool project_view(const Gauss& g, const float* __restrict__ params, int64
   double d[3] = {g.p[0] - campos[0], g.p[1] - campos[1], g.p[2] - campos[2]};
   v.dlen = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
   for (int k = 0; k < 3; ++k) v.dir[k] = d[k] / v.dlen;
-  sh_eval(deg, v.dir[0], v.dir[1], v.dir[2], v.Y);
+  sh_eval<double>(deg, v.dir[0], v.dir[1], v.dir[2], v.Y);
   const int nb = (deg + 1) * (deg + 1);
   for (int ch = 0; ch < 3; ++ch) {
     double acc = 0.0;

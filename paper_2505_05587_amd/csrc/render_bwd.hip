@@ -4,11 +4,15 @@
 // Kernel 1 (raster backward, persistent over tiles): every pixel walks its
 // contributors back to front, recomputing alpha with the forward's own
 // routine and the transmittance T_i = T_{i+1} / (1 - alpha_i) from the stored
-// final value (no per-pixel lists are stored).  Per contributor it forms
+// final value (no per-pixel lists are stored).  The walk starts at the last
+// contributor of the workgroup (of the wavefront, per wave), and a wavefront
+// skips entries whose alpha >= alpha_min ellipse misses its 8x8 quadrant.
+// Per contributor it forms
 //   g = dL/dalpha_i = sum_c dL/dC_c (c_i T_i - R_c / (1 - alpha_i)),
 // R = colour of everything behind i (background included), and the
 // gradients w.r.t. the 2D mean, conic, opacity and colour.  A wavefront sums
-// them over its 64 pixels and issues one atomic per quantity.
+// them over its 64 pixels with DPP row operations and issues one atomic per
+// quantity.
 //
 // Kernel 2 (one thread per Gaussian, all views): chain rule from the 2D
 // quantities to the 3D parameters, and the splitting matrix.  With
@@ -35,32 +39,33 @@ __global__ void __launch_bounds__(TW* TH) k_render_bwd(const steepgs_splat* __re
                                                       const float* __restrict__ target, float* __restrict__ g2d,
                                                       int64_t m, uint32_t* __restrict__ queue) {
   constexpr int NT = TW * TH;
-  __shared__ float s_mx[NT], s_my[NT], s_a[NT], s_b[NT], s_c[NT], s_o[NT], s_r[NT], s_g[NT], s_bl[NT];
-  __shared__ uint32_t s_id[NT];
+  constexpr int WX = TW / 8;  // each wavefront owns an 8x8 pixel quadrant of the tile
+  __shared__ float4 s_m[NT];    // mean x, mean y, cut-off half extents x, y
+  __shared__ float4 s_q[NT];    // conic a, b, c, opacity
+  __shared__ float4 s_col[NT];  // rgb, record id (bits)
+  __shared__ uint32_t s_last[NT / 64];
   __shared__ int s_tile;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int qx = (wave % WX) * 8 + (lane & 7), qy = (wave / WX) * 8 + (lane >> 3);
   for (;;) {
     // The barrier closes the previous tile before lane 0 fetches the next one,
-    // so no lane-0-only region can span the loop's back edge (the compiler
-    // would otherwise merge them and let the other lanes re-enter the tile
-    // loop without the fetch).
+    // so no lane-0-only region can span the loop's back edge.
     __syncthreads();
     if (tid == 0) s_tile = (int)atomicAdd(queue, 1u);
     __syncthreads();
-    // scalar (wave-uniform) copy: the loop exit below must be a uniform branch,
-    // or the compiler may move the queue atomic out of the per-tile loop
+    // scalar (wave-uniform) copy: the loop exit below must be a uniform branch
     const int tile = __builtin_amdgcn_readfirstlane(s_tile);
-    __syncthreads();
     if (tile >= total_tiles) break;
     const int v = view_of_tile(cams, V, tile);
     const int W = cams[v].width, H = cams[v].height, tiles_x = cams[v].tiles_x;
     const int64_t pix_off = cams[v].pixel_offset;
     const int lt = tile - cams[v].tile_offset;
-    const int px = (lt % tiles_x) * TW + tid % TW;
-    const int py = (lt / tiles_x) * TH + tid / TW;
+    const int tx0 = (lt % tiles_x) * TW, ty0 = (lt / tiles_x) * TH;
+    const int px = tx0 + qx, py = ty0 + qy;
     const bool inside = px < W && py < H;
-    const uint32_t begin = ranges[2 * tile], end = ranges[2 * tile + 1];
+    const float wx0 = (float)(tx0 + (wave % WX) * 8), wy0 = (float)(ty0 + (wave / WX) * 8);
+    const float wx1 = wx0 + 7.f, wy1 = wy0 + 7.f;
+    const uint32_t begin = ranges[2 * tile];
     const float fx = (float)px, fy = (float)py;
     float T = 1.f, dC0 = 0.f, dC1 = 0.f, dC2 = 0.f, R0 = 0.f, R1 = 0.f, R2 = 0.f;
     uint32_t last = 0;
@@ -86,47 +91,55 @@ __global__ void __launch_bounds__(TW* TH) k_render_bwd(const steepgs_splat* __re
       R1 = T * opt.bg[1];
       R2 = T * opt.bg[2];
     }
-    const int count = (int)(end - begin);
+    // entries at or past a wavefront's last contributor need no work from it;
+    // the workgroup walks back from the largest last contributor
+    const int wlast = (int)__builtin_amdgcn_readfirstlane(wave_max_u32(last));
+    if (lane == 0) s_last[wave] = (uint32_t)wlast;
+    __syncthreads();
+    int count = 0;
+    for (int w = 0; w < NT / 64; ++w) count = max(count, (int)s_last[w]);
+    count = __builtin_amdgcn_readfirstlane(count);
     for (int b_end = count; b_end > 0; b_end -= NT) {
       const int b_start = b_end > NT ? b_end - NT : 0;
       __syncthreads();
       if (b_start + tid < b_end) {
         const uint32_t id = vals[begin + b_start + tid];
         const steepgs_splat s = splats[id];
-        s_id[tid] = id;
-        s_mx[tid] = s.mean_x;
-        s_my[tid] = s.mean_y;
-        s_a[tid] = s.conic_a;
-        s_b[tid] = s.conic_b;
-        s_c[tid] = s.conic_c;
-        s_o[tid] = s.opacity;
-        s_r[tid] = s.rgb[0];
-        s_g[tid] = s.rgb[1];
-        s_bl[tid] = s.rgb[2];
+        float ex, ey;
+        cutoff_extent(s.conic_a, s.conic_b, s.conic_c, s.opacity, opt.alpha_min, ex, ey);
+        s_m[tid] = make_float4(s.mean_x, s.mean_y, ex, ey);
+        s_q[tid] = make_float4(s.conic_a, s.conic_b, s.conic_c, s.opacity);
+        s_col[tid] = make_float4(s.rgb[0], s.rgb[1], s.rgb[2], __uint_as_float(id));
       }
       __syncthreads();
-      for (int j = b_end - b_start - 1; j >= 0; --j) {
+      const int jtop = min(b_end, wlast) - b_start - 1;
+      for (int j = jtop; j >= 0; --j) {
+        const float4 mm = s_m[j];
+        const bool hit = (mm.x + mm.z >= wx0) && (mm.x - mm.z <= wx1) && (mm.y + mm.w >= wy0) && (mm.y - mm.w <= wy1);
+        if (!__builtin_amdgcn_readfirstlane((int)hit)) continue;
         const uint32_t pos = (uint32_t)(b_start + j);
         bool contrib = pos < last;  // false for pixels outside the image (last = 0)
         float gmx = 0.f, gmy = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
         if (contrib) {
-          const float dx = fx - s_mx[j], dy = fy - s_my[j];
-          const float a = s_a[j], b = s_b[j], c = s_c[j];
+          const float4 qq = s_q[j];
+          const float dx = fx - mm.x, dy = fy - mm.y;
+          const float a = qq.x, b = qq.y, c = qq.z;
           const float G = __expf(splat_power(dx, dy, a, b, c));
-          const float raw = s_o[j] * G;
+          const float raw = qq.w * G;
           const bool clamped = raw > opt.alpha_max;
           const float alpha = clamped ? opt.alpha_max : raw;
           contrib = alpha >= opt.alpha_min;
           if (contrib) {
+            const float4 col = s_col[j];
             const float om = 1.f - alpha;
             T = T / om;  // transmittance in front of this entry
             const float w = alpha * T;
             const float inv_om = 1.f / om;
-            const float g = dC0 * (s_r[j] * T - R0 * inv_om) + dC1 * (s_g[j] * T - R1 * inv_om) +
-                            dC2 * (s_bl[j] * T - R2 * inv_om);
-            R0 += s_r[j] * w;
-            R1 += s_g[j] * w;
-            R2 += s_bl[j] * w;
+            const float g = dC0 * (col.x * T - R0 * inv_om) + dC1 * (col.y * T - R1 * inv_om) +
+                            dC2 * (col.z * T - R2 * inv_om);
+            R0 += col.x * w;
+            R1 += col.y * w;
+            R2 += col.z * w;
             gr = w * dC0;
             gg = w * dC1;
             gbl = w * dC2;
@@ -142,17 +155,17 @@ __global__ void __launch_bounds__(TW* TH) k_render_bwd(const steepgs_splat* __re
           }
         }
         if (ballot(contrib)) {
-          gmx = wave_sum(gmx);
-          gmy = wave_sum(gmy);
-          ga = wave_sum(ga);
-          gb = wave_sum(gb);
-          gc = wave_sum(gc);
-          go = wave_sum(go);
-          gr = wave_sum(gr);
-          gg = wave_sum(gg);
-          gbl = wave_sum(gbl);
+          gmx = wave_sum_dpp(gmx);
+          gmy = wave_sum_dpp(gmy);
+          ga = wave_sum_dpp(ga);
+          gb = wave_sum_dpp(gb);
+          gc = wave_sum_dpp(gc);
+          go = wave_sum_dpp(go);
+          gr = wave_sum_dpp(gr);
+          gg = wave_sum_dpp(gg);
+          gbl = wave_sum_dpp(gbl);
           if (lane == 0) {
-            const int64_t id = s_id[j];
+            const int64_t id = __float_as_uint(s_col[j].w);
             unsafeAtomicAdd(&g2d[0 * m + id], gmx);
             unsafeAtomicAdd(&g2d[1 * m + id], gmy);
             unsafeAtomicAdd(&g2d[2 * m + id], ga);
@@ -170,126 +183,232 @@ __global__ void __launch_bounds__(TW* TH) k_render_bwd(const steepgs_splat* __re
 }
 
 // ---------------------------------------------------------------------------
-// kernel 2: projection backward and the splitting-matrix lift
+// kernel 2: projection backward and the splitting-matrix lift.
+// One thread per Gaussian loops over the views.  The two discrete decisions
+// the forward took in fp64 are re-taken identically: the frustum-guard clamp
+// (fp64 camera-space position, same operation order) and the colour clamp
+// (fp32 value, re-evaluated in fp64 when within 1e-5 of zero).  The chain
+// rule itself runs in fp32.
 
-__global__ void __launch_bounds__(128) k_proj_bwd(const float* __restrict__ params, int64_t n, int deg,
+// fp64 colour of one channel, for a clamp decision too close to call in fp32
+__device__ __noinline__ bool colour_clamped_fp64(const float* __restrict__ params, int64_t n, int64_t i, int deg,
+                                                  const steepgs_camera& cam, int ch) {
+#pragma clang fp contract(off)
+  double R[9], t[3];
+  for (int k = 0; k < 9; ++k) R[k] = cam.R[k];
+  for (int k = 0; k < 3; ++k) t[k] = cam.t[k];
+  double campos[3], d[3];
+  for (int k = 0; k < 3; ++k) campos[k] = -(R[0 + k] * t[0] + R[3 + k] * t[1] + R[6 + k] * t[2]);
+  for (int k = 0; k < 3; ++k) d[k] = (double)params[(STEEPGS_ROW_MEAN + k) * n + i] - campos[k];
+  const double len = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  double Y[16];
+  sh_eval<double>(deg, d[0] / len, d[1] / len, d[2] / len, Y);
+  double acc = 0.0;
+  for (int k = 0; k < (deg + 1) * (deg + 1); ++k) acc = acc + (double)params[(STEEPGS_ROW_SH + 3 * k + ch) * n + i] * Y[k];
+  acc = acc + 0.5;
+  return acc < 0.0;
+}
+
+template <int D>
+__global__ void __launch_bounds__(128) k_proj_bwd(const float* __restrict__ params, int64_t n,
                                                   const steepgs_camera* __restrict__ cams, int V, steepgs_opts opt,
                                                   const uint32_t* __restrict__ tiles, const float* __restrict__ g2d,
                                                   float* __restrict__ grads, float* __restrict__ S) {
+  constexpr int NB = (D + 1) * (D + 1);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int64_t m = (int64_t)V * n;
-  const int nb = (deg + 1) * (deg + 1);
-  Gauss g;
-  load_gauss(params, n, i, g);
-  double dp[3] = {0, 0, 0}, dSig[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, dop = 0.0;
-  double S3[6] = {0, 0, 0, 0, 0, 0};
-  float dsh[48];
-  for (int k = 0; k < 3 * nb; ++k) dsh[k] = 0.f;
+  float p[3];
+  for (int k = 0; k < 3; ++k) p[k] = params[(STEEPGS_ROW_MEAN + k) * n + i];
+  float sh[3 * NB];
+#pragma unroll
+  for (int k = 0; k < 3 * NB; ++k) sh[k] = params[(STEEPGS_ROW_SH + k) * n + i];
+  // covariance R diag(s^2) R^T (fp32), opacity
+  float q[4];
+  for (int k = 0; k < 4; ++k) q[k] = params[(STEEPGS_ROW_QUAT + k) * n + i];
+  const float qn = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  const float w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+  const float Rq[3][3] = {{1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y)},
+                          {2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x)},
+                          {2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)}};
+  float sc[3];
+  for (int k = 0; k < 3; ++k) sc[k] = expf(params[(STEEPGS_ROW_LOG_SCALE + k) * n + i]);
+  float Sig[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      Sig[a][b] = Rq[a][0] * sc[0] * sc[0] * Rq[b][0] + Rq[a][1] * sc[1] * sc[1] * Rq[b][1] +
+                  Rq[a][2] * sc[2] * sc[2] * Rq[b][2];
+  const float o = 1.f / (1.f + expf(-params[STEEPGS_ROW_OPACITY * n + i]));
+
+  float dp[3] = {0.f, 0.f, 0.f}, dSig[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, dop = 0.f;
+  float S3[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float dsh[3 * NB];
+#pragma unroll
+  for (int k = 0; k < 3 * NB; ++k) dsh[k] = 0.f;
   bool any = false;
   for (int v = 0; v < V; ++v) {
     const int64_t r = (int64_t)v * n + i;
     if (tiles[r] == 0) continue;
-    double G9[9];
+    float G9[9];
     bool nz = false;
-    for (int q = 0; q < 9; ++q) {
-      G9[q] = g2d[q * m + r];
-      nz |= G9[q] != 0.0;
+    for (int k = 0; k < 9; ++k) {
+      G9[k] = g2d[k * m + r];
+      nz |= G9[k] != 0.f;
     }
     if (!nz) continue;
-    CamD cam;
-    load_cam(cams[v], cam);
-    ViewProj pv;
-    if (!project_view(g, params, n, i, deg, cam, opt, pv, true)) continue;
     any = true;
-    const double gmx = G9[0], gmy = G9[1], ga = G9[2], gb = G9[3], gc = G9[4], go = G9[5];
+    const steepgs_camera& cam = cams[v];
+    float W[9];
+    for (int k = 0; k < 9; ++k) W[k] = cam.R[k];
+    const float fx = cam.fx, fy = cam.fy;
+    const float gmx = G9[0], gmy = G9[1], ga = G9[2], gb = G9[3], gc = G9[4], go = G9[5];
+
+    // camera-space position: fp64 in the forward's operation order for the guard decision
+    double pcd[3];
+    {
+#pragma clang fp contract(off)
+      for (int k = 0; k < 3; ++k)
+        pcd[k] = (double)cam.R[3 * k + 0] * (double)p[0] + (double)cam.R[3 * k + 1] * (double)p[1] +
+                 (double)cam.R[3 * k + 2] * (double)p[2] + (double)cam.t[k];
+    }
+    const float pcx = (float)pcd[0], pcy = (float)pcd[1], pcz = (float)pcd[2];
+    float J[2][3];
+    float gx = 0.f, gy = 0.f;
+    bool gx_free = false, gy_free = false;
+    if (cam.model == 0) {
+      double gxd = pcd[0] / pcd[2], gyd = pcd[1] / pcd[2];
+      gx_free = gy_free = true;
+      if (opt.frustum_guard > 0.f) {
+        const double limx = (double)opt.frustum_guard * (0.5 * cam.width / (double)cam.fx);
+        const double limy = (double)opt.frustum_guard * (0.5 * cam.height / (double)cam.fy);
+        if (gxd < -limx) { gxd = -limx; gx_free = false; }
+        if (gxd > limx) { gxd = limx; gx_free = false; }
+        if (gyd < -limy) { gyd = -limy; gy_free = false; }
+        if (gyd > limy) { gyd = limy; gy_free = false; }
+      }
+      gx = (float)gxd;
+      gy = (float)gyd;
+      const float iz = 1.f / pcz;
+      J[0][0] = fx * iz; J[0][1] = 0.f; J[0][2] = -fx * gx * iz;
+      J[1][0] = 0.f; J[1][1] = fy * iz; J[1][2] = -fy * gy * iz;
+    } else {
+      J[0][0] = fx; J[0][1] = 0.f; J[0][2] = 0.f;
+      J[1][0] = 0.f; J[1][1] = fy; J[1][2] = 0.f;
+    }
+    float P[2][3];
+    for (int a = 0; a < 2; ++a)
+      for (int c = 0; c < 3; ++c) P[a][c] = J[a][0] * W[c] + J[a][1] * W[3 + c] + J[a][2] * W[6 + c];
+    // Pi(Sigma) and its inverse (the conic)
+    float PS[2][3];
+    for (int a = 0; a < 2; ++a)
+      for (int c = 0; c < 3; ++c) PS[a][c] = P[a][0] * Sig[0][c] + P[a][1] * Sig[1][c] + P[a][2] * Sig[2][c];
+    const float s00 = PS[0][0] * P[0][0] + PS[0][1] * P[0][1] + PS[0][2] * P[0][2] + opt.dilation;
+    const float s01 = PS[0][0] * P[1][0] + PS[0][1] * P[1][1] + PS[0][2] * P[1][2];
+    const float s11 = PS[1][0] * P[1][0] + PS[1][1] * P[1][1] + PS[1][2] * P[1][2] + opt.dilation;
+    const float idet = 1.f / (s00 * s11 - s01 * s01);
+    const float A[2][2] = {{s11 * idet, -s01 * idet}, {-s01 * idet, s00 * idet}};
 
     // colour: rgb = max(0, sum_k sh_k Y_k(dir) + 1/2)
-    double dcol[3];
-    for (int ch = 0; ch < 3; ++ch) dcol[ch] = pv.raw[ch] < 0.0 ? 0.0 : G9[6 + ch];
-    double dY[16];
-    for (int k = 0; k < nb; ++k) {
-      double s = 0.0;
-      for (int ch = 0; ch < 3; ++ch) {
-        dsh[3 * k + ch] += (float)(pv.Y[k] * dcol[ch]);
-        s += (double)params[(STEEPGS_ROW_SH + 3 * k + ch) * n + i] * dcol[ch];
-      }
-      dY[k] = s;
+    float campos[3];
+    for (int k = 0; k < 3; ++k) campos[k] = -(W[0 + k] * cam.t[0] + W[3 + k] * cam.t[1] + W[6 + k] * cam.t[2]);
+    float dv[3] = {p[0] - campos[0], p[1] - campos[1], p[2] - campos[2]};
+    const float dlen = sqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+    const float idl = 1.f / dlen;
+    const float dir[3] = {dv[0] * idl, dv[1] * idl, dv[2] * idl};
+    float Y[NB];
+    sh_eval<float>(D, dir[0], dir[1], dir[2], Y);
+    float dcol[3];
+    for (int ch = 0; ch < 3; ++ch) {
+      float raw = 0.5f;
+#pragma unroll
+      for (int k = 0; k < NB; ++k) raw += sh[3 * k + ch] * Y[k];
+      bool clamped = raw < 0.f;
+      if (fabsf(raw) < 1e-5f) clamped = colour_clamped_fp64(params, n, i, D, cam, ch);
+      dcol[ch] = clamped ? 0.f : G9[6 + ch];
     }
-    if (deg > 0) {
-      double gd[3] = {0, 0, 0};
-      sh_grad(deg, pv.dir[0], pv.dir[1], pv.dir[2], dY, gd);
-      const double dot = gd[0] * pv.dir[0] + gd[1] * pv.dir[1] + gd[2] * pv.dir[2];
-      for (int k = 0; k < 3; ++k) dp[k] += (gd[k] - pv.dir[k] * dot) / pv.dlen;
+    float dY[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      dY[k] = sh[3 * k] * dcol[0] + sh[3 * k + 1] * dcol[1] + sh[3 * k + 2] * dcol[2];
+      dsh[3 * k] += Y[k] * dcol[0];
+      dsh[3 * k + 1] += Y[k] * dcol[1];
+      dsh[3 * k + 2] += Y[k] * dcol[2];
+    }
+    if (D > 0) {
+      float gd[3] = {0.f, 0.f, 0.f};
+      sh_grad<float>(D, dir[0], dir[1], dir[2], dY, gd);
+      const float dot = gd[0] * dir[0] + gd[1] * dir[1] + gd[2] * dir[2];
+      for (int k = 0; k < 3; ++k) dp[k] += (gd[k] - dir[k] * dot) * idl;
     }
 
-    // conic -> Pi(Sigma): dL/dS2 = -A G_A A with G_A = [[ga, gb/2], [gb/2, gc]]
-    const double A[2][2] = {{pv.A00, pv.A01}, {pv.A01, pv.A11}};
-    const double GA[2][2] = {{ga, 0.5 * gb}, {0.5 * gb, gc}};
-    double AG[2][2], GS2[2][2];
+    // conic -> Pi(Sigma): dL/dS2 = -A G_A A, G_A = [[ga, gb/2], [gb/2, gc]]
+    const float GA[2][2] = {{ga, 0.5f * gb}, {0.5f * gb, gc}};
+    float AG[2][2], GS2[2][2];
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b) AG[a][b] = A[a][0] * GA[0][b] + A[a][1] * GA[1][b];
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b) GS2[a][b] = -(AG[a][0] * A[0][b] + AG[a][1] * A[1][b]);
-    // Pi(Sigma) = P Sigma P^T (+dilation): dL/dSigma += P^T GS2 P, dL/dP = 2 GS2 P Sigma
-    double GSP[2][3];
+    // Pi(Sigma) = P Sigma P^T + dilation: dL/dSigma += P^T GS2 P; dL/dP = 2 GS2 P Sigma
+    float GSP[2][3];
     for (int a = 0; a < 2; ++a)
-      for (int c = 0; c < 3; ++c) GSP[a][c] = GS2[a][0] * pv.P[0][c] + GS2[a][1] * pv.P[1][c];
-    for (int c = 0; c < 3; ++c)
-      for (int d = 0; d < 3; ++d) dSig[c][d] += pv.P[0][c] * GSP[0][d] + pv.P[1][c] * GSP[1][d];
-    double GP[2][3];
-    for (int a = 0; a < 2; ++a)
-      for (int c = 0; c < 3; ++c)
-        GP[a][c] = 2.0 * (GSP[a][0] * g.Sig[0][c] + GSP[a][1] * g.Sig[1][c] + GSP[a][2] * g.Sig[2][c]);
-    // P = J W: dL/dJ = dL/dP W^T
-    double GJ[2][3];
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 3; ++b)
-        GJ[a][b] = GP[a][0] * cam.R[3 * b + 0] + GP[a][1] * cam.R[3 * b + 1] + GP[a][2] * cam.R[3 * b + 2];
-    // camera-space position gradient from the mean and from J
-    double dpc[3] = {0, 0, 0};
-    const double x = pv.pc[0], y = pv.pc[1], z = pv.pc[2];
-    double Pe[2][3];  // Jacobian of the projected mean w.r.t. p (exact, unguarded)
-    if (cam.model == 0) {
-      const double iz = 1.0 / z, iz2 = iz * iz;
-      dpc[0] += gmx * cam.fx * iz;
-      dpc[1] += gmy * cam.fy * iz;
-      dpc[2] -= (gmx * cam.fx * x + gmy * cam.fy * y) * iz2;
-      dpc[2] -= (GJ[0][0] * cam.fx + GJ[1][1] * cam.fy) * iz2;
-      // J02 = -fx gx / z, J12 = -fy gy / z, gx = x/z unless clamped
-      dpc[2] += GJ[0][2] * cam.fx * pv.gx * iz2 + GJ[1][2] * cam.fy * pv.gy * iz2;
-      if (pv.gx_free) {
-        dpc[0] -= GJ[0][2] * cam.fx * iz2;
-        dpc[2] += GJ[0][2] * cam.fx * x * iz2 * iz;
-      }
-      if (pv.gy_free) {
-        dpc[1] -= GJ[1][2] * cam.fy * iz2;
-        dpc[2] += GJ[1][2] * cam.fy * y * iz2 * iz;
-      }
-      const double Je[2][3] = {{cam.fx * iz, 0.0, -cam.fx * x * iz2}, {0.0, cam.fy * iz, -cam.fy * y * iz2}};
-      for (int a = 0; a < 2; ++a)
-        for (int c = 0; c < 3; ++c) Pe[a][c] = Je[a][0] * cam.R[c] + Je[a][1] * cam.R[3 + c] + Je[a][2] * cam.R[6 + c];
-    } else {
-      dpc[0] += gmx * cam.fx;
-      dpc[1] += gmy * cam.fy;
-      for (int a = 0; a < 2; ++a)
-        for (int c = 0; c < 3; ++c) Pe[a][c] = pv.P[a][c];
+      for (int c = 0; c < 3; ++c) GSP[a][c] = GS2[a][0] * P[0][c] + GS2[a][1] * P[1][c];
+    const int ij[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const int c = ij[k][0], d = ij[k][1];
+      dSig[k] += P[0][c] * GSP[0][d] + P[1][c] * GSP[1][d];
     }
-    for (int c = 0; c < 3; ++c) dp[c] += cam.R[c] * dpc[0] + cam.R[3 + c] * dpc[1] + cam.R[6 + c] * dpc[2];
+    float GJ[2][3];
+    for (int a = 0; a < 2; ++a) {
+      float GP[3];
+      for (int c = 0; c < 3; ++c)
+        GP[c] = 2.f * (GSP[a][0] * Sig[0][c] + GSP[a][1] * Sig[1][c] + GSP[a][2] * Sig[2][c]);
+      // P = J W: dL/dJ = dL/dP W^T
+      for (int b = 0; b < 3; ++b) GJ[a][b] = GP[0] * W[3 * b + 0] + GP[1] * W[3 * b + 1] + GP[2] * W[3 * b + 2];
+    }
+    // camera-space position gradient from the mean and from J
+    float dpc[3] = {0.f, 0.f, 0.f};
+    float Pe[2][3];  // Jacobian of the projected mean w.r.t. p (exact, unguarded)
+    if (cam.model == 0) {
+      const float iz = 1.f / pcz, iz2 = iz * iz;
+      dpc[0] += gmx * fx * iz;
+      dpc[1] += gmy * fy * iz;
+      dpc[2] -= (gmx * fx * pcx + gmy * fy * pcy) * iz2;
+      dpc[2] -= (GJ[0][0] * fx + GJ[1][1] * fy) * iz2;
+      // J02 = -fx gx / z, J12 = -fy gy / z with gx = x/z unless clamped
+      dpc[2] += (GJ[0][2] * fx * gx + GJ[1][2] * fy * gy) * iz2;
+      if (gx_free) {
+        dpc[0] -= GJ[0][2] * fx * iz2;
+        dpc[2] += GJ[0][2] * fx * pcx * iz2 * iz;
+      }
+      if (gy_free) {
+        dpc[1] -= GJ[1][2] * fy * iz2;
+        dpc[2] += GJ[1][2] * fy * pcy * iz2 * iz;
+      }
+      const float Je[2][3] = {{fx * iz, 0.f, -fx * pcx * iz2}, {0.f, fy * iz, -fy * pcy * iz2}};
+      for (int a = 0; a < 2; ++a)
+        for (int c = 0; c < 3; ++c) Pe[a][c] = Je[a][0] * W[c] + Je[a][2] * W[6 + c] + Je[a][1] * W[3 + c];
+    } else {
+      dpc[0] += gmx * fx;
+      dpc[1] += gmy * fy;
+      for (int a = 0; a < 2; ++a)
+        for (int c = 0; c < 3; ++c) Pe[a][c] = P[a][c];
+    }
+    for (int c = 0; c < 3; ++c) dp[c] += W[c] * dpc[0] + W[3 + c] * dpc[1] + W[6 + c] * dpc[2];
     dop += go;
 
     // splitting matrix: S2D = A M A - m0 A, M = [[-2ga, -gb], [-gb, -2gc]], m0 = o * go
-    const double M[2][2] = {{-2.0 * ga, -gb}, {-gb, -2.0 * gc}};
-    double AM[2][2], S2D[2][2];
+    const float M[2][2] = {{-2.f * ga, -gb}, {-gb, -2.f * gc}};
+    float AM[2][2], S2D[2][2];
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b) AM[a][b] = A[a][0] * M[0][b] + A[a][1] * M[1][b];
-    const double m0 = g.o * go;
+    const float m0 = o * go;
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b) S2D[a][b] = AM[a][0] * A[0][b] + AM[a][1] * A[1][b] - m0 * A[a][b];
-    double SP[2][3];
+    float SP[2][3];
     for (int a = 0; a < 2; ++a)
       for (int c = 0; c < 3; ++c) SP[a][c] = S2D[a][0] * Pe[0][c] + S2D[a][1] * Pe[1][c];
-    const int ij[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+#pragma unroll
     for (int k = 0; k < 6; ++k) {
       const int a = ij[k][0], b = ij[k][1];
       S3[k] += Pe[0][a] * SP[0][b] + Pe[1][a] * SP[1][b];
@@ -297,37 +416,37 @@ __global__ void __launch_bounds__(128) k_proj_bwd(const float* __restrict__ para
   }
   if (!any) return;
 
-  // Sigma = M M^T, M = R diag(s): dL/dM = 2 dSig M
-  double GM[3][3];
-  for (int a = 0; a < 3; ++a)
-    for (int k = 0; k < 3; ++k)
-      GM[a][k] = 2.0 * (dSig[a][0] * g.R[0][k] + dSig[a][1] * g.R[1][k] + dSig[a][2] * g.R[2][k]) * g.s[k];
-  double dls[3], GR[3][3];
+  // Sigma = M M^T, M = R diag(s): dL/dM = 2 dSig M (dSig symmetric)
+  const float G[3][3] = {{dSig[0], dSig[1], dSig[2]}, {dSig[1], dSig[3], dSig[4]}, {dSig[2], dSig[4], dSig[5]}};
+  float GR[3][3], dls[3];
   for (int k = 0; k < 3; ++k) {
-    dls[k] = (GM[0][k] * g.R[0][k] + GM[1][k] * g.R[1][k] + GM[2][k] * g.R[2][k]) * g.s[k];
-    for (int a = 0; a < 3; ++a) GR[a][k] = GM[a][k] * g.s[k];
+    float acc = 0.f;
+    for (int a = 0; a < 3; ++a) {
+      const float gm = 2.f * (G[a][0] * Rq[0][k] + G[a][1] * Rq[1][k] + G[a][2] * Rq[2][k]) * sc[k];
+      acc += gm * Rq[a][k];
+      GR[a][k] = gm * sc[k];
+    }
+    dls[k] = acc * sc[k];
   }
-  const double w = g.qw, x = g.qx, y = g.qy, z = g.qz;
-  double dq[4];
-  dq[0] = 2.0 * (-z * GR[0][1] + y * GR[0][2] + z * GR[1][0] - x * GR[1][2] - y * GR[2][0] + x * GR[2][1]);
-  dq[1] = 2.0 * (y * GR[0][1] + z * GR[0][2] + y * GR[1][0] - 2.0 * x * GR[1][1] - w * GR[1][2] + z * GR[2][0] +
-                 w * GR[2][1] - 2.0 * x * GR[2][2]);
-  dq[2] = 2.0 * (-2.0 * y * GR[0][0] + x * GR[0][1] + w * GR[0][2] + x * GR[1][0] + z * GR[1][2] - w * GR[2][0] +
-                 z * GR[2][1] - 2.0 * y * GR[2][2]);
-  dq[3] = 2.0 * (-2.0 * z * GR[0][0] - w * GR[0][1] + x * GR[0][2] + w * GR[1][0] - 2.0 * z * GR[1][1] +
+  float dq[4];
+  dq[0] = 2.f * (-z * GR[0][1] + y * GR[0][2] + z * GR[1][0] - x * GR[1][2] - y * GR[2][0] + x * GR[2][1]);
+  dq[1] = 2.f * (y * GR[0][1] + z * GR[0][2] + y * GR[1][0] - 2.f * x * GR[1][1] - w * GR[1][2] + z * GR[2][0] +
+                 w * GR[2][1] - 2.f * x * GR[2][2]);
+  dq[2] = 2.f * (-2.f * y * GR[0][0] + x * GR[0][1] + w * GR[0][2] + x * GR[1][0] + z * GR[1][2] - w * GR[2][0] +
+                 z * GR[2][1] - 2.f * y * GR[2][2]);
+  dq[3] = 2.f * (-2.f * z * GR[0][0] - w * GR[0][1] + x * GR[0][2] + w * GR[1][0] - 2.f * z * GR[1][1] +
                  y * GR[1][2] + x * GR[2][0] + y * GR[2][1]);
   // through the normalisation q_hat = q / |q|
-  const double qd = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
-  const double qh[4] = {w, x, y, z};
-  for (int k = 0; k < 4; ++k) dq[k] = (dq[k] - qh[k] * qd) / g.qn;
-
+  const float qd = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
+  const float qh[4] = {w, x, y, z};
   float* gp = grads + i;
-  for (int k = 0; k < 3; ++k) gp[(STEEPGS_ROW_MEAN + k) * n] += (float)dp[k];
-  for (int k = 0; k < 3; ++k) gp[(STEEPGS_ROW_LOG_SCALE + k) * n] += (float)dls[k];
-  for (int k = 0; k < 4; ++k) gp[(STEEPGS_ROW_QUAT + k) * n] += (float)dq[k];
-  gp[STEEPGS_ROW_OPACITY * n] += (float)(dop * g.o * (1.0 - g.o));
-  for (int k = 0; k < 3 * nb; ++k) gp[(STEEPGS_ROW_SH + k) * n] += dsh[k];
-  for (int k = 0; k < 6; ++k) S[k * n + i] += (float)S3[k];
+  for (int k = 0; k < 3; ++k) gp[(STEEPGS_ROW_MEAN + k) * n] += dp[k];
+  for (int k = 0; k < 3; ++k) gp[(STEEPGS_ROW_LOG_SCALE + k) * n] += dls[k];
+  for (int k = 0; k < 4; ++k) gp[(STEEPGS_ROW_QUAT + k) * n] += (dq[k] - qh[k] * qd) / qn;
+  gp[STEEPGS_ROW_OPACITY * n] += dop * o * (1.f - o);
+#pragma unroll
+  for (int k = 0; k < 3 * NB; ++k) gp[(STEEPGS_ROW_SH + k) * n] += dsh[k];
+  for (int k = 0; k < 6; ++k) S[k * n + i] += S3[k];
 }
 
 __global__ void k_zero(float* __restrict__ p, int64_t count) {
@@ -401,8 +520,13 @@ extern "C" steepgs_status steepgs_render_bwd_split(const float* d_params, int64_
                      d_n_contrib, d_dL_dimage, d_target, g2d, m, queue);
   timer_end(STEEPGS_TIMER_RENDER_BWD, st);
   timer_begin(STEEPGS_TIMER_PROJ_BWD, st);
-  hipLaunchKernelGGL(k_proj_bwd, dim3((unsigned)ceil_div(n, 128)), dim3(128), 0, st, d_params, n, sh_degree, d_cams, V,
-                     o, d_tiles_touched, g2d, d_grads, d_S);
+  const dim3 pg((unsigned)ceil_div(n, 128));
+  switch (sh_degree) {
+    case 0: hipLaunchKernelGGL(k_proj_bwd<0>, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d, d_grads, d_S); break;
+    case 1: hipLaunchKernelGGL(k_proj_bwd<1>, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d, d_grads, d_S); break;
+    case 2: hipLaunchKernelGGL(k_proj_bwd<2>, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d, d_grads, d_S); break;
+    default: hipLaunchKernelGGL(k_proj_bwd<3>, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d, d_grads, d_S); break;
+  }
   timer_end(STEEPGS_TIMER_PROJ_BWD, st);
   SG_TRY_LAUNCH();
   return STEEPGS_OK;

@@ -1,11 +1,14 @@
 // Stage 3: front-to-back alpha blending (Eq. alpha_blend) of every tile of
 // every view in one persistent launch.
 //
-// A workgroup owns one screen tile at a time (one thread per pixel) and takes
-// the next tile from a global atomic queue when done, so tiles with long
-// instance lists do not stall the rest of the grid.  The tile's instances are
-// staged through LDS in batches of one record per thread; the whole workgroup
-// leaves the tile as soon as every pixel's transmittance has hit the cut-off.
+// A workgroup owns one screen tile at a time (one thread per pixel, each
+// wavefront an 8x8 quadrant) and takes the next tile from a global atomic
+// queue when done, so tiles with long instance lists do not stall the rest of
+// the grid.  The tile's instances are staged through LDS in batches of one
+// record per thread.  A wavefront skips an entry outright when its quadrant
+// lies outside the entry's alpha >= alpha_min ellipse, stops when all its
+// pixels are saturated, and the workgroup leaves the tile when every pixel's
+// transmittance has hit the cut-off.
 #include "common.h"
 
 namespace sg {
@@ -18,12 +21,17 @@ __global__ void __launch_bounds__(TW* TH) k_render_fwd(const steepgs_splat* __re
                                                       steepgs_opts opt, int total_tiles,
                                                       const float* __restrict__ target, float* __restrict__ image,
                                                       float* __restrict__ T_final, uint32_t* __restrict__ n_contrib,
-                                                      uint32_t* __restrict__ n_used, float* __restrict__ loss, uint32_t* __restrict__ queue) {
+                                                      uint32_t* __restrict__ n_used, float* __restrict__ loss,
+                                                      uint32_t* __restrict__ queue) {
   constexpr int NT = TW * TH;
-  __shared__ float s_mx[NT], s_my[NT], s_a[NT], s_b[NT], s_c[NT], s_o[NT], s_r[NT], s_g[NT], s_bl[NT];
+  constexpr int WX = TW / 8;          // each wavefront owns an 8x8 pixel quadrant of the tile
+  __shared__ float4 s_m[NT];          // mean x, mean y, cut-off half extents x, y
+  __shared__ float4 s_q[NT];          // conic a, b, c, opacity
+  __shared__ float4 s_col[NT];        // rgb
   __shared__ float s_red[NT / 64];
   __shared__ int s_tile;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int qx = (wave % WX) * 8 + (lane & 7), qy = (wave / WX) * 8 + (lane >> 3);
   for (;;) {
     // The barrier closes the previous tile before lane 0 fetches the next one,
     // so no lane-0-only region can span the loop's back edge (the compiler
@@ -32,18 +40,19 @@ __global__ void __launch_bounds__(TW* TH) k_render_fwd(const steepgs_splat* __re
     __syncthreads();
     if (tid == 0) s_tile = (int)atomicAdd(queue, 1u);
     __syncthreads();
-    // scalar (wave-uniform) copy: the loop exit below must be a uniform branch,
-    // or the compiler may move the queue atomic out of the per-tile loop
+    // scalar (wave-uniform) copy: the loop exit below must be a uniform branch
     const int tile = __builtin_amdgcn_readfirstlane(s_tile);
-    __syncthreads();
     if (tile >= total_tiles) break;
     const int v = view_of_tile(cams, V, tile);
     const int W = cams[v].width, H = cams[v].height, tiles_x = cams[v].tiles_x;
     const int64_t pix_off = cams[v].pixel_offset;
     const int lt = tile - cams[v].tile_offset;
-    const int px = (lt % tiles_x) * TW + tid % TW;
-    const int py = (lt / tiles_x) * TH + tid / TW;
+    const int tx0 = (lt % tiles_x) * TW, ty0 = (lt / tiles_x) * TH;
+    const int px = tx0 + qx, py = ty0 + qy;
     const bool inside = px < W && py < H;
+    // the wavefront's pixel block, for the per-wave cut-off test
+    const float wx0 = (float)(tx0 + (wave % WX) * 8), wy0 = (float)(ty0 + (wave / WX) * 8);
+    const float wx1 = wx0 + 7.f, wy1 = wy0 + 7.f;
     const uint32_t begin = ranges[2 * tile], end = ranges[2 * tile + 1];
     const float fx = (float)px, fy = (float)py;
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
@@ -54,37 +63,39 @@ __global__ void __launch_bounds__(TW* TH) k_render_fwd(const steepgs_splat* __re
       const uint32_t idx = b0 + tid;
       if (idx < end) {
         const steepgs_splat s = splats[vals[idx]];
-        s_mx[tid] = s.mean_x;
-        s_my[tid] = s.mean_y;
-        s_a[tid] = s.conic_a;
-        s_b[tid] = s.conic_b;
-        s_c[tid] = s.conic_c;
-        s_o[tid] = s.opacity;
-        s_r[tid] = s.rgb[0];
-        s_g[tid] = s.rgb[1];
-        s_bl[tid] = s.rgb[2];
+        float ex, ey;
+        cutoff_extent(s.conic_a, s.conic_b, s.conic_c, s.opacity, opt.alpha_min, ex, ey);
+        s_m[tid] = make_float4(s.mean_x, s.mean_y, ex, ey);
+        s_q[tid] = make_float4(s.conic_a, s.conic_b, s.conic_c, s.opacity);
+        s_col[tid] = make_float4(s.rgb[0], s.rgb[1], s.rgb[2], 0.f);
       }
       __syncthreads();
       const int cnt = (int)min((uint32_t)NT, end - b0);
-      if (!done) {
-        for (int j = 0; j < cnt; ++j) {
-          const float dx = fx - s_mx[j], dy = fy - s_my[j];
-          const float G = __expf(splat_power(dx, dy, s_a[j], s_b[j], s_c[j]));
-          const float alpha = fminf(opt.alpha_max, s_o[j] * G);
-          if (alpha < opt.alpha_min) continue;
-          const float Tn = T * (1.f - alpha);
-          if (Tn < opt.t_min) {
-            done = true;
-            break;
-          }
-          const float w = alpha * T;
-          C0 += s_r[j] * w;
-          C1 += s_g[j] * w;
-          C2 += s_bl[j] * w;
-          T = Tn;
-          last = b0 - begin + (uint32_t)j + 1u;
-          ++used;
+      for (int j = 0; j < cnt; ++j) {
+        if (ballot(!done) == 0) break;  // the whole wavefront is finished
+        const float4 m = s_m[j];
+        // no pixel of this wavefront reaches alpha_min: skip for the whole wave
+        const bool hit = (m.x + m.z >= wx0) && (m.x - m.z <= wx1) && (m.y + m.w >= wy0) && (m.y - m.w <= wy1);
+        if (!__builtin_amdgcn_readfirstlane((int)hit)) continue;
+        if (done) continue;
+        const float4 q = s_q[j];
+        const float dx = fx - m.x, dy = fy - m.y;
+        const float G = __expf(splat_power(dx, dy, q.x, q.y, q.z));
+        const float alpha = fminf(opt.alpha_max, q.w * G);
+        if (alpha < opt.alpha_min) continue;
+        const float Tn = T * (1.f - alpha);
+        if (Tn < opt.t_min) {
+          done = true;
+          continue;
         }
+        const float4 c = s_col[j];
+        const float w = alpha * T;
+        C0 += c.x * w;
+        C1 += c.y * w;
+        C2 += c.z * w;
+        T = Tn;
+        last = b0 - begin + (uint32_t)j + 1u;
+        ++used;
       }
     }
     float err = 0.f;
@@ -105,8 +116,8 @@ __global__ void __launch_bounds__(TW* TH) k_render_fwd(const steepgs_splat* __re
       }
     }
     if (target) {
-      err = wave_sum(err);
-      if ((tid & 63) == 0) s_red[tid >> 6] = err;
+      err = wave_sum_dpp(err);
+      if (lane == 0) s_red[wave] = err;
       __syncthreads();
       if (tid == 0) {
         float s = 0.f;
