@@ -49,21 +49,26 @@ def parse():
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eps", type=float, default=1e-3)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (HBM counter calibration under a profiler)")
     return ap.parse_args()
 
 
 def time_region(fn, steps, torch):
+    """Mean ms per step over exactly `steps` calls between two synchronised
+    events, the host wall clock of the same region, and the per-step times
+    (an event after each step)."""
     torch.cuda.synchronize()
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    a.record()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for k in range(steps):
         fn()
-    b.record()
+        ev[k + 1].record()
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3 / steps
-    return a.elapsed_time(b) / steps, wall
+    per = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+    return ev[0].elapsed_time(ev[steps]) / steps, wall, per
 
 
 def kernel_times(step, steps, torch, L):
@@ -135,6 +140,13 @@ def main():
     scene = scenes.make(args.workload)
     opts = scenes.opts("3dgs")
     say(f"scene ready in {time.perf_counter() - t0:.1f} s: n={scene.n} V={scene.cams.V} px={scene.cams.total_pixels()}")
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        say(f"calibration copy of {args.copy_mib} MiB done")
+        del src, dst
     P = torch.from_numpy(scene.params).to(dev)
     target = torch.from_numpy(scene.target).to(dev)
     cams = CameraBatch(scene.cams, opts, dev)
@@ -165,9 +177,13 @@ def main():
             use_graph = False
     fn = step.replay if use_graph else step.run
     say(f"timing {args.steps} batched steps ({'graph' if use_graph else 'eager'})")
-    ms_batched, wall_batched = time_region(fn, args.steps, torch)
+    torch.cuda.reset_peak_memory_stats()
+    ms_batched, wall_batched, per_step = time_region(fn, args.steps, torch)
+    peak_gb = torch.cuda.max_memory_allocated() / 2**30
     step.check()
-    say(f"batched: {ms_batched:.3f} ms/step (host wall {wall_batched:.3f})")
+    pct = np.percentile(per_step, [10, 50, 90])
+    say(f"batched: {ms_batched:.3f} ms/step (host wall {wall_batched:.3f}; p10/p50/p90 "
+        f"{pct[0]:.3f}/{pct[1]:.3f}/{pct[2]:.3f}); peak allocated {peak_gb:.2f} GiB")
 
     say("per-kernel events over eager steps")
     kt = kernel_times(step, args.steps, torch, L)
@@ -183,7 +199,7 @@ def main():
             pv.run()
         pv.check()
         say(f"timing {args.steps} per-view steps")
-        per_view, _ = time_region(pv.run, args.steps, torch)
+        per_view, _, _ = time_region(pv.run, args.steps, torch)
         pv.check()
         say(f"per-view: {per_view:.3f} ms/step")
         del pv
@@ -237,6 +253,8 @@ def main():
         "config": {"workload": args.workload, "gaussians": n, "views": V, "pixels": Px, "sh_degree": scene.sh_degree,
                    "resolutions": [f"{w}x{h}" for w, h in zip(cams.widths, cams.heights)],
                    "tile": f"{opts['tile_w']}x{opts['tile_h']}", "graph": use_graph, "eps_split": -1e-6},
+        "step_ms_p10_p50_p90": [round(float(x), 4) for x in pct],
+        "peak_allocated_gib": round(peak_gb, 3),
         "per_view_ms_per_step": None if per_view is None else round(per_view, 4),
         "speedup_batched_vs_per_view": None if per_view is None else round(per_view / ms_batched, 3),
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},

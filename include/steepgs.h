@@ -107,7 +107,8 @@ typedef struct {
 /* Projected record of one (view, Gaussian) pair, 48 bytes.  Index r = v*n + i.
  * conic = (a, b, c) with A = [[a, b], [b, c]] = Pi(Sigma)^-1.  rect packs the
  * inclusive tile rectangle: rect_lo = x0 | y0 << 16, rect_hi = x1 | y1 << 16.
- * A culled pair has opacity 0 and tiles_touched 0. */
+ * A pair is culled when tiles_touched is 0; a pair culled by the projection
+ * itself (near plane, degenerate conic, empty rectangle) also has opacity 0. */
 typedef struct {
   float mean_x, mean_y;
   float conic_a, conic_b;
@@ -129,15 +130,19 @@ size_t steepgs_workspace_size(int32_t stage, int64_t n, int32_t V, uint64_t capa
 
 /* Stage 1 -- projection (Sec. 3, Eqs. sigma_3D / sigma_2D).
  * In:  d_params [F][n], d_cams [V] (device copy of laid-out cameras).
- * Out: d_splats [V*n], d_tiles_touched [V*n] (tiles in the rectangle, 0 if
- *      culled).  Discrete outcomes (culling, footprint, depth) are computed in
- *      fp64 in a fixed operation order. */
+ * Out: d_splats [V*n], d_tiles_touched [V*n]: the tiles of the rectangle whose
+ *      box of pixel centres meets the footprint ellipse d^T A d <=
+ *      radius_sigmas^2 (tested in fp64 on the stored float32 mean and conic,
+ *      1e-6 relative slack; the same test selects the instances in
+ *      steepgs_sort), 0 if culled.  Discrete outcomes (culling, footprint,
+ *      depth) are computed in fp64 in a fixed operation order. */
 steepgs_status steepgs_project(const float* d_params, int64_t n, int32_t sh_degree, const steepgs_camera* d_cams,
                                int32_t V, const steepgs_opts* opts, steepgs_splat* d_splats,
                                uint32_t* d_tiles_touched, void* stream);
 
 /* Stage 2 -- instance list (Sec. 3 "Rasterization": sort by view-dependent
- * depth).  One instance per (visible pair, covered tile); 64-bit key
+ * depth).  One instance per (visible pair, tile of its footprint, the tiles
+ * counted by steepgs_project); 64-bit key
  * global_tile << 32 | float bits of depth; value r = v*n + i; sorted by key,
  * ties by r (the order of emission view, Gaussian, row-major tile).
  * Out: d_vals [capacity] sorted values; d_keys [capacity] (nullable) sorted

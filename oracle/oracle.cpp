@@ -239,7 +239,45 @@ struct Proj {
   double depth = 0;  // camera-space z
   double rgb_raw[3] = {0, 0, 0};
   int rect[4] = {0, 0, -1, -1};  // tile x0, y0, x1, y1 (inclusive)
+  float fmx, fmy, fa, fb, fc;    // mean and conic rounded to float32 (the stored record)
+  int ntiles = 0;                // tiles of the rectangle that meet the cut-off ellipse
 };
+
+// Smallest value of q(d) = a dx^2 + 2 b dx dy + c dy^2, d = x - m, over the box
+// [x0, x1] x [y0, y1] for a positive-definite conic: 0 when m lies inside,
+// otherwise the smallest of the four edge minima, each the one-dimensional
+// minimiser clamped to its edge (q is convex).
+double box_min_q(double a, double b, double c, double mx, double my, double x0, double x1, double y0, double y1) {
+  if (mx >= x0 && mx <= x1 && my >= y0 && my <= y1) return 0.0;
+  double best = INFINITY;
+  for (int e = 0; e < 2; ++e) {
+    double dx = (e == 0 ? x0 : x1) - mx;
+    double dy = -(b * dx) / c;
+    if (dy < y0 - my) dy = y0 - my;
+    if (dy > y1 - my) dy = y1 - my;
+    double q = a * dx * dx + 2.0 * b * dx * dy + c * dy * dy;
+    if (q < best) best = q;
+    double ey = (e == 0 ? y0 : y1) - my;
+    double ex = -(b * ey) / a;
+    if (ex < x0 - mx) ex = x0 - mx;
+    if (ex > x1 - mx) ex = x1 - mx;
+    q = a * ex * ex + 2.0 * b * ex * ey + c * ey * ey;
+    if (q < best) best = q;
+  }
+  return best;
+}
+
+// Tile (tx, ty) belongs to the footprint when its box of pixel centres meets
+// the ellipse q <= radius_sigmas^2 (1e-6 relative slack), evaluated on the
+// float32 record so that any implementation storing that record can repeat it.
+template <class T>
+bool tile_hit(const Proj<T>& p, const Opts& opt, int tx, int ty) {
+  double k2 = (double)opt.radius_sigmas * (double)opt.radius_sigmas;
+  double x0 = (double)tx * opt.tw, y0 = (double)ty * opt.th;
+  double q = box_min_q((double)p.fa, (double)p.fb, (double)p.fc, (double)p.fmx, (double)p.fmy, x0, x0 + (opt.tw - 1),
+                       y0, y0 + (opt.th - 1));
+  return q <= k2 * (1.0 + 1e-6);
+}
 
 template <class T>
 void project(const T* th, int deg, const Cam& cam, const Opts& opt, Proj<T>& out) {
@@ -334,6 +372,16 @@ void project(const T* th, int deg, const Cam& cam, const Opts& opt, Proj<T>& out
   out.rect[1] = (int)y0;
   out.rect[2] = (int)x1;
   out.rect[3] = (int)y1;
+  // of the rectangle, the tiles that meet the cut-off ellipse
+  out.fmx = (float)val(out.mx);
+  out.fmy = (float)val(out.my);
+  out.fa = (float)val(out.A00);
+  out.fb = (float)val(out.A01);
+  out.fc = (float)val(out.A11);
+  out.ntiles = 0;
+  for (int ty = out.rect[1]; ty <= out.rect[3]; ++ty)
+    for (int tx = out.rect[0]; tx <= out.rect[2]; ++tx) out.ntiles += tile_hit(out, opt, tx, ty) ? 1 : 0;
+  if (out.ntiles == 0) return;
 
   // colour: SH evaluated at the unit direction from the camera centre
   double campos[3];
@@ -362,6 +410,14 @@ T alpha_raw(const T& mx, const T& my, const T& A00, const T& A01, const T& A11, 
   T dx = u - mx, dy = v - my;
   T power = -0.5 * (A00 * dx * dx + 2.0 * A01 * dx * dy + A11 * dy * dy);
   return o * exp_(power);
+}
+
+// alpha inside the footprint (q <= radius_sigmas^2), 0 outside
+double alpha_in_footprint(const Proj<double>& g, const Opts& opt, double u, double v) {
+  double dx = u - g.mx, dy = v - g.my;
+  double q = g.A00 * dx * dx + 2.0 * g.A01 * dx * dy + g.A11 * dy * dy;
+  if (q > opt.radius_sigmas * opt.radius_sigmas) return 0.0;
+  return alpha_raw(g.mx, g.my, g.A00, g.A01, g.A11, g.o, u, v);
 }
 
 // Hessian of alpha w.r.t. the projected mean (Sec. 4.4, App. C.4):
@@ -441,7 +497,8 @@ struct Pixel {
 };
 
 constexpr double kAlphaBand = 1e-5;  // relative band around alpha_min / alpha_max
-constexpr double kTBand = 1e-4;      // relative band around t_min
+constexpr double kQBand = 1e-5;      // relative band around the footprint cut-off radius_sigmas^2
+constexpr double kTBand = 5e-5;      // relative band around t_min (fp32 transmittance after ~400 factors)
 
 void blend_pixel(const View& view, int u, int v, Pixel& px) {
   const Cam& cam = *view.cam;
@@ -453,11 +510,21 @@ void blend_pixel(const View& view, int u, int v, Pixel& px) {
   px.amb_ids.clear();
   px.ambig = false;
   px.listed = (int)lst.size();
+  const double k2 = opt.radius_sigmas * opt.radius_sigmas;
   for (size_t j = 0; j < lst.size(); ++j) {
     const Proj<double>& g = view.rec[lst[j]];
+    // footprint: only pixels within radius_sigmas (Mahalanobis) of the mean
+    double dxu = u - g.mx, dyv = v - g.my;
+    double q = g.A00 * dxu * dxu + 2.0 * g.A01 * dxu * dyv + g.A11 * dyv * dyv;
+    bool amb = std::fabs(q - k2) <= kQBand * k2;
+    if (amb) {
+      px.ambig = true;
+      px.amb_ids.push_back(lst[j]);
+    }
+    if (q > k2) continue;
     double a = alpha_raw(g.mx, g.my, g.A00, g.A01, g.A11, g.o, (double)u, (double)v);
     bool clamped = false;
-    bool amb = false;
+    amb = false;
     if (opt.alpha_max < 1.0 && std::fabs(a - opt.alpha_max) <= kAlphaBand * opt.alpha_max) amb = true;
     if (a > opt.alpha_max) {
       a = opt.alpha_max;
@@ -671,7 +738,7 @@ int orc_project(const float* params, int64_t n, int deg, const float* cam_f, con
       o[10] = p.rgb_raw[0]; o[11] = p.rgb_raw[1]; o[12] = p.rgb_raw[2];
       for (int k = 0; k < 4; ++k) rect[4 * r + k] = p.rect[k];
       visible[r] = p.visible ? 1 : 0;
-      tiles[r] = p.visible ? (uint32_t)((p.rect[2] - p.rect[0] + 1) * (p.rect[3] - p.rect[1] + 1)) : 0u;
+      tiles[r] = p.visible ? (uint32_t)p.ntiles : 0u;
       dbits[r] = p.visible ? depth_bits(p.depth) : 0u;
     }
   return 0;
@@ -698,6 +765,7 @@ int orc_sort(const float* params, int64_t n, int deg, const float* cam_f, const 
       uint64_t db = depth_bits(p.depth);
       for (int ty = p.rect[1]; ty <= p.rect[3]; ++ty)
         for (int tx = p.rect[0]; tx <= p.rect[2]; ++tx) {
+          if (!tile_hit(p, opt, tx, ty)) continue;
           uint64_t tile = (uint64_t)cams[v].tile_offset + (uint64_t)ty * cams[v].tiles_x + tx;
           inst.push_back({(tile << 32) | db, (uint32_t)((int64_t)v * n + i)});
         }
@@ -724,7 +792,8 @@ int orc_sort(const float* params, int64_t n, int deg, const float* cam_f, const 
 //   g2d [V*n][9] and H2d [V*n][3] per-view accumulators, gauss_ambig [n].
 // sign_band: |C - target| below it marks the pixel ambiguous.
 int orc_forward_backward(const float* params, int64_t n, int deg, const float* cam_f, const int32_t* cam_i, int V,
-                         const double* opts, const float* target, double sign_band, double* image, double* T_final,
+                         const double* opts, const float* target, const double* dLdimage, double sign_band,
+                         double* image, double* T_final,
                          int32_t* n_used, uint8_t* pix_ambig, double* loss, double* grads, double* S, double* g2d,
                          double* H2d, uint8_t* gauss_ambig) {
   if (n < 0 || V <= 0 || deg < 0 || deg > 3) return 1;
@@ -751,14 +820,18 @@ int orc_forward_backward(const float* params, int64_t n, int deg, const float* c
         if (T_final) T_final[pid] = px.T_final;
         if (n_used) n_used[pid] = (int32_t)px.list.size();
         bool amb = px.ambig;
-        if (!target) {
+        if (!target && !dLdimage) {
           if (pix_ambig) pix_ambig[pid] = amb;
           continue;
         }
         double dLdC[3];
         for (int ch = 0; ch < 3; ++ch) {
-          double tg = target[3 * cam.pixel_offset + (int64_t)ch * cam.W * cam.H + (int64_t)y * cam.W + x];
-          double diff = px.C[ch] - tg;
+          const int64_t e = 3 * cam.pixel_offset + (int64_t)ch * cam.W * cam.H + (int64_t)y * cam.W + x;
+          if (dLdimage) {  // an upstream loss gradient: no L1 term
+            dLdC[ch] = dLdimage[e];
+            continue;
+          }
+          double diff = px.C[ch] - target[e];
           lsum += std::fabs(diff);
           dLdC[ch] = sgn(diff) * inv;
           if (std::fabs(diff) < sign_band) amb = true;
@@ -767,8 +840,8 @@ int orc_forward_backward(const float* params, int64_t n, int deg, const float* c
         if (amb && gauss_ambig) mark_affected(px, gauss_ambig);
         backward_pixel(view, x, y, px, dLdC, acc, nullptr);
       }
-    if (!target) continue;
-    if (loss) loss[v] = lsum * inv;
+    if (!target && !dLdimage) continue;
+    if (loss) loss[v] = dLdimage ? 0.0 : lsum * inv;
     for (int64_t i = 0; i < n; ++i) {
       int64_t r = (int64_t)v * n + i;
       if (g2d)
@@ -938,10 +1011,10 @@ double orc_loss_merged_split(const float* params, int64_t n, int deg, const floa
           if (lst[j] == gi) {
             a = 0.0;
             for (int ch = 0; ch < 3; ++ch) rgb[ch] = g.rgb[ch];
-            if (cp.visible) a += 0.5 * alpha_raw(cp.mx, cp.my, cp.A00, cp.A01, cp.A11, cp.o, (double)x, (double)y);
-            if (cm.visible) a += 0.5 * alpha_raw(cm.mx, cm.my, cm.A00, cm.A01, cm.A11, cm.o, (double)x, (double)y);
+            if (cp.visible) a += 0.5 * alpha_in_footprint(cp, opt, (double)x, (double)y);
+            if (cm.visible) a += 0.5 * alpha_in_footprint(cm, opt, (double)x, (double)y);
           } else {
-            a = alpha_raw(g.mx, g.my, g.A00, g.A01, g.A11, g.o, (double)x, (double)y);
+            a = alpha_in_footprint(g, opt, (double)x, (double)y);
             for (int ch = 0; ch < 3; ++ch) rgb[ch] = g.rgb[ch];
           }
           if (a > opt.alpha_max) a = opt.alpha_max;
@@ -1020,6 +1093,55 @@ int64_t orc_densify(const float* params, int64_t n, int deg, const double* S, do
     out_params[(int64_t)10 * out_cap + o + 1] = logit;
   }
   return off[n];
+}
+
+}  // extern "C"
+
+extern "C" {
+
+// Instance lists of selected global tiles (the values a sorted instance list
+// holds in each tile's range): records r = v*n + i whose footprint holds the
+// tile, ordered by (depth float bits, r).  counts[k] = list length of tile k;
+// lists is filled back to back when non-null (call once with nullptr for the
+// counts).
+int orc_tile_lists(const float* params, int64_t n, int deg, const float* cam_f, const int32_t* cam_i, int V,
+                   const double* opts, const int64_t* tiles, int64_t nt, int64_t* counts, uint32_t* lists) {
+  Opts opt = read_opts(opts);
+  std::vector<Cam> cams = read_cams(cam_f, cam_i, V, opt);
+  std::vector<std::vector<uint32_t>> out(nt);
+  double th[59];
+  for (int v = 0; v < V; ++v) {
+    const Cam& cam = cams[v];
+    int64_t first = cam.tile_offset, last = cam.tile_offset + (int64_t)cam.tiles_x * cam.tiles_y;
+    bool any = false;
+    for (int64_t k = 0; k < nt; ++k) any |= tiles[k] >= first && tiles[k] < last;
+    if (!any) continue;
+    std::vector<Proj<double>> rec(n);
+    for (int64_t i = 0; i < n; ++i) {
+      load_theta(params, n, deg, i, th);
+      project(th, deg, cam, opt, rec[i]);
+    }
+    for (int64_t k = 0; k < nt; ++k) {
+      if (tiles[k] < first || tiles[k] >= last) continue;
+      int tx = (int)((tiles[k] - first) % cam.tiles_x), ty = (int)((tiles[k] - first) / cam.tiles_x);
+      std::vector<std::pair<uint32_t, uint32_t>> items;
+      for (int64_t i = 0; i < n; ++i) {
+        const Proj<double>& p = rec[i];
+        if (!p.visible || tx < p.rect[0] || tx > p.rect[2] || ty < p.rect[1] || ty > p.rect[3]) continue;
+        if (!tile_hit(p, opt, tx, ty)) continue;
+        items.push_back({depth_bits(p.depth), (uint32_t)((int64_t)v * n + i)});
+      }
+      std::sort(items.begin(), items.end());
+      for (auto& it : items) out[k].push_back(it.second);
+    }
+  }
+  int64_t pos = 0;
+  for (int64_t k = 0; k < nt; ++k) {
+    counts[k] = (int64_t)out[k].size();
+    if (lists)
+      for (uint32_t r : out[k]) lists[pos++] = r;
+  }
+  return 0;
 }
 
 }  // extern "C"

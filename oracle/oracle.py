@@ -51,7 +51,7 @@ def lib():
         L.orc_project.restype = C.c_int
         L.orc_sort.argtypes = common + [C.POINTER(C.c_uint64), C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_sort.restype = C.c_int
-        L.orc_forward_backward.argtypes = common + [C.c_void_p, C.c_double] + [C.c_void_p] * 10
+        L.orc_forward_backward.argtypes = common + [C.c_void_p, C.c_void_p, C.c_double] + [C.c_void_p] * 10
         L.orc_forward_backward.restype = C.c_int
         L.orc_loss.argtypes = common + [_c_f32]
         L.orc_loss.restype = C.c_double
@@ -72,6 +72,8 @@ def lib():
         L.orc_densify.argtypes = [_c_f32, C.c_int64, C.c_int, _c_f64, C.c_double, C.c_double, C.c_double, _c_f64,
                                   C.c_int64, _c_f64, _c_f64, _c_u8, C.POINTER(C.c_int64)]
         L.orc_densify.restype = C.c_int64
+        L.orc_tile_lists.argtypes = common + [_c_i64, C.c_int64, _c_i64, C.c_void_p]
+        L.orc_tile_lists.restype = C.c_int
         L.orc_num_params.argtypes = [C.c_int]
         L.orc_num_params.restype = C.c_int
         _lib = L
@@ -147,7 +149,9 @@ def sort(params, sh_degree, cams, opts):
     return keys[:K], vals[:K], ranges
 
 
-def forward_backward(params, sh_degree, cams, opts, target=None, sign_band=1e-5, per_view=False):
+def forward_backward(params, sh_degree, cams, opts, target=None, sign_band=1e-5, per_view=False, dl_dimage=None):
+    """Image, and with ``target`` (L1 loss of Eq. loss) or ``dl_dimage`` (an
+    upstream gradient w.r.t. the packed image, [3*Px]) the gradients and S."""
     args = _common(params, sh_degree, cams, opts)
     n = args[1]
     F = params.shape[0]
@@ -158,8 +162,9 @@ def forward_backward(params, sh_degree, cams, opts, target=None, sign_band=1e-5,
     pamb = np.zeros(Px, np.uint8)
     out = dict(image=image, T_final=T, n_used=used, pix_ambig=pamb)
     tgt = None if target is None else np.ascontiguousarray(target, np.float32)
+    dld = None if dl_dimage is None else np.ascontiguousarray(dl_dimage, np.float64)
     loss = grads = S = g2d = H2d = gamb = None
-    if tgt is not None:
+    if tgt is not None or dld is not None:
         loss = np.zeros(cams.V, np.float64)
         grads = np.zeros((F, n), np.float64)
         S = np.zeros((9, n), np.float64)
@@ -167,11 +172,11 @@ def forward_backward(params, sh_degree, cams, opts, target=None, sign_band=1e-5,
         if per_view:
             g2d = np.zeros((cams.V * n, 9), np.float64)
             H2d = np.zeros((cams.V * n, 3), np.float64)
-    rc = lib().orc_forward_backward(*args, _ptr(tgt), float(sign_band), _ptr(image), _ptr(T), _ptr(used),
+    rc = lib().orc_forward_backward(*args, _ptr(tgt), _ptr(dld), float(sign_band), _ptr(image), _ptr(T), _ptr(used),
                                     _ptr(pamb), _ptr(loss), _ptr(grads), _ptr(S), _ptr(g2d), _ptr(H2d), _ptr(gamb))
     assert rc == 0
     out["pix_ambig"] = pamb.astype(bool)
-    if tgt is not None:
+    if tgt is not None or dld is not None:
         out.update(loss=loss, grads=grads, S=S, gauss_ambig=gamb.astype(bool))
         if per_view:
             out.update(g2d=g2d, H2d=H2d)
@@ -251,3 +256,18 @@ def densify(params, sh_degree, S9, s_scale, eps, eps_split, out_cap=None):
                               lam, vmin, split, C.byref(need))
     return dict(n_out=int(n_out), needed=int(need.value), params=out[:, :max(n_out, 0)], lambda_min=lam,
                 vmin=vmin, split=split.astype(bool))
+
+
+def tile_lists(params, sh_degree, cams, opts, tiles):
+    """Expected instance-list values of the given global tiles: {tile: record ids}."""
+    args = _common(params, sh_degree, cams, opts)
+    t = np.ascontiguousarray(tiles, np.int64)
+    counts = np.zeros(len(t), np.int64)
+    assert lib().orc_tile_lists(*args, t, len(t), counts, None) == 0
+    lists = np.zeros(max(int(counts.sum()), 1), np.uint32)
+    assert lib().orc_tile_lists(*args, t, len(t), counts, _ptr(lists)) == 0
+    out, pos = {}, 0
+    for k, tile in enumerate(t):
+        out[int(tile)] = lists[pos: pos + counts[k]]
+        pos += int(counts[k])
+    return out

@@ -105,24 +105,29 @@ SG_DEV float splat_power(float dx, float dy, float a, float b, float c) {
   return -0.5f * (a * dx * dx + c * dy * dy) - b * dx * dy;
 }
 
-// Half-extents of the region where alpha >= alpha_min: the ellipse
-// d^T A d <= 2 ln(o / alpha_min), whose x half-width is sqrt(tau (A^-1)_xx).
-// Widened by 1% and 1/16 pixel so a test against it is conservative for the
-// fp32 evaluation of alpha; empty (negative) when o <= alpha_min; unbounded
-// when alpha_min = 0.
-SG_DEV void cutoff_extent(float a, float b, float c, float o, float alpha_min, float& ex, float& ey) {
-  if (!(alpha_min > 0.f)) {
-    ex = ey = INFINITY;
-    return;
+// A pixel takes part in a Gaussian's blend only inside its footprint,
+// d^T A d <= radius_sigmas^2, i.e. power = -1/2 d^T A d >= this value.  The
+// forward and backward raster kernels both test against it.
+SG_DEV float footprint_power_cut(const steepgs_opts& opt) { return -0.5f * opt.radius_sigmas * opt.radius_sigmas; }
+
+// Half-extents of the region where a pixel can contribute: inside the
+// footprint and alpha >= alpha_min, the ellipse d^T A d <= t with
+// t = min(radius_sigmas^2, 2 ln(o / alpha_min)); its x half-width is
+// sqrt(t (A^-1)_xx).  Widened by 1% and 1/16 pixel so a test against it is
+// conservative for the fp32 evaluation; empty (negative) when
+// o <= alpha_min.
+SG_DEV void cutoff_extent(float a, float b, float c, float o, const steepgs_opts& opt, float& ex, float& ey) {
+  float t = opt.radius_sigmas * opt.radius_sigmas;
+  if (opt.alpha_min > 0.f) {
+    if (!(o > opt.alpha_min)) {
+      ex = ey = -INFINITY;
+      return;
+    }
+    t = fminf(t, 2.f * __logf(o / opt.alpha_min));
   }
-  if (!(o > alpha_min)) {
-    ex = ey = -INFINITY;
-    return;
-  }
-  const float tau = 2.f * __logf(o / alpha_min);
   const float det = a * c - b * b;
-  ex = sqrtf(tau * c / det) * 1.01f + 0.0625f;
-  ey = sqrtf(tau * a / det) * 1.01f + 0.0625f;
+  ex = sqrtf(t * c / det) * 1.01f + 0.0625f;
+  ey = sqrtf(t * a / det) * 1.01f + 0.0625f;
 }
 
 // wave-wide sum with DPP row operations; the total is returned to every lane

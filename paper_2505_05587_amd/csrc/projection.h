@@ -99,6 +99,45 @@ SG_DEV void sh_grad(int deg, T x, T y, T z, const T* w, T g[3]) {
   g[1] += T(6.0 * kSH3a) * x * y * w[15];
 }
 
+// Smallest value of q(d) = a dx^2 + 2 b dx dy + c dy^2, d = x - m, over the box
+// [x0, x1] x [y0, y1] for a positive-definite conic: 0 when m lies inside,
+// otherwise the smallest of the four edge minima, each the one-dimensional
+// minimiser clamped to its edge (q is convex).  fp64, fixed operation order.
+SG_DEV double box_min_q(double a, double b, double c, double mx, double my, double x0, double x1, double y0,
+                        double y1) {
+#pragma clang fp contract(off)
+  if (mx >= x0 && mx <= x1 && my >= y0 && my <= y1) return 0.0;
+  double best = INFINITY;
+  for (int e = 0; e < 2; ++e) {
+    const double dx = (e == 0 ? x0 : x1) - mx;
+    double dy = -(b * dx) / c;
+    if (dy < y0 - my) dy = y0 - my;
+    if (dy > y1 - my) dy = y1 - my;
+    double q = a * dx * dx + 2.0 * b * dx * dy + c * dy * dy;
+    if (q < best) best = q;
+    const double ey = (e == 0 ? y0 : y1) - my;
+    double ex = -(b * ey) / a;
+    if (ex < x0 - mx) ex = x0 - mx;
+    if (ex > x1 - mx) ex = x1 - mx;
+    q = a * ex * ex + 2.0 * b * ex * ey + c * ey * ey;
+    if (q < best) best = q;
+  }
+  return best;
+}
+
+// A tile belongs to a Gaussian's footprint when its box of pixel centres
+// meets the ellipse q <= radius_sigmas^2 (1e-6 relative slack).  Evaluated on
+// the stored float32 mean and conic, so the projection (which counts the
+// tiles) and the instance emission (which lists them) take the same decision.
+SG_DEV bool tile_hit(float mx, float my, float a, float b, float c, const steepgs_opts& opt, int tx, int ty) {
+#pragma clang fp contract(off)
+  const double k2 = (double)opt.radius_sigmas * (double)opt.radius_sigmas;
+  const double x0 = (double)tx * opt.tile_w, y0 = (double)ty * opt.tile_h;
+  const double q = box_min_q((double)a, (double)b, (double)c, (double)mx, (double)my, x0, x0 + (opt.tile_w - 1), y0,
+                             y0 + (opt.tile_h - 1));
+  return q <= k2 * (1.0 + 1e-6);
+}
+
 // view-independent part of a Gaussian
 struct Gauss {
   double p[3];

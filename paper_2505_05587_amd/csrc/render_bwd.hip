@@ -5,8 +5,9 @@
 // contributors back to front, recomputing alpha with the forward's own
 // routine and the transmittance T_i = T_{i+1} / (1 - alpha_i) from the stored
 // final value (no per-pixel lists are stored).  The walk starts at the last
-// contributor of the workgroup (of the wavefront, per wave), and a wavefront
-// skips entries whose alpha >= alpha_min ellipse misses its 8x8 quadrant.
+// contributor of the workgroup (of the wavefront, per wave); the thread that
+// stages an entry tests its alpha >= alpha_min box against every 8x8
+// quadrant, and each wavefront walks only the entries that reach its own.
 // Per contributor it forms
 //   g = dL/dalpha_i = sum_c dL/dC_c (c_i T_i - R_c / (1 - alpha_i)),
 // R = colour of everything behind i (background included), and the
@@ -39,14 +40,17 @@ __global__ void __launch_bounds__(TW* TH) k_render_bwd(const steepgs_splat* __re
                                                       const float* __restrict__ target, float* __restrict__ g2d,
                                                       int64_t m, uint32_t* __restrict__ queue) {
   constexpr int NT = TW * TH;
-  constexpr int WX = TW / 8;  // each wavefront owns an 8x8 pixel quadrant of the tile
-  __shared__ float4 s_m[NT];    // mean x, mean y, cut-off half extents x, y
-  __shared__ float4 s_q[NT];    // conic a, b, c, opacity
-  __shared__ float4 s_col[NT];  // rgb, record id (bits)
-  __shared__ uint32_t s_last[NT / 64];
+  constexpr int NW = NT / 64;           // wavefronts per workgroup = 64-entry chunks per batch
+  constexpr int WX = TW / 8;            // each wavefront owns an 8x8 pixel quadrant of the tile
+  __shared__ float4 s_a[NT];            // mean x, mean y, conic a, conic b
+  __shared__ float4 s_c[NT];            // conic c, opacity, red, green
+  __shared__ float2 s_e[NT];            // blue, record id (bits)
+  __shared__ uint64_t s_bits[NW][NW];   // [wave][chunk]: entries of the chunk that reach the wave's quadrant
+  __shared__ uint32_t s_last[NW];
   __shared__ int s_tile;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int qx = (wave % WX) * 8 + (lane & 7), qy = (wave / WX) * 8 + (lane >> 3);
+  const float cut = footprint_power_cut(opt);
   for (;;) {
     // The barrier closes the previous tile before lane 0 fetches the next one,
     // so no lane-0-only region can span the loop's back edge.
@@ -63,8 +67,6 @@ __global__ void __launch_bounds__(TW* TH) k_render_bwd(const steepgs_splat* __re
     const int tx0 = (lt % tiles_x) * TW, ty0 = (lt / tiles_x) * TH;
     const int px = tx0 + qx, py = ty0 + qy;
     const bool inside = px < W && py < H;
-    const float wx0 = (float)(tx0 + (wave % WX) * 8), wy0 = (float)(ty0 + (wave / WX) * 8);
-    const float wx1 = wx0 + 7.f, wy1 = wy0 + 7.f;
     const uint32_t begin = ranges[2 * tile];
     const float fx = (float)px, fy = (float)py;
     float T = 1.f, dC0 = 0.f, dC1 = 0.f, dC2 = 0.f, R0 = 0.f, R1 = 0.f, R2 = 0.f;
@@ -97,84 +99,109 @@ __global__ void __launch_bounds__(TW* TH) k_render_bwd(const steepgs_splat* __re
     if (lane == 0) s_last[wave] = (uint32_t)wlast;
     __syncthreads();
     int count = 0;
-    for (int w = 0; w < NT / 64; ++w) count = max(count, (int)s_last[w]);
+    for (int w = 0; w < NW; ++w) count = max(count, (int)s_last[w]);
     count = __builtin_amdgcn_readfirstlane(count);
     for (int b_end = count; b_end > 0; b_end -= NT) {
       const int b_start = b_end > NT ? b_end - NT : 0;
       __syncthreads();
+      // stage one batch; the loading thread tests the entry's cut-off box
+      // against the quadrant of every wavefront
+      uint32_t qmask = 0;
       if (b_start + tid < b_end) {
         const uint32_t id = vals[begin + b_start + tid];
         const steepgs_splat s = splats[id];
         float ex, ey;
-        cutoff_extent(s.conic_a, s.conic_b, s.conic_c, s.opacity, opt.alpha_min, ex, ey);
-        s_m[tid] = make_float4(s.mean_x, s.mean_y, ex, ey);
-        s_q[tid] = make_float4(s.conic_a, s.conic_b, s.conic_c, s.opacity);
-        s_col[tid] = make_float4(s.rgb[0], s.rgb[1], s.rgb[2], __uint_as_float(id));
+        cutoff_extent(s.conic_a, s.conic_b, s.conic_c, s.opacity, opt, ex, ey);
+        s_a[tid] = make_float4(s.mean_x, s.mean_y, s.conic_a, s.conic_b);
+        s_c[tid] = make_float4(s.conic_c, s.opacity, s.rgb[0], s.rgb[1]);
+        s_e[tid] = make_float2(s.rgb[2], __uint_as_float(id));
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          const float x0 = (float)(tx0 + (w % WX) * 8), y0 = (float)(ty0 + (w / WX) * 8);
+          const bool hit = (s.mean_x + ex >= x0) && (s.mean_x - ex <= x0 + 7.f) && (s.mean_y + ey >= y0) &&
+                           (s.mean_y - ey <= y0 + 7.f);
+          qmask |= hit ? (1u << w) : 0u;
+        }
+      }
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const uint64_t b = ballot((qmask >> w) & 1u);
+        if (lane == 0) s_bits[w][wave] = b;
       }
       __syncthreads();
+      // this wavefront's entries of the batch below its last contributor, back to front
       const int jtop = min(b_end, wlast) - b_start - 1;
-      for (int j = jtop; j >= 0; --j) {
-        const float4 mm = s_m[j];
-        const bool hit = (mm.x + mm.z >= wx0) && (mm.x - mm.z <= wx1) && (mm.y + mm.w >= wy0) && (mm.y - mm.w <= wy1);
-        if (!__builtin_amdgcn_readfirstlane((int)hit)) continue;
-        const uint32_t pos = (uint32_t)(b_start + j);
-        bool contrib = pos < last;  // false for pixels outside the image (last = 0)
-        float gmx = 0.f, gmy = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
-        if (contrib) {
-          const float4 qq = s_q[j];
-          const float dx = fx - mm.x, dy = fy - mm.y;
-          const float a = qq.x, b = qq.y, c = qq.z;
-          const float G = __expf(splat_power(dx, dy, a, b, c));
-          const float raw = qq.w * G;
-          const bool clamped = raw > opt.alpha_max;
-          const float alpha = clamped ? opt.alpha_max : raw;
-          contrib = alpha >= opt.alpha_min;
+      for (int c = NW - 1; c >= 0; --c) {
+        if (jtop < c * 64) continue;
+        const uint64_t raw = s_bits[wave][c];
+        uint64_t bits = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(raw >> 32)) << 32) |
+                        (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)raw);
+        if (jtop - c * 64 < 63) bits &= (2ull << (jtop - c * 64)) - 1ull;
+        while (bits) {
+          const int hb = 63 - (int)__builtin_clzll(bits);
+          bits &= ~(1ull << hb);
+          const int j = c * 64 + hb;
+          const float4 a = s_a[j];
+          const float4 qq = s_c[j];
+          const uint32_t pos = (uint32_t)(b_start + j);
+          bool contrib = pos < last;  // false for pixels outside the image (last = 0)
+          float gmx = 0.f, gmy = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
           if (contrib) {
-            const float4 col = s_col[j];
-            const float om = 1.f - alpha;
-            T = T / om;  // transmittance in front of this entry
-            const float w = alpha * T;
-            const float inv_om = 1.f / om;
-            const float g = dC0 * (col.x * T - R0 * inv_om) + dC1 * (col.y * T - R1 * inv_om) +
-                            dC2 * (col.z * T - R2 * inv_om);
-            R0 += col.x * w;
-            R1 += col.y * w;
-            R2 += col.z * w;
-            gr = w * dC0;
-            gg = w * dC1;
-            gbl = w * dC2;
-            if (!clamped) {
-              const float gaw = g * alpha;
-              gmx = gaw * (a * dx + b * dy);
-              gmy = gaw * (b * dx + c * dy);
-              ga = -0.5f * gaw * dx * dx;
-              gb = -gaw * dx * dy;
-              gc = -0.5f * gaw * dy * dy;
-              go = g * G;
+            const float dx = fx - a.x, dy = fy - a.y;
+            const float ca = a.z, cb = a.w, cc = qq.x;
+            const float power = splat_power(dx, dy, ca, cb, cc);
+            const float G = __expf(power);
+            const float raw_a = qq.y * G;
+            const bool clamped = raw_a > opt.alpha_max;
+            const float alpha = clamped ? opt.alpha_max : raw_a;
+            contrib = power >= cut && alpha >= opt.alpha_min;
+            if (contrib) {
+              const float blue = s_e[j].x;
+              const float om = 1.f - alpha;
+              T = T / om;  // transmittance in front of this entry
+              const float w = alpha * T;
+              const float inv_om = 1.f / om;
+              const float g = dC0 * (qq.z * T - R0 * inv_om) + dC1 * (qq.w * T - R1 * inv_om) +
+                              dC2 * (blue * T - R2 * inv_om);
+              R0 += qq.z * w;
+              R1 += qq.w * w;
+              R2 += blue * w;
+              gr = w * dC0;
+              gg = w * dC1;
+              gbl = w * dC2;
+              if (!clamped) {
+                const float gaw = g * alpha;
+                gmx = gaw * (ca * dx + cb * dy);
+                gmy = gaw * (cb * dx + cc * dy);
+                ga = -0.5f * gaw * dx * dx;
+                gb = -gaw * dx * dy;
+                gc = -0.5f * gaw * dy * dy;
+                go = g * G;
+              }
             }
           }
-        }
-        if (ballot(contrib)) {
-          gmx = wave_sum_dpp(gmx);
-          gmy = wave_sum_dpp(gmy);
-          ga = wave_sum_dpp(ga);
-          gb = wave_sum_dpp(gb);
-          gc = wave_sum_dpp(gc);
-          go = wave_sum_dpp(go);
-          gr = wave_sum_dpp(gr);
-          gg = wave_sum_dpp(gg);
-          gbl = wave_sum_dpp(gbl);
-          if (lane == 0) {
-            const int64_t id = __float_as_uint(s_col[j].w);
-            unsafeAtomicAdd(&g2d[0 * m + id], gmx);
-            unsafeAtomicAdd(&g2d[1 * m + id], gmy);
-            unsafeAtomicAdd(&g2d[2 * m + id], ga);
-            unsafeAtomicAdd(&g2d[3 * m + id], gb);
-            unsafeAtomicAdd(&g2d[4 * m + id], gc);
-            unsafeAtomicAdd(&g2d[5 * m + id], go);
-            unsafeAtomicAdd(&g2d[6 * m + id], gr);
-            unsafeAtomicAdd(&g2d[7 * m + id], gg);
-            unsafeAtomicAdd(&g2d[8 * m + id], gbl);
+          if (ballot(contrib)) {
+            gmx = wave_sum_dpp(gmx);
+            gmy = wave_sum_dpp(gmy);
+            ga = wave_sum_dpp(ga);
+            gb = wave_sum_dpp(gb);
+            gc = wave_sum_dpp(gc);
+            go = wave_sum_dpp(go);
+            gr = wave_sum_dpp(gr);
+            gg = wave_sum_dpp(gg);
+            gbl = wave_sum_dpp(gbl);
+            if (lane == 0) {
+              const int64_t id = __float_as_uint(s_e[j].y);
+              unsafeAtomicAdd(&g2d[0 * m + id], gmx);
+              unsafeAtomicAdd(&g2d[1 * m + id], gmy);
+              unsafeAtomicAdd(&g2d[2 * m + id], ga);
+              unsafeAtomicAdd(&g2d[3 * m + id], gb);
+              unsafeAtomicAdd(&g2d[4 * m + id], gc);
+              unsafeAtomicAdd(&g2d[5 * m + id], go);
+              unsafeAtomicAdd(&g2d[6 * m + id], gr);
+              unsafeAtomicAdd(&g2d[7 * m + id], gg);
+              unsafeAtomicAdd(&g2d[8 * m + id], gbl);
+            }
           }
         }
       }

@@ -5,10 +5,11 @@
 // wavefront an 8x8 quadrant) and takes the next tile from a global atomic
 // queue when done, so tiles with long instance lists do not stall the rest of
 // the grid.  The tile's instances are staged through LDS in batches of one
-// record per thread.  A wavefront skips an entry outright when its quadrant
-// lies outside the entry's alpha >= alpha_min ellipse, stops when all its
-// pixels are saturated, and the workgroup leaves the tile when every pixel's
-// transmittance has hit the cut-off.
+// record per thread; the loading thread also tests the entry's cut-off box
+// against every quadrant, and each wavefront then walks only the entries
+// that reach its quadrant (a per-chunk bit mask scanned on the scalar unit).
+// A wavefront stops when all its pixels are saturated, and the workgroup
+// leaves the tile when every pixel's transmittance has hit the cut-off.
 #include "common.h"
 
 namespace sg {
@@ -24,14 +25,17 @@ __global__ void __launch_bounds__(TW* TH) k_render_fwd(const steepgs_splat* __re
                                                       uint32_t* __restrict__ n_used, float* __restrict__ loss,
                                                       uint32_t* __restrict__ queue) {
   constexpr int NT = TW * TH;
+  constexpr int NW = NT / 64;         // wavefronts per workgroup = 64-entry chunks per batch
   constexpr int WX = TW / 8;          // each wavefront owns an 8x8 pixel quadrant of the tile
-  __shared__ float4 s_m[NT];          // mean x, mean y, cut-off half extents x, y
-  __shared__ float4 s_q[NT];          // conic a, b, c, opacity
-  __shared__ float4 s_col[NT];        // rgb
-  __shared__ float s_red[NT / 64];
+  __shared__ float4 s_a[NT];          // mean x, mean y, conic a, conic b
+  __shared__ float4 s_c[NT];          // conic c, opacity, red, green
+  __shared__ float s_bl[NT];          // blue
+  __shared__ uint64_t s_bits[NW][NW]; // [wave][chunk]: entries of the chunk that reach the wave's quadrant
+  __shared__ float s_red[NW];
   __shared__ int s_tile;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int qx = (wave % WX) * 8 + (lane & 7), qy = (wave / WX) * 8 + (lane >> 3);
+  const float cut = footprint_power_cut(opt);
   for (;;) {
     // The barrier closes the previous tile before lane 0 fetches the next one,
     // so no lane-0-only region can span the loop's back edge (the compiler
@@ -50,9 +54,6 @@ __global__ void __launch_bounds__(TW* TH) k_render_fwd(const steepgs_splat* __re
     const int tx0 = (lt % tiles_x) * TW, ty0 = (lt / tiles_x) * TH;
     const int px = tx0 + qx, py = ty0 + qy;
     const bool inside = px < W && py < H;
-    // the wavefront's pixel block, for the per-wave cut-off test
-    const float wx0 = (float)(tx0 + (wave % WX) * 8), wy0 = (float)(ty0 + (wave / WX) * 8);
-    const float wx1 = wx0 + 7.f, wy1 = wy0 + 7.f;
     const uint32_t begin = ranges[2 * tile], end = ranges[2 * tile + 1];
     const float fx = (float)px, fy = (float)py;
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
@@ -60,42 +61,62 @@ __global__ void __launch_bounds__(TW* TH) k_render_fwd(const steepgs_splat* __re
     bool done = !inside;
     for (uint32_t b0 = begin; b0 < end; b0 += NT) {
       if (__builtin_amdgcn_readfirstlane(__syncthreads_count(done)) == NT) break;
+      // stage one batch; the thread that loads an entry tests its cut-off
+      // box (alpha >= alpha_min and inside the footprint) against the
+      // quadrant of every wavefront
       const uint32_t idx = b0 + tid;
+      uint32_t qmask = 0;
       if (idx < end) {
         const steepgs_splat s = splats[vals[idx]];
         float ex, ey;
-        cutoff_extent(s.conic_a, s.conic_b, s.conic_c, s.opacity, opt.alpha_min, ex, ey);
-        s_m[tid] = make_float4(s.mean_x, s.mean_y, ex, ey);
-        s_q[tid] = make_float4(s.conic_a, s.conic_b, s.conic_c, s.opacity);
-        s_col[tid] = make_float4(s.rgb[0], s.rgb[1], s.rgb[2], 0.f);
+        cutoff_extent(s.conic_a, s.conic_b, s.conic_c, s.opacity, opt, ex, ey);
+        s_a[tid] = make_float4(s.mean_x, s.mean_y, s.conic_a, s.conic_b);
+        s_c[tid] = make_float4(s.conic_c, s.opacity, s.rgb[0], s.rgb[1]);
+        s_bl[tid] = s.rgb[2];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          const float x0 = (float)(tx0 + (w % WX) * 8), y0 = (float)(ty0 + (w / WX) * 8);
+          const bool hit = (s.mean_x + ex >= x0) && (s.mean_x - ex <= x0 + 7.f) && (s.mean_y + ey >= y0) &&
+                           (s.mean_y - ey <= y0 + 7.f);
+          qmask |= hit ? (1u << w) : 0u;
+        }
+      }
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const uint64_t b = ballot((qmask >> w) & 1u);
+        if (lane == 0) s_bits[w][wave] = b;
       }
       __syncthreads();
-      const int cnt = (int)min((uint32_t)NT, end - b0);
-      for (int j = 0; j < cnt; ++j) {
-        if (ballot(!done) == 0) break;  // the whole wavefront is finished
-        const float4 m = s_m[j];
-        // no pixel of this wavefront reaches alpha_min: skip for the whole wave
-        const bool hit = (m.x + m.z >= wx0) && (m.x - m.z <= wx1) && (m.y + m.w >= wy0) && (m.y - m.w <= wy1);
-        if (!__builtin_amdgcn_readfirstlane((int)hit)) continue;
-        if (done) continue;
-        const float4 q = s_q[j];
-        const float dx = fx - m.x, dy = fy - m.y;
-        const float G = __expf(splat_power(dx, dy, q.x, q.y, q.z));
-        const float alpha = fminf(opt.alpha_max, q.w * G);
-        if (alpha < opt.alpha_min) continue;
-        const float Tn = T * (1.f - alpha);
-        if (Tn < opt.t_min) {
-          done = true;
-          continue;
+      // this wavefront's entries of the batch, front to back
+      for (int c = 0; c < NW; ++c) {
+        const uint64_t raw = s_bits[wave][c];
+        uint64_t bits = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(raw >> 32)) << 32) |
+                        (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)raw);
+        while (bits) {
+          if (ballot(!done) == 0) break;  // the whole wavefront is finished
+          const int j = c * 64 + (int)__builtin_ctzll(bits);
+          bits &= bits - 1;
+          const float4 a = s_a[j];
+          const float4 q = s_c[j];
+          if (done) continue;
+          const float dx = fx - a.x, dy = fy - a.y;
+          const float power = splat_power(dx, dy, a.z, a.w, q.x);
+          if (power < cut) continue;  // outside the footprint
+          const float alpha = fminf(opt.alpha_max, q.y * __expf(power));
+          if (alpha < opt.alpha_min) continue;
+          const float Tn = T * (1.f - alpha);
+          if (Tn < opt.t_min) {
+            done = true;
+            continue;
+          }
+          const float w = alpha * T;
+          C0 += q.z * w;
+          C1 += q.w * w;
+          C2 += s_bl[j] * w;
+          T = Tn;
+          last = b0 - begin + (uint32_t)j + 1u;
+          ++used;
         }
-        const float4 c = s_col[j];
-        const float w = alpha * T;
-        C0 += c.x * w;
-        C1 += c.y * w;
-        C2 += c.z * w;
-        T = Tn;
-        last = b0 - begin + (uint32_t)j + 1u;
-        ++used;
       }
     }
     float err = 0.f;
@@ -121,7 +142,7 @@ __global__ void __launch_bounds__(TW* TH) k_render_fwd(const steepgs_splat* __re
       __syncthreads();
       if (tid == 0) {
         float s = 0.f;
-        for (int w = 0; w < NT / 64; ++w) s += s_red[w];
+        for (int w = 0; w < NW; ++w) s += s_red[w];
         atomicAdd(&loss[v], s / (3.f * (float)W * (float)H));
       }
     }

@@ -13,91 +13,160 @@
 //
 // All kernels read the instance count K from device memory, so the whole
 // stage can be captured in a HIP graph.
-#include "common.h"
+#include "projection.h"
 #include "scan.h"
 
 namespace sg {
 
 // ---------------------------------------------------------------------------
-// stable LSD radix sort of (u32 key, u32 value) pairs, count in device memory.
-// The input is cut into kRsChunks contiguous chunks, one per wavefront; each
-// wave ranks its elements with ballots (a wave-wide match on the digit) and
-// keeps private per-digit cursors in LDS, so no block barrier is needed inside
-// the scatter loop.
+// Stable LSD radix sort of (u32 key, u32 value) pairs; the element count is
+// read from device memory.  A fixed grid of kRsGrid workgroups cuts the input
+// into contiguous ranges; each workgroup walks its range in tiles of kRsTile
+// elements.  Per tile, every wavefront ranks its contiguous 1024 elements
+// with ballots (a wave-wide match on the digit) against wave-private digit
+// counters, the workgroup combines the counters into tile-local digit
+// offsets, scatters the tile into LDS in sorted order and writes it out so
+// that consecutive lanes write consecutive addresses of one digit's run.
 
-constexpr int kRsBlocks = 1024;
-constexpr int kRsWaves = 4;
-constexpr int kRsChunks = kRsBlocks * kRsWaves;
-constexpr int kRsMaxBits = 10;
+constexpr int kRsThreads = 256;
+constexpr int kRsWaves = kRsThreads / 64;
+constexpr int kRsItems = 16;                     // elements per lane per tile
+constexpr int kRsTile = kRsThreads * kRsItems;   // 4096 elements per tile
+constexpr int kRsWaveSpan = 64 * kRsItems;       // contiguous elements per wavefront
+constexpr int kRsGrid = 1024;
+constexpr int kRsMaxBits = 9;
 
-SG_DEV void rs_chunk(uint64_t count, int chunk_id, uint64_t& begin, uint64_t& end) {
-  uint64_t per = (count + kRsChunks - 1) / kRsChunks;
-  per = (per + 63) & ~uint64_t(63);
-  begin = (uint64_t)chunk_id * per;
+SG_DEV void rs_range(uint64_t count, uint64_t& begin, uint64_t& end) {
+  uint64_t per = (count + kRsGrid - 1) / kRsGrid;
+  per = (per + kRsTile - 1) / kRsTile * kRsTile;
+  begin = (uint64_t)blockIdx.x * per;
   end = begin + per;
   if (begin > count) begin = count;
   if (end > count) end = count;
 }
 
-__global__ void __launch_bounds__(256) k_rs_hist(const uint32_t* __restrict__ keys, const uint64_t* __restrict__ d_count,
-                                                 const uint64_t* __restrict__ d_cap, int shift, int bits,
-                                                 uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[kRsWaves][1 << kRsMaxBits];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int digits = 1 << bits;
-  for (int d = lane; d < digits; d += 64) h[wave][d] = 0;
+SG_DEV uint64_t rs_count(const uint64_t* d_count, const uint64_t* d_cap) {
   uint64_t count = *d_count;
   if (d_cap && count > *d_cap) count = 0;
-  const int chunk = blockIdx.x * kRsWaves + wave;
-  uint64_t b, e;
-  rs_chunk(count, chunk, b, e);
-  const uint32_t mask = (uint32_t)digits - 1;
-  for (uint64_t base = b; base < e; base += 64) {
-    const uint64_t idx = base + lane;
-    if (idx < e) atomicAdd(&h[wave][(keys[idx] >> shift) & mask], 1u);
-  }
-  for (int d = lane; d < digits; d += 64) hist[(size_t)d * kRsChunks + chunk] = h[wave][d];
+  return count;
 }
 
-__global__ void __launch_bounds__(256) k_rs_scatter(const uint32_t* __restrict__ keys_in,
-                                                    const uint32_t* __restrict__ vals_in,
-                                                    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
-                                                    const uint64_t* __restrict__ d_count,
-                                                    const uint64_t* __restrict__ d_cap, int shift, int bits,
-                                                    const uint32_t* __restrict__ hist_scanned) {
-  __shared__ uint32_t cur[kRsWaves][1 << kRsMaxBits];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int digits = 1 << bits;
-  const int chunk = blockIdx.x * kRsWaves + wave;
-  for (int d = lane; d < digits; d += 64) cur[wave][d] = hist_scanned[(size_t)d * kRsChunks + chunk];
-  uint64_t count = *d_count;
-  if (d_cap && count > *d_cap) count = 0;
+template <int BITS>
+__global__ void __launch_bounds__(kRsThreads) k_rs_hist(const uint32_t* __restrict__ keys,
+                                                        const uint64_t* __restrict__ d_count,
+                                                        const uint64_t* __restrict__ d_cap, int shift, int bits,
+                                                        uint32_t* __restrict__ hist) {
+  constexpr int DIG = 1 << BITS;
+  __shared__ uint32_t h[kRsWaves][DIG];
+  const int tid = threadIdx.x, wave = tid >> 6;
+  for (int d = tid; d < kRsWaves * DIG; d += kRsThreads) (&h[0][0])[d] = 0u;
+  __syncthreads();
   uint64_t b, e;
-  rs_chunk(count, chunk, b, e);
-  const uint32_t mask = (uint32_t)digits - 1;
+  rs_range(rs_count(d_count, d_cap), b, e);
+  const uint32_t mask = (1u << bits) - 1u;
+  for (uint64_t i = b + tid; i < e; i += kRsThreads) atomicAdd(&h[wave][(keys[i] >> shift) & mask], 1u);
+  __syncthreads();
+  for (int d = tid; d < DIG; d += kRsThreads) {
+    uint32_t t = 0;
+    for (int w = 0; w < kRsWaves; ++w) t += h[w][d];
+    hist[(size_t)d * kRsGrid + blockIdx.x] = t;
+  }
+}
+
+template <int BITS>
+__global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const uint32_t* __restrict__ keys_in,
+                                                           const uint32_t* __restrict__ vals_in,
+                                                           uint32_t* __restrict__ keys_out,
+                                                           uint32_t* __restrict__ vals_out,
+                                                           const uint64_t* __restrict__ d_count,
+                                                           const uint64_t* __restrict__ d_cap, int shift, int bits,
+                                                           const uint32_t* __restrict__ hist_scanned) {
+  constexpr int DIG = 1 << BITS;
+  constexpr int PER = DIG / kRsThreads > 0 ? DIG / kRsThreads : 1;  // digits per thread in the tile scan
+  __shared__ uint32_t s_key[kRsTile], s_val[kRsTile];
+  __shared__ uint32_t s_wc[kRsWaves][DIG];  // per-wave digit counts, then offsets
+  __shared__ uint32_t s_cnt[DIG], s_start[DIG], s_run[DIG];
+  __shared__ uint32_t s_scan[kRsThreads / 64 + 1];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const uint32_t mask = (1u << bits) - 1u;
   const uint64_t lt = lanemask_lt();
-  for (uint64_t base = b; base < e; base += 64) {
-    const uint64_t idx = base + lane;
-    const bool valid = idx < e;
-    const uint32_t key = valid ? keys_in[idx] : 0u;
-    const uint32_t val = valid ? vals_in[idx] : 0u;
-    const uint32_t d = (key >> shift) & mask;
-    uint64_t peers = ballot(valid);
-    for (int k = 0; k < bits; ++k) {
-      const bool bit = (d >> k) & 1u;
-      const uint64_t m = ballot(bit);
-      peers &= bit ? m : ~m;
+  for (int d = tid; d < DIG; d += kRsThreads) s_run[d] = hist_scanned[(size_t)d * kRsGrid + blockIdx.x];
+  uint64_t b, e;
+  rs_range(rs_count(d_count, d_cap), b, e);
+  for (uint64_t base = b; base < e; base += kRsTile) {
+    const int n_tile = (int)((e - base) < (uint64_t)kRsTile ? (e - base) : (uint64_t)kRsTile);
+    for (int d = lane; d < DIG; d += 64) s_wc[wave][d] = 0u;
+    uint32_t k[kRsItems], v[kRsItems], rank[kRsItems];
+#pragma unroll
+    for (int it = 0; it < kRsItems; ++it) {
+      const int idx = wave * kRsWaveSpan + it * 64 + lane;
+      const bool valid = idx < n_tile;
+      k[it] = valid ? keys_in[base + idx] : 0u;
+      v[it] = valid ? vals_in[base + idx] : 0u;
+      const uint32_t d = (k[it] >> shift) & mask;
+      uint64_t peers = ballot(valid);
+      for (int q = 0; q < bits; ++q) {
+        const bool bit = (d >> q) & 1u;
+        const uint64_t m = ballot(bit);
+        peers &= bit ? m : ~m;
+      }
+      const uint32_t r = (uint32_t)__popcll(peers & lt);
+      const uint32_t c = s_wc[wave][d];
+      rank[it] = c + r;
+      // the lowest lane of each digit group advances the wave's counter; all
+      // lanes have read it above (LDS operations of one wave complete in order)
+      if (valid && r == 0) s_wc[wave][d] = c + (uint32_t)__popcll(peers);
     }
-    const uint32_t rank = (uint32_t)__popcll(peers & lt);
-    const uint32_t pos = cur[wave][d] + rank;
-    if (valid) {
-      keys_out[pos] = key;
-      vals_out[pos] = val;
+    __syncthreads();
+    // tile totals per digit and the wave offsets within a digit
+    for (int d = tid; d < DIG; d += kRsThreads) {
+      uint32_t sum = 0;
+      for (int w = 0; w < kRsWaves; ++w) {
+        const uint32_t t = s_wc[w][d];
+        s_wc[w][d] = sum;
+        sum += t;
+      }
+      s_cnt[d] = sum;
     }
-    // the lowest lane of each digit group advances that digit's cursor; all
-    // lanes have read their cursor above (LDS operations of one wave complete
-    // in program order)
-    if (valid && rank == 0) cur[wave][d] += (uint32_t)__popcll(peers);
+    __syncthreads();
+    // tile-local start of each digit's run
+    {
+      uint32_t loc[PER], tot = 0;
+      for (int q = 0; q < PER; ++q) {
+        const int d = tid * PER + q;
+        loc[q] = d < DIG ? s_cnt[d] : 0u;
+        tot += loc[q];
+      }
+      uint32_t all;
+      uint32_t run = block_exclusive_scan<uint32_t>(tot, s_scan, all);
+      for (int q = 0; q < PER; ++q) {
+        const int d = tid * PER + q;
+        if (d < DIG) s_start[d] = run;
+        run += loc[q];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kRsItems; ++it) {
+      const int idx = wave * kRsWaveSpan + it * 64 + lane;
+      if (idx < n_tile) {
+        const uint32_t d = (k[it] >> shift) & mask;
+        const uint32_t pos = s_start[d] + s_wc[wave][d] + rank[it];
+        s_key[pos] = k[it];
+        s_val[pos] = v[it];
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < n_tile; i += kRsThreads) {
+      const uint32_t key = s_key[i];
+      const uint32_t d = (key >> shift) & mask;
+      const uint32_t g = s_run[d] + ((uint32_t)i - s_start[d]);
+      keys_out[g] = key;
+      vals_out[g] = s_val[i];
+    }
+    __syncthreads();
+    for (int d = tid; d < DIG; d += kRsThreads) s_run[d] += s_cnt[d];
+    __syncthreads();
   }
 }
 
@@ -105,6 +174,18 @@ struct LoadU32 {
   const uint32_t* p;
   SG_DEV uint32_t operator()(int64_t i) const { return p[i]; }
 };
+
+template <int BITS>
+static void radix_pass(uint32_t* kin, uint32_t* vin, uint32_t* kout, uint32_t* vout, const uint64_t* d_count,
+                       const uint64_t* d_cap, int shift, int b, uint32_t* hist, uint32_t* hist_partials,
+                       hipStream_t st, hipError_t& err) {
+  hipLaunchKernelGGL(k_rs_hist<BITS>, dim3(kRsGrid), dim3(kRsThreads), 0, st, kin, d_count, d_cap, shift, b, hist);
+  const int64_t hn = (int64_t)(1 << BITS) * kRsGrid;
+  err = exclusive_scan<LoadU32, uint32_t, uint32_t>(LoadU32{hist}, hn, hist, hist_partials, st);
+  if (err != hipSuccess) return;
+  hipLaunchKernelGGL(k_rs_scatter<BITS>, dim3(kRsGrid), dim3(kRsThreads), 0, st, kin, vin, kout, vout, d_count, d_cap,
+                     shift, b, hist);
+}
 
 // sorts (keys, vals) of `count` (device) elements on bits [0, total_bits),
 // ping-ponging between buffer pair 0 = (k0, v0) and 1 = (k1, v1); the input is
@@ -116,18 +197,18 @@ static int radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* 
   const int bits = (total_bits + npass - 1) / npass;
   int cur = start;
   int shift = 0;
+  err = hipSuccess;
   for (int p = 0; p < npass; ++p) {
     const int b = (shift + bits > total_bits) ? total_bits - shift : bits;
     uint32_t* kin = cur ? k1 : k0;
     uint32_t* vin = cur ? v1 : v0;
     uint32_t* kout = cur ? k0 : k1;
     uint32_t* vout = cur ? v0 : v1;
-    hipLaunchKernelGGL(k_rs_hist, dim3(kRsBlocks), dim3(256), 0, st, kin, d_count, d_cap, shift, b, hist);
-    const int64_t hn = (int64_t)(1 << b) * kRsChunks;
-    err = exclusive_scan<LoadU32, uint32_t, uint32_t>(LoadU32{hist}, hn, hist, hist_partials, st);
+    if (b <= 8)
+      radix_pass<8>(kin, vin, kout, vout, d_count, d_cap, shift, b, hist, hist_partials, st, err);
+    else
+      radix_pass<9>(kin, vin, kout, vout, d_count, d_cap, shift, b, hist, hist_partials, st, err);
     if (err != hipSuccess) return cur;
-    hipLaunchKernelGGL(k_rs_scatter, dim3(kRsBlocks), dim3(256), 0, st, kin, vin, kout, vout, d_count, d_cap, shift,
-                       b, hist);
     cur ^= 1;
     shift += b;
   }
@@ -167,29 +248,85 @@ __global__ void k_instance_total(const uint64_t* __restrict__ total, uint64_t ca
   *cap_out = capacity;
 }
 
+// Each wavefront takes 64 consecutive records of the depth order; their
+// instances are contiguous in the output, so the lanes walk the group's tile
+// rectangles together (rectangle tile j goes to lane j mod 64, owner found by
+// a binary search over the group's area prefix), keep the tiles that meet the
+// footprint ellipse and append them in order.  Stores are coalesced.
 __global__ void __launch_bounds__(256) k_emit(const steepgs_splat* __restrict__ splats,
                                               const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ order,
                                               const uint64_t* __restrict__ offs, int64_t m, int64_t n,
-                                              const steepgs_camera* __restrict__ cams,
+                                              const steepgs_camera* __restrict__ cams, steepgs_opts opt,
                                               const uint64_t* __restrict__ d_num, uint64_t capacity,
                                               uint32_t* __restrict__ tkeys, uint32_t* __restrict__ ivals) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= m || *d_num > capacity) return;
-  const uint32_t r = order[s];
-  const uint32_t cnt = tiles[r];
-  if (cnt == 0) return;
-  uint64_t o = offs[s];
-  const steepgs_splat& sp = splats[r];
-  const int x0 = sp.rect_lo & 0xFFFF, y0 = sp.rect_lo >> 16, x1 = sp.rect_hi & 0xFFFF, y1 = sp.rect_hi >> 16;
-  const int v = (int)(r / (uint64_t)n);
-  const uint32_t base = (uint32_t)cams[v].tile_offset;
-  const uint32_t tx = (uint32_t)cams[v].tiles_x;
-  for (int y = y0; y <= y1; ++y)
-    for (int x = x0; x <= x1; ++x) {
-      tkeys[o] = base + (uint32_t)y * tx + (uint32_t)x;
-      ivals[o] = r;
-      ++o;
+  if (*d_num > capacity) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t s0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) - lane;  // first record of the group
+  if (s0 >= m) return;
+  const int64_t s = s0 + lane;
+  const bool valid = s < m;
+  uint32_t r = 0, x0 = 0, y0 = 0, wdt = 1, area = 0, tbase = 0, tx = 0;
+  float mx = 0.f, my = 0.f, ca = 0.f, cb = 0.f, cc = 0.f;
+  uint64_t off = 0;
+  if (valid) {
+    r = order[s];
+    off = offs[s];
+    if (tiles[r]) {
+      const steepgs_splat& sp = splats[r];
+      x0 = sp.rect_lo & 0xFFFF;
+      y0 = sp.rect_lo >> 16;
+      wdt = (sp.rect_hi & 0xFFFF) - x0 + 1;
+      area = wdt * ((sp.rect_hi >> 16) - y0 + 1);
+      mx = sp.mean_x;
+      my = sp.mean_y;
+      ca = sp.conic_a;
+      cb = sp.conic_b;
+      cc = sp.conic_c;
+      const int v = (int)(r / (uint64_t)n);
+      tbase = (uint32_t)cams[v].tile_offset;
+      tx = (uint32_t)cams[v].tiles_x;
     }
+  }
+  // the group's instances are contiguous from the first record's offset; the
+  // lanes walk the group's rectangles (exclusive prefix `aoff` of their areas),
+  // test each tile against the footprint and append the hits in order
+  uint32_t aoff = area;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t t = __shfl_up(aoff, d, 64);
+    if (lane >= d) aoff += t;
+  }
+  const uint32_t atotal = __shfl(aoff, 63, 64);
+  aoff -= area;
+  const int lastl = (int)min<int64_t>(63, m - 1 - s0);
+  uint64_t cursor = __shfl(off, 0, 64);
+  for (uint32_t j0 = 0; j0 < atotal; j0 += 64) {
+    const uint32_t j = j0 + (uint32_t)lane;
+    // owner: the largest lane L with aoff[L] <= j (empty rectangles share
+    // their successor's prefix, so the owner is never empty)
+    int lo = 0, hi = lastl;
+    for (int step = 0; step < 6; ++step) {
+      const int mid = (lo + hi + 1) >> 1;
+      const uint32_t om = __shfl(aoff, mid, 64);
+      if (om <= j) lo = mid; else hi = mid - 1;
+    }
+    const uint32_t q = j - __shfl(aoff, lo, 64);
+    const uint32_t w = __shfl(wdt, lo, 64);
+    const int ttx = (int)(__shfl(x0, lo, 64) + q % w), tty = (int)(__shfl(y0, lo, 64) + q / w);
+    // the owner's record is fetched with every lane active: a cross-lane read
+    // from a lane that is switched off does not return that lane's value
+    const float omx = __shfl(mx, lo, 64), omy = __shfl(my, lo, 64);
+    const float oa = __shfl(ca, lo, 64), ob = __shfl(cb, lo, 64), oc = __shfl(cc, lo, 64);
+    const bool hit = j < atotal && tile_hit(omx, omy, oa, ob, oc, opt, ttx, tty);
+    const uint64_t hits = ballot(hit);
+    const uint32_t tile = __shfl(tbase, lo, 64) + (uint32_t)tty * __shfl(tx, lo, 64) + (uint32_t)ttx;
+    const uint32_t rec = __shfl(r, lo, 64);
+    if (hit) {
+      const uint64_t o = cursor + (uint64_t)__popcll(hits & lanemask_lt());
+      tkeys[o] = tile;
+      ivals[o] = rec;
+    }
+    cursor += (uint64_t)__popcll(hits);
+  }
 }
 
 __global__ void k_ranges(const uint32_t* __restrict__ tkeys, const uint64_t* __restrict__ d_num, uint64_t capacity,
@@ -233,8 +370,8 @@ static size_t sort_layout(void* base, int64_t m, uint64_t cap, SortWs& w) {
   w.tkA = c.take<uint32_t>(cap);
   w.tkB = c.take<uint32_t>(cap);
   w.ivB = c.take<uint32_t>(cap);
-  w.hist = c.take<uint32_t>((size_t)(1 << kRsMaxBits) * kRsChunks);
-  w.hist_partials = c.take<uint32_t>(scan_partials_count((int64_t)(1 << kRsMaxBits) * kRsChunks) + 1);
+  w.hist = c.take<uint32_t>((size_t)(1 << kRsMaxBits) * kRsGrid);
+  w.hist_partials = c.take<uint32_t>(scan_partials_count((int64_t)(1 << kRsMaxBits) * kRsGrid) + 1);
   w.counters = c.take<uint64_t>(4);
   return c.used + 256;
 }
@@ -298,7 +435,7 @@ extern "C" steepgs_status steepgs_sort(const steepgs_splat* d_splats, const uint
   uint32_t* ev = start ? w.ivB : d_vals;
   if (capacity > 0) {
     hipLaunchKernelGGL(k_emit, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, d_splats, d_tiles_touched, order,
-                       w.offs, m, n, d_cams, d_num_instances, capacity, ek, ev);
+                       w.offs, m, n, d_cams, *opts, d_num_instances, capacity, ek, ev);
     int fin = radix_sort_pairs(w.tkA, d_vals, w.tkB, w.ivB, start, d_num_instances, w.counters + 1, tile_bits, w.hist,
                                w.hist_partials, st, err);
     if (err != hipSuccess) return STEEPGS_ERR_HIP;

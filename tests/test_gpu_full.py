@@ -1,0 +1,188 @@
+"""GPU parity at full workload sizes, in the launch configuration bench.py
+times (batched step, HIP-graph replay): sampled outputs the oracle computes
+one by one, and properties that hold at any size.
+
+* ``single_view`` (100,000 Gaussians, 800x800, SH degree 3): projection and the
+  whole instance list bit-exact against the oracle; image on sampled pixels;
+  gradients and S_i on sampled Gaussians.
+* ``batched_16`` (1,000,000 Gaussians, 16 views): instance-list invariants
+  over all instances and exact lists on sampled tiles; image on sampled
+  pixels; gradients and S_i on sampled Gaussians; densification invariants.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2505_05587_amd import scenes
+from paper_2505_05587_amd.pipeline import CameraBatch
+from paper_2505_05587_amd.step import BatchedStep
+from tests.gpu_common import GROUPS, s6_to_mats
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[full] {msg}", flush=True)
+
+
+def _run_step(scene, opts):
+    dev = torch.device("cuda", 0)
+    P = torch.from_numpy(scene.params).to(dev)
+    tg = torch.from_numpy(scene.target).to(dev)
+    cams = CameraBatch(scene.cams, opts, dev)
+    step = BatchedStep(P, scene.sh_degree, cams, tg, eps=1e-3, eps_split=-1e-6)
+    step.prepare()
+    step.run()
+    step.check()
+    step.capture()
+    step.replay()
+    torch.cuda.synchronize()
+    new = step.check()
+    return step, cams, new
+
+
+def _rect(sp):
+    lo = sp[:, 10].view(np.uint32)
+    hi = sp[:, 11].view(np.uint32)
+    return np.stack([lo & 0xFFFF, lo >> 16, hi & 0xFFFF, hi >> 16], 1).astype(np.int64)
+
+
+def _sample_pixel_parity(oracle, scene, opts, image, rng, count):
+    Px = scene.cams.total_pixels()
+    pix = np.sort(rng.choice(Px, size=count, replace=False))
+    rgb, T, amb = oracle.render_pixels(scene.params, scene.sh_degree, scene.cams, opts, pix)
+    offs = scene.cams.pixel_offsets()
+    got = np.zeros((count, 3))
+    for k, p in enumerate(pix):
+        v = int(np.searchsorted(offs, p, side="right") - 1)
+        local = p - offs[v]
+        plane = int(scene.cams.width[v]) * int(scene.cams.height[v])
+        for ch in range(3):
+            got[k, ch] = image[3 * offs[v] + ch * plane + local]
+    ok = (np.abs(got - rgb) <= 1e-5 + 1e-4 * np.abs(rgb)).all(axis=1) | amb
+    assert ok.all(), f"{(~ok).sum()} of {count} sampled pixels out of tolerance"
+    return amb.mean()
+
+
+def _sample_grad_parity(oracle, scene, opts, grads, S6, gids):
+    g_ref, S_ref, amb = oracle.grads_sampled(scene.params, scene.sh_degree, scene.cams, opts, scene.target, gids)
+    keep = ~amb
+    assert keep.sum() >= 0.6 * len(gids)
+    G = grads[:, gids].T  # [ns, F]
+    scale = {name: np.linalg.norm(g_ref[:, sl], axis=1).max() for name, sl in GROUPS.items()}
+    for name, sl in GROUPS.items():
+        d = np.linalg.norm(G[:, sl] - g_ref[:, sl], axis=1)
+        r = np.linalg.norm(g_ref[:, sl], axis=1)
+        bad = keep & (d > 1e-3 * r + 1e-6 * scale[name])
+        assert not bad.any(), f"group {name}: {bad.sum()} sampled Gaussians out of tolerance"
+    Mg = s6_to_mats(S6[:, gids])
+    Mr = S_ref.reshape(-1, 3, 3)
+    d = np.linalg.norm((Mg - Mr).reshape(len(gids), -1), axis=1)
+    r = np.linalg.norm(Mr.reshape(len(gids), -1), axis=1)
+    bad = keep & (d > 1e-3 * r + 1e-6 * r.max())
+    assert not bad.any(), f"S: {bad.sum()} sampled Gaussians out of tolerance"
+
+
+def _densify_invariants(scene, step, new):
+    n = scene.n
+    lam = step.dens.lam[:n].cpu().numpy().astype(np.float64)
+    v = step.dens.vmin[:, :n].cpu().numpy().astype(np.float64)
+    split = step.dens.split[:n].cpu().numpy().astype(bool)
+    S = s6_to_mats(step.S.cpu().numpy().astype(np.float64))
+    nrm = np.linalg.norm(S.reshape(n, -1), axis=1)
+    sure = np.abs(lam + 1e-6) > 1e-6 * nrm + 1e-12
+    np.testing.assert_array_equal(split[sure], (lam < -1e-6)[sure])
+    assert new.shape[1] == n + split.sum()
+    # eigen-equation of the reported pair, where S is non-zero
+    live = nrm > 0
+    res = np.einsum("kij,jk->ki", S, v) - lam[:, None] * v.T
+    assert (np.linalg.norm(res, axis=1)[live] <= 1e-4 * nrm[live]).all()
+    np.testing.assert_allclose(np.linalg.norm(v[:, live], axis=0), 1.0, atol=1e-6)
+    # lambda_min is the smallest eigenvalue
+    ev = np.linalg.eigvalsh(S[live])
+    assert (np.abs(ev[:, 0] - lam[live]) <= 1e-4 * nrm[live] + 1e-30).all()
+    # offspring layout: exclusive scan of the split flags
+    P = scene.params.astype(np.float64)
+    Q = new.cpu().numpy().astype(np.float64)
+    off = np.concatenate([[0], np.cumsum(1 + split)[:-1]])
+    un = ~split
+    np.testing.assert_array_equal(Q[:, off[un]], P[:, un])
+    sp = np.nonzero(split)[0]
+    a, b = Q[:, off[sp]], Q[:, off[sp] + 1]
+    np.testing.assert_allclose(0.5 * (a[0:3] + b[0:3]), P[0:3, sp], atol=1e-6)
+    np.testing.assert_allclose(0.5 * (a[0:3] - b[0:3]), 1e-3 * v[:, sp], atol=1e-6)
+    o = 1 / (1 + np.exp(-P[10, sp]))
+    np.testing.assert_allclose(1 / (1 + np.exp(-a[10])), 0.5 * o, rtol=1e-5)
+
+
+def test_single_view_full(oracle):
+    scene = scenes.single_view()
+    opts = scenes.opts("3dgs")
+    print(f"\n[case] single_view n={scene.n}", flush=True)
+    step, cams, new = _run_step(scene, opts)
+    _say("gpu step done; oracle sort")
+    r = step.ras
+    K = int(r.num.item())
+    keys, vals, ranges = oracle.sort(scene.params, scene.sh_degree, scene.cams, opts)
+    assert K == len(keys)
+    np.testing.assert_array_equal(r.vals[:K].cpu().numpy().view(np.uint32), vals)
+    np.testing.assert_array_equal(r.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2), ranges)
+    pr = oracle.project(scene.params, scene.sh_degree, scene.cams, opts)
+    sp = r.splats.cpu().numpy()
+    vis = pr["visible"]
+    np.testing.assert_array_equal(_rect(sp)[vis], pr["rect"][vis])
+    np.testing.assert_array_equal(sp[vis, 9].view(np.uint32), pr["depth_bits"][vis])
+    rng = np.random.default_rng(11)
+    _say("sampled pixels")
+    _sample_pixel_parity(oracle, scene, opts, r.image.cpu().numpy().astype(np.float64), rng, 3000)
+    gids = rng.choice(np.nonzero(vis)[0], size=60, replace=False)
+    _say("sampled gradients")
+    _sample_grad_parity(oracle, scene, opts, step.grads.cpu().numpy().astype(np.float64),
+                        step.S.cpu().numpy().astype(np.float64), gids)
+    _say("densify invariants")
+    _densify_invariants(scene, step, new)
+
+
+def test_batched_16_full(oracle):
+    scene = scenes.batched_16()
+    opts = scenes.opts("3dgs")
+    print(f"\n[case] batched_16 n={scene.n} V={scene.cams.V}", flush=True)
+    step, cams, new = _run_step(scene, opts)
+    _say("gpu step done; list invariants")
+    r = step.ras
+    K = int(r.num.item())
+    vals = r.vals[:K].cpu().numpy().view(np.uint32)
+    ranges = r.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2)
+    tiles = r.tiles.cpu().numpy().view(np.uint32)
+    sp = r.splats.cpu().numpy()
+    # invariants over the whole list: ranges partition [0, K); every record
+    # appears once per covered tile; inside a tile depth is non-decreasing and
+    # ties keep record order
+    nonempty = ranges[:, 1] > ranges[:, 0]
+    order = np.argsort(ranges[nonempty, 0])
+    b, e = ranges[nonempty][order, 0], ranges[nonempty][order, 1]
+    assert b[0] == 0 and e[-1] == K and (b[1:] == e[:-1]).all()
+    np.testing.assert_array_equal(np.bincount(vals, minlength=len(tiles)), tiles)
+    depth = sp[:, 9].view(np.uint32)[vals].astype(np.uint64)
+    tile_of = np.repeat(np.nonzero(nonempty)[0][order], (e - b).astype(np.int64))
+    key = (tile_of.astype(np.uint64) << np.uint64(32)) | depth
+    dk = np.diff(key.astype(np.int64))
+    assert (dk >= 0).all()
+    assert (np.diff(vals.astype(np.int64))[dk == 0] > 0).all()
+    # exact lists of sampled tiles from the oracle
+    _say("oracle tile lists")
+    n = scene.n
+    rng = np.random.default_rng(12)
+    sample = rng.choice(cams.total_tiles, size=40, replace=False)
+    expect = oracle.tile_lists(scene.params, scene.sh_degree, scene.cams, opts, sample)
+    for t in sample:
+        np.testing.assert_array_equal(vals[ranges[t, 0]:ranges[t, 1]], expect[int(t)])
+    _say("sampled pixels")
+    _sample_pixel_parity(oracle, scene, opts, r.image.cpu().numpy().astype(np.float64), rng, 800)
+    seen = np.nonzero(tiles.reshape(scene.cams.V, n).sum(0) > 0)[0]
+    gids = rng.choice(seen, size=8, replace=False)
+    _say("sampled gradients")
+    _sample_grad_parity(oracle, scene, opts, step.grads.cpu().numpy().astype(np.float64),
+                        step.S.cpu().numpy().astype(np.float64), gids)
+    _say("densify invariants")
+    _densify_invariants(scene, step, new)

@@ -8,19 +8,24 @@ from tests.helpers import ortho_camera, pack_params, tiny_scene
 
 
 def _brute_image(pr, cams, opts, n):
-    """Per pixel: every visible Gaussian whose tile rectangle holds the
-    pixel's tile, ordered by (float32 depth, index), composited front to
-    back with the cut-offs.  Plain Python loops."""
+    """Per pixel: every visible Gaussian within radius_sigmas (Mahalanobis) of
+    the pixel, ordered by (float32 depth, index), composited front to back with
+    the cut-offs.  No tiles; plain Python loops."""
     W, H = int(cams.width[0]), int(cams.height[0])
-    tw, th = opts["tile_w"], opts["tile_h"]
+    k2 = opts["radius_sigmas"] ** 2
     img = np.zeros((3, H, W))
     Tf = np.zeros((H, W))
     used = np.zeros((H, W), np.int64)
     for y in range(H):
         for x in range(W):
-            tx, ty = x // tw, y // th
-            cand = [i for i in range(n) if pr["visible"][i] and pr["rect"][i][0] <= tx <= pr["rect"][i][2]
-                    and pr["rect"][i][1] <= ty <= pr["rect"][i][3]]
+            cand = []
+            for i in range(n):
+                if not pr["visible"][i]:
+                    continue
+                (mx, my), (a, b, c) = pr["mean"][i], pr["conic"][i]
+                dx, dy = x - mx, y - my
+                if a * dx * dx + 2 * b * dx * dy + c * dy * dy <= k2:
+                    cand.append(i)
             cand.sort(key=lambda i: (np.float32(pr["depth"][i]), i))
             T, C, k = 1.0, np.zeros(3), 0
             for i in cand:

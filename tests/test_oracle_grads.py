@@ -213,3 +213,41 @@ def test_theorem2_vmin_minimises_split_characteristic(oracle):
         d /= np.linalg.norm(d, axis=-1, keepdims=True)
         vals = 0.5 * np.einsum("kji,il,kjl->k", d, S, d)
         assert (vals >= lam[0, 0] - 1e-12).all()
+
+
+def test_upstream_image_gradient_matches_central_differences(oracle):
+    # backward of Eq. (alpha_blend) for an arbitrary loss: with dL/dC = w fixed,
+    # L = sum w * C is linear in the image, so the gradient must match central
+    # differences of the oracle's own image; S must equal the L1 result's when
+    # w is the L1 sign gradient
+    P, cams, target = tiny_scene(47, 40, 32, sh_degree=1)
+    P = quantize(P)
+    opts = scenes.opts("smooth", radius_sigmas=4.0)
+    rng = np.random.default_rng(48)
+    w = rng.normal(size=3 * cams.total_pixels())
+    out = oracle.forward_backward(P, 1, cams, opts, dl_dimage=w)
+    G = out["grads"]
+    step = 2.0 ** -13
+    base_pr = oracle.project(P, 1, cams, opts)
+    checked = 0
+    for i in range(0, 40, 6):
+        for f in range(P.shape[0]):
+            Pp, Pm = P.copy(), P.copy()
+            Pp[f, i] += step
+            Pm[f, i] -= step
+            prp, prm = oracle.project(Pp, 1, cams, opts), oracle.project(Pm, 1, cams, opts)
+            if not all(np.array_equal(np.argsort(pr["depth_bits"], kind="stable"),
+                                      np.argsort(base_pr["depth_bits"], kind="stable")) for pr in (prp, prm)):
+                continue
+            Ip = oracle.forward_backward(Pp, 1, cams, opts)["image"]
+            Im = oracle.forward_backward(Pm, 1, cams, opts)["image"]
+            fd = float(w @ (Ip - Im)) / (2 * step)
+            assert abs(fd - G[f, i]) <= 2e-4 * abs(G[f, i]) + 1e-8 * np.abs(G).max(), (i, f, fd, G[f, i])
+            checked += 1
+    assert checked >= 0.8 * 7 * P.shape[0]
+    # the L1 loss path is the special case w = sign(C - target) / (3HW)
+    l1 = oracle.forward_backward(P, 1, cams, opts, target)
+    w1 = np.sign(l1["image"] - target) / (3.0 * cams.total_pixels())
+    alt = oracle.forward_backward(P, 1, cams, opts, dl_dimage=w1)
+    np.testing.assert_allclose(alt["grads"], l1["grads"], rtol=1e-12, atol=1e-18)
+    np.testing.assert_allclose(alt["S"], l1["S"], rtol=1e-12, atol=1e-18)

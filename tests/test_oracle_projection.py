@@ -148,7 +148,10 @@ def test_sh_colour_is_basis_dot_coefficients(oracle):
 
 
 def test_cull_and_footprint(oracle):
-    # behind the near plane -> culled; footprint covers radius_sigmas * sqrt(lambda_max)
+    # behind the near plane -> culled.  The footprint is the set of tiles whose
+    # box of pixel centres meets the ellipse q(d) = d^T A d <= radius_sigmas^2;
+    # it must hold every tile with a pixel inside the ellipse (brute force over
+    # pixels) and nothing whose box stays clear of it (dense boundary sampling).
     rng = np.random.default_rng(14)
     g = list(_rand_gauss(rng, 40, spread=1.0))
     g[0][:5, 2] = 4.0   # behind the camera at z = 3
@@ -156,15 +159,24 @@ def test_cull_and_footprint(oracle):
     cams = pinhole_camera(64)
     opts = scenes.opts("3dgs")
     pr = oracle.project(P, 0, cams, opts)
+    keys, vals, ranges = oracle.sort(P, 0, cams, opts)
     assert not pr["visible"][:5].any()
+    k2 = opts["radius_sigmas"] ** 2
+    ys, xs = np.mgrid[0:64, 0:64]
     for i in np.nonzero(pr["visible"])[0]:
-        S2 = _sigma2d_from_conic(pr, i)
-        r = math.ceil(3.0 * math.sqrt(np.linalg.eigvalsh(S2).max()))
-        mx, my = pr["mean"][i]
-        x0, y0, x1, y1 = pr["rect"][i]
-        for tx in range(4):
-            for ty in range(4):
-                hit = (tx * 16 <= mx + r) and ((tx + 1) * 16 > mx - r) and (ty * 16 <= my + r) and ((ty + 1) * 16 > my - r)
-                assert hit == (x0 <= tx <= x1 and y0 <= ty <= y1)
-        assert pr["tiles"][i] == (x1 - x0 + 1) * (y1 - y0 + 1)
+        a, b, c = pr["conic"][i].astype(np.float32).astype(np.float64)
+        mx, my = pr["mean"][i].astype(np.float32).astype(np.float64)
+        listed = {int(k >> np.uint64(32)) for k, v in zip(keys, vals) if v == i}
+        assert len(listed) == pr["tiles"][i] > 0
+        q = a * (xs - mx) ** 2 + 2 * b * (xs - mx) * (ys - my) + c * (ys - my) ** 2
+        inside = {int((y // 16) * 4 + x // 16) for y, x in zip(*np.nonzero(q <= k2 * (1 - 1e-6)))}
+        assert inside <= listed
+        for t in listed:
+            tx, ty = t % 4, t // 4
+            s = np.linspace(0, 15, 1501)
+            bx = np.concatenate([tx * 16 + s, tx * 16 + s, np.full_like(s, tx * 16), np.full_like(s, tx * 16 + 15)])
+            by = np.concatenate([np.full_like(s, ty * 16), np.full_like(s, ty * 16 + 15), ty * 16 + s, ty * 16 + s])
+            qb = a * (bx - mx) ** 2 + 2 * b * (bx - mx) * (by - my) + c * (by - my) ** 2
+            inbox = tx * 16 <= mx <= tx * 16 + 15 and ty * 16 <= my <= ty * 16 + 15
+            assert inbox or qb.min() <= k2 * (1 + 1e-3)
         assert pr["depth_bits"][i] == np.float32(pr["depth"][i]).view(np.uint32)

@@ -118,42 +118,37 @@ def test_densify_scale_and_threshold(oracle):
 
 def test_instance_sort_properties(oracle):
     # view-dependent depth sort per tile (Sec. 3, Rasterization): keys are
-    # tile | depth, non-decreasing, each visible Gaussian appears once per
-    # covered tile, ranges partition the list.  Re-emitted here from the
-    # projection and re-sorted with numpy's stable sort.
+    # tile | depth, non-decreasing; each visible record appears once per
+    # footprint tile (its count, inside its rectangle); ranges partition the
+    # list; and the list is numpy's stable sort of the keys in emission order
+    # (view, Gaussian, row-major tile).
     P, cams, _ = tiny_scene(54, 300, 64, sh_degree=0)
     cams = scenes.make_cameras([(0, 0, 3.0), (1.5, 0.5, 2.5)], [(64, 48), (40, 72)])
     opts = scenes.opts("3dgs")
     keys, vals, ranges = oracle.sort(P, 0, cams, opts)
     pr = oracle.project(P, 0, cams, opts)
     n = P.shape[1]
-    assert (np.diff(keys.astype(np.uint64)) >= 0).all() if len(keys) > 1 else True
+    tile = (keys >> np.uint64(32)).astype(np.int64)
+    assert (np.diff(keys.astype(np.uint64)) >= 0).all()
     assert len(keys) == int(pr["tiles"].sum())
-    em_k, em_v = [], []
-    tile_off = 0
-    for v in range(cams.V):
-        tx = (int(cams.width[v]) + 15) // 16
-        ty = (int(cams.height[v]) + 15) // 16
-        for i in range(n):
-            r = v * n + i
-            if not pr["visible"][r]:
-                continue
-            x0, y0, x1, y1 = pr["rect"][r]
-            for yy in range(y0, y1 + 1):
-                for xx in range(x0, x1 + 1):
-                    em_k.append(((tile_off + yy * tx + xx) << 32) | int(pr["depth_bits"][r]))
-                    em_v.append(r)
-        tile_off += tx * ty
-    em_k = np.array(em_k, np.uint64)
-    em_v = np.array(em_v, np.uint32)
-    order = np.argsort(em_k, kind="stable")
-    np.testing.assert_array_equal(keys, em_k[order])
-    np.testing.assert_array_equal(vals, em_v[order])
-    assert ranges.shape[0] == tile_off
+    np.testing.assert_array_equal(np.bincount(vals, minlength=cams.V * n), pr["tiles"])
+    txs = (cams.width.astype(np.int64) + 15) // 16
+    tys = (cams.height.astype(np.int64) + 15) // 16
+    toff = np.concatenate([[0], np.cumsum(txs * tys)[:-1]])
+    v = vals // n
+    lt = tile - toff[v]
+    x, y = lt % txs[v], lt // txs[v]
+    rect = pr["rect"][vals]
+    assert ((rect[:, 0] <= x) & (x <= rect[:, 2]) & (rect[:, 1] <= y) & (y <= rect[:, 3])).all()
+    np.testing.assert_array_equal(keys & np.uint64(0xFFFFFFFF), pr["depth_bits"][vals])
+    em = np.lexsort((tile, vals))  # emission order
+    order = np.argsort(keys[em], kind="stable")
+    np.testing.assert_array_equal(keys[em][order], keys)
+    np.testing.assert_array_equal(vals[em][order], vals)
     covered = np.zeros(len(keys), np.int64)
-    for t in range(tile_off):
+    for t in range(int((txs * tys).sum())):
         b, e = ranges[t]
-        assert (keys[b:e] >> np.uint64(32) == t).all()
+        assert (tile[b:e] == t).all()
         covered[b:e] += 1
     assert (covered == 1).all()
 
