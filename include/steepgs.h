@@ -189,10 +189,27 @@ steepgs_status steepgs_render_bwd_split(const float* d_params, int64_t n, int32_
                                         const float* d_target, float* d_grads, float* d_S, float* d_grad2d,
                                         void* d_ws, size_t ws_bytes, void* stream);
 
+/* Optional selection rules of the split step (the paper's "Variants"):
+ *  - compactest splitting: a Gaussian is a candidate only when also
+ *    |g_scale * G_i| <= eps_grad, G = d_G [3][n] the accumulated gradient of
+ *    the position (Algorithm 1's G; g_scale = 1 / T_split averages it); the
+ *    norm is compared squared in fp64.  d_G = NULL or eps_grad <= 0: off.
+ *  - increment budget: when more than `budget` Gaussians are candidates,
+ *    only the `budget` ones with the smallest lambda_min split (ties: lower
+ *    index first), compared on the float32 lambda_min the call reports.
+ *    budget <= 0: no limit. */
+typedef struct {
+  const float* d_G;
+  float g_scale;
+  float eps_grad;
+  int64_t budget;
+} steepgs_split_select;
+
 /* Stage 5 -- Steepest Density Control (Theorem 2; Algorithm 1; App. A.3).
  * S' = s_scale * S (Algorithm 1 averages over the interval); smallest
  * eigenpair by the trigonometric root formula in fp64; split iff
- * lambda_min < eps_split.  Output layout: exclusive scan of m_i in {1, 2}:
+ * lambda_min < eps_split, and the rules of `select` (host pointer, nullable:
+ * none).  Output layout: exclusive scan of m_i in {1, 2}:
  * d_out [F][out_capacity] row stride out_capacity; an unsplit Gaussian is
  * copied to out[off_i]; a split one writes (p + eps v_min, o/2) to off_i and
  * (p - eps v_min, o/2) to off_i + 1 (opacity halved in [0,1], logit re-derived;
@@ -201,7 +218,8 @@ steepgs_status steepgs_render_bwd_split(const float* d_params, int64_t n, int32_
  * If n + #splits > out_capacity: *d_status = STEEPGS_ERR_CAPACITY, *d_n_out holds
  * the needed size and d_out is not written. */
 steepgs_status steepgs_densify(const float* d_params, int64_t n, int32_t sh_degree, const float* d_S, float s_scale,
-                               float eps, float eps_split, float* d_out, int64_t out_capacity, int64_t* d_n_out,
+                               float eps, float eps_split, const steepgs_split_select* select, float* d_out,
+                               int64_t out_capacity, int64_t* d_n_out,
                                float* d_lambda_min, float* d_vmin, uint8_t* d_split, int32_t* d_status, void* d_ws,
                                size_t ws_bytes, void* stream);
 

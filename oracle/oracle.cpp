@@ -1057,20 +1057,47 @@ void orc_eigh(const double* S, int64_t m, double* lam, double* vec) {
 // accumulated matrix over the densification interval).  out_params is
 // [F][out_cap] doubles; returns n_out (or -1 if out_cap is too small, with
 // *needed set).  lam_min [n], vmin [3][n], split [n].
+// Steepest Density Control (Theorem 2, Algorithm 1) with the two variants of
+// the paper's "Variants" section:
+//  - compactest splitting: a Gaussian is a candidate only if, besides
+//    lambda_min < eps_split, its averaged position gradient G (Algorithm 1's
+//    accumulator, times g_scale) has norm <= eps_grad (G == nullptr or
+//    eps_grad <= 0: no gradient condition);
+//  - increment budget: when more than `budget` Gaussians are candidates
+//    (budget > 0), only the `budget` candidates with the smallest lambda_min
+//    split (ties: lower index first), since the loss decrease of a split is
+//    proportional to lambda_min / 2 (Theorem 2).
 int64_t orc_densify(const float* params, int64_t n, int deg, const double* S, double s_scale, double eps,
-                    double eps_split, double* out_params, int64_t out_cap, double* lam_min, double* vmin,
-                    uint8_t* split, int64_t* needed) {
+                    double eps_split, const float* G, double g_scale, double eps_grad, int64_t budget,
+                    double* out_params, int64_t out_cap, double* lam_min, double* vmin, uint8_t* split,
+                    int64_t* needed) {
   int F = num_params(deg);
-  std::vector<int64_t> off(n + 1, 0);
+  std::vector<int64_t> cand;
   for (int64_t i = 0; i < n; ++i) {
     double M[9], lam[3], vec[9];
     for (int k = 0; k < 9; ++k) M[k] = s_scale * S[(int64_t)k * n + i];
     jacobi_eigh(M, lam, vec);
     lam_min[i] = lam[0];
     for (int r = 0; r < 3; ++r) vmin[(int64_t)r * n + i] = vec[3 * r + 0];
-    split[i] = lam[0] < eps_split ? 1 : 0;
-    off[i + 1] = off[i] + 1 + split[i];
+    bool c = lam[0] < eps_split;
+    if (c && G && eps_grad > 0.0) {
+      double g2 = 0.0;
+      for (int k = 0; k < 3; ++k) {
+        double g = g_scale * (double)G[(int64_t)k * n + i];
+        g2 = g2 + g * g;
+      }
+      c = g2 <= eps_grad * eps_grad;
+    }
+    split[i] = 0;
+    if (c) cand.push_back(i);
   }
+  if (budget > 0 && (int64_t)cand.size() > budget) {
+    std::stable_sort(cand.begin(), cand.end(), [&](int64_t a, int64_t b) { return lam_min[a] < lam_min[b]; });
+    cand.resize(budget);
+  }
+  for (int64_t i : cand) split[i] = 1;
+  std::vector<int64_t> off(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) off[i + 1] = off[i] + 1 + split[i];
   *needed = off[n];
   if (off[n] > out_cap) return -1;
   for (int64_t i = 0; i < n; ++i) {

@@ -35,6 +35,10 @@ class Opts(C.Structure):
                 ("bg", C.c_float * 3)]
 
 
+class SplitSelect(C.Structure):
+    _fields_ = [("d_G", C.c_void_p), ("g_scale", C.c_float), ("eps_grad", C.c_float), ("budget", C.c_int64)]
+
+
 assert C.sizeof(Camera) == 96
 SPLAT_FLOATS = 12  # 48-byte record
 
@@ -68,7 +72,8 @@ def lib():
         L.steepgs_set_kernel_timer.restype = C.c_int
         L.steepgs_render_bwd_split.argtypes = [vp, i64, i32, vp, i32, C.POINTER(Opts), vp, vp, vp, vp, i32, i64,
                                                vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
-        L.steepgs_densify.argtypes = [vp, i64, i32, vp, f32, f32, f32, vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.steepgs_densify.argtypes = [vp, i64, i32, vp, f32, f32, f32, C.POINTER(SplitSelect), vp, i64, vp, vp, vp,
+                                      vp, vp, vp, sz, vp]
         for fn in ("steepgs_layout_cameras", "steepgs_project", "steepgs_sort", "steepgs_render_fwd",
                    "steepgs_render_bwd_split", "steepgs_densify"):
             getattr(L, fn).restype = C.c_int
@@ -171,11 +176,17 @@ def steepgs_render_bwd_split(params, n, sh_degree, d_cams, V, opts, splats, tile
 
 
 def steepgs_densify(params, n, sh_degree, S, s_scale, eps, eps_split, out, out_capacity, n_out, lambda_min, vmin,
-                    split, status, ws, stream=None):
+                    split, status, ws, stream=None, G=None, g_scale=1.0, eps_grad=0.0, budget=0):
+    """``G`` [3, n] / ``g_scale`` / ``eps_grad``: the compactest gate;
+    ``budget``: the increment budget (both off by default)."""
+    sel = None
+    if G is not None or budget > 0:
+        sel = SplitSelect(_p(G), float(g_scale), float(eps_grad), int(budget))
     _check("steepgs_densify",
            lib().steepgs_densify(_p(params), n, sh_degree, _p(S), float(s_scale), float(eps), float(eps_split),
-                                 _p(out), out_capacity, _p(n_out), _p(lambda_min), _p(vmin), _p(split), _p(status),
-                                 _p(ws), ws.numel() * ws.element_size(), _stream(stream)))
+                                 None if sel is None else C.byref(sel), _p(out), out_capacity, _p(n_out),
+                                 _p(lambda_min), _p(vmin), _p(split), _p(status), _p(ws),
+                                 ws.numel() * ws.element_size(), _stream(stream)))
 
 
 def version() -> str:

@@ -143,6 +143,14 @@ SG_DEV float wave_sum_dpp(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
 }
 
+// wave-uniform (scalar) copy of a 64-bit value that every lane holds alike;
+// both halves are zero-extended (the builtin returns a signed int)
+SG_DEV uint64_t uniform_u64(uint64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | (uint64_t)lo;
+}
+
 // largest value over the wave
 SG_DEV uint32_t wave_max_u32(uint32_t v) {
 #pragma unroll

@@ -2,11 +2,15 @@
 // closed-form 3x3 eigensolve of App. A.3.
 //
 // Kernel 1, one thread per Gaussian: S' = s_scale * S, smallest eigenpair by
-// the trigonometric root formula (fp64), split flag lambda_min < eps_split.
+// the trigonometric root formula (fp64), split flag lambda_min < eps_split
+// (and the optional gradient gate); an optional budget then keeps only the
+// candidates with the smallest lambda_min (radix select).
 // An exclusive scan of the flags places the output: Gaussian i lands at
 // i + (#splits before i), a split one occupies two slots.  Kernel 2 scatters
 // the parent, or the two offspring p +/- eps v_min with opacity o/2 (the
 // logit re-derived) and every other attribute copied.
+#include <algorithm>
+
 #include "common.h"
 #include "scan.h"
 
@@ -94,18 +98,122 @@ SG_DEV void eig3_min(const double s[6], double& lam_min, double v[3]) {
   }
 }
 
+// order-preserving map of a float to an unsigned key
+SG_DEV uint32_t float_key(float f) {
+  const uint32_t b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
 __global__ void __launch_bounds__(256) k_densify_eig(const float* __restrict__ S, int64_t n, float s_scale,
-                                                     float eps_split, float* __restrict__ lam_out,
-                                                     float* __restrict__ v_out, uint32_t* __restrict__ flag) {
+                                                     float eps_split, const float* __restrict__ G, float g_scale,
+                                                     float eps_grad, float* __restrict__ lam_out,
+                                                     float* __restrict__ v_out, uint32_t* __restrict__ flag,
+                                                     uint32_t* __restrict__ key) {
+#pragma clang fp contract(off)
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double s[6];
   for (int k = 0; k < 6; ++k) s[k] = (double)s_scale * (double)S[k * n + i];
   double lam, v[3];
   eig3_min(s, lam, v);
-  lam_out[i] = (float)lam;
+  const float lam32 = (float)lam;
+  lam_out[i] = lam32;
   for (int k = 0; k < 3; ++k) v_out[k * n + i] = (float)v[k];
-  flag[i] = (lam < (double)eps_split) ? 1u : 0u;
+  bool cand = lam < (double)eps_split;
+  if (cand && G && eps_grad > 0.f) {  // compactest gate on the averaged position gradient
+    double g2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const double g = (double)g_scale * (double)G[k * n + i];
+      g2 = g2 + g * g;
+    }
+    cand = g2 <= (double)eps_grad * (double)eps_grad;
+  }
+  flag[i] = cand ? 1u : 0u;
+  if (key) key[i] = float_key(lam32);
+}
+
+// ---------------------------------------------------------------------------
+// increment budget: the `budget` candidates with the smallest float32
+// lambda_min (ties: lower index).  A four-pass radix select (8 bits per pass,
+// most significant first) finds the key of the budget-th smallest candidate;
+// state lives in device memory so the stage stays graph-capturable.
+
+struct SelectState {
+  uint32_t prefix;   // key bits fixed so far
+  uint32_t remain;   // how many still to take among keys matching the prefix
+  uint32_t all;      // 1: the budget does not bind, every candidate splits
+  uint32_t pad;
+};
+
+__global__ void k_select_init(SelectState* st, uint32_t* __restrict__ hist, int64_t budget) {
+  const int t = threadIdx.x;
+  for (int k = t; k < 4 * 256; k += blockDim.x) hist[k] = 0u;
+  if (t == 0) {
+    st->prefix = 0u;
+    st->remain = (uint32_t)budget;
+    st->all = 0u;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_select_hist(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ key,
+                                                     int64_t n, int pass, const SelectState* __restrict__ st,
+                                                     uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0u;
+  __syncthreads();
+  const int shift = 24 - 8 * pass;
+  const uint32_t hmask = pass == 0 ? 0u : (0xFFFFFFFFu << (32 - 8 * pass));
+  const uint32_t prefix = st->prefix;
+  const bool live = st->all == 0u;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; live && i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (!flag[i]) continue;
+    const uint32_t k = key[i];
+    if ((k & hmask) == (prefix & hmask)) atomicAdd(&h[(k >> shift) & 0xFFu], 1u);
+  }
+  __syncthreads();
+  const uint32_t c = h[threadIdx.x];
+  if (c) atomicAdd(&hist[pass * 256 + threadIdx.x], c);
+}
+
+__global__ void k_select_pick(SelectState* st, const uint32_t* __restrict__ hist, int pass) {
+  if (threadIdx.x != 0 || st->all) return;
+  const uint32_t* h = hist + pass * 256;
+  if (pass == 0) {
+    uint64_t total = 0;
+    for (int d = 0; d < 256; ++d) total += h[d];
+    if (total <= st->remain) {
+      st->all = 1u;
+      return;
+    }
+  }
+  uint32_t below = 0;
+  int d = 0;
+  for (; d < 255; ++d) {
+    if (below + h[d] >= st->remain) break;
+    below += h[d];
+  }
+  st->prefix |= (uint32_t)d << (24 - 8 * pass);
+  st->remain -= below;
+}
+
+// candidates whose key equals the selected key, in index order (for the tie rule)
+struct LoadTies {
+  const uint32_t* flag;
+  const uint32_t* key;
+  const SelectState* st;
+  SG_DEV uint32_t operator()(int64_t i) const {
+    return (st->all == 0u && flag[i] && key[i] == st->prefix) ? 1u : 0u;
+  }
+};
+
+__global__ void __launch_bounds__(256) k_select_apply(uint32_t* __restrict__ flag, const uint32_t* __restrict__ key,
+                                                      const uint32_t* __restrict__ tie_rank, int64_t n,
+                                                      const SelectState* __restrict__ st) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || st->all || !flag[i]) return;
+  const uint32_t k = key[i];
+  const bool take = k < st->prefix || (k == st->prefix && tie_rank[i] < st->remain);
+  if (!take) flag[i] = 0u;
 }
 
 struct LoadFlags {
@@ -156,6 +264,9 @@ struct DensWs {
   uint32_t* flag;
   uint32_t* before;
   uint32_t* partials;
+  uint32_t* key;
+  uint32_t* hist;
+  SelectState* state;
 };
 
 static size_t densify_layout(void* base, int64_t n, DensWs& w) {
@@ -165,6 +276,9 @@ static size_t densify_layout(void* base, int64_t n, DensWs& w) {
   w.flag = c.take<uint32_t>(n);
   w.before = c.take<uint32_t>(n);
   w.partials = c.take<uint32_t>(scan_partials_count(n) + 1);
+  w.key = c.take<uint32_t>(n);
+  w.hist = c.take<uint32_t>(4 * 256);
+  w.state = c.take<SelectState>(1);
   return c.used + 256;
 }
 
@@ -193,7 +307,8 @@ __global__ void k_densify_empty(int64_t* n_out, int32_t* status) {
 using namespace sg;
 
 extern "C" steepgs_status steepgs_densify(const float* d_params, int64_t n, int32_t sh_degree, const float* d_S,
-                                          float s_scale, float eps, float eps_split, float* d_out,
+                                          float s_scale, float eps, float eps_split,
+                                          const steepgs_split_select* select, float* d_out,
                                           int64_t out_capacity, int64_t* d_n_out, float* d_lambda_min, float* d_vmin,
                                           uint8_t* d_split, int32_t* d_status, void* d_ws, size_t ws_bytes,
                                           void* stream) {
@@ -213,9 +328,27 @@ extern "C" steepgs_status steepgs_densify(const float* d_params, int64_t n, int3
   densify_layout(d_ws, n, w);
   const int F = STEEPGS_NUM_PARAMS(sh_degree);
   const unsigned nb = (unsigned)ceil_div(n, 256);
+  const float* G = select ? select->d_G : nullptr;
+  const float g_scale = select ? select->g_scale : 1.f;
+  const float eps_grad = select ? select->eps_grad : 0.f;
+  const int64_t budget = select ? select->budget : 0;
+  if (budget >= (int64_t)1 << 32) return STEEPGS_ERR_INVALID_ARG;
   timer_begin(STEEPGS_TIMER_DENSIFY, st);
-  hipLaunchKernelGGL(k_densify_eig, dim3(nb), dim3(256), 0, st, d_S, n, s_scale, eps_split, w.lam, w.vmin, w.flag);
+  hipLaunchKernelGGL(k_densify_eig, dim3(nb), dim3(256), 0, st, d_S, n, s_scale, eps_split, G, g_scale, eps_grad,
+                     w.lam, w.vmin, w.flag, budget > 0 ? w.key : nullptr);
   timer_end(STEEPGS_TIMER_DENSIFY, st);
+  if (budget > 0) {
+    const unsigned hb = (unsigned)std::min<int64_t>(ceil_div(n, 256), 2048);
+    hipLaunchKernelGGL(k_select_init, dim3(1), dim3(256), 0, st, w.state, w.hist, budget);
+    for (int pass = 0; pass < 4; ++pass) {
+      hipLaunchKernelGGL(k_select_hist, dim3(hb), dim3(256), 0, st, w.flag, w.key, n, pass, w.state, w.hist);
+      hipLaunchKernelGGL(k_select_pick, dim3(1), dim3(64), 0, st, w.state, w.hist, pass);
+    }
+    if (exclusive_scan<LoadTies, uint32_t, uint32_t>(LoadTies{w.flag, w.key, w.state}, n, w.before, w.partials, st) !=
+        hipSuccess)
+      return STEEPGS_ERR_HIP;
+    hipLaunchKernelGGL(k_select_apply, dim3(nb), dim3(256), 0, st, w.flag, w.key, w.before, n, w.state);
+  }
   if (exclusive_scan<LoadFlags, uint32_t, uint32_t>(LoadFlags{w.flag}, n, w.before, w.partials, st) != hipSuccess)
     return STEEPGS_ERR_HIP;
   hipLaunchKernelGGL(k_densify_total, dim3(1), dim3(1), 0, st, w.partials + scan_partials_count(n), n, out_capacity,

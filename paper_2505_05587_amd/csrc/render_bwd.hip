@@ -133,9 +133,7 @@ __global__ void __launch_bounds__(TW* TH) k_render_bwd(const steepgs_splat* __re
       const int jtop = min(b_end, wlast) - b_start - 1;
       for (int c = NW - 1; c >= 0; --c) {
         if (jtop < c * 64) continue;
-        const uint64_t raw = s_bits[wave][c];
-        uint64_t bits = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(raw >> 32)) << 32) |
-                        (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)raw);
+        uint64_t bits = uniform_u64(s_bits[wave][c]);
         if (jtop - c * 64 < 63) bits &= (2ull << (jtop - c * 64)) - 1ull;
         while (bits) {
           const int hb = 63 - (int)__builtin_clzll(bits);

@@ -89,9 +89,7 @@ __global__ void __launch_bounds__(TW* TH) k_render_fwd(const steepgs_splat* __re
       __syncthreads();
       // this wavefront's entries of the batch, front to back
       for (int c = 0; c < NW; ++c) {
-        const uint64_t raw = s_bits[wave][c];
-        uint64_t bits = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(raw >> 32)) << 32) |
-                        (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)raw);
+        uint64_t bits = uniform_u64(s_bits[wave][c]);
         while (bits) {
           if (ballot(!done) == 0) break;  // the whole wavefront is finished
           const int j = c * 64 + (int)__builtin_ctzll(bits);

@@ -65,8 +65,11 @@ def test_bad_arguments_rejected_on_host():
                                   None, None, 0, None) == L.ERR_WORKSPACE
     assert lib.steepgs_set_kernel_timer(9, None, None, 0) == L.ERR_INVALID_ARG
     assert lib.steepgs_set_kernel_timer(0, None, None, 0) == L.OK
-    assert lib.steepgs_densify(None, 10, 0, None, 1.0, 0.01, 0.0, None, 0, None, None, None, None, None, None, 0,
-                               None) == L.ERR_INVALID_ARG
+    assert lib.steepgs_densify(None, 10, 0, None, 1.0, 0.01, 0.0, None, None, 0, None, None, None, None, None, None,
+                               0, None) == L.ERR_INVALID_ARG
+    sel = L.SplitSelect(None, 1.0, 0.0, 1 << 40)  # budget beyond 32 bits
+    assert lib.steepgs_densify(fake, 10, 0, fake, 1.0, 0.01, 0.0, C.byref(sel), fake, 20, fake, None, None, None,
+                               fake, fake, 1 << 20, None) == L.ERR_INVALID_ARG
     assert lib.steepgs_status_string(2) == b"output capacity exceeded"
 
 

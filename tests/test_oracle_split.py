@@ -116,6 +116,62 @@ def test_densify_scale_and_threshold(oracle):
     assert small["n_out"] == -1 and small["needed"] == a["n_out"]
 
 
+def test_densify_increment_budget(oracle):
+    # Variants, increment budget: with more candidates than the budget K, the
+    # K smallest lambda_min split (Theorem 2: the loss decrease of a split is
+    # lambda_min / 2); equal lambda_min: lower index first.  Eigenvalues from
+    # LAPACK, selection from numpy's stable argsort.
+    rng = np.random.default_rng(54)
+    n = 400
+    P = scenes.uniform_gaussians(rng, n)
+    S = _random_S(rng, n)
+    S[300:310] = S[200]  # ties with one another
+    S9 = S.reshape(n, 9).T.copy()
+    lam = np.linalg.eigvalsh(S)[:, 0]
+    cand = np.nonzero(lam < -1e-6)[0]
+    assert len(cand) > 150
+    for K in (1, 17, 150, len(cand), len(cand) + 5):
+        out = oracle.densify(P, 0, S9, 1.0, 0.01, -1e-6, budget=K)
+        keep = cand[np.argsort(lam[cand], kind="stable")][:K]
+        want = np.zeros(n, bool)
+        want[keep] = True
+        if K < len(cand):
+            kth = np.sort(lam[cand])[K - 1]
+            near = np.abs(lam - kth) < 1e-12 * np.abs(S).max()
+            np.testing.assert_array_equal(out["split"][~near], want[~near])
+            assert out["split"].sum() == K
+        else:
+            np.testing.assert_array_equal(out["split"], want)
+        assert out["n_out"] == n + out["split"].sum()
+    # exact ties: the budget boundary inside the tied group keeps the lowest indices
+    tied = [200] + list(range(300, 310))
+    K = int(np.sum(lam[cand] < lam[200])) + 4
+    out = oracle.densify(P, 0, S9, 1.0, 0.01, -1e-6, budget=K)
+    assert out["split"][[200, 300, 301, 302]].all() and not out["split"][303:310].any()
+    assert out["split"][tied].sum() == 4
+
+
+def test_densify_compactest_gate(oracle):
+    # Variants, compactest splitting: split only where |G| <= eps_grad and
+    # lambda_min < eps_split; G is the interval-averaged position gradient
+    rng = np.random.default_rng(55)
+    n = 300
+    P = scenes.uniform_gaussians(rng, n)
+    S9 = _random_S(rng, n).reshape(n, 9).T.copy()
+    G = (rng.normal(size=(3, n)) * np.exp(rng.normal(0, 1, size=n))).astype(np.float32)
+    lam = np.linalg.eigvalsh(S9.T.reshape(n, 3, 3))[:, 0]
+    gn = np.linalg.norm(G.astype(np.float64) * 0.25, axis=0)
+    for eps_grad in (0.1, 0.5, 2.0):
+        out = oracle.densify(P, 0, S9, 1.0, 0.01, -1e-6, G=G, g_scale=0.25, eps_grad=eps_grad)
+        np.testing.assert_array_equal(out["split"], (lam < -1e-6) & (gn <= eps_grad))
+    off = oracle.densify(P, 0, S9, 1.0, 0.01, -1e-6, G=G, g_scale=0.25, eps_grad=0.0)
+    np.testing.assert_array_equal(off["split"], lam < -1e-6)
+    both = oracle.densify(P, 0, S9, 1.0, 0.01, -1e-6, G=G, g_scale=0.25, eps_grad=0.5, budget=10)
+    gated = np.nonzero((lam < -1e-6) & (gn <= 0.5))[0]
+    keep = gated[np.argsort(lam[gated], kind="stable")][:10]
+    assert set(np.nonzero(both["split"])[0]) == set(keep)
+
+
 def test_instance_sort_properties(oracle):
     # view-dependent depth sort per tile (Sec. 3, Rasterization): keys are
     # tile | depth, non-decreasing; each visible record appears once per
