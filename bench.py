@@ -94,6 +94,42 @@ def kernel_times(step, steps, torch, L):
     return {L.TIMER_NAMES[w]: [s.elapsed_time(e) for s, e in zip(st, en)] for w, (st, en) in events.items()}
 
 
+# HBM bytes per launch of each kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# passes over this workload (profiles/hbm_traffic.txt: one line per stage with
+# the counter readings in KiB per dispatch, the scale factors from a plain
+# 1 GiB device copy and the SHA-256 of the kernel's sources); reported only
+# while those sources are unchanged.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+KERNEL_SOURCE = {"project": "project.hip", "sort": "sort.hip", "render_fwd": "render_fwd.hip",
+                 "render_bwd": "render_bwd.hip", "proj_bwd": "render_bwd.hip", "densify": "densify.hip"}
+
+
+def _source_digest(stage):
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2505_05587_amd", "csrc")
+    for name in (KERNEL_SOURCE[stage], "common.h", "projection.h"):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(stage):
+    rec = None
+    try:
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                tok = line.split()
+                if len(tok) >= 2 and tok[0] == "stage" and tok[1] == stage:
+                    rec = dict(zip(tok[2::2], tok[3::2]))
+    except OSError:
+        return None
+    if not rec or rec.get("sha256") != _source_digest(stage):
+        return None
+    return int(float(rec["fetch_kib"]) * float(rec["fetch_scale"]) * 1024 +
+               float(rec["write_kib"]) * float(rec["write_scale"]) * 1024)
+
+
 def cpu_baseline(scene, opts):
     """The oracle as it stands on one view of the workload (full Gaussian set),
     scaled to the 16-view step, plus its densification over all Gaussians."""
@@ -228,6 +264,7 @@ def main():
         achieved = work / t_s / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_NONPACKED_TFLOPS, 1),
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4), "traffic": None}
+    roof["traffic"] = measured_traffic(dom)
     roof["kernel"] = dom
     roof["ms"] = round(stages[dom], 4)
 

@@ -178,8 +178,9 @@ steepgs_status steepgs_render_fwd(const steepgs_splat* d_splats, int64_t n, cons
  *                   with Hessian_p alpha = alpha P^T (A d d^T A - A) P, P the
  *                   Jacobian of the projected mean w.r.t. p, held fixed with
  *                   Pi(Sigma) and colour (App. C.4).
- * d_grad2d (nullable) [9][V*n] receives the per-pair gradients w.r.t.
- * (mean_x, mean_y, conic a, b, c, opacity, r, g, b) (overwritten). */
+ * d_grad2d (nullable) [V*n][12] receives the per-pair gradients w.r.t.
+ * (mean_x, mean_y, conic a, b, c, opacity, r, g, b) in entries 0-8 of each
+ * 48-byte slot (overwritten; entries 9-11 are zero). */
 steepgs_status steepgs_render_bwd_split(const float* d_params, int64_t n, int32_t sh_degree,
                                         const steepgs_camera* d_cams, int32_t V, const steepgs_opts* opts,
                                         const steepgs_splat* d_splats, const uint32_t* d_tiles_touched,
@@ -222,6 +223,37 @@ steepgs_status steepgs_densify(const float* d_params, int64_t n, int32_t sh_degr
                                int64_t out_capacity, int64_t* d_n_out,
                                float* d_lambda_min, float* d_vmin, uint8_t* d_split, int32_t* d_status, void* d_ws,
                                size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Training-loop support (Algorithm 1 around the hot path). */
+
+/* Adam hyper-parameters; lr per parameter group: position, log-scales,
+ * quaternion, opacity logit, SH degree 0, SH degrees >= 1. */
+typedef struct {
+  float lr[6];
+  float beta1, beta2, eps;
+} steepgs_adam_opts;
+
+/* One Adam step, the optimizer of the 3DGS training pipeline that Sec. 5.1
+ * keeps: t = ++*d_step (device int64), m = b1 m + (1 - b1) g,
+ * v = b2 v + (1 - b2) g^2, p -= (lr / (1 - b1^t)) m / (sqrt(v) / sqrt(1 - b2^t)
+ * + eps) elementwise over d_params, d_grads, d_m, d_v [F][n] (fp32; the bias
+ * corrections in fp64).  d_G [3][n] (nullable) accumulates the position
+ * gradient (Algorithm 1's G += grad).  Errors: INVALID_ARG for a null
+ * pointer, a degree outside 0..3, betas outside [0, 1) or eps <= 0. */
+steepgs_status steepgs_adam_step(float* d_params, const float* d_grads, float* d_m, float* d_v, int64_t n,
+                                 int32_t sh_degree, const steepgs_adam_opts* opts, int64_t* d_step, float* d_G,
+                                 void* stream);
+
+/* Per-Gaussian state (e.g. Adam moments) onto the layout of a densification
+ * (Algorithm 1's replacement of a split Gaussian by two offspring): with
+ * d_split [n] the flags steepgs_densify reported, a kept Gaussian i's rows
+ * d_src[r][i] (rows x n) go to d_dst[r][i + #splits before i] (row stride
+ * dst_capacity), and both offspring slots of a split one are zero (fresh
+ * state).  Slots at or beyond dst_capacity are not written.  Workspace: at
+ * least steepgs_workspace_size(4, n, 1, 0, 0) bytes. */
+steepgs_status steepgs_split_remap(const float* d_src, int32_t rows, int64_t n, const uint8_t* d_split, float* d_dst,
+                                   int64_t dst_capacity, void* d_ws, size_t ws_bytes, void* stream);
 
 /* Profiling hook.  When set for kernel `which` (STEEPGS_TIMER_*), every
  * later launch of that kernel records start_events[i] immediately before and

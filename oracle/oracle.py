@@ -278,3 +278,45 @@ def tile_lists(params, sh_degree, cams, opts, tiles):
         out[int(tile)] = lists[pos: pos + counts[k]]
         pos += int(counts[k])
     return out
+
+
+# ----------------------------------------------------------------------------
+# training-loop references (plain numpy, fp64)
+
+# parameter rows of each learning-rate group: position, log-scales, quaternion,
+# opacity logit, SH degree 0, SH degrees >= 1
+def _lr_rows(F, lr6):
+    lr = np.empty(F, np.float64)
+    lr[0:3], lr[3:6], lr[6:10], lr[10] = lr6[0], lr6[1], lr6[2], lr6[3]
+    lr[11:14] = lr6[4]
+    lr[14:] = lr6[5]
+    return lr
+
+
+def adam_step(params, grads, m, v, t, lr6, beta1=0.9, beta2=0.999, eps=1e-15):
+    """One Adam step (Kingma and Ba, Algorithm 1) with bias-corrected moments:
+    m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+    p -= lr m / (1 - b1^t) / (sqrt(v / (1 - b2^t)) + eps), per parameter row
+    group.  Returns (params, m, v) in fp64."""
+    p = np.asarray(params, np.float64)
+    g = np.asarray(grads, np.float64)
+    m = beta1 * np.asarray(m, np.float64) + (1 - beta1) * g
+    v = beta2 * np.asarray(v, np.float64) + (1 - beta2) * g * g
+    mhat = m / (1 - beta1 ** t)
+    vhat = v / (1 - beta2 ** t)
+    lr = _lr_rows(p.shape[0], lr6)[:, None]
+    return p - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+def split_remap(state, split):
+    """Per-Gaussian state [rows][n] onto the densified layout: a kept
+    Gaussian's column moves to i + #splits before i, both offspring columns of
+    a split one are zero."""
+    state = np.asarray(state, np.float64)
+    split = np.asarray(split, bool)
+    n = state.shape[1]
+    off = np.concatenate([[0], np.cumsum(1 + split)[:-1]]).astype(np.int64)
+    out = np.zeros((state.shape[0], n + int(split.sum())))
+    keep = ~split
+    out[:, off[keep]] = state[:, keep]
+    return out

@@ -39,6 +39,10 @@ class SplitSelect(C.Structure):
     _fields_ = [("d_G", C.c_void_p), ("g_scale", C.c_float), ("eps_grad", C.c_float), ("budget", C.c_int64)]
 
 
+class AdamOpts(C.Structure):
+    _fields_ = [("lr", C.c_float * 6), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
+
+
 assert C.sizeof(Camera) == 96
 SPLAT_FLOATS = 12  # 48-byte record
 
@@ -74,8 +78,10 @@ def lib():
                                                vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.steepgs_densify.argtypes = [vp, i64, i32, vp, f32, f32, f32, C.POINTER(SplitSelect), vp, i64, vp, vp, vp,
                                       vp, vp, vp, sz, vp]
+        L.steepgs_adam_step.argtypes = [vp, vp, vp, vp, i64, i32, C.POINTER(AdamOpts), vp, vp, vp]
+        L.steepgs_split_remap.argtypes = [vp, i32, i64, vp, vp, i64, vp, sz, vp]
         for fn in ("steepgs_layout_cameras", "steepgs_project", "steepgs_sort", "steepgs_render_fwd",
-                   "steepgs_render_bwd_split", "steepgs_densify"):
+                   "steepgs_render_bwd_split", "steepgs_densify", "steepgs_adam_step", "steepgs_split_remap"):
             getattr(L, fn).restype = C.c_int
         L.steepgs_status_string.argtypes = [C.c_int]
         L.steepgs_status_string.restype = C.c_char_p
@@ -187,6 +193,27 @@ def steepgs_densify(params, n, sh_degree, S, s_scale, eps, eps_split, out, out_c
                                  None if sel is None else C.byref(sel), _p(out), out_capacity, _p(n_out),
                                  _p(lambda_min), _p(vmin), _p(split), _p(status), _p(ws),
                                  ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def make_adam_opts(lr, beta1=0.9, beta2=0.999, eps=1e-15):
+    """lr: six learning rates (position, log-scales, quaternion, opacity logit,
+    SH degree 0, SH degrees >= 1)."""
+    lr = list(lr)
+    if len(lr) != 6:
+        raise ValueError("six learning rates expected")
+    return AdamOpts((C.c_float * 6)(*[float(x) for x in lr]), float(beta1), float(beta2), float(eps))
+
+
+def steepgs_adam_step(params, grads, m, v, n, sh_degree, opts, step, G=None, stream=None):
+    _check("steepgs_adam_step",
+           lib().steepgs_adam_step(_p(params), _p(grads), _p(m), _p(v), n, sh_degree, C.byref(opts), _p(step),
+                                   _p(G), _stream(stream)))
+
+
+def steepgs_split_remap(src, rows, n, split, dst, dst_capacity, ws, stream=None):
+    _check("steepgs_split_remap",
+           lib().steepgs_split_remap(_p(src), rows, n, _p(split), _p(dst), dst_capacity, _p(ws),
+                                     ws.numel() * ws.element_size(), _stream(stream)))
 
 
 def version() -> str:

@@ -6,11 +6,24 @@
 
 namespace sg {
 
-__global__ void __launch_bounds__(256) k_project(const float* __restrict__ params, int64_t n, int deg,
-                                                 const steepgs_camera* __restrict__ cams, int V, steepgs_opts opt,
-                                                 steepgs_splat* __restrict__ out, uint32_t* __restrict__ tiles) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// One thread per Gaussian loops over the views; the Gaussian's SH
+// coefficients are staged once in the thread's own LDS column, so every view
+// reads them from LDS instead of HBM.
+constexpr int kProjThreads = 128;
+
+template <int D>
+__global__ void __launch_bounds__(kProjThreads) k_project(const float* __restrict__ params, int64_t n,
+                                                          const steepgs_camera* __restrict__ cams, int V,
+                                                          steepgs_opts opt, steepgs_splat* __restrict__ out,
+                                                          uint32_t* __restrict__ tiles) {
+  constexpr int NS = 3 * (D + 1) * (D + 1);
+  __shared__ float s_sh[NS * kProjThreads];  // [coefficient][thread]
+  const int tid = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * kProjThreads + tid;
+  if (i >= n) return;  // no barrier below: each thread touches only its own column
+  float* const sh = s_sh + tid;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) sh[k * kProjThreads] = params[(STEEPGS_ROW_SH + k) * n + i];
   Gauss g;
   load_gauss(params, n, i, g);
   for (int v = 0; v < V; ++v) {
@@ -20,16 +33,18 @@ __global__ void __launch_bounds__(256) k_project(const float* __restrict__ param
     const int64_t r = (int64_t)v * n + i;
     steepgs_splat s;
     uint32_t count = 0;
-    if (project_view(g, params, n, i, deg, cam, opt, pv, true)) {
+    if (project_view(g, cam, opt, pv)) {
+      double rgb[3];
+      view_colour<D>(g, cam, sh, kProjThreads, rgb);
       s.mean_x = (float)pv.mx;
       s.mean_y = (float)pv.my;
       s.conic_a = (float)pv.A00;
       s.conic_b = (float)pv.A01;
       s.conic_c = (float)pv.A11;
       s.opacity = (float)g.o;
-      s.rgb[0] = (float)pv.rgb[0];
-      s.rgb[1] = (float)pv.rgb[1];
-      s.rgb[2] = (float)pv.rgb[2];
+      s.rgb[0] = (float)rgb[0];
+      s.rgb[1] = (float)rgb[1];
+      s.rgb[2] = (float)rgb[2];
       s.depth = (float)pv.pc[2];
       s.rect_lo = (uint32_t)pv.rect[0] | ((uint32_t)pv.rect[1] << 16);
       s.rect_hi = (uint32_t)pv.rect[2] | ((uint32_t)pv.rect[3] << 16);
@@ -120,10 +135,15 @@ extern "C" steepgs_status steepgs_project(const float* d_params, int64_t n, int3
   if (n == 0) return STEEPGS_OK;
   if (!d_params || !d_cams || !d_splats || !d_tiles_touched) return STEEPGS_ERR_INVALID_ARG;
   if ((int64_t)V * n >= (int64_t)UINT32_MAX) return STEEPGS_ERR_INVALID_ARG;  // record ids are 32-bit
-  const int threads = 256;
   timer_begin(STEEPGS_TIMER_PROJECT, as_stream(stream));
-  hipLaunchKernelGGL(k_project, dim3((unsigned)ceil_div(n, threads)), dim3(threads), 0, as_stream(stream), d_params,
-                     n, sh_degree, d_cams, V, *opts, d_splats, d_tiles_touched);
+  const dim3 pg((unsigned)ceil_div(n, kProjThreads)), pb(kProjThreads);
+  hipStream_t st = as_stream(stream);
+  switch (sh_degree) {
+    case 0: hipLaunchKernelGGL(k_project<0>, pg, pb, 0, st, d_params, n, d_cams, V, *opts, d_splats, d_tiles_touched); break;
+    case 1: hipLaunchKernelGGL(k_project<1>, pg, pb, 0, st, d_params, n, d_cams, V, *opts, d_splats, d_tiles_touched); break;
+    case 2: hipLaunchKernelGGL(k_project<2>, pg, pb, 0, st, d_params, n, d_cams, V, *opts, d_splats, d_tiles_touched); break;
+    default: hipLaunchKernelGGL(k_project<3>, pg, pb, 0, st, d_params, n, d_cams, V, *opts, d_splats, d_tiles_touched); break;
+  }
   const int64_t m = (int64_t)V * n;
   hipLaunchKernelGGL(k_count_tiles, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, as_stream(stream), d_splats,
                      d_tiles_touched, m, *opts);

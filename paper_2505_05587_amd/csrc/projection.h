@@ -129,13 +129,48 @@ SG_DEV double box_min_q(double a, double b, double c, double mx, double my, doub
 // meets the ellipse q <= radius_sigmas^2 (1e-6 relative slack).  Evaluated on
 // the stored float32 mean and conic, so the projection (which counts the
 // tiles) and the instance emission (which lists them) take the same decision.
-SG_DEV bool tile_hit(float mx, float my, float a, float b, float c, const steepgs_opts& opt, int tx, int ty) {
+SG_DEV bool tile_hit_fp64(float mx, float my, float a, float b, float c, const steepgs_opts& opt, int tx, int ty) {
 #pragma clang fp contract(off)
   const double k2 = (double)opt.radius_sigmas * (double)opt.radius_sigmas;
   const double x0 = (double)tx * opt.tile_w, y0 = (double)ty * opt.tile_h;
   const double q = box_min_q((double)a, (double)b, (double)c, (double)mx, (double)my, x0, x0 + (opt.tile_w - 1), y0,
                              y0 + (opt.tile_h - 1));
   return q <= k2 * (1.0 + 1e-6);
+}
+
+// The same decision, certified in fp32 where it can be: each edge minimum is
+// evaluated in fp32 together with M = a dx^2 + 2|b dx dy| + c dy^2, which
+// bounds its rounding error by ~10 ulp * M (the fp64 evaluation's own error
+// is far smaller).  When an edge's estimate plus 1e-5 M (and a 1e-6 margin on
+// the threshold) is below the threshold the tile is hit; when every edge's
+// estimate minus that bound is above it the tile is missed; otherwise the
+// fp64 rule decides.  Mean inside the box: hit (the same comparisons either
+// way).  Result identical to tile_hit_fp64.
+SG_DEV bool tile_hit(float mx, float my, float a, float b, float c, const steepgs_opts& opt, int tx, int ty) {
+  const float x0 = (float)(tx * opt.tile_w), x1 = (float)(tx * opt.tile_w + opt.tile_w - 1);
+  const float y0 = (float)(ty * opt.tile_h), y1 = (float)(ty * opt.tile_h + opt.tile_h - 1);
+  if (mx >= x0 && mx <= x1 && my >= y0 && my <= y1) return true;
+  const float T = opt.radius_sigmas * opt.radius_sigmas * (1.f + 1e-6f);
+  const float tm = 1e-6f * T;
+  bool sure_hit = false, all_miss = true;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    // edges x = x0, x = x1 (free coordinate y), then y = y0, y = y1 (free x)
+    const bool xe = e < 2;
+    const float fixed = xe ? ((e == 0 ? x0 : x1) - mx) : ((e == 2 ? y0 : y1) - my);
+    const float lo = xe ? (y0 - my) : (x0 - mx), hi = xe ? (y1 - my) : (x1 - mx);
+    const float pf = xe ? a : c, pv = xe ? c : a;  // coefficient of fixed^2 and of free^2
+    float fr = -(b * fixed) / pv;
+    fr = fminf(fmaxf(fr, lo), hi);
+    const float q = pf * fixed * fixed + 2.f * b * fixed * fr + pv * fr * fr;
+    const float M = pf * fixed * fixed + 2.f * fabsf(b * fixed * fr) + pv * fr * fr;
+    const float err = 1e-5f * M;
+    sure_hit |= q + err + tm <= T;
+    all_miss &= q - err - tm > T;
+  }
+  if (sure_hit) return true;
+  if (all_miss) return false;
+  return tile_hit_fp64(mx, my, a, b, c, opt, tx, ty);
 }
 
 // view-independent part of a Gaussian
@@ -211,14 +246,10 @@ struct ViewProj {
   double det;
   double A00, A01, A11;  // conic
   int rect[4];
-  double dir[3], dlen;  // unit direction from the camera centre and its length
-  double Y[16];
-  double raw[3], rgb[3];
 };
 
-// Returns false when culled.  With want_colour the SH colour is evaluated.
-SG_DEV bool project_view(const Gauss& g, const float* __restrict__ params, int64_t n, int64_t i, int deg,
-                         const CamD& cam, const steepgs_opts& opt, ViewProj& v, bool want_colour) {
+// Geometry of one view; returns false when culled.
+SG_DEV bool project_view(const Gauss& g, const CamD& cam, const steepgs_opts& opt, ViewProj& v) {
 #pragma clang fp contract(off)
   for (int r = 0; r < 3; ++r)
     v.pc[r] = cam.R[3 * r + 0] * g.p[0] + cam.R[3 * r + 1] * g.p[1] + cam.R[3 * r + 2] * g.p[2] + cam.t[r];
@@ -290,22 +321,31 @@ SG_DEV bool project_view(const Gauss& g, const float* __restrict__ params, int64
   v.rect[2] = (int)x1;
   v.rect[3] = (int)y1;
 
-  if (!want_colour) return true;
+  return true;
+}
+
+// SH colour of one view (Sec. 3: colour stored as SH coefficients), fp64:
+// max(0, sum_k sh_k Y_k(dir) + 1/2), dir the unit vector from the camera
+// centre to the mean.  sh[(3 k + ch) * stride] holds coefficient k of
+// channel ch.
+template <int D>
+SG_DEV void view_colour(const Gauss& g, const CamD& cam, const float* sh, int stride, double rgb[3]) {
+#pragma clang fp contract(off)
+  constexpr int NB = (D + 1) * (D + 1);
   double campos[3];
   for (int k = 0; k < 3; ++k) campos[k] = -(cam.R[0 + k] * cam.t[0] + cam.R[3 + k] * cam.t[1] + cam.R[6 + k] * cam.t[2]);
   double d[3] = {g.p[0] - campos[0], g.p[1] - campos[1], g.p[2] - campos[2]};
-  v.dlen = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-  for (int k = 0; k < 3; ++k) v.dir[k] = d[k] / v.dlen;
-  sh_eval<double>(deg, v.dir[0], v.dir[1], v.dir[2], v.Y);
-  const int nb = (deg + 1) * (deg + 1);
+  const double len = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  double Y[16];
+  sh_eval<double>(D, d[0] / len, d[1] / len, d[2] / len, Y);
+#pragma unroll
   for (int ch = 0; ch < 3; ++ch) {
     double acc = 0.0;
-    for (int k = 0; k < nb; ++k) acc = acc + (double)params[(STEEPGS_ROW_SH + 3 * k + ch) * n + i] * v.Y[k];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) acc = acc + (double)sh[(3 * k + ch) * stride] * Y[k];
     acc = acc + 0.5;
-    v.raw[ch] = acc;
-    v.rgb[ch] = acc < 0.0 ? 0.0 : acc;
+    rgb[ch] = acc < 0.0 ? 0.0 : acc;
   }
-  return true;
 }
 
 }  // namespace sg

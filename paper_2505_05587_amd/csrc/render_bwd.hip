@@ -1,19 +1,21 @@
 // Stage 4: backward of the blend and of the projection, with the splitting
 // matrices of Theorem 1 accumulated on the way (Sec. 4.4).
 //
-// Kernel 1 (raster backward, persistent over tiles): every pixel walks its
-// contributors back to front, recomputing alpha with the forward's own
-// routine and the transmittance T_i = T_{i+1} / (1 - alpha_i) from the stored
-// final value (no per-pixel lists are stored).  The walk starts at the last
-// contributor of the workgroup (of the wavefront, per wave); the thread that
-// stages an entry tests its alpha >= alpha_min box against every 8x8
-// quadrant, and each wavefront walks only the entries that reach its own.
-// Per contributor it forms
+// Kernel 1 (raster backward, persistent over tiles, one wavefront per tile):
+// each lane owns one pixel in every 8x8 quadrant of the tile; every pixel
+// walks its contributors back to front, recomputing alpha with the forward's
+// own routine and the transmittance T_i = T_{i+1} / (1 - alpha_i) from the
+// stored final value (no per-pixel lists are stored).  The walk starts at the
+// tile's last contributor; the lane that stages an entry tests its
+// alpha >= alpha_min box against every quadrant, and a quadrant whose pixels
+// the entry cannot reach (or whose last contributor lies before it) is
+// skipped for the whole wave.  Per contributor it forms
 //   g = dL/dalpha_i = sum_c dL/dC_c (c_i T_i - R_c / (1 - alpha_i)),
 // R = colour of everything behind i (background included), and the
-// gradients w.r.t. the 2D mean, conic, opacity and colour.  A wavefront sums
-// them over its 64 pixels with DPP row operations and issues one atomic per
-// quantity.
+// gradients w.r.t. the 2D mean, conic, opacity and colour.  A lane adds up
+// its pixels' contributions, the wavefront sums them over its lanes with DPP
+// row operations and issues one atomic per quantity and entry for the whole
+// tile.
 //
 // Kernel 2 (one thread per Gaussian, all views): chain rule from the 2D
 // quantities to the 3D parameters, and the splitting matrix.  With
@@ -27,179 +29,191 @@
 
 namespace sg {
 
+constexpr int kBwdWaves = 4;    // wavefronts per workgroup, each on a tile of its own
+constexpr int kG2dStride = 12;  // floats per record in the 2D-gradient buffer (9 used)
+
 template <int TW, int TH>
-__global__ void __launch_bounds__(TW* TH) k_render_bwd(const steepgs_splat* __restrict__ splats,
-                                                      const uint32_t* __restrict__ vals,
-                                                      const uint32_t* __restrict__ ranges,
-                                                      const steepgs_camera* __restrict__ cams, int V,
-                                                      steepgs_opts opt, int total_tiles,
-                                                      const float* __restrict__ image,
-                                                      const float* __restrict__ T_final,
-                                                      const uint32_t* __restrict__ n_contrib,
-                                                      const float* __restrict__ dL_dimage,
-                                                      const float* __restrict__ target, float* __restrict__ g2d,
-                                                      int64_t m, uint32_t* __restrict__ queue) {
-  constexpr int NT = TW * TH;
-  constexpr int NW = NT / 64;           // wavefronts per workgroup = 64-entry chunks per batch
-  constexpr int WX = TW / 8;            // each wavefront owns an 8x8 pixel quadrant of the tile
-  __shared__ float4 s_a[NT];            // mean x, mean y, conic a, conic b
-  __shared__ float4 s_c[NT];            // conic c, opacity, red, green
-  __shared__ float2 s_e[NT];            // blue, record id (bits)
-  __shared__ uint64_t s_bits[NW][NW];   // [wave][chunk]: entries of the chunk that reach the wave's quadrant
-  __shared__ uint32_t s_last[NW];
-  __shared__ int s_tile;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int qx = (wave % WX) * 8 + (lane & 7), qy = (wave / WX) * 8 + (lane >> 3);
+__global__ void __launch_bounds__(64 * kBwdWaves) k_render_bwd(const steepgs_splat* __restrict__ splats,
+                                                               const uint32_t* __restrict__ vals,
+                                                               const uint32_t* __restrict__ ranges,
+                                                               const steepgs_camera* __restrict__ cams, int V,
+                                                               steepgs_opts opt, int total_tiles,
+                                                               const float* __restrict__ image,
+                                                               const float* __restrict__ T_final,
+                                                               const uint32_t* __restrict__ n_contrib,
+                                                               const float* __restrict__ dL_dimage,
+                                                               const float* __restrict__ target,
+                                                               float* __restrict__ g2d, int64_t m,
+                                                               uint32_t* __restrict__ queue) {
+  constexpr int NQ = TW * TH / 64;  // 8x8 quadrants of the tile = pixels per lane
+  constexpr int QX = TW / 8;
+  __shared__ float4 s_a[kBwdWaves][64];  // mean x, mean y, conic a, conic b
+  __shared__ float4 s_c[kBwdWaves][64];  // conic c, opacity, red, green
+  __shared__ float2 s_e[kBwdWaves][64];  // blue, record id (bits)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lx = lane & 7, ly = lane >> 3;
+  float4* const A = s_a[wave];
+  float4* const Cq = s_c[wave];
+  float2* const E = s_e[wave];
   const float cut = footprint_power_cut(opt);
   for (;;) {
-    // The barrier closes the previous tile before lane 0 fetches the next one,
-    // so no lane-0-only region can span the loop's back edge.
-    __syncthreads();
-    if (tid == 0) s_tile = (int)atomicAdd(queue, 1u);
-    __syncthreads();
-    // scalar (wave-uniform) copy: the loop exit below must be a uniform branch
-    const int tile = __builtin_amdgcn_readfirstlane(s_tile);
+    // the wave barrier keeps the lane-0 fetch inside the loop
+    __builtin_amdgcn_wave_barrier();
+    uint32_t ticket = 0;
+    if (lane == 0) ticket = atomicAdd(queue, 1u);
+    const int tile = (int)__builtin_amdgcn_readfirstlane(ticket);
     if (tile >= total_tiles) break;
     const int v = view_of_tile(cams, V, tile);
     const int W = cams[v].width, H = cams[v].height, tiles_x = cams[v].tiles_x;
     const int64_t pix_off = cams[v].pixel_offset;
     const int lt = tile - cams[v].tile_offset;
     const int tx0 = (lt % tiles_x) * TW, ty0 = (lt / tiles_x) * TH;
-    const int px = tx0 + qx, py = ty0 + qy;
-    const bool inside = px < W && py < H;
     const uint32_t begin = ranges[2 * tile];
-    const float fx = (float)px, fy = (float)py;
-    float T = 1.f, dC0 = 0.f, dC1 = 0.f, dC2 = 0.f, R0 = 0.f, R1 = 0.f, R2 = 0.f;
-    uint32_t last = 0;
-    if (inside) {
-      const int64_t p = pix_off + (int64_t)py * W + px;
-      const int64_t plane = (int64_t)W * H;
-      const int64_t q = 3 * pix_off + (int64_t)py * W + px;
-      T = T_final[p];
-      last = n_contrib[p];
-      if (dL_dimage) {
-        dC0 = dL_dimage[q];
-        dC1 = dL_dimage[q + plane];
-        dC2 = dL_dimage[q + 2 * plane];
-      } else {
-        const float inv = 1.f / (3.f * (float)W * (float)H);
-        const float e0 = image[q] - target[q], e1 = image[q + plane] - target[q + plane];
-        const float e2 = image[q + 2 * plane] - target[q + 2 * plane];
-        dC0 = (e0 > 0.f) ? inv : ((e0 < 0.f) ? -inv : 0.f);
-        dC1 = (e1 > 0.f) ? inv : ((e1 < 0.f) ? -inv : 0.f);
-        dC2 = (e2 > 0.f) ? inv : ((e2 < 0.f) ? -inv : 0.f);
-      }
-      R0 = T * opt.bg[0];
-      R1 = T * opt.bg[1];
-      R2 = T * opt.bg[2];
-    }
-    // entries at or past a wavefront's last contributor need no work from it;
-    // the workgroup walks back from the largest last contributor
-    const int wlast = (int)__builtin_amdgcn_readfirstlane(wave_max_u32(last));
-    if (lane == 0) s_last[wave] = (uint32_t)wlast;
-    __syncthreads();
+    const int64_t plane = (int64_t)W * H;
+    const float inv = 1.f / (3.f * (float)W * (float)H);
+    // per-pixel state of the lane's pixel in every quadrant
+    float T[NQ], dC[NQ][3], R[NQ][3];
+    uint32_t last[NQ], qlast[NQ];
     int count = 0;
-    for (int w = 0; w < NW; ++w) count = max(count, (int)s_last[w]);
-    count = __builtin_amdgcn_readfirstlane(count);
-    for (int b_end = count; b_end > 0; b_end -= NT) {
-      const int b_start = b_end > NT ? b_end - NT : 0;
-      __syncthreads();
-      // stage one batch; the loading thread tests the entry's cut-off box
-      // against the quadrant of every wavefront
-      uint32_t qmask = 0;
-      if (b_start + tid < b_end) {
-        const uint32_t id = vals[begin + b_start + tid];
-        const steepgs_splat s = splats[id];
-        float ex, ey;
-        cutoff_extent(s.conic_a, s.conic_b, s.conic_c, s.opacity, opt, ex, ey);
-        s_a[tid] = make_float4(s.mean_x, s.mean_y, s.conic_a, s.conic_b);
-        s_c[tid] = make_float4(s.conic_c, s.opacity, s.rgb[0], s.rgb[1]);
-        s_e[tid] = make_float2(s.rgb[2], __uint_as_float(id));
 #pragma unroll
-        for (int w = 0; w < NW; ++w) {
-          const float x0 = (float)(tx0 + (w % WX) * 8), y0 = (float)(ty0 + (w / WX) * 8);
-          const bool hit = (s.mean_x + ex >= x0) && (s.mean_x - ex <= x0 + 7.f) && (s.mean_y + ey >= y0) &&
-                           (s.mean_y - ey <= y0 + 7.f);
-          qmask |= hit ? (1u << w) : 0u;
+    for (int q = 0; q < NQ; ++q) {
+      const int px = tx0 + (q % QX) * 8 + lx, py = ty0 + (q / QX) * 8 + ly;
+      T[q] = 1.f;
+      last[q] = 0;
+      dC[q][0] = dC[q][1] = dC[q][2] = 0.f;
+      R[q][0] = R[q][1] = R[q][2] = 0.f;
+      if (px < W && py < H) {
+        const int64_t pp = pix_off + (int64_t)py * W + px;
+        const int64_t e = 3 * pix_off + (int64_t)py * W + px;
+        T[q] = T_final[pp];
+        last[q] = n_contrib[pp];
+        if (dL_dimage) {
+          dC[q][0] = dL_dimage[e];
+          dC[q][1] = dL_dimage[e + plane];
+          dC[q][2] = dL_dimage[e + 2 * plane];
+        } else {
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) {
+            const float d = image[e + ch * plane] - target[e + ch * plane];
+            dC[q][ch] = (d > 0.f) ? inv : ((d < 0.f) ? -inv : 0.f);
+          }
+        }
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) R[q][ch] = T[q] * opt.bg[ch];
+      }
+      // entries at or past a quadrant's last contributor need no work for it
+      qlast[q] = (uint32_t)__builtin_amdgcn_readfirstlane(wave_max_u32(last[q]));
+      count = max(count, (int)qlast[q]);
+    }
+    for (int b_end = count; b_end > 0; b_end -= 64) {
+      const int b_start = b_end > 64 ? b_end - 64 : 0;
+      // stage one batch of 64 entries in the wave's LDS slice; the loading
+      // lane tests the entry's cut-off box against every quadrant
+      const bool have = b_start + lane < b_end;
+      bool hitq[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) hitq[q] = false;
+      __builtin_amdgcn_wave_barrier();
+      if (have) {
+        const uint32_t id = vals[begin + b_start + lane];
+        const steepgs_splat sp = splats[id];
+        float ex, ey;
+        cutoff_extent(sp.conic_a, sp.conic_b, sp.conic_c, sp.opacity, opt, ex, ey);
+        A[lane] = make_float4(sp.mean_x, sp.mean_y, sp.conic_a, sp.conic_b);
+        Cq[lane] = make_float4(sp.conic_c, sp.opacity, sp.rgb[0], sp.rgb[1]);
+        E[lane] = make_float2(sp.rgb[2], __uint_as_float(id));
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const float x0 = (float)(tx0 + (q % QX) * 8), y0 = (float)(ty0 + (q / QX) * 8);
+          hitq[q] = (sp.mean_x + ex >= x0) && (sp.mean_x - ex <= x0 + 7.f) && (sp.mean_y + ey >= y0) &&
+                    (sp.mean_y - ey <= y0 + 7.f);
         }
       }
+      uint64_t qm[NQ], any_q = 0;
 #pragma unroll
-      for (int w = 0; w < NW; ++w) {
-        const uint64_t b = ballot((qmask >> w) & 1u);
-        if (lane == 0) s_bits[w][wave] = b;
+      for (int q = 0; q < NQ; ++q) {
+        qm[q] = uniform_u64(ballot(hitq[q]));
+        // only entries below the quadrant's last contributor
+        const int lim = (int)qlast[q] - b_start;
+        if (lim <= 0) qm[q] = 0;
+        else if (lim < 64) qm[q] &= (1ull << lim) - 1ull;
+        any_q |= qm[q];
       }
-      __syncthreads();
-      // this wavefront's entries of the batch below its last contributor, back to front
-      const int jtop = min(b_end, wlast) - b_start - 1;
-      for (int c = NW - 1; c >= 0; --c) {
-        if (jtop < c * 64) continue;
-        uint64_t bits = uniform_u64(s_bits[wave][c]);
-        if (jtop - c * 64 < 63) bits &= (2ull << (jtop - c * 64)) - 1ull;
-        while (bits) {
-          const int hb = 63 - (int)__builtin_clzll(bits);
-          bits &= ~(1ull << hb);
-          const int j = c * 64 + hb;
-          const float4 a = s_a[j];
-          const float4 qq = s_c[j];
-          const uint32_t pos = (uint32_t)(b_start + j);
-          bool contrib = pos < last;  // false for pixels outside the image (last = 0)
-          float gmx = 0.f, gmy = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
-          if (contrib) {
-            const float dx = fx - a.x, dy = fy - a.y;
-            const float ca = a.z, cb = a.w, cc = qq.x;
-            const float power = splat_power(dx, dy, ca, cb, cc);
-            const float G = __expf(power);
-            const float raw_a = qq.y * G;
-            const bool clamped = raw_a > opt.alpha_max;
-            const float alpha = clamped ? opt.alpha_max : raw_a;
-            contrib = power >= cut && alpha >= opt.alpha_min;
-            if (contrib) {
-              const float blue = s_e[j].x;
-              const float om = 1.f - alpha;
-              T = T / om;  // transmittance in front of this entry
-              const float w = alpha * T;
-              const float inv_om = 1.f / om;
-              const float g = dC0 * (qq.z * T - R0 * inv_om) + dC1 * (qq.w * T - R1 * inv_om) +
-                              dC2 * (blue * T - R2 * inv_om);
-              R0 += qq.z * w;
-              R1 += qq.w * w;
-              R2 += blue * w;
-              gr = w * dC0;
-              gg = w * dC1;
-              gbl = w * dC2;
-              if (!clamped) {
-                const float gaw = g * alpha;
-                gmx = gaw * (ca * dx + cb * dy);
-                gmy = gaw * (cb * dx + cc * dy);
-                ga = -0.5f * gaw * dx * dx;
-                gb = -gaw * dx * dy;
-                gc = -0.5f * gaw * dy * dy;
-                go = g * G;
-              }
-            }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // back to front over the batch
+      while (any_q) {
+        const int j = 63 - (int)__builtin_clzll(any_q);
+        any_q &= ~(1ull << j);
+        const float4 a = A[j];
+        const float4 cq = Cq[j];
+        const uint32_t pos = (uint32_t)(b_start + j);
+        float gmx = 0.f, gmy = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
+        bool any = false;
+        float blue = 0.f;
+        bool blue_loaded = false;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          if (!((qm[q] >> j) & 1ull)) continue;  // wave-uniform
+          if (pos >= last[q]) continue;          // past this pixel's last contributor (or outside the image)
+          const float dx = (float)(tx0 + (q % QX) * 8 + lx) - a.x;
+          const float dy = (float)(ty0 + (q / QX) * 8 + ly) - a.y;
+          const float power = splat_power(dx, dy, a.z, a.w, cq.x);
+          const float G = __expf(power);
+          const float raw = cq.y * G;
+          const bool clamped = raw > opt.alpha_max;
+          const float alpha = clamped ? opt.alpha_max : raw;
+          if (!(power >= cut && alpha >= opt.alpha_min)) continue;
+          if (!blue_loaded) {
+            blue = E[j].x;
+            blue_loaded = true;
           }
-          if (ballot(contrib)) {
-            gmx = wave_sum_dpp(gmx);
-            gmy = wave_sum_dpp(gmy);
-            ga = wave_sum_dpp(ga);
-            gb = wave_sum_dpp(gb);
-            gc = wave_sum_dpp(gc);
-            go = wave_sum_dpp(go);
-            gr = wave_sum_dpp(gr);
-            gg = wave_sum_dpp(gg);
-            gbl = wave_sum_dpp(gbl);
-            if (lane == 0) {
-              const int64_t id = __float_as_uint(s_e[j].y);
-              unsafeAtomicAdd(&g2d[0 * m + id], gmx);
-              unsafeAtomicAdd(&g2d[1 * m + id], gmy);
-              unsafeAtomicAdd(&g2d[2 * m + id], ga);
-              unsafeAtomicAdd(&g2d[3 * m + id], gb);
-              unsafeAtomicAdd(&g2d[4 * m + id], gc);
-              unsafeAtomicAdd(&g2d[5 * m + id], go);
-              unsafeAtomicAdd(&g2d[6 * m + id], gr);
-              unsafeAtomicAdd(&g2d[7 * m + id], gg);
-              unsafeAtomicAdd(&g2d[8 * m + id], gbl);
-            }
+          any = true;
+          const float om = 1.f - alpha;
+          T[q] = T[q] / om;  // transmittance in front of this entry
+          const float w = alpha * T[q];
+          const float inv_om = 1.f / om;
+          const float g = dC[q][0] * (cq.z * T[q] - R[q][0] * inv_om) + dC[q][1] * (cq.w * T[q] - R[q][1] * inv_om) +
+                          dC[q][2] * (blue * T[q] - R[q][2] * inv_om);
+          R[q][0] += cq.z * w;
+          R[q][1] += cq.w * w;
+          R[q][2] += blue * w;
+          gr += w * dC[q][0];
+          gg += w * dC[q][1];
+          gbl += w * dC[q][2];
+          if (!clamped) {
+            const float gaw = g * alpha;
+            gmx += gaw * (a.z * dx + a.w * dy);
+            gmy += gaw * (a.w * dx + cq.x * dy);
+            ga += -0.5f * gaw * dx * dx;
+            gb += -gaw * dx * dy;
+            gc += -0.5f * gaw * dy * dy;
+            go += g * G;
+          }
+        }
+        if (ballot(any)) {
+          gmx = wave_sum_dpp(gmx);
+          gmy = wave_sum_dpp(gmy);
+          ga = wave_sum_dpp(ga);
+          gb = wave_sum_dpp(gb);
+          gc = wave_sum_dpp(gc);
+          go = wave_sum_dpp(go);
+          gr = wave_sum_dpp(gr);
+          gg = wave_sum_dpp(gg);
+          gbl = wave_sum_dpp(gbl);
+          if (lane == 0) {
+            // one 48-byte slot per record: the nine updates share a cache line or two
+            float* const slot = g2d + (int64_t)__float_as_uint(E[j].y) * kG2dStride;
+            unsafeAtomicAdd(slot + 0, gmx);
+            unsafeAtomicAdd(slot + 1, gmy);
+            unsafeAtomicAdd(slot + 2, ga);
+            unsafeAtomicAdd(slot + 3, gb);
+            unsafeAtomicAdd(slot + 4, gc);
+            unsafeAtomicAdd(slot + 5, go);
+            unsafeAtomicAdd(slot + 6, gr);
+            unsafeAtomicAdd(slot + 7, gg);
+            unsafeAtomicAdd(slot + 8, gbl);
           }
         }
       }
@@ -242,7 +256,6 @@ __global__ void __launch_bounds__(128) k_proj_bwd(const float* __restrict__ para
   constexpr int NB = (D + 1) * (D + 1);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int64_t m = (int64_t)V * n;
   float p[3];
   for (int k = 0; k < 3; ++k) p[k] = params[(STEEPGS_ROW_MEAN + k) * n + i];
   float sh[3 * NB];
@@ -275,11 +288,15 @@ __global__ void __launch_bounds__(128) k_proj_bwd(const float* __restrict__ para
     const int64_t r = (int64_t)v * n + i;
     if (tiles[r] == 0) continue;
     float G9[9];
-    bool nz = false;
-    for (int k = 0; k < 9; ++k) {
-      G9[k] = g2d[k * m + r];
-      nz |= G9[k] != 0.f;
+    {
+      const float4* slot = reinterpret_cast<const float4*>(g2d + r * kG2dStride);
+      const float4 u0 = slot[0], u1 = slot[1], u2 = slot[2];
+      G9[0] = u0.x; G9[1] = u0.y; G9[2] = u0.z; G9[3] = u0.w;
+      G9[4] = u1.x; G9[5] = u1.y; G9[6] = u1.z; G9[7] = u1.w;
+      G9[8] = u2.x;
     }
+    bool nz = false;
+    for (int k = 0; k < 9; ++k) nz |= G9[k] != 0.f;
     if (!nz) continue;
     any = true;
     const steepgs_camera& cam = cams[v];
@@ -482,7 +499,7 @@ __global__ void k_zero(float* __restrict__ p, int64_t count) {
 static size_t bwd_layout(void* base, int64_t m, float** g2d, uint32_t** queue) {
   Carver c(base);
   *queue = c.take<uint32_t>(64);
-  *g2d = c.take<float>((size_t)9 * m);
+  *g2d = c.take<float>((size_t)kG2dStride * m);
   return c.used + 256;
 }
 
@@ -497,7 +514,7 @@ static void launch_bwd(int grid, hipStream_t st, const steepgs_splat* splats, co
                        const uint32_t* ranges, const steepgs_camera* cams, int V, const steepgs_opts& opt,
                        int total_tiles, const float* image, const float* T_final, const uint32_t* n_contrib,
                        const float* dL_dimage, const float* target, float* g2d, int64_t m, uint32_t* queue) {
-  hipLaunchKernelGGL((k_render_bwd<TW, TH>), dim3(grid), dim3(TW * TH), 0, st, splats, vals, ranges, cams, V, opt,
+  hipLaunchKernelGGL((k_render_bwd<TW, TH>), dim3(grid), dim3(64 * kBwdWaves), 0, st, splats, vals, ranges, cams, V, opt,
                      total_tiles, image, T_final, n_contrib, dL_dimage, target, g2d, m, queue);
 }
 
@@ -529,9 +546,9 @@ extern "C" steepgs_status steepgs_render_bwd_split(const float* d_params, int64_
   if (d_grad2d) g2d = d_grad2d;
   hipStream_t st = as_stream(stream);
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, reinterpret_cast<float*>(queue), (int64_t)1);
-  hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<int64_t>(ceil_div(9 * m, 256), 65536)), dim3(256), 0, st, g2d,
-                     9 * m);
-  const int grid = (int)std::min<int64_t>(total_tiles, (int64_t)device_cu_count() * 8);
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<int64_t>(ceil_div(kG2dStride * m, 256), 65536)), dim3(256), 0,
+                     st, g2d, kG2dStride * m);
+  const int grid = (int)std::min<int64_t>(ceil_div(total_tiles, kBwdWaves), (int64_t)device_cu_count() * 8);
   const steepgs_opts& o = *opts;
   timer_begin(STEEPGS_TIMER_RENDER_BWD, st);
   if (o.tile_w == 16 && o.tile_h == 16)

@@ -1,148 +1,159 @@
 // Stage 3: front-to-back alpha blending (Eq. alpha_blend) of every tile of
 // every view in one persistent launch.
 //
-// A workgroup owns one screen tile at a time (one thread per pixel, each
-// wavefront an 8x8 quadrant) and takes the next tile from a global atomic
-// queue when done, so tiles with long instance lists do not stall the rest of
-// the grid.  The tile's instances are staged through LDS in batches of one
-// record per thread; the loading thread also tests the entry's cut-off box
-// against every quadrant, and each wavefront then walks only the entries
-// that reach its quadrant (a per-chunk bit mask scanned on the scalar unit).
-// A wavefront stops when all its pixels are saturated, and the workgroup
-// leaves the tile when every pixel's transmittance has hit the cut-off.
+// One wavefront owns one screen tile at a time and takes the next tile from a
+// global atomic queue when done, so tiles with long instance lists do not
+// stall the rest of the grid; each lane owns one pixel in every 8x8 quadrant
+// of the tile.  The tile's instances are staged through the wavefront's LDS
+// slice in batches of 64; the loading lane tests the entry's cut-off box
+// against every quadrant, and a quadrant the entry cannot reach (or whose
+// pixels are all saturated) is skipped for the whole wavefront.  The
+// wavefront leaves the tile when every pixel's transmittance has hit the
+// cut-off.
 #include "common.h"
 
 namespace sg {
 
+constexpr int kFwdWaves = 4;  // wavefronts per workgroup, each on a tile of its own
+
 template <int TW, int TH>
-__global__ void __launch_bounds__(TW* TH) k_render_fwd(const steepgs_splat* __restrict__ splats,
-                                                      const uint32_t* __restrict__ vals,
-                                                      const uint32_t* __restrict__ ranges,
-                                                      const steepgs_camera* __restrict__ cams, int V,
-                                                      steepgs_opts opt, int total_tiles,
-                                                      const float* __restrict__ target, float* __restrict__ image,
-                                                      float* __restrict__ T_final, uint32_t* __restrict__ n_contrib,
-                                                      uint32_t* __restrict__ n_used, float* __restrict__ loss,
-                                                      uint32_t* __restrict__ queue) {
-  constexpr int NT = TW * TH;
-  constexpr int NW = NT / 64;         // wavefronts per workgroup = 64-entry chunks per batch
-  constexpr int WX = TW / 8;          // each wavefront owns an 8x8 pixel quadrant of the tile
-  __shared__ float4 s_a[NT];          // mean x, mean y, conic a, conic b
-  __shared__ float4 s_c[NT];          // conic c, opacity, red, green
-  __shared__ float s_bl[NT];          // blue
-  __shared__ uint64_t s_bits[NW][NW]; // [wave][chunk]: entries of the chunk that reach the wave's quadrant
-  __shared__ float s_red[NW];
-  __shared__ int s_tile;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int qx = (wave % WX) * 8 + (lane & 7), qy = (wave / WX) * 8 + (lane >> 3);
+__global__ void __launch_bounds__(64 * kFwdWaves) k_render_fwd(const steepgs_splat* __restrict__ splats,
+                                                               const uint32_t* __restrict__ vals,
+                                                               const uint32_t* __restrict__ ranges,
+                                                               const steepgs_camera* __restrict__ cams, int V,
+                                                               steepgs_opts opt, int total_tiles,
+                                                               const float* __restrict__ target,
+                                                               float* __restrict__ image, float* __restrict__ T_final,
+                                                               uint32_t* __restrict__ n_contrib,
+                                                               uint32_t* __restrict__ n_used, float* __restrict__ loss,
+                                                               uint32_t* __restrict__ queue) {
+  constexpr int NQ = TW * TH / 64;  // 8x8 quadrants of the tile = pixels per lane
+  constexpr int QX = TW / 8;
+  __shared__ float4 s_a[kFwdWaves][64];  // mean x, mean y, conic a, conic b
+  __shared__ float4 s_c[kFwdWaves][64];  // conic c, opacity, red, green
+  __shared__ float s_b[kFwdWaves][64];   // blue
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lx = lane & 7, ly = lane >> 3;
+  float4* const A = s_a[wave];
+  float4* const Cq = s_c[wave];
+  float* const Bl = s_b[wave];
   const float cut = footprint_power_cut(opt);
   for (;;) {
-    // The barrier closes the previous tile before lane 0 fetches the next one,
-    // so no lane-0-only region can span the loop's back edge (the compiler
-    // would otherwise merge them and let the other lanes re-enter the tile
-    // loop without the fetch).
-    __syncthreads();
-    if (tid == 0) s_tile = (int)atomicAdd(queue, 1u);
-    __syncthreads();
-    // scalar (wave-uniform) copy: the loop exit below must be a uniform branch
-    const int tile = __builtin_amdgcn_readfirstlane(s_tile);
+    // the wave barrier keeps the lane-0 fetch inside the loop
+    __builtin_amdgcn_wave_barrier();
+    uint32_t ticket = 0;
+    if (lane == 0) ticket = atomicAdd(queue, 1u);
+    const int tile = (int)__builtin_amdgcn_readfirstlane(ticket);
     if (tile >= total_tiles) break;
     const int v = view_of_tile(cams, V, tile);
     const int W = cams[v].width, H = cams[v].height, tiles_x = cams[v].tiles_x;
     const int64_t pix_off = cams[v].pixel_offset;
     const int lt = tile - cams[v].tile_offset;
     const int tx0 = (lt % tiles_x) * TW, ty0 = (lt / tiles_x) * TH;
-    const int px = tx0 + qx, py = ty0 + qy;
-    const bool inside = px < W && py < H;
     const uint32_t begin = ranges[2 * tile], end = ranges[2 * tile + 1];
-    const float fx = (float)px, fy = (float)py;
-    float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
-    uint32_t last = 0, used = 0;
-    bool done = !inside;
-    for (uint32_t b0 = begin; b0 < end; b0 += NT) {
-      if (__builtin_amdgcn_readfirstlane(__syncthreads_count(done)) == NT) break;
-      // stage one batch; the thread that loads an entry tests its cut-off
-      // box (alpha >= alpha_min and inside the footprint) against the
-      // quadrant of every wavefront
-      const uint32_t idx = b0 + tid;
-      uint32_t qmask = 0;
-      if (idx < end) {
-        const steepgs_splat s = splats[vals[idx]];
-        float ex, ey;
-        cutoff_extent(s.conic_a, s.conic_b, s.conic_c, s.opacity, opt, ex, ey);
-        s_a[tid] = make_float4(s.mean_x, s.mean_y, s.conic_a, s.conic_b);
-        s_c[tid] = make_float4(s.conic_c, s.opacity, s.rgb[0], s.rgb[1]);
-        s_bl[tid] = s.rgb[2];
+    float T[NQ], C[NQ][3];
+    uint32_t last[NQ], used[NQ];
+    bool done[NQ];
 #pragma unroll
-        for (int w = 0; w < NW; ++w) {
-          const float x0 = (float)(tx0 + (w % WX) * 8), y0 = (float)(ty0 + (w / WX) * 8);
-          const bool hit = (s.mean_x + ex >= x0) && (s.mean_x - ex <= x0 + 7.f) && (s.mean_y + ey >= y0) &&
-                           (s.mean_y - ey <= y0 + 7.f);
-          qmask |= hit ? (1u << w) : 0u;
+    for (int q = 0; q < NQ; ++q) {
+      const int px = tx0 + (q % QX) * 8 + lx, py = ty0 + (q / QX) * 8 + ly;
+      T[q] = 1.f;
+      C[q][0] = C[q][1] = C[q][2] = 0.f;
+      last[q] = used[q] = 0;
+      done[q] = !(px < W && py < H);
+    }
+    for (uint32_t b0 = begin; b0 < end; b0 += 64) {
+      // quadrants with a pixel still open (wave-uniform)
+      uint32_t alive = 0;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) alive |= ballot(!done[q]) ? (1u << q) : 0u;
+      alive = __builtin_amdgcn_readfirstlane(alive);
+      if (!alive) break;
+      // stage one batch of 64 entries in the wave's LDS slice; the loading
+      // lane tests the entry's cut-off box against every quadrant
+      const uint32_t idx = b0 + (uint32_t)lane;
+      bool hitq[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) hitq[q] = false;
+      __builtin_amdgcn_wave_barrier();
+      if (idx < end) {
+        const steepgs_splat sp = splats[vals[idx]];
+        float ex, ey;
+        cutoff_extent(sp.conic_a, sp.conic_b, sp.conic_c, sp.opacity, opt, ex, ey);
+        A[lane] = make_float4(sp.mean_x, sp.mean_y, sp.conic_a, sp.conic_b);
+        Cq[lane] = make_float4(sp.conic_c, sp.opacity, sp.rgb[0], sp.rgb[1]);
+        Bl[lane] = sp.rgb[2];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const float x0 = (float)(tx0 + (q % QX) * 8), y0 = (float)(ty0 + (q / QX) * 8);
+          hitq[q] = (sp.mean_x + ex >= x0) && (sp.mean_x - ex <= x0 + 7.f) && (sp.mean_y + ey >= y0) &&
+                    (sp.mean_y - ey <= y0 + 7.f);
         }
       }
+      uint64_t qm[NQ], any_q = 0;
 #pragma unroll
-      for (int w = 0; w < NW; ++w) {
-        const uint64_t b = ballot((qmask >> w) & 1u);
-        if (lane == 0) s_bits[w][wave] = b;
+      for (int q = 0; q < NQ; ++q) {
+        qm[q] = ((alive >> q) & 1u) ? uniform_u64(ballot(hitq[q])) : 0ull;
+        any_q |= qm[q];
       }
-      __syncthreads();
-      // this wavefront's entries of the batch, front to back
-      for (int c = 0; c < NW; ++c) {
-        uint64_t bits = uniform_u64(s_bits[wave][c]);
-        while (bits) {
-          if (ballot(!done) == 0) break;  // the whole wavefront is finished
-          const int j = c * 64 + (int)__builtin_ctzll(bits);
-          bits &= bits - 1;
-          const float4 a = s_a[j];
-          const float4 q = s_c[j];
-          if (done) continue;
-          const float dx = fx - a.x, dy = fy - a.y;
-          const float power = splat_power(dx, dy, a.z, a.w, q.x);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // front to back over the batch
+      while (any_q) {
+        const int j = (int)__builtin_ctzll(any_q);
+        any_q &= any_q - 1ull;
+        const float4 a = A[j];
+        const float4 cq = Cq[j];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          if (!((qm[q] >> j) & 1ull)) continue;  // wave-uniform
+          if (done[q]) continue;
+          const float dx = (float)(tx0 + (q % QX) * 8 + lx) - a.x;
+          const float dy = (float)(ty0 + (q / QX) * 8 + ly) - a.y;
+          const float power = splat_power(dx, dy, a.z, a.w, cq.x);
           if (power < cut) continue;  // outside the footprint
-          const float alpha = fminf(opt.alpha_max, q.y * __expf(power));
+          const float alpha = fminf(opt.alpha_max, cq.y * __expf(power));
           if (alpha < opt.alpha_min) continue;
-          const float Tn = T * (1.f - alpha);
+          const float Tn = T[q] * (1.f - alpha);
           if (Tn < opt.t_min) {
-            done = true;
+            done[q] = true;
             continue;
           }
-          const float w = alpha * T;
-          C0 += q.z * w;
-          C1 += q.w * w;
-          C2 += s_bl[j] * w;
-          T = Tn;
-          last = b0 - begin + (uint32_t)j + 1u;
-          ++used;
+          const float w = alpha * T[q];
+          C[q][0] += cq.z * w;
+          C[q][1] += cq.w * w;
+          C[q][2] += Bl[j] * w;
+          T[q] = Tn;
+          last[q] = b0 - begin + (uint32_t)j + 1u;
+          ++used[q];
         }
       }
     }
     float err = 0.f;
-    if (inside) {
-      const int64_t p = pix_off + (int64_t)py * W + px;
-      const int64_t plane = (int64_t)W * H;
-      float* img = image + 3 * pix_off + (int64_t)py * W + px;
-      const float o0 = C0 + T * opt.bg[0], o1 = C1 + T * opt.bg[1], o2 = C2 + T * opt.bg[2];
-      img[0] = o0;
-      img[plane] = o1;
-      img[2 * plane] = o2;
-      T_final[p] = T;
-      n_contrib[p] = last;
-      if (n_used) n_used[p] = used;
-      if (target) {
-        const float* tg = target + 3 * pix_off + (int64_t)py * W + px;
-        err = fabsf(o0 - tg[0]) + fabsf(o1 - tg[plane]) + fabsf(o2 - tg[2 * plane]);
+    const int64_t plane = (int64_t)W * H;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int px = tx0 + (q % QX) * 8 + lx, py = ty0 + (q / QX) * 8 + ly;
+      if (px < W && py < H) {
+        const int64_t p = pix_off + (int64_t)py * W + px;
+        float* img = image + 3 * pix_off + (int64_t)py * W + px;
+        const float o0 = C[q][0] + T[q] * opt.bg[0], o1 = C[q][1] + T[q] * opt.bg[1], o2 = C[q][2] + T[q] * opt.bg[2];
+        img[0] = o0;
+        img[plane] = o1;
+        img[2 * plane] = o2;
+        T_final[p] = T[q];
+        n_contrib[p] = last[q];
+        if (n_used) n_used[p] = used[q];
+        if (target) {
+          const float* tg = target + 3 * pix_off + (int64_t)py * W + px;
+          err += fabsf(o0 - tg[0]) + fabsf(o1 - tg[plane]) + fabsf(o2 - tg[2 * plane]);
+        }
       }
     }
     if (target) {
       err = wave_sum_dpp(err);
-      if (lane == 0) s_red[wave] = err;
-      __syncthreads();
-      if (tid == 0) {
-        float s = 0.f;
-        for (int w = 0; w < NW; ++w) s += s_red[w];
-        atomicAdd(&loss[v], s / (3.f * (float)W * (float)H));
-      }
+      if (lane == 0) atomicAdd(&loss[v], err / (3.f * (float)W * (float)H));
     }
   }
 }
@@ -164,7 +175,7 @@ static void launch_fwd(int grid, hipStream_t st, const steepgs_splat* splats, co
                        const uint32_t* ranges, const steepgs_camera* cams, int V, const steepgs_opts& opt,
                        int total_tiles, const float* target, float* image, float* T_final, uint32_t* n_contrib,
                        uint32_t* n_used, float* loss, uint32_t* queue) {
-  hipLaunchKernelGGL((k_render_fwd<TW, TH>), dim3(grid), dim3(TW * TH), 0, st, splats, vals, ranges, cams, V, opt,
+  hipLaunchKernelGGL((k_render_fwd<TW, TH>), dim3(grid), dim3(64 * kFwdWaves), 0, st, splats, vals, ranges, cams, V, opt,
                      total_tiles, target, image, T_final, n_contrib, n_used, loss, queue);
 }
 
@@ -187,7 +198,7 @@ extern "C" steepgs_status steepgs_render_fwd(const steepgs_splat* d_splats, int6
   uint32_t* queue = static_cast<uint32_t*>(d_ws);
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, queue, (int64_t)1);
   if (d_target) hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)ceil_div(V, 64)), dim3(64), 0, st, d_loss, (int64_t)V);
-  const int grid = (int)std::min<int64_t>(total_tiles, (int64_t)device_cu_count() * 8);
+  const int grid = (int)std::min<int64_t>(ceil_div(total_tiles, kFwdWaves), (int64_t)device_cu_count() * 8);
   const steepgs_opts& o = *opts;
   timer_begin(STEEPGS_TIMER_RENDER_FWD, st);
   if (o.tile_w == 16 && o.tile_h == 16)

@@ -234,11 +234,12 @@ __global__ void k_depth_keys(const steepgs_splat* __restrict__ splats, const uin
   vals[r] = (uint32_t)r;
 }
 
-struct LoadTilesSorted {
-  const uint32_t* tiles;
-  const uint32_t* order;
-  SG_DEV uint32_t operator()(int64_t s) const { return tiles[order[s]]; }
-};
+// tile counts in depth order (one gather, so the scan reads contiguously)
+__global__ void k_gather_counts(const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ order, int64_t m,
+                                uint32_t* __restrict__ out) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < m) out[s] = tiles[order[s]];
+}
 
 __global__ void k_instance_total(const uint64_t* __restrict__ total, uint64_t capacity,
                                  uint64_t* __restrict__ d_num, int32_t* __restrict__ d_status, uint64_t* cap_out) {
@@ -419,9 +420,11 @@ extern "C" steepgs_status steepgs_sort(const steepgs_splat* d_splats, const uint
                                err);
   if (err != hipSuccess) return STEEPGS_ERR_HIP;
   const uint32_t* order = where ? w.dvB : w.dvA;
+  uint32_t* counts = where ? w.dkB : w.dkA;  // the sorted depth keys are no longer needed
   // 2. instance offsets in depth order; K and the capacity check
-  err = exclusive_scan<LoadTilesSorted, uint64_t, uint64_t>(LoadTilesSorted{d_tiles_touched, order}, m, w.offs,
-                                                           w.partials64, st);
+  hipLaunchKernelGGL(k_gather_counts, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, d_tiles_touched, order, m,
+                     counts);
+  err = exclusive_scan<LoadU32, uint64_t, uint64_t>(LoadU32{counts}, m, w.offs, w.partials64, st);
   if (err != hipSuccess) return STEEPGS_ERR_HIP;
   uint64_t* total = w.partials64 + scan_partials_count(m);
   hipLaunchKernelGGL(k_instance_total, dim3(1), dim3(1), 0, st, total, capacity, d_num_instances, d_status,

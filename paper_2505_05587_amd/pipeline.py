@@ -156,7 +156,7 @@ class Rasterizer:
         """grads [F, n] and S [6, n] accumulate (+=)."""
         g2d = None
         if keep_grad2d:
-            self.grad2d = _grow(self.grad2d, 9 * self.cams.V * self.n, torch.float32, self.dev)
+            self.grad2d = _grow(self.grad2d, 12 * self.cams.V * self.n, torch.float32, self.dev)
             g2d = self.grad2d
         L.steepgs_render_bwd_split(params, self.n, self.sh_degree, self.cams.dev, self.cams.V, self.cams.opts,
                                    self.splats, self.tiles, self.vals, self.ranges, self.cams.total_tiles,

@@ -33,7 +33,8 @@ def run_gpu(params, sh_degree, cams, opts, target=None, backward=True, want_keys
             out["grads"] = grads.cpu().numpy().astype(np.float64)
             out["S6"] = S.cpu().numpy().astype(np.float64)
             if keep_grad2d:
-                out["grad2d"] = ras.grad2d[: 9 * cams.V * P.shape[1]].view(9, -1).cpu().numpy()
+                slots = ras.grad2d[: 12 * cams.V * P.shape[1]].view(-1, 12)
+                out["grad2d"] = slots[:, :9].t().contiguous().cpu().numpy()  # [9][V*n]
     torch.cuda.synchronize()
     return out
 

@@ -70,6 +70,11 @@ def test_bad_arguments_rejected_on_host():
     sel = L.SplitSelect(None, 1.0, 0.0, 1 << 40)  # budget beyond 32 bits
     assert lib.steepgs_densify(fake, 10, 0, fake, 1.0, 0.01, 0.0, C.byref(sel), fake, 20, fake, None, None, None,
                                fake, fake, 1 << 20, None) == L.ERR_INVALID_ARG
+    assert lib.steepgs_adam_step(None, None, None, None, 10, 0, None, None, None, None) == L.ERR_INVALID_ARG
+    bad = L.make_adam_opts([1e-3] * 6, beta1=1.0)
+    assert lib.steepgs_adam_step(fake, fake, fake, fake, 10, 0, C.byref(bad), fake, None, None) == L.ERR_INVALID_ARG
+    assert lib.steepgs_split_remap(fake, 1, 10, fake, fake, 20, None, 0, None) == L.ERR_WORKSPACE
+    assert lib.steepgs_split_remap(fake, -1, 10, fake, fake, 20, None, 0, None) == L.ERR_INVALID_ARG
     assert lib.steepgs_status_string(2) == b"output capacity exceeded"
 
 

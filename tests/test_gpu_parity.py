@@ -80,6 +80,27 @@ def test_forward_backward(oracle, kind, mode):
     assert_S_close(g["S6"], ref["S"], gamb)
 
 
+@pytest.mark.parametrize("kind", ["multiview", "sh3_pinhole"])
+def test_pair_gradients_2d(oracle, kind):
+    # the raster backward's per-(view, Gaussian) gradients w.r.t. the projected
+    # mean, conic, opacity and colour, before the projection backward
+    P, deg, cams, target = scene_small(kind)
+    opts = scenes.opts("3dgs")
+    print(f"\n[case] 2D pair gradients kind={kind}", flush=True)
+    g = run_gpu(P, deg, cams, opts, target=target, keep_grad2d=True)
+    ref = oracle.forward_backward(P, deg, cams, opts, target, per_view=True)
+    n = P.shape[1]
+    amb = np.tile(ref["gauss_ambig"], cams.V)
+    got = g["grad2d"].T.astype(np.float64)  # [V*n][9]
+    want = ref["g2d"]
+    for name, sl in {"mean": slice(0, 2), "conic": slice(2, 5), "opacity": slice(5, 6), "rgb": slice(6, 9)}.items():
+        d = np.linalg.norm(got[:, sl] - want[:, sl], axis=1)
+        r = np.linalg.norm(want[:, sl], axis=1)
+        bad = ~amb & (d > 1e-3 * r + 1e-6 * r.max())
+        assert not bad.any(), f"{name}: {bad.sum()} of {len(r)} records out of tolerance"
+    assert got.shape == (cams.V * n, 9)
+
+
 def test_densify_matches_oracle(oracle):
     rng = np.random.default_rng(7)
     n = 20000

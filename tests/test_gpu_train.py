@@ -1,0 +1,93 @@
+"""GPU parity of the Algorithm 1 training loop, following the device's own
+trajectory: at every gradient step the oracle recomputes the gradient and
+the splitting matrix from the device's parameters, applies Adam to the
+device's gradient and moments, and the accumulators S and G are checked
+against the oracle's sums; at the densification step the split set, the
+offspring and the remapped Adam moments are checked against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2505_05587_amd import scenes
+from paper_2505_05587_amd.pipeline import CameraBatch
+from paper_2505_05587_amd.train import Schedule, SteepGSTrainer
+from tests.gpu_common import assert_group_close, s6_to_mats
+
+pytestmark = pytest.mark.gpu
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("eps_grad,budget", [(0.0, 0), (0.0, 25), (5e-4, 0)])
+def test_training_loop_follows_oracle(oracle, eps_grad, budget):
+    s = scenes.plain_small()
+    opts = scenes.opts("3dgs")
+    dev = torch.device("cuda", 0)
+    print(f"\n[case] training loop eps_grad={eps_grad} budget={budget}", flush=True)
+    tr = SteepGSTrainer(torch.from_numpy(s.params).to(dev), s.sh_degree, CameraBatch(s.cams, opts, dev),
+                        torch.from_numpy(s.target).to(dev), eps=0.01, eps_grad=eps_grad, budget=budget,
+                        schedule=Schedule(densify_from=8, densify_every=4, densify_until=8))
+    lr6 = tr.lr
+    S_ref = np.zeros((9, s.n))
+    S_scale = np.zeros(s.n)  # sum over steps of |S_t| (the accumulated sum may cancel)
+    G_ref = np.zeros((3, s.n))
+    amb_any = np.zeros(s.n, bool)
+    t_adam = 0
+    for t in range(1, 8):
+        theta = _np(tr.params)
+        m0, v0 = _np(tr.m), _np(tr.v)
+        if t == tr.schedule.accumulate_from():
+            S_ref[:] = 0
+            S_scale[:] = 0
+            G_ref[:] = 0
+            amb_any[:] = False
+        tr.iterate()
+        torch.cuda.synchronize()
+        t_adam += 1
+        # the step's gradient against the oracle at the device's parameters
+        ref = oracle.forward_backward(theta.astype(np.float32), s.sh_degree, s.cams, opts, s.target)
+        amb = ref["gauss_ambig"]
+        g = _np(tr.grads)
+        assert_group_close(g, ref["grads"], amb, what=f"step {t}")
+        S_ref += ref["S"]
+        S_scale += np.linalg.norm(ref["S"], axis=0)
+        G_ref += g[0:3]
+        amb_any |= amb
+        # Adam on the device's own gradient and moments
+        p_ref, m_ref, v_ref = oracle.adam_step(theta, g, m0, v0, t_adam, lr6)
+        step = np.abs(p_ref - theta)
+        np.testing.assert_allclose(_np(tr.params), p_ref, rtol=0, atol=1e-6 * np.abs(theta).max() + 1e-3 * step.max())
+        np.testing.assert_allclose(_np(tr.m), m_ref, rtol=1e-5, atol=1e-9 * np.abs(m_ref).max())
+        np.testing.assert_allclose(_np(tr.v), v_ref, rtol=1e-5, atol=1e-12 * np.abs(v_ref).max())
+    # accumulators over the window
+    k = tr.acc_steps
+    assert k == 7 - tr.schedule.accumulate_from() + 1
+    Mg, Mr = s6_to_mats(_np(tr.S)), S_ref.T.reshape(-1, 3, 3)
+    d = np.linalg.norm((Mg - Mr).reshape(s.n, -1), axis=1)
+    assert not (~amb_any & (d > 1e-3 * S_scale + 1e-6 * S_scale.max())).any()
+    np.testing.assert_allclose(_np(tr.G), G_ref, rtol=1e-5, atol=1e-7 * np.abs(G_ref).max())
+    # the densification iteration
+    S9 = np.stack([_np(tr.S)[[0, 1, 2]], _np(tr.S)[[1, 3, 4]], _np(tr.S)[[2, 4, 5]]]).reshape(9, s.n)
+    G32 = tr.G.cpu().numpy()
+    m_old, v_old = _np(tr.m), _np(tr.v)
+    theta = tr.params.cpu().numpy()
+    out = tr.iterate()
+    torch.cuda.synchronize()
+    assert out is not None and tr.history and tr.history[-1].accumulated_steps == k
+    dref = oracle.densify(theta, s.sh_degree, S9, 1.0 / k, 0.01, -1e-6, G=G32 if eps_grad > 0 else None,
+                          g_scale=1.0 / k, eps_grad=eps_grad, budget=budget)
+    split = out["split"].cpu().numpy().astype(bool)
+    Sn = np.linalg.norm(S9, axis=0) / k
+    sure = np.abs(dref["lambda_min"] + 1e-6) > 1e-4 * Sn
+    if budget and dref["split"].sum() == budget:
+        thr = np.sort(dref["lambda_min"][dref["split"]])[-1]
+        sure &= np.abs(dref["lambda_min"] - thr) > 1e-5 * Sn
+        assert split.sum() == budget
+    np.testing.assert_array_equal(split[sure], dref["split"][sure])
+    assert tr.n == s.n + split.sum()
+    np.testing.assert_array_equal(_np(tr.m), oracle.split_remap(m_old, split))
+    np.testing.assert_array_equal(_np(tr.v), oracle.split_remap(v_old, split))
+    # the accumulators restart on the new layout
+    assert tr.S.shape == (6, tr.n) and float(tr.S.abs().sum()) == 0.0 and tr.acc_steps == 0

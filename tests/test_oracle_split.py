@@ -213,3 +213,47 @@ def test_paper_constants_fixture():
     c = json.load(open(os.path.join(GOLDEN, "paper_constants.json")))
     assert c["eps_split"]["value"] == -1e-6
     assert c["offspring_weight"]["value"] == 0.5 and c["offspring_count"]["value"] == 2
+
+
+def test_adam_reference_against_torch_and_first_step(oracle):
+    # the oracle's Adam against torch.optim.Adam (a separate implementation,
+    # float64 on the CPU), and the textbook first step: |update| = lr where
+    # |g| >> eps
+    import torch
+    rng = np.random.default_rng(56)
+    F, n = 23, 40
+    lr6 = (1.6e-4, 5e-3, 1e-3, 2.5e-2, 2.5e-3, 1.25e-4)
+    p0 = rng.normal(size=(F, n))
+    p, m, v = p0.copy(), np.zeros((F, n)), np.zeros((F, n))
+    lr_rows = oracle._lr_rows(F, lr6)
+    # one torch optimizer per parameter row, each with that row's learning rate
+    opts = [torch.optim.Adam([torch.nn.Parameter(torch.tensor(p0[r], dtype=torch.float64))], lr=float(lr_rows[r]),
+                             betas=(0.9, 0.999), eps=1e-15) for r in range(F)]
+    rows = [o.param_groups[0]["params"][0] for o in opts]
+    for t in range(1, 6):
+        g = rng.normal(size=(F, n)) * np.exp(rng.normal(0, 2, size=(F, 1)))
+        p, m, v = oracle.adam_step(p, g, m, v, t, lr6)
+        for r in range(F):
+            rows[r].grad = torch.tensor(g[r], dtype=torch.float64)
+            opts[r].step()
+        ref = np.stack([x.detach().numpy() for x in rows])
+        np.testing.assert_allclose(p, ref, rtol=1e-12, atol=1e-15)
+        if t == 1:
+            np.testing.assert_allclose(np.abs(p - p0), np.broadcast_to(lr_rows[:, None], p.shape), rtol=1e-9)
+
+
+def test_split_remap_layout(oracle):
+    rng = np.random.default_rng(57)
+    n = 50
+    state = rng.normal(size=(4, n))
+    split = rng.random(n) < 0.3
+    out = oracle.split_remap(state, split)
+    assert out.shape == (4, n + split.sum())
+    o = 0
+    for i in range(n):
+        if split[i]:
+            assert (out[:, o] == 0).all() and (out[:, o + 1] == 0).all()
+            o += 2
+        else:
+            np.testing.assert_array_equal(out[:, o], state[:, i])
+            o += 1
