@@ -36,6 +36,16 @@ inline bool opts_ok(const steepgs_opts* o) {
 // compute units of the current device (cached per device id)
 int device_cu_count();
 
+// Grid for a grid-stride kernel over `items` work items of `per_block` each:
+// enough workgroups to fill every CU several times over, never more than the
+// items need.  Short-lived waves are limited by the rate at which the
+// hardware launches them, so element-wise kernels loop instead.
+inline unsigned stride_grid(int64_t items, int per_block) {
+  const int64_t need = (items + per_block - 1) / per_block;
+  const int64_t cap = (int64_t)device_cu_count() * 16;
+  return (unsigned)(need < 1 ? 1 : (need < cap ? need : cap));
+}
+
 // optional launch timing (see steepgs_set_kernel_timer)
 struct KernelTimer {
   hipEvent_t starts[1024];

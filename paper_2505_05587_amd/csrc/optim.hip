@@ -23,20 +23,21 @@ __global__ void __launch_bounds__(256) k_adam(float* __restrict__ p, const float
                                               float* __restrict__ m, float* __restrict__ v, int64_t n, int F,
                                               steepgs_adam_opts o, const int64_t* __restrict__ step,
                                               float* __restrict__ G) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)F * n) return;
-  const int row = (int)(e / n);
-  if (G && row < 3) G[e] += g[e];  // Algorithm 1's accumulated position gradient
   const double t = (double)*step;
   const float bc1 = (float)(1.0 - pow((double)o.beta1, t));
-  const float bc2 = (float)(1.0 - pow((double)o.beta2, t));
-  const float gi = g[e];
-  const float mi = o.beta1 * m[e] + (1.f - o.beta1) * gi;
-  const float vi = o.beta2 * v[e] + (1.f - o.beta2) * gi * gi;
-  m[e] = mi;
-  v[e] = vi;
-  const float denom = sqrtf(vi) / sqrtf(bc2) + o.eps;
-  p[e] -= (o.lr[adam_group(row)] / bc1) * (mi / denom);
+  const float sbc2 = sqrtf((float)(1.0 - pow((double)o.beta2, t)));
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)F * n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int row = (int)(e / n);
+    const float gi = g[e];
+    if (G && row < 3) G[e] += gi;  // Algorithm 1's accumulated position gradient
+    const float mi = o.beta1 * m[e] + (1.f - o.beta1) * gi;
+    const float vi = o.beta2 * v[e] + (1.f - o.beta2) * gi * gi;
+    m[e] = mi;
+    v[e] = vi;
+    const float denom = sqrtf(vi) / sbc2 + o.eps;
+    p[e] -= (o.lr[adam_group(row)] / bc1) * (mi / denom);
+  }
 }
 
 struct LoadSplit {
@@ -76,7 +77,7 @@ extern "C" steepgs_status steepgs_adam_step(float* d_params, const float* d_grad
   if (n > 0) {
     if (!d_params || !d_grads || !d_m || !d_v) return STEEPGS_ERR_INVALID_ARG;
     const int F = STEEPGS_NUM_PARAMS(sh_degree);
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)ceil_div((int64_t)F * n, 256)), dim3(256), 0, st, d_params, d_grads,
+    hipLaunchKernelGGL(k_adam, dim3(stride_grid((int64_t)F * n, 256)), dim3(256), 0, st, d_params, d_grads,
                        d_m, d_v, n, F, *opts, d_step, d_G);
   }
   SG_TRY_LAUNCH();

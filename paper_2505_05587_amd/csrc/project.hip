@@ -3,6 +3,7 @@
 // views, so the parameters are read from HBM once per batch, not once per
 // view.
 #include "projection.h"
+#include "rectwalk.h"
 
 namespace sg {
 
@@ -71,57 +72,43 @@ __global__ void __launch_bounds__(kProjThreads) k_project(const float* __restric
 
 // Exact footprint tile count of every record: a tile counts when its box of
 // pixel centres meets the cut-off ellipse (tile_hit, the test the instance
-// emission applies).  Each wavefront takes 64 consecutive records and its
-// lanes walk the records' rectangles together (rectangle tile j of the group
-// goes to lane j mod 64; the owner is found by a binary search over the
-// prefix of the areas), so large rectangles do not serialise on one lane.
-// A record none of whose tiles meets the ellipse gets 0 (culled).
+// emission applies).  Each wavefront takes 64 consecutive records and walks
+// their rectangles together (rect_walk), so large rectangles do not serialise
+// on one lane.  A record none of whose tiles meets the ellipse gets 0
+// (culled).
 __global__ void __launch_bounds__(256) k_count_tiles(const steepgs_splat* __restrict__ splats,
                                                      uint32_t* __restrict__ tiles, int64_t m, steepgs_opts opt) {
+  __shared__ RectWalkLds s_walk[4];
   __shared__ uint32_t s_cnt[256];
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int64_t s0 = (int64_t)blockIdx.x * 256 + (tid - lane);
-  const int64_t r = s0 + lane;
-  uint32_t x0 = 0, y0 = 0, wdt = 1, area = 0;
-  float mx = 0.f, my = 0.f, ca = 0.f, cb = 0.f, cc = 0.f;
-  if (r < m && tiles[r]) {
-    const steepgs_splat sp = splats[r];
-    x0 = sp.rect_lo & 0xFFFF;
-    y0 = sp.rect_lo >> 16;
-    wdt = (sp.rect_hi & 0xFFFF) - x0 + 1;
-    area = wdt * ((sp.rect_hi >> 16) - y0 + 1);
-    mx = sp.mean_x;
-    my = sp.mean_y;
-    ca = sp.conic_a;
-    cb = sp.conic_b;
-    cc = sp.conic_c;
-  }
-  s_cnt[tid] = 0u;
-  uint32_t aoff = area;
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t t = __shfl_up(aoff, d, 64);
-    if (lane >= d) aoff += t;
-  }
-  const uint32_t atotal = __shfl(aoff, 63, 64);
-  aoff -= area;
-  __syncthreads();
-  for (uint32_t j0 = 0; j0 < atotal; j0 += 64) {
-    const uint32_t j = j0 + (uint32_t)lane;
-    int lo = 0, hi = 63;  // largest lane with aoff <= j (empty rectangles share their successor's prefix)
-    for (int step = 0; step < 6; ++step) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (__shfl(aoff, mid, 64) <= j) lo = mid; else hi = mid - 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint32_t* const cnt = s_cnt + (tid - lane);
+  for (int64_t base = (int64_t)blockIdx.x * 256; base < m; base += (int64_t)gridDim.x * 256) {
+    const int64_t r = base + tid;
+    uint32_t area = 0;
+    RectRec me = {};
+    me.wdt = 1;
+    if (r < m && tiles[r]) {
+      const steepgs_splat sp = splats[r];
+      const uint32_t x0 = sp.rect_lo & 0xFFFF, y0 = sp.rect_lo >> 16;
+      me.wdt = (sp.rect_hi & 0xFFFF) - x0 + 1;
+      area = me.wdt * ((sp.rect_hi >> 16) - y0 + 1);
+      me.mx = sp.mean_x;
+      me.my = sp.mean_y;
+      me.a = sp.conic_a;
+      me.b = sp.conic_b;
+      me.c = sp.conic_c;
+      me.xy0 = sp.rect_lo;
     }
-    // all cross-lane reads with every lane active
-    const uint32_t q = j - __shfl(aoff, lo, 64);
-    const uint32_t w = __shfl(wdt, lo, 64);
-    const int tx = (int)(__shfl(x0, lo, 64) + q % w), ty = (int)(__shfl(y0, lo, 64) + q / w);
-    const float omx = __shfl(mx, lo, 64), omy = __shfl(my, lo, 64);
-    const float oa = __shfl(ca, lo, 64), ob = __shfl(cb, lo, 64), oc = __shfl(cc, lo, 64);
-    if (j < atotal && tile_hit(omx, omy, oa, ob, oc, opt, tx, ty)) atomicAdd(&s_cnt[(tid - lane) + lo], 1u);
+    s_cnt[tid] = 0u;
+    rect_walk(s_walk[wave], lane, area, me, opt, [&](int owner, const RectRec&, int, int, bool hit) {
+      if (hit) atomicAdd(&cnt[owner], 1u);
+    });
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (r < m && area) tiles[r] = s_cnt[tid];
+    __builtin_amdgcn_wave_barrier();
   }
-  __syncthreads();
-  if (r < m && area) tiles[r] = s_cnt[tid];
 }
 
 }  // namespace sg

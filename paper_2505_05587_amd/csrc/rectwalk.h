@@ -1,0 +1,78 @@
+// Cooperative walk of one wavefront over the tile rectangles of 64
+// consecutive records, shared by the footprint tile count (projection) and the
+// instance emission (sort).
+//
+// The rectangles are laid end to end (exclusive prefix `aoff` of their
+// areas); chunk j0 .. j0+63 of that sequence goes to lanes 0..63.  The owner
+// of position p is the record whose run contains it: every record starting
+// inside the chunk writes its lane id into a 64-entry table at its start, a
+// ballot over the table marks the starts, and a lane takes the nearest start
+// at or below its position (or the record carried over from the previous
+// chunk).  The owner's record is read from the wavefront's LDS slice.  Each
+// position's tile is tested against the footprint ellipse (tile_hit) and
+// handed to the caller's visitor in order.
+#pragma once
+
+#include "projection.h"
+
+namespace sg {
+
+struct RectRec {
+  float mx, my, a, b;     // stored float32 mean and conic
+  float c;
+  uint32_t xy0;           // rect x0 | y0 << 16
+  uint32_t wdt;           // rect width in tiles
+  uint32_t aoff;          // start of the record's run
+  uint32_t tag0, tag1;    // caller data (record id, tile base / tiles_x ...)
+  uint32_t pad0, pad1;
+};
+
+// LDS per wavefront: RectRec[64] + int[64]
+struct RectWalkLds {
+  RectRec rec[64];
+  int at[64];
+};
+
+// `visit(owner_lane, rec, tx, ty, hit)` is called once per chunk with every
+// lane active (hit false beyond the last position).  Returns the total area.
+template <class Visit>
+SG_DEV uint32_t rect_walk(RectWalkLds& L, int lane, uint32_t area, const RectRec& mine, const steepgs_opts& opt,
+                          Visit&& visit) {
+  uint32_t incl = area;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t t = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += t;
+  }
+  const uint32_t atotal = __shfl(incl, 63, 64);
+  const uint32_t aoff = incl - area;
+  RectRec me = mine;
+  me.aoff = aoff;
+  L.rec[lane] = me;
+  int carry = 0;
+  for (uint32_t j0 = 0; j0 < atotal; j0 += 64) {
+    // starts of the records inside this chunk
+    L.at[lane] = -1;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (area > 0 && aoff >= j0 && aoff - j0 < 64u) L.at[aoff - j0] = lane;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint64_t starts = ballot(L.at[lane] >= 0);
+    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    const uint64_t below = starts & upto;
+    const int owner = below ? L.at[63 - __builtin_clzll(below)] : carry;
+    carry = __builtin_amdgcn_readlane(owner, 63);
+    const RectRec& R = L.rec[owner];
+    const uint32_t j = j0 + (uint32_t)lane;
+    const uint32_t q = j - R.aoff;
+    const int tx = (int)((R.xy0 & 0xFFFFu) + q % R.wdt), ty = (int)((R.xy0 >> 16) + q / R.wdt);
+    const bool hit = j < atotal && tile_hit(R.mx, R.my, R.a, R.b, R.c, opt, tx, ty);
+    visit(owner, R, tx, ty, hit);
+    __builtin_amdgcn_wave_barrier();
+  }
+  return atotal;
+}
+
+}  // namespace sg

@@ -33,7 +33,7 @@ constexpr int kBwdWaves = 4;    // wavefronts per workgroup, each on a tile of i
 constexpr int kG2dStride = 12;  // floats per record in the 2D-gradient buffer (9 used)
 
 template <int TW, int TH>
-__global__ void __launch_bounds__(64 * kBwdWaves) k_render_bwd(const steepgs_splat* __restrict__ splats,
+__global__ void __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_per_eu(5))) k_render_bwd(const steepgs_splat* __restrict__ splats,
                                                                const uint32_t* __restrict__ vals,
                                                                const uint32_t* __restrict__ ranges,
                                                                const steepgs_camera* __restrict__ cams, int V,
@@ -202,19 +202,19 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_render_bwd(const steepgs_spl
           gr = wave_sum_dpp(gr);
           gg = wave_sum_dpp(gg);
           gbl = wave_sum_dpp(gbl);
-          if (lane == 0) {
-            // one 48-byte slot per record: the nine updates share a cache line or two
-            float* const slot = g2d + (int64_t)__float_as_uint(E[j].y) * kG2dStride;
-            unsafeAtomicAdd(slot + 0, gmx);
-            unsafeAtomicAdd(slot + 1, gmy);
-            unsafeAtomicAdd(slot + 2, ga);
-            unsafeAtomicAdd(slot + 3, gb);
-            unsafeAtomicAdd(slot + 4, gc);
-            unsafeAtomicAdd(slot + 5, go);
-            unsafeAtomicAdd(slot + 6, gr);
-            unsafeAtomicAdd(slot + 7, gg);
-            unsafeAtomicAdd(slot + 8, gbl);
-          }
+          // one 48-byte slot per record: lane k adds quantity k, so the nine
+          // updates leave as one memory instruction into one or two cache lines
+          float v = gmx;
+          v = lane == 1 ? gmy : v;
+          v = lane == 2 ? ga : v;
+          v = lane == 3 ? gb : v;
+          v = lane == 4 ? gc : v;
+          v = lane == 5 ? go : v;
+          v = lane == 6 ? gr : v;
+          v = lane == 7 ? gg : v;
+          v = lane == 8 ? gbl : v;
+          float* const slot = g2d + (int64_t)__float_as_uint(E[j].y) * kG2dStride;
+          if (lane < 9) unsafeAtomicAdd(slot + lane, v);
         }
       }
     }
@@ -546,8 +546,7 @@ extern "C" steepgs_status steepgs_render_bwd_split(const float* d_params, int64_
   if (d_grad2d) g2d = d_grad2d;
   hipStream_t st = as_stream(stream);
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, reinterpret_cast<float*>(queue), (int64_t)1);
-  hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<int64_t>(ceil_div(kG2dStride * m, 256), 65536)), dim3(256), 0,
-                     st, g2d, kG2dStride * m);
+  hipLaunchKernelGGL(k_zero, dim3(stride_grid(kG2dStride * m, 256)), dim3(256), 0, st, g2d, kG2dStride * m);
   const int grid = (int)std::min<int64_t>(ceil_div(total_tiles, kBwdWaves), (int64_t)device_cu_count() * 8);
   const steepgs_opts& o = *opts;
   timer_begin(STEEPGS_TIMER_RENDER_BWD, st);

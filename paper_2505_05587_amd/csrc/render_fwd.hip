@@ -17,7 +17,7 @@ namespace sg {
 constexpr int kFwdWaves = 4;  // wavefronts per workgroup, each on a tile of its own
 
 template <int TW, int TH>
-__global__ void __launch_bounds__(64 * kFwdWaves) k_render_fwd(const steepgs_splat* __restrict__ splats,
+__global__ void __launch_bounds__(64 * kFwdWaves) __attribute__((amdgpu_waves_per_eu(7))) k_render_fwd(const steepgs_splat* __restrict__ splats,
                                                                const uint32_t* __restrict__ vals,
                                                                const uint32_t* __restrict__ ranges,
                                                                const steepgs_camera* __restrict__ cams, int V,

@@ -14,6 +14,7 @@
 // All kernels read the instance count K from device memory, so the whole
 // stage can be captured in a HIP graph.
 #include "projection.h"
+#include "rectwalk.h"
 #include "scan.h"
 
 namespace sg {
@@ -228,17 +229,17 @@ __global__ void k_set_u64(uint64_t* __restrict__ p, uint64_t v) { *p = v; }
 
 __global__ void k_depth_keys(const steepgs_splat* __restrict__ splats, const uint32_t* __restrict__ tiles,
                              int64_t m, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= m) return;
-  keys[r] = tiles[r] ? __float_as_uint(splats[r].depth) : 0xFFFFFFFFu;  // culled records sort last
-  vals[r] = (uint32_t)r;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x) {
+    keys[r] = tiles[r] ? __float_as_uint(splats[r].depth) : 0xFFFFFFFFu;  // culled records sort last
+    vals[r] = (uint32_t)r;
+  }
 }
 
 // tile counts in depth order (one gather, so the scan reads contiguously)
 __global__ void k_gather_counts(const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ order, int64_t m,
                                 uint32_t* __restrict__ out) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < m) out[s] = tiles[order[s]];
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < m; s += (int64_t)gridDim.x * blockDim.x)
+    out[s] = tiles[order[s]];
 }
 
 __global__ void k_instance_total(const uint64_t* __restrict__ total, uint64_t capacity,
@@ -251,82 +252,55 @@ __global__ void k_instance_total(const uint64_t* __restrict__ total, uint64_t ca
 
 // Each wavefront takes 64 consecutive records of the depth order; their
 // instances are contiguous in the output, so the lanes walk the group's tile
-// rectangles together (rectangle tile j goes to lane j mod 64, owner found by
-// a binary search over the group's area prefix), keep the tiles that meet the
-// footprint ellipse and append them in order.  Stores are coalesced.
+// rectangles together (rect_walk), keep the tiles that meet the footprint
+// ellipse and append them in order with ballots.  Stores are coalesced.
 __global__ void __launch_bounds__(256) k_emit(const steepgs_splat* __restrict__ splats,
                                               const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ order,
                                               const uint64_t* __restrict__ offs, int64_t m, int64_t n,
                                               const steepgs_camera* __restrict__ cams, steepgs_opts opt,
                                               const uint64_t* __restrict__ d_num, uint64_t capacity,
                                               uint32_t* __restrict__ tkeys, uint32_t* __restrict__ ivals) {
+  __shared__ RectWalkLds s_walk[4];
   if (*d_num > capacity) return;
-  const int lane = threadIdx.x & 63;
-  const int64_t s0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) - lane;  // first record of the group
-  if (s0 >= m) return;
-  const int64_t s = s0 + lane;
-  const bool valid = s < m;
-  uint32_t r = 0, x0 = 0, y0 = 0, wdt = 1, area = 0, tbase = 0, tx = 0;
-  float mx = 0.f, my = 0.f, ca = 0.f, cb = 0.f, cc = 0.f;
-  uint64_t off = 0;
-  if (valid) {
-    r = order[s];
-    off = offs[s];
-    if (tiles[r]) {
-      const steepgs_splat& sp = splats[r];
-      x0 = sp.rect_lo & 0xFFFF;
-      y0 = sp.rect_lo >> 16;
-      wdt = (sp.rect_hi & 0xFFFF) - x0 + 1;
-      area = wdt * ((sp.rect_hi >> 16) - y0 + 1);
-      mx = sp.mean_x;
-      my = sp.mean_y;
-      ca = sp.conic_a;
-      cb = sp.conic_b;
-      cc = sp.conic_c;
-      const int v = (int)(r / (uint64_t)n);
-      tbase = (uint32_t)cams[v].tile_offset;
-      tx = (uint32_t)cams[v].tiles_x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t lt = lanemask_lt();
+  for (int64_t s0 = (int64_t)blockIdx.x * 256 + wave * 64; s0 < m; s0 += (int64_t)gridDim.x * 256) {
+    // s0: first record of this wavefront's group (wave-uniform)
+    const int64_t s = s0 + lane;
+    uint32_t area = 0;
+    RectRec me = {};
+    me.wdt = 1;
+    if (s < m) {
+      const uint32_t r = order[s];
+      if (tiles[r]) {
+        const steepgs_splat sp = splats[r];
+        const uint32_t x0 = sp.rect_lo & 0xFFFF, y0 = sp.rect_lo >> 16;
+        me.wdt = (sp.rect_hi & 0xFFFF) - x0 + 1;
+        area = me.wdt * ((sp.rect_hi >> 16) - y0 + 1);
+        me.mx = sp.mean_x;
+        me.my = sp.mean_y;
+        me.a = sp.conic_a;
+        me.b = sp.conic_b;
+        me.c = sp.conic_c;
+        me.xy0 = sp.rect_lo;
+        const int v = (int)(r / (uint64_t)n);
+        me.tag0 = r;
+        me.tag1 = (uint32_t)cams[v].tile_offset;
+        me.pad0 = (uint32_t)cams[v].tiles_x;
+      }
     }
-  }
-  // the group's instances are contiguous from the first record's offset; the
-  // lanes walk the group's rectangles (exclusive prefix `aoff` of their areas),
-  // test each tile against the footprint and append the hits in order
-  uint32_t aoff = area;
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t t = __shfl_up(aoff, d, 64);
-    if (lane >= d) aoff += t;
-  }
-  const uint32_t atotal = __shfl(aoff, 63, 64);
-  aoff -= area;
-  const int lastl = (int)min<int64_t>(63, m - 1 - s0);
-  uint64_t cursor = __shfl(off, 0, 64);
-  for (uint32_t j0 = 0; j0 < atotal; j0 += 64) {
-    const uint32_t j = j0 + (uint32_t)lane;
-    // owner: the largest lane L with aoff[L] <= j (empty rectangles share
-    // their successor's prefix, so the owner is never empty)
-    int lo = 0, hi = lastl;
-    for (int step = 0; step < 6; ++step) {
-      const int mid = (lo + hi + 1) >> 1;
-      const uint32_t om = __shfl(aoff, mid, 64);
-      if (om <= j) lo = mid; else hi = mid - 1;
-    }
-    const uint32_t q = j - __shfl(aoff, lo, 64);
-    const uint32_t w = __shfl(wdt, lo, 64);
-    const int ttx = (int)(__shfl(x0, lo, 64) + q % w), tty = (int)(__shfl(y0, lo, 64) + q / w);
-    // the owner's record is fetched with every lane active: a cross-lane read
-    // from a lane that is switched off does not return that lane's value
-    const float omx = __shfl(mx, lo, 64), omy = __shfl(my, lo, 64);
-    const float oa = __shfl(ca, lo, 64), ob = __shfl(cb, lo, 64), oc = __shfl(cc, lo, 64);
-    const bool hit = j < atotal && tile_hit(omx, omy, oa, ob, oc, opt, ttx, tty);
-    const uint64_t hits = ballot(hit);
-    const uint32_t tile = __shfl(tbase, lo, 64) + (uint32_t)tty * __shfl(tx, lo, 64) + (uint32_t)ttx;
-    const uint32_t rec = __shfl(r, lo, 64);
-    if (hit) {
-      const uint64_t o = cursor + (uint64_t)__popcll(hits & lanemask_lt());
-      tkeys[o] = tile;
-      ivals[o] = rec;
-    }
-    cursor += (uint64_t)__popcll(hits);
+    // the group's instances are contiguous from the first record's offset
+    uint64_t cursor = offs[s0];
+    rect_walk(s_walk[wave], lane, area, me, opt, [&](int, const RectRec& R, int tx, int ty, bool hit) {
+      const uint64_t hits = ballot(hit);
+      if (hit) {
+        const uint64_t o = cursor + (uint64_t)__popcll(hits & lt);
+        tkeys[o] = R.tag1 + (uint32_t)ty * R.pad0 + (uint32_t)tx;
+        ivals[o] = R.tag0;
+      }
+      cursor += (uint64_t)__popcll(hits);
+    });
+    __builtin_amdgcn_wave_barrier();
   }
 }
 

@@ -29,7 +29,9 @@ def test_training_loop_follows_oracle(oracle, eps_grad, budget):
     tr = SteepGSTrainer(torch.from_numpy(s.params).to(dev), s.sh_degree, CameraBatch(s.cams, opts, dev),
                         torch.from_numpy(s.target).to(dev), eps=0.01, eps_grad=eps_grad, budget=budget,
                         schedule=Schedule(densify_from=8, densify_every=4, densify_until=8))
-    lr6 = tr.lr
+    # the library takes its hyper-parameters as float32: the oracle uses the same values
+    lr6 = [float(np.float32(x)) for x in tr.lr]
+    b1, b2, eps_adam = float(np.float32(0.9)), float(np.float32(0.999)), float(np.float32(1e-15))
     S_ref = np.zeros((9, s.n))
     S_scale = np.zeros(s.n)  # sum over steps of |S_t| (the accumulated sum may cancel)
     G_ref = np.zeros((3, s.n))
@@ -56,7 +58,7 @@ def test_training_loop_follows_oracle(oracle, eps_grad, budget):
         G_ref += g[0:3]
         amb_any |= amb
         # Adam on the device's own gradient and moments
-        p_ref, m_ref, v_ref = oracle.adam_step(theta, g, m0, v0, t_adam, lr6)
+        p_ref, m_ref, v_ref = oracle.adam_step(theta, g, m0, v0, t_adam, lr6, b1, b2, eps_adam)
         step = np.abs(p_ref - theta)
         np.testing.assert_allclose(_np(tr.params), p_ref, rtol=0, atol=1e-6 * np.abs(theta).max() + 1e-3 * step.max())
         np.testing.assert_allclose(_np(tr.m), m_ref, rtol=1e-5, atol=1e-9 * np.abs(m_ref).max())
