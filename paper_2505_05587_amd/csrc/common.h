@@ -161,6 +161,56 @@ SG_DEV uint64_t uniform_u64(uint64_t v) {
   return ((uint64_t)hi << 32) | (uint64_t)lo;
 }
 
+// Sums of nine per-lane values over the wavefront, delivered one per lane:
+// a transposed butterfly (lane halves swapped with v_permlane32_swap and
+// v_permlane16_swap, then DPP row rotations and quad permutations), about a
+// quarter of the instructions of nine separate reductions.  On return the
+// total of value k sits in lane reduce9_lane(k): 0, 32, 16, 48, 8, 40, 24,
+// 56, 4 for k = 0..8; other lanes hold duplicates or zeros.
+SG_DEV float sg_swap_add32(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+SG_DEV float sg_swap_add16(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+#define SG_DPP_ALL(v, ctrl) \
+  __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, (v)), (ctrl), 0xf, 0xf, false))
+SG_DEV float reduce9(const float v[9]) {
+  const int lane = __lane_id();
+  // distance 32: pairs of values share a register, one per 32-lane half
+  float s0 = v[0], s1 = v[2], s2 = v[4], s3 = v[6], s4 = v[8];
+  s0 = sg_swap_add32(s0, v[1]);
+  s1 = sg_swap_add32(s1, v[3]);
+  s2 = sg_swap_add32(s2, v[5]);
+  s3 = sg_swap_add32(s3, v[7]);
+  s4 = sg_swap_add32(s4, 0.f);
+  // distance 16: four values per register, one per 16-lane row
+  const float t0 = sg_swap_add16(s0, s1);
+  const float t1 = sg_swap_add16(s2, s3);
+  const float t2 = sg_swap_add16(s4, 0.f);
+  // every cross-lane read below runs with all lanes active, before any
+  // per-lane selection (a DPP read from a switched-off lane yields 0)
+  // distance 8: two values per row (row_ror:8 pairs lanes l and l^8)
+  const float e0 = SG_DPP_ALL(t0, 0x128), e1 = SG_DPP_ALL(t1, 0x128), e2 = SG_DPP_ALL(t2, 0x128);
+  const float u0 = (lane & 8) ? t1 + e1 : t0 + e0;
+  const float u1 = t2 + e2;
+  // distance 4 within each group of 8 (row_ror:12 reads lane l+4, row_ror:4 lane l-4)
+  const float f0 = SG_DPP_ALL(u0, 0x12C), f1 = SG_DPP_ALL(u1, 0x124);
+  float w = (lane & 4) ? u1 + f1 : u0 + f0;
+  // distances 2 and 1 within quads
+  w += SG_DPP_ALL(w, 0x4e);  // quad_perm [2,3,0,1]
+  w += SG_DPP_ALL(w, 0xb1);  // quad_perm [1,0,3,2]
+  return w;
+}
+// value index held by `lane` after reduce9, or -1
+SG_DEV int reduce9_index(int lane) {
+  if (lane == 4) return 8;
+  if (lane & 7) return -1;
+  return ((lane >> 5) & 1) | (((lane >> 4) & 1) << 1) | (((lane >> 3) & 1) << 2);
+}
+
 // largest value over the wave
 SG_DEV uint32_t wave_max_u32(uint32_t v) {
 #pragma unroll

@@ -52,6 +52,7 @@ __global__ void __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_pe
   __shared__ float2 s_e[kBwdWaves][64];  // blue, record id (bits)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lx = lane & 7, ly = lane >> 3;
+  const int red_idx = reduce9_index(lane);
   float4* const A = s_a[wave];
   float4* const Cq = s_c[wave];
   float2* const E = s_e[wave];
@@ -193,28 +194,12 @@ __global__ void __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_pe
           }
         }
         if (ballot(any)) {
-          gmx = wave_sum_dpp(gmx);
-          gmy = wave_sum_dpp(gmy);
-          ga = wave_sum_dpp(ga);
-          gb = wave_sum_dpp(gb);
-          gc = wave_sum_dpp(gc);
-          go = wave_sum_dpp(go);
-          gr = wave_sum_dpp(gr);
-          gg = wave_sum_dpp(gg);
-          gbl = wave_sum_dpp(gbl);
-          // one 48-byte slot per record: lane k adds quantity k, so the nine
-          // updates leave as one memory instruction into one or two cache lines
-          float v = gmx;
-          v = lane == 1 ? gmy : v;
-          v = lane == 2 ? ga : v;
-          v = lane == 3 ? gb : v;
-          v = lane == 4 ? gc : v;
-          v = lane == 5 ? go : v;
-          v = lane == 6 ? gr : v;
-          v = lane == 7 ? gg : v;
-          v = lane == 8 ? gbl : v;
+          // per-entry sums over the tile, one quantity per lane, and one
+          // nine-lane atomic into the record's 48-byte slot
+          const float part[9] = {gmx, gmy, ga, gb, gc, go, gr, gg, gbl};
+          const float tot = reduce9(part);
           float* const slot = g2d + (int64_t)__float_as_uint(E[j].y) * kG2dStride;
-          if (lane < 9) unsafeAtomicAdd(slot + lane, v);
+          if (red_idx >= 0) unsafeAtomicAdd(slot + red_idx, tot);
         }
       }
     }

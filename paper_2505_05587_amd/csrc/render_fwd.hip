@@ -105,28 +105,28 @@ __global__ void __launch_bounds__(64 * kFwdWaves) __attribute__((amdgpu_waves_pe
         any_q &= any_q - 1ull;
         const float4 a = A[j];
         const float4 cq = Cq[j];
+        const float blue = Bl[j];
+        const uint32_t pos1 = b0 - begin + (uint32_t)j + 1u;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
           if (!((qm[q] >> j) & 1ull)) continue;  // wave-uniform
-          if (done[q]) continue;
+          // per pixel: predicated, no divergent branch
           const float dx = (float)(tx0 + (q % QX) * 8 + lx) - a.x;
           const float dy = (float)(ty0 + (q / QX) * 8 + ly) - a.y;
           const float power = splat_power(dx, dy, a.z, a.w, cq.x);
-          if (power < cut) continue;  // outside the footprint
           const float alpha = fminf(opt.alpha_max, cq.y * __expf(power));
-          if (alpha < opt.alpha_min) continue;
+          bool c = !done[q] && power >= cut && alpha >= opt.alpha_min;
           const float Tn = T[q] * (1.f - alpha);
-          if (Tn < opt.t_min) {
-            done[q] = true;
-            continue;
-          }
+          const bool stop = c && Tn < opt.t_min;  // would cross the cut-off: excluded, pixel done
+          done[q] = done[q] || stop;
+          c = c && !stop;
           const float w = alpha * T[q];
-          C[q][0] += cq.z * w;
-          C[q][1] += cq.w * w;
-          C[q][2] += Bl[j] * w;
-          T[q] = Tn;
-          last[q] = b0 - begin + (uint32_t)j + 1u;
-          ++used[q];
+          C[q][0] = c ? C[q][0] + cq.z * w : C[q][0];
+          C[q][1] = c ? C[q][1] + cq.w * w : C[q][1];
+          C[q][2] = c ? C[q][2] + blue * w : C[q][2];
+          T[q] = c ? Tn : T[q];
+          last[q] = c ? pos1 : last[q];
+          used[q] += c ? 1u : 0u;
         }
       }
     }
