@@ -146,7 +146,17 @@ SG_DEV bool tile_hit_fp64(float mx, float my, float a, float b, float c, const s
 // estimate minus that bound is above it the tile is missed; otherwise the
 // fp64 rule decides.  Mean inside the box: hit (the same comparisons either
 // way).  Result identical to tile_hit_fp64.
+SG_DEV bool tile_hit_rcp(float mx, float my, float a, float b, float c, float ia, float ic, const steepgs_opts& opt,
+                         int tx, int ty);
 SG_DEV bool tile_hit(float mx, float my, float a, float b, float c, const steepgs_opts& opt, int tx, int ty) {
+  return tile_hit_rcp(mx, my, a, b, c, 1.f / a, 1.f / c, opt, tx, ty);
+}
+
+// tile_hit with the reciprocals 1/a and 1/c supplied (the edge minimiser is
+// a product instead of a division; its rounding enters the edge value only
+// at second order, inside the certified bound)
+SG_DEV bool tile_hit_rcp(float mx, float my, float a, float b, float c, float ia, float ic, const steepgs_opts& opt,
+                         int tx, int ty) {
   const float x0 = (float)(tx * opt.tile_w), x1 = (float)(tx * opt.tile_w + opt.tile_w - 1);
   const float y0 = (float)(ty * opt.tile_h), y1 = (float)(ty * opt.tile_h + opt.tile_h - 1);
   if (mx >= x0 && mx <= x1 && my >= y0 && my <= y1) return true;
@@ -160,7 +170,7 @@ SG_DEV bool tile_hit(float mx, float my, float a, float b, float c, const steepg
     const float fixed = xe ? ((e == 0 ? x0 : x1) - mx) : ((e == 2 ? y0 : y1) - my);
     const float lo = xe ? (y0 - my) : (x0 - mx), hi = xe ? (y1 - my) : (x1 - mx);
     const float pf = xe ? a : c, pv = xe ? c : a;  // coefficient of fixed^2 and of free^2
-    float fr = -(b * fixed) / pv;
+    float fr = -(b * fixed) * (xe ? ic : ia);
     fr = fminf(fmaxf(fr, lo), hi);
     const float q = pf * fixed * fixed + 2.f * b * fixed * fr + pv * fr * fr;
     const float M = pf * fixed * fixed + 2.f * fabsf(b * fixed * fr) + pv * fr * fr;

@@ -25,9 +25,11 @@ struct RectRec {
   uint32_t aoff;          // start of the record's run
   uint32_t tag0, tag1;    // caller data (record id, tile base / tiles_x ...)
   uint32_t pad0, pad1;
+  float ia, ic;           // 1/a, 1/c (filled by rect_walk)
+  float iw, pad2;         // 1/width (filled by rect_walk)
 };
 
-// LDS per wavefront: RectRec[64] + int[64]
+// LDS per wavefront: RectRec[64] + int[64]  (RectRec is 64 bytes)
 struct RectWalkLds {
   RectRec rec[64];
   int at[64];
@@ -48,6 +50,9 @@ SG_DEV uint32_t rect_walk(RectWalkLds& L, int lane, uint32_t area, const RectRec
   const uint32_t aoff = incl - area;
   RectRec me = mine;
   me.aoff = aoff;
+  me.ia = 1.f / me.a;
+  me.ic = 1.f / me.c;
+  me.iw = 1.f / (float)me.wdt;
   L.rec[lane] = me;
   int carry = 0;
   for (uint32_t j0 = 0; j0 < atotal; j0 += 64) {
@@ -67,8 +72,25 @@ SG_DEV uint32_t rect_walk(RectWalkLds& L, int lane, uint32_t area, const RectRec
     const RectRec& R = L.rec[owner];
     const uint32_t j = j0 + (uint32_t)lane;
     const uint32_t q = j - R.aoff;
-    const int tx = (int)((R.xy0 & 0xFFFFu) + q % R.wdt), ty = (int)((R.xy0 >> 16) + q / R.wdt);
-    const bool hit = j < atotal && tile_hit(R.mx, R.my, R.a, R.b, R.c, opt, tx, ty);
+    // q / width without an integer division: the float quotient is off by at
+    // most one for q < 2^24, fixed up exactly below (larger q: integer path)
+    int row, col;
+    if (q < (1u << 24)) {
+      row = (int)((float)q * R.iw);
+      col = (int)q - row * (int)R.wdt;
+      if (col < 0) {
+        --row;
+        col += (int)R.wdt;
+      } else if (col >= (int)R.wdt) {
+        ++row;
+        col -= (int)R.wdt;
+      }
+    } else {
+      row = (int)(q / R.wdt);
+      col = (int)(q % R.wdt);
+    }
+    const int tx = (int)(R.xy0 & 0xFFFFu) + col, ty = (int)(R.xy0 >> 16) + row;
+    const bool hit = j < atotal && tile_hit_rcp(R.mx, R.my, R.a, R.b, R.c, R.ia, R.ic, opt, tx, ty);
     visit(owner, R, tx, ty, hit);
     __builtin_amdgcn_wave_barrier();
   }
