@@ -112,7 +112,9 @@ SG_DEV int view_of_tile(const steepgs_camera* __restrict__ cams, int V, int tile
 // The forward and backward raster kernels evaluate it with this one routine
 // so that both see bit-identical values.
 SG_DEV float splat_power(float dx, float dy, float a, float b, float c) {
-  return -0.5f * (a * dx * dx + c * dy * dy) - b * dx * dy;
+  // explicit fused operations: one fixed rounding sequence in every kernel
+  const float quad = __builtin_fmaf(dx, a * dx, dy * (c * dy));
+  return __builtin_fmaf(quad, -0.5f, -(dy * (b * dx)));
 }
 
 // A pixel takes part in a Gaussian's blend only inside its footprint,

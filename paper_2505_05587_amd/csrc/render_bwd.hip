@@ -171,10 +171,11 @@ __global__ void __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_pe
             blue_loaded = true;
           }
           any = true;
-          const float om = 1.f - alpha;
-          T[q] = T[q] / om;  // transmittance in front of this entry
+          // transmittance in front of this entry, T_i = T_{i+1} / (1 - alpha_i),
+          // with the hardware reciprocal (within 1 ulp)
+          const float inv_om = __builtin_amdgcn_rcpf(1.f - alpha);
+          T[q] *= inv_om;
           const float w = alpha * T[q];
-          const float inv_om = 1.f / om;
           const float g = dC[q][0] * (cq.z * T[q] - R[q][0] * inv_om) + dC[q][1] * (cq.w * T[q] - R[q][1] * inv_om) +
                           dC[q][2] * (blue * T[q] - R[q][2] * inv_om);
           R[q][0] += cq.z * w;

@@ -21,7 +21,7 @@ namespace sg {
 
 // ---------------------------------------------------------------------------
 // Stable LSD radix sort of (u32 key, u32 value) pairs; the element count is
-// read from device memory.  A fixed grid of kRsGrid workgroups cuts the input
+// read from device memory.  A fixed grid of workgroups cuts the input
 // into contiguous ranges; each workgroup walks its range in tiles of kRsTile
 // elements.  Per tile, every wavefront ranks its contiguous 1024 elements
 // with ballots (a wave-wide match on the digit) against wave-private digit
@@ -34,11 +34,19 @@ constexpr int kRsWaves = kRsThreads / 64;
 constexpr int kRsItems = 16;                     // elements per lane per tile
 constexpr int kRsTile = kRsThreads * kRsItems;   // 4096 elements per tile
 constexpr int kRsWaveSpan = 64 * kRsItems;       // contiguous elements per wavefront
-constexpr int kRsGrid = 1024;
+constexpr int kRsGrid = 1024;  // largest grid (sizes the digit-count table)
 constexpr int kRsMaxBits = 9;
 
+// LDS of one scatter workgroup; the grid is as many workgroups as are
+// resident together (160 KiB of LDS per CU), capped at kRsGrid, so that no
+// second partial round of workgroups follows the first
+constexpr int rs_scatter_lds(int bits) {
+  return 8 * kRsTile + 4 * kRsWaves * (1 << bits) + 12 * (1 << bits) + 4 * (kRsWaves + 1);
+}
+
 SG_DEV void rs_range(uint64_t count, uint64_t& begin, uint64_t& end) {
-  uint64_t per = (count + kRsGrid - 1) / kRsGrid;
+  const uint64_t G = gridDim.x;
+  uint64_t per = (count + G - 1) / G;
   per = (per + kRsTile - 1) / kRsTile * kRsTile;
   begin = (uint64_t)blockIdx.x * per;
   end = begin + per;
@@ -70,7 +78,7 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_hist(const uint32_t* __restri
   for (int d = tid; d < DIG; d += kRsThreads) {
     uint32_t t = 0;
     for (int w = 0; w < kRsWaves; ++w) t += h[w][d];
-    hist[(size_t)d * kRsGrid + blockIdx.x] = t;
+    hist[(size_t)d * gridDim.x + blockIdx.x] = t;
   }
 }
 
@@ -91,7 +99,7 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const uint32_t* __res
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const uint32_t mask = (1u << bits) - 1u;
   const uint64_t lt = lanemask_lt();
-  for (int d = tid; d < DIG; d += kRsThreads) s_run[d] = hist_scanned[(size_t)d * kRsGrid + blockIdx.x];
+  for (int d = tid; d < DIG; d += kRsThreads) s_run[d] = hist_scanned[(size_t)d * gridDim.x + blockIdx.x];
   uint64_t b, e;
   rs_range(rs_count(d_count, d_cap), b, e);
   for (uint64_t base = b; base < e; base += kRsTile) {
@@ -180,11 +188,15 @@ template <int BITS>
 static void radix_pass(uint32_t* kin, uint32_t* vin, uint32_t* kout, uint32_t* vout, const uint64_t* d_count,
                        const uint64_t* d_cap, int shift, int b, uint32_t* hist, uint32_t* hist_partials,
                        hipStream_t st, hipError_t& err) {
-  hipLaunchKernelGGL(k_rs_hist<BITS>, dim3(kRsGrid), dim3(kRsThreads), 0, st, kin, d_count, d_cap, shift, b, hist);
-  const int64_t hn = (int64_t)(1 << BITS) * kRsGrid;
+  static_assert(rs_scatter_lds(BITS) <= 65536, "scatter LDS");
+  int grid = device_cu_count() * (160 * 1024 / rs_scatter_lds(BITS));
+  if (grid > kRsGrid) grid = kRsGrid;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(k_rs_hist<BITS>, dim3(grid), dim3(kRsThreads), 0, st, kin, d_count, d_cap, shift, b, hist);
+  const int64_t hn = (int64_t)(1 << BITS) * grid;
   err = exclusive_scan<LoadU32, uint32_t, uint32_t>(LoadU32{hist}, hn, hist, hist_partials, st);
   if (err != hipSuccess) return;
-  hipLaunchKernelGGL(k_rs_scatter<BITS>, dim3(kRsGrid), dim3(kRsThreads), 0, st, kin, vin, kout, vout, d_count, d_cap,
+  hipLaunchKernelGGL(k_rs_scatter<BITS>, dim3(grid), dim3(kRsThreads), 0, st, kin, vin, kout, vout, d_count, d_cap,
                      shift, b, hist);
 }
 
@@ -255,7 +267,7 @@ __global__ void k_instance_total(const uint64_t* __restrict__ total, uint64_t ca
 // rectangles together (rect_walk), keep the tiles that meet the footprint
 // ellipse and append them in order with ballots.  Stores are coalesced.
 __global__ void __launch_bounds__(256) k_emit(const steepgs_splat* __restrict__ splats,
-                                              const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ order,
+                                              const uint32_t* __restrict__ counts, const uint32_t* __restrict__ order,
                                               const uint64_t* __restrict__ offs, int64_t m, int64_t n,
                                               const steepgs_camera* __restrict__ cams, steepgs_opts opt,
                                               const uint64_t* __restrict__ d_num, uint64_t capacity,
@@ -270,24 +282,23 @@ __global__ void __launch_bounds__(256) k_emit(const steepgs_splat* __restrict__ 
     uint32_t area = 0;
     RectRec me = {};
     me.wdt = 1;
-    if (s < m) {
+    // counts: tile counts already gathered into depth order (contiguous)
+    if (s < m && counts[s]) {
       const uint32_t r = order[s];
-      if (tiles[r]) {
-        const steepgs_splat sp = splats[r];
-        const uint32_t x0 = sp.rect_lo & 0xFFFF, y0 = sp.rect_lo >> 16;
-        me.wdt = (sp.rect_hi & 0xFFFF) - x0 + 1;
-        area = me.wdt * ((sp.rect_hi >> 16) - y0 + 1);
-        me.mx = sp.mean_x;
-        me.my = sp.mean_y;
-        me.a = sp.conic_a;
-        me.b = sp.conic_b;
-        me.c = sp.conic_c;
-        me.xy0 = sp.rect_lo;
-        const int v = (int)(r / (uint64_t)n);
-        me.tag0 = r;
-        me.tag1 = (uint32_t)cams[v].tile_offset;
-        me.pad0 = (uint32_t)cams[v].tiles_x;
-      }
+      const steepgs_splat sp = splats[r];
+      const uint32_t x0 = sp.rect_lo & 0xFFFF, y0 = sp.rect_lo >> 16;
+      me.wdt = (sp.rect_hi & 0xFFFF) - x0 + 1;
+      area = me.wdt * ((sp.rect_hi >> 16) - y0 + 1);
+      me.mx = sp.mean_x;
+      me.my = sp.mean_y;
+      me.a = sp.conic_a;
+      me.b = sp.conic_b;
+      me.c = sp.conic_c;
+      me.xy0 = sp.rect_lo;
+      const int v = (int)(r / (uint64_t)n);
+      me.tag0 = r;
+      me.tag1 = (uint32_t)cams[v].tile_offset;
+      me.pad0 = (uint32_t)cams[v].tiles_x;
     }
     // the group's instances are contiguous from the first record's offset
     uint64_t cursor = offs[s0];
@@ -411,7 +422,7 @@ extern "C" steepgs_status steepgs_sort(const steepgs_splat* d_splats, const uint
   uint32_t* ek = start ? w.tkB : w.tkA;
   uint32_t* ev = start ? w.ivB : d_vals;
   if (capacity > 0) {
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, d_splats, d_tiles_touched, order,
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, d_splats, counts, order,
                        w.offs, m, n, d_cams, *opts, d_num_instances, capacity, ek, ev);
     int fin = radix_sort_pairs(w.tkA, d_vals, w.tkB, w.ivB, start, d_num_instances, w.counters + 1, tile_bits, w.hist,
                                w.hist_partials, st, err);
