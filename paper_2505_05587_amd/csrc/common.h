@@ -142,6 +142,49 @@ SG_DEV void cutoff_extent(float a, float b, float c, float o, const steepgs_opts
   ey = sqrtf(t * a / det) * 1.01f + 0.0625f;
 }
 
+// Threshold of the same region for an ellipse test, d^T A d <= this value,
+// widened like the extents (2% and 1e-3); negative when no pixel can
+// contribute.
+SG_DEV float cutoff_level(float o, const steepgs_opts& opt) {
+  float t = opt.radius_sigmas * opt.radius_sigmas;
+  if (opt.alpha_min > 0.f) {
+    if (!(o > opt.alpha_min)) return -1.f;
+    t = fminf(t, 2.f * __logf(o / opt.alpha_min));
+  }
+  return t * 1.0201f + 1e-3f;
+}
+
+// Conservative test of a pixel block [x0, x1] x [y0, y1] (pixel centres at
+// integer coordinates) against the ellipse d^T A d <= t: false only when the
+// minimum of the quadratic over the block exceeds t by more than 1e-4 of its
+// terms' magnitude (far above the rounding of the blend's fp32 evaluation).
+// With the mean outside the block the minimum lies on a face seen from the
+// mean -- at most one face across x and one across y -- and on a face it is
+// the stationary point along the face, clamped to the face's extent.
+// ia, ic: reciprocals of a and c (their rounding moves the evaluated point
+// along the face, which changes the value only at second order).
+SG_DEV bool block_reach(float mx, float my, float a, float b, float c, float ia, float ic, float t, float x0, float y0,
+                        float x1, float y1) {
+  const bool fxl = mx < x0, fxh = mx > x1, fyl = my < y0, fyh = my > y1;
+  if (!(fxl || fxh || fyl || fyh)) return true;
+  float qmin = INFINITY;
+  if (fxl || fxh) {
+    const float f = (fxl ? x0 : x1) - mx;
+    const float r = fminf(fmaxf(-(b * f) * ic, y0 - my), y1 - my);
+    const float q = a * f * f + 2.f * b * f * r + c * r * r;
+    const float M = a * f * f + 2.f * fabsf(b * f * r) + c * r * r;
+    qmin = fminf(qmin, q - 1e-4f * M);
+  }
+  if (fyl || fyh) {
+    const float f = (fyl ? y0 : y1) - my;
+    const float r = fminf(fmaxf(-(b * f) * ia, x0 - mx), x1 - mx);
+    const float q = c * f * f + 2.f * b * f * r + a * r * r;
+    const float M = c * f * f + 2.f * fabsf(b * f * r) + a * r * r;
+    qmin = fminf(qmin, q - 1e-4f * M);
+  }
+  return qmin <= t;
+}
+
 // wave-wide sum with DPP row operations; the total is returned to every lane
 #define SG_DPP(v, ctrl, rmask) \
   __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, (v)), (ctrl), (rmask), 0xf, false))

@@ -7,7 +7,8 @@
 // own routine and the transmittance T_i = T_{i+1} / (1 - alpha_i) from the
 // stored final value (no per-pixel lists are stored).  The walk starts at the
 // tile's last contributor; the lane that stages an entry tests its
-// alpha >= alpha_min box against every quadrant, and a quadrant whose pixels
+// alpha >= alpha_min region (bounding box, then the ellipse) against every
+// quadrant, and a quadrant whose pixels
 // the entry cannot reach (or whose last contributor lies before it) is
 // skipped for the whole wave.  Per contributor it forms
 //   g = dL/dalpha_i = sum_c dL/dC_c (c_i T_i - R_c / (1 - alpha_i)),
@@ -109,7 +110,8 @@ __global__ void __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_pe
     for (int b_end = count; b_end > 0; b_end -= 64) {
       const int b_start = b_end > 64 ? b_end - 64 : 0;
       // stage one batch of 64 entries in the wave's LDS slice; the loading
-      // lane tests the entry's cut-off box against every quadrant
+      // lane tests the entry's cut-off region (bounding box, then the
+      // ellipse) against every quadrant
       const bool have = b_start + lane < b_end;
       bool hitq[NQ];
 #pragma unroll
@@ -120,6 +122,8 @@ __global__ void __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_pe
         const steepgs_splat sp = splats[id];
         float ex, ey;
         cutoff_extent(sp.conic_a, sp.conic_b, sp.conic_c, sp.opacity, opt, ex, ey);
+        const float lev = cutoff_level(sp.opacity, opt);
+        const float ia = __builtin_amdgcn_rcpf(sp.conic_a), ic = __builtin_amdgcn_rcpf(sp.conic_c);
         A[lane] = make_float4(sp.mean_x, sp.mean_y, sp.conic_a, sp.conic_b);
         Cq[lane] = make_float4(sp.conic_c, sp.opacity, sp.rgb[0], sp.rgb[1]);
         E[lane] = make_float2(sp.rgb[2], __uint_as_float(id));
@@ -127,7 +131,9 @@ __global__ void __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_pe
         for (int q = 0; q < NQ; ++q) {
           const float x0 = (float)(tx0 + (q % QX) * 8), y0 = (float)(ty0 + (q / QX) * 8);
           hitq[q] = (sp.mean_x + ex >= x0) && (sp.mean_x - ex <= x0 + 7.f) && (sp.mean_y + ey >= y0) &&
-                    (sp.mean_y - ey <= y0 + 7.f);
+                    (sp.mean_y - ey <= y0 + 7.f) &&
+                    block_reach(sp.mean_x, sp.mean_y, sp.conic_a, sp.conic_b, sp.conic_c, ia, ic, lev, x0, y0,
+                                x0 + 7.f, y0 + 7.f);
         }
       }
       uint64_t qm[NQ], any_q = 0;

@@ -5,11 +5,12 @@
 // global atomic queue when done, so tiles with long instance lists do not
 // stall the rest of the grid; each lane owns one pixel in every 8x8 quadrant
 // of the tile.  The tile's instances are staged through the wavefront's LDS
-// slice in batches of 64; the loading lane tests the entry's cut-off box
-// against every quadrant, and a quadrant the entry cannot reach (or whose
-// pixels are all saturated) is skipped for the whole wavefront.  The
-// wavefront leaves the tile when every pixel's transmittance has hit the
-// cut-off.
+// slice in batches of 64; the loading lane tests the entry's cut-off region
+// (alpha >= alpha_min inside the footprint: its bounding box, then the
+// ellipse itself) against every quadrant, and a quadrant the entry cannot
+// reach (or whose pixels are all saturated) is skipped for the whole
+// wavefront.  The wavefront leaves the tile when every pixel's
+// transmittance has hit the cut-off.
 #include "common.h"
 
 namespace sg {
@@ -70,7 +71,8 @@ __global__ void __launch_bounds__(64 * kFwdWaves) __attribute__((amdgpu_waves_pe
       alive = __builtin_amdgcn_readfirstlane(alive);
       if (!alive) break;
       // stage one batch of 64 entries in the wave's LDS slice; the loading
-      // lane tests the entry's cut-off box against every quadrant
+      // lane tests the entry's cut-off region (bounding box, then the
+      // ellipse) against every quadrant
       const uint32_t idx = b0 + (uint32_t)lane;
       bool hitq[NQ];
 #pragma unroll
@@ -80,6 +82,8 @@ __global__ void __launch_bounds__(64 * kFwdWaves) __attribute__((amdgpu_waves_pe
         const steepgs_splat sp = splats[vals[idx]];
         float ex, ey;
         cutoff_extent(sp.conic_a, sp.conic_b, sp.conic_c, sp.opacity, opt, ex, ey);
+        const float lev = cutoff_level(sp.opacity, opt);
+        const float ia = __builtin_amdgcn_rcpf(sp.conic_a), ic = __builtin_amdgcn_rcpf(sp.conic_c);
         A[lane] = make_float4(sp.mean_x, sp.mean_y, sp.conic_a, sp.conic_b);
         Cq[lane] = make_float4(sp.conic_c, sp.opacity, sp.rgb[0], sp.rgb[1]);
         Bl[lane] = sp.rgb[2];
@@ -87,7 +91,9 @@ __global__ void __launch_bounds__(64 * kFwdWaves) __attribute__((amdgpu_waves_pe
         for (int q = 0; q < NQ; ++q) {
           const float x0 = (float)(tx0 + (q % QX) * 8), y0 = (float)(ty0 + (q / QX) * 8);
           hitq[q] = (sp.mean_x + ex >= x0) && (sp.mean_x - ex <= x0 + 7.f) && (sp.mean_y + ey >= y0) &&
-                    (sp.mean_y - ey <= y0 + 7.f);
+                    (sp.mean_y - ey <= y0 + 7.f) &&
+                    block_reach(sp.mean_x, sp.mean_y, sp.conic_a, sp.conic_b, sp.conic_c, ia, ic, lev, x0, y0,
+                                x0 + 7.f, y0 + 7.f);
         }
       }
       uint64_t qm[NQ], any_q = 0;
