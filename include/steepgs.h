@@ -23,7 +23,8 @@
  *   - Every pointer named d_* is device memory owned by the caller.  The
  *     library never allocates, frees or keeps device memory between calls;
  *     scratch space comes from the caller's workspace (see
- *     steepgs_workspace_size).  Host pointers are read during the call only.
+ *     steepgs_workspace_size; 4-byte alignment suffices, the library aligns
+ *     its own sub-buffers).  Host pointers are read during the call only.
  *   - `stream` is a hipStream_t.  Calls only enqueue work on it: no host
  *     synchronisation, no device allocation and no memset nodes, so every call
  *     may be captured into a HIP graph.  Calls that overlap on one workspace

@@ -71,7 +71,10 @@ inline void timer_end(int which, hipStream_t st) {
 struct Carver {
   char* base;
   size_t used = 0;
-  explicit Carver(void* p) : base(static_cast<char*>(p)) {}
+  // the base is rounded up to 256 bytes (every workspace size has 256 bytes of
+  // slack for it), so a caller's workspace needs no particular alignment
+  explicit Carver(void* p)
+      : base(p ? reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(p) + 255) & ~uintptr_t(255)) : nullptr) {}
   template <class T>
   T* take(size_t count) {
     used = (used + 255) & ~size_t(255);

@@ -37,12 +37,6 @@ constexpr int kRsWaveSpan = 64 * kRsItems;       // contiguous elements per wave
 constexpr int kRsGrid = 1024;  // largest grid (sizes the digit-count table)
 constexpr int kRsMaxBits = 9;
 
-// LDS of one scatter workgroup; the grid is as many workgroups as are
-// resident together (160 KiB of LDS per CU), capped at kRsGrid, so that no
-// second partial round of workgroups follows the first
-constexpr int rs_scatter_lds(int bits) {
-  return 8 * kRsTile + 4 * kRsWaves * (1 << bits) + 12 * (1 << bits) + 4 * (kRsWaves + 1);
-}
 
 SG_DEV void rs_range(uint64_t count, uint64_t& begin, uint64_t& end) {
   const uint64_t G = gridDim.x;
@@ -73,7 +67,18 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_hist(const uint32_t* __restri
   uint64_t b, e;
   rs_range(rs_count(d_count, d_cap), b, e);
   const uint32_t mask = (1u << bits) - 1u;
-  for (uint64_t i = b + tid; i < e; i += kRsThreads) atomicAdd(&h[wave][(keys[i] >> shift) & mask], 1u);
+  for (uint64_t base = b; base < e; base += kRsTile) {
+    // all of the tile's loads first, then the counter updates
+    uint32_t k[kRsItems];
+#pragma unroll
+    for (int it = 0; it < kRsItems; ++it) {
+      const uint64_t i = base + (uint64_t)(it * kRsThreads + tid);
+      k[it] = i < e ? keys[i] : 0u;
+    }
+#pragma unroll
+    for (int it = 0; it < kRsItems; ++it)
+      if (base + (uint64_t)(it * kRsThreads + tid) < e) atomicAdd(&h[wave][(k[it] >> shift) & mask], 1u);
+  }
   __syncthreads();
   for (int d = tid; d < DIG; d += kRsThreads) {
     uint32_t t = 0;
@@ -106,15 +111,23 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const uint32_t* __res
     const int n_tile = (int)((e - base) < (uint64_t)kRsTile ? (e - base) : (uint64_t)kRsTile);
     for (int d = lane; d < DIG; d += 64) s_wc[wave][d] = 0u;
     uint32_t k[kRsItems], v[kRsItems], rank[kRsItems];
+    // all of the tile's loads first (kept in flight together), then the ranks
 #pragma unroll
     for (int it = 0; it < kRsItems; ++it) {
       const int idx = wave * kRsWaveSpan + it * 64 + lane;
       const bool valid = idx < n_tile;
       k[it] = valid ? keys_in[base + idx] : 0u;
       v[it] = valid ? vals_in[base + idx] : 0u;
+    }
+#pragma unroll
+    for (int it = 0; it < kRsItems; ++it) {
+      const int idx = wave * kRsWaveSpan + it * 64 + lane;
+      const bool valid = idx < n_tile;
       const uint32_t d = (k[it] >> shift) & mask;
       uint64_t peers = ballot(valid);
-      for (int q = 0; q < bits; ++q) {
+      // digit bits at and above `bits` are zero (masked): their ballots agree
+#pragma unroll
+      for (int q = 0; q < BITS; ++q) {
         const bool bit = (d >> q) & 1u;
         const uint64_t m = ballot(bit);
         peers &= bit ? m : ~m;
@@ -166,12 +179,16 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const uint32_t* __res
       }
     }
     __syncthreads();
-    for (int i = tid; i < n_tile; i += kRsThreads) {
-      const uint32_t key = s_key[i];
-      const uint32_t d = (key >> shift) & mask;
-      const uint32_t g = s_run[d] + ((uint32_t)i - s_start[d]);
-      keys_out[g] = key;
-      vals_out[g] = s_val[i];
+#pragma unroll
+    for (int it = 0; it < kRsItems; ++it) {
+      const int i = it * kRsThreads + tid;
+      if (i < n_tile) {
+        const uint32_t key = s_key[i];
+        const uint32_t d = (key >> shift) & mask;
+        const uint32_t g = s_run[d] + ((uint32_t)i - s_start[d]);
+        keys_out[g] = key;
+        vals_out[g] = s_val[i];
+      }
     }
     __syncthreads();
     for (int d = tid; d < DIG; d += kRsThreads) s_run[d] += s_cnt[d];
@@ -188,10 +205,16 @@ template <int BITS>
 static void radix_pass(uint32_t* kin, uint32_t* vin, uint32_t* kout, uint32_t* vout, const uint64_t* d_count,
                        const uint64_t* d_cap, int shift, int b, uint32_t* hist, uint32_t* hist_partials,
                        hipStream_t st, hipError_t& err) {
-  static_assert(rs_scatter_lds(BITS) <= 65536, "scatter LDS");
-  int grid = device_cu_count() * (160 * 1024 / rs_scatter_lds(BITS));
+  // as many workgroups as are resident together (LDS and registers), capped
+  // at kRsGrid, so that no second partial round follows the first
+  static int per_cu = 0;  // same code object on every device
+  if (per_cu == 0) {
+    int r = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, k_rs_scatter<BITS>, kRsThreads, 0) != hipSuccess || r < 1) r = 1;
+    per_cu = r;
+  }
+  int grid = device_cu_count() * per_cu;
   if (grid > kRsGrid) grid = kRsGrid;
-  if (grid < 1) grid = 1;
   hipLaunchKernelGGL(k_rs_hist<BITS>, dim3(grid), dim3(kRsThreads), 0, st, kin, d_count, d_cap, shift, b, hist);
   const int64_t hn = (int64_t)(1 << BITS) * grid;
   err = exclusive_scan<LoadU32, uint32_t, uint32_t>(LoadU32{hist}, hn, hist, hist_partials, st);
@@ -315,14 +338,39 @@ __global__ void __launch_bounds__(256) k_emit(const steepgs_splat* __restrict__ 
   }
 }
 
+// per-tile [begin, end) of the sorted list: four consecutive entries per
+// thread (one 16-byte load) and their two neighbours
+constexpr int kRangesPer = 4;
 __global__ void k_ranges(const uint32_t* __restrict__ tkeys, const uint64_t* __restrict__ d_num, uint64_t capacity,
                          uint32_t* __restrict__ ranges) {
   const uint64_t K = *d_num;
   if (K > capacity) return;
-  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < K; s += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t t = tkeys[s];
-    if (s == 0 || tkeys[s - 1] != t) ranges[2 * (size_t)t] = (uint32_t)s;
-    if (s + 1 == K || tkeys[s + 1] != t) ranges[2 * (size_t)t + 1] = (uint32_t)(s + 1);
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * kRangesPer;
+  for (uint64_t s0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRangesPer; s0 < K; s0 += stride) {
+    uint32_t t[kRangesPer];
+    if (s0 + kRangesPer <= K) {
+      const uint4 q = *reinterpret_cast<const uint4*>(tkeys + s0);
+      t[0] = q.x;
+      t[1] = q.y;
+      t[2] = q.z;
+      t[3] = q.w;
+    } else {
+#pragma unroll
+      for (int j = 0; j < kRangesPer; ++j) t[j] = s0 + j < K ? tkeys[s0 + j] : 0u;
+    }
+    const bool has_prev = s0 > 0;
+    const uint32_t prev = has_prev ? tkeys[s0 - 1] : 0u;
+    const bool has_next = s0 + kRangesPer < K;
+    const uint32_t next = has_next ? tkeys[s0 + kRangesPer] : 0u;
+#pragma unroll
+    for (int j = 0; j < kRangesPer; ++j) {
+      const uint64_t s = s0 + j;
+      if (s >= K) break;
+      const bool first = j == 0 ? (!has_prev || prev != t[0]) : t[j - 1] != t[j];
+      const bool last = j == kRangesPer - 1 ? (!has_next || next != t[j]) : (s + 1 == K || t[j + 1] != t[j]);
+      if (first) ranges[2 * (size_t)t[j]] = (uint32_t)s;
+      if (last) ranges[2 * (size_t)t[j] + 1] = (uint32_t)(s + 1);
+    }
   }
 }
 
@@ -429,7 +477,8 @@ extern "C" steepgs_status steepgs_sort(const steepgs_splat* d_splats, const uint
     if (err != hipSuccess) return STEEPGS_ERR_HIP;
     if (fin != 0) return STEEPGS_ERR_HIP;  // cannot happen: start chosen so the result lands in d_vals
     // 4. per-tile ranges and the optional 64-bit keys
-    hipLaunchKernelGGL(k_ranges, dim3(2048), dim3(256), 0, st, w.tkA, d_num_instances, capacity, d_tile_ranges);
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)ceil_div((int64_t)capacity, 256 * kRangesPer)), dim3(256), 0, st, w.tkA,
+                       d_num_instances, capacity, d_tile_ranges);
     if (d_keys)
       hipLaunchKernelGGL(k_keys64, dim3(2048), dim3(256), 0, st, w.tkA, d_vals, d_splats, d_num_instances, capacity,
                          d_keys);
