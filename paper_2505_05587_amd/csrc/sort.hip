@@ -60,9 +60,14 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_hist(const uint32_t* __restri
                                                         const uint64_t* __restrict__ d_cap, int shift, int bits,
                                                         uint32_t* __restrict__ hist) {
   constexpr int DIG = 1 << BITS;
-  __shared__ uint32_t h[kRsWaves][DIG];
+  // several counter copies per wavefront (by lane), so that lanes holding
+  // equal digits -- common in clustered keys -- rarely update one address
+  constexpr int SUB = BITS <= 8 ? 8 : 4;
+  constexpr int COPIES = kRsWaves * SUB;
+  __shared__ uint32_t h[COPIES][DIG];
   const int tid = threadIdx.x, wave = tid >> 6;
-  for (int d = tid; d < kRsWaves * DIG; d += kRsThreads) (&h[0][0])[d] = 0u;
+  const int copy = wave * SUB + (tid & (SUB - 1));
+  for (int d = tid; d < COPIES * DIG; d += kRsThreads) (&h[0][0])[d] = 0u;
   __syncthreads();
   uint64_t b, e;
   rs_range(rs_count(d_count, d_cap), b, e);
@@ -77,12 +82,12 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_hist(const uint32_t* __restri
     }
 #pragma unroll
     for (int it = 0; it < kRsItems; ++it)
-      if (base + (uint64_t)(it * kRsThreads + tid) < e) atomicAdd(&h[wave][(k[it] >> shift) & mask], 1u);
+      if (base + (uint64_t)(it * kRsThreads + tid) < e) atomicAdd(&h[copy][(k[it] >> shift) & mask], 1u);
   }
   __syncthreads();
   for (int d = tid; d < DIG; d += kRsThreads) {
     uint32_t t = 0;
-    for (int w = 0; w < kRsWaves; ++w) t += h[w][d];
+    for (int w = 0; w < COPIES; ++w) t += h[w][d];
     hist[(size_t)d * gridDim.x + blockIdx.x] = t;
   }
 }
