@@ -17,7 +17,8 @@ namespace sg {
 
 constexpr int kFwdWaves = 4;  // wavefronts per workgroup, each on a tile of its own
 
-template <int TW, int TH>
+// COUNT: also count each pixel's contributors (the optional n_used output)
+template <int TW, int TH, bool COUNT>
 __global__ void __launch_bounds__(64 * kFwdWaves) __attribute__((amdgpu_waves_per_eu(7))) k_render_fwd(const steepgs_splat* __restrict__ splats,
                                                                const uint32_t* __restrict__ vals,
                                                                const uint32_t* __restrict__ ranges,
@@ -132,7 +133,7 @@ __global__ void __launch_bounds__(64 * kFwdWaves) __attribute__((amdgpu_waves_pe
           C[q][2] = c ? C[q][2] + blue * w : C[q][2];
           T[q] = c ? Tn : T[q];
           last[q] = c ? pos1 : last[q];
-          used[q] += c ? 1u : 0u;
+          if (COUNT) used[q] += c ? 1u : 0u;
         }
       }
     }
@@ -150,7 +151,7 @@ __global__ void __launch_bounds__(64 * kFwdWaves) __attribute__((amdgpu_waves_pe
         img[2 * plane] = o2;
         T_final[p] = T[q];
         n_contrib[p] = last[q];
-        if (n_used) n_used[p] = used[q];
+        if (COUNT) n_used[p] = used[q];
         if (target) {
           const float* tg = target + 3 * pix_off + (int64_t)py * W + px;
           err += fabsf(o0 - tg[0]) + fabsf(o1 - tg[plane]) + fabsf(o2 - tg[2 * plane]);
@@ -181,8 +182,12 @@ static void launch_fwd(int grid, hipStream_t st, const steepgs_splat* splats, co
                        const uint32_t* ranges, const steepgs_camera* cams, int V, const steepgs_opts& opt,
                        int total_tiles, const float* target, float* image, float* T_final, uint32_t* n_contrib,
                        uint32_t* n_used, float* loss, uint32_t* queue) {
-  hipLaunchKernelGGL((k_render_fwd<TW, TH>), dim3(grid), dim3(64 * kFwdWaves), 0, st, splats, vals, ranges, cams, V, opt,
-                     total_tiles, target, image, T_final, n_contrib, n_used, loss, queue);
+  if (n_used)
+    hipLaunchKernelGGL((k_render_fwd<TW, TH, true>), dim3(grid), dim3(64 * kFwdWaves), 0, st, splats, vals, ranges, cams,
+                       V, opt, total_tiles, target, image, T_final, n_contrib, n_used, loss, queue);
+  else
+    hipLaunchKernelGGL((k_render_fwd<TW, TH, false>), dim3(grid), dim3(64 * kFwdWaves), 0, st, splats, vals, ranges,
+                       cams, V, opt, total_tiles, target, image, T_final, n_contrib, n_used, loss, queue);
 }
 
 }  // namespace sg

@@ -36,10 +36,14 @@ SG_DEV T block_exclusive_scan(T x, T* lds /*[kScanThreads/64 + 1]*/, T& total) {
 template <class Load, class Acc>
 __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(Load in, int64_t N, Acc* __restrict__ partials) {
   __shared__ Acc lds[kScanThreads / 64 + 1];
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  // only the block's total is needed: strided (coalesced) reads, any order
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
   Acc s = 0;
-  for (int k = 0; k < kScanItems; ++k)
-    if (base + k < N) s += (Acc)in(base + k);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + (int64_t)k * kScanThreads;
+    if (i < N) s += (Acc)in(i);
+  }
   Acc total;
   block_exclusive_scan<Acc>(s, lds, total);
   if (threadIdx.x == 0) partials[blockIdx.x] = total;
@@ -66,24 +70,43 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_partials(Acc* __restrict_
   if (threadIdx.x == 0 && total_out) *total_out = total;
 }
 
+// Each wavefront scans a contiguous quarter of the block's elements in rounds
+// of 64 consecutive elements (coalesced loads and stores), carrying the
+// running sum from round to round; the block's partial and the totals of the
+// wavefronts before it give the starting offset.
 template <class Load, class Acc, class Out>
 __global__ void __launch_bounds__(kScanThreads) k_scan_final(Load in, int64_t N, const Acc* __restrict__ partials,
                                                                Out* __restrict__ out) {
-  __shared__ Acc lds[kScanThreads / 64 + 1];
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  constexpr int kWaves = kScanThreads / 64;
+  __shared__ Acc lds[kWaves];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)wave * (kScanTile / kWaves) + lane;
   Acc v[kScanItems];
   Acc s = 0;
+#pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    v[k] = (base + k < N) ? (Acc)in(base + k) : Acc(0);
+    const int64_t i = base + (int64_t)k * 64;
+    v[k] = i < N ? (Acc)in(i) : Acc(0);
     s += v[k];
   }
-  Acc total;
-  Acc run = block_exclusive_scan<Acc>(s, lds, total) + partials[blockIdx.x];
-  for (int k = 0; k < kScanItems; ++k)
-    if (base + k < N) {
-      out[base + k] = (Out)run;
-      run += v[k];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) lds[wave] = s;
+  __syncthreads();
+  Acc carry = partials[blockIdx.x];
+  for (int w = 0; w < wave; ++w) carry += lds[w];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    Acc inc = v[k];
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const Acc y = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += y;
     }
+    const int64_t i = base + (int64_t)k * 64;
+    if (i < N) out[i] = (Out)(carry + inc - v[k]);
+    carry += __shfl(inc, 63, 64);
+  }
 }
 
 inline size_t scan_partials_count(int64_t N) { return (size_t)ceil_div(N > 0 ? N : 1, kScanTile); }
