@@ -12,17 +12,20 @@
 // the entry cannot reach (or whose last contributor lies before it) is
 // skipped for the whole wave.  Per contributor it forms
 //   g = dL/dalpha_i = sum_c dL/dC_c (c_i T_i - R_c / (1 - alpha_i)),
-// R = colour of everything behind i (background included), and the
-// gradients w.r.t. the 2D mean, conic, opacity and colour.  A lane adds up
-// its pixels' contributions, the wavefront sums them over its lanes with DPP
-// row operations and issues one atomic per quantity and entry for the whole
-// tile.
+// R = colour of everything behind i (background included; a pixel carries
+// only the scalar dL/dC . R), and accumulates the opacity and colour
+// gradients and the moments m1 = sum g alpha d, m2 = sum g alpha d d^T
+// (d = pixel - mean, unclamped pixels): the 2D mean and conic gradients are
+// linear in them, dL/dmean = A m1 and dL/d(a, b, c) = -(m2_xx / 2, m2_xy,
+// m2_yy / 2).  A lane adds up its pixels' contributions, the wavefront sums
+// them over its lanes with DPP row operations and issues one atomic per
+// quantity and entry for the whole tile.
 //
 // Kernel 2 (one thread per Gaussian, all views): chain rule from the 2D
 // quantities to the 3D parameters, and the splitting matrix.  With
 // g(x) = dL/dalpha_i(x), the per-view sum
 //   sum_x g alpha (A d d^T A - A) = A M A - m0 A,
-//   M = sum_x g alpha d d^T = -2 dL/dA,  m0 = sum_x g alpha = o dL/do,
+//   M = sum_x g alpha d d^T = m2,  m0 = sum_x g alpha = o dL/do,
 // so the 2x2 matrix comes from the conic and opacity gradients the raster
 // backward already produced: S_i += P^T (A M A - m0 A) P at no per-pixel cost
 // (P = Jacobian of the projected mean w.r.t. p, App. C.4).
@@ -31,10 +34,14 @@
 namespace sg {
 
 constexpr int kBwdWaves = 4;    // wavefronts per workgroup, each on a tile of its own
-constexpr int kG2dStride = 12;  // floats per record in the 2D-gradient buffer (9 used)
+// floats per record in the 2D-gradient buffer: the raster backward leaves
+// (m1_x, m1_y, m2_xx, m2_xy, m2_yy, dL/do, dL/dr, dL/dg, dL/db) in entries
+// 0-8; when the buffer is the caller's, a last pass turns entries 0-4 into
+// dL/d(mean_x, mean_y, a, b, c)
+constexpr int kG2dStride = 12;
 
 template <int TW, int TH>
-__global__ void __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_per_eu(5))) k_render_bwd(const steepgs_splat* __restrict__ splats,
+__global__ void __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_per_eu(6))) k_render_bwd(const steepgs_splat* __restrict__ splats,
                                                                const uint32_t* __restrict__ vals,
                                                                const uint32_t* __restrict__ ranges,
                                                                const steepgs_camera* __restrict__ cams, int V,
@@ -73,8 +80,9 @@ __global__ void __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_pe
     const uint32_t begin = ranges[2 * tile];
     const int64_t plane = (int64_t)W * H;
     const float inv = 1.f / (3.f * (float)W * (float)H);
-    // per-pixel state of the lane's pixel in every quadrant
-    float T[NQ], dC[NQ][3], R[NQ][3];
+    // per-pixel state of the lane's pixel in every quadrant; D = dL/dC . R with
+    // R the colour of everything behind the current entry (background included)
+    float T[NQ], dC[NQ][3], D[NQ];
     uint32_t last[NQ], qlast[NQ];
     int count = 0;
 #pragma unroll
@@ -83,7 +91,7 @@ __global__ void __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_pe
       T[q] = 1.f;
       last[q] = 0;
       dC[q][0] = dC[q][1] = dC[q][2] = 0.f;
-      R[q][0] = R[q][1] = R[q][2] = 0.f;
+      D[q] = 0.f;
       if (px < W && py < H) {
         const int64_t pp = pix_off + (int64_t)py * W + px;
         const int64_t e = 3 * pix_off + (int64_t)py * W + px;
@@ -100,8 +108,7 @@ __global__ void __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_pe
             dC[q][ch] = (d > 0.f) ? inv : ((d < 0.f) ? -inv : 0.f);
           }
         }
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) R[q][ch] = T[q] * opt.bg[ch];
+        D[q] = T[q] * (dC[q][0] * opt.bg[0] + dC[q][1] * opt.bg[1] + dC[q][2] * opt.bg[2]);
       }
       // entries at or past a quadrant's last contributor need no work for it
       qlast[q] = (uint32_t)__builtin_amdgcn_readfirstlane(wave_max_u32(last[q]));
@@ -156,7 +163,9 @@ __global__ void __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_pe
         const float4 a = A[j];
         const float4 cq = Cq[j];
         const uint32_t pos = (uint32_t)(b_start + j);
-        float gmx = 0.f, gmy = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
+        // moments of g alpha d over the tile's pixels (the mean and conic
+        // gradients are linear in them), opacity and colour gradients
+        float mx = 0.f, my = 0.f, mxx = 0.f, mxy = 0.f, myy = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
         bool any = false;
         float blue = 0.f;
         bool blue_loaded = false;
@@ -182,28 +191,28 @@ __global__ void __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_pe
           const float inv_om = __builtin_amdgcn_rcpf(1.f - alpha);
           T[q] *= inv_om;
           const float w = alpha * T[q];
-          const float g = dC[q][0] * (cq.z * T[q] - R[q][0] * inv_om) + dC[q][1] * (cq.w * T[q] - R[q][1] * inv_om) +
-                          dC[q][2] * (blue * T[q] - R[q][2] * inv_om);
-          R[q][0] += cq.z * w;
-          R[q][1] += cq.w * w;
-          R[q][2] += blue * w;
+          // g = dL/dalpha_i = sum_c dL/dC_c (c_c T_i - R_c / (1 - alpha_i))
+          const float x = dC[q][0] * cq.z + dC[q][1] * cq.w + dC[q][2] * blue;
+          const float g = T[q] * x - D[q] * inv_om;
+          D[q] += x * w;
           gr += w * dC[q][0];
           gg += w * dC[q][1];
           gbl += w * dC[q][2];
           if (!clamped) {
             const float gaw = g * alpha;
-            gmx += gaw * (a.z * dx + a.w * dy);
-            gmy += gaw * (a.w * dx + cq.x * dy);
-            ga += -0.5f * gaw * dx * dx;
-            gb += -gaw * dx * dy;
-            gc += -0.5f * gaw * dy * dy;
+            const float tx = gaw * dx, ty = gaw * dy;
+            mx += tx;
+            my += ty;
+            mxx += tx * dx;
+            mxy += tx * dy;
+            myy += ty * dy;
             go += g * G;
           }
         }
         if (ballot(any)) {
           // per-entry sums over the tile, one quantity per lane, and one
           // nine-lane atomic into the record's 48-byte slot
-          const float part[9] = {gmx, gmy, ga, gb, gc, go, gr, gg, gbl};
+          const float part[9] = {mx, my, mxx, mxy, myy, go, gr, gg, gbl};
           const float tot = reduce9(part);
           float* const slot = g2d + (int64_t)__float_as_uint(E[j].y) * kG2dStride;
           if (red_idx >= 0) unsafeAtomicAdd(slot + red_idx, tot);
@@ -295,7 +304,7 @@ __global__ void __launch_bounds__(128) k_proj_bwd(const float* __restrict__ para
     float W[9];
     for (int k = 0; k < 9; ++k) W[k] = cam.R[k];
     const float fx = cam.fx, fy = cam.fy;
-    const float gmx = G9[0], gmy = G9[1], ga = G9[2], gb = G9[3], gc = G9[4], go = G9[5];
+    const float m1x = G9[0], m1y = G9[1], m2xx = G9[2], m2xy = G9[3], m2yy = G9[4], go = G9[5];
 
     // camera-space position: fp64 in the forward's operation order for the guard decision
     double pcd[3];
@@ -341,6 +350,9 @@ __global__ void __launch_bounds__(128) k_proj_bwd(const float* __restrict__ para
     const float s11 = PS[1][0] * P[1][0] + PS[1][1] * P[1][1] + PS[1][2] * P[1][2] + opt.dilation;
     const float idet = 1.f / (s00 * s11 - s01 * s01);
     const float A[2][2] = {{s11 * idet, -s01 * idet}, {-s01 * idet, s00 * idet}};
+    // 2D mean and conic gradients from the moments
+    const float gmx = A[0][0] * m1x + A[0][1] * m1y, gmy = A[1][0] * m1x + A[1][1] * m1y;
+    const float ga = -0.5f * m2xx, gb = -m2xy, gc = -0.5f * m2yy;
 
     // colour: rgb = max(0, sum_k sh_k Y_k(dir) + 1/2)
     float campos[3];
@@ -431,8 +443,8 @@ __global__ void __launch_bounds__(128) k_proj_bwd(const float* __restrict__ para
     for (int c = 0; c < 3; ++c) dp[c] += W[c] * dpc[0] + W[3 + c] * dpc[1] + W[6 + c] * dpc[2];
     dop += go;
 
-    // splitting matrix: S2D = A M A - m0 A, M = [[-2ga, -gb], [-gb, -2gc]], m0 = o * go
-    const float M[2][2] = {{-2.f * ga, -gb}, {-gb, -2.f * gc}};
+    // splitting matrix: S2D = A M A - m0 A, M = m2, m0 = o * go
+    const float M[2][2] = {{m2xx, m2xy}, {m2xy, m2yy}};
     float AM[2][2], S2D[2][2];
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b) AM[a][b] = A[a][0] * M[0][b] + A[a][1] * M[1][b];
@@ -481,6 +493,23 @@ __global__ void __launch_bounds__(128) k_proj_bwd(const float* __restrict__ para
 #pragma unroll
   for (int k = 0; k < 3 * NB; ++k) gp[(STEEPGS_ROW_SH + k) * n] += dsh[k];
   for (int k = 0; k < 6; ++k) S[k * n + i] += S3[k];
+}
+
+// the caller's 2D-gradient buffer: moments -> mean and conic gradients, with
+// the conic the raster kernels used (the projected record's)
+__global__ void k_export2d(const steepgs_splat* __restrict__ splats, const uint32_t* __restrict__ tiles, int64_t m,
+                           float* __restrict__ g2d) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x) {
+    if (tiles[r] == 0) continue;
+    float* slot = g2d + r * kG2dStride;
+    const float m1x = slot[0], m1y = slot[1], m2xx = slot[2], m2xy = slot[3], m2yy = slot[4];
+    const float a = splats[r].conic_a, b = splats[r].conic_b, c = splats[r].conic_c;
+    slot[0] = a * m1x + b * m1y;
+    slot[1] = b * m1x + c * m1y;
+    slot[2] = -0.5f * m2xx;
+    slot[3] = -m2xy;
+    slot[4] = -0.5f * m2yy;
+  }
 }
 
 __global__ void k_zero(float* __restrict__ p, int64_t count) {
@@ -561,6 +590,8 @@ extern "C" steepgs_status steepgs_render_bwd_split(const float* d_params, int64_
     default: hipLaunchKernelGGL(k_proj_bwd<3>, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d, d_grads, d_S); break;
   }
   timer_end(STEEPGS_TIMER_PROJ_BWD, st);
+  if (d_grad2d)
+    hipLaunchKernelGGL(k_export2d, dim3(stride_grid(m, 256)), dim3(256), 0, st, d_splats, d_tiles_touched, m, d_grad2d);
   SG_TRY_LAUNCH();
   return STEEPGS_OK;
 }
