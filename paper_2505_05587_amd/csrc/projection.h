@@ -138,14 +138,18 @@ SG_DEV bool tile_hit_fp64(float mx, float my, float a, float b, float c, const s
   return q <= k2 * (1.0 + 1e-6);
 }
 
-// The same decision, certified in fp32 where it can be: each edge minimum is
-// evaluated in fp32 together with M = a dx^2 + 2|b dx dy| + c dy^2, which
-// bounds its rounding error by ~10 ulp * M (the fp64 evaluation's own error
-// is far smaller).  When an edge's estimate plus 1e-5 M (and a 1e-6 margin on
-// the threshold) is below the threshold the tile is hit; when every edge's
-// estimate minus that bound is above it the tile is missed; otherwise the
-// fp64 rule decides.  Mean inside the box: hit (the same comparisons either
-// way).  Result identical to tile_hit_fp64.
+// The same decision, certified in fp32 where it can be.  With the mean
+// outside the box the minimum lies on a face seen from the mean (the segment
+// from the mean to any point of the box enters it through such a face, and
+// the quadratic grows along it), so only those faces -- at most one across x
+// and one across y -- are evaluated.  Each face minimum is computed in fp32
+// together with M = a dx^2 + 2|b dx dy| + c dy^2, which bounds its rounding
+// error by ~10 ulp * M (the fp64 evaluation's own error is far smaller).
+// When a face's estimate plus 1e-5 M (and a 1e-6 margin on the threshold) is
+// below the threshold the tile is hit; when every evaluated face's estimate
+// minus that bound is above it the tile is missed; otherwise the fp64 rule
+// decides.  Mean inside the box: hit (the same comparisons either way).
+// Result identical to tile_hit_fp64.
 SG_DEV bool tile_hit_rcp(float mx, float my, float a, float b, float c, float ia, float ic, const steepgs_opts& opt,
                          int tx, int ty);
 SG_DEV bool tile_hit(float mx, float my, float a, float b, float c, const steepgs_opts& opt, int tx, int ty) {
@@ -159,15 +163,17 @@ SG_DEV bool tile_hit_rcp(float mx, float my, float a, float b, float c, float ia
                          int tx, int ty) {
   const float x0 = (float)(tx * opt.tile_w), x1 = (float)(tx * opt.tile_w + opt.tile_w - 1);
   const float y0 = (float)(ty * opt.tile_h), y1 = (float)(ty * opt.tile_h + opt.tile_h - 1);
-  if (mx >= x0 && mx <= x1 && my >= y0 && my <= y1) return true;
+  const bool fxl = mx < x0, fxh = mx > x1, fyl = my < y0, fyh = my > y1;
+  if (!(fxl || fxh || fyl || fyh)) return true;
   const float T = opt.radius_sigmas * opt.radius_sigmas * (1.f + 1e-6f);
   const float tm = 1e-6f * T;
   bool sure_hit = false, all_miss = true;
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    // edges x = x0, x = x1 (free coordinate y), then y = y0, y = y1 (free x)
-    const bool xe = e < 2;
-    const float fixed = xe ? ((e == 0 ? x0 : x1) - mx) : ((e == 2 ? y0 : y1) - my);
+  for (int e = 0; e < 2; ++e) {
+    // the face seen across x (x = x0 or x1, free coordinate y), then across y
+    const bool xe = e == 0;
+    if (xe ? !(fxl || fxh) : !(fyl || fyh)) continue;
+    const float fixed = xe ? ((fxl ? x0 : x1) - mx) : ((fyl ? y0 : y1) - my);
     const float lo = xe ? (y0 - my) : (x0 - mx), hi = xe ? (y1 - my) : (x1 - mx);
     const float pf = xe ? a : c, pv = xe ? c : a;  // coefficient of fixed^2 and of free^2
     float fr = -(b * fixed) * (xe ? ic : ia);
