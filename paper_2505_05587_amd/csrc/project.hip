@@ -87,18 +87,8 @@ __global__ void __launch_bounds__(256) k_count_tiles(const steepgs_splat* __rest
     uint32_t area = 0;
     RectRec me = {};
     me.wdt = 1;
-    if (r < m && tiles[r]) {
-      const steepgs_splat sp = splats[r];
-      const uint32_t x0 = sp.rect_lo & 0xFFFF, y0 = sp.rect_lo >> 16;
-      me.wdt = (sp.rect_hi & 0xFFFF) - x0 + 1;
-      area = me.wdt * ((sp.rect_hi >> 16) - y0 + 1);
-      me.mx = sp.mean_x;
-      me.my = sp.mean_y;
-      me.a = sp.conic_a;
-      me.b = sp.conic_b;
-      me.c = sp.conic_c;
-      me.xy0 = sp.rect_lo;
-    }
+    const bool live = r < m && tiles[r];
+    if (live) area = walk_rect(splats[r], opt, me);
     s_cnt[tid] = 0u;
     rect_walk(s_walk[wave], lane, area, me, opt, [&](int owner, const RectRec&, int, int, bool hit) {
       if (hit) atomicAdd(&cnt[owner], 1u);
@@ -106,7 +96,7 @@ __global__ void __launch_bounds__(256) k_count_tiles(const steepgs_splat* __rest
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (r < m && area) tiles[r] = s_cnt[tid];
+    if (live) tiles[r] = s_cnt[tid];
     __builtin_amdgcn_wave_barrier();
   }
 }

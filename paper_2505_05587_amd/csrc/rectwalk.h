@@ -29,6 +29,47 @@ struct RectRec {
   float iw, pad2;         // 1/width (filled by rect_walk)
 };
 
+// The rectangle a record's walk covers: its stored tile rectangle (a square
+// of radius 3 sqrt(lambda_max) around the mean) cut down to the tiles whose
+// boxes of pixel centres meet the bounding box of the footprint ellipse
+// d^T A d <= radius_sigmas^2 (1 + 1e-6) -- the only tiles tile_hit can
+// accept.  The half-widths sqrt(t A^-1_xx), sqrt(t A^-1_yy) come from the
+// stored float conic (determinant in fp64, then fp32) and are widened by
+// 1e-4 relative and 1e-2 px, far above their rounding.  Fills the record's
+// geometry and returns the area (0: nothing to walk).
+SG_DEV uint32_t walk_rect(const steepgs_splat& sp, const steepgs_opts& opt, RectRec& me) {
+  int x0 = (int)(sp.rect_lo & 0xFFFFu), y0 = (int)(sp.rect_lo >> 16);
+  int x1 = (int)(sp.rect_hi & 0xFFFFu), y1 = (int)(sp.rect_hi >> 16);
+  const double det = (double)sp.conic_a * (double)sp.conic_c - (double)sp.conic_b * (double)sp.conic_b;
+  if (det > 0.0) {
+    const float t = opt.radius_sigmas * opt.radius_sigmas * (1.f + 1e-6f);
+    const float idet = (float)(1.0 / det);
+    const float ex = sqrtf(t * sp.conic_c * idet) * (1.f + 1e-4f) + 1e-2f;
+    const float ey = sqrtf(t * sp.conic_a * idet) * (1.f + 1e-4f) + 1e-2f;
+    const float tw = (float)opt.tile_w, th = (float)opt.tile_h;
+    // tile tx is reachable when tx*tw <= mx + ex and tx*tw + tw - 1 >= mx - ex
+    const float lx = ceilf((sp.mean_x - ex - (tw - 1.f)) / tw), hx = floorf((sp.mean_x + ex) / tw);
+    const float ly = ceilf((sp.mean_y - ey - (th - 1.f)) / th), hy = floorf((sp.mean_y + ey) / th);
+    if (lx > (float)x0) x0 = lx > (float)x1 ? x1 + 1 : (int)lx;
+    if (hx < (float)x1) x1 = hx < (float)x0 ? x0 - 1 : (int)hx;
+    if (ly > (float)y0) y0 = ly > (float)y1 ? y1 + 1 : (int)ly;
+    if (hy < (float)y1) y1 = hy < (float)y0 ? y0 - 1 : (int)hy;
+  }
+  me.mx = sp.mean_x;
+  me.my = sp.mean_y;
+  me.a = sp.conic_a;
+  me.b = sp.conic_b;
+  me.c = sp.conic_c;
+  if (x1 < x0 || y1 < y0) {
+    me.wdt = 1;
+    me.xy0 = 0;
+    return 0u;
+  }
+  me.wdt = (uint32_t)(x1 - x0 + 1);
+  me.xy0 = (uint32_t)x0 | ((uint32_t)y0 << 16);
+  return me.wdt * (uint32_t)(y1 - y0 + 1);
+}
+
 // LDS per wavefront: RectRec[64] + int[64]  (RectRec is 64 bytes)
 struct RectWalkLds {
   RectRec rec[64];

@@ -313,16 +313,7 @@ __global__ void __launch_bounds__(256) k_emit(const steepgs_splat* __restrict__ 
     // counts: tile counts already gathered into depth order (contiguous)
     if (s < m && counts[s]) {
       const uint32_t r = order[s];
-      const steepgs_splat sp = splats[r];
-      const uint32_t x0 = sp.rect_lo & 0xFFFF, y0 = sp.rect_lo >> 16;
-      me.wdt = (sp.rect_hi & 0xFFFF) - x0 + 1;
-      area = me.wdt * ((sp.rect_hi >> 16) - y0 + 1);
-      me.mx = sp.mean_x;
-      me.my = sp.mean_y;
-      me.a = sp.conic_a;
-      me.b = sp.conic_b;
-      me.c = sp.conic_c;
-      me.xy0 = sp.rect_lo;
+      area = walk_rect(splats[r], opt, me);
       const int v = (int)(r / (uint64_t)n);
       me.tag0 = r;
       me.tag1 = (uint32_t)cams[v].tile_offset;
