@@ -191,11 +191,18 @@ steepgs_status steepgs_render_bwd_split(const float* d_params, int64_t n, int32_
                                         const float* d_target, float* d_grads, float* d_S, float* d_grad2d,
                                         void* d_ws, size_t ws_bytes, void* stream);
 
-/* Optional selection rules of the split step (the paper's "Variants"):
+/* Optional selection rules of the split step (the paper's "Variants" and
+ * Algorithm 1's "condition on G"):
  *  - compactest splitting: a Gaussian is a candidate only when also
  *    |g_scale * G_i| <= eps_grad, G = d_G [3][n] the accumulated gradient of
  *    the position (Algorithm 1's G; g_scale = 1 / T_split averages it); the
  *    norm is compared squared in fp64.  d_G = NULL or eps_grad <= 0: off.
+ *  - ADC-style gate (the condition of the adaptive density control that the
+ *    "Variants" section contrasts with the compactest rule, on the mean of
+ *    the gradient's norm rather than the norm of its mean): a candidate only
+ *    when also g_scale * Gabs_i >= adc_tau, Gabs = d_Gabs [n] the
+ *    accumulated per-step norm of the position gradient (steepgs_adam_step
+ *    accumulates it); compared in fp64.  d_Gabs = NULL or adc_tau <= 0: off.
  *  - increment budget: when more than `budget` Gaussians are candidates,
  *    only the `budget` ones with the smallest lambda_min split (ties: lower
  *    index first), compared on the float32 lambda_min the call reports.
@@ -205,6 +212,8 @@ typedef struct {
   float g_scale;
   float eps_grad;
   int64_t budget;
+  const float* d_Gabs;
+  float adc_tau;
 } steepgs_split_select;
 
 /* Stage 5 -- Steepest Density Control (Theorem 2; Algorithm 1; App. A.3).
@@ -240,11 +249,13 @@ typedef struct {
  * v = b2 v + (1 - b2) g^2, p -= (lr / (1 - b1^t)) m / (sqrt(v) / sqrt(1 - b2^t)
  * + eps) elementwise over d_params, d_grads, d_m, d_v [F][n] (fp32; the bias
  * corrections in fp64).  d_G [3][n] (nullable) accumulates the position
- * gradient (Algorithm 1's G += grad).  Errors: INVALID_ARG for a null
- * pointer, a degree outside 0..3, betas outside [0, 1) or eps <= 0. */
+ * gradient (Algorithm 1's G += grad); d_Gabs [n] (nullable) accumulates its
+ * Euclidean norm (fp32), the statistic of the ADC-style gate.  Errors:
+ * INVALID_ARG for a null pointer, a degree outside 0..3, betas outside
+ * [0, 1) or eps <= 0. */
 steepgs_status steepgs_adam_step(float* d_params, const float* d_grads, float* d_m, float* d_v, int64_t n,
                                  int32_t sh_degree, const steepgs_adam_opts* opts, int64_t* d_step, float* d_G,
-                                 void* stream);
+                                 float* d_Gabs, void* stream);
 
 /* Per-Gaussian state (e.g. Adam moments) onto the layout of a densification
  * (Algorithm 1's replacement of a split Gaussian by two offspring): with

@@ -1063,13 +1063,18 @@ void orc_eigh(const double* S, int64_t m, double* lam, double* vec) {
 //    lambda_min < eps_split, its averaged position gradient G (Algorithm 1's
 //    accumulator, times g_scale) has norm <= eps_grad (G == nullptr or
 //    eps_grad <= 0: no gradient condition);
+//  - ADC-style gate (Algorithm 1's "condition on G" in the form of the
+//    adaptive density control the Variants section compares with): a
+//    candidate only if also the averaged per-step norm of the position
+//    gradient, g_scale * Gabs, is >= adc_tau (Gabs == nullptr or
+//    adc_tau <= 0: off);
 //  - increment budget: when more than `budget` Gaussians are candidates
 //    (budget > 0), only the `budget` candidates with the smallest lambda_min
 //    split (ties: lower index first), since the loss decrease of a split is
 //    proportional to lambda_min / 2 (Theorem 2).
 int64_t orc_densify(const float* params, int64_t n, int deg, const double* S, double s_scale, double eps,
-                    double eps_split, const float* G, double g_scale, double eps_grad, int64_t budget,
-                    double* out_params, int64_t out_cap, double* lam_min, double* vmin, uint8_t* split,
+                    double eps_split, const float* G, double g_scale, double eps_grad, const float* Gabs,
+                    double adc_tau, int64_t budget, double* out_params, int64_t out_cap, double* lam_min, double* vmin, uint8_t* split,
                     int64_t* needed) {
   int F = num_params(deg);
   std::vector<int64_t> cand;
@@ -1088,6 +1093,7 @@ int64_t orc_densify(const float* params, int64_t n, int deg, const double* S, do
       }
       c = g2 <= eps_grad * eps_grad;
     }
+    if (c && Gabs && adc_tau > 0.0) c = g_scale * (double)Gabs[i] >= adc_tau;
     split[i] = 0;
     if (c) cand.push_back(i);
   }

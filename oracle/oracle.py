@@ -70,8 +70,8 @@ def lib():
         L.orc_eigh.argtypes = [_c_f64, C.c_int64, _c_f64, _c_f64]
         L.orc_eigh.restype = None
         L.orc_densify.argtypes = [_c_f32, C.c_int64, C.c_int, _c_f64, C.c_double, C.c_double, C.c_double,
-                                  C.c_void_p, C.c_double, C.c_double, C.c_int64, _c_f64, C.c_int64, _c_f64, _c_f64,
-                                  _c_u8, C.POINTER(C.c_int64)]
+                                  C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.c_double, C.c_int64, _c_f64,
+                                  C.c_int64, _c_f64, _c_f64, _c_u8, C.POINTER(C.c_int64)]
         L.orc_densify.restype = C.c_int64
         L.orc_tile_lists.argtypes = common + [_c_i64, C.c_int64, _c_i64, C.c_void_p]
         L.orc_tile_lists.restype = C.c_int
@@ -244,10 +244,11 @@ def eigh(S):
 
 
 def densify(params, sh_degree, S9, s_scale, eps, eps_split, out_cap=None, G=None, g_scale=1.0, eps_grad=0.0,
-            budget=0):
+            budget=0, Gabs=None, adc_tau=0.0):
     """Algorithm 1's split step; optional compactest gate (G [3][n] float32,
-    |g_scale G| <= eps_grad) and increment budget (at most `budget` splits,
-    smallest lambda_min first)."""
+    |g_scale G| <= eps_grad), ADC-style gate (Gabs [n] float32, the summed
+    per-step norms of the position gradient: g_scale Gabs >= adc_tau) and
+    increment budget (at most `budget` splits, smallest lambda_min first)."""
     params = np.ascontiguousarray(params, np.float32)
     F, n = params.shape
     S9 = np.ascontiguousarray(S9, np.float64).reshape(9, n)
@@ -258,9 +259,10 @@ def densify(params, sh_degree, S9, s_scale, eps, eps_split, out_cap=None, G=None
     split = np.zeros(n, np.uint8)
     need = C.c_int64(0)
     Gc = None if G is None else np.ascontiguousarray(G, np.float32).reshape(3, n)
+    Ga = None if Gabs is None else np.ascontiguousarray(Gabs, np.float32).reshape(n)
     n_out = lib().orc_densify(params, n, sh_degree, S9, float(s_scale), float(eps), float(eps_split), _ptr(Gc),
-                              float(g_scale), float(eps_grad), int(budget), out, cap, lam, vmin, split,
-                              C.byref(need))
+                              float(g_scale), float(eps_grad), _ptr(Ga), float(adc_tau), int(budget), out, cap, lam,
+                              vmin, split, C.byref(need))
     return dict(n_out=int(n_out), needed=int(need.value), params=out[:, :max(n_out, 0)], lambda_min=lam,
                 vmin=vmin, split=split.astype(bool))
 

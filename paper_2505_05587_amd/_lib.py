@@ -36,7 +36,8 @@ class Opts(C.Structure):
 
 
 class SplitSelect(C.Structure):
-    _fields_ = [("d_G", C.c_void_p), ("g_scale", C.c_float), ("eps_grad", C.c_float), ("budget", C.c_int64)]
+    _fields_ = [("d_G", C.c_void_p), ("g_scale", C.c_float), ("eps_grad", C.c_float), ("budget", C.c_int64),
+                ("d_Gabs", C.c_void_p), ("adc_tau", C.c_float)]
 
 
 class AdamOpts(C.Structure):
@@ -78,7 +79,7 @@ def lib():
                                                vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.steepgs_densify.argtypes = [vp, i64, i32, vp, f32, f32, f32, C.POINTER(SplitSelect), vp, i64, vp, vp, vp,
                                       vp, vp, vp, sz, vp]
-        L.steepgs_adam_step.argtypes = [vp, vp, vp, vp, i64, i32, C.POINTER(AdamOpts), vp, vp, vp]
+        L.steepgs_adam_step.argtypes = [vp, vp, vp, vp, i64, i32, C.POINTER(AdamOpts), vp, vp, vp, vp]
         L.steepgs_split_remap.argtypes = [vp, i32, i64, vp, vp, i64, vp, sz, vp]
         for fn in ("steepgs_layout_cameras", "steepgs_project", "steepgs_sort", "steepgs_render_fwd",
                    "steepgs_render_bwd_split", "steepgs_densify", "steepgs_adam_step", "steepgs_split_remap"):
@@ -182,12 +183,14 @@ def steepgs_render_bwd_split(params, n, sh_degree, d_cams, V, opts, splats, tile
 
 
 def steepgs_densify(params, n, sh_degree, S, s_scale, eps, eps_split, out, out_capacity, n_out, lambda_min, vmin,
-                    split, status, ws, stream=None, G=None, g_scale=1.0, eps_grad=0.0, budget=0):
+                    split, status, ws, stream=None, G=None, g_scale=1.0, eps_grad=0.0, budget=0, Gabs=None,
+                    adc_tau=0.0):
     """``G`` [3, n] / ``g_scale`` / ``eps_grad``: the compactest gate;
-    ``budget``: the increment budget (both off by default)."""
+    ``Gabs`` [n] / ``adc_tau``: the ADC-style gate; ``budget``: the increment
+    budget (all off by default)."""
     sel = None
-    if G is not None or budget > 0:
-        sel = SplitSelect(_p(G), float(g_scale), float(eps_grad), int(budget))
+    if G is not None or Gabs is not None or budget > 0:
+        sel = SplitSelect(_p(G), float(g_scale), float(eps_grad), int(budget), _p(Gabs), float(adc_tau))
     _check("steepgs_densify",
            lib().steepgs_densify(_p(params), n, sh_degree, _p(S), float(s_scale), float(eps), float(eps_split),
                                  None if sel is None else C.byref(sel), _p(out), out_capacity, _p(n_out),
@@ -204,10 +207,10 @@ def make_adam_opts(lr, beta1=0.9, beta2=0.999, eps=1e-15):
     return AdamOpts((C.c_float * 6)(*[float(x) for x in lr]), float(beta1), float(beta2), float(eps))
 
 
-def steepgs_adam_step(params, grads, m, v, n, sh_degree, opts, step, G=None, stream=None):
+def steepgs_adam_step(params, grads, m, v, n, sh_degree, opts, step, G=None, Gabs=None, stream=None):
     _check("steepgs_adam_step",
            lib().steepgs_adam_step(_p(params), _p(grads), _p(m), _p(v), n, sh_degree, C.byref(opts), _p(step),
-                                   _p(G), _stream(stream)))
+                                   _p(G), _p(Gabs), _stream(stream)))
 
 
 def steepgs_split_remap(src, rows, n, split, dst, dst_capacity, ws, stream=None):

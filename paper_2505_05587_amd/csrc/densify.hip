@@ -106,7 +106,8 @@ SG_DEV uint32_t float_key(float f) {
 
 __global__ void __launch_bounds__(256) k_densify_eig(const float* __restrict__ S, int64_t n, float s_scale,
                                                      float eps_split, const float* __restrict__ G, float g_scale,
-                                                     float eps_grad, float* __restrict__ lam_out,
+                                                     float eps_grad, const float* __restrict__ Gabs, float adc_tau,
+                                                     float* __restrict__ lam_out,
                                                      float* __restrict__ v_out, uint32_t* __restrict__ flag,
                                                      uint32_t* __restrict__ key) {
 #pragma clang fp contract(off)
@@ -128,6 +129,8 @@ __global__ void __launch_bounds__(256) k_densify_eig(const float* __restrict__ S
     }
     cand = g2 <= (double)eps_grad * (double)eps_grad;
   }
+  // ADC-style gate on the averaged per-step norm of the position gradient
+  if (cand && Gabs && adc_tau > 0.f) cand = (double)g_scale * (double)Gabs[i] >= (double)adc_tau;
   flag[i] = cand ? 1u : 0u;
   if (key) key[i] = float_key(lam32);
 }
@@ -332,10 +335,12 @@ extern "C" steepgs_status steepgs_densify(const float* d_params, int64_t n, int3
   const float g_scale = select ? select->g_scale : 1.f;
   const float eps_grad = select ? select->eps_grad : 0.f;
   const int64_t budget = select ? select->budget : 0;
+  const float* Gabs = select ? select->d_Gabs : nullptr;
+  const float adc_tau = select ? select->adc_tau : 0.f;
   if (budget >= (int64_t)1 << 32) return STEEPGS_ERR_INVALID_ARG;
   timer_begin(STEEPGS_TIMER_DENSIFY, st);
   hipLaunchKernelGGL(k_densify_eig, dim3(nb), dim3(256), 0, st, d_S, n, s_scale, eps_split, G, g_scale, eps_grad,
-                     w.lam, w.vmin, w.flag, budget > 0 ? w.key : nullptr);
+                     Gabs, adc_tau, w.lam, w.vmin, w.flag, budget > 0 ? w.key : nullptr);
   timer_end(STEEPGS_TIMER_DENSIFY, st);
   if (budget > 0) {
     const unsigned hb = (unsigned)std::min<int64_t>(ceil_div(n, 256), 2048);

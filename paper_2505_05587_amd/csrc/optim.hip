@@ -40,6 +40,14 @@ __global__ void __launch_bounds__(256) k_adam(float* __restrict__ p, const float
   }
 }
 
+// Gabs[i] += |dL/dp_i| (the position rows 0-2 of one Gaussian)
+__global__ void __launch_bounds__(256) k_grad_norm(const float* __restrict__ g, int64_t n, float* __restrict__ Gabs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float x = g[i], y = g[n + i], z = g[2 * n + i];
+  Gabs[i] += sqrtf(x * x + y * y + z * z);
+}
+
 struct LoadSplit {
   const uint8_t* f;
   SG_DEV uint32_t operator()(int64_t i) const { return f[i] ? 1u : 0u; }
@@ -68,15 +76,17 @@ using namespace sg;
 
 extern "C" steepgs_status steepgs_adam_step(float* d_params, const float* d_grads, float* d_m, float* d_v, int64_t n,
                                             int32_t sh_degree, const steepgs_adam_opts* opts, int64_t* d_step,
-                                            float* d_G, void* stream) {
+                                            float* d_G, float* d_Gabs, void* stream) {
   if (n < 0 || sh_degree < 0 || sh_degree > 3 || !opts || !d_step) return STEEPGS_ERR_INVALID_ARG;
   if (!(opts->beta1 >= 0.f && opts->beta1 < 1.f && opts->beta2 >= 0.f && opts->beta2 < 1.f && opts->eps > 0.f))
     return STEEPGS_ERR_INVALID_ARG;
+  if (n > 0 && (!d_params || !d_grads || !d_m || !d_v)) return STEEPGS_ERR_INVALID_ARG;
   hipStream_t st = as_stream(stream);
   hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(1), 0, st, d_step);
   if (n > 0) {
-    if (!d_params || !d_grads || !d_m || !d_v) return STEEPGS_ERR_INVALID_ARG;
     const int F = STEEPGS_NUM_PARAMS(sh_degree);
+    if (d_Gabs)
+      hipLaunchKernelGGL(k_grad_norm, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, d_grads, n, d_Gabs);
     hipLaunchKernelGGL(k_adam, dim3(stride_grid((int64_t)F * n, 256)), dim3(256), 0, st, d_params, d_grads,
                        d_m, d_v, n, F, *opts, d_step, d_G);
   }

@@ -166,11 +166,13 @@ class Rasterizer:
 
 def densify(params: torch.Tensor, sh_degree: int, S: torch.Tensor, s_scale: float, eps: float,
             eps_split: float = -1e-6, out_capacity: int | None = None, G: torch.Tensor | None = None,
-            g_scale: float = 1.0, eps_grad: float = 0.0, budget: int = 0):
+            g_scale: float = 1.0, eps_grad: float = 0.0, budget: int = 0, Gabs: torch.Tensor | None = None,
+            adc_tau: float = 0.0):
     """Steepest Density Control on the device; returns the new parameter
     tensor [F, n_out] and the per-Gaussian eigen results.  Reads n_out back.
-    Optional: the compactest gate (``G`` [3, n], ``g_scale``, ``eps_grad``)
-    and the increment budget (``budget``)."""
+    Optional: the compactest gate (``G`` [3, n], ``g_scale``, ``eps_grad``),
+    the ADC-style gate (``Gabs`` [n], ``g_scale``, ``adc_tau``) and the
+    increment budget (``budget``)."""
     F, n = params.shape
     dev = params.device
     cap = 2 * n if out_capacity is None else int(out_capacity)
@@ -183,8 +185,10 @@ def densify(params: torch.Tensor, sh_degree: int, S: torch.Tensor, s_scale: floa
     ws = torch.empty(L.steepgs_workspace_size(L.STAGE_DENSIFY, n, 1) // 4 + 64, dtype=torch.int32, device=dev)
     if G is not None and (G.shape != (3, n) or G.dtype != torch.float32 or not G.is_contiguous()):
         raise ValueError("G must be a contiguous float32 tensor [3, n]")
+    if Gabs is not None and (Gabs.shape != (n,) or Gabs.dtype != torch.float32 or not Gabs.is_contiguous()):
+        raise ValueError("Gabs must be a contiguous float32 tensor [n]")
     L.steepgs_densify(params, n, sh_degree, S, s_scale, eps, eps_split, out, cap, n_out, lam, vmin, split, status, ws,
-                      G=G, g_scale=g_scale, eps_grad=eps_grad, budget=budget)
+                      G=G, g_scale=g_scale, eps_grad=eps_grad, budget=budget, Gabs=Gabs, adc_tau=adc_tau)
     no = int(n_out.item())
     st = int(status.item())
     return dict(params=out[:, :no] if st == L.OK else None, n_out=no, status=st, lambda_min=lam[:n],

@@ -2,7 +2,8 @@
 
 Every iteration either takes a gradient step -- forward with the fused L1
 loss, backward with the splitting matrices accumulated into S, Adam (which
-also accumulates the position gradient G) -- or, on densification
+also accumulates the position gradient G and, for the ADC-style gate, its
+norm) -- or, on densification
 iterations, runs Steepest Density Control with S and G averaged over the
 steps since the last one (s_scale = g_scale = 1 / steps), remaps the Adam
 moments onto the new layout (offspring start from zero) and restarts the
@@ -57,6 +58,7 @@ class SteepGSTrainer:
     eps: float = 1e-3               # offspring displacement (Algorithm 1's stepsize)
     eps_split: float = -1e-6        # Sec. 5.1
     eps_grad: float = 0.0           # compactest gate (off when 0)
+    adc_tau: float = 0.0            # ADC-style gate on the mean gradient norm (off when 0)
     budget: int = 0                 # increment budget (off when 0)
     lr: tuple = DEFAULT_LR
     schedule: Schedule = field(default_factory=Schedule)
@@ -78,6 +80,7 @@ class SteepGSTrainer:
         self.grads = torch.zeros((self.params.shape[0], n), dtype=torch.float32, device=dev)
         self.S = torch.zeros((6, n), dtype=torch.float32, device=dev)
         self.G = torch.zeros((3, n), dtype=torch.float32, device=dev)
+        self.Gabs = torch.zeros(n, dtype=torch.float32, device=dev)
         self.acc_steps = 0
 
     @property
@@ -90,7 +93,7 @@ class SteepGSTrainer:
         self.grads.zero_()
         r.backward(self.params, self.grads, self.S, target=self.target)
         L.steepgs_adam_step(self.params, self.grads, self.m, self.v, self.n, self.sh_degree, self.opts, self.step_dev,
-                            G=self.G)
+                            G=self.G, Gabs=self.Gabs if self.adc_tau > 0 else None)
         self.acc_steps += 1
 
     def densify_step(self):
@@ -98,7 +101,7 @@ class SteepGSTrainer:
         k = max(self.acc_steps, 1)
         out = densify(self.params, self.sh_degree, self.S, 1.0 / k, self.eps, self.eps_split,
                       G=self.G if self.eps_grad > 0 else None, g_scale=1.0 / k, eps_grad=self.eps_grad,
-                      budget=self.budget)
+                      budget=self.budget, Gabs=self.Gabs if self.adc_tau > 0 else None, adc_tau=self.adc_tau)
         if out["status"] != L.OK:
             raise RuntimeError("densification output capacity exceeded")
         n_out = out["n_out"]
@@ -123,6 +126,7 @@ class SteepGSTrainer:
         if self.t == self.schedule.accumulate_from():
             self.S.zero_()
             self.G.zero_()
+            self.Gabs.zero_()
             self.acc_steps = 0
         if self.schedule.is_densify(self.t):
             return self.densify_step()

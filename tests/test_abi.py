@@ -32,6 +32,7 @@ def test_header_symbols_exported():
 def test_struct_sizes_match_header():
     assert C.sizeof(L.Camera) == 96
     assert C.sizeof(L.Opts) == 48
+    assert C.sizeof(L.SplitSelect) == 40
 
 
 def test_layout_cameras():
@@ -67,12 +68,17 @@ def test_bad_arguments_rejected_on_host():
     assert lib.steepgs_set_kernel_timer(0, None, None, 0) == L.OK
     assert lib.steepgs_densify(None, 10, 0, None, 1.0, 0.01, 0.0, None, None, 0, None, None, None, None, None, None,
                                0, None) == L.ERR_INVALID_ARG
-    sel = L.SplitSelect(None, 1.0, 0.0, 1 << 40)  # budget beyond 32 bits
+    sel = L.SplitSelect(None, 1.0, 0.0, 1 << 40, None, 0.0)  # budget beyond 32 bits
     assert lib.steepgs_densify(fake, 10, 0, fake, 1.0, 0.01, 0.0, C.byref(sel), fake, 20, fake, None, None, None,
                                fake, fake, 1 << 20, None) == L.ERR_INVALID_ARG
-    assert lib.steepgs_adam_step(None, None, None, None, 10, 0, None, None, None, None) == L.ERR_INVALID_ARG
+    assert lib.steepgs_adam_step(None, None, None, None, 10, 0, None, None, None, None, None) == L.ERR_INVALID_ARG
     bad = L.make_adam_opts([1e-3] * 6, beta1=1.0)
-    assert lib.steepgs_adam_step(fake, fake, fake, fake, 10, 0, C.byref(bad), fake, None, None) == L.ERR_INVALID_ARG
+    assert lib.steepgs_adam_step(fake, fake, fake, fake, 10, 0, C.byref(bad), fake, None, None,
+                                 None) == L.ERR_INVALID_ARG
+    good = L.make_adam_opts([1e-3] * 6)
+    # missing parameter buffers are rejected before anything is enqueued
+    assert lib.steepgs_adam_step(None, fake, fake, fake, 10, 0, C.byref(good), fake, None, None,
+                                 None) == L.ERR_INVALID_ARG
     assert lib.steepgs_split_remap(fake, 1, 10, fake, fake, 20, None, 0, None) == L.ERR_WORKSPACE
     assert lib.steepgs_split_remap(fake, -1, 10, fake, fake, 20, None, 0, None) == L.ERR_INVALID_ARG
     assert lib.steepgs_status_string(2) == b"output capacity exceeded"

@@ -1,6 +1,7 @@
 """GPU parity of the split-selection variants (the paper's "Variants"
 section): the increment budget (the K candidates with the smallest
-lambda_min, ties by index) and the compactest gate (|G| <= eps_grad)."""
+lambda_min, ties by index), the compactest gate (|G| <= eps_grad) and the
+ADC-style gate (mean per-step gradient norm >= adc_tau)."""
 import numpy as np
 import pytest
 import torch
@@ -31,8 +32,10 @@ def _key(lam32):
 def _gpu(P, S6, **kw):
     dev = torch.device("cuda", 0)
     G = kw.pop("G", None)
+    Gabs = kw.pop("Gabs", None)
     out = pipeline.densify(torch.from_numpy(P).to(dev), 1, torch.from_numpy(S6).to(dev), 1.0, 0.01, -1e-6,
-                           G=None if G is None else torch.from_numpy(G).to(dev), **kw)
+                           G=None if G is None else torch.from_numpy(G).to(dev),
+                           Gabs=None if Gabs is None else torch.from_numpy(Gabs).to(dev), **kw)
     torch.cuda.synchronize()
     return dict(split=out["split"].cpu().numpy().astype(bool), lam=out["lambda_min"].cpu().numpy(),
                 n_out=out["n_out"], params=None if out["params"] is None else out["params"].cpu().numpy())
@@ -82,3 +85,29 @@ def test_compactest_gate_and_budget(oracle):
             assert got["split"].sum() == budget
         np.testing.assert_array_equal(got["split"][sure], ref["split"][sure])
         assert not (got["split"] & (gn > eps_grad * (1 + 1e-6))).any()
+
+
+def test_adc_gate_with_compactest_and_budget(oracle):
+    n = 20000
+    P, S9, S6, G = _problem(62, n)
+    rng = np.random.default_rng(63)
+    Gabs = (np.linalg.norm(G, axis=0) * (1 + rng.random(n) * 3)).astype(np.float32)  # |mean| <= mean |.|
+    print("\n[case] densify ADC gate", flush=True)
+    Sn = np.linalg.norm(S9, axis=0)
+    mean_norm = 0.25 * Gabs.astype(np.float64)
+    gn = np.linalg.norm(0.25 * G.astype(np.float64), axis=0)
+    for tau, eps_grad, budget in [(0.5, 0.0, 0), (1.5, 0.0, 0), (0.5, 2.0, 0), (0.5, 2.0, 300)]:
+        got = _gpu(P, S6, G=G if eps_grad else None, Gabs=Gabs, g_scale=0.25, eps_grad=eps_grad, adc_tau=tau,
+                   budget=budget)
+        ref = oracle.densify(P, 1, S9, 1.0, 0.01, -1e-6, G=G if eps_grad else None, g_scale=0.25,
+                             eps_grad=eps_grad, Gabs=Gabs, adc_tau=tau, budget=budget)
+        sure = (np.abs(ref["lambda_min"] + 1e-6) > 1e-4 * Sn) & (np.abs(mean_norm - tau) > 1e-9)
+        if eps_grad:
+            sure &= np.abs(gn - eps_grad) > 1e-9
+        if budget:
+            thr = np.sort(ref["lambda_min"][ref["split"]])[-1]
+            sure &= np.abs(ref["lambda_min"] - thr) > 1e-5 * Sn
+            assert got["split"].sum() == budget
+        np.testing.assert_array_equal(got["split"][sure], ref["split"][sure])
+        assert not (got["split"] & (mean_norm < tau * (1 - 1e-6))).any()
+        assert 0 < ref["split"].sum() < (ref["lambda_min"] < -1e-6).sum()

@@ -20,14 +20,19 @@ def _np(t):
     return t.detach().cpu().numpy().astype(np.float64)
 
 
-@pytest.mark.parametrize("eps_grad,budget", [(0.0, 0), (0.0, 25), (5e-4, 0)])
-def test_training_loop_follows_oracle(oracle, eps_grad, budget):
+@pytest.mark.parametrize("eps_grad,budget,adc", [(0.0, 0, False), (0.0, 25, False), (5e-4, 0, False),
+                                                  (0.0, 0, True)])
+def test_training_loop_follows_oracle(oracle, eps_grad, budget, adc):
     s = scenes.plain_small()
     opts = scenes.opts("3dgs")
     dev = torch.device("cuda", 0)
-    print(f"\n[case] training loop eps_grad={eps_grad} budget={budget}", flush=True)
+    print(f"\n[case] training loop eps_grad={eps_grad} budget={budget} adc={adc}", flush=True)
+    # adc: the norm accumulator runs from the start; the threshold is set from
+    # the accumulated values just before the densification (median of the
+    # unambiguous candidates), so the gate removes about half of them
     tr = SteepGSTrainer(torch.from_numpy(s.params).to(dev), s.sh_degree, CameraBatch(s.cams, opts, dev),
                         torch.from_numpy(s.target).to(dev), eps=0.01, eps_grad=eps_grad, budget=budget,
+                        adc_tau=1e-30 if adc else 0.0,
                         schedule=Schedule(densify_from=8, densify_every=4, densify_until=8))
     # the library takes its hyper-parameters as float32: the oracle uses the same values
     lr6 = [float(np.float32(x)) for x in tr.lr]
@@ -35,6 +40,7 @@ def test_training_loop_follows_oracle(oracle, eps_grad, budget):
     S_ref = np.zeros((9, s.n))
     S_scale = np.zeros(s.n)  # sum over steps of |S_t| (the accumulated sum may cancel)
     G_ref = np.zeros((3, s.n))
+    Gabs_ref = np.zeros(s.n)
     amb_any = np.zeros(s.n, bool)
     t_adam = 0
     for t in range(1, 8):
@@ -44,6 +50,7 @@ def test_training_loop_follows_oracle(oracle, eps_grad, budget):
             S_ref[:] = 0
             S_scale[:] = 0
             G_ref[:] = 0
+            Gabs_ref[:] = 0
             amb_any[:] = False
         tr.iterate()
         torch.cuda.synchronize()
@@ -56,6 +63,7 @@ def test_training_loop_follows_oracle(oracle, eps_grad, budget):
         S_ref += ref["S"]
         S_scale += np.linalg.norm(ref["S"], axis=0)
         G_ref += g[0:3]
+        Gabs_ref += np.linalg.norm(g[0:3], axis=0)
         amb_any |= amb
         # Adam on the device's own gradient and moments
         p_ref, m_ref, v_ref = oracle.adam_step(theta, g, m0, v0, t_adam, lr6, b1, b2, eps_adam)
@@ -70,19 +78,32 @@ def test_training_loop_follows_oracle(oracle, eps_grad, budget):
     d = np.linalg.norm((Mg - Mr).reshape(s.n, -1), axis=1)
     assert not (~amb_any & (d > 1e-3 * S_scale + 1e-6 * S_scale.max())).any()
     np.testing.assert_allclose(_np(tr.G), G_ref, rtol=1e-5, atol=1e-7 * np.abs(G_ref).max())
+    if adc:
+        np.testing.assert_allclose(_np(tr.Gabs), Gabs_ref, rtol=1e-5, atol=1e-7 * Gabs_ref.max())
     # the densification iteration
     S9 = np.stack([_np(tr.S)[[0, 1, 2]], _np(tr.S)[[1, 3, 4]], _np(tr.S)[[2, 4, 5]]]).reshape(9, s.n)
     G32 = tr.G.cpu().numpy()
+    Gabs32 = tr.Gabs.cpu().numpy()
+    tau = 0.0
+    if adc:
+        lam_pre = oracle.densify(tr.params.cpu().numpy(), s.sh_degree, S9, 1.0 / k, 0.01, -1e-6)["lambda_min"]
+        cand = (lam_pre < -1e-6) & ~amb_any
+        tau = float(np.median(Gabs32[cand].astype(np.float64) / k))
+        tr.adc_tau = tau
     m_old, v_old = _np(tr.m), _np(tr.v)
     theta = tr.params.cpu().numpy()
     out = tr.iterate()
     torch.cuda.synchronize()
     assert out is not None and tr.history and tr.history[-1].accumulated_steps == k
     dref = oracle.densify(theta, s.sh_degree, S9, 1.0 / k, 0.01, -1e-6, G=G32 if eps_grad > 0 else None,
-                          g_scale=1.0 / k, eps_grad=eps_grad, budget=budget)
+                          g_scale=1.0 / k, eps_grad=eps_grad, budget=budget, Gabs=Gabs32 if adc else None,
+                          adc_tau=tau)
     split = out["split"].cpu().numpy().astype(bool)
     Sn = np.linalg.norm(S9, axis=0) / k
     sure = np.abs(dref["lambda_min"] + 1e-6) > 1e-4 * Sn
+    if adc:
+        sure &= np.abs(Gabs32.astype(np.float64) / k - tau) > 1e-6 * tau
+        assert 0 < dref["split"].sum() < (dref["lambda_min"] < -1e-6).sum()
     if budget and dref["split"].sum() == budget:
         thr = np.sort(dref["lambda_min"][dref["split"]])[-1]
         sure &= np.abs(dref["lambda_min"] - thr) > 1e-5 * Sn

@@ -172,6 +172,32 @@ def test_densify_compactest_gate(oracle):
     assert set(np.nonzero(both["split"])[0]) == set(keep)
 
 
+def test_densify_adc_gate(oracle):
+    # ADC-style condition on G (the mean of the per-step gradient norms, which
+    # the Variants section contrasts with the compactest |mean gradient|):
+    # split only where g_scale * Gabs >= adc_tau and lambda_min < eps_split.
+    # The expected set comes from LAPACK's eigenvalues and numpy norms.
+    rng = np.random.default_rng(56)
+    n = 300
+    P = scenes.uniform_gaussians(rng, n)
+    S9 = _random_S(rng, n).reshape(n, 9).T.copy()
+    steps = rng.normal(size=(8, 3, n)) * np.exp(rng.normal(0, 1, size=n))
+    Gabs = np.linalg.norm(steps, axis=1).sum(axis=0).astype(np.float32)  # sum over 8 steps of |g_t|
+    lam = np.linalg.eigvalsh(S9.T.reshape(n, 3, 3))[:, 0]
+    mean_norm = Gabs.astype(np.float64) / 8
+    for tau in (0.3, 1.0, 3.0):
+        out = oracle.densify(P, 0, S9, 1.0, 0.01, -1e-6, g_scale=1 / 8, Gabs=Gabs, adc_tau=tau)
+        np.testing.assert_array_equal(out["split"], (lam < -1e-6) & (mean_norm >= tau))
+        assert out["split"].sum() < (lam < -1e-6).sum()  # the gate removes some candidates
+    off = oracle.densify(P, 0, S9, 1.0, 0.01, -1e-6, g_scale=1 / 8, Gabs=Gabs, adc_tau=0.0)
+    np.testing.assert_array_equal(off["split"], lam < -1e-6)
+    # the two gates together: mean norm large, norm of the mean small
+    G = steps.sum(axis=0).astype(np.float32)
+    gn = np.linalg.norm(G.astype(np.float64) / 8, axis=0)
+    both = oracle.densify(P, 0, S9, 1.0, 0.01, -1e-6, G=G, g_scale=1 / 8, eps_grad=1.0, Gabs=Gabs, adc_tau=1.0)
+    np.testing.assert_array_equal(both["split"], (lam < -1e-6) & (gn <= 1.0) & (mean_norm >= 1.0))
+
+
 def test_instance_sort_properties(oracle):
     # view-dependent depth sort per tile (Sec. 3, Rasterization): keys are
     # tile | depth, non-decreasing; each visible record appears once per
