@@ -499,6 +499,12 @@ struct Pixel {
 constexpr double kAlphaBand = 1e-5;  // relative band around alpha_min / alpha_max
 constexpr double kQBand = 1e-5;      // relative band around the footprint cut-off radius_sigmas^2
 constexpr double kTBand = 5e-5;      // relative band around t_min (fp32 transmittance after ~400 factors)
+// A float32 evaluation of q = d^T A d on float32 record values is only good to
+// about 2^-24 of the magnitude of its terms, |A00| dx^2 + 2|A01 dx dy| + |A11| dy^2,
+// which exceeds q by orders of magnitude for a thin Gaussian seen far along its
+// long axis.  The bands widen with that bound, and a pair whose alpha is
+// uncertain by more than kAlphaValue (alpha * bound / 2) marks its pixel as well.
+constexpr double kAlphaValue = 1e-5;
 
 void blend_pixel(const View& view, int u, int v, Pixel& px) {
   const Cam& cam = *view.cam;
@@ -516,21 +522,26 @@ void blend_pixel(const View& view, int u, int v, Pixel& px) {
     // footprint: only pixels within radius_sigmas (Mahalanobis) of the mean
     double dxu = u - g.mx, dyv = v - g.my;
     double q = g.A00 * dxu * dxu + 2.0 * g.A01 * dxu * dyv + g.A11 * dyv * dyv;
-    bool amb = std::fabs(q - k2) <= kQBand * k2;
+    const double terms =
+        std::fabs(g.A00) * dxu * dxu + 2.0 * std::fabs(g.A01 * dxu * dyv) + std::fabs(g.A11) * dyv * dyv;
+    const double eq = std::ldexp(terms, -23);  // float32 bound on q, with a factor 2 of margin
+    bool amb = std::fabs(q - k2) <= std::max(kQBand * k2, eq);
     if (amb) {
       px.ambig = true;
       px.amb_ids.push_back(lst[j]);
     }
     if (q > k2) continue;
     double a = alpha_raw(g.mx, g.my, g.A00, g.A01, g.A11, g.o, (double)u, (double)v);
+    const double aband = std::max(kAlphaBand, 0.5 * eq);  // relative: d alpha / alpha = dq / 2
     bool clamped = false;
     amb = false;
-    if (opt.alpha_max < 1.0 && std::fabs(a - opt.alpha_max) <= kAlphaBand * opt.alpha_max) amb = true;
+    if (opt.alpha_max < 1.0 && std::fabs(a - opt.alpha_max) <= aband * opt.alpha_max) amb = true;
     if (a > opt.alpha_max) {
       a = opt.alpha_max;
       clamped = true;
     }
-    if (opt.alpha_min > 0.0 && std::fabs(a - opt.alpha_min) <= kAlphaBand * opt.alpha_min) amb = true;
+    if (opt.alpha_min > 0.0 && std::fabs(a - opt.alpha_min) <= aband * opt.alpha_min) amb = true;
+    if (a >= opt.alpha_min && a * std::ldexp(terms, -25) > kAlphaValue) amb = true;
     if (amb) {
       px.ambig = true;
       px.amb_ids.push_back(lst[j]);

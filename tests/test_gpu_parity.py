@@ -15,12 +15,12 @@ import pytest
 import torch
 
 from paper_2505_05587_amd import scenes
-from tests.gpu_common import (assert_group_close, assert_S_close, expand_pixel_mask, image_close, run_gpu,
-                              scene_small)
+from tests.gpu_common import (assert_group_close, assert_S_close, conditioned_rel, expand_pixel_mask, image_close,
+                              run_gpu, scene_small)
 
 pytestmark = pytest.mark.gpu
 
-KINDS = ["plain_small", "sh3_pinhole", "multiview", "ortho"]
+KINDS = ["plain_small", "sh3_pinhole", "multiview", "ortho", "extreme"]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -67,7 +67,11 @@ def test_forward_backward(oracle, kind, mode):
     g = run_gpu(P, deg, cams, opts, target=target)
     ref = oracle.forward_backward(P, deg, cams, opts, target)
     pix_amb = ref["pix_ambig"]
-    assert pix_amb.mean() < 1e-3 or mode == "3dgs" and pix_amb.mean() < 5e-3
+    # excluded fractions: the extreme scene's needles, seen far along their
+    # long axis, carry pairs whose float32 quadratic form is ill-conditioned
+    # (the oracle flags them from the bound 2^-24 (|a| dx^2 + 2|b dx dy| + |c| dy^2))
+    lim_pix, lim_g = (0.02, 0.15) if kind == "extreme" else (1e-3 if mode == "smooth" else 5e-3, 0.1)
+    assert pix_amb.mean() < lim_pix
     ok = image_close(g["image"], ref["image"], expand_pixel_mask(pix_amb, cams))
     assert ok.all(), f"{(~ok).sum()} image values out of tolerance"
     okT = np.abs(g["T_final"] - ref["T_final"]) <= 1e-5 + 1e-4 * ref["T_final"]
@@ -75,9 +79,10 @@ def test_forward_backward(oracle, kind, mode):
     np.testing.assert_array_equal(g["n_used"][~pix_amb], ref["n_used"][~pix_amb])
     np.testing.assert_allclose(g["loss"], ref["loss"], rtol=1e-4)
     gamb = ref["gauss_ambig"]
-    assert gamb.mean() < 0.1
-    assert_group_close(g["grads"], ref["grads"], gamb, what=f"{kind}/{mode}")
-    assert_S_close(g["S6"], ref["S"], gamb)
+    assert gamb.mean() < lim_g
+    rel = conditioned_rel(oracle, P, deg, cams, opts)
+    assert_group_close(g["grads"], ref["grads"], gamb, rel=rel, what=f"{kind}/{mode}")
+    assert_S_close(g["S6"], ref["S"], gamb, rel=rel)
 
 
 @pytest.mark.parametrize("kind", ["multiview", "sh3_pinhole"])
