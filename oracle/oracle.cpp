@@ -241,6 +241,13 @@ struct Proj {
   int rect[4] = {0, 0, -1, -1};  // tile x0, y0, x1, y1 (inclusive)
   float fmx, fmy, fa, fb, fc;    // mean and conic rounded to float32 (the stored record)
   int ntiles = 0;                // tiles of the rectangle that meet the cut-off ellipse
+  // at the point (values only): the map of the 2D covariance P = J W (J at
+  // the frustum-guarded point), the exact Jacobian of the projected mean
+  // w.r.t. p, the rotation of the Gaussian and its log-scales
+  double Pg[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  double Pe[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  double Rot[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  double logs[3] = {0, 0, 0};
 };
 
 // Smallest value of q(d) = a dx^2 + 2 b dx dy + c dy^2, d = x - m, over the box
@@ -297,6 +304,10 @@ void project(const T* th, int deg, const Cam& cam, const Opts& opt, Proj<T>& out
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) Sig[a][b] = Rq[a][0] * s2[0] * Rq[b][0] + Rq[a][1] * s2[1] * Rq[b][1] + Rq[a][2] * s2[2] * Rq[b][2];
   out.o = 1.0 / (1.0 + exp_(-th[10]));
+  for (int a = 0; a < 3; ++a) {
+    out.logs[a] = val(th[3 + a]);
+    for (int b = 0; b < 3; ++b) out.Rot[a][b] = val(Rq[a][b]);
+  }
 
   // camera space
   T pc[3];
@@ -338,6 +349,22 @@ void project(const T* th, int deg, const Cam& cam, const Opts& opt, Proj<T>& out
   T P[2][3];
   for (int a = 0; a < 2; ++a)
     for (int c = 0; c < 3; ++c) P[a][c] = J[a][0] * cam.R[0 + c] + J[a][1] * cam.R[3 + c] + J[a][2] * cam.R[6 + c];
+  {
+    // exact (unguarded) Jacobian of the projected mean w.r.t. p
+    double Je[2][3] = {{cam.fx, 0.0, 0.0}, {0.0, cam.fy, 0.0}};
+    if (cam.model == 0) {
+      const double z = val(pc[2]);
+      Je[0][0] = cam.fx / z;
+      Je[0][2] = -cam.fx * val(pc[0]) / (z * z);
+      Je[1][1] = cam.fy / z;
+      Je[1][2] = -cam.fy * val(pc[1]) / (z * z);
+    }
+    for (int a = 0; a < 2; ++a)
+      for (int c = 0; c < 3; ++c) {
+        out.Pg[a][c] = val(P[a][c]);
+        out.Pe[a][c] = Je[a][0] * cam.R[0 + c] + Je[a][1] * cam.R[3 + c] + Je[a][2] * cam.R[6 + c];
+      }
+  }
   T S2[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) {
@@ -430,6 +457,108 @@ void alpha_hessian_mu(double mx, double my, double A00, double A01, double A11, 
   H[0] = a * (Adx * Adx - A00);
   H[1] = a * (Adx * Ady - A01);
   H[2] = a * (Ady * Ady - A11);
+}
+
+// ---------------------------------------------------------------------------
+// Second-order forward mode over six variables: value, gradient and the
+// upper triangle of the Hessian, propagated by the product and chain rules.
+// Used for the splitting matrix over theta = (p, log-scales).
+
+constexpr int kH6 = 21;  // upper triangle of a 6x6, row-major: (0,0) (0,1) .. (0,5) (1,1) .. (5,5)
+int h6(int i, int j) {
+  if (i > j) std::swap(i, j);
+  return i * 6 - i * (i - 1) / 2 + (j - i);
+}
+
+struct HD {
+  double v = 0.0;
+  double g[6] = {0, 0, 0, 0, 0, 0};
+  double h[kH6] = {};
+  HD() = default;
+  HD(double x) : v(x) {}  // NOLINT: constants promote
+};
+
+HD operator+(const HD& a, const HD& b) {
+  HD r(a.v + b.v);
+  for (int k = 0; k < 6; ++k) r.g[k] = a.g[k] + b.g[k];
+  for (int k = 0; k < kH6; ++k) r.h[k] = a.h[k] + b.h[k];
+  return r;
+}
+HD operator-(const HD& a, const HD& b) {
+  HD r(a.v - b.v);
+  for (int k = 0; k < 6; ++k) r.g[k] = a.g[k] - b.g[k];
+  for (int k = 0; k < kH6; ++k) r.h[k] = a.h[k] - b.h[k];
+  return r;
+}
+HD operator*(const HD& a, const HD& b) {  // (ab)'' = a'' b + a' b'^T + b' a'^T + a b''
+  HD r(a.v * b.v);
+  for (int k = 0; k < 6; ++k) r.g[k] = a.g[k] * b.v + a.v * b.g[k];
+  for (int i = 0; i < 6; ++i)
+    for (int j = i; j < 6; ++j) {
+      const int k = h6(i, j);
+      r.h[k] = a.h[k] * b.v + a.g[i] * b.g[j] + a.g[j] * b.g[i] + a.v * b.h[k];
+    }
+  return r;
+}
+// f(a) for a scalar function with f(a.v), f'(a.v), f''(a.v) given
+HD apply(const HD& a, double f0, double f1, double f2) {
+  HD r(f0);
+  for (int k = 0; k < 6; ++k) r.g[k] = f1 * a.g[k];
+  for (int i = 0; i < 6; ++i)
+    for (int j = i; j < 6; ++j) r.h[h6(i, j)] = f1 * a.h[h6(i, j)] + f2 * a.g[i] * a.g[j];
+  return r;
+}
+HD recip(const HD& a) { return apply(a, 1.0 / a.v, -1.0 / (a.v * a.v), 2.0 / (a.v * a.v * a.v)); }
+HD operator/(const HD& a, const HD& b) { return a * recip(b); }
+HD hexp(const HD& a) {
+  const double e = std::exp(a.v);
+  return apply(a, e, e, e);
+}
+double hexp(double a) { return std::exp(a); }
+double recip(double a) { return 1.0 / a; }
+
+// alpha at pixel (u, v) as a function of theta = (p, log-scales) moved by dth
+// from the Gaussian's point, with the maps of the projection frozen there (the
+// "approximately" of the Hessian in Sec. 4.4, App. C.4): the mean moves along
+// the exact Jacobian Pe, the 2D covariance is Pg Sigma(s) Pg^T + dilation with
+// Sigma(s) = R diag(exp(2 s)) R^T, R and the opacity fixed.
+template <class T>
+T alpha_theta6(const Proj<double>& g, double dil, double u, double v, const T dth[6]) {
+  T mx = T(g.mx), my = T(g.my);
+  for (int c = 0; c < 3; ++c) {
+    mx = mx + T(g.Pe[0][c]) * dth[c];
+    my = my + T(g.Pe[1][c]) * dth[c];
+  }
+  T s2[3];
+  for (int k = 0; k < 3; ++k) s2[k] = hexp(T(2.0 * g.logs[k]) + T(2.0) * dth[3 + k]);
+  T Sig[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      Sig[a][b] = T(0.0);
+      for (int k = 0; k < 3; ++k) Sig[a][b] = Sig[a][b] + T(g.Rot[a][k] * g.Rot[b][k]) * s2[k];
+    }
+  T S2[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      S2[a][b] = T(0.0);
+      for (int c = 0; c < 3; ++c)
+        for (int d = 0; d < 3; ++d) S2[a][b] = S2[a][b] + T(g.Pg[a][c] * g.Pg[b][d]) * Sig[c][d];
+    }
+  S2[0][0] = S2[0][0] + T(dil);
+  S2[1][1] = S2[1][1] + T(dil);
+  const T idet = recip(S2[0][0] * S2[1][1] - S2[0][1] * S2[1][0]);
+  const T A00 = S2[1][1] * idet, A01 = T(0.0) - S2[0][1] * idet, A11 = S2[0][0] * idet;
+  const T dx = T(u) - mx, dy = T(v) - my;
+  const T q = A00 * dx * dx + T(2.0) * A01 * dx * dy + A11 * dy * dy;
+  return T(g.o) * hexp(T(-0.5) * q);
+}
+
+// Hessian of alpha over theta = (p, log-scales) at the point, upper triangle
+void alpha_hessian_theta6(const Proj<double>& g, double dil, double u, double v, double H[kH6]) {
+  HD d[6];
+  for (int k = 0; k < 6; ++k) d[k].g[k] = 1.0;
+  const HD a = alpha_theta6<HD>(g, dil, u, v, d);
+  for (int k = 0; k < kH6; ++k) H[k] = a.h[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -568,12 +697,13 @@ void blend_pixel(const View& view, int u, int v, Pixel& px) {
 struct Grad2D {
   double g[9];  // dL/d(mx, my, A00, A01, A11, o, r, g, b)
   double H[3];  // sum_x dL/dalpha * Hessian_mu alpha: xx, xy, yy
+  double H6[kH6];  // sum_x dL/dalpha * Hessian_theta alpha, theta = (p, log-scales) (when asked)
 };
 
 // Exact reverse sweep of one pixel given dL/dC.  Accumulates into acc[g]
 // for every contributing Gaussian g with want[g] set (want == nullptr: all).
 void backward_pixel(const View& view, int u, int v, const Pixel& px, const double dLdC[3],
-                    std::vector<Grad2D>& acc, const std::vector<uint8_t>* want) {
+                    std::vector<Grad2D>& acc, const std::vector<uint8_t>* want, bool hess6 = false) {
   const Opts& opt = *view.opt;
   double R[3];  // sum of the colour behind the current entry, background included
   for (int ch = 0; ch < 3; ++ch) R[ch] = px.T_final * opt.bg[ch];
@@ -598,6 +728,11 @@ void backward_pixel(const View& view, int u, int v, const Pixel& px, const doubl
     double H[3];
     alpha_hessian_mu(g.mx, g.my, g.A00, g.A01, g.A11, g.o, (double)u, (double)v, H);
     for (int k2 = 0; k2 < 3; ++k2) A.H[k2] += dLda * H[k2];
+    if (hess6) {
+      double H6[kH6];
+      alpha_hessian_theta6(g, opt.dilation, (double)u, (double)v, H6);
+      for (int k2 = 0; k2 < kH6; ++k2) A.H6[k2] += dLda * H6[k2];
+    }
   }
 }
 
@@ -711,6 +846,60 @@ void jacobi_eigh(const double Ain[9], double lam[3], double vec[9] /* columns = 
       if (std::fabs(col[r]) > std::fabs(col[big])) big = r;
     double sg = col[big] < 0.0 ? -1.0 : 1.0;
     for (int r = 0; r < 3; ++r) vec[3 * r + k] = sg * col[r];
+  }
+}
+
+// symmetric N x N eigen-decomposition by cyclic Jacobi rotations (N <= 6),
+// eigenvalues ascending, eigenvectors in columns with the canonical sign
+void jacobi_eigh_n(const double* Ain, int N, double* lam, double* vec) {
+  double A[6][6], Vm[6][6];
+  double norm = 0.0;
+  for (int a = 0; a < N; ++a)
+    for (int b = 0; b < N; ++b) {
+      A[a][b] = 0.5 * (Ain[N * a + b] + Ain[N * b + a]);
+      Vm[a][b] = (a == b) ? 1.0 : 0.0;
+      norm += A[a][b] * A[a][b];
+    }
+  norm = std::sqrt(norm);
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int a = 0; a < N; ++a)
+      for (int b = a + 1; b < N; ++b) off += 2.0 * A[a][b] * A[a][b];
+    off = std::sqrt(off);
+    if (off <= 1e-15 * norm || off == 0.0) break;
+    for (int p = 0; p < N; ++p)
+      for (int q = p + 1; q < N; ++q) {
+        if (A[p][q] == 0.0) continue;
+        const double theta = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        // A <- G^T A G, V <- V G with the plane rotation G in (p, q)
+        for (int k = 0; k < N; ++k) {
+          const double akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - sn * akq;
+          A[k][q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < N; ++k) {
+          const double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - sn * aqk;
+          A[q][k] = sn * apk + c * aqk;
+        }
+        for (int k = 0; k < N; ++k) {
+          const double vkp = Vm[k][p], vkq = Vm[k][q];
+          Vm[k][p] = c * vkp - sn * vkq;
+          Vm[k][q] = sn * vkp + c * vkq;
+        }
+      }
+  }
+  int idx[6] = {0, 1, 2, 3, 4, 5};
+  std::sort(idx, idx + N, [&](int a, int b) { return A[a][a] < A[b][b]; });
+  for (int k = 0; k < N; ++k) {
+    lam[k] = A[idx[k]][idx[k]];
+    int big = 0;
+    for (int r = 1; r < N; ++r)
+      if (std::fabs(Vm[r][idx[k]]) > std::fabs(Vm[big][idx[k]])) big = r;
+    const double sg = Vm[big][idx[k]] < 0.0 ? -1.0 : 1.0;
+    for (int r = 0; r < N; ++r) vec[N * r + k] = sg * Vm[r][idx[k]];
   }
 }
 
@@ -874,6 +1063,58 @@ int orc_forward_backward(const float* params, int64_t n, int deg, const float* c
     }
   }
   (void)F;
+  return 0;
+}
+
+// Splitting matrices over theta = (p, log-scales) (dim 6; the paper's theta
+// generalised beyond position, Sec. 4.4): S6[21][n] += sum over views and
+// contributing unclamped pixels of dL/dalpha * Hessian_theta alpha, upper
+// triangle row-major, theta order (p_x, p_y, p_z, s_x, s_y, s_z).  The
+// loss is the fused L1 against target (or the upstream dLdimage).
+int orc_split6(const float* params, int64_t n, int deg, const float* cam_f, const int32_t* cam_i, int V,
+               const double* opts, const float* target, const double* dLdimage, double* S6) {
+  if (n < 0 || V <= 0 || deg < 0 || deg > 3 || (!target && !dLdimage)) return 1;
+  Opts opt = read_opts(opts);
+  std::vector<Cam> cams = read_cams(cam_f, cam_i, V, opt);
+  for (int v = 0; v < V; ++v) {
+    const Cam& cam = cams[v];
+    View view;
+    build_view(params, n, deg, cam, opt, view);
+    std::vector<Grad2D> acc(n);
+    for (auto& a : acc) std::memset(&a, 0, sizeof(a));
+    const double inv = 1.0 / (3.0 * cam.W * cam.H);
+    Pixel px;
+    for (int y = 0; y < cam.H; ++y)
+      for (int x = 0; x < cam.W; ++x) {
+        blend_pixel(view, x, y, px);
+        double dLdC[3];
+        for (int ch = 0; ch < 3; ++ch) {
+          const int64_t e = 3 * cam.pixel_offset + (int64_t)ch * cam.W * cam.H + (int64_t)y * cam.W + x;
+          dLdC[ch] = dLdimage ? dLdimage[e] : sgn(px.C[ch] - target[e]) * inv;
+        }
+        backward_pixel(view, x, y, px, dLdC, acc, nullptr, true);
+      }
+    for (int64_t i = 0; i < n; ++i)
+      for (int k = 0; k < kH6; ++k) S6[(int64_t)k * n + i] += acc[i].H6[k];
+  }
+  return 0;
+}
+
+// alpha at (u, v) of a Gaussian (its projected record in `params`-space:
+// view 0 of `cam`) moved by dth in theta = (p, log-scales), maps frozen; and
+// its Hessian there.  For the pins.
+int orc_alpha_theta6(const float* params, int64_t n, int deg, const float* cam_f, const int32_t* cam_i,
+                     const double* opts, int64_t i, double u, double v, const double* dth, double* alpha,
+                     double* H6) {
+  Opts opt = read_opts(opts);
+  std::vector<Cam> cams = read_cams(cam_f, cam_i, 1, opt);
+  double th[59];
+  load_theta(params, n, deg, i, th);
+  Proj<double> g;
+  project(th, deg, cams[0], opt, g);
+  if (g.depth <= opt.near_z) return 1;
+  *alpha = alpha_theta6<double>(g, opt.dilation, u, v, dth);
+  if (H6) alpha_hessian_theta6(g, opt.dilation, u, v, H6);
   return 0;
 }
 
@@ -1137,6 +1378,55 @@ int64_t orc_densify(const float* params, int64_t n, int deg, const double* S, do
     out_params[(int64_t)10 * out_cap + o + 1] = logit;
   }
   return off[n];
+}
+
+// Steepest Density Control over theta = (p, log-scales): S6 [21][n] (upper
+// triangle of the 6x6 splitting matrix, any scale) times s_scale; split iff
+// lambda_min < eps_split; the offspring move by +-eps v_min in theta (both the
+// position and the log-scales) and take o/2; other rows copied.  Same layout
+// as orc_densify; vmin [6][n].
+int64_t orc_densify6(const float* params, int64_t n, int deg, const double* S6, double s_scale, double eps,
+                     double eps_split, double* out_params, int64_t out_cap, double* lam_min, double* vmin,
+                     uint8_t* split, int64_t* needed) {
+  const int F = num_params(deg);
+  for (int64_t i = 0; i < n; ++i) {
+    double M[36], lam[6], vec[36];
+    for (int a = 0; a < 6; ++a)
+      for (int b = 0; b < 6; ++b) M[6 * a + b] = s_scale * S6[(int64_t)h6(a, b) * n + i];
+    jacobi_eigh_n(M, 6, lam, vec);
+    lam_min[i] = lam[0];
+    for (int r = 0; r < 6; ++r) vmin[(int64_t)r * n + i] = vec[6 * r + 0];
+    split[i] = lam[0] < eps_split ? 1 : 0;
+  }
+  std::vector<int64_t> off(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) off[i + 1] = off[i] + 1 + split[i];
+  *needed = off[n];
+  if (off[n] > out_cap) return -1;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t o = off[i];
+    for (int f = 0; f < F; ++f) {
+      const double x = params[(int64_t)f * n + i];
+      out_params[(int64_t)f * out_cap + o] = x;
+      if (split[i]) out_params[(int64_t)f * out_cap + o + 1] = x;
+    }
+    if (!split[i]) continue;
+    for (int k = 0; k < 6; ++k) {  // rows 0-2 position, 3-5 log-scales
+      const double x = params[(int64_t)k * n + i], d = vmin[(int64_t)k * n + i];
+      out_params[(int64_t)k * out_cap + o] = x + eps * d;
+      out_params[(int64_t)k * out_cap + o + 1] = x - eps * d;
+    }
+    const double op = 1.0 / (1.0 + std::exp(-(double)params[(int64_t)10 * n + i]));
+    const double oh = 0.5 * op;
+    const double logit = std::log(oh / (1.0 - oh));
+    out_params[(int64_t)10 * out_cap + o] = logit;
+    out_params[(int64_t)10 * out_cap + o + 1] = logit;
+  }
+  return off[n];
+}
+
+// eigen-decomposition of m symmetric N x N matrices (N <= 6) S[m][N*N]
+void orc_eigh_n(const double* S, int64_t m, int N, double* lam, double* vec) {
+  for (int64_t k = 0; k < m; ++k) jacobi_eigh_n(S + (int64_t)N * N * k, N, lam + N * k, vec + (int64_t)N * N * k);
 }
 
 }  // extern "C"

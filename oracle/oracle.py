@@ -73,6 +73,16 @@ def lib():
                                   C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.c_double, C.c_int64, _c_f64,
                                   C.c_int64, _c_f64, _c_f64, _c_u8, C.POINTER(C.c_int64)]
         L.orc_densify.restype = C.c_int64
+        L.orc_split6.argtypes = common + [C.c_void_p, C.c_void_p, _c_f64]
+        L.orc_split6.restype = C.c_int
+        L.orc_alpha_theta6.argtypes = [_c_f32, C.c_int64, C.c_int, _c_f32, _c_i32, _c_f64, C.c_int64, C.c_double,
+                                       C.c_double, _c_f64, C.POINTER(C.c_double), C.c_void_p]
+        L.orc_alpha_theta6.restype = C.c_int
+        L.orc_densify6.argtypes = [_c_f32, C.c_int64, C.c_int, _c_f64, C.c_double, C.c_double, C.c_double, _c_f64,
+                                   C.c_int64, _c_f64, _c_f64, _c_u8, C.POINTER(C.c_int64)]
+        L.orc_densify6.restype = C.c_int64
+        L.orc_eigh_n.argtypes = [_c_f64, C.c_int64, C.c_int, _c_f64, _c_f64]
+        L.orc_eigh_n.restype = None
         L.orc_tile_lists.argtypes = common + [_c_i64, C.c_int64, _c_i64, C.c_void_p]
         L.orc_tile_lists.restype = C.c_int
         L.orc_num_params.argtypes = [C.c_int]
@@ -322,3 +332,74 @@ def split_remap(state, split):
     keep = ~split
     out[:, off[keep]] = state[:, keep]
     return out
+
+
+# ----------------------------------------------------------------------------
+# splitting matrices over theta = (p, log-scales), dimension 6
+
+H6_PAIRS = [(i, j) for i in range(6) for j in range(i, 6)]  # upper triangle, row-major
+
+
+def h6_to_mats(S21):
+    """[21][n] upper triangles -> [n][6][6] symmetric"""
+    S21 = np.asarray(S21, np.float64)
+    n = S21.shape[1]
+    M = np.zeros((n, 6, 6))
+    for k, (i, j) in enumerate(H6_PAIRS):
+        M[:, i, j] = S21[k]
+        M[:, j, i] = S21[k]
+    return M
+
+
+def split6(params, sh_degree, cams, opts, target=None, dl_dimage=None):
+    """S over theta = (p, log-scales): [21][n] upper triangle of the 6x6 per
+    Gaussian, summed over views and contributing unclamped pixels of
+    dL/dalpha * Hessian_theta alpha (the projection's maps frozen)."""
+    args = _common(params, sh_degree, cams, opts)
+    n = args[1]
+    tgt = None if target is None else np.ascontiguousarray(target, np.float32)
+    dld = None if dl_dimage is None else np.ascontiguousarray(dl_dimage, np.float64)
+    S21 = np.zeros((21, n), np.float64)
+    assert lib().orc_split6(*args, _ptr(tgt), _ptr(dld), S21) == 0
+    return S21
+
+
+def alpha_theta6(params, sh_degree, cam1, opts, i, u, v, dth, hessian=False):
+    """alpha of Gaussian i (single-view camera cam1) at pixel (u, v) with
+    theta = (p, log-scales) moved by dth, maps frozen; optionally the Hessian
+    [21] at dth = 0."""
+    params = np.ascontiguousarray(params, np.float32)
+    cf, ci = cam_arrays(cam1)
+    a = C.c_double(0.0)
+    H = np.zeros(21, np.float64) if hessian else None
+    rc = lib().orc_alpha_theta6(params, params.shape[1], sh_degree, cf, ci, opts_array(opts), int(i), float(u),
+                                float(v), np.ascontiguousarray(dth, np.float64), C.byref(a), _ptr(H))
+    assert rc == 0
+    return (a.value, H) if hessian else a.value
+
+
+def eigh_n(S):
+    """ascending eigenvalues and column eigenvectors of [m][N][N] symmetric (N <= 6)"""
+    S = np.ascontiguousarray(np.asarray(S, np.float64))
+    m, N = S.shape[0], S.shape[1]
+    lam = np.zeros((m, N), np.float64)
+    vec = np.zeros((m, N, N), np.float64)
+    lib().orc_eigh_n(S.reshape(m, N * N), m, N, lam, vec.reshape(m, N * N))
+    return lam, vec
+
+
+def densify6(params, sh_degree, S21, s_scale, eps, eps_split, out_cap=None):
+    """Steepest Density Control over theta = (p, log-scales)."""
+    params = np.ascontiguousarray(params, np.float32)
+    F, n = params.shape
+    S21 = np.ascontiguousarray(S21, np.float64).reshape(21, n)
+    cap = 2 * n if out_cap is None else out_cap
+    out = np.zeros((F, max(cap, 1)), np.float64)
+    lam = np.zeros(n, np.float64)
+    vmin = np.zeros((6, n), np.float64)
+    split = np.zeros(n, np.uint8)
+    need = C.c_int64(0)
+    n_out = lib().orc_densify6(params, n, sh_degree, S21, float(s_scale), float(eps), float(eps_split), out, cap,
+                               lam, vmin, split, C.byref(need))
+    return dict(n_out=int(n_out), needed=int(need.value), params=out[:, :max(n_out, 0)], lambda_min=lam,
+                vmin=vmin, split=split.astype(bool))
