@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eps", type=float, default=1e-3)
+    ap.add_argument("--theta-dim", type=int, choices=(3, 6), default=3,
+                    help="splitting matrix over the position (3, the paper's) or position and log-scales (6)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration under a profiler)")
     return ap.parse_args()
@@ -187,7 +189,7 @@ def main():
     target = torch.from_numpy(scene.target).to(dev)
     cams = CameraBatch(scene.cams, opts, dev)
 
-    step = BatchedStep(P, scene.sh_degree, cams, target, eps=args.eps, eps_split=-1e-6)
+    step = BatchedStep(P, scene.sh_degree, cams, target, eps=args.eps, eps_split=-1e-6, theta_dim=args.theta_dim)
     K = step.prepare()
     say(f"instances K={K} tiles={cams.total_tiles}")
     for _ in range(max(args.warmup, 1)):
@@ -229,7 +231,8 @@ def main():
     per_view = None
     if not args.no_per_view:
         step.graph = None
-        pv = PerViewStep(P, scene.sh_degree, scene.cams, opts, target, eps=args.eps, eps_split=-1e-6)
+        pv = PerViewStep(P, scene.sh_degree, scene.cams, opts, target, eps=args.eps, eps_split=-1e-6,
+                         theta_dim=args.theta_dim)
         pv.prepare()
         for _ in range(max(args.warmup, 1)):
             pv.run()
@@ -289,7 +292,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "gaussians": n, "views": V, "pixels": Px, "sh_degree": scene.sh_degree,
                    "resolutions": [f"{w}x{h}" for w, h in zip(cams.widths, cams.heights)],
-                   "tile": f"{opts['tile_w']}x{opts['tile_h']}", "graph": use_graph, "eps_split": -1e-6},
+                   "tile": f"{opts['tile_w']}x{opts['tile_h']}", "graph": use_graph, "eps_split": -1e-6,
+                   "theta_dim": args.theta_dim},
         "step_ms_p10_p50_p90": [round(float(x), 4) for x in pct],
         "peak_allocated_gib": round(peak_gb, 3),
         "per_view_ms_per_step": None if per_view is None else round(per_view, 4),

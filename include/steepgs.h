@@ -125,8 +125,9 @@ steepgs_status steepgs_layout_cameras(steepgs_camera* cams, int32_t V, const ste
                                       int64_t* total_pixels, int32_t* total_tiles);
 
 /* Workspace (device bytes) each stage needs.  stage: 1 sort, 2 render_fwd,
- * 3 render_bwd_split, 4 densify (project needs none).  n = Gaussians, V =
- * views, capacity = instance capacity of the sort. */
+ * 3 render_bwd_split, 4 densify (and densify6), 5 render_bwd_split6 (project
+ * needs none).  n = Gaussians, V = views, capacity = instance capacity of the
+ * sort. */
 size_t steepgs_workspace_size(int32_t stage, int64_t n, int32_t V, uint64_t capacity, int32_t total_tiles);
 
 /* Stage 1 -- projection (Sec. 3, Eqs. sigma_3D / sigma_2D).
@@ -191,6 +192,28 @@ steepgs_status steepgs_render_bwd_split(const float* d_params, int64_t n, int32_
                                         const float* d_target, float* d_grads, float* d_S, float* d_grad2d,
                                         void* d_ws, size_t ws_bytes, void* stream);
 
+/* Stage 4 over theta = (p, log-scales) (dim 6; Sec. 4.4 defines S_i over the
+ * parameters the Hessian is taken in, the paper's experiments use p alone):
+ * as steepgs_render_bwd_split, and in addition
+ *   d_S6 [21][n] (+=) the 6x6 splitting matrix, upper triangle row-major
+ *                over (p_x, p_y, p_z, s_x, s_y, s_z) (s = log-scales):
+ *                sum over views and contributing unclamped pixels of
+ *                dL/dalpha * Hessian_theta alpha, with the projection's maps
+ *                frozen at the point (the mean moves along the exact
+ *                Jacobian of the projection, the 2D covariance is
+ *                P Sigma(s) P^T + dilation with P at the guarded point;
+ *                App. C.4's approximation, extended to the scales).
+ * d_S (nullable here) receives the dim-3 S as before.  No d_grad2d output.
+ * Workspace: steepgs_workspace_size(5, ...). */
+steepgs_status steepgs_render_bwd_split6(const float* d_params, int64_t n, int32_t sh_degree,
+                                         const steepgs_camera* d_cams, int32_t V, const steepgs_opts* opts,
+                                         const steepgs_splat* d_splats, const uint32_t* d_tiles_touched,
+                                         const uint32_t* d_vals, const uint32_t* d_tile_ranges, int32_t total_tiles,
+                                         int64_t total_pixels, const float* d_image, const float* d_T_final,
+                                         const uint32_t* d_n_contrib, const float* d_dL_dimage,
+                                         const float* d_target, float* d_grads, float* d_S, float* d_S6,
+                                         void* d_ws, size_t ws_bytes, void* stream);
+
 /* Optional selection rules of the split step (the paper's "Variants" and
  * Algorithm 1's "condition on G"):
  *  - compactest splitting: a Gaussian is a candidate only when also
@@ -233,6 +256,18 @@ steepgs_status steepgs_densify(const float* d_params, int64_t n, int32_t sh_degr
                                int64_t out_capacity, int64_t* d_n_out,
                                float* d_lambda_min, float* d_vmin, uint8_t* d_split, int32_t* d_status, void* d_ws,
                                size_t ws_bytes, void* stream);
+
+/* Stage 5 over theta = (p, log-scales): S' = s_scale * S6 (d_S6 [21][n] as
+ * steepgs_render_bwd_split6 fills it); smallest eigenpair of the 6x6 by cyclic
+ * Jacobi rotations in fp64; split iff lambda_min < eps_split; the offspring
+ * move by +- eps v_min in theta -- position rows 0-2 and log-scale rows 3-5
+ * -- and take o/2 (logit re-derived); other rows copied.  Layout, capacity,
+ * status and outputs as steepgs_densify, with d_vmin [6][n].  Workspace:
+ * steepgs_workspace_size(4, ...). */
+steepgs_status steepgs_densify6(const float* d_params, int64_t n, int32_t sh_degree, const float* d_S6,
+                                float s_scale, float eps, float eps_split, float* d_out, int64_t out_capacity,
+                                int64_t* d_n_out, float* d_lambda_min, float* d_vmin, uint8_t* d_split,
+                                int32_t* d_status, void* d_ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Training-loop support (Algorithm 1 around the hot path). */

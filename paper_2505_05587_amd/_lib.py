@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libsteepgs.so")
 STATUS = {0: "ok", 1: "invalid argument", 2: "output capacity exceeded", 3: "HIP runtime error",
           4: "workspace too small"}
 OK, ERR_INVALID_ARG, ERR_CAPACITY, ERR_HIP, ERR_WORKSPACE = 0, 1, 2, 3, 4
-STAGE_SORT, STAGE_RENDER_FWD, STAGE_RENDER_BWD, STAGE_DENSIFY = 1, 2, 3, 4
+STAGE_SORT, STAGE_RENDER_FWD, STAGE_RENDER_BWD, STAGE_DENSIFY, STAGE_RENDER_BWD6 = 1, 2, 3, 4, 5
 
 
 class Camera(C.Structure):
@@ -79,10 +79,13 @@ def lib():
                                                vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.steepgs_densify.argtypes = [vp, i64, i32, vp, f32, f32, f32, C.POINTER(SplitSelect), vp, i64, vp, vp, vp,
                                       vp, vp, vp, sz, vp]
+        L.steepgs_render_bwd_split6.argtypes = L.steepgs_render_bwd_split.argtypes
+        L.steepgs_densify6.argtypes = [vp, i64, i32, vp, f32, f32, f32, vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]
         L.steepgs_adam_step.argtypes = [vp, vp, vp, vp, i64, i32, C.POINTER(AdamOpts), vp, vp, vp, vp]
         L.steepgs_split_remap.argtypes = [vp, i32, i64, vp, vp, i64, vp, sz, vp]
         for fn in ("steepgs_layout_cameras", "steepgs_project", "steepgs_sort", "steepgs_render_fwd",
-                   "steepgs_render_bwd_split", "steepgs_densify", "steepgs_adam_step", "steepgs_split_remap"):
+                   "steepgs_render_bwd_split", "steepgs_densify", "steepgs_adam_step", "steepgs_split_remap",
+                   "steepgs_render_bwd_split6", "steepgs_densify6"):
             getattr(L, fn).restype = C.c_int
         L.steepgs_status_string.argtypes = [C.c_int]
         L.steepgs_status_string.restype = C.c_char_p
@@ -180,6 +183,25 @@ def steepgs_render_bwd_split(params, n, sh_degree, d_cams, V, opts, splats, tile
                                           _p(image), _p(T_final), _p(n_contrib), _p(dL_dimage), _p(target),
                                           _p(grads), _p(S), _p(grad2d), _p(ws), ws.numel() * ws.element_size(),
                                           _stream(stream)))
+
+
+def steepgs_render_bwd_split6(params, n, sh_degree, d_cams, V, opts, splats, tiles_touched, vals, tile_ranges,
+                              total_tiles, total_pixels, image, T_final, n_contrib, dL_dimage, target, grads, S, S6,
+                              ws, stream=None):
+    _check("steepgs_render_bwd_split6",
+           lib().steepgs_render_bwd_split6(_p(params), n, sh_degree, _p(d_cams), V, C.byref(opts), _p(splats),
+                                           _p(tiles_touched), _p(vals), _p(tile_ranges), total_tiles, total_pixels,
+                                           _p(image), _p(T_final), _p(n_contrib), _p(dL_dimage), _p(target),
+                                           _p(grads), _p(S), _p(S6), _p(ws), ws.numel() * ws.element_size(),
+                                           _stream(stream)))
+
+
+def steepgs_densify6(params, n, sh_degree, S6, s_scale, eps, eps_split, out, out_capacity, n_out, lambda_min, vmin,
+                     split, status, ws, stream=None):
+    _check("steepgs_densify6",
+           lib().steepgs_densify6(_p(params), n, sh_degree, _p(S6), float(s_scale), float(eps), float(eps_split),
+                                  _p(out), out_capacity, _p(n_out), _p(lambda_min), _p(vmin), _p(split), _p(status),
+                                  _p(ws), ws.numel() * ws.element_size(), _stream(stream)))
 
 
 def steepgs_densify(params, n, sh_degree, S, s_scale, eps, eps_split, out, out_capacity, n_out, lambda_min, vmin,

@@ -231,10 +231,12 @@ __global__ void k_densify_total(const uint32_t* __restrict__ total, int64_t n, i
   *status = need > cap ? (int32_t)STEEPGS_ERR_CAPACITY : (int32_t)STEEPGS_OK;
 }
 
+// rows: the leading parameter rows the offspring move along +-eps v_min (3:
+// the position; 6: the position and the log-scales)
 __global__ void __launch_bounds__(256) k_densify_scatter(const float* __restrict__ params, int64_t n, int F,
                                                          const uint32_t* __restrict__ flag,
                                                          const uint32_t* __restrict__ before,
-                                                         const float* __restrict__ vmin, float eps,
+                                                         const float* __restrict__ vmin, int rows, float eps,
                                                          float* __restrict__ out, int64_t cap,
                                                          const int32_t* __restrict__ status) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -247,7 +249,7 @@ __global__ void __launch_bounds__(256) k_densify_scatter(const float* __restrict
     if (split) out[(int64_t)f * cap + o + 1] = x;
   }
   if (!split) return;
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < rows; ++k) {
     const double p = params[(int64_t)k * n + i];
     const double d = (double)eps * (double)vmin[k * n + i];
     out[(int64_t)k * cap + o] = (float)(p + d);
@@ -275,7 +277,7 @@ struct DensWs {
 static size_t densify_layout(void* base, int64_t n, DensWs& w) {
   Carver c(base);
   w.lam = c.take<float>(n);
-  w.vmin = c.take<float>(3 * n);
+  w.vmin = c.take<float>(6 * n);  // room for the dim-6 eigenvectors
   w.flag = c.take<uint32_t>(n);
   w.before = c.take<uint32_t>(n);
   w.partials = c.take<uint32_t>(scan_partials_count(n) + 1);
@@ -303,6 +305,98 @@ __global__ void k_flag_u8(const uint32_t* __restrict__ f, uint8_t* __restrict__ 
 __global__ void k_densify_empty(int64_t* n_out, int32_t* status) {
   *n_out = 0;
   *status = STEEPGS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// splitting matrix over theta = (p, log-scales): smallest eigenpair of a
+// symmetric 6x6 by cyclic Jacobi rotations in fp64 (no closed form beyond 4x4)
+
+SG_DEV int h6_index(int i, int j) { return i <= j ? i * 6 - i * (i - 1) / 2 + (j - i) : j * 6 - j * (j - 1) / 2 + (i - j); }
+
+SG_DEV void eig6_min(const double s[21], double& lam_min, double v[6]) {
+  double A[6][6], Q[6][6];
+  double norm2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < 6; ++a)
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+      A[a][b] = s[h6_index(a, b)];
+      Q[a][b] = a == b ? 1.0 : 0.0;
+      norm2 += A[a][b] * A[a][b];
+    }
+  for (int sweep = 0; sweep < 50; ++sweep) {
+    double off = 0.0;
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+#pragma unroll
+      for (int b = a + 1; b < 6; ++b) off += A[a][b] * A[a][b];
+    if (!(2.0 * off > 1e-30 * norm2)) break;
+#pragma unroll
+    for (int p = 0; p < 6; ++p)
+#pragma unroll
+      for (int q = p + 1; q < 6; ++q) {
+        const double apq = A[p][q];
+        if (apq == 0.0) continue;
+        // the plane rotation (p, q) that zeroes A[p][q]
+        const double th = (A[q][q] - A[p][p]) / (2.0 * apq);
+        const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          const double akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - sn * akq;
+          A[k][q] = sn * akp + c * akq;
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          const double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - sn * aqk;
+          A[q][k] = sn * apk + c * aqk;
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          const double qkp = Q[k][p], qkq = Q[k][q];
+          Q[k][p] = c * qkp - sn * qkq;
+          Q[k][q] = sn * qkp + c * qkq;
+        }
+      }
+  }
+  int m = 0;
+#pragma unroll
+  for (int k = 1; k < 6; ++k)
+    if (A[k][k] < A[m][m]) m = k;
+  lam_min = A[0][0];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    if (k == m) lam_min = A[k][k];
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+      if (k == m) v[r] = Q[r][k];
+  }
+  // canonical sign: largest-magnitude component positive (ties: lowest index)
+  int big = 0;
+#pragma unroll
+  for (int r = 1; r < 6; ++r)
+    if (fabs(v[r]) > fabs(v[big])) big = r;
+  const double sg = v[big] < 0.0 ? -1.0 : 1.0;
+#pragma unroll
+  for (int r = 0; r < 6; ++r) v[r] *= sg;
+}
+
+__global__ void __launch_bounds__(128) k_densify6_eig(const float* __restrict__ S6, int64_t n, float s_scale,
+                                                      float eps_split, float* __restrict__ lam_out,
+                                                      float* __restrict__ v_out, uint32_t* __restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s[21];
+#pragma unroll
+  for (int k = 0; k < 21; ++k) s[k] = (double)s_scale * (double)S6[k * n + i];
+  double lam, v[6];
+  eig6_min(s, lam, v);
+  lam_out[i] = (float)lam;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) v_out[k * n + i] = (float)v[k];
+  flag[i] = lam < (double)eps_split ? 1u : 0u;
 }
 
 }  // namespace sg
@@ -359,10 +453,49 @@ extern "C" steepgs_status steepgs_densify(const float* d_params, int64_t n, int3
   hipLaunchKernelGGL(k_densify_total, dim3(1), dim3(1), 0, st, w.partials + scan_partials_count(n), n, out_capacity,
                      d_n_out, d_status);
   if (out_capacity > 0)
-    hipLaunchKernelGGL(k_densify_scatter, dim3(nb), dim3(256), 0, st, d_params, n, F, w.flag, w.before, w.vmin, eps,
+    hipLaunchKernelGGL(k_densify_scatter, dim3(nb), dim3(256), 0, st, d_params, n, F, w.flag, w.before, w.vmin, 3, eps,
                        d_out, out_capacity, d_status);
   if (d_lambda_min) hipLaunchKernelGGL(k_copy_f32, dim3(nb), dim3(256), 0, st, w.lam, d_lambda_min, n);
   if (d_vmin) hipLaunchKernelGGL(k_copy_f32, dim3((unsigned)ceil_div(3 * n, 256)), dim3(256), 0, st, w.vmin, d_vmin, 3 * n);
+  if (d_split) hipLaunchKernelGGL(k_flag_u8, dim3(nb), dim3(256), 0, st, w.flag, d_split, n);
+  SG_TRY_LAUNCH();
+  return STEEPGS_OK;
+}
+
+extern "C" steepgs_status steepgs_densify6(const float* d_params, int64_t n, int32_t sh_degree, const float* d_S6,
+                                           float s_scale, float eps, float eps_split, float* d_out,
+                                           int64_t out_capacity, int64_t* d_n_out, float* d_lambda_min,
+                                           float* d_vmin, uint8_t* d_split, int32_t* d_status, void* d_ws,
+                                           size_t ws_bytes, void* stream) {
+  if (n < 0 || sh_degree < 0 || sh_degree > 3 || out_capacity < 0 || !d_n_out || !d_status)
+    return STEEPGS_ERR_INVALID_ARG;
+  if (n >= (int64_t)1 << 31) return STEEPGS_ERR_INVALID_ARG;
+  hipStream_t st = as_stream(stream);
+  if (n == 0) {
+    hipLaunchKernelGGL(k_densify_empty, dim3(1), dim3(1), 0, st, d_n_out, d_status);
+    SG_TRY_LAUNCH();
+    return STEEPGS_OK;
+  }
+  if (!d_params || !d_S6 || (out_capacity > 0 && !d_out)) return STEEPGS_ERR_INVALID_ARG;
+  DensWs w;
+  const size_t need = densify_layout(nullptr, n, w);
+  if (!d_ws || ws_bytes < need) return STEEPGS_ERR_WORKSPACE;
+  densify_layout(d_ws, n, w);
+  const int F = STEEPGS_NUM_PARAMS(sh_degree);
+  const unsigned nb = (unsigned)ceil_div(n, 256);
+  timer_begin(STEEPGS_TIMER_DENSIFY, st);
+  hipLaunchKernelGGL(k_densify6_eig, dim3((unsigned)ceil_div(n, 128)), dim3(128), 0, st, d_S6, n, s_scale, eps_split,
+                     w.lam, w.vmin, w.flag);
+  timer_end(STEEPGS_TIMER_DENSIFY, st);
+  if (exclusive_scan<LoadFlags, uint32_t, uint32_t>(LoadFlags{w.flag}, n, w.before, w.partials, st) != hipSuccess)
+    return STEEPGS_ERR_HIP;
+  hipLaunchKernelGGL(k_densify_total, dim3(1), dim3(1), 0, st, w.partials + scan_partials_count(n), n, out_capacity,
+                     d_n_out, d_status);
+  if (out_capacity > 0)
+    hipLaunchKernelGGL(k_densify_scatter, dim3(nb), dim3(256), 0, st, d_params, n, F, w.flag, w.before, w.vmin, 6, eps,
+                       d_out, out_capacity, d_status);
+  if (d_lambda_min) hipLaunchKernelGGL(k_copy_f32, dim3(nb), dim3(256), 0, st, w.lam, d_lambda_min, n);
+  if (d_vmin) hipLaunchKernelGGL(k_copy_f32, dim3((unsigned)ceil_div(6 * n, 256)), dim3(256), 0, st, w.vmin, d_vmin, 6 * n);
   if (d_split) hipLaunchKernelGGL(k_flag_u8, dim3(nb), dim3(256), 0, st, w.flag, d_split, n);
   SG_TRY_LAUNCH();
   return STEEPGS_OK;

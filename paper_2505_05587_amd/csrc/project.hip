@@ -187,6 +187,7 @@ size_t sort_workspace(int64_t m, uint64_t cap);
 size_t render_fwd_workspace();
 size_t render_bwd_workspace(int64_t m);
 size_t densify_workspace(int64_t n);
+size_t render_bwd6_workspace(int64_t m);
 }  // namespace sg
 
 extern "C" size_t steepgs_workspace_size(int32_t stage, int64_t n, int32_t V, uint64_t capacity,
@@ -199,6 +200,7 @@ extern "C" size_t steepgs_workspace_size(int32_t stage, int64_t n, int32_t V, ui
     case 2: return sg::render_fwd_workspace();
     case 3: return sg::render_bwd_workspace(m);
     case 4: return sg::densify_workspace(n);
+    case 5: return sg::render_bwd6_workspace(m);
     default: return 0;
   }
 }

@@ -39,9 +39,15 @@ constexpr int kBwdWaves = 4;    // wavefronts per workgroup, each on a tile of i
 // 0-8; when the buffer is the caller's, a last pass turns entries 0-4 into
 // dL/d(mean_x, mean_y, a, b, c)
 constexpr int kG2dStride = 12;
+// with the splitting matrix over theta = (p, log-scales) the slot also holds
+// the third and fourth moments: (m3_xxx, m3_xxy, m3_xyy, m3_yyy,
+// m4_xxxx, m4_xxxy, m4_xxyy, m4_xyyy, m4_yyyy) in entries 9-17
+constexpr int kG2dStride6 = 20;
 
-template <int TW, int TH>
-__global__ void __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_per_eu(6))) k_render_bwd(const steepgs_splat* __restrict__ splats,
+// H6: also the moments the dim-6 splitting matrix needs (third and fourth
+// order in d), summed like the others
+template <int TW, int TH, bool H6>
+__global__ void __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_per_eu(H6 ? 4 : 6))) k_render_bwd(const steepgs_splat* __restrict__ splats,
                                                                const uint32_t* __restrict__ vals,
                                                                const uint32_t* __restrict__ ranges,
                                                                const steepgs_camera* __restrict__ cams, int V,
@@ -166,6 +172,7 @@ __global__ void __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_pe
         // moments of g alpha d over the tile's pixels (the mean and conic
         // gradients are linear in them), opacity and colour gradients
         float mx = 0.f, my = 0.f, mxx = 0.f, mxy = 0.f, myy = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
+        float h3[4] = {0.f, 0.f, 0.f, 0.f}, h4[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
         bool any = false;
         float blue = 0.f;
         bool blue_loaded = false;
@@ -207,6 +214,19 @@ __global__ void __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_pe
             mxy += tx * dy;
             myy += ty * dy;
             go += g * G;
+            if (H6) {
+              const float txx = tx * dx, tyy = ty * dy;
+              h3[0] += txx * dx;
+              h3[1] += txx * dy;
+              h3[2] += tyy * dx;
+              h3[3] += tyy * dy;
+              const float dxx = dx * dx, dxy = dx * dy, dyy = dy * dy;
+              h4[0] += txx * dxx;
+              h4[1] += txx * dxy;
+              h4[2] += txx * dyy;
+              h4[3] += tyy * dxy;
+              h4[4] += tyy * dyy;
+            }
           }
         }
         if (ballot(any)) {
@@ -214,8 +234,13 @@ __global__ void __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_pe
           // nine-lane atomic into the record's 48-byte slot
           const float part[9] = {mx, my, mxx, mxy, myy, go, gr, gg, gbl};
           const float tot = reduce9(part);
-          float* const slot = g2d + (int64_t)__float_as_uint(E[j].y) * kG2dStride;
+          float* const slot = g2d + (int64_t)__float_as_uint(E[j].y) * (H6 ? kG2dStride6 : kG2dStride);
           if (red_idx >= 0) unsafeAtomicAdd(slot + red_idx, tot);
+          if (H6) {
+            const float part2[9] = {h3[0], h3[1], h3[2], h3[3], h4[0], h4[1], h4[2], h4[3], h4[4]};
+            const float tot2 = reduce9(part2);
+            if (red_idx >= 0) unsafeAtomicAdd(slot + 9 + red_idx, tot2);
+          }
         }
       }
     }
@@ -253,7 +278,7 @@ template <int D>
 __global__ void __launch_bounds__(128) k_proj_bwd(const float* __restrict__ params, int64_t n,
                                                   const steepgs_camera* __restrict__ cams, int V, steepgs_opts opt,
                                                   const uint32_t* __restrict__ tiles, const float* __restrict__ g2d,
-                                                  float* __restrict__ grads, float* __restrict__ S) {
+                                                  int stride, float* __restrict__ grads, float* __restrict__ S) {
   constexpr int NB = (D + 1) * (D + 1);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -290,7 +315,7 @@ __global__ void __launch_bounds__(128) k_proj_bwd(const float* __restrict__ para
     if (tiles[r] == 0) continue;
     float G9[9];
     {
-      const float4* slot = reinterpret_cast<const float4*>(g2d + r * kG2dStride);
+      const float4* slot = reinterpret_cast<const float4*>(g2d + r * stride);
       const float4 u0 = slot[0], u1 = slot[1], u2 = slot[2];
       G9[0] = u0.x; G9[1] = u0.y; G9[2] = u0.z; G9[3] = u0.w;
       G9[4] = u1.x; G9[5] = u1.y; G9[6] = u1.z; G9[7] = u1.w;
@@ -492,7 +517,171 @@ __global__ void __launch_bounds__(128) k_proj_bwd(const float* __restrict__ para
   gp[STEEPGS_ROW_OPACITY * n] += dop * o * (1.f - o);
 #pragma unroll
   for (int k = 0; k < 3 * NB; ++k) gp[(STEEPGS_ROW_SH + k) * n] += dsh[k];
-  for (int k = 0; k < 6; ++k) S[k * n + i] += S3[k];
+  if (S)
+    for (int k = 0; k < 6; ++k) S[k * n + i] += S3[k];
+}
+
+// ---------------------------------------------------------------------------
+// kernel 3 (dim 6): the splitting matrix over theta = (p, log-scales), from the
+// pixel moments of every view.  With the projection's maps frozen at the point
+// (the mean moves along the exact Jacobian Pe, the 2D covariance is
+// Pg Sigma(s) Pg^T + dilation, Pg = J W with J at the guarded point), per
+// pixel q = d^T A d has
+//   dq/dp = -2 Pe^T A d,  dq/ds_k = -2 sig_k^2 z_k^2,  z_k = a_k . d,
+//   a_k = A w_k, w_k = Pg r_k (r_k the k-th axis of the rotation, sig_k^2 =
+//   exp(2 s_k)), d2q/dp2 = 2 Pe^T A Pe, d2q/dp ds_k = 4 sig_k^2 z_k Pe^T a_k,
+//   d2q/ds_j ds_k = -4 sig_k^2 [j = k] z_k^2 + 8 sig_j^2 sig_k^2 M_jk z_j z_k,
+//   M_jk = w_j^T A w_k,
+// and Hess alpha = alpha (dq dq^T / 4 - d2q / 2).  Summed with g = dL/dalpha
+// over a view's pixels, every block is a contraction of the moments
+// m0 = sum g alpha, m1 = sum g alpha d, m2 (second), m3 (third), m4 (fourth):
+//   S_pp = Pe^T (A m2 A - m0 A) Pe,
+//   S_ps[:, k] = sig_k^2 Pe^T (A T3(a_k) - 2 (a_k . m1) a_k),
+//   S_ss[j][k] = sig_j^2 sig_k^2 T4(a_j, a_k) + 2 sig_k^2 [j = k] T2(a_k, a_k)
+//                - 4 sig_j^2 sig_k^2 M_jk T2(a_j, a_k),
+// T2(a, b) = a^T m2 b, T3(a) = sum g alpha d (a . d)^2, T4(a, b) =
+// sum g alpha (a . d)^2 (b . d)^2.  S6 [21][n] accumulates the upper triangle,
+// row-major over (p_x, p_y, p_z, s_x, s_y, s_z).
+
+SG_DEV int h6_slot(int i, int j) { return i <= j ? i * 6 - i * (i - 1) / 2 + (j - i) : j * 6 - j * (j - 1) / 2 + (i - j); }
+
+// coefficients of (a . d)^2 in (dx^2, dx dy, dy^2)
+SG_DEV void sq_coef(const float a[2], float c[3]) {
+  c[0] = a[0] * a[0];
+  c[1] = 2.f * a[0] * a[1];
+  c[2] = a[1] * a[1];
+}
+
+__global__ void __launch_bounds__(128) k_split6_lift(const float* __restrict__ params, int64_t n,
+                                                     const steepgs_camera* __restrict__ cams, int V, steepgs_opts opt,
+                                                     const uint32_t* __restrict__ tiles, const float* __restrict__ g2d,
+                                                     float* __restrict__ S6) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float p[3], q[4], s2[3];
+  for (int k = 0; k < 3; ++k) p[k] = params[(STEEPGS_ROW_MEAN + k) * n + i];
+  for (int k = 0; k < 4; ++k) q[k] = params[(STEEPGS_ROW_QUAT + k) * n + i];
+  for (int k = 0; k < 3; ++k) s2[k] = expf(2.f * params[(STEEPGS_ROW_LOG_SCALE + k) * n + i]);
+  const float qn = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  const float w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+  const float Rq[3][3] = {{1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y)},
+                          {2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x)},
+                          {2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)}};
+  const float o = 1.f / (1.f + expf(-params[STEEPGS_ROW_OPACITY * n + i]));
+  float acc[21];
+#pragma unroll
+  for (int k = 0; k < 21; ++k) acc[k] = 0.f;
+  for (int v = 0; v < V; ++v) {
+    const int64_t r = (int64_t)v * n + i;
+    if (tiles[r] == 0) continue;
+    const float* slot = g2d + r * kG2dStride6;
+    const float m1[2] = {slot[0], slot[1]};
+    const float m2[3] = {slot[2], slot[3], slot[4]};  // xx, xy, yy
+    const float go = slot[5];
+    const float m3[4] = {slot[9], slot[10], slot[11], slot[12]};  // xxx, xxy, xyy, yyy
+    const float m4[5] = {slot[13], slot[14], slot[15], slot[16], slot[17]};  // xxxx .. yyyy
+    if (m1[0] == 0.f && m1[1] == 0.f && m2[0] == 0.f && m2[1] == 0.f && m2[2] == 0.f && go == 0.f) continue;
+    const steepgs_camera& cam = cams[v];
+    // camera space (fp64 for the guard decision, as the forward)
+    double pcd[3];
+    {
+#pragma clang fp contract(off)
+      for (int k = 0; k < 3; ++k)
+        pcd[k] = (double)cam.R[3 * k + 0] * (double)p[0] + (double)cam.R[3 * k + 1] * (double)p[1] +
+                 (double)cam.R[3 * k + 2] * (double)p[2] + (double)cam.t[k];
+    }
+    float Jg[2][3], Je[2][3];
+    if (cam.model == 0) {
+      double gxd = pcd[0] / pcd[2], gyd = pcd[1] / pcd[2];
+      const double exd = gxd, eyd = gyd;
+      if (opt.frustum_guard > 0.f) {
+        const double limx = (double)opt.frustum_guard * (0.5 * cam.width / (double)cam.fx);
+        const double limy = (double)opt.frustum_guard * (0.5 * cam.height / (double)cam.fy);
+        gxd = gxd < -limx ? -limx : (gxd > limx ? limx : gxd);
+        gyd = gyd < -limy ? -limy : (gyd > limy ? limy : gyd);
+      }
+      const float iz = (float)(1.0 / pcd[2]);
+      Jg[0][0] = cam.fx * iz; Jg[0][1] = 0.f; Jg[0][2] = -cam.fx * (float)gxd * iz;
+      Jg[1][0] = 0.f; Jg[1][1] = cam.fy * iz; Jg[1][2] = -cam.fy * (float)gyd * iz;
+      Je[0][0] = Jg[0][0]; Je[0][1] = 0.f; Je[0][2] = -cam.fx * (float)exd * iz;
+      Je[1][0] = 0.f; Je[1][1] = Jg[1][1]; Je[1][2] = -cam.fy * (float)eyd * iz;
+    } else {
+      Jg[0][0] = cam.fx; Jg[0][1] = 0.f; Jg[0][2] = 0.f;
+      Jg[1][0] = 0.f; Jg[1][1] = cam.fy; Jg[1][2] = 0.f;
+      for (int a = 0; a < 2; ++a)
+        for (int c = 0; c < 3; ++c) Je[a][c] = Jg[a][c];
+    }
+    float Pg[2][3], Pe[2][3];
+    for (int a = 0; a < 2; ++a)
+      for (int c = 0; c < 3; ++c) {
+        Pg[a][c] = Jg[a][0] * cam.R[c] + Jg[a][1] * cam.R[3 + c] + Jg[a][2] * cam.R[6 + c];
+        Pe[a][c] = Je[a][0] * cam.R[c] + Je[a][1] * cam.R[3 + c] + Je[a][2] * cam.R[6 + c];
+      }
+    // w_k = Pg r_k; Sigma_2D = sum_k sig_k^2 w_k w_k^T + dilation; A its inverse
+    float wv[3][2];
+    for (int k = 0; k < 3; ++k)
+      for (int a = 0; a < 2; ++a) wv[k][a] = Pg[a][0] * Rq[0][k] + Pg[a][1] * Rq[1][k] + Pg[a][2] * Rq[2][k];
+    float c00 = opt.dilation, c01 = 0.f, c11 = opt.dilation;
+    for (int k = 0; k < 3; ++k) {
+      c00 += s2[k] * wv[k][0] * wv[k][0];
+      c01 += s2[k] * wv[k][0] * wv[k][1];
+      c11 += s2[k] * wv[k][1] * wv[k][1];
+    }
+    const float idet = (float)(1.0 / ((double)c00 * (double)c11 - (double)c01 * (double)c01));
+    const float A[2][2] = {{c11 * idet, -c01 * idet}, {-c01 * idet, c00 * idet}};
+    const float m0 = o * go;
+    float ak[3][2];
+    for (int k = 0; k < 3; ++k)
+      for (int a = 0; a < 2; ++a) ak[k][a] = A[a][0] * wv[k][0] + A[a][1] * wv[k][1];
+    const float M2[2][2] = {{m2[0], m2[1]}, {m2[1], m2[2]}};
+    // position block: Pe^T (A m2 A - m0 A) Pe
+    float AM[2][2], K[2][2];
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) AM[a][b] = A[a][0] * M2[0][b] + A[a][1] * M2[1][b];
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) K[a][b] = AM[a][0] * A[0][b] + AM[a][1] * A[1][b] - m0 * A[a][b];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = a; b < 3; ++b) {
+        float t = 0.f;
+        for (int x2 = 0; x2 < 2; ++x2)
+          for (int y2 = 0; y2 < 2; ++y2) t += Pe[x2][a] * K[x2][y2] * Pe[y2][b];
+        acc[h6_slot(a, b)] += t;
+      }
+    // mixed block
+    float cf[3][3];
+    for (int k = 0; k < 3; ++k) sq_coef(ak[k], cf[k]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float t3x = cf[k][0] * m3[0] + cf[k][1] * m3[1] + cf[k][2] * m3[2];
+      const float t3y = cf[k][0] * m3[1] + cf[k][1] * m3[2] + cf[k][2] * m3[3];
+      const float c1 = ak[k][0] * m1[0] + ak[k][1] * m1[1];
+      const float vx = A[0][0] * t3x + A[0][1] * t3y - 2.f * c1 * ak[k][0];
+      const float vy = A[1][0] * t3x + A[1][1] * t3y - 2.f * c1 * ak[k][1];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) acc[h6_slot(a, 3 + k)] += s2[k] * (Pe[0][a] * vx + Pe[1][a] * vy);
+    }
+    // scale block
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int k = j; k < 3; ++k) {
+        const float* aj = cf[j];
+        const float* bk = cf[k];
+        const float t4 = aj[0] * bk[0] * m4[0] + (aj[0] * bk[1] + aj[1] * bk[0]) * m4[1] +
+                         (aj[0] * bk[2] + aj[1] * bk[1] + aj[2] * bk[0]) * m4[2] +
+                         (aj[1] * bk[2] + aj[2] * bk[1]) * m4[3] + aj[2] * bk[2] * m4[4];
+        const float t2 = ak[j][0] * (M2[0][0] * ak[k][0] + M2[0][1] * ak[k][1]) +
+                         ak[j][1] * (M2[1][0] * ak[k][0] + M2[1][1] * ak[k][1]);
+        const float Mjk = wv[j][0] * ak[k][0] + wv[j][1] * ak[k][1];
+        float t = s2[j] * s2[k] * (t4 - 4.f * Mjk * t2);
+        if (j == k) t += 2.f * s2[k] * t2;
+        acc[h6_slot(3 + j, 3 + k)] += t;
+      }
+  }
+#pragma unroll
+  for (int k = 0; k < 21; ++k) S6[k * n + i] += acc[k];
 }
 
 // the caller's 2D-gradient buffer: moments -> mean and conic gradients, with
@@ -517,31 +706,97 @@ __global__ void k_zero(float* __restrict__ p, int64_t count) {
     p[i] = 0.f;
 }
 
-static size_t bwd_layout(void* base, int64_t m, float** g2d, uint32_t** queue) {
+static size_t bwd_layout(void* base, int64_t m, int stride, float** g2d, uint32_t** queue) {
   Carver c(base);
   *queue = c.take<uint32_t>(64);
-  *g2d = c.take<float>((size_t)kG2dStride * m);
+  *g2d = c.take<float>((size_t)stride * m);
   return c.used + 256;
 }
 
 size_t render_bwd_workspace(int64_t m) {
   float* g;
   uint32_t* q;
-  return bwd_layout(nullptr, m, &g, &q);
+  return bwd_layout(nullptr, m, kG2dStride, &g, &q);
 }
 
-template <int TW, int TH>
+size_t render_bwd6_workspace(int64_t m) {
+  float* g;
+  uint32_t* q;
+  return bwd_layout(nullptr, m, kG2dStride6, &g, &q);
+}
+
+template <int TW, int TH, bool H6>
 static void launch_bwd(int grid, hipStream_t st, const steepgs_splat* splats, const uint32_t* vals,
                        const uint32_t* ranges, const steepgs_camera* cams, int V, const steepgs_opts& opt,
                        int total_tiles, const float* image, const float* T_final, const uint32_t* n_contrib,
                        const float* dL_dimage, const float* target, float* g2d, int64_t m, uint32_t* queue) {
-  hipLaunchKernelGGL((k_render_bwd<TW, TH>), dim3(grid), dim3(64 * kBwdWaves), 0, st, splats, vals, ranges, cams, V, opt,
+  hipLaunchKernelGGL((k_render_bwd<TW, TH, H6>), dim3(grid), dim3(64 * kBwdWaves), 0, st, splats, vals, ranges, cams, V, opt,
                      total_tiles, image, T_final, n_contrib, dL_dimage, target, g2d, m, queue);
 }
 
 }  // namespace sg
 
 using namespace sg;
+
+static steepgs_status bwd_impl(const float* d_params, int64_t n, int32_t sh_degree, const steepgs_camera* d_cams,
+                               int32_t V, const steepgs_opts* opts, const steepgs_splat* d_splats,
+                               const uint32_t* d_tiles_touched, const uint32_t* d_vals,
+                               const uint32_t* d_tile_ranges, int32_t total_tiles, int64_t total_pixels,
+                               const float* d_image, const float* d_T_final, const uint32_t* d_n_contrib,
+                               const float* d_dL_dimage, const float* d_target, float* d_grads, float* d_S,
+                               float* d_S6, float* d_grad2d, void* d_ws, size_t ws_bytes, void* stream) {
+  const bool h6 = d_S6 != nullptr;
+  if (n < 0 || V <= 0 || sh_degree < 0 || sh_degree > 3 || total_tiles <= 0 || total_pixels <= 0 || !opts_ok(opts))
+    return STEEPGS_ERR_INVALID_ARG;
+  if (!d_cams || !d_tile_ranges || !d_T_final || !d_n_contrib || !d_grads || (!d_S && !h6))
+    return STEEPGS_ERR_INVALID_ARG;
+  if (!d_dL_dimage && (!d_target || !d_image)) return STEEPGS_ERR_INVALID_ARG;
+  if (n == 0) return STEEPGS_OK;
+  if (!d_params || !d_splats || !d_tiles_touched) return STEEPGS_ERR_INVALID_ARG;
+  const int64_t m = (int64_t)V * n;
+  const int stride = h6 ? kG2dStride6 : kG2dStride;
+  float* g2d;
+  uint32_t* queue;
+  const size_t need = bwd_layout(nullptr, m, stride, &g2d, &queue);
+  if (!d_ws || ws_bytes < need) return STEEPGS_ERR_WORKSPACE;
+  bwd_layout(d_ws, m, stride, &g2d, &queue);
+  if (d_grad2d) g2d = d_grad2d;
+  hipStream_t st = as_stream(stream);
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, reinterpret_cast<float*>(queue), (int64_t)1);
+  hipLaunchKernelGGL(k_zero, dim3(stride_grid(stride * m, 256)), dim3(256), 0, st, g2d, stride * m);
+  const int grid = (int)std::min<int64_t>(ceil_div(total_tiles, kBwdWaves), (int64_t)device_cu_count() * 8);
+  const steepgs_opts& o = *opts;
+  timer_begin(STEEPGS_TIMER_RENDER_BWD, st);
+#define SG_LAUNCH_BWD(TW, TH)                                                                                        \
+  (h6 ? launch_bwd<TW, TH, true>(grid, st, d_splats, d_vals, d_tile_ranges, d_cams, V, o, total_tiles, d_image,       \
+                                 d_T_final, d_n_contrib, d_dL_dimage, d_target, g2d, m, queue)                      \
+      : launch_bwd<TW, TH, false>(grid, st, d_splats, d_vals, d_tile_ranges, d_cams, V, o, total_tiles, d_image,     \
+                                  d_T_final, d_n_contrib, d_dL_dimage, d_target, g2d, m, queue))
+  if (o.tile_w == 16 && o.tile_h == 16)
+    SG_LAUNCH_BWD(16, 16);
+  else if (o.tile_w == 16 && o.tile_h == 8)
+    SG_LAUNCH_BWD(16, 8);
+  else
+    SG_LAUNCH_BWD(8, 8);
+#undef SG_LAUNCH_BWD
+  timer_end(STEEPGS_TIMER_RENDER_BWD, st);
+  timer_begin(STEEPGS_TIMER_PROJ_BWD, st);
+  const dim3 pg((unsigned)ceil_div(n, 128));
+  switch (sh_degree) {
+    case 0: hipLaunchKernelGGL(k_proj_bwd<0>, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d, stride, d_grads, d_S); break;
+    case 1: hipLaunchKernelGGL(k_proj_bwd<1>, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d, stride, d_grads, d_S); break;
+    case 2: hipLaunchKernelGGL(k_proj_bwd<2>, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d, stride, d_grads, d_S); break;
+    default: hipLaunchKernelGGL(k_proj_bwd<3>, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d, stride, d_grads, d_S); break;
+  }
+  if (h6) hipLaunchKernelGGL(k_split6_lift, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d, d_S6);
+  timer_end(STEEPGS_TIMER_PROJ_BWD, st);
+  if (d_grad2d && !h6)
+    hipLaunchKernelGGL(k_export2d, dim3(stride_grid(m, 256)), dim3(256), 0, st, d_splats, d_tiles_touched, m, d_grad2d);
+  SG_TRY_LAUNCH();
+  return STEEPGS_OK;
+}
+
+
 
 extern "C" steepgs_status steepgs_render_bwd_split(const float* d_params, int64_t n, int32_t sh_degree,
                                                    const steepgs_camera* d_cams, int32_t V, const steepgs_opts* opts,
@@ -552,46 +807,22 @@ extern "C" steepgs_status steepgs_render_bwd_split(const float* d_params, int64_
                                                    const float* d_dL_dimage, const float* d_target, float* d_grads,
                                                    float* d_S, float* d_grad2d, void* d_ws, size_t ws_bytes,
                                                    void* stream) {
-  if (n < 0 || V <= 0 || sh_degree < 0 || sh_degree > 3 || total_tiles <= 0 || total_pixels <= 0 || !opts_ok(opts))
-    return STEEPGS_ERR_INVALID_ARG;
-  if (!d_cams || !d_tile_ranges || !d_T_final || !d_n_contrib || !d_grads || !d_S) return STEEPGS_ERR_INVALID_ARG;
-  if (!d_dL_dimage && (!d_target || !d_image)) return STEEPGS_ERR_INVALID_ARG;
-  if (n == 0) return STEEPGS_OK;
-  if (!d_params || !d_splats || !d_tiles_touched) return STEEPGS_ERR_INVALID_ARG;
-  const int64_t m = (int64_t)V * n;
-  float* g2d;
-  uint32_t* queue;
-  const size_t need = bwd_layout(nullptr, m, &g2d, &queue);
-  if (!d_ws || ws_bytes < need) return STEEPGS_ERR_WORKSPACE;
-  bwd_layout(d_ws, m, &g2d, &queue);
-  if (d_grad2d) g2d = d_grad2d;
-  hipStream_t st = as_stream(stream);
-  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, reinterpret_cast<float*>(queue), (int64_t)1);
-  hipLaunchKernelGGL(k_zero, dim3(stride_grid(kG2dStride * m, 256)), dim3(256), 0, st, g2d, kG2dStride * m);
-  const int grid = (int)std::min<int64_t>(ceil_div(total_tiles, kBwdWaves), (int64_t)device_cu_count() * 8);
-  const steepgs_opts& o = *opts;
-  timer_begin(STEEPGS_TIMER_RENDER_BWD, st);
-  if (o.tile_w == 16 && o.tile_h == 16)
-    launch_bwd<16, 16>(grid, st, d_splats, d_vals, d_tile_ranges, d_cams, V, o, total_tiles, d_image, d_T_final,
-                       d_n_contrib, d_dL_dimage, d_target, g2d, m, queue);
-  else if (o.tile_w == 16 && o.tile_h == 8)
-    launch_bwd<16, 8>(grid, st, d_splats, d_vals, d_tile_ranges, d_cams, V, o, total_tiles, d_image, d_T_final,
-                      d_n_contrib, d_dL_dimage, d_target, g2d, m, queue);
-  else
-    launch_bwd<8, 8>(grid, st, d_splats, d_vals, d_tile_ranges, d_cams, V, o, total_tiles, d_image, d_T_final,
-                     d_n_contrib, d_dL_dimage, d_target, g2d, m, queue);
-  timer_end(STEEPGS_TIMER_RENDER_BWD, st);
-  timer_begin(STEEPGS_TIMER_PROJ_BWD, st);
-  const dim3 pg((unsigned)ceil_div(n, 128));
-  switch (sh_degree) {
-    case 0: hipLaunchKernelGGL(k_proj_bwd<0>, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d, d_grads, d_S); break;
-    case 1: hipLaunchKernelGGL(k_proj_bwd<1>, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d, d_grads, d_S); break;
-    case 2: hipLaunchKernelGGL(k_proj_bwd<2>, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d, d_grads, d_S); break;
-    default: hipLaunchKernelGGL(k_proj_bwd<3>, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d, d_grads, d_S); break;
-  }
-  timer_end(STEEPGS_TIMER_PROJ_BWD, st);
-  if (d_grad2d)
-    hipLaunchKernelGGL(k_export2d, dim3(stride_grid(m, 256)), dim3(256), 0, st, d_splats, d_tiles_touched, m, d_grad2d);
-  SG_TRY_LAUNCH();
-  return STEEPGS_OK;
+  return bwd_impl(d_params, n, sh_degree, d_cams, V, opts, d_splats, d_tiles_touched, d_vals, d_tile_ranges,
+                  total_tiles, total_pixels, d_image, d_T_final, d_n_contrib, d_dL_dimage, d_target, d_grads, d_S,
+                  nullptr, d_grad2d, d_ws, ws_bytes, stream);
+}
+
+extern "C" steepgs_status steepgs_render_bwd_split6(const float* d_params, int64_t n, int32_t sh_degree,
+                                                    const steepgs_camera* d_cams, int32_t V, const steepgs_opts* opts,
+                                                    const steepgs_splat* d_splats, const uint32_t* d_tiles_touched,
+                                                    const uint32_t* d_vals, const uint32_t* d_tile_ranges,
+                                                    int32_t total_tiles, int64_t total_pixels, const float* d_image,
+                                                    const float* d_T_final, const uint32_t* d_n_contrib,
+                                                    const float* d_dL_dimage, const float* d_target, float* d_grads,
+                                                    float* d_S, float* d_S6, void* d_ws, size_t ws_bytes,
+                                                    void* stream) {
+  if (!d_S6) return STEEPGS_ERR_INVALID_ARG;
+  return bwd_impl(d_params, n, sh_degree, d_cams, V, opts, d_splats, d_tiles_touched, d_vals, d_tile_ranges,
+                  total_tiles, total_pixels, d_image, d_T_final, d_n_contrib, d_dL_dimage, d_target, d_grads, d_S,
+                  d_S6, nullptr, d_ws, ws_bytes, stream);
 }

@@ -84,7 +84,7 @@ class Rasterizer:
         self.ranges = torch.empty(2 * cams.total_tiles, dtype=torch.int32, device=self.dev)
         self.num = torch.zeros(1, dtype=torch.int64, device=self.dev)
         self.status = torch.zeros(1, dtype=torch.int32, device=self.dev)
-        self.ws_sort = self.ws_bwd = None
+        self.ws_sort = self.ws_bwd = self.ws_bwd6 = None
         self.ws_fwd = torch.zeros(L.steepgs_workspace_size(L.STAGE_RENDER_FWD, 0, 1) // 4 + 64, dtype=torch.int32,
                                   device=self.dev)
         Px = cams.total_pixels
@@ -162,6 +162,40 @@ class Rasterizer:
                                    self.splats, self.tiles, self.vals, self.ranges, self.cams.total_tiles,
                                    self.cams.total_pixels, self.image, self.T_final, self.n_contrib, dL_dimage,
                                    target, grads, S, g2d, self.ws_bwd)
+
+    def backward6(self, params: torch.Tensor, grads: torch.Tensor, S6: torch.Tensor, S: torch.Tensor | None = None,
+                  target=None, dL_dimage=None):
+        """As backward, and the splitting matrix over theta = (p, log-scales):
+        S6 [21, n] (upper triangle of the 6x6) accumulates (+=)."""
+        V, n = self.cams.V, self.n
+        need = L.steepgs_workspace_size(L.STAGE_RENDER_BWD6, n, V) // 4 + 64
+        if self.ws_bwd6 is None or self.ws_bwd6.numel() < need:
+            self.ws_bwd6 = torch.empty(need, dtype=torch.int32, device=self.dev)
+        L.steepgs_render_bwd_split6(params, n, self.sh_degree, self.cams.dev, V, self.cams.opts, self.splats,
+                                    self.tiles, self.vals, self.ranges, self.cams.total_tiles,
+                                    self.cams.total_pixels, self.image, self.T_final, self.n_contrib, dL_dimage,
+                                    target, grads, S, S6, self.ws_bwd6)
+
+
+def densify6(params: torch.Tensor, sh_degree: int, S6: torch.Tensor, s_scale: float, eps: float,
+             eps_split: float = -1e-6, out_capacity: int | None = None):
+    """Steepest Density Control over theta = (p, log-scales) on the device:
+    S6 [21, n]; the offspring move in position and log-scales."""
+    F, n = params.shape
+    dev = params.device
+    cap = 2 * n if out_capacity is None else int(out_capacity)
+    out = torch.empty((F, max(cap, 1)), dtype=torch.float32, device=dev)
+    n_out = torch.zeros(1, dtype=torch.int64, device=dev)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    lam = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
+    vmin = torch.empty((6, max(n, 1)), dtype=torch.float32, device=dev)
+    split = torch.empty(max(n, 1), dtype=torch.uint8, device=dev)
+    ws = torch.empty(L.steepgs_workspace_size(L.STAGE_DENSIFY, n, 1) // 4 + 64, dtype=torch.int32, device=dev)
+    L.steepgs_densify6(params, n, sh_degree, S6, s_scale, eps, eps_split, out, cap, n_out, lam, vmin, split, status, ws)
+    no = int(n_out.item())
+    st = int(status.item())
+    return dict(params=out[:, :no] if st == L.OK else None, n_out=no, status=st, lambda_min=lam[:n],
+                vmin=vmin[:, :n], split=split[:n])
 
 
 def densify(params: torch.Tensor, sh_degree: int, S: torch.Tensor, s_scale: float, eps: float,

@@ -17,20 +17,23 @@ from .pipeline import CameraBatch, Rasterizer
 
 
 class _Densify:
-    def __init__(self, F, n, dev):
+    def __init__(self, F, n, dev, theta_dim=3):
+        self.theta_dim = theta_dim
         self.cap = 2 * n
         self.out = torch.empty((F, max(self.cap, 1)), dtype=torch.float32, device=dev)
         self.n_out = torch.zeros(1, dtype=torch.int64, device=dev)
         self.status = torch.zeros(1, dtype=torch.int32, device=dev)
         self.lam = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
-        self.vmin = torch.empty((3, max(n, 1)), dtype=torch.float32, device=dev)
+        self.vmin = torch.empty((theta_dim, max(n, 1)), dtype=torch.float32, device=dev)
         self.split = torch.empty(max(n, 1), dtype=torch.uint8, device=dev)
         self.ws = torch.empty(L.steepgs_workspace_size(L.STAGE_DENSIFY, n, 1) // 4 + 64, dtype=torch.int32,
                               device=dev)
 
     def run(self, params, sh_degree, S, s_scale, eps, eps_split):
-        L.steepgs_densify(params, params.shape[1], sh_degree, S, s_scale, eps, eps_split, self.out, self.cap,
-                          self.n_out, self.lam, self.vmin, self.split, self.status, self.ws)
+        """S: [6, n] (theta = p) or [21, n] (theta = (p, log-scales))"""
+        fn = L.steepgs_densify6 if self.theta_dim == 6 else L.steepgs_densify
+        fn(params, params.shape[1], sh_degree, S, s_scale, eps, eps_split, self.out, self.cap, self.n_out, self.lam,
+           self.vmin, self.split, self.status, self.ws)
 
     def result(self):
         n_out = int(self.n_out.item())
@@ -40,16 +43,22 @@ class _Densify:
 
 
 class BatchedStep:
+    """theta_dim 3: the splitting matrix over the position (the paper's);
+    6: over (position, log-scales), S [21, n] and the dim-6 split."""
+
     def __init__(self, params: torch.Tensor, sh_degree: int, cams: CameraBatch, target: torch.Tensor,
-                 eps: float, eps_split: float = -1e-6, s_scale: float = 1.0, capacity: int = 0):
+                 eps: float, eps_split: float = -1e-6, s_scale: float = 1.0, capacity: int = 0, theta_dim: int = 3):
+        if theta_dim not in (3, 6):
+            raise ValueError("theta_dim is 3 or 6")
         self.params, self.sh_degree, self.cams, self.target = params, sh_degree, cams, target
         self.eps, self.eps_split, self.s_scale = eps, eps_split, s_scale
+        self.theta_dim = theta_dim
         F, n = params.shape
         dev = params.device
         self.ras = Rasterizer(cams, sh_degree, capacity)
         self.grads = torch.zeros((F, n), dtype=torch.float32, device=dev)
-        self.S = torch.zeros((6, n), dtype=torch.float32, device=dev)
-        self.dens = _Densify(F, n, dev)
+        self.S = torch.zeros((6 if theta_dim == 3 else 21, n), dtype=torch.float32, device=dev)
+        self.dens = _Densify(F, n, dev, theta_dim)
         self.graph = None
 
     def prepare(self, headroom: float = 1.1) -> int:
@@ -67,7 +76,10 @@ class BatchedStep:
         r.render(self.target)
         self.grads.zero_()
         self.S.zero_()
-        r.backward(self.params, self.grads, self.S, target=self.target)
+        if self.theta_dim == 6:
+            r.backward6(self.params, self.grads, self.S, target=self.target)
+        else:
+            r.backward(self.params, self.grads, self.S, target=self.target)
         self.dens.run(self.params, self.sh_degree, self.S, self.s_scale, self.eps, self.eps_split)
 
     def capture(self):
@@ -99,9 +111,10 @@ class PerViewStep:
     the views, then one densification."""
 
     def __init__(self, params: torch.Tensor, sh_degree: int, scene_cams, opts: dict, target: torch.Tensor,
-                 eps: float, eps_split: float = -1e-6, s_scale: float = 1.0):
+                 eps: float, eps_split: float = -1e-6, s_scale: float = 1.0, theta_dim: int = 3):
         self.params, self.sh_degree = params, sh_degree
         self.eps, self.eps_split, self.s_scale = eps, eps_split, s_scale
+        self.theta_dim = theta_dim
         F, n = params.shape
         dev = params.device
         offs = scene_cams.pixel_offsets()
@@ -112,8 +125,8 @@ class PerViewStep:
             tg = target[o: o + 3 * cb.total_pixels]
             self.views.append((cb, Rasterizer(cb, sh_degree), tg))
         self.grads = torch.zeros((F, n), dtype=torch.float32, device=dev)
-        self.S = torch.zeros((6, n), dtype=torch.float32, device=dev)
-        self.dens = _Densify(F, n, dev)
+        self.S = torch.zeros((6 if theta_dim == 3 else 21, n), dtype=torch.float32, device=dev)
+        self.dens = _Densify(F, n, dev, theta_dim)
 
     def prepare(self, headroom: float = 1.1):
         for cb, r, _ in self.views:
@@ -129,7 +142,10 @@ class PerViewStep:
             L.steepgs_sort(r.splats, r.tiles, r.n, 1, cb.dev, cb.opts, cb.total_tiles, None, r.vals, r.capacity,
                            r.ranges, r.num, r.status, r.ws_sort)
             r.render(tg)
-            r.backward(self.params, self.grads, self.S, target=tg)
+            if self.theta_dim == 6:
+                r.backward6(self.params, self.grads, self.S, target=tg)
+            else:
+                r.backward(self.params, self.grads, self.S, target=tg)
         self.dens.run(self.params, self.sh_degree, self.S, self.s_scale, self.eps, self.eps_split)
 
     def check(self):

@@ -81,6 +81,12 @@ def test_bad_arguments_rejected_on_host():
                                  None) == L.ERR_INVALID_ARG
     assert lib.steepgs_split_remap(fake, 1, 10, fake, fake, 20, None, 0, None) == L.ERR_WORKSPACE
     assert lib.steepgs_split_remap(fake, -1, 10, fake, fake, 20, None, 0, None) == L.ERR_INVALID_ARG
+    assert lib.steepgs_render_bwd_split6(fake, 10, 0, fake, 1, C.byref(o), fake, fake, fake, fake, 4, 64, fake, fake,
+                                         fake, None, fake, fake, fake, None, fake, 1 << 20, None) == L.ERR_INVALID_ARG
+    assert lib.steepgs_densify6(None, -1, 0, None, 1.0, 0.01, 0.0, None, 0, None, None, None, None, None, None, 0,
+                                None) == L.ERR_INVALID_ARG
+    assert lib.steepgs_densify6(fake, 10, 0, fake, 1.0, 0.01, 0.0, fake, 20, fake, None, None, None, fake, None, 0,
+                                None) == L.ERR_WORKSPACE
     assert lib.steepgs_status_string(2) == b"output capacity exceeded"
 
 
