@@ -169,67 +169,70 @@ __global__ void __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_pe
         const float4 a = A[j];
         const float4 cq = Cq[j];
         const uint32_t pos = (uint32_t)(b_start + j);
+        const float blue = E[j].x;
         // moments of g alpha d over the tile's pixels (the mean and conic
-        // gradients are linear in them), opacity and colour gradients
+        // gradients are linear in them), opacity and colour gradients.  The
+        // per-pixel work is predicated (selects, no divergent branch), so the
+        // sums are updated in place; a quadrant is skipped as a whole when
+        // the entry is outside its reach or no pixel of it takes the entry.
         float mx = 0.f, my = 0.f, mxx = 0.f, mxy = 0.f, myy = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
         float h3[4] = {0.f, 0.f, 0.f, 0.f}, h4[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-        bool any = false;
-        float blue = 0.f;
-        bool blue_loaded = false;
+        uint64_t took = 0;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
           if (!((qm[q] >> j) & 1ull)) continue;  // wave-uniform
-          if (pos >= last[q]) continue;          // past this pixel's last contributor (or outside the image)
           const float dx = (float)(tx0 + (q % QX) * 8 + lx) - a.x;
           const float dy = (float)(ty0 + (q / QX) * 8 + ly) - a.y;
           const float power = splat_power(dx, dy, a.z, a.w, cq.x);
           const float G = __expf(power);
           const float raw = cq.y * G;
           const bool clamped = raw > opt.alpha_max;
-          const float alpha = clamped ? opt.alpha_max : raw;
-          if (!(power >= cut && alpha >= opt.alpha_min)) continue;
-          if (!blue_loaded) {
-            blue = E[j].x;
-            blue_loaded = true;
-          }
-          any = true;
+          const float alpha = fminf(opt.alpha_max, raw);
+          // entries at or past the pixel's last contributor (or outside the
+          // image) and those below the cut-off were skipped by the forward
+          const bool c = pos < last[q] && power >= cut && alpha >= opt.alpha_min;
+          const uint64_t cm = __builtin_amdgcn_ballot_w64(c);
+          if (!cm) continue;
+          took |= cm;
           // transmittance in front of this entry, T_i = T_{i+1} / (1 - alpha_i),
-          // with the hardware reciprocal (within 1 ulp)
+          // with the hardware reciprocal (within 1 ulp); alpha <= alpha_max < 1
+          // on every lane, so the lanes that do not take the entry stay finite
           const float inv_om = __builtin_amdgcn_rcpf(1.f - alpha);
-          T[q] *= inv_om;
-          const float w = alpha * T[q];
+          const float Ti = T[q] * inv_om;
           // g = dL/dalpha_i = sum_c dL/dC_c (c_c T_i - R_c / (1 - alpha_i))
           const float x = dC[q][0] * cq.z + dC[q][1] * cq.w + dC[q][2] * blue;
-          const float g = T[q] * x - D[q] * inv_om;
+          const float g = Ti * x - D[q] * inv_om;
+          const float w = c ? alpha * Ti : 0.f;
+          T[q] = c ? Ti : T[q];
           D[q] += x * w;
           gr += w * dC[q][0];
           gg += w * dC[q][1];
           gbl += w * dC[q][2];
-          if (!clamped) {
-            const float gaw = g * alpha;
-            const float tx = gaw * dx, ty = gaw * dy;
-            mx += tx;
-            my += ty;
-            mxx += tx * dx;
-            mxy += tx * dy;
-            myy += ty * dy;
-            go += g * G;
-            if (H6) {
-              const float txx = tx * dx, tyy = ty * dy;
-              h3[0] += txx * dx;
-              h3[1] += txx * dy;
-              h3[2] += tyy * dx;
-              h3[3] += tyy * dy;
-              const float dxx = dx * dx, dxy = dx * dy, dyy = dy * dy;
-              h4[0] += txx * dxx;
-              h4[1] += txx * dxy;
-              h4[2] += txx * dyy;
-              h4[3] += tyy * dxy;
-              h4[4] += tyy * dyy;
-            }
+          // the clamped alpha does not depend on the mean, conic or opacity
+          const bool lin = c && !clamped;
+          const float gaw = lin ? g * alpha : 0.f;
+          const float tx = gaw * dx, ty = gaw * dy;
+          mx += tx;
+          my += ty;
+          mxx += tx * dx;
+          mxy += tx * dy;
+          myy += ty * dy;
+          go += lin ? g * G : 0.f;
+          if (H6) {
+            const float txx = tx * dx, tyy = ty * dy;
+            h3[0] += txx * dx;
+            h3[1] += txx * dy;
+            h3[2] += tyy * dx;
+            h3[3] += tyy * dy;
+            const float dxx = dx * dx, dxy = dx * dy, dyy = dy * dy;
+            h4[0] += txx * dxx;
+            h4[1] += txx * dxy;
+            h4[2] += txx * dyy;
+            h4[3] += tyy * dxy;
+            h4[4] += tyy * dyy;
           }
         }
-        if (ballot(any)) {
+        if (took) {
           // per-entry sums over the tile, one quantity per lane, and one
           // nine-lane atomic into the record's 48-byte slot
           const float part[9] = {mx, my, mxx, mxy, myy, go, gr, gg, gbl};

@@ -64,7 +64,11 @@ def test_torch_l1_equals_fused_l1(oracle, kind):
     ref = oracle.forward_backward(P0, deg, cams, opts, target)
     gamb = ref["gauss_ambig"]
     G = P.grad.cpu().numpy().astype(np.float64)
-    assert_group_close(G, fused["grads"], np.zeros(P0.shape[1], bool), rel=1e-5, abs_frac=1e-7, what="vs fused")
+    # the two runs share every kernel; what differs is the order of the
+    # float32 atomic adds over tiles, which is not fixed: run against itself
+    # the fused path already differs by 3e-5 relative on a quaternion
+    # gradient that cancels to 1e-4 of the largest, hence the absolute term
+    assert_group_close(G, fused["grads"], np.zeros(P0.shape[1], bool), rel=1e-5, abs_frac=1e-6, what="vs fused")
     assert_group_close(G, ref["grads"], gamb, what="vs oracle")
     assert_S_close(S.cpu().numpy().astype(np.float64), ref["S"], gamb)
 
