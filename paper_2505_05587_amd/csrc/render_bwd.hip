@@ -278,7 +278,7 @@ __device__ __noinline__ bool colour_clamped_fp64(const float* __restrict__ param
 }
 
 template <int D>
-__global__ void __launch_bounds__(128) k_proj_bwd(const float* __restrict__ params, int64_t n,
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) k_proj_bwd(const float* __restrict__ params, int64_t n,
                                                   const steepgs_camera* __restrict__ cams, int V, steepgs_opts opt,
                                                   const uint32_t* __restrict__ tiles, const float* __restrict__ g2d,
                                                   int stride, float* __restrict__ grads, float* __restrict__ S) {
@@ -313,17 +313,43 @@ __global__ void __launch_bounds__(128) k_proj_bwd(const float* __restrict__ para
 #pragma unroll
   for (int k = 0; k < 3 * NB; ++k) dsh[k] = 0.f;
   bool any = false;
-  for (int v = 0; v < V; ++v) {
-    const int64_t r = (int64_t)v * n + i;
-    if (tiles[r] == 0) continue;
-    float G9[9];
-    {
-      const float4* slot = reinterpret_cast<const float4*>(g2d + r * stride);
-      const float4 u0 = slot[0], u1 = slot[1], u2 = slot[2];
-      G9[0] = u0.x; G9[1] = u0.y; G9[2] = u0.z; G9[3] = u0.w;
-      G9[4] = u1.x; G9[5] = u1.y; G9[6] = u1.z; G9[7] = u1.w;
-      G9[8] = u2.x;
+  // views in groups of 32: which of them see the Gaussian is loaded up front
+  // (eight flags in flight at a time), and the slot of the next visible view
+  // is in flight while the current one is processed; the view index stays
+  // uniform over the wavefront, so camera data remain scalar loads
+  for (int v0 = 0; v0 < V; v0 += 32) {
+  const int nv = min(32, V - v0);
+  uint32_t vis = 0;
+  for (int k0 = 0; k0 < nv; k0 += 8) {
+    uint32_t f[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) f[k] = (k0 + k < nv) ? tiles[(int64_t)(v0 + k0 + k) * n + i] : 0u;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) vis |= (f[k] != 0u ? 1u : 0u) << (k0 + k);
+  }
+  float4 c0 = make_float4(0.f, 0.f, 0.f, 0.f), c1 = c0;
+  float c2 = 0.f;
+  if (vis & 1u) {
+    const float* slot = g2d + ((int64_t)v0 * n + i) * stride;
+    c0 = *reinterpret_cast<const float4*>(slot);
+    c1 = *reinterpret_cast<const float4*>(slot + 4);
+    c2 = slot[8];
+  }
+  for (int k = 0; k < nv; ++k) {
+    const int v = v0 + k;
+    const float4 u0 = c0, u1 = c1;
+    const float u2 = c2;
+    if (k + 1 < nv && ((vis >> (k + 1)) & 1u)) {
+      const float* slot = g2d + ((int64_t)(v + 1) * n + i) * stride;
+      c0 = *reinterpret_cast<const float4*>(slot);
+      c1 = *reinterpret_cast<const float4*>(slot + 4);
+      c2 = slot[8];
     }
+    if (!((vis >> k) & 1u)) continue;
+    float G9[9];
+    G9[0] = u0.x; G9[1] = u0.y; G9[2] = u0.z; G9[3] = u0.w;
+    G9[4] = u1.x; G9[5] = u1.y; G9[6] = u1.z; G9[7] = u1.w;
+    G9[8] = u2;
     bool nz = false;
     for (int k = 0; k < 9; ++k) nz |= G9[k] != 0.f;
     if (!nz) continue;
@@ -487,6 +513,7 @@ __global__ void __launch_bounds__(128) k_proj_bwd(const float* __restrict__ para
       const int a = ij[k][0], b = ij[k][1];
       S3[k] += Pe[0][a] * SP[0][b] + Pe[1][a] * SP[1][b];
     }
+  }
   }
   if (!any) return;
 
