@@ -127,10 +127,12 @@ __global__ void __launch_bounds__(64 * kFwdWaves) __attribute__((amdgpu_waves_pe
           const bool stop = c && Tn < opt.t_min;  // would cross the cut-off: excluded, pixel done
           done[q] = done[q] || stop;
           c = c && !stop;
-          const float w = alpha * T[q];
-          C[q][0] = c ? C[q][0] + cq.z * w : C[q][0];
-          C[q][1] = c ? C[q][1] + cq.w * w : C[q][1];
-          C[q][2] = c ? C[q][2] + blue * w : C[q][2];
+          // the weight is zero for a pixel that does not take the entry, so
+          // the colour sums need no select (fma(colour, 0, C) = C)
+          const float w = c ? alpha * T[q] : 0.f;
+          C[q][0] += cq.z * w;
+          C[q][1] += cq.w * w;
+          C[q][2] += blue * w;
           T[q] = c ? Tn : T[q];
           last[q] = c ? pos1 : last[q];
           if (COUNT) used[q] += c ? 1u : 0u;
