@@ -698,6 +698,13 @@ struct Grad2D {
   double g[9];  // dL/d(mx, my, A00, A01, A11, o, r, g, b)
   double H[3];  // sum_x dL/dalpha * Hessian_mu alpha: xx, xy, yy
   double H6[kH6];  // sum_x dL/dalpha * Hessian_theta alpha, theta = (p, log-scales) (when asked)
+  // Gross magnitudes of the per-pixel terms whose sums the gradients and S
+  // are made of (not part of the method: the scale of the float32 summation
+  // error of an implementation that adds them in some order), with
+  // g = dL/dalpha, d = pixel - mean, G = alpha / o:
+  //   sum |g alpha| |dx|, |g alpha| |dy|, |g alpha| dx^2, |g alpha| |dx dy|,
+  //   |g alpha| dy^2, |g| G, alpha T |dL/dC_c| (c = r, g, b), |g alpha|
+  double gross[10];
 };
 
 // Exact reverse sweep of one pixel given dL/dC.  Accumulates into acc[g]
@@ -716,7 +723,18 @@ void backward_pixel(const View& view, int u, int v, const Pixel& px, const doubl
     if (want && !(*want)[c.g]) continue;
     Grad2D& A = acc[c.g];
     for (int ch = 0; ch < 3; ++ch) A.g[6 + ch] += c.a * c.T * dLdC[ch];
+    for (int ch = 0; ch < 3; ++ch) A.gross[6 + ch] += c.a * c.T * std::fabs(dLdC[ch]);
     if (c.clamped) continue;  // alpha = alpha_max: constant in (mean, conic, opacity)
+    {
+      const double ga = std::fabs(dLda) * c.a, dx = u - g.mx, dy = v - g.my;
+      A.gross[0] += ga * std::fabs(dx);
+      A.gross[1] += ga * std::fabs(dy);
+      A.gross[2] += ga * dx * dx;
+      A.gross[3] += ga * std::fabs(dx * dy);
+      A.gross[4] += ga * dy * dy;
+      A.gross[5] += std::fabs(dLda) * c.a / g.o;
+      A.gross[9] += ga;
+    }
     Dual<6> in[6];
     double vals[6] = {g.mx, g.my, g.A00, g.A01, g.A11, g.o};
     for (int k2 = 0; k2 < 6; ++k2) {
@@ -765,12 +783,47 @@ bool jacobian_any(const float* params, int64_t n, int deg, int64_t i, const Cam&
 }
 
 // lift the per-view accumulators of Gaussian i to parameter space:
-// grads += J^T g2d, S += P^T H P with P = d Pi(p) / dp (rows 0-1, columns 0-2)
+// grads += J^T g2d, S += P^T H P with P = d Pi(p) / dp (rows 0-1, columns 0-2).
+// With rec given, also the gross magnitudes (Grad2D::gross) through the
+// absolute Jacobian: gabs += |J|^T (|A| m1, m2 / 2, ..., colour), and
+// Sabs += |P|^T (|A| M |A| + m0 |A|) |P| with M, m0 the gross second and
+// zeroth moments, |A| the entrywise absolute conic; |S| <= Sabs entrywise.
 void lift(const float* params, int64_t n, int deg, int64_t i, const Cam& cam, const Opts& opt, const Grad2D& acc,
-          double* grad_i /*[F] stride gstride*/, int64_t gstride, double* S_i /*[9] stride sstride*/, int64_t sstride) {
+          double* grad_i /*[F] stride gstride*/, int64_t gstride, double* S_i /*[9] stride sstride*/, int64_t sstride,
+          const Proj<double>* rec = nullptr, double* gabs_i = nullptr, double* Sabs_i = nullptr) {
   double J[9][59];
   if (!jacobian_any(params, n, deg, i, cam, opt, J)) return;
   int F = num_params(deg);
+  if (rec && (gabs_i || Sabs_i)) {
+    const double* q = acc.gross;
+    const double a0 = std::fabs(rec->A00), a1 = std::fabs(rec->A01), a2 = std::fabs(rec->A11);
+    const double g2abs[9] = {a0 * q[0] + a1 * q[1], a1 * q[0] + a2 * q[1], 0.5 * q[2], q[3], 0.5 * q[4], q[5],
+                             q[6], q[7], q[8]};
+    if (gabs_i)
+      for (int f = 0; f < F; ++f) {
+        double s = 0.0;
+        for (int r = 0; r < 9; ++r) s += g2abs[r] * std::fabs(J[r][f]);
+        gabs_i[f * gstride] += s;
+      }
+    if (Sabs_i) {
+      const double Aa[2][2] = {{a0, a1}, {a1, a2}}, Ma[2][2] = {{q[2], q[3]}, {q[3], q[4]}};
+      double Ha[2][2];
+      for (int x = 0; x < 2; ++x)
+        for (int y = 0; y < 2; ++y) {
+          double s = q[9] * Aa[x][y];
+          for (int k = 0; k < 2; ++k)
+            for (int l = 0; l < 2; ++l) s += Aa[x][k] * Ma[k][l] * Aa[l][y];
+          Ha[x][y] = s;
+        }
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          double s = 0.0;
+          for (int x = 0; x < 2; ++x)
+            for (int y = 0; y < 2; ++y) s += std::fabs(J[x][a]) * Ha[x][y] * std::fabs(J[y][b]);
+          Sabs_i[(3 * a + b) * sstride] += s;
+        }
+    }
+  }
   for (int f = 0; f < F; ++f) {
     double s = 0.0;
     for (int r = 0; r < 9; ++r) s += acc.g[r] * J[r][f];
@@ -989,13 +1042,15 @@ int orc_sort(const float* params, int64_t n, int deg, const float* cam_f, const 
 // Full forward + backward.  Outputs (nullable unless stated):
 //   image [packed 3*Px], T_final [Px], n_used [Px] (contributing count),
 //   pix_ambig [Px], loss [V] (needs target), grads [F][n] (+=), S [9][n] (+=),
-//   g2d [V*n][9] and H2d [V*n][3] per-view accumulators, gauss_ambig [n].
+//   g2d [V*n][9] and H2d [V*n][3] per-view accumulators, gauss_ambig [n],
+//   grads_abs [F][n] and S_abs [9][n] (+=): the gross magnitudes of the terms
+//   the gradients and S are sums of (see lift).
 // sign_band: |C - target| below it marks the pixel ambiguous.
 int orc_forward_backward(const float* params, int64_t n, int deg, const float* cam_f, const int32_t* cam_i, int V,
                          const double* opts, const float* target, const double* dLdimage, double sign_band,
                          double* image, double* T_final,
                          int32_t* n_used, uint8_t* pix_ambig, double* loss, double* grads, double* S, double* g2d,
-                         double* H2d, uint8_t* gauss_ambig) {
+                         double* H2d, uint8_t* gauss_ambig, double* grads_abs, double* S_abs) {
   if (n < 0 || V <= 0 || deg < 0 || deg > 3) return 1;
   Opts opt = read_opts(opts);
   std::vector<Cam> cams = read_cams(cam_f, cam_i, V, opt);
@@ -1052,14 +1107,21 @@ int orc_forward_backward(const float* params, int64_t n, int deg, const float* c
       bool any = false;
       for (int k = 0; k < 9; ++k) any |= acc[i].g[k] != 0.0;
       if (!any || (!grads && !S)) continue;
-      static thread_local std::vector<double> gtmp, stmp;
+      static thread_local std::vector<double> gtmp, stmp, gatmp, satmp;
       gtmp.assign(F, 0.0);
       stmp.assign(9, 0.0);
-      lift(params, n, deg, i, cam, opt, acc[i], gtmp.data(), 1, stmp.data(), 1);
+      gatmp.assign(F, 0.0);
+      satmp.assign(9, 0.0);
+      lift(params, n, deg, i, cam, opt, acc[i], gtmp.data(), 1, stmp.data(), 1, &view.rec[i], gatmp.data(),
+           satmp.data());
       if (grads)
         for (int f = 0; f < F; ++f) grads[(int64_t)f * n + i] += gtmp[f];
       if (S)
         for (int k = 0; k < 9; ++k) S[(int64_t)k * n + i] += stmp[k];
+      if (grads_abs)
+        for (int f = 0; f < F; ++f) grads_abs[(int64_t)f * n + i] += gatmp[f];
+      if (S_abs)
+        for (int k = 0; k < 9; ++k) S_abs[(int64_t)k * n + i] += satmp[k];
     }
   }
   (void)F;

@@ -51,7 +51,7 @@ def lib():
         L.orc_project.restype = C.c_int
         L.orc_sort.argtypes = common + [C.POINTER(C.c_uint64), C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_sort.restype = C.c_int
-        L.orc_forward_backward.argtypes = common + [C.c_void_p, C.c_void_p, C.c_double] + [C.c_void_p] * 10
+        L.orc_forward_backward.argtypes = common + [C.c_void_p, C.c_void_p, C.c_double] + [C.c_void_p] * 12
         L.orc_forward_backward.restype = C.c_int
         L.orc_loss.argtypes = common + [_c_f32]
         L.orc_loss.restype = C.c_double
@@ -174,21 +174,26 @@ def forward_backward(params, sh_degree, cams, opts, target=None, sign_band=1e-5,
     out = dict(image=image, T_final=T, n_used=used, pix_ambig=pamb)
     tgt = None if target is None else np.ascontiguousarray(target, np.float32)
     dld = None if dl_dimage is None else np.ascontiguousarray(dl_dimage, np.float64)
-    loss = grads = S = g2d = H2d = gamb = None
+    loss = grads = S = g2d = H2d = gamb = gabs = Sabs = None
     if tgt is not None or dld is not None:
         loss = np.zeros(cams.V, np.float64)
         grads = np.zeros((F, n), np.float64)
         S = np.zeros((9, n), np.float64)
         gamb = np.zeros(n, np.uint8)
+        gabs = np.zeros((F, n), np.float64)
+        Sabs = np.zeros((9, n), np.float64)
         if per_view:
             g2d = np.zeros((cams.V * n, 9), np.float64)
             H2d = np.zeros((cams.V * n, 3), np.float64)
     rc = lib().orc_forward_backward(*args, _ptr(tgt), _ptr(dld), float(sign_band), _ptr(image), _ptr(T), _ptr(used),
-                                    _ptr(pamb), _ptr(loss), _ptr(grads), _ptr(S), _ptr(g2d), _ptr(H2d), _ptr(gamb))
+                                    _ptr(pamb), _ptr(loss), _ptr(grads), _ptr(S), _ptr(g2d), _ptr(H2d), _ptr(gamb),
+                                    _ptr(gabs), _ptr(Sabs))
     assert rc == 0
     out["pix_ambig"] = pamb.astype(bool)
     if tgt is not None or dld is not None:
-        out.update(loss=loss, grads=grads, S=S, gauss_ambig=gamb.astype(bool))
+        # grads_abs / S_abs: gross magnitudes of the summed per-pixel terms
+        # (the scale of an order-dependent float32 summation error)
+        out.update(loss=loss, grads=grads, S=S, gauss_ambig=gamb.astype(bool), grads_abs=gabs, S_abs=Sabs)
         if per_view:
             out.update(g2d=g2d, H2d=H2d)
     return out

@@ -54,9 +54,22 @@ def s6_to_mats(S6):
     return M
 
 
-def assert_group_close(got, ref, exclude, rel=1e-3, abs_frac=1e-6, what=""):
+# Bar term for the order of float32 summation.  The kernels add per-pixel
+# terms per lane, across the 64 lanes of a wavefront (a 6-level tree) and,
+# with atomics in an order the hardware leaves open, over the tiles a
+# footprint covers; recursive summation of N partial sums is off by at most
+# (N - 1) 2^-24 of the sum of their magnitudes.  2^-17 (N = 128) of the
+# gross magnitude the oracle reports (grads_abs, S_abs) covers footprints
+# of up to ~100 tiles; it matters only where terms of both signs cancel to
+# far below their magnitude (run-to-run the atomic order alone moves such an
+# S_i by more than the relative bar).
+SUM_BAR = 2.0 ** -17
+
+
+def assert_group_close(got, ref, exclude, rel=1e-3, abs_frac=1e-6, what="", gross=None):
     """Per Gaussian and parameter group: |d| <= rel*|ref| + abs_frac*max_i |ref_i|
-    (Euclidean norms over the group's rows)."""
+    (+ SUM_BAR * |gross| when the oracle's gross magnitudes are given;
+    Euclidean norms over the group's rows)."""
     keep = ~exclude
     worst = 0.0
     for name, sl in GROUPS.items():
@@ -67,6 +80,8 @@ def assert_group_close(got, ref, exclude, rel=1e-3, abs_frac=1e-6, what=""):
         dn = np.linalg.norm(g - r, axis=0)
         rn = np.linalg.norm(r, axis=0)
         tol = (rel[keep] if np.ndim(rel) else rel) * rn + abs_frac * rn.max()
+        if gross is not None:
+            tol = tol + SUM_BAR * np.linalg.norm(gross[sl][:, keep], axis=0)
         bad = dn > tol
         if bad.any():
             i = np.argmax(dn - tol)
@@ -76,7 +91,7 @@ def assert_group_close(got, ref, exclude, rel=1e-3, abs_frac=1e-6, what=""):
     return worst
 
 
-def assert_S_close(S6_gpu, S9_ref, exclude, rel=1e-3, abs_frac=1e-6):
+def assert_S_close(S6_gpu, S9_ref, exclude, rel=1e-3, abs_frac=1e-6, gross=None):
     ref = s9_to_s6(S9_ref)
     keep = ~exclude
     M_g = s6_to_mats(S6_gpu)[keep]
@@ -84,6 +99,8 @@ def assert_S_close(S6_gpu, S9_ref, exclude, rel=1e-3, abs_frac=1e-6):
     dn = np.linalg.norm((M_g - M_r).reshape(len(M_g), -1), axis=1)
     rn = np.linalg.norm(M_r.reshape(len(M_r), -1), axis=1)
     tol = (rel[keep] if np.ndim(rel) else rel) * rn + abs_frac * rn.max()
+    if gross is not None:
+        tol = tol + SUM_BAR * np.linalg.norm(gross[:, keep], axis=0)
     bad = dn > tol
     assert not bad.any(), f"S: {bad.sum()} of {bad.size} out of tolerance; worst {np.max(dn - tol):.3e}"
 

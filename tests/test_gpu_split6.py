@@ -43,7 +43,8 @@ def test_split6_matches_oracle(oracle, kind, mode):
     amb = ref["gauss_ambig"]
     rel = conditioned_rel(oracle, P, deg, cams, opts)
     # the gradients of the dim-6 backward are those of the plain one
-    assert_group_close(grads.cpu().numpy().astype(np.float64), ref["grads"], amb, rel=rel, what=f"{kind}/{mode}")
+    assert_group_close(grads.cpu().numpy().astype(np.float64), ref["grads"], amb, rel=rel, what=f"{kind}/{mode}",
+                       gross=ref["grads_abs"])
     Mg, Mr = _mats(S6.cpu().numpy().astype(np.float64)), _mats(ref6)
     keep = ~amb
     d = np.linalg.norm((Mg - Mr).reshape(-1, 36), axis=1)

@@ -251,3 +251,30 @@ def test_upstream_image_gradient_matches_central_differences(oracle):
     alt = oracle.forward_backward(P, 1, cams, opts, dl_dimage=w1)
     np.testing.assert_allclose(alt["grads"], l1["grads"], rtol=1e-12, atol=1e-18)
     np.testing.assert_allclose(alt["S"], l1["S"], rtol=1e-12, atol=1e-18)
+
+
+def test_gross_magnitudes_bound_the_sums(oracle):
+    # grads_abs and S_abs are the gross magnitudes of the per-pixel terms the
+    # gradients and S_i are sums of (the scale of a float32 implementation's
+    # order-dependent summation error): they bound the sums entrywise, do not
+    # change when the upstream image gradient changes sign (the sums do) and
+    # scale with its magnitude
+    P, cams, target = tiny_scene(47, 50, 36, sh_degree=1)
+    opts = scenes.opts("smooth")
+    Px = cams.total_pixels()
+    rng = np.random.default_rng(5)
+    D = rng.normal(size=3 * Px)
+    a = oracle.forward_backward(P, 1, cams, opts, dl_dimage=D)
+    b = oracle.forward_backward(P, 1, cams, opts, dl_dimage=-D)
+    c = oracle.forward_backward(P, 1, cams, opts, dl_dimage=2.0 * D)
+    assert (np.abs(a["grads"]) <= a["grads_abs"] * (1 + 1e-12) + 1e-300).all()
+    assert (np.abs(a["S"]) <= a["S_abs"] * (1 + 1e-12) + 1e-300).all()
+    seen = np.abs(a["S"]).sum(axis=0) > 0
+    assert seen.sum() > 10 and (a["S_abs"][:, seen].sum(axis=0) > 0).all()
+    np.testing.assert_allclose(b["grads"], -a["grads"], rtol=1e-12, atol=1e-300)
+    np.testing.assert_allclose(b["grads_abs"], a["grads_abs"], rtol=1e-12, atol=1e-300)
+    np.testing.assert_allclose(b["S_abs"], a["S_abs"], rtol=1e-12, atol=1e-300)
+    np.testing.assert_allclose(c["grads_abs"], 2.0 * a["grads_abs"], rtol=1e-12, atol=1e-300)
+    np.testing.assert_allclose(c["S_abs"], 2.0 * a["S_abs"], rtol=1e-12, atol=1e-300)
+    # the gross exceeds the net where terms of both signs meet
+    assert (a["S_abs"][:, seen].sum(axis=0) > 1.5 * np.abs(a["S"][:, seen]).sum(axis=0)).any()
