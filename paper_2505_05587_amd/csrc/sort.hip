@@ -99,7 +99,8 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const uint32_t* __res
                                                            uint32_t* __restrict__ vals_out,
                                                            const uint64_t* __restrict__ d_count,
                                                            const uint64_t* __restrict__ d_cap, int shift, int bits,
-                                                           const uint32_t* __restrict__ hist_scanned) {
+                                                           const uint32_t* __restrict__ hist_scanned,
+                                                           const uint32_t* __restrict__ gather) {
   constexpr int DIG = 1 << BITS;
   constexpr int PER = DIG / kRsThreads > 0 ? DIG / kRsThreads : 1;  // digits per thread in the tile scan
   __shared__ uint32_t s_key[kRsTile], s_val[kRsTile];
@@ -191,8 +192,10 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const uint32_t* __res
         const uint32_t key = s_key[i];
         const uint32_t d = (key >> shift) & mask;
         const uint32_t g = s_run[d] + ((uint32_t)i - s_start[d]);
-        keys_out[g] = key;
-        vals_out[g] = s_val[i];
+        const uint32_t val = s_val[i];
+        // a last pass may write gather[value] instead of the key
+        keys_out[g] = gather ? gather[val] : key;
+        vals_out[g] = val;
       }
     }
     __syncthreads();
@@ -209,7 +212,7 @@ struct LoadU32 {
 template <int BITS>
 static void radix_pass(uint32_t* kin, uint32_t* vin, uint32_t* kout, uint32_t* vout, const uint64_t* d_count,
                        const uint64_t* d_cap, int shift, int b, uint32_t* hist, uint32_t* hist_partials,
-                       hipStream_t st, hipError_t& err) {
+                       const uint32_t* gather, hipStream_t st, hipError_t& err) {
   // as many workgroups as are resident together (LDS and registers), capped
   // at kRsGrid, so that no second partial round follows the first
   static int per_cu = 0;  // same code object on every device
@@ -225,15 +228,17 @@ static void radix_pass(uint32_t* kin, uint32_t* vin, uint32_t* kout, uint32_t* v
   err = exclusive_scan<LoadU32, uint32_t, uint32_t>(LoadU32{hist}, hn, hist, hist_partials, st);
   if (err != hipSuccess) return;
   hipLaunchKernelGGL(k_rs_scatter<BITS>, dim3(grid), dim3(kRsThreads), 0, st, kin, vin, kout, vout, d_count, d_cap,
-                     shift, b, hist);
+                     shift, b, hist, gather);
 }
 
 // sorts (keys, vals) of `count` (device) elements on bits [0, total_bits),
 // ping-ponging between buffer pair 0 = (k0, v0) and 1 = (k1, v1); the input is
-// in pair `start`; returns the pair holding the result
+// in pair `start`; returns the pair holding the result.  With gather_last,
+// the last pass writes gather_last[value] in place of each sorted key.
 static int radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int start,
                             const uint64_t* d_count, const uint64_t* d_cap, int total_bits, uint32_t* hist,
-                            uint32_t* hist_partials, hipStream_t st, hipError_t& err) {
+                            uint32_t* hist_partials, hipStream_t st, hipError_t& err,
+                            const uint32_t* gather_last = nullptr) {
   const int npass = (total_bits + kRsMaxBits - 1) / kRsMaxBits;
   const int bits = (total_bits + npass - 1) / npass;
   int cur = start;
@@ -245,10 +250,11 @@ static int radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* 
     uint32_t* vin = cur ? v1 : v0;
     uint32_t* kout = cur ? k0 : k1;
     uint32_t* vout = cur ? v0 : v1;
+    const uint32_t* gather = p + 1 == npass ? gather_last : nullptr;
     if (b <= 8)
-      radix_pass<8>(kin, vin, kout, vout, d_count, d_cap, shift, b, hist, hist_partials, st, err);
+      radix_pass<8>(kin, vin, kout, vout, d_count, d_cap, shift, b, hist, hist_partials, gather, st, err);
     else
-      radix_pass<9>(kin, vin, kout, vout, d_count, d_cap, shift, b, hist, hist_partials, st, err);
+      radix_pass<9>(kin, vin, kout, vout, d_count, d_cap, shift, b, hist, hist_partials, gather, st, err);
     if (err != hipSuccess) return cur;
     cur ^= 1;
     shift += b;
@@ -273,13 +279,6 @@ __global__ void k_depth_keys(const steepgs_splat* __restrict__ splats, const uin
     keys[r] = tiles[r] ? __float_as_uint(splats[r].depth) : 0xFFFFFFFFu;  // culled records sort last
     vals[r] = (uint32_t)r;
   }
-}
-
-// tile counts in depth order (one gather, so the scan reads contiguously)
-__global__ void k_gather_counts(const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ order, int64_t m,
-                                uint32_t* __restrict__ out) {
-  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < m; s += (int64_t)gridDim.x * blockDim.x)
-    out[s] = tiles[order[s]];
 }
 
 __global__ void k_instance_total(const uint64_t* __restrict__ total, uint64_t capacity,
@@ -445,14 +444,14 @@ extern "C" steepgs_status steepgs_sort(const steepgs_splat* d_splats, const uint
   hipLaunchKernelGGL(k_depth_keys, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, d_splats, d_tiles_touched, m,
                      w.dkA, w.dvA);
   hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, w.counters, (uint64_t)m);
+  // (its last pass writes each record's tile count in place of the sorted
+  // depth key, so the counts come out in depth order, read contiguously below)
   int where = radix_sort_pairs(w.dkA, w.dvA, w.dkB, w.dvB, 0, w.counters, nullptr, 32, w.hist, w.hist_partials, st,
-                               err);
+                               err, d_tiles_touched);
   if (err != hipSuccess) return STEEPGS_ERR_HIP;
   const uint32_t* order = where ? w.dvB : w.dvA;
-  uint32_t* counts = where ? w.dkB : w.dkA;  // the sorted depth keys are no longer needed
+  uint32_t* counts = where ? w.dkB : w.dkA;
   // 2. instance offsets in depth order; K and the capacity check
-  hipLaunchKernelGGL(k_gather_counts, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, d_tiles_touched, order, m,
-                     counts);
   err = exclusive_scan<LoadU32, uint64_t, uint64_t>(LoadU32{counts}, m, w.offs, w.partials64, st);
   if (err != hipSuccess) return STEEPGS_ERR_HIP;
   uint64_t* total = w.partials64 + scan_partials_count(m);
