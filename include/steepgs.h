@@ -137,10 +137,14 @@ size_t steepgs_workspace_size(int32_t stage, int64_t n, int32_t V, uint64_t capa
  *      radius_sigmas^2 (tested in fp64 on the stored float32 mean and conic,
  *      1e-6 relative slack; the same test selects the instances in
  *      steepgs_sort), 0 if culled.  Discrete outcomes (culling, footprint,
- *      depth) are computed in fp64 in a fixed operation order. */
+ *      depth) are computed in fp64 in a fixed operation order.
+ *      d_depth_keys (nullable) [V*n]: the keys of steepgs_sort's depth order,
+ *      the float bits of each record's depth, 0xFFFFFFFF for a culled one;
+ *      written while the footprint count streams the records, so that the
+ *      sort need not read them again (pass them to steepgs_sort). */
 steepgs_status steepgs_project(const float* d_params, int64_t n, int32_t sh_degree, const steepgs_camera* d_cams,
                                int32_t V, const steepgs_opts* opts, steepgs_splat* d_splats,
-                               uint32_t* d_tiles_touched, void* stream);
+                               uint32_t* d_tiles_touched, uint32_t* d_depth_keys, void* stream);
 
 /* Stage 2 -- instance list (Sec. 3 "Rasterization": sort by view-dependent
  * depth).  One instance per (visible pair, tile of its footprint, the tiles
@@ -151,8 +155,13 @@ steepgs_status steepgs_project(const float* d_params, int64_t n, int32_t sh_degr
  *      keys; d_tile_ranges [total_tiles][2] = [begin, end) ((0,0) if empty);
  *      *d_num_instances = K.  If K > capacity, *d_status = STEEPGS_ERR_CAPACITY,
  *      *d_num_instances holds K and the outputs are not written.  *d_status is
- *      set to 0 otherwise. */
-steepgs_status steepgs_sort(const steepgs_splat* d_splats, const uint32_t* d_tiles_touched, int64_t n, int32_t V,
+ *      set to 0 otherwise.
+ * d_depth_keys (nullable) [V*n]: the depth keys steepgs_project wrote for
+ *      these same records and counts; when null they are formed here from
+ *      d_splats and d_tiles_touched (same result, one more pass over the
+ *      records). */
+steepgs_status steepgs_sort(const steepgs_splat* d_splats, const uint32_t* d_tiles_touched,
+                            const uint32_t* d_depth_keys, int64_t n, int32_t V,
                             const steepgs_camera* d_cams, const steepgs_opts* opts, int32_t total_tiles,
                             uint64_t* d_keys, uint32_t* d_vals, uint64_t capacity, uint32_t* d_tile_ranges,
                             uint64_t* d_num_instances, int32_t* d_status, void* d_ws, size_t ws_bytes,

@@ -64,7 +64,7 @@ class GroupedStep:
         for cb, r, tg in self.groups:
             r.project(self.params)
             L.steepgs_sort(r.splats, r.tiles, r.n, cb.V, cb.dev, cb.opts, cb.total_tiles, None, r.vals, r.capacity,
-                           r.ranges, r.num, r.status, r.ws_sort)
+                           r.ranges, r.num, r.status, r.ws_sort, depth_keys=r.dkeys)
             r.render(tg)
             r.backward(self.params, self.grads, self.S, target=tg)
         self.dens.run(self.params, self.sh_degree, self.S, 1.0, self.eps, self.eps_split)

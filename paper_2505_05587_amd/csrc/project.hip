@@ -75,9 +75,11 @@ __global__ void __launch_bounds__(kProjThreads) k_project(const float* __restric
 // emission applies).  Each wavefront takes 64 consecutive records and walks
 // their rectangles together (rect_walk), so large rectangles do not serialise
 // on one lane.  A record none of whose tiles meets the ellipse gets 0
-// (culled).
+// (culled).  With dkeys, also the key the depth sort orders the records by:
+// the float bits of the depth (positive), all ones for a culled record.
 __global__ void __launch_bounds__(256) k_count_tiles(const steepgs_splat* __restrict__ splats,
-                                                     uint32_t* __restrict__ tiles, int64_t m, steepgs_opts opt) {
+                                                     uint32_t* __restrict__ tiles, int64_t m, steepgs_opts opt,
+                                                     uint32_t* __restrict__ dkeys) {
   __shared__ RectWalkLds s_walk[4];
   __shared__ uint32_t s_cnt[256];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -97,6 +99,7 @@ __global__ void __launch_bounds__(256) k_count_tiles(const steepgs_splat* __rest
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (live) tiles[r] = s_cnt[tid];
+    if (dkeys && r < m) dkeys[r] = (live && s_cnt[tid]) ? __float_as_uint(splats[r].depth) : 0xFFFFFFFFu;
     __builtin_amdgcn_wave_barrier();
   }
 }
@@ -107,7 +110,8 @@ using namespace sg;
 
 extern "C" steepgs_status steepgs_project(const float* d_params, int64_t n, int32_t sh_degree,
                                           const steepgs_camera* d_cams, int32_t V, const steepgs_opts* opts,
-                                          steepgs_splat* d_splats, uint32_t* d_tiles_touched, void* stream) {
+                                          steepgs_splat* d_splats, uint32_t* d_tiles_touched,
+                                          uint32_t* d_depth_keys, void* stream) {
   if (n < 0 || V <= 0 || sh_degree < 0 || sh_degree > 3 || !opts_ok(opts)) return STEEPGS_ERR_INVALID_ARG;
   if (n == 0) return STEEPGS_OK;
   if (!d_params || !d_cams || !d_splats || !d_tiles_touched) return STEEPGS_ERR_INVALID_ARG;
@@ -123,7 +127,7 @@ extern "C" steepgs_status steepgs_project(const float* d_params, int64_t n, int3
   }
   const int64_t m = (int64_t)V * n;
   hipLaunchKernelGGL(k_count_tiles, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, as_stream(stream), d_splats,
-                     d_tiles_touched, m, *opts);
+                     d_tiles_touched, m, *opts, d_depth_keys);
   timer_end(STEEPGS_TIMER_PROJECT, as_stream(stream));
   SG_TRY_LAUNCH();
   return STEEPGS_OK;

@@ -123,7 +123,8 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const uint32_t* __res
       const int idx = wave * kRsWaveSpan + it * 64 + lane;
       const bool valid = idx < n_tile;
       k[it] = valid ? keys_in[base + idx] : 0u;
-      v[it] = valid ? vals_in[base + idx] : 0u;
+      // no value array: the values are the element indices
+      v[it] = valid ? (vals_in ? vals_in[base + idx] : (uint32_t)(base + idx)) : 0u;
     }
 #pragma unroll
     for (int it = 0; it < kRsItems; ++it) {
@@ -210,7 +211,7 @@ struct LoadU32 {
 };
 
 template <int BITS>
-static void radix_pass(uint32_t* kin, uint32_t* vin, uint32_t* kout, uint32_t* vout, const uint64_t* d_count,
+static void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, const uint64_t* d_count,
                        const uint64_t* d_cap, int shift, int b, uint32_t* hist, uint32_t* hist_partials,
                        const uint32_t* gather, hipStream_t st, hipError_t& err) {
   // as many workgroups as are resident together (LDS and registers), capped
@@ -234,11 +235,13 @@ static void radix_pass(uint32_t* kin, uint32_t* vin, uint32_t* kout, uint32_t* v
 // sorts (keys, vals) of `count` (device) elements on bits [0, total_bits),
 // ping-ponging between buffer pair 0 = (k0, v0) and 1 = (k1, v1); the input is
 // in pair `start`; returns the pair holding the result.  With gather_last,
-// the last pass writes gather_last[value] in place of each sorted key.
+// the last pass writes gather_last[value] in place of each sorted key.  With
+// first_keys, the first pass reads its keys there (not from pair `start`)
+// and takes the element indices as values.
 static int radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int start,
                             const uint64_t* d_count, const uint64_t* d_cap, int total_bits, uint32_t* hist,
                             uint32_t* hist_partials, hipStream_t st, hipError_t& err,
-                            const uint32_t* gather_last = nullptr) {
+                            const uint32_t* gather_last = nullptr, const uint32_t* first_keys = nullptr) {
   const int npass = (total_bits + kRsMaxBits - 1) / kRsMaxBits;
   const int bits = (total_bits + npass - 1) / npass;
   int cur = start;
@@ -246,8 +249,12 @@ static int radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* 
   err = hipSuccess;
   for (int p = 0; p < npass; ++p) {
     const int b = (shift + bits > total_bits) ? total_bits - shift : bits;
-    uint32_t* kin = cur ? k1 : k0;
-    uint32_t* vin = cur ? v1 : v0;
+    const uint32_t* kin = cur ? k1 : k0;
+    const uint32_t* vin = cur ? v1 : v0;
+    if (p == 0 && first_keys) {
+      kin = first_keys;
+      vin = nullptr;
+    }
     uint32_t* kout = cur ? k0 : k1;
     uint32_t* vout = cur ? v0 : v1;
     const uint32_t* gather = p + 1 == npass ? gather_last : nullptr;
@@ -414,7 +421,8 @@ size_t sort_workspace(int64_t m, uint64_t cap) {
 
 using namespace sg;
 
-extern "C" steepgs_status steepgs_sort(const steepgs_splat* d_splats, const uint32_t* d_tiles_touched, int64_t n,
+extern "C" steepgs_status steepgs_sort(const steepgs_splat* d_splats, const uint32_t* d_tiles_touched,
+                                       const uint32_t* d_depth_keys, int64_t n,
                                        int32_t V, const steepgs_camera* d_cams, const steepgs_opts* opts,
                                        int32_t total_tiles, uint64_t* d_keys, uint32_t* d_vals, uint64_t capacity,
                                        uint32_t* d_tile_ranges, uint64_t* d_num_instances, int32_t* d_status,
@@ -440,14 +448,16 @@ extern "C" steepgs_status steepgs_sort(const steepgs_splat* d_splats, const uint
   }
   if (!d_splats || !d_tiles_touched || (capacity > 0 && !d_vals)) return STEEPGS_ERR_INVALID_ARG;
   hipError_t err = hipSuccess;
-  // 1. depth order of the records (culled last)
-  hipLaunchKernelGGL(k_depth_keys, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, d_splats, d_tiles_touched, m,
-                     w.dkA, w.dvA);
+  // 1. depth order of the records (culled last); the keys come from the
+  // projection stage when it wrote them, else they are formed here
+  if (!d_depth_keys)
+    hipLaunchKernelGGL(k_depth_keys, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, d_splats, d_tiles_touched,
+                       m, w.dkA, w.dvA);
   hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, w.counters, (uint64_t)m);
   // (its last pass writes each record's tile count in place of the sorted
   // depth key, so the counts come out in depth order, read contiguously below)
   int where = radix_sort_pairs(w.dkA, w.dvA, w.dkB, w.dvB, 0, w.counters, nullptr, 32, w.hist, w.hist_partials, st,
-                               err, d_tiles_touched);
+                               err, d_tiles_touched, d_depth_keys);
   if (err != hipSuccess) return STEEPGS_ERR_HIP;
   const uint32_t* order = where ? w.dvB : w.dvA;
   uint32_t* counts = where ? w.dkB : w.dkA;

@@ -101,6 +101,7 @@ class Rasterizer:
         if n != self.n:
             self.splats = torch.empty((max(V * n, 1), L.SPLAT_FLOATS), dtype=torch.float32, device=self.dev)
             self.tiles = torch.empty(max(V * n, 1), dtype=torch.int32, device=self.dev)
+            self.dkeys = torch.empty(max(V * n, 1), dtype=torch.int32, device=self.dev)
             self.ws_bwd = torch.empty(L.steepgs_workspace_size(L.STAGE_RENDER_BWD, n, V) // 4 + 64,
                                       dtype=torch.int32, device=self.dev)
             self.n = n
@@ -117,7 +118,7 @@ class Rasterizer:
         n = params.shape[1]
         self._ensure(n, self.capacity)
         L.steepgs_project(params, n, self.sh_degree, self.cams.dev, self.cams.V, self.cams.opts, self.splats,
-                          self.tiles)
+                          self.tiles, depth_keys=self.dkeys)
 
     def sort(self, want_keys: bool = False) -> int:
         """Instance list; grows the capacity and retries on overflow (reads
@@ -129,7 +130,8 @@ class Rasterizer:
                 self.keys = _grow(self.keys, self.capacity, torch.int64, self.dev)
                 keys = self.keys
             L.steepgs_sort(self.splats, self.tiles, n, V, self.cams.dev, self.cams.opts, self.cams.total_tiles, keys,
-                           self.vals, self.capacity, self.ranges, self.num, self.status, self.ws_sort)
+                           self.vals, self.capacity, self.ranges, self.num, self.status, self.ws_sort,
+                           depth_keys=self.dkeys)
             K = int(self.num.item())
             if int(self.status.item()) == L.OK:
                 return K

@@ -72,7 +72,7 @@ class BatchedStep:
         r = self.ras
         r.project(self.params)
         L.steepgs_sort(r.splats, r.tiles, r.n, self.cams.V, self.cams.dev, self.cams.opts, self.cams.total_tiles,
-                       None, r.vals, r.capacity, r.ranges, r.num, r.status, r.ws_sort)
+                       None, r.vals, r.capacity, r.ranges, r.num, r.status, r.ws_sort, depth_keys=r.dkeys)
         r.render(self.target)
         self.grads.zero_()
         self.S.zero_()
@@ -140,7 +140,7 @@ class PerViewStep:
         for cb, r, tg in self.views:
             r.project(self.params)
             L.steepgs_sort(r.splats, r.tiles, r.n, 1, cb.dev, cb.opts, cb.total_tiles, None, r.vals, r.capacity,
-                           r.ranges, r.num, r.status, r.ws_sort)
+                           r.ranges, r.num, r.status, r.ws_sort, depth_keys=r.dkeys)
             r.render(tg)
             if self.theta_dim == 6:
                 r.backward6(self.params, self.grads, self.S, target=tg)

@@ -178,3 +178,33 @@ def test_all_culled_and_empty(oracle):
     np.testing.assert_allclose(img, np.broadcast_to(np.array([0.2, 0.4, 0.6], np.float32)[:, None, None], img.shape))
     ref = oracle.forward_backward(P, 0, cams, opts)
     np.testing.assert_allclose(fs.image.cpu().numpy(), ref["image"], rtol=1e-6)
+
+
+@pytest.mark.parametrize("kind", ["multiview", "extreme"])
+def test_sort_with_projected_depth_keys_matches_own_keys(oracle, kind):
+    # the depth keys written by the projection stage and the ones the sort
+    # forms itself order the records identically
+    P, deg, cams, target = scene_small(kind)
+    opts = scenes.opts("3dgs")
+    print(f"\n[case] sort with / without projected depth keys kind={kind}", flush=True)
+    from paper_2505_05587_amd import _lib as L, pipeline
+    dev = torch.device("cuda", 0)
+    cb = pipeline.CameraBatch(cams, opts, dev)
+    ras = pipeline.Rasterizer(cb, deg, capacity=1 << 16)
+    ras.project(torch.from_numpy(P).to(dev))
+    outs = []
+    for dk in (ras.dkeys, None):
+        vals = torch.full((ras.capacity,), -1, dtype=torch.int32, device=dev)
+        ranges = torch.full_like(ras.ranges, -1)
+        keys = torch.zeros(ras.capacity, dtype=torch.int64, device=dev)
+        L.steepgs_sort(ras.splats, ras.tiles, ras.n, cams.V, cb.dev, cb.opts, cb.total_tiles, keys, vals,
+                       ras.capacity, ranges, ras.num, ras.status, ras.ws_sort, depth_keys=dk)
+        torch.cuda.synchronize()
+        assert int(ras.status.item()) == L.OK
+        K = int(ras.num.item())
+        outs.append((K, vals[:K].cpu().numpy(), keys[:K].cpu().numpy(), ranges.cpu().numpy()))
+    assert outs[0][0] == outs[1][0] > 0
+    for a, b in zip(outs[0][1:], outs[1][1:]):
+        np.testing.assert_array_equal(a, b)
+    keys_ref, vals_ref, _ = oracle.sort(P, deg, cams, opts)
+    np.testing.assert_array_equal(outs[0][1].view(np.uint32), vals_ref)
