@@ -109,14 +109,16 @@ typedef struct {
  * conic = (a, b, c) with A = [[a, b], [b, c]] = Pi(Sigma)^-1.  rect packs the
  * inclusive tile rectangle: rect_lo = x0 | y0 << 16, rect_hi = x1 | y1 << 16.
  * A pair is culled when tiles_touched is 0; a pair culled by the projection
- * itself (near plane, degenerate conic, empty rectangle) also has opacity 0. */
+ * itself (near plane, degenerate conic, empty rectangle) also has opacity 0.
+ * The fields the footprint walk reads (mean, conic, opacity, rect) come first,
+ * in one 32-byte block: the instance emission gathers records in depth order. */
 typedef struct {
   float mean_x, mean_y;
   float conic_a, conic_b;
   float conic_c, opacity;
+  uint32_t rect_lo, rect_hi;
   float rgb[3];
   float depth; /* camera-space z */
-  uint32_t rect_lo, rect_hi;
 } steepgs_splat;
 
 /* Fill tiles_x/tiles_y/tile_offset/pixel_offset of V host cameras for the

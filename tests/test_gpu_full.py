@@ -42,8 +42,8 @@ def _run_step(scene, opts):
 
 
 def _rect(sp):
-    lo = sp[:, 10].view(np.uint32)
-    hi = sp[:, 11].view(np.uint32)
+    lo = sp[:, 6].view(np.uint32)
+    hi = sp[:, 7].view(np.uint32)
     return np.stack([lo & 0xFFFF, lo >> 16, hi & 0xFFFF, hi >> 16], 1).astype(np.int64)
 
 
@@ -131,7 +131,7 @@ def test_single_view_full(oracle):
     sp = r.splats.cpu().numpy()
     vis = pr["visible"]
     np.testing.assert_array_equal(_rect(sp)[vis], pr["rect"][vis])
-    np.testing.assert_array_equal(sp[vis, 9].view(np.uint32), pr["depth_bits"][vis])
+    np.testing.assert_array_equal(sp[vis, 11].view(np.uint32), pr["depth_bits"][vis])
     rng = np.random.default_rng(11)
     _say("sampled pixels")
     _sample_pixel_parity(oracle, scene, opts, r.image.cpu().numpy().astype(np.float64), rng, 3000)
@@ -163,7 +163,7 @@ def test_batched_16_full(oracle):
     b, e = ranges[nonempty][order, 0], ranges[nonempty][order, 1]
     assert b[0] == 0 and e[-1] == K and (b[1:] == e[:-1]).all()
     np.testing.assert_array_equal(np.bincount(vals, minlength=len(tiles)), tiles)
-    depth = sp[:, 9].view(np.uint32)[vals].astype(np.uint64)
+    depth = sp[:, 11].view(np.uint32)[vals].astype(np.uint64)
     tile_of = np.repeat(np.nonzero(nonempty)[0][order], (e - b).astype(np.int64))
     key = (tile_of.astype(np.uint64) << np.uint64(32)) | depth
     dk = np.diff(key.astype(np.int64))

@@ -42,15 +42,15 @@ def test_project_and_sort(oracle, kind, mode):
     np.testing.assert_array_equal(g["tiles"] > 0, vis)
     np.testing.assert_array_equal(g["tiles"], pr["tiles"])
     sp = g["splats"]
-    rect_lo = sp[:, 10].view(np.uint32)
-    rect_hi = sp[:, 11].view(np.uint32)
+    rect_lo = sp[:, 6].view(np.uint32)
+    rect_hi = sp[:, 7].view(np.uint32)
     rect = np.stack([rect_lo & 0xFFFF, rect_lo >> 16, rect_hi & 0xFFFF, rect_hi >> 16], 1).astype(np.int32)
     np.testing.assert_array_equal(rect[vis], pr["rect"][vis])
-    np.testing.assert_array_equal(sp[vis, 9].view(np.uint32), pr["depth_bits"][vis])
+    np.testing.assert_array_equal(sp[vis, 11].view(np.uint32), pr["depth_bits"][vis])
     np.testing.assert_allclose(sp[vis, 0:2], pr["mean"][vis], rtol=2e-7, atol=1e-5)
     np.testing.assert_allclose(sp[vis, 2:5], pr["conic"][vis], rtol=2e-6, atol=1e-12)
     np.testing.assert_allclose(sp[vis, 5], pr["opacity"][vis], rtol=2e-7)
-    np.testing.assert_allclose(sp[vis, 6:9], pr["rgb"][vis], rtol=2e-6, atol=1e-7)
+    np.testing.assert_allclose(sp[vis, 8:11], pr["rgb"][vis], rtol=2e-6, atol=1e-7)
     keys, vals, ranges = oracle.sort(P, deg, cams, opts)
     assert g["K"] == len(keys)
     np.testing.assert_array_equal(g["vals"], vals)
