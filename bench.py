@@ -113,6 +113,9 @@ def _source_digest(stage):
     for name in (KERNEL_SOURCE[stage], "common.h", "projection.h"):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
+    # the record and option layouts every kernel is compiled against
+    with open(os.path.join(ROOT, "include", "steepgs.h"), "rb") as f:
+        h.update(f.read())
     return h.hexdigest()
 
 
