@@ -193,7 +193,9 @@ steepgs_status steepgs_render_fwd(const steepgs_splat* d_splats, int64_t n, cons
  *                   Pi(Sigma) and colour (App. C.4).
  * d_grad2d (nullable) [V*n][12] receives the per-pair gradients w.r.t.
  * (mean_x, mean_y, conic a, b, c, opacity, r, g, b) in entries 0-8 of each
- * 48-byte slot (overwritten; entries 9-11 are zero). */
+ * 48-byte slot (overwritten; entries 9-11 are zero).
+ * With n = 0 nothing is accumulated and the per-Gaussian buffers (params,
+ * records, counts, grads, S) may be null. */
 steepgs_status steepgs_render_bwd_split(const float* d_params, int64_t n, int32_t sh_degree,
                                         const steepgs_camera* d_cams, int32_t V, const steepgs_opts* opts,
                                         const steepgs_splat* d_splats, const uint32_t* d_tiles_touched,

@@ -778,11 +778,10 @@ static steepgs_status bwd_impl(const float* d_params, int64_t n, int32_t sh_degr
   const bool h6 = d_S6 != nullptr;
   if (n < 0 || V <= 0 || sh_degree < 0 || sh_degree > 3 || total_tiles <= 0 || total_pixels <= 0 || !opts_ok(opts))
     return STEEPGS_ERR_INVALID_ARG;
-  if (!d_cams || !d_tile_ranges || !d_T_final || !d_n_contrib || !d_grads || (!d_S && !h6))
-    return STEEPGS_ERR_INVALID_ARG;
+  if (!d_cams || !d_tile_ranges || !d_T_final || !d_n_contrib) return STEEPGS_ERR_INVALID_ARG;
   if (!d_dL_dimage && (!d_target || !d_image)) return STEEPGS_ERR_INVALID_ARG;
-  if (n == 0) return STEEPGS_OK;
-  if (!d_params || !d_splats || !d_tiles_touched) return STEEPGS_ERR_INVALID_ARG;
+  if (n == 0) return STEEPGS_OK;  // nothing to accumulate; the per-Gaussian buffers may be empty
+  if (!d_params || !d_splats || !d_tiles_touched || !d_grads || (!d_S && !h6)) return STEEPGS_ERR_INVALID_ARG;
   const int64_t m = (int64_t)V * n;
   const int stride = h6 ? kG2dStride6 : kG2dStride;
   float* g2d;

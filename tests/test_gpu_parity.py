@@ -208,3 +208,39 @@ def test_sort_with_projected_depth_keys_matches_own_keys(oracle, kind):
         np.testing.assert_array_equal(a, b)
     keys_ref, vals_ref, _ = oracle.sort(P, deg, cams, opts)
     np.testing.assert_array_equal(outs[0][1].view(np.uint32), vals_ref)
+
+
+@pytest.mark.parametrize("n", [0, 40])
+def test_empty_set_and_tiny_views(oracle, n):
+    # no Gaussians at all, and views of 1x1 and 17x9 pixels (a single
+    # partial tile each): forward, backward and densification
+    from paper_2505_05587_amd import _lib as L, pipeline
+    dev = torch.device("cuda", 0)
+    rng = np.random.default_rng(11)
+    cams = scenes.make_cameras([(0, 0, 3.0), (0.5, 0.2, 2.5)], [(1, 1), (17, 9)])
+    opts = scenes.opts("3dgs", bg=(0.1, 0.2, 0.3))
+    P = scenes.uniform_gaussians(rng, n, log_scale_mu=-1.5, extent=0.3)
+    target = scenes.uniform_target(rng, cams)
+    print(f"\n[case] empty/tiny views n={n}", flush=True)
+    cb = pipeline.CameraBatch(cams, opts, dev)
+    ras = pipeline.Rasterizer(cb, 0, capacity=64)
+    Pt = torch.from_numpy(np.ascontiguousarray(P)).to(dev)
+    tg = torch.from_numpy(target).to(dev)
+    fs = ras.forward(Pt, tg)
+    grads = torch.zeros_like(Pt)
+    S = torch.zeros((6, n), dtype=torch.float32, device=dev)
+    ras.backward(Pt, grads, S, target=tg)
+    d = pipeline.densify(Pt, 0, S, 1.0, 0.01, -1e-6)
+    torch.cuda.synchronize()
+    ref = oracle.forward_backward(P, 0, cams, opts, target)
+    ok = image_close(fs.image.cpu().numpy().astype(np.float64), ref["image"], expand_pixel_mask(ref["pix_ambig"], cams))
+    assert ok.all()
+    assert d["status"] == L.OK and d["n_out"] >= n
+    if n == 0:
+        assert fs.K == 0 and d["n_out"] == 0
+        return
+    assert fs.K > 0
+    gamb = ref["gauss_ambig"]
+    assert_group_close(grads.cpu().numpy().astype(np.float64), ref["grads"], gamb, what=f"tiny/{n}",
+                       gross=ref["grads_abs"])
+    assert_S_close(S.cpu().numpy().astype(np.float64), ref["S"], gamb, gross=ref["S_abs"])
