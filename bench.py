@@ -162,7 +162,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (views would shard across GPUs with one "
+        print("bench.py measures one GPU: there is no multi-GPU path (views would shard across GPUs with one "
               "all-reduce of gradients and splitting matrices; not implemented). Run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
