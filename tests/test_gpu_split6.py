@@ -22,7 +22,7 @@ def _mats(S21):
     return M
 
 
-@pytest.mark.parametrize("kind", ["plain_small", "multiview", "ortho"])
+@pytest.mark.parametrize("kind", ["plain_small", "multiview", "ortho", "sh3_pinhole"])
 @pytest.mark.parametrize("mode", ["smooth", "3dgs"])
 def test_split6_matches_oracle(oracle, kind, mode):
     P, deg, cams, target = scene_small(kind)
