@@ -65,3 +65,45 @@ def test_graph_replays_match_eager(kind):
         np.testing.assert_array_equal(got["split"][sure], ref["split"][sure])
         if np.array_equal(got["split"], ref["split"]):
             assert got["new"].shape == ref["new"].shape
+
+
+def test_per_view_form_matches_batched():
+    # the same five calls issued once per view (V = 1 each, S accumulated)
+    # against the batched step over all views: images and transmittance
+    # bit-identical per view, losses per view, gradients and S within the
+    # reordering of float sums, the same split decisions where lambda_min is
+    # clear of the threshold
+    from paper_2505_05587_amd.step import PerViewStep
+    P0, deg, cams, target = scene_small("multiview")
+    print("\n[case] per-view form vs batched, multiview", flush=True)
+    dev = torch.device("cuda", 0)
+    opts = scenes.opts("3dgs")
+    P = torch.from_numpy(P0).to(dev)
+    tg = torch.from_numpy(target).to(dev)
+    bat = BatchedStep(P, deg, CameraBatch(cams, opts, dev), tg, eps=1e-3, eps_split=-1e-6)
+    bat.prepare()
+    bat.run()
+    pv = PerViewStep(P, deg, cams, opts, tg, eps=1e-3, eps_split=-1e-6)
+    pv.prepare()
+    pv.run()
+    torch.cuda.synchronize()
+    n = P0.shape[1]
+    offs = cams.pixel_offsets()
+    img_b = bat.ras.image.cpu().numpy()
+    T_b = bat.ras.T_final.cpu().numpy()
+    loss_b = bat.ras.loss.cpu().numpy()
+    for v, (cb, r, _) in enumerate(pv.views):
+        npx = cb.total_pixels
+        np.testing.assert_array_equal(r.image.cpu().numpy(), img_b[3 * offs[v]: 3 * offs[v] + 3 * npx])
+        np.testing.assert_array_equal(r.T_final.cpu().numpy(), T_b[offs[v]: offs[v] + npx])
+        np.testing.assert_allclose(r.loss.cpu().numpy()[0], loss_b[v], rtol=1e-5)  # summed with float atomics
+    gb = bat.grads.cpu().numpy().astype(np.float64)
+    gp = pv.grads.cpu().numpy().astype(np.float64)
+    assert_group_close(gp, gb, np.zeros(n, bool), rel=1e-4, abs_frac=1e-6, what="per-view vs batched")
+    Mb, Mp = s6_to_mats(bat.S.cpu().numpy().astype(np.float64)), s6_to_mats(pv.S.cpu().numpy().astype(np.float64))
+    d = np.linalg.norm((Mp - Mb).reshape(n, -1), axis=1)
+    r = np.linalg.norm(Mb.reshape(n, -1), axis=1)
+    assert (d <= 1e-4 * r + 1e-6 * r.max()).all()
+    lam_b = bat.dens.lam[:n].cpu().numpy().astype(np.float64)
+    sure = np.abs(lam_b + 1e-6) > 1e-4 * r + 1e-12
+    np.testing.assert_array_equal(pv.dens.split[:n].cpu().numpy()[sure], bat.dens.split[:n].cpu().numpy()[sure])
