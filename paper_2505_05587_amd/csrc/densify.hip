@@ -314,45 +314,49 @@ __global__ void k_densify_empty(int64_t* n_out, int32_t* status) {
 SG_DEV int h6_index(int i, int j) { return i <= j ? i * 6 - i * (i - 1) / 2 + (j - i) : j * 6 - j * (j - 1) / 2 + (i - j); }
 
 SG_DEV void eig6_min(const double s[21], double& lam_min, double v[6]) {
-  double A[6][6], Q[6][6];
+  // the symmetric matrix as its upper triangle (h6_index; every index below
+  // is a compile-time constant once the loops are unrolled) and the
+  // accumulated rotations
+  double A[21], Q[6][6];
   double norm2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 21; ++k) A[k] = s[k];
 #pragma unroll
   for (int a = 0; a < 6; ++a)
 #pragma unroll
     for (int b = 0; b < 6; ++b) {
-      A[a][b] = s[h6_index(a, b)];
+      norm2 += A[h6_index(a, b)] * A[h6_index(a, b)];
       Q[a][b] = a == b ? 1.0 : 0.0;
-      norm2 += A[a][b] * A[a][b];
     }
   for (int sweep = 0; sweep < 50; ++sweep) {
     double off = 0.0;
 #pragma unroll
     for (int a = 0; a < 6; ++a)
 #pragma unroll
-      for (int b = a + 1; b < 6; ++b) off += A[a][b] * A[a][b];
+      for (int b = a + 1; b < 6; ++b) off += A[h6_index(a, b)] * A[h6_index(a, b)];
     if (!(2.0 * off > 1e-30 * norm2)) break;
 #pragma unroll
     for (int p = 0; p < 6; ++p)
 #pragma unroll
       for (int q = p + 1; q < 6; ++q) {
-        const double apq = A[p][q];
+        const double apq = A[h6_index(p, q)];
         if (apq == 0.0) continue;
-        // the plane rotation (p, q) that zeroes A[p][q]
-        const double th = (A[q][q] - A[p][p]) / (2.0 * apq);
+        // the plane rotation (p, q) that zeroes A[p][q]: t = tan of its
+        // angle, the smaller root of t^2 + 2 th t - 1 = 0
+        const double th = (A[h6_index(q, q)] - A[h6_index(p, p)]) / (2.0 * apq);
         const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
         const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+        // J^T A J touches rows and columns p and q only
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-          const double akp = A[k][p], akq = A[k][q];
-          A[k][p] = c * akp - sn * akq;
-          A[k][q] = sn * akp + c * akq;
+          if (k == p || k == q) continue;
+          const double akp = A[h6_index(k, p)], akq = A[h6_index(k, q)];
+          A[h6_index(k, p)] = c * akp - sn * akq;
+          A[h6_index(k, q)] = sn * akp + c * akq;
         }
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-          const double apk = A[p][k], aqk = A[q][k];
-          A[p][k] = c * apk - sn * aqk;
-          A[q][k] = sn * apk + c * aqk;
-        }
+        A[h6_index(p, p)] -= t * apq;
+        A[h6_index(q, q)] += t * apq;
+        A[h6_index(p, q)] = 0.0;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
           const double qkp = Q[k][p], qkq = Q[k][q];
@@ -361,14 +365,18 @@ SG_DEV void eig6_min(const double s[21], double& lam_min, double v[6]) {
         }
       }
   }
+  // the smallest diagonal entry, tracked by value (indexing A with the
+  // run-time m would place the matrix in scratch memory)
   int m = 0;
+  lam_min = A[h6_index(0, 0)];
 #pragma unroll
   for (int k = 1; k < 6; ++k)
-    if (A[k][k] < A[m][m]) m = k;
-  lam_min = A[0][0];
+    if (A[h6_index(k, k)] < lam_min) {
+      lam_min = A[h6_index(k, k)];
+      m = k;
+    }
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
-    if (k == m) lam_min = A[k][k];
 #pragma unroll
     for (int r = 0; r < 6; ++r)
       if (k == m) v[r] = Q[r][k];
