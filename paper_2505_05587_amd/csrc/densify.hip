@@ -43,48 +43,56 @@ SG_DEV void eig3_min(const double s[6], double& lam_min, double v[3]) {
   const double r0[3] = {a00 - lam_min, a01, a02};
   const double r1[3] = {a01, a11 - lam_min, a12};
   const double r2[3] = {a02, a12, a22 - lam_min};
-  double c[3][3];
+  // (the best candidate is kept by value: indexing arrays with a run-time
+  // choice would place them in scratch memory)
   const double* rows[3][2] = {{r0, r1}, {r0, r2}, {r1, r2}};
-  double best = -1.0;
-  int bi = 0;
+  double best = -1.0, cb0 = 0.0, cb1 = 0.0, cb2 = 0.0;
+#pragma unroll
   for (int k = 0; k < 3; ++k) {
     const double* u = rows[k][0];
     const double* w = rows[k][1];
-    c[k][0] = u[1] * w[2] - u[2] * w[1];
-    c[k][1] = u[2] * w[0] - u[0] * w[2];
-    c[k][2] = u[0] * w[1] - u[1] * w[0];
-    const double nn = c[k][0] * c[k][0] + c[k][1] * c[k][1] + c[k][2] * c[k][2];
+    const double x = u[1] * w[2] - u[2] * w[1];
+    const double y = u[2] * w[0] - u[0] * w[2];
+    const double z = u[0] * w[1] - u[1] * w[0];
+    const double nn = x * x + y * y + z * z;
     if (nn > best) {
       best = nn;
-      bi = k;
+      cb0 = x;
+      cb1 = y;
+      cb2 = z;
     }
   }
   const double scale2 = p2 * p2;  // |A - q I|^4 sets the scale of a cross product's square norm
   if (best > 1e-24 * scale2) {
     const double inv = 1.0 / sqrt(best);
-    for (int k = 0; k < 3; ++k) v[k] = c[bi][k] * inv;
+    v[0] = cb0 * inv;
+    v[1] = cb1 * inv;
+    v[2] = cb2 * inv;
   } else {
     // lambda_min repeated: A - lambda I has rank <= 1; any unit vector
     // orthogonal to its largest row is an eigenvector
     const double* rr[3] = {r0, r1, r2};
-    int br = 0;
-    double bn = -1.0;
+    double bn = -1.0, u0 = 0.0, u1 = 0.0, u2 = 0.0;
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
       const double nn = rr[k][0] * rr[k][0] + rr[k][1] * rr[k][1] + rr[k][2] * rr[k][2];
       if (nn > bn) {
         bn = nn;
-        br = k;
+        u0 = rr[k][0];
+        u1 = rr[k][1];
+        u2 = rr[k][2];
       }
     }
     if (bn > 1e-24 * p2) {
-      const double* u = rr[br];
       int ax = 0;  // axis least aligned with u
-      if (fabs(u[1]) < fabs(u[ax])) ax = 1;
-      if (fabs(u[2]) < fabs(u[ax])) ax = 2;
-      const double e[3] = {ax == 0 ? 1.0 : 0.0, ax == 1 ? 1.0 : 0.0, ax == 2 ? 1.0 : 0.0};
-      double t[3] = {u[1] * e[2] - u[2] * e[1], u[2] * e[0] - u[0] * e[2], u[0] * e[1] - u[1] * e[0]};
-      const double inv = 1.0 / sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
-      for (int k = 0; k < 3; ++k) v[k] = t[k] * inv;
+      if (fabs(u1) < fabs(u0)) ax = 1;
+      if (fabs(u2) < fabs(ax == 0 ? u0 : u1)) ax = 2;
+      const double e0 = ax == 0 ? 1.0 : 0.0, e1 = ax == 1 ? 1.0 : 0.0, e2 = ax == 2 ? 1.0 : 0.0;
+      const double t0 = u1 * e2 - u2 * e1, t1 = u2 * e0 - u0 * e2, t2 = u0 * e1 - u1 * e0;
+      const double inv = 1.0 / sqrt(t0 * t0 + t1 * t1 + t2 * t2);
+      v[0] = t0 * inv;
+      v[1] = t1 * inv;
+      v[2] = t2 * inv;
     }
   }
   // canonical sign: largest-magnitude component positive (ties: lowest index)
