@@ -33,8 +33,13 @@
  *     work is enqueued (bad argument, launch failure).  Failures that depend on
  *     data (instance or output capacity) are written to *d_status on the
  *     device together with the size that would have been needed.
- *   - Floating point is IEEE fp32 storage; projection, eigensolve and the
- *     projection backward compute in fp64, the rasterizer in fp32.
+ *   - Floating point is IEEE fp32 storage.  Projection, eigensolve and the
+ *     geometric part of the projection backward (camera map, Pi(Sigma), its
+ *     inverse, quaternion and scale, splitting-matrix lift) compute in fp64;
+ *     the rasterizer and the SH colour in fp32.  The backward sums each
+ *     Gaussian's per-tile float32 partials in fp64, so its results do not
+ *     depend on the order in which the tiles finish: repeated launches on
+ *     the same inputs give bit-identical gradients and S.
  *
  * Gaussian parameters: one planar float32 array [F][n] (row stride n),
  *   rows 0-2 position p, 3-5 log-scales, 6-9 quaternion (w,x,y,z) (normalised
@@ -193,7 +198,9 @@ steepgs_status steepgs_render_fwd(const steepgs_splat* d_splats, int64_t n, cons
  *                   Pi(Sigma) and colour (App. C.4).
  * d_grad2d (nullable) [V*n][12] receives the per-pair gradients w.r.t.
  * (mean_x, mean_y, conic a, b, c, opacity, r, g, b) in entries 0-8 of each
- * 48-byte slot (overwritten; entries 9-11 are zero).
+ * 48-byte slot (overwritten; entries 9-11 and culled pairs are zero), rounded
+ * from the fp64 sums in the workspace (steepgs_workspace_size(3, ...) bytes
+ * are needed either way).
  * With n = 0 nothing is accumulated and the per-Gaussian buffers (params,
  * records, counts, grads, S) may be null. */
 steepgs_status steepgs_render_bwd_split(const float* d_params, int64_t n, int32_t sh_degree,

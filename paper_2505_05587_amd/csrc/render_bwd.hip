@@ -34,15 +34,16 @@
 namespace sg {
 
 constexpr int kBwdWaves = 4;    // wavefronts per workgroup, each on a tile of its own
-// floats per record in the 2D-gradient buffer: the raster backward leaves
-// (m1_x, m1_y, m2_xx, m2_xy, m2_yy, dL/do, dL/dr, dL/dg, dL/db) in entries
-// 0-8; when the buffer is the caller's, a last pass turns entries 0-4 into
-// dL/d(mean_x, mean_y, a, b, c)
-constexpr int kG2dStride = 12;
+// doubles per record in the backward's accumulation slots: the raster
+// backward leaves (m1_x, m1_y, m2_xx, m2_xy, m2_yy, dL/do, dL/dr, dL/dg,
+// dL/db) in entries 0-8 (fp64 sums of the per-tile float32 partials)
+constexpr int kG2dStride = 9;
 // with the splitting matrix over theta = (p, log-scales) the slot also holds
 // the third and fourth moments: (m3_xxx, m3_xxy, m3_xyy, m3_yyy,
 // m4_xxxx, m4_xxxy, m4_xxyy, m4_xyyy, m4_yyyy) in entries 9-17
-constexpr int kG2dStride6 = 20;
+constexpr int kG2dStride6 = 18;
+// floats per record of the caller's optional 2D-gradient output
+constexpr int kGrad2dOut = 12;
 
 // H6: also the moments the dim-6 splitting matrix needs (third and fourth
 // order in d), summed like the others
@@ -57,7 +58,7 @@ __global__ void __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_pe
                                                                const uint32_t* __restrict__ n_contrib,
                                                                const float* __restrict__ dL_dimage,
                                                                const float* __restrict__ target,
-                                                               float* __restrict__ g2d, int64_t m,
+                                                               double* __restrict__ g2d, int64_t m,
                                                                uint32_t* __restrict__ queue) {
   constexpr int NQ = TW * TH / 64;  // 8x8 quadrants of the tile = pixels per lane
   constexpr int QX = TW / 8;
@@ -234,15 +235,17 @@ __global__ void __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_pe
         }
         if (took) {
           // per-entry sums over the tile, one quantity per lane, and one
-          // nine-lane atomic into the record's 48-byte slot
+          // nine-lane fp64 atomic into the record's slot: the sums over the
+          // tiles of a footprint are exact up to fp64 rounding, so their
+          // hardware-chosen order leaves the float32 results unchanged
           const float part[9] = {mx, my, mxx, mxy, myy, go, gr, gg, gbl};
           const float tot = reduce9(part);
-          float* const slot = g2d + (int64_t)__float_as_uint(E[j].y) * (H6 ? kG2dStride6 : kG2dStride);
-          if (red_idx >= 0) unsafeAtomicAdd(slot + red_idx, tot);
+          double* const slot = g2d + (int64_t)__float_as_uint(E[j].y) * (H6 ? kG2dStride6 : kG2dStride);
+          if (red_idx >= 0) unsafeAtomicAdd(slot + red_idx, (double)tot);
           if (H6) {
             const float part2[9] = {h3[0], h3[1], h3[2], h3[3], h4[0], h4[1], h4[2], h4[3], h4[4]};
             const float tot2 = reduce9(part2);
-            if (red_idx >= 0) unsafeAtomicAdd(slot + 9 + red_idx, tot2);
+            if (red_idx >= 0) unsafeAtomicAdd(slot + 9 + red_idx, (double)tot2);
           }
         }
       }
@@ -277,48 +280,9 @@ __device__ __noinline__ bool colour_clamped_fp64(const float* __restrict__ param
   return acc < 0.0;
 }
 
-template <int D>
-__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) k_proj_bwd(const float* __restrict__ params, int64_t n,
-                                                  const steepgs_camera* __restrict__ cams, int V, steepgs_opts opt,
-                                                  const uint32_t* __restrict__ tiles, const float* __restrict__ g2d,
-                                                  int stride, float* __restrict__ grads, float* __restrict__ S) {
-  constexpr int NB = (D + 1) * (D + 1);
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  float p[3];
-  for (int k = 0; k < 3; ++k) p[k] = params[(STEEPGS_ROW_MEAN + k) * n + i];
-  float sh[3 * NB];
-#pragma unroll
-  for (int k = 0; k < 3 * NB; ++k) sh[k] = params[(STEEPGS_ROW_SH + k) * n + i];
-  // covariance R diag(s^2) R^T (fp32), opacity
-  float q[4];
-  for (int k = 0; k < 4; ++k) q[k] = params[(STEEPGS_ROW_QUAT + k) * n + i];
-  const float qn = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-  const float w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
-  const float Rq[3][3] = {{1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y)},
-                          {2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x)},
-                          {2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)}};
-  float sc[3];
-  for (int k = 0; k < 3; ++k) sc[k] = expf(params[(STEEPGS_ROW_LOG_SCALE + k) * n + i]);
-  float Sig[3][3];
-  for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b)
-      Sig[a][b] = Rq[a][0] * sc[0] * sc[0] * Rq[b][0] + Rq[a][1] * sc[1] * sc[1] * Rq[b][1] +
-                  Rq[a][2] * sc[2] * sc[2] * Rq[b][2];
-  const float o = 1.f / (1.f + expf(-params[STEEPGS_ROW_OPACITY * n + i]));
-
-  float dp[3] = {0.f, 0.f, 0.f}, dSig[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, dop = 0.f;
-  float S3[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  float dsh[3 * NB];
-#pragma unroll
-  for (int k = 0; k < 3 * NB; ++k) dsh[k] = 0.f;
-  bool any = false;
-  // views in groups of 32: which of them see the Gaussian is loaded up front
-  // (eight flags in flight at a time), and the slot of the next visible view
-  // is in flight while the current one is processed; the view index stays
-  // uniform over the wavefront, so camera data remain scalar loads
-  for (int v0 = 0; v0 < V; v0 += 32) {
-  const int nv = min(32, V - v0);
+// bit v - v0 set when view v of [v0, v0 + 32) sees Gaussian i (eight flags in
+// flight at a time)
+SG_DEV uint32_t visible_views(const uint32_t* __restrict__ tiles, int64_t n, int64_t i, int v0, int nv) {
   uint32_t vis = 0;
   for (int k0 = 0; k0 < nv; k0 += 8) {
     uint32_t f[8];
@@ -327,228 +291,279 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) k
 #pragma unroll
     for (int k = 0; k < 8; ++k) vis |= (f[k] != 0u ? 1u : 0u) << (k0 + k);
   }
-  float4 c0 = make_float4(0.f, 0.f, 0.f, 0.f), c1 = c0;
-  float c2 = 0.f;
-  if (vis & 1u) {
-    const float* slot = g2d + ((int64_t)v0 * n + i) * stride;
-    c0 = *reinterpret_cast<const float4*>(slot);
-    c1 = *reinterpret_cast<const float4*>(slot + 4);
-    c2 = slot[8];
-  }
-  for (int k = 0; k < nv; ++k) {
-    const int v = v0 + k;
-    const float4 u0 = c0, u1 = c1;
-    const float u2 = c2;
-    if (k + 1 < nv && ((vis >> (k + 1)) & 1u)) {
-      const float* slot = g2d + ((int64_t)(v + 1) * n + i) * stride;
-      c0 = *reinterpret_cast<const float4*>(slot);
-      c1 = *reinterpret_cast<const float4*>(slot + 4);
-      c2 = slot[8];
-    }
-    if (!((vis >> k) & 1u)) continue;
-    float G9[9];
-    G9[0] = u0.x; G9[1] = u0.y; G9[2] = u0.z; G9[3] = u0.w;
-    G9[4] = u1.x; G9[5] = u1.y; G9[6] = u1.z; G9[7] = u1.w;
-    G9[8] = u2;
-    bool nz = false;
-    for (int k = 0; k < 9; ++k) nz |= G9[k] != 0.f;
-    if (!nz) continue;
-    any = true;
-    const steepgs_camera& cam = cams[v];
-    float W[9];
-    for (int k = 0; k < 9; ++k) W[k] = cam.R[k];
-    const float fx = cam.fx, fy = cam.fy;
-    const float m1x = G9[0], m1y = G9[1], m2xx = G9[2], m2xy = G9[3], m2yy = G9[4], go = G9[5];
+  return vis;
+}
 
-    // camera-space position: fp64 in the forward's operation order for the guard decision
-    double pcd[3];
-    {
+// One thread per Gaussian, two passes over the views: the colour (SH) part
+// in fp32, then the geometric chain -- camera map, Pi(Sigma), its inverse,
+// (quaternion, scale) -- and the splitting-matrix lift in fp64 (the conic of a
+// thin footprint, condition number kappa, loses ~kappa ulps when inverted or
+// differentiated in fp32).  The passes keep the SH coefficients and the
+// fp64 geometry out of each other's live range.  The view index stays
+// uniform over the wavefront, so camera data are scalar loads.
+template <int D>
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) k_proj_bwd(const float* __restrict__ params, int64_t n,
+                                                  const steepgs_camera* __restrict__ cams, int V, steepgs_opts opt,
+                                                  const uint32_t* __restrict__ tiles, const double* __restrict__ g2d,
+                                                  int stride, float* __restrict__ grads, float* __restrict__ S) {
+  constexpr int NB = (D + 1) * (D + 1);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float pf[3];
+  for (int k = 0; k < 3; ++k) pf[k] = params[(STEEPGS_ROW_MEAN + k) * n + i];
+  double dp[3] = {0.0, 0.0, 0.0};
+  bool any = false;
+
+  // pass 1: colour, rgb = max(0, sum_k sh_k Y_k(dir) + 1/2) (the clamp decision
+  // re-taken in fp64 when within 1e-5 of zero)
+  {
+    float sh[3 * NB];
+#pragma unroll
+    for (int k = 0; k < 3 * NB; ++k) sh[k] = params[(STEEPGS_ROW_SH + k) * n + i];
+    float dsh[3 * NB];
+#pragma unroll
+    for (int k = 0; k < 3 * NB; ++k) dsh[k] = 0.f;
+    for (int v0 = 0; v0 < V; v0 += 32) {
+      const int nv = min(32, V - v0);
+      const uint32_t vis = visible_views(tiles, n, i, v0, nv);
+      for (int k = 0; k < nv; ++k) {
+        if (!((vis >> k) & 1u)) continue;
+        const int v = v0 + k;
+        const double* slot = g2d + ((int64_t)v * n + i) * stride;
+        const float gcol[3] = {(float)slot[6], (float)slot[7], (float)slot[8]};
+        if (gcol[0] == 0.f && gcol[1] == 0.f && gcol[2] == 0.f) continue;
+        any = true;
+        const steepgs_camera& cam = cams[v];
+        float campos[3];
+        for (int e = 0; e < 3; ++e)
+          campos[e] = -(cam.R[0 + e] * cam.t[0] + cam.R[3 + e] * cam.t[1] + cam.R[6 + e] * cam.t[2]);
+        const float dv[3] = {pf[0] - campos[0], pf[1] - campos[1], pf[2] - campos[2]};
+        const float dlen = sqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+        const float idl = 1.f / dlen;
+        const float dir[3] = {dv[0] * idl, dv[1] * idl, dv[2] * idl};
+        float Y[NB];
+        sh_eval<float>(D, dir[0], dir[1], dir[2], Y);
+        float dcol[3];
+        for (int ch = 0; ch < 3; ++ch) {
+          float raw = 0.5f;
+#pragma unroll
+          for (int e = 0; e < NB; ++e) raw += sh[3 * e + ch] * Y[e];
+          bool clamped = raw < 0.f;
+          if (fabsf(raw) < 1e-5f) clamped = colour_clamped_fp64(params, n, i, D, cam, ch);
+          dcol[ch] = clamped ? 0.f : gcol[ch];
+        }
+        float dY[NB];
+#pragma unroll
+        for (int e = 0; e < NB; ++e) {
+          dY[e] = sh[3 * e] * dcol[0] + sh[3 * e + 1] * dcol[1] + sh[3 * e + 2] * dcol[2];
+          dsh[3 * e] += Y[e] * dcol[0];
+          dsh[3 * e + 1] += Y[e] * dcol[1];
+          dsh[3 * e + 2] += Y[e] * dcol[2];
+        }
+        if (D > 0) {
+          float gd[3] = {0.f, 0.f, 0.f};
+          sh_grad<float>(D, dir[0], dir[1], dir[2], dY, gd);
+          const float dot = gd[0] * dir[0] + gd[1] * dir[1] + gd[2] * dir[2];
+          for (int e = 0; e < 3; ++e) dp[e] += (double)((gd[e] - dir[e] * dot) * idl);
+        }
+      }
+    }
+    if (any) {
+#pragma unroll
+      for (int k = 0; k < 3 * NB; ++k) grads[(STEEPGS_ROW_SH + k) * n + i] += dsh[k];
+    }
+  }
+
+  // pass 2: geometry.  Covariance R diag(s^2) R^T and opacity in fp64.
+  double q[4];
+  for (int k = 0; k < 4; ++k) q[k] = (double)params[(STEEPGS_ROW_QUAT + k) * n + i];
+  const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  const double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+  const double Rq[3][3] = {{1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y)},
+                           {2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x)},
+                           {2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)}};
+  double sc[3];
+  for (int k = 0; k < 3; ++k) sc[k] = exp((double)params[(STEEPGS_ROW_LOG_SCALE + k) * n + i]);
+  const int ij[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+  double Sg[6];  // unique entries xx xy xz yy yz zz
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int a = ij[k][0], b = ij[k][1];
+    Sg[k] = Rq[a][0] * sc[0] * sc[0] * Rq[b][0] + Rq[a][1] * sc[1] * sc[1] * Rq[b][1] +
+            Rq[a][2] * sc[2] * sc[2] * Rq[b][2];
+  }
+  const double o = 1.0 / (1.0 + exp(-(double)params[STEEPGS_ROW_OPACITY * n + i]));
+  double dSig[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, dop = 0.0;
+  double S3[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int v0 = 0; v0 < V; v0 += 32) {
+    const int nv = min(32, V - v0);
+    const uint32_t vis = visible_views(tiles, n, i, v0, nv);
+    for (int k = 0; k < nv; ++k) {
+      if (!((vis >> k) & 1u)) continue;
+      const int v = v0 + k;
+      const double* slot = g2d + ((int64_t)v * n + i) * stride;
+      const double m1x = slot[0], m1y = slot[1], m2xx = slot[2], m2xy = slot[3], m2yy = slot[4], go = slot[5];
+      if (m1x == 0.0 && m1y == 0.0 && m2xx == 0.0 && m2xy == 0.0 && m2yy == 0.0 && go == 0.0) continue;
+      any = true;
+      const steepgs_camera& cam = cams[v];
+      double W[9];
+#pragma unroll
+      for (int e = 0; e < 9; ++e) W[e] = (double)cam.R[e];
+      const double fx = cam.fx, fy = cam.fy;
+
+      // camera-space position: fp64 in the forward's operation order for the guard decision
+      double pcd[3];
+      {
 #pragma clang fp contract(off)
-      for (int k = 0; k < 3; ++k)
-        pcd[k] = (double)cam.R[3 * k + 0] * (double)p[0] + (double)cam.R[3 * k + 1] * (double)p[1] +
-                 (double)cam.R[3 * k + 2] * (double)p[2] + (double)cam.t[k];
-    }
-    const float pcx = (float)pcd[0], pcy = (float)pcd[1], pcz = (float)pcd[2];
-    float J[2][3];
-    float gx = 0.f, gy = 0.f;
-    bool gx_free = false, gy_free = false;
-    if (cam.model == 0) {
-      double gxd = pcd[0] / pcd[2], gyd = pcd[1] / pcd[2];
-      gx_free = gy_free = true;
-      if (opt.frustum_guard > 0.f) {
-        const double limx = (double)opt.frustum_guard * (0.5 * cam.width / (double)cam.fx);
-        const double limy = (double)opt.frustum_guard * (0.5 * cam.height / (double)cam.fy);
-        if (gxd < -limx) { gxd = -limx; gx_free = false; }
-        if (gxd > limx) { gxd = limx; gx_free = false; }
-        if (gyd < -limy) { gyd = -limy; gy_free = false; }
-        if (gyd > limy) { gyd = limy; gy_free = false; }
+        for (int e = 0; e < 3; ++e)
+          pcd[e] = (double)cam.R[3 * e + 0] * (double)pf[0] + (double)cam.R[3 * e + 1] * (double)pf[1] +
+                   (double)cam.R[3 * e + 2] * (double)pf[2] + (double)cam.t[e];
       }
-      gx = (float)gxd;
-      gy = (float)gyd;
-      const float iz = 1.f / pcz;
-      J[0][0] = fx * iz; J[0][1] = 0.f; J[0][2] = -fx * gx * iz;
-      J[1][0] = 0.f; J[1][1] = fy * iz; J[1][2] = -fy * gy * iz;
-    } else {
-      J[0][0] = fx; J[0][1] = 0.f; J[0][2] = 0.f;
-      J[1][0] = 0.f; J[1][1] = fy; J[1][2] = 0.f;
-    }
-    float P[2][3];
-    for (int a = 0; a < 2; ++a)
-      for (int c = 0; c < 3; ++c) P[a][c] = J[a][0] * W[c] + J[a][1] * W[3 + c] + J[a][2] * W[6 + c];
-    // Pi(Sigma) and its inverse (the conic)
-    float PS[2][3];
-    for (int a = 0; a < 2; ++a)
-      for (int c = 0; c < 3; ++c) PS[a][c] = P[a][0] * Sig[0][c] + P[a][1] * Sig[1][c] + P[a][2] * Sig[2][c];
-    const float s00 = PS[0][0] * P[0][0] + PS[0][1] * P[0][1] + PS[0][2] * P[0][2] + opt.dilation;
-    const float s01 = PS[0][0] * P[1][0] + PS[0][1] * P[1][1] + PS[0][2] * P[1][2];
-    const float s11 = PS[1][0] * P[1][0] + PS[1][1] * P[1][1] + PS[1][2] * P[1][2] + opt.dilation;
-    const float idet = 1.f / (s00 * s11 - s01 * s01);
-    const float A[2][2] = {{s11 * idet, -s01 * idet}, {-s01 * idet, s00 * idet}};
-    // 2D mean and conic gradients from the moments
-    const float gmx = A[0][0] * m1x + A[0][1] * m1y, gmy = A[1][0] * m1x + A[1][1] * m1y;
-    const float ga = -0.5f * m2xx, gb = -m2xy, gc = -0.5f * m2yy;
-
-    // colour: rgb = max(0, sum_k sh_k Y_k(dir) + 1/2)
-    float campos[3];
-    for (int k = 0; k < 3; ++k) campos[k] = -(W[0 + k] * cam.t[0] + W[3 + k] * cam.t[1] + W[6 + k] * cam.t[2]);
-    float dv[3] = {p[0] - campos[0], p[1] - campos[1], p[2] - campos[2]};
-    const float dlen = sqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
-    const float idl = 1.f / dlen;
-    const float dir[3] = {dv[0] * idl, dv[1] * idl, dv[2] * idl};
-    float Y[NB];
-    sh_eval<float>(D, dir[0], dir[1], dir[2], Y);
-    float dcol[3];
-    for (int ch = 0; ch < 3; ++ch) {
-      float raw = 0.5f;
-#pragma unroll
-      for (int k = 0; k < NB; ++k) raw += sh[3 * k + ch] * Y[k];
-      bool clamped = raw < 0.f;
-      if (fabsf(raw) < 1e-5f) clamped = colour_clamped_fp64(params, n, i, D, cam, ch);
-      dcol[ch] = clamped ? 0.f : G9[6 + ch];
-    }
-    float dY[NB];
-#pragma unroll
-    for (int k = 0; k < NB; ++k) {
-      dY[k] = sh[3 * k] * dcol[0] + sh[3 * k + 1] * dcol[1] + sh[3 * k + 2] * dcol[2];
-      dsh[3 * k] += Y[k] * dcol[0];
-      dsh[3 * k + 1] += Y[k] * dcol[1];
-      dsh[3 * k + 2] += Y[k] * dcol[2];
-    }
-    if (D > 0) {
-      float gd[3] = {0.f, 0.f, 0.f};
-      sh_grad<float>(D, dir[0], dir[1], dir[2], dY, gd);
-      const float dot = gd[0] * dir[0] + gd[1] * dir[1] + gd[2] * dir[2];
-      for (int k = 0; k < 3; ++k) dp[k] += (gd[k] - dir[k] * dot) * idl;
-    }
-
-    // conic -> Pi(Sigma): dL/dS2 = -A G_A A, G_A = [[ga, gb/2], [gb/2, gc]]
-    const float GA[2][2] = {{ga, 0.5f * gb}, {0.5f * gb, gc}};
-    float AG[2][2], GS2[2][2];
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b) AG[a][b] = A[a][0] * GA[0][b] + A[a][1] * GA[1][b];
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b) GS2[a][b] = -(AG[a][0] * A[0][b] + AG[a][1] * A[1][b]);
-    // Pi(Sigma) = P Sigma P^T + dilation: dL/dSigma += P^T GS2 P; dL/dP = 2 GS2 P Sigma
-    float GSP[2][3];
-    for (int a = 0; a < 2; ++a)
-      for (int c = 0; c < 3; ++c) GSP[a][c] = GS2[a][0] * P[0][c] + GS2[a][1] * P[1][c];
-    const int ij[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      const int c = ij[k][0], d = ij[k][1];
-      dSig[k] += P[0][c] * GSP[0][d] + P[1][c] * GSP[1][d];
-    }
-    float GJ[2][3];
-    for (int a = 0; a < 2; ++a) {
-      float GP[3];
-      for (int c = 0; c < 3; ++c)
-        GP[c] = 2.f * (GSP[a][0] * Sig[0][c] + GSP[a][1] * Sig[1][c] + GSP[a][2] * Sig[2][c]);
-      // P = J W: dL/dJ = dL/dP W^T
-      for (int b = 0; b < 3; ++b) GJ[a][b] = GP[0] * W[3 * b + 0] + GP[1] * W[3 * b + 1] + GP[2] * W[3 * b + 2];
-    }
-    // camera-space position gradient from the mean and from J
-    float dpc[3] = {0.f, 0.f, 0.f};
-    float Pe[2][3];  // Jacobian of the projected mean w.r.t. p (exact, unguarded)
-    if (cam.model == 0) {
-      const float iz = 1.f / pcz, iz2 = iz * iz;
-      dpc[0] += gmx * fx * iz;
-      dpc[1] += gmy * fy * iz;
-      dpc[2] -= (gmx * fx * pcx + gmy * fy * pcy) * iz2;
-      dpc[2] -= (GJ[0][0] * fx + GJ[1][1] * fy) * iz2;
-      // J02 = -fx gx / z, J12 = -fy gy / z with gx = x/z unless clamped
-      dpc[2] += (GJ[0][2] * fx * gx + GJ[1][2] * fy * gy) * iz2;
-      if (gx_free) {
-        dpc[0] -= GJ[0][2] * fx * iz2;
-        dpc[2] += GJ[0][2] * fx * pcx * iz2 * iz;
+      double J[2][3];
+      double gx = 0.0, gy = 0.0;
+      bool gx_free = false, gy_free = false;
+      if (cam.model == 0) {
+        gx = pcd[0] / pcd[2];
+        gy = pcd[1] / pcd[2];
+        gx_free = gy_free = true;
+        if (opt.frustum_guard > 0.f) {
+          const double limx = (double)opt.frustum_guard * (0.5 * cam.width / (double)cam.fx);
+          const double limy = (double)opt.frustum_guard * (0.5 * cam.height / (double)cam.fy);
+          if (gx < -limx) { gx = -limx; gx_free = false; }
+          if (gx > limx) { gx = limx; gx_free = false; }
+          if (gy < -limy) { gy = -limy; gy_free = false; }
+          if (gy > limy) { gy = limy; gy_free = false; }
+        }
+        const double iz = 1.0 / pcd[2];
+        J[0][0] = fx * iz; J[0][1] = 0.0; J[0][2] = -fx * gx * iz;
+        J[1][0] = 0.0; J[1][1] = fy * iz; J[1][2] = -fy * gy * iz;
+      } else {
+        J[0][0] = fx; J[0][1] = 0.0; J[0][2] = 0.0;
+        J[1][0] = 0.0; J[1][1] = fy; J[1][2] = 0.0;
       }
-      if (gy_free) {
-        dpc[1] -= GJ[1][2] * fy * iz2;
-        dpc[2] += GJ[1][2] * fy * pcy * iz2 * iz;
-      }
-      const float Je[2][3] = {{fx * iz, 0.f, -fx * pcx * iz2}, {0.f, fy * iz, -fy * pcy * iz2}};
+      double P[2][3];
       for (int a = 0; a < 2; ++a)
-        for (int c = 0; c < 3; ++c) Pe[a][c] = Je[a][0] * W[c] + Je[a][2] * W[6 + c] + Je[a][1] * W[3 + c];
-    } else {
-      dpc[0] += gmx * fx;
-      dpc[1] += gmy * fy;
+        for (int c = 0; c < 3; ++c) P[a][c] = J[a][0] * W[c] + J[a][1] * W[3 + c] + J[a][2] * W[6 + c];
+      const double Sig[3][3] = {{Sg[0], Sg[1], Sg[2]}, {Sg[1], Sg[3], Sg[4]}, {Sg[2], Sg[4], Sg[5]}};
+      // Pi(Sigma) and its inverse (the conic)
+      double PS[2][3];
       for (int a = 0; a < 2; ++a)
-        for (int c = 0; c < 3; ++c) Pe[a][c] = P[a][c];
-    }
-    for (int c = 0; c < 3; ++c) dp[c] += W[c] * dpc[0] + W[3 + c] * dpc[1] + W[6 + c] * dpc[2];
-    dop += go;
+        for (int c = 0; c < 3; ++c) PS[a][c] = P[a][0] * Sig[0][c] + P[a][1] * Sig[1][c] + P[a][2] * Sig[2][c];
+      const double s00 = PS[0][0] * P[0][0] + PS[0][1] * P[0][1] + PS[0][2] * P[0][2] + (double)opt.dilation;
+      const double s01 = PS[0][0] * P[1][0] + PS[0][1] * P[1][1] + PS[0][2] * P[1][2];
+      const double s11 = PS[1][0] * P[1][0] + PS[1][1] * P[1][1] + PS[1][2] * P[1][2] + (double)opt.dilation;
+      const double idet = 1.0 / (s00 * s11 - s01 * s01);
+      const double A[2][2] = {{s11 * idet, -s01 * idet}, {-s01 * idet, s00 * idet}};
+      // 2D mean and conic gradients from the moments
+      const double gmx = A[0][0] * m1x + A[0][1] * m1y, gmy = A[1][0] * m1x + A[1][1] * m1y;
+      const double ga = -0.5 * m2xx, gb = -m2xy, gc = -0.5 * m2yy;
 
-    // splitting matrix: S2D = A M A - m0 A, M = m2, m0 = o * go
-    const float M[2][2] = {{m2xx, m2xy}, {m2xy, m2yy}};
-    float AM[2][2], S2D[2][2];
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b) AM[a][b] = A[a][0] * M[0][b] + A[a][1] * M[1][b];
-    const float m0 = o * go;
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b) S2D[a][b] = AM[a][0] * A[0][b] + AM[a][1] * A[1][b] - m0 * A[a][b];
-    float SP[2][3];
-    for (int a = 0; a < 2; ++a)
-      for (int c = 0; c < 3; ++c) SP[a][c] = S2D[a][0] * Pe[0][c] + S2D[a][1] * Pe[1][c];
+      // conic -> Pi(Sigma): dL/dS2 = -A G_A A, G_A = [[ga, gb/2], [gb/2, gc]]
+      const double GA[2][2] = {{ga, 0.5 * gb}, {0.5 * gb, gc}};
+      double AG[2][2], GS2[2][2];
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) AG[a][b] = A[a][0] * GA[0][b] + A[a][1] * GA[1][b];
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) GS2[a][b] = -(AG[a][0] * A[0][b] + AG[a][1] * A[1][b]);
+      // Pi(Sigma) = P Sigma P^T + dilation: dL/dSigma += P^T GS2 P; dL/dP = 2 GS2 P Sigma
+      double GSP[2][3];
+      for (int a = 0; a < 2; ++a)
+        for (int c = 0; c < 3; ++c) GSP[a][c] = GS2[a][0] * P[0][c] + GS2[a][1] * P[1][c];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      const int a = ij[k][0], b = ij[k][1];
-      S3[k] += Pe[0][a] * SP[0][b] + Pe[1][a] * SP[1][b];
+      for (int e = 0; e < 6; ++e) {
+        const int c = ij[e][0], d = ij[e][1];
+        dSig[e] += P[0][c] * GSP[0][d] + P[1][c] * GSP[1][d];
+      }
+      double GJ[2][3];
+      for (int a = 0; a < 2; ++a) {
+        double GP[3];
+        for (int c = 0; c < 3; ++c)
+          GP[c] = 2.0 * (GSP[a][0] * Sig[0][c] + GSP[a][1] * Sig[1][c] + GSP[a][2] * Sig[2][c]);
+        // P = J W: dL/dJ = dL/dP W^T
+        for (int b = 0; b < 3; ++b) GJ[a][b] = GP[0] * W[3 * b + 0] + GP[1] * W[3 * b + 1] + GP[2] * W[3 * b + 2];
+      }
+      // camera-space position gradient from the mean and from J
+      double dpc[3] = {0.0, 0.0, 0.0};
+      double Pe[2][3];  // Jacobian of the projected mean w.r.t. p (exact, unguarded)
+      if (cam.model == 0) {
+        const double pcx = pcd[0], pcy = pcd[1];
+        const double iz = 1.0 / pcd[2], iz2 = iz * iz;
+        dpc[0] += gmx * fx * iz;
+        dpc[1] += gmy * fy * iz;
+        dpc[2] -= (gmx * fx * pcx + gmy * fy * pcy) * iz2;
+        dpc[2] -= (GJ[0][0] * fx + GJ[1][1] * fy) * iz2;
+        // J02 = -fx gx / z, J12 = -fy gy / z with gx = x/z unless clamped
+        dpc[2] += (GJ[0][2] * fx * gx + GJ[1][2] * fy * gy) * iz2;
+        if (gx_free) {
+          dpc[0] -= GJ[0][2] * fx * iz2;
+          dpc[2] += GJ[0][2] * fx * pcx * iz2 * iz;
+        }
+        if (gy_free) {
+          dpc[1] -= GJ[1][2] * fy * iz2;
+          dpc[2] += GJ[1][2] * fy * pcy * iz2 * iz;
+        }
+        const double Je[2][3] = {{fx * iz, 0.0, -fx * pcx * iz2}, {0.0, fy * iz, -fy * pcy * iz2}};
+        for (int a = 0; a < 2; ++a)
+          for (int c = 0; c < 3; ++c) Pe[a][c] = Je[a][0] * W[c] + Je[a][2] * W[6 + c] + Je[a][1] * W[3 + c];
+      } else {
+        dpc[0] += gmx * fx;
+        dpc[1] += gmy * fy;
+        for (int a = 0; a < 2; ++a)
+          for (int c = 0; c < 3; ++c) Pe[a][c] = P[a][c];
+      }
+      for (int c = 0; c < 3; ++c) dp[c] += W[c] * dpc[0] + W[3 + c] * dpc[1] + W[6 + c] * dpc[2];
+      dop += go;
+
+      // splitting matrix: S2D = A M A - m0 A, M = m2, m0 = o * go
+      const double M[2][2] = {{m2xx, m2xy}, {m2xy, m2yy}};
+      double AM[2][2], S2D[2][2];
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) AM[a][b] = A[a][0] * M[0][b] + A[a][1] * M[1][b];
+      const double m0 = o * go;
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) S2D[a][b] = AM[a][0] * A[0][b] + AM[a][1] * A[1][b] - m0 * A[a][b];
+      double SP[2][3];
+      for (int a = 0; a < 2; ++a)
+        for (int c = 0; c < 3; ++c) SP[a][c] = S2D[a][0] * Pe[0][c] + S2D[a][1] * Pe[1][c];
+#pragma unroll
+      for (int e = 0; e < 6; ++e) {
+        const int a = ij[e][0], b = ij[e][1];
+        S3[e] += Pe[0][a] * SP[0][b] + Pe[1][a] * SP[1][b];
+      }
     }
-  }
   }
   if (!any) return;
 
   // Sigma = M M^T, M = R diag(s): dL/dM = 2 dSig M (dSig symmetric)
-  const float G[3][3] = {{dSig[0], dSig[1], dSig[2]}, {dSig[1], dSig[3], dSig[4]}, {dSig[2], dSig[4], dSig[5]}};
-  float GR[3][3], dls[3];
+  const double G[3][3] = {{dSig[0], dSig[1], dSig[2]}, {dSig[1], dSig[3], dSig[4]}, {dSig[2], dSig[4], dSig[5]}};
+  double GR[3][3], dls[3];
   for (int k = 0; k < 3; ++k) {
-    float acc = 0.f;
+    double acc = 0.0;
     for (int a = 0; a < 3; ++a) {
-      const float gm = 2.f * (G[a][0] * Rq[0][k] + G[a][1] * Rq[1][k] + G[a][2] * Rq[2][k]) * sc[k];
+      const double gm = 2.0 * (G[a][0] * Rq[0][k] + G[a][1] * Rq[1][k] + G[a][2] * Rq[2][k]) * sc[k];
       acc += gm * Rq[a][k];
       GR[a][k] = gm * sc[k];
     }
     dls[k] = acc * sc[k];
   }
-  float dq[4];
-  dq[0] = 2.f * (-z * GR[0][1] + y * GR[0][2] + z * GR[1][0] - x * GR[1][2] - y * GR[2][0] + x * GR[2][1]);
-  dq[1] = 2.f * (y * GR[0][1] + z * GR[0][2] + y * GR[1][0] - 2.f * x * GR[1][1] - w * GR[1][2] + z * GR[2][0] +
-                 w * GR[2][1] - 2.f * x * GR[2][2]);
-  dq[2] = 2.f * (-2.f * y * GR[0][0] + x * GR[0][1] + w * GR[0][2] + x * GR[1][0] + z * GR[1][2] - w * GR[2][0] +
-                 z * GR[2][1] - 2.f * y * GR[2][2]);
-  dq[3] = 2.f * (-2.f * z * GR[0][0] - w * GR[0][1] + x * GR[0][2] + w * GR[1][0] - 2.f * z * GR[1][1] +
+  double dq[4];
+  dq[0] = 2.0 * (-z * GR[0][1] + y * GR[0][2] + z * GR[1][0] - x * GR[1][2] - y * GR[2][0] + x * GR[2][1]);
+  dq[1] = 2.0 * (y * GR[0][1] + z * GR[0][2] + y * GR[1][0] - 2.0 * x * GR[1][1] - w * GR[1][2] + z * GR[2][0] +
+                 w * GR[2][1] - 2.0 * x * GR[2][2]);
+  dq[2] = 2.0 * (-2.0 * y * GR[0][0] + x * GR[0][1] + w * GR[0][2] + x * GR[1][0] + z * GR[1][2] - w * GR[2][0] +
+                 z * GR[2][1] - 2.0 * y * GR[2][2]);
+  dq[3] = 2.0 * (-2.0 * z * GR[0][0] - w * GR[0][1] + x * GR[0][2] + w * GR[1][0] - 2.0 * z * GR[1][1] +
                  y * GR[1][2] + x * GR[2][0] + y * GR[2][1]);
   // through the normalisation q_hat = q / |q|
-  const float qd = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
-  const float qh[4] = {w, x, y, z};
+  const double qd = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
+  const double qh[4] = {w, x, y, z};
   float* gp = grads + i;
-  for (int k = 0; k < 3; ++k) gp[(STEEPGS_ROW_MEAN + k) * n] += dp[k];
-  for (int k = 0; k < 3; ++k) gp[(STEEPGS_ROW_LOG_SCALE + k) * n] += dls[k];
-  for (int k = 0; k < 4; ++k) gp[(STEEPGS_ROW_QUAT + k) * n] += (dq[k] - qh[k] * qd) / qn;
-  gp[STEEPGS_ROW_OPACITY * n] += dop * o * (1.f - o);
-#pragma unroll
-  for (int k = 0; k < 3 * NB; ++k) gp[(STEEPGS_ROW_SH + k) * n] += dsh[k];
+  for (int k = 0; k < 3; ++k) gp[(STEEPGS_ROW_MEAN + k) * n] += (float)dp[k];
+  for (int k = 0; k < 3; ++k) gp[(STEEPGS_ROW_LOG_SCALE + k) * n] += (float)dls[k];
+  for (int k = 0; k < 4; ++k) gp[(STEEPGS_ROW_QUAT + k) * n] += (float)((dq[k] - qh[k] * qd) / qn);
+  gp[STEEPGS_ROW_OPACITY * n] += (float)(dop * o * (1.0 - o));
   if (S)
-    for (int k = 0; k < 6; ++k) S[k * n + i] += S3[k];
+    for (int k = 0; k < 6; ++k) S[k * n + i] += (float)S3[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -576,41 +591,41 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) k
 SG_DEV int h6_slot(int i, int j) { return i <= j ? i * 6 - i * (i - 1) / 2 + (j - i) : j * 6 - j * (j - 1) / 2 + (i - j); }
 
 // coefficients of (a . d)^2 in (dx^2, dx dy, dy^2)
-SG_DEV void sq_coef(const float a[2], float c[3]) {
+SG_DEV void sq_coef(const double a[2], double c[3]) {
   c[0] = a[0] * a[0];
-  c[1] = 2.f * a[0] * a[1];
+  c[1] = 2.0 * a[0] * a[1];
   c[2] = a[1] * a[1];
 }
 
 __global__ void __launch_bounds__(128) k_split6_lift(const float* __restrict__ params, int64_t n,
                                                      const steepgs_camera* __restrict__ cams, int V, steepgs_opts opt,
-                                                     const uint32_t* __restrict__ tiles, const float* __restrict__ g2d,
+                                                     const uint32_t* __restrict__ tiles, const double* __restrict__ g2d,
                                                      float* __restrict__ S6) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  float p[3], q[4], s2[3];
+  double p[3], q[4], s2[3];
   for (int k = 0; k < 3; ++k) p[k] = params[(STEEPGS_ROW_MEAN + k) * n + i];
   for (int k = 0; k < 4; ++k) q[k] = params[(STEEPGS_ROW_QUAT + k) * n + i];
-  for (int k = 0; k < 3; ++k) s2[k] = expf(2.f * params[(STEEPGS_ROW_LOG_SCALE + k) * n + i]);
-  const float qn = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-  const float w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
-  const float Rq[3][3] = {{1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y)},
-                          {2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x)},
-                          {2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)}};
-  const float o = 1.f / (1.f + expf(-params[STEEPGS_ROW_OPACITY * n + i]));
-  float acc[21];
+  for (int k = 0; k < 3; ++k) s2[k] = exp(2.0 * params[(STEEPGS_ROW_LOG_SCALE + k) * n + i]);
+  const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  const double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+  const double Rq[3][3] = {{1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y)},
+                          {2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x)},
+                          {2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)}};
+  const double o = 1.0 / (1.0 + exp(-params[STEEPGS_ROW_OPACITY * n + i]));
+  double acc[21];
 #pragma unroll
-  for (int k = 0; k < 21; ++k) acc[k] = 0.f;
+  for (int k = 0; k < 21; ++k) acc[k] = 0.0;
   for (int v = 0; v < V; ++v) {
     const int64_t r = (int64_t)v * n + i;
     if (tiles[r] == 0) continue;
-    const float* slot = g2d + r * kG2dStride6;
-    const float m1[2] = {slot[0], slot[1]};
-    const float m2[3] = {slot[2], slot[3], slot[4]};  // xx, xy, yy
-    const float go = slot[5];
-    const float m3[4] = {slot[9], slot[10], slot[11], slot[12]};  // xxx, xxy, xyy, yyy
-    const float m4[5] = {slot[13], slot[14], slot[15], slot[16], slot[17]};  // xxxx .. yyyy
-    if (m1[0] == 0.f && m1[1] == 0.f && m2[0] == 0.f && m2[1] == 0.f && m2[2] == 0.f && go == 0.f) continue;
+    const double* slot = g2d + r * kG2dStride6;
+    const double m1[2] = {slot[0], slot[1]};
+    const double m2[3] = {slot[2], slot[3], slot[4]};  // xx, xy, yy
+    const double go = slot[5];
+    const double m3[4] = {slot[9], slot[10], slot[11], slot[12]};  // xxx, xxy, xyy, yyy
+    const double m4[5] = {slot[13], slot[14], slot[15], slot[16], slot[17]};  // xxxx .. yyyy
+    if (m1[0] == 0.0 && m1[1] == 0.0 && m2[0] == 0.0 && m2[1] == 0.0 && m2[2] == 0.0 && go == 0.0) continue;
     const steepgs_camera& cam = cams[v];
     // camera space (fp64 for the guard decision, as the forward)
     double pcd[3];
@@ -620,52 +635,52 @@ __global__ void __launch_bounds__(128) k_split6_lift(const float* __restrict__ p
         pcd[k] = (double)cam.R[3 * k + 0] * (double)p[0] + (double)cam.R[3 * k + 1] * (double)p[1] +
                  (double)cam.R[3 * k + 2] * (double)p[2] + (double)cam.t[k];
     }
-    float Jg[2][3], Je[2][3];
+    double Jg[2][3], Je[2][3];
     if (cam.model == 0) {
       double gxd = pcd[0] / pcd[2], gyd = pcd[1] / pcd[2];
       const double exd = gxd, eyd = gyd;
-      if (opt.frustum_guard > 0.f) {
+      if (opt.frustum_guard > 0.0) {
         const double limx = (double)opt.frustum_guard * (0.5 * cam.width / (double)cam.fx);
         const double limy = (double)opt.frustum_guard * (0.5 * cam.height / (double)cam.fy);
         gxd = gxd < -limx ? -limx : (gxd > limx ? limx : gxd);
         gyd = gyd < -limy ? -limy : (gyd > limy ? limy : gyd);
       }
-      const float iz = (float)(1.0 / pcd[2]);
-      Jg[0][0] = cam.fx * iz; Jg[0][1] = 0.f; Jg[0][2] = -cam.fx * (float)gxd * iz;
-      Jg[1][0] = 0.f; Jg[1][1] = cam.fy * iz; Jg[1][2] = -cam.fy * (float)gyd * iz;
-      Je[0][0] = Jg[0][0]; Je[0][1] = 0.f; Je[0][2] = -cam.fx * (float)exd * iz;
-      Je[1][0] = 0.f; Je[1][1] = Jg[1][1]; Je[1][2] = -cam.fy * (float)eyd * iz;
+      const double iz = 1.0 / pcd[2];
+      Jg[0][0] = cam.fx * iz; Jg[0][1] = 0.0; Jg[0][2] = -cam.fx * (double)gxd * iz;
+      Jg[1][0] = 0.0; Jg[1][1] = cam.fy * iz; Jg[1][2] = -cam.fy * (double)gyd * iz;
+      Je[0][0] = Jg[0][0]; Je[0][1] = 0.0; Je[0][2] = -cam.fx * (double)exd * iz;
+      Je[1][0] = 0.0; Je[1][1] = Jg[1][1]; Je[1][2] = -cam.fy * (double)eyd * iz;
     } else {
-      Jg[0][0] = cam.fx; Jg[0][1] = 0.f; Jg[0][2] = 0.f;
-      Jg[1][0] = 0.f; Jg[1][1] = cam.fy; Jg[1][2] = 0.f;
+      Jg[0][0] = cam.fx; Jg[0][1] = 0.0; Jg[0][2] = 0.0;
+      Jg[1][0] = 0.0; Jg[1][1] = cam.fy; Jg[1][2] = 0.0;
       for (int a = 0; a < 2; ++a)
         for (int c = 0; c < 3; ++c) Je[a][c] = Jg[a][c];
     }
-    float Pg[2][3], Pe[2][3];
+    double Pg[2][3], Pe[2][3];
     for (int a = 0; a < 2; ++a)
       for (int c = 0; c < 3; ++c) {
         Pg[a][c] = Jg[a][0] * cam.R[c] + Jg[a][1] * cam.R[3 + c] + Jg[a][2] * cam.R[6 + c];
         Pe[a][c] = Je[a][0] * cam.R[c] + Je[a][1] * cam.R[3 + c] + Je[a][2] * cam.R[6 + c];
       }
     // w_k = Pg r_k; Sigma_2D = sum_k sig_k^2 w_k w_k^T + dilation; A its inverse
-    float wv[3][2];
+    double wv[3][2];
     for (int k = 0; k < 3; ++k)
       for (int a = 0; a < 2; ++a) wv[k][a] = Pg[a][0] * Rq[0][k] + Pg[a][1] * Rq[1][k] + Pg[a][2] * Rq[2][k];
-    float c00 = opt.dilation, c01 = 0.f, c11 = opt.dilation;
+    double c00 = opt.dilation, c01 = 0.0, c11 = opt.dilation;
     for (int k = 0; k < 3; ++k) {
       c00 += s2[k] * wv[k][0] * wv[k][0];
       c01 += s2[k] * wv[k][0] * wv[k][1];
       c11 += s2[k] * wv[k][1] * wv[k][1];
     }
-    const float idet = (float)(1.0 / ((double)c00 * (double)c11 - (double)c01 * (double)c01));
-    const float A[2][2] = {{c11 * idet, -c01 * idet}, {-c01 * idet, c00 * idet}};
-    const float m0 = o * go;
-    float ak[3][2];
+    const double idet = 1.0 / (c00 * c11 - c01 * c01);
+    const double A[2][2] = {{c11 * idet, -c01 * idet}, {-c01 * idet, c00 * idet}};
+    const double m0 = o * go;
+    double ak[3][2];
     for (int k = 0; k < 3; ++k)
       for (int a = 0; a < 2; ++a) ak[k][a] = A[a][0] * wv[k][0] + A[a][1] * wv[k][1];
-    const float M2[2][2] = {{m2[0], m2[1]}, {m2[1], m2[2]}};
+    const double M2[2][2] = {{m2[0], m2[1]}, {m2[1], m2[2]}};
     // position block: Pe^T (A m2 A - m0 A) Pe
-    float AM[2][2], K[2][2];
+    double AM[2][2], K[2][2];
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b) AM[a][b] = A[a][0] * M2[0][b] + A[a][1] * M2[1][b];
     for (int a = 0; a < 2; ++a)
@@ -674,21 +689,21 @@ __global__ void __launch_bounds__(128) k_split6_lift(const float* __restrict__ p
     for (int a = 0; a < 3; ++a)
 #pragma unroll
       for (int b = a; b < 3; ++b) {
-        float t = 0.f;
+        double t = 0.0;
         for (int x2 = 0; x2 < 2; ++x2)
           for (int y2 = 0; y2 < 2; ++y2) t += Pe[x2][a] * K[x2][y2] * Pe[y2][b];
         acc[h6_slot(a, b)] += t;
       }
     // mixed block
-    float cf[3][3];
+    double cf[3][3];
     for (int k = 0; k < 3; ++k) sq_coef(ak[k], cf[k]);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const float t3x = cf[k][0] * m3[0] + cf[k][1] * m3[1] + cf[k][2] * m3[2];
-      const float t3y = cf[k][0] * m3[1] + cf[k][1] * m3[2] + cf[k][2] * m3[3];
-      const float c1 = ak[k][0] * m1[0] + ak[k][1] * m1[1];
-      const float vx = A[0][0] * t3x + A[0][1] * t3y - 2.f * c1 * ak[k][0];
-      const float vy = A[1][0] * t3x + A[1][1] * t3y - 2.f * c1 * ak[k][1];
+      const double t3x = cf[k][0] * m3[0] + cf[k][1] * m3[1] + cf[k][2] * m3[2];
+      const double t3y = cf[k][0] * m3[1] + cf[k][1] * m3[2] + cf[k][2] * m3[3];
+      const double c1 = ak[k][0] * m1[0] + ak[k][1] * m1[1];
+      const double vx = A[0][0] * t3x + A[0][1] * t3y - 2.0 * c1 * ak[k][0];
+      const double vy = A[1][0] * t3x + A[1][1] * t3y - 2.0 * c1 * ak[k][1];
 #pragma unroll
       for (int a = 0; a < 3; ++a) acc[h6_slot(a, 3 + k)] += s2[k] * (Pe[0][a] * vx + Pe[1][a] * vy);
     }
@@ -697,37 +712,46 @@ __global__ void __launch_bounds__(128) k_split6_lift(const float* __restrict__ p
     for (int j = 0; j < 3; ++j)
 #pragma unroll
       for (int k = j; k < 3; ++k) {
-        const float* aj = cf[j];
-        const float* bk = cf[k];
-        const float t4 = aj[0] * bk[0] * m4[0] + (aj[0] * bk[1] + aj[1] * bk[0]) * m4[1] +
+        const double* aj = cf[j];
+        const double* bk = cf[k];
+        const double t4 = aj[0] * bk[0] * m4[0] + (aj[0] * bk[1] + aj[1] * bk[0]) * m4[1] +
                          (aj[0] * bk[2] + aj[1] * bk[1] + aj[2] * bk[0]) * m4[2] +
                          (aj[1] * bk[2] + aj[2] * bk[1]) * m4[3] + aj[2] * bk[2] * m4[4];
-        const float t2 = ak[j][0] * (M2[0][0] * ak[k][0] + M2[0][1] * ak[k][1]) +
+        const double t2 = ak[j][0] * (M2[0][0] * ak[k][0] + M2[0][1] * ak[k][1]) +
                          ak[j][1] * (M2[1][0] * ak[k][0] + M2[1][1] * ak[k][1]);
-        const float Mjk = wv[j][0] * ak[k][0] + wv[j][1] * ak[k][1];
-        float t = s2[j] * s2[k] * (t4 - 4.f * Mjk * t2);
-        if (j == k) t += 2.f * s2[k] * t2;
+        const double Mjk = wv[j][0] * ak[k][0] + wv[j][1] * ak[k][1];
+        double t = s2[j] * s2[k] * (t4 - 4.0 * Mjk * t2);
+        if (j == k) t += 2.0 * s2[k] * t2;
         acc[h6_slot(3 + j, 3 + k)] += t;
       }
   }
 #pragma unroll
-  for (int k = 0; k < 21; ++k) S6[k * n + i] += acc[k];
+  for (int k = 0; k < 21; ++k) S6[k * n + i] += (float)acc[k];
 }
 
 // the caller's 2D-gradient buffer: moments -> mean and conic gradients, with
 // the conic the raster kernels used (the projected record's)
 __global__ void k_export2d(const steepgs_splat* __restrict__ splats, const uint32_t* __restrict__ tiles, int64_t m,
-                           float* __restrict__ g2d) {
+                           const double* __restrict__ g2d, float* __restrict__ out) {
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x) {
-    if (tiles[r] == 0) continue;
-    float* slot = g2d + r * kG2dStride;
-    const float m1x = slot[0], m1y = slot[1], m2xx = slot[2], m2xy = slot[3], m2yy = slot[4];
-    const float a = splats[r].conic_a, b = splats[r].conic_b, c = splats[r].conic_c;
-    slot[0] = a * m1x + b * m1y;
-    slot[1] = b * m1x + c * m1y;
-    slot[2] = -0.5f * m2xx;
-    slot[3] = -m2xy;
-    slot[4] = -0.5f * m2yy;
+    float* o = out + r * kGrad2dOut;
+    float v[kGrad2dOut];
+#pragma unroll
+    for (int k = 0; k < kGrad2dOut; ++k) v[k] = 0.f;
+    if (tiles[r] != 0) {
+      const double* slot = g2d + r * kG2dStride;
+      const double m1x = slot[0], m1y = slot[1];
+      const double a = splats[r].conic_a, b = splats[r].conic_b, c = splats[r].conic_c;
+      v[0] = (float)(a * m1x + b * m1y);
+      v[1] = (float)(b * m1x + c * m1y);
+      v[2] = (float)(-0.5 * slot[2]);
+      v[3] = (float)(-slot[3]);
+      v[4] = (float)(-0.5 * slot[4]);
+#pragma unroll
+      for (int k = 5; k < 9; ++k) v[k] = (float)slot[k];
+    }
+#pragma unroll
+    for (int k = 0; k < kGrad2dOut; ++k) o[k] = v[k];
   }
 }
 
@@ -736,21 +760,26 @@ __global__ void k_zero(float* __restrict__ p, int64_t count) {
     p[i] = 0.f;
 }
 
-static size_t bwd_layout(void* base, int64_t m, int stride, float** g2d, uint32_t** queue) {
+__global__ void k_zero64(double* __restrict__ p, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+static size_t bwd_layout(void* base, int64_t m, int stride, double** g2d, uint32_t** queue) {
   Carver c(base);
   *queue = c.take<uint32_t>(64);
-  *g2d = c.take<float>((size_t)stride * m);
+  *g2d = c.take<double>((size_t)stride * m);
   return c.used + 256;
 }
 
 size_t render_bwd_workspace(int64_t m) {
-  float* g;
+  double* g;
   uint32_t* q;
   return bwd_layout(nullptr, m, kG2dStride, &g, &q);
 }
 
 size_t render_bwd6_workspace(int64_t m) {
-  float* g;
+  double* g;
   uint32_t* q;
   return bwd_layout(nullptr, m, kG2dStride6, &g, &q);
 }
@@ -759,7 +788,7 @@ template <int TW, int TH, bool H6>
 static void launch_bwd(int grid, hipStream_t st, const steepgs_splat* splats, const uint32_t* vals,
                        const uint32_t* ranges, const steepgs_camera* cams, int V, const steepgs_opts& opt,
                        int total_tiles, const float* image, const float* T_final, const uint32_t* n_contrib,
-                       const float* dL_dimage, const float* target, float* g2d, int64_t m, uint32_t* queue) {
+                       const float* dL_dimage, const float* target, double* g2d, int64_t m, uint32_t* queue) {
   hipLaunchKernelGGL((k_render_bwd<TW, TH, H6>), dim3(grid), dim3(64 * kBwdWaves), 0, st, splats, vals, ranges, cams, V, opt,
                      total_tiles, image, T_final, n_contrib, dL_dimage, target, g2d, m, queue);
 }
@@ -784,15 +813,14 @@ static steepgs_status bwd_impl(const float* d_params, int64_t n, int32_t sh_degr
   if (!d_params || !d_splats || !d_tiles_touched || !d_grads || (!d_S && !h6)) return STEEPGS_ERR_INVALID_ARG;
   const int64_t m = (int64_t)V * n;
   const int stride = h6 ? kG2dStride6 : kG2dStride;
-  float* g2d;
+  double* g2d;
   uint32_t* queue;
   const size_t need = bwd_layout(nullptr, m, stride, &g2d, &queue);
   if (!d_ws || ws_bytes < need) return STEEPGS_ERR_WORKSPACE;
   bwd_layout(d_ws, m, stride, &g2d, &queue);
-  if (d_grad2d) g2d = d_grad2d;
   hipStream_t st = as_stream(stream);
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, reinterpret_cast<float*>(queue), (int64_t)1);
-  hipLaunchKernelGGL(k_zero, dim3(stride_grid(stride * m, 256)), dim3(256), 0, st, g2d, stride * m);
+  hipLaunchKernelGGL(k_zero64, dim3(stride_grid(stride * m, 256)), dim3(256), 0, st, g2d, stride * m);
   const int grid = (int)std::min<int64_t>(ceil_div(total_tiles, kBwdWaves), (int64_t)device_cu_count() * 8);
   const steepgs_opts& o = *opts;
   timer_begin(STEEPGS_TIMER_RENDER_BWD, st);
@@ -820,7 +848,8 @@ static steepgs_status bwd_impl(const float* d_params, int64_t n, int32_t sh_degr
   if (h6) hipLaunchKernelGGL(k_split6_lift, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d, d_S6);
   timer_end(STEEPGS_TIMER_PROJ_BWD, st);
   if (d_grad2d && !h6)
-    hipLaunchKernelGGL(k_export2d, dim3(stride_grid(m, 256)), dim3(256), 0, st, d_splats, d_tiles_touched, m, d_grad2d);
+    hipLaunchKernelGGL(k_export2d, dim3(stride_grid(m, 256)), dim3(256), 0, st, d_splats, d_tiles_touched, m, g2d,
+                       d_grad2d);
   SG_TRY_LAUNCH();
   return STEEPGS_OK;
 }

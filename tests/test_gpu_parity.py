@@ -15,12 +15,12 @@ import pytest
 import torch
 
 from paper_2505_05587_amd import scenes
-from tests.gpu_common import (assert_group_close, assert_S_close, conditioned_rel, expand_pixel_mask, image_close,
+from tests.gpu_common import (assert_group_close, assert_S_close, expand_pixel_mask, image_close,
                               run_gpu, scene_small)
 
 pytestmark = pytest.mark.gpu
 
-KINDS = ["plain_small", "sh3_pinhole", "multiview", "ortho", "extreme"]
+KINDS = ["plain_small", "sh3_pinhole", "multiview", "ortho", "extreme", "extreme_rand"]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -70,7 +70,7 @@ def test_forward_backward(oracle, kind, mode):
     # excluded fractions: the extreme scene's needles, seen far along their
     # long axis, carry pairs whose float32 quadratic form is ill-conditioned
     # (the oracle flags them from the bound 2^-24 (|a| dx^2 + 2|b dx dy| + |c| dy^2))
-    lim_pix, lim_g = (0.02, 0.15) if kind == "extreme" else (1e-3 if mode == "smooth" else 5e-3, 0.1)
+    lim_pix, lim_g = (0.02, 0.15) if kind.startswith("extreme") else (1e-3 if mode == "smooth" else 5e-3, 0.1)
     assert pix_amb.mean() < lim_pix
     ok = image_close(g["image"], ref["image"], expand_pixel_mask(pix_amb, cams))
     assert ok.all(), f"{(~ok).sum()} image values out of tolerance"
@@ -80,9 +80,8 @@ def test_forward_backward(oracle, kind, mode):
     np.testing.assert_allclose(g["loss"], ref["loss"], rtol=1e-4)
     gamb = ref["gauss_ambig"]
     assert gamb.mean() < lim_g
-    rel = conditioned_rel(oracle, P, deg, cams, opts)
-    assert_group_close(g["grads"], ref["grads"], gamb, rel=rel, what=f"{kind}/{mode}", gross=ref["grads_abs"])
-    assert_S_close(g["S6"], ref["S"], gamb, rel=rel, gross=ref["S_abs"])
+    assert_group_close(g["grads"], ref["grads"], gamb, what=f"{kind}/{mode}", gross=ref["grads_abs"])
+    assert_S_close(g["S6"], ref["S"], gamb, gross=ref["S_abs"], what=f"{kind}/{mode}")
 
 
 @pytest.mark.parametrize("kind", ["multiview", "sh3_pinhole"])
@@ -244,3 +243,30 @@ def test_empty_set_and_tiny_views(oracle, n):
     assert_group_close(grads.cpu().numpy().astype(np.float64), ref["grads"], gamb, what=f"tiny/{n}",
                        gross=ref["grads_abs"])
     assert_S_close(S.cpu().numpy().astype(np.float64), ref["S"], gamb, gross=ref["S_abs"])
+
+
+@pytest.mark.parametrize("kind", ["extreme_rand", "multiview"])
+def test_backward_bitwise_repeatable(kind):
+    # the cross-tile sums are fp64 atomics of float32 per-tile partials: their
+    # hardware-chosen order does not show in the float32 gradients and S, so
+    # repeated backward launches on one forward state agree bit for bit
+    P, deg, cams, target = scene_small(kind)
+    opts = scenes.opts("3dgs")
+    print(f"\n[case] backward repeatability kind={kind}", flush=True)
+    from paper_2505_05587_amd import pipeline
+    dev = torch.device("cuda", 0)
+    ras = pipeline.Rasterizer(pipeline.CameraBatch(cams, opts, dev), deg, capacity=1 << 16)
+    Pt = torch.from_numpy(np.ascontiguousarray(P)).to(dev)
+    tg = torch.from_numpy(np.ascontiguousarray(target)).to(dev)
+    ras.forward(Pt, tg)
+    outs = []
+    for _ in range(4):
+        grads = torch.zeros_like(Pt)
+        S = torch.zeros((6, P.shape[1]), dtype=torch.float32, device=dev)
+        ras.backward(Pt, grads, S, target=tg)
+        torch.cuda.synchronize()
+        outs.append((grads.cpu().numpy().view(np.uint32), S.cpu().numpy().view(np.uint32)))
+    assert np.abs(outs[0][1].view(np.float32)).max() > 0
+    for g, s in outs[1:]:
+        np.testing.assert_array_equal(g, outs[0][0])
+        np.testing.assert_array_equal(s, outs[0][1])

@@ -6,7 +6,7 @@ import pytest
 import torch
 
 from paper_2505_05587_amd import pipeline, scenes
-from tests.gpu_common import assert_group_close, conditioned_rel, scene_small
+from tests.gpu_common import assert_group_close, scene_small
 
 pytestmark = pytest.mark.gpu
 
@@ -41,7 +41,7 @@ def test_split6_matches_oracle(oracle, kind, mode):
     ref = oracle.forward_backward(P, deg, cams, opts, target)
     ref6 = oracle.split6(P, deg, cams, opts, target)
     amb = ref["gauss_ambig"]
-    rel = conditioned_rel(oracle, P, deg, cams, opts)
+    rel = 1e-3
     # the gradients of the dim-6 backward are those of the plain one
     assert_group_close(grads.cpu().numpy().astype(np.float64), ref["grads"], amb, rel=rel, what=f"{kind}/{mode}",
                        gross=ref["grads_abs"])
@@ -52,8 +52,9 @@ def test_split6_matches_oracle(oracle, kind, mode):
     tol = rel * r + 1e-6 * r.max()
     bad = keep & (d > tol)
     assert not bad.any(), f"{bad.sum()} of {keep.sum()} S6 out of tolerance; worst {np.max((d / tol)[keep]):.2f}"
-    # and its position block is the dim-3 S (two float32 evaluations of one
-    # quantity: per Gaussian within the conditioned bar)
+    print(f"[bar] split6 {kind}/{mode} S6: worst |d|/tol = {np.max((d / tol)[keep]):.3f}", flush=True)
+    # and its position block is the dim-3 S (two fp64 lifts of the same
+    # moments: per Gaussian within the bar)
     S3g = S3.cpu().numpy().astype(np.float64)
     M3 = np.zeros((P.shape[1], 3, 3))
     for k, (i, j) in enumerate([(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]):

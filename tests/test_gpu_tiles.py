@@ -8,7 +8,7 @@ import torch
 
 from paper_2505_05587_amd import scenes
 from paper_2505_05587_amd.autotune import tune
-from tests.gpu_common import (assert_group_close, assert_S_close, conditioned_rel, expand_pixel_mask, image_close,
+from tests.gpu_common import (assert_group_close, assert_S_close, expand_pixel_mask, image_close,
                               run_gpu, scene_small)
 
 pytestmark = pytest.mark.gpu
@@ -29,10 +29,9 @@ def test_tile_shape_parity(oracle, kind, tile):
     ref = oracle.forward_backward(P, deg, cams, opts, target)
     ok = image_close(g["image"], ref["image"], expand_pixel_mask(ref["pix_ambig"], cams))
     assert ok.all()
-    rel = conditioned_rel(oracle, P, deg, cams, opts)
-    assert_group_close(g["grads"], ref["grads"], ref["gauss_ambig"], rel=rel, what=f"tile {tile}",
+    assert_group_close(g["grads"], ref["grads"], ref["gauss_ambig"], what=f"tile {tile} {kind}",
                        gross=ref["grads_abs"])
-    assert_S_close(g["S6"], ref["S"], ref["gauss_ambig"], rel=rel, gross=ref["S_abs"])
+    assert_S_close(g["S6"], ref["S"], ref["gauss_ambig"], gross=ref["S_abs"], what=f"tile {tile} {kind}")
     # the image does not depend on the tiling
     g16 = run_gpu(P, deg, cams, scenes.opts("3dgs"), target=target)
     np.testing.assert_array_equal(g["image"], g16["image"])
