@@ -34,14 +34,19 @@
 namespace sg {
 
 constexpr int kBwdWaves = 4;    // wavefronts per workgroup, each on a tile of its own
-// doubles per record in the backward's accumulation slots: the raster
-// backward leaves (m1_x, m1_y, m2_xx, m2_xy, m2_yy, dL/do, dL/dr, dL/dg,
-// dL/db) in entries 0-8 (fp64 sums of the per-tile float32 partials)
-constexpr int kG2dStride = 9;
-// with the splitting matrix over theta = (p, log-scales) the slot also holds
-// the third and fourth moments: (m3_xxx, m3_xxy, m3_xyy, m3_yyy,
-// m4_xxxx, m4_xxxy, m4_xxyy, m4_xyyy, m4_yyyy) in entries 9-17
-constexpr int kG2dStride6 = 18;
+// The backward's per-record accumulators (fp64 sums of the per-tile float32
+// partials): slot [m][9] = (m1_x, m1_y, m2_xx, m2_xy, m2_yy, dL/do, dL/dr,
+// dL/dg, dL/db), one 72-byte block per record so that the nine atomics of a
+// (tile, entry) touch one or two cache lines (planar geometry and colour
+// arrays were measured 0.1 ms slower in the raster backward on the 16-view
+// workload).  With the splitting matrix over theta = (p, log-scales) a
+// second array h6 [m][9] holds the third and fourth moments (m3_xxx, m3_xxy,
+// m3_xyy, m3_yyy, m4_xxxx, m4_xxxy, m4_xxyy, m4_xyyy, m4_yyyy).
+struct Slots {
+  double* slot;
+  double* h6;
+};
+constexpr int kSlot = 9, kH6 = 9;
 // floats per record of the caller's optional 2D-gradient output
 constexpr int kGrad2dOut = 12;
 
@@ -58,7 +63,7 @@ __global__ void __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_pe
                                                                const uint32_t* __restrict__ n_contrib,
                                                                const float* __restrict__ dL_dimage,
                                                                const float* __restrict__ target,
-                                                               double* __restrict__ g2d, int64_t m,
+                                                               Slots g2d, int64_t m,
                                                                uint32_t* __restrict__ queue) {
   constexpr int NQ = TW * TH / 64;  // 8x8 quadrants of the tile = pixels per lane
   constexpr int QX = TW / 8;
@@ -240,12 +245,12 @@ __global__ void __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_pe
           // hardware-chosen order leaves the float32 results unchanged
           const float part[9] = {mx, my, mxx, mxy, myy, go, gr, gg, gbl};
           const float tot = reduce9(part);
-          double* const slot = g2d + (int64_t)__float_as_uint(E[j].y) * (H6 ? kG2dStride6 : kG2dStride);
-          if (red_idx >= 0) unsafeAtomicAdd(slot + red_idx, (double)tot);
+          const int64_t rid = (int64_t)__float_as_uint(E[j].y);
+          if (red_idx >= 0) unsafeAtomicAdd(g2d.slot + rid * kSlot + red_idx, (double)tot);
           if (H6) {
             const float part2[9] = {h3[0], h3[1], h3[2], h3[3], h4[0], h4[1], h4[2], h4[3], h4[4]};
             const float tot2 = reduce9(part2);
-            if (red_idx >= 0) unsafeAtomicAdd(slot + 9 + red_idx, (double)tot2);
+            if (red_idx >= 0) unsafeAtomicAdd(g2d.h6 + rid * kH6 + red_idx, (double)tot2);
           }
         }
       }
@@ -280,6 +285,21 @@ __device__ __noinline__ bool colour_clamped_fp64(const float* __restrict__ param
   return acc < 0.0;
 }
 
+// fp64 rotation of the normalised quaternion qh = q / |q| and the scales
+// exp(log_scale) of Gaussian i
+SG_DEV void rotation_scales(const float* __restrict__ params, int64_t n, int64_t i, double Rq[3][3], double sc[3],
+                            double qh[4], double& qn) {
+  double q[4];
+  for (int k = 0; k < 4; ++k) q[k] = (double)params[(STEEPGS_ROW_QUAT + k) * n + i];
+  qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  for (int k = 0; k < 4; ++k) qh[k] = q[k] / qn;
+  const double w = qh[0], x = qh[1], y = qh[2], z = qh[3];
+  Rq[0][0] = 1.0 - 2.0 * (y * y + z * z); Rq[0][1] = 2.0 * (x * y - w * z); Rq[0][2] = 2.0 * (x * z + w * y);
+  Rq[1][0] = 2.0 * (x * y + w * z); Rq[1][1] = 1.0 - 2.0 * (x * x + z * z); Rq[1][2] = 2.0 * (y * z - w * x);
+  Rq[2][0] = 2.0 * (x * z - w * y); Rq[2][1] = 2.0 * (y * z + w * x); Rq[2][2] = 1.0 - 2.0 * (x * x + y * y);
+  for (int k = 0; k < 3; ++k) sc[k] = exp((double)params[(STEEPGS_ROW_LOG_SCALE + k) * n + i]);
+}
+
 // bit v - v0 set when view v of [v0, v0 + 32) sees Gaussian i (eight flags in
 // flight at a time)
 SG_DEV uint32_t visible_views(const uint32_t* __restrict__ tiles, int64_t n, int64_t i, int v0, int nv) {
@@ -305,7 +325,7 @@ template <int D>
 __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) k_proj_bwd(const float* __restrict__ params, int64_t n,
                                                   const steepgs_camera* __restrict__ cams, int V, steepgs_opts opt,
                                                   const uint32_t* __restrict__ tiles, const double* __restrict__ g2d,
-                                                  int stride, float* __restrict__ grads, float* __restrict__ S) {
+                                                  float* __restrict__ grads, float* __restrict__ S) {
   constexpr int NB = (D + 1) * (D + 1);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -329,7 +349,7 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) k
       for (int k = 0; k < nv; ++k) {
         if (!((vis >> k) & 1u)) continue;
         const int v = v0 + k;
-        const double* slot = g2d + ((int64_t)v * n + i) * stride;
+        const double* slot = g2d + ((int64_t)v * n + i) * kSlot;
         const float gcol[3] = {(float)slot[6], (float)slot[7], (float)slot[8]};
         if (gcol[0] == 0.f && gcol[1] == 0.f && gcol[2] == 0.f) continue;
         any = true;
@@ -374,23 +394,19 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) k
     }
   }
 
-  // pass 2: geometry.  Covariance R diag(s^2) R^T and opacity in fp64.
-  double q[4];
-  for (int k = 0; k < 4; ++k) q[k] = (double)params[(STEEPGS_ROW_QUAT + k) * n + i];
-  const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-  const double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
-  const double Rq[3][3] = {{1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y)},
-                           {2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x)},
-                           {2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)}};
-  double sc[3];
-  for (int k = 0; k < 3; ++k) sc[k] = exp((double)params[(STEEPGS_ROW_LOG_SCALE + k) * n + i]);
+  // pass 2: geometry.  Covariance R diag(s^2) R^T and opacity in fp64; the
+  // rotation is formed again after the loop rather than kept live across it.
   const int ij[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
   double Sg[6];  // unique entries xx xy xz yy yz zz
+  {
+    double Rq[3][3], sc[3], qh[4], qn;
+    rotation_scales(params, n, i, Rq, sc, qh, qn);
 #pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    const int a = ij[k][0], b = ij[k][1];
-    Sg[k] = Rq[a][0] * sc[0] * sc[0] * Rq[b][0] + Rq[a][1] * sc[1] * sc[1] * Rq[b][1] +
-            Rq[a][2] * sc[2] * sc[2] * Rq[b][2];
+    for (int k = 0; k < 6; ++k) {
+      const int a = ij[k][0], b = ij[k][1];
+      Sg[k] = Rq[a][0] * sc[0] * sc[0] * Rq[b][0] + Rq[a][1] * sc[1] * sc[1] * Rq[b][1] +
+              Rq[a][2] * sc[2] * sc[2] * Rq[b][2];
+    }
   }
   const double o = 1.0 / (1.0 + exp(-(double)params[STEEPGS_ROW_OPACITY * n + i]));
   double dSig[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, dop = 0.0;
@@ -401,7 +417,7 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) k
     for (int k = 0; k < nv; ++k) {
       if (!((vis >> k) & 1u)) continue;
       const int v = v0 + k;
-      const double* slot = g2d + ((int64_t)v * n + i) * stride;
+      const double* slot = g2d + ((int64_t)v * n + i) * kSlot;
       const double m1x = slot[0], m1y = slot[1], m2xx = slot[2], m2xy = slot[3], m2yy = slot[4], go = slot[5];
       if (m1x == 0.0 && m1y == 0.0 && m2xx == 0.0 && m2xy == 0.0 && m2yy == 0.0 && go == 0.0) continue;
       any = true;
@@ -535,6 +551,9 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) k
   if (!any) return;
 
   // Sigma = M M^T, M = R diag(s): dL/dM = 2 dSig M (dSig symmetric)
+  double Rq[3][3], sc[3], qh[4], qn;
+  rotation_scales(params, n, i, Rq, sc, qh, qn);
+  const double w = qh[0], x = qh[1], y = qh[2], z = qh[3];
   const double G[3][3] = {{dSig[0], dSig[1], dSig[2]}, {dSig[1], dSig[3], dSig[4]}, {dSig[2], dSig[4], dSig[5]}};
   double GR[3][3], dls[3];
   for (int k = 0; k < 3; ++k) {
@@ -556,7 +575,6 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) k
                  y * GR[1][2] + x * GR[2][0] + y * GR[2][1]);
   // through the normalisation q_hat = q / |q|
   const double qd = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
-  const double qh[4] = {w, x, y, z};
   float* gp = grads + i;
   for (int k = 0; k < 3; ++k) gp[(STEEPGS_ROW_MEAN + k) * n] += (float)dp[k];
   for (int k = 0; k < 3; ++k) gp[(STEEPGS_ROW_LOG_SCALE + k) * n] += (float)dls[k];
@@ -600,7 +618,7 @@ SG_DEV void sq_coef(const double a[2], double c[3]) {
 __global__ void __launch_bounds__(128) k_split6_lift(const float* __restrict__ params, int64_t n,
                                                      const steepgs_camera* __restrict__ cams, int V, steepgs_opts opt,
                                                      const uint32_t* __restrict__ tiles, const double* __restrict__ g2d,
-                                                     float* __restrict__ S6) {
+                                                     const double* __restrict__ h6, float* __restrict__ S6) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double p[3], q[4], s2[3];
@@ -619,12 +637,13 @@ __global__ void __launch_bounds__(128) k_split6_lift(const float* __restrict__ p
   for (int v = 0; v < V; ++v) {
     const int64_t r = (int64_t)v * n + i;
     if (tiles[r] == 0) continue;
-    const double* slot = g2d + r * kG2dStride6;
+    const double* slot = g2d + r * kSlot;
+    const double* hs = h6 + r * kH6;
     const double m1[2] = {slot[0], slot[1]};
     const double m2[3] = {slot[2], slot[3], slot[4]};  // xx, xy, yy
     const double go = slot[5];
-    const double m3[4] = {slot[9], slot[10], slot[11], slot[12]};  // xxx, xxy, xyy, yyy
-    const double m4[5] = {slot[13], slot[14], slot[15], slot[16], slot[17]};  // xxxx .. yyyy
+    const double m3[4] = {hs[0], hs[1], hs[2], hs[3]};  // xxx, xxy, xyy, yyy
+    const double m4[5] = {hs[4], hs[5], hs[6], hs[7], hs[8]};  // xxxx .. yyyy
     if (m1[0] == 0.0 && m1[1] == 0.0 && m2[0] == 0.0 && m2[1] == 0.0 && m2[2] == 0.0 && go == 0.0) continue;
     const steepgs_camera& cam = cams[v];
     // camera space (fp64 for the guard decision, as the forward)
@@ -739,7 +758,7 @@ __global__ void k_export2d(const steepgs_splat* __restrict__ splats, const uint3
 #pragma unroll
     for (int k = 0; k < kGrad2dOut; ++k) v[k] = 0.f;
     if (tiles[r] != 0) {
-      const double* slot = g2d + r * kG2dStride;
+      const double* slot = g2d + r * kSlot;
       const double m1x = slot[0], m1y = slot[1];
       const double a = splats[r].conic_a, b = splats[r].conic_b, c = splats[r].conic_c;
       v[0] = (float)(a * m1x + b * m1y);
@@ -765,30 +784,33 @@ __global__ void k_zero64(double* __restrict__ p, int64_t count) {
     p[i] = 0.0;
 }
 
-static size_t bwd_layout(void* base, int64_t m, int stride, double** g2d, uint32_t** queue) {
+// the slot arrays are carved back to back, so one fill clears them
+static size_t bwd_layout(void* base, int64_t m, bool h6, Slots* g2d, uint32_t** queue) {
   Carver c(base);
   *queue = c.take<uint32_t>(64);
-  *g2d = c.take<double>((size_t)stride * m);
+  double* all = c.take<double>((size_t)(kSlot + (h6 ? kH6 : 0)) * m);
+  g2d->slot = all;
+  g2d->h6 = (all && h6) ? all + (size_t)kSlot * m : nullptr;
   return c.used + 256;
 }
 
 size_t render_bwd_workspace(int64_t m) {
-  double* g;
+  Slots g;
   uint32_t* q;
-  return bwd_layout(nullptr, m, kG2dStride, &g, &q);
+  return bwd_layout(nullptr, m, false, &g, &q);
 }
 
 size_t render_bwd6_workspace(int64_t m) {
-  double* g;
+  Slots g;
   uint32_t* q;
-  return bwd_layout(nullptr, m, kG2dStride6, &g, &q);
+  return bwd_layout(nullptr, m, true, &g, &q);
 }
 
 template <int TW, int TH, bool H6>
 static void launch_bwd(int grid, hipStream_t st, const steepgs_splat* splats, const uint32_t* vals,
                        const uint32_t* ranges, const steepgs_camera* cams, int V, const steepgs_opts& opt,
                        int total_tiles, const float* image, const float* T_final, const uint32_t* n_contrib,
-                       const float* dL_dimage, const float* target, double* g2d, int64_t m, uint32_t* queue) {
+                       const float* dL_dimage, const float* target, Slots g2d, int64_t m, uint32_t* queue) {
   hipLaunchKernelGGL((k_render_bwd<TW, TH, H6>), dim3(grid), dim3(64 * kBwdWaves), 0, st, splats, vals, ranges, cams, V, opt,
                      total_tiles, image, T_final, n_contrib, dL_dimage, target, g2d, m, queue);
 }
@@ -812,15 +834,15 @@ static steepgs_status bwd_impl(const float* d_params, int64_t n, int32_t sh_degr
   if (n == 0) return STEEPGS_OK;  // nothing to accumulate; the per-Gaussian buffers may be empty
   if (!d_params || !d_splats || !d_tiles_touched || !d_grads || (!d_S && !h6)) return STEEPGS_ERR_INVALID_ARG;
   const int64_t m = (int64_t)V * n;
-  const int stride = h6 ? kG2dStride6 : kG2dStride;
-  double* g2d;
+  const int per_record = kSlot + (h6 ? kH6 : 0);
+  Slots g2d;
   uint32_t* queue;
-  const size_t need = bwd_layout(nullptr, m, stride, &g2d, &queue);
+  const size_t need = bwd_layout(nullptr, m, h6, &g2d, &queue);
   if (!d_ws || ws_bytes < need) return STEEPGS_ERR_WORKSPACE;
-  bwd_layout(d_ws, m, stride, &g2d, &queue);
+  bwd_layout(d_ws, m, h6, &g2d, &queue);
   hipStream_t st = as_stream(stream);
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, reinterpret_cast<float*>(queue), (int64_t)1);
-  hipLaunchKernelGGL(k_zero64, dim3(stride_grid(stride * m, 256)), dim3(256), 0, st, g2d, stride * m);
+  hipLaunchKernelGGL(k_zero64, dim3(stride_grid(per_record * m, 256)), dim3(256), 0, st, g2d.slot, per_record * m);
   const int grid = (int)std::min<int64_t>(ceil_div(total_tiles, kBwdWaves), (int64_t)device_cu_count() * 8);
   const steepgs_opts& o = *opts;
   timer_begin(STEEPGS_TIMER_RENDER_BWD, st);
@@ -840,15 +862,17 @@ static steepgs_status bwd_impl(const float* d_params, int64_t n, int32_t sh_degr
   timer_begin(STEEPGS_TIMER_PROJ_BWD, st);
   const dim3 pg((unsigned)ceil_div(n, 128));
   switch (sh_degree) {
-    case 0: hipLaunchKernelGGL(k_proj_bwd<0>, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d, stride, d_grads, d_S); break;
-    case 1: hipLaunchKernelGGL(k_proj_bwd<1>, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d, stride, d_grads, d_S); break;
-    case 2: hipLaunchKernelGGL(k_proj_bwd<2>, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d, stride, d_grads, d_S); break;
-    default: hipLaunchKernelGGL(k_proj_bwd<3>, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d, stride, d_grads, d_S); break;
+    case 0: hipLaunchKernelGGL(k_proj_bwd<0>, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d.slot, d_grads, d_S); break;
+    case 1: hipLaunchKernelGGL(k_proj_bwd<1>, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d.slot, d_grads, d_S); break;
+    case 2: hipLaunchKernelGGL(k_proj_bwd<2>, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d.slot, d_grads, d_S); break;
+    default: hipLaunchKernelGGL(k_proj_bwd<3>, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d.slot, d_grads, d_S); break;
   }
-  if (h6) hipLaunchKernelGGL(k_split6_lift, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d, d_S6);
+  if (h6)
+    hipLaunchKernelGGL(k_split6_lift, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d.slot,
+                       g2d.h6, d_S6);
   timer_end(STEEPGS_TIMER_PROJ_BWD, st);
   if (d_grad2d && !h6)
-    hipLaunchKernelGGL(k_export2d, dim3(stride_grid(m, 256)), dim3(256), 0, st, d_splats, d_tiles_touched, m, g2d,
+    hipLaunchKernelGGL(k_export2d, dim3(stride_grid(m, 256)), dim3(256), 0, st, d_splats, d_tiles_touched, m, g2d.slot,
                        d_grad2d);
   SG_TRY_LAUNCH();
   return STEEPGS_OK;
