@@ -187,6 +187,25 @@ steepgs_status steepgs_render_fwd(const steepgs_splat* d_splats, int64_t n, cons
                                   const float* d_target, float* d_image, float* d_T_final, uint32_t* d_n_contrib,
                                   uint32_t* d_n_used, float* d_loss, void* d_ws, size_t ws_bytes, void* stream);
 
+/* steepgs_render_fwd without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same inputs, outputs, errors and results
+ * as steepgs_render_fwd.  Its scratch -- the persistent launch's 4-byte
+ * tile-queue counter, cleared by a kernel at every call -- lives in a
+ * 256-byte file-scope device array of the library, one copy per GPU, which
+ * the GPU holds until the process ends; its address is looked up on the
+ * first call on each device (current device at call time, at most 64
+ * devices; the stream must belong to that device).  The call allocates
+ * nothing.  Every call on one GPU shares that array: calls that overlap on
+ * one GPU (other streams, other host threads) race; calls in stream order
+ * do not.  STEEPGS_ERR_WORKSPACE if the forward ever needed more scratch
+ * than the array holds; STEEPGS_ERR_HIP if the array cannot be located. */
+steepgs_status steepgs_render_fwd_noalloc(const steepgs_splat* d_splats, int64_t n, const uint32_t* d_vals,
+                                          const uint32_t* d_tile_ranges, const steepgs_camera* d_cams, int32_t V,
+                                          const steepgs_opts* opts, int32_t total_tiles, int64_t total_pixels,
+                                          const float* d_target, float* d_image, float* d_T_final,
+                                          uint32_t* d_n_contrib, uint32_t* d_n_used, float* d_loss, void* stream);
+
 /* Stage 4 -- backward of the blend and the projection, and the splitting
  * matrices (Theorem 1; Sec. 4.4).  Loss gradient per pixel: d_dL_dimage when
  * non-null, else the L1 loss of Eq. (loss) against d_target (sum over views

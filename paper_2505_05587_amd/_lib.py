@@ -73,6 +73,8 @@ def lib():
         L.steepgs_sort.argtypes = [vp, vp, vp, i64, i32, vp, C.POINTER(Opts), i32, vp, vp, u64, vp, vp, vp, vp, sz, vp]
         L.steepgs_render_fwd.argtypes = [vp, i64, vp, vp, vp, i32, C.POINTER(Opts), i32, i64, vp, vp, vp, vp, vp,
                                          vp, vp, sz, vp]
+        L.steepgs_render_fwd_noalloc.argtypes = [vp, i64, vp, vp, vp, i32, C.POINTER(Opts), i32, i64, vp, vp, vp,
+                                                 vp, vp, vp, vp]
         L.steepgs_set_kernel_timer.argtypes = [i32, vp, vp, i32]
         L.steepgs_set_kernel_timer.restype = C.c_int
         L.steepgs_render_bwd_split.argtypes = [vp, i64, i32, vp, i32, C.POINTER(Opts), vp, vp, vp, vp, i32, i64,
@@ -84,6 +86,7 @@ def lib():
         L.steepgs_adam_step.argtypes = [vp, vp, vp, vp, i64, i32, C.POINTER(AdamOpts), vp, vp, vp, vp]
         L.steepgs_split_remap.argtypes = [vp, i32, i64, vp, vp, i64, vp, sz, vp]
         for fn in ("steepgs_layout_cameras", "steepgs_project", "steepgs_sort", "steepgs_render_fwd",
+                   "steepgs_render_fwd_noalloc",
                    "steepgs_render_bwd_split", "steepgs_densify", "steepgs_adam_step", "steepgs_split_remap",
                    "steepgs_render_bwd_split6", "steepgs_densify6"):
             getattr(L, fn).restype = C.c_int
@@ -158,6 +161,14 @@ def steepgs_render_fwd(splats, n, vals, tile_ranges, d_cams, V, opts, total_tile
                                     total_tiles, total_pixels, _p(target), _p(image), _p(T_final), _p(n_contrib),
                                     _p(n_used), _p(loss), _p(ws), ws.numel() * ws.element_size(),
                                     _stream(stream)))
+
+
+def steepgs_render_fwd_noalloc(splats, n, vals, tile_ranges, d_cams, V, opts, total_tiles, total_pixels, target,
+                               image, T_final, n_contrib, n_used, loss, stream=None):
+    _check("steepgs_render_fwd_noalloc",
+           lib().steepgs_render_fwd_noalloc(_p(splats), n, _p(vals), _p(tile_ranges), _p(d_cams), V, C.byref(opts),
+                                            total_tiles, total_pixels, _p(target), _p(image), _p(T_final),
+                                            _p(n_contrib), _p(n_used), _p(loss), _stream(stream)))
 
 
 TIMER_PROJECT, TIMER_SORT, TIMER_RENDER_FWD, TIMER_RENDER_BWD, TIMER_PROJ_BWD, TIMER_DENSIFY = range(6)

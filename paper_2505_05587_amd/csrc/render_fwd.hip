@@ -11,6 +11,8 @@
 // reach (or whose pixels are all saturated) is skipped for the whole
 // wavefront.  The wavefront leaves the tile when every pixel's
 // transmittance has hit the cut-off.
+#include <mutex>
+
 #include "common.h"
 
 namespace sg {
@@ -196,23 +198,25 @@ static void launch_fwd(int grid, hipStream_t st, const steepgs_splat* splats, co
 
 using namespace sg;
 
-extern "C" steepgs_status steepgs_render_fwd(const steepgs_splat* d_splats, int64_t n, const uint32_t* d_vals,
-                                             const uint32_t* d_tile_ranges, const steepgs_camera* d_cams, int32_t V,
-                                             const steepgs_opts* opts, int32_t total_tiles, int64_t total_pixels,
-                                             const float* d_target, float* d_image, float* d_T_final,
-                                             uint32_t* d_n_contrib, uint32_t* d_n_used, float* d_loss, void* d_ws,
-                                             size_t ws_bytes,
-                                             void* stream) {
+static steepgs_status fwd_check(int64_t n, const uint32_t* d_tile_ranges, const steepgs_camera* d_cams, int32_t V,
+                                const steepgs_opts* opts, int32_t total_tiles, int64_t total_pixels,
+                                const float* d_target, float* d_image, float* d_T_final, uint32_t* d_n_contrib,
+                                float* d_loss) {
   if (n < 0 || V <= 0 || total_tiles <= 0 || total_pixels <= 0 || !opts_ok(opts)) return STEEPGS_ERR_INVALID_ARG;
   if (!d_tile_ranges || !d_cams || !d_image || !d_T_final || !d_n_contrib) return STEEPGS_ERR_INVALID_ARG;
   if (d_target && !d_loss) return STEEPGS_ERR_INVALID_ARG;
-  if (!d_ws || ws_bytes < render_fwd_workspace()) return STEEPGS_ERR_WORKSPACE;
-  hipStream_t st = as_stream(stream);
-  uint32_t* queue = static_cast<uint32_t*>(d_ws);
+  return STEEPGS_OK;
+}
+
+// queue: the persistent launch's tile counter (zeroed here by a kernel, so
+// that the call stays legal under graph capture)
+static steepgs_status fwd_launch(const steepgs_splat* d_splats, const uint32_t* d_vals, const uint32_t* d_tile_ranges,
+                                 const steepgs_camera* d_cams, int32_t V, const steepgs_opts& o, int32_t total_tiles,
+                                 const float* d_target, float* d_image, float* d_T_final, uint32_t* d_n_contrib,
+                                 uint32_t* d_n_used, float* d_loss, uint32_t* queue, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, queue, (int64_t)1);
   if (d_target) hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)ceil_div(V, 64)), dim3(64), 0, st, d_loss, (int64_t)V);
   const int grid = (int)std::min<int64_t>(ceil_div(total_tiles, kFwdWaves), (int64_t)device_cu_count() * 8);
-  const steepgs_opts& o = *opts;
   timer_begin(STEEPGS_TIMER_RENDER_FWD, st);
   if (o.tile_w == 16 && o.tile_h == 16)
     launch_fwd<16, 16>(grid, st, d_splats, d_vals, d_tile_ranges, d_cams, V, o, total_tiles, d_target, d_image,
@@ -226,4 +230,68 @@ extern "C" steepgs_status steepgs_render_fwd(const steepgs_splat* d_splats, int6
   timer_end(STEEPGS_TIMER_RENDER_FWD, st);
   SG_TRY_LAUNCH();
   return STEEPGS_OK;
+}
+
+extern "C" steepgs_status steepgs_render_fwd(const steepgs_splat* d_splats, int64_t n, const uint32_t* d_vals,
+                                             const uint32_t* d_tile_ranges, const steepgs_camera* d_cams, int32_t V,
+                                             const steepgs_opts* opts, int32_t total_tiles, int64_t total_pixels,
+                                             const float* d_target, float* d_image, float* d_T_final,
+                                             uint32_t* d_n_contrib, uint32_t* d_n_used, float* d_loss, void* d_ws,
+                                             size_t ws_bytes,
+                                             void* stream) {
+  const steepgs_status chk = fwd_check(n, d_tile_ranges, d_cams, V, opts, total_tiles, total_pixels, d_target,
+                                       d_image, d_T_final, d_n_contrib, d_loss);
+  if (chk != STEEPGS_OK) return chk;
+  if (!d_ws || ws_bytes < render_fwd_workspace()) return STEEPGS_ERR_WORKSPACE;
+  return fwd_launch(d_splats, d_vals, d_tile_ranges, d_cams, V, *opts, total_tiles, d_target, d_image, d_T_final,
+                    d_n_contrib, d_n_used, d_loss, static_cast<uint32_t*>(d_ws), as_stream(stream));
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant.  Its scratch (the tile-queue counter) lives in a
+// file-scope device array; each device holds its own copy, whose address is
+// looked up once per device with that device current and kept on the host.
+// Host code never passes the array's name to a kernel: it names a host-side
+// stand-in, not device memory.
+
+namespace sg {
+constexpr size_t kNoAllocScratchBytes = 256;
+constexpr int kNoAllocMaxDevices = 64;
+static std::mutex g_noalloc_mu;
+static uint32_t* g_noalloc_ptr[kNoAllocMaxDevices];
+}  // namespace sg
+
+static __device__ __align__(256) uint32_t scratch[sg::kNoAllocScratchBytes / sizeof(uint32_t)];
+
+static steepgs_status noalloc_scratch(uint32_t** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return STEEPGS_ERR_HIP;
+  if (dev >= kNoAllocMaxDevices) return STEEPGS_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return STEEPGS_ERR_HIP;
+    g_noalloc_ptr[dev] = static_cast<uint32_t*>(p);
+  }
+  *out = g_noalloc_ptr[dev];
+  return STEEPGS_OK;
+}
+
+extern "C" steepgs_status steepgs_render_fwd_noalloc(const steepgs_splat* d_splats, int64_t n, const uint32_t* d_vals,
+                                                     const uint32_t* d_tile_ranges, const steepgs_camera* d_cams,
+                                                     int32_t V, const steepgs_opts* opts, int32_t total_tiles,
+                                                     int64_t total_pixels, const float* d_target, float* d_image,
+                                                     float* d_T_final, uint32_t* d_n_contrib, uint32_t* d_n_used,
+                                                     float* d_loss, void* stream) {
+  const steepgs_status chk = fwd_check(n, d_tile_ranges, d_cams, V, opts, total_tiles, total_pixels, d_target,
+                                       d_image, d_T_final, d_n_contrib, d_loss);
+  if (chk != STEEPGS_OK) return chk;
+  // the scratch a launch needs does not grow with the problem; a build whose
+  // forward needed more than the array holds fails here, not on the device
+  if (render_fwd_workspace() > kNoAllocScratchBytes) return STEEPGS_ERR_WORKSPACE;
+  uint32_t* queue = nullptr;
+  const steepgs_status st = noalloc_scratch(&queue);
+  if (st != STEEPGS_OK) return st;
+  return fwd_launch(d_splats, d_vals, d_tile_ranges, d_cams, V, *opts, total_tiles, d_target, d_image, d_T_final,
+                    d_n_contrib, d_n_used, d_loss, queue, as_stream(stream));
 }
