@@ -203,7 +203,8 @@ def main():
     step.ras.render(target, count_used=True)
     pairs = int(step.ras.n_contrib.to(torch.int64).sum())
     contrib = int(step.ras.n_used.to(torch.int64).sum())
-    visible = int((step.ras.tiles > 0).sum())
+    step.ras.sort(want_counts=True)
+    visible = int((step.ras.counts[: cams.V * scene.n] > 0).sum())
     say(f"warm: loss={loss:.5f} n_out={n_out} pairs={pairs} contributors={contrib} visible={visible}")
 
     use_graph = not args.no_graph

@@ -139,40 +139,40 @@ size_t steepgs_workspace_size(int32_t stage, int64_t n, int32_t V, uint64_t capa
 
 /* Stage 1 -- projection (Sec. 3, Eqs. sigma_3D / sigma_2D).
  * In:  d_params [F][n], d_cams [V] (device copy of laid-out cameras).
- * Out: d_splats [V*n], d_tiles_touched [V*n]: the tiles of the rectangle whose
- *      box of pixel centres meets the footprint ellipse d^T A d <=
- *      radius_sigmas^2 (tested in fp64 on the stored float32 mean and conic,
- *      1e-6 relative slack; the same test selects the instances in
- *      steepgs_sort), 0 if culled.  Discrete outcomes (culling, footprint,
- *      depth) are computed in fp64 in a fixed operation order.
+ * Out: d_splats [V*n], d_tiles_touched [V*n]: the number of tiles of the
+ *      record's tile rectangle (a bound of its instance count; the exact
+ *      count is an output of steepgs_sort), 0 if culled.  Discrete outcomes
+ *      (culling, rectangle, depth) are computed in fp64 in a fixed operation
+ *      order.
  *      d_depth_keys (nullable) [V*n]: the keys of steepgs_sort's depth order,
- *      the float bits of each record's depth, 0xFFFFFFFF for a culled one;
- *      written while the footprint count streams the records, so that the
- *      sort need not read them again (pass them to steepgs_sort). */
+ *      the float bits of each record's depth, 0xFFFFFFFF for a culled one
+ *      (pass them to steepgs_sort, which need not form them again). */
 steepgs_status steepgs_project(const float* d_params, int64_t n, int32_t sh_degree, const steepgs_camera* d_cams,
                                int32_t V, const steepgs_opts* opts, steepgs_splat* d_splats,
                                uint32_t* d_tiles_touched, uint32_t* d_depth_keys, void* stream);
 
 /* Stage 2 -- instance list (Sec. 3 "Rasterization": sort by view-dependent
- * depth).  One instance per (visible pair, tile of its footprint, the tiles
- * counted by steepgs_project); 64-bit key
- * global_tile << 32 | float bits of depth; value r = v*n + i; sorted by key,
- * ties by r (the order of emission view, Gaussian, row-major tile).
+ * depth).  One instance per (record, tile of its rectangle whose box of pixel
+ * centres meets the footprint ellipse d^T A d <= radius_sigmas^2; tested in
+ * fp64 on the stored float32 mean and conic, 1e-6 relative slack); 64-bit
+ * key global_tile << 32 | float bits of depth; value r = v*n + i; sorted by
+ * key, ties by r (the order of emission view, Gaussian, row-major tile).
  * Out: d_vals [capacity] sorted values; d_keys [capacity] (nullable) sorted
  *      keys; d_tile_ranges [total_tiles][2] = [begin, end) ((0,0) if empty);
+ *      d_counts [V*n] (nullable): each record's instance count (0 if culled);
  *      *d_num_instances = K.  If K > capacity, *d_status = STEEPGS_ERR_CAPACITY,
- *      *d_num_instances holds K and the outputs are not written.  *d_status is
- *      set to 0 otherwise.
+ *      *d_num_instances holds K and the outputs other than d_counts are not
+ *      written.  *d_status is set to 0 otherwise.
+ * d_tiles_touched [V*n]: as steepgs_project wrote it (0: culled).
  * d_depth_keys (nullable) [V*n]: the depth keys steepgs_project wrote for
- *      these same records and counts; when null they are formed here from
- *      d_splats and d_tiles_touched (same result, one more pass over the
- *      records). */
+ *      these same records; when null they are formed here from d_splats and
+ *      d_tiles_touched (same result, one more pass over the records). */
 steepgs_status steepgs_sort(const steepgs_splat* d_splats, const uint32_t* d_tiles_touched,
                             const uint32_t* d_depth_keys, int64_t n, int32_t V,
                             const steepgs_camera* d_cams, const steepgs_opts* opts, int32_t total_tiles,
                             uint64_t* d_keys, uint32_t* d_vals, uint64_t capacity, uint32_t* d_tile_ranges,
-                            uint64_t* d_num_instances, int32_t* d_status, void* d_ws, size_t ws_bytes,
-                            void* stream);
+                            uint32_t* d_counts, uint64_t* d_num_instances, int32_t* d_status, void* d_ws,
+                            size_t ws_bytes, void* stream);
 
 /* Stage 3 -- forward blend (Eq. alpha_blend), all V views in one persistent
  * launch.  Out: d_image packed per view as [3][H][W] planes (offset

@@ -70,7 +70,8 @@ def lib():
         L.steepgs_workspace_size.argtypes = [i32, i64, i32, u64, i32]
         L.steepgs_workspace_size.restype = sz
         L.steepgs_project.argtypes = [vp, i64, i32, vp, i32, C.POINTER(Opts), vp, vp, vp, vp]
-        L.steepgs_sort.argtypes = [vp, vp, vp, i64, i32, vp, C.POINTER(Opts), i32, vp, vp, u64, vp, vp, vp, vp, sz, vp]
+        L.steepgs_sort.argtypes = [vp, vp, vp, i64, i32, vp, C.POINTER(Opts), i32, vp, vp, u64, vp, vp, vp, vp, vp, sz,
+                                   vp]
         L.steepgs_render_fwd.argtypes = [vp, i64, vp, vp, vp, i32, C.POINTER(Opts), i32, i64, vp, vp, vp, vp, vp,
                                          vp, vp, sz, vp]
         L.steepgs_render_fwd_noalloc.argtypes = [vp, i64, vp, vp, vp, i32, C.POINTER(Opts), i32, i64, vp, vp, vp,
@@ -146,11 +147,11 @@ def steepgs_project(params, n, sh_degree, d_cams, V, opts, splats, tiles_touched
 
 
 def steepgs_sort(splats, tiles_touched, n, V, d_cams, opts, total_tiles, keys, vals, capacity, tile_ranges,
-                 num_instances, status, ws, stream=None, depth_keys=None):
+                 num_instances, status, ws, stream=None, depth_keys=None, counts=None):
     _check("steepgs_sort", lib().steepgs_sort(_p(splats), _p(tiles_touched), _p(depth_keys), n, V, _p(d_cams),
                                               C.byref(opts),
                                               total_tiles, _p(keys), _p(vals), capacity, _p(tile_ranges),
-                                              _p(num_instances), _p(status), _p(ws), ws.numel() * ws.element_size(),
+                                              _p(counts), _p(num_instances), _p(status), _p(ws), ws.numel() * ws.element_size(),
                                               _stream(stream)))
 
 

@@ -3,7 +3,6 @@
 // views, so the parameters are read from HBM once per batch, not once per
 // view.
 #include "projection.h"
-#include "rectwalk.h"
 
 namespace sg {
 
@@ -16,7 +15,7 @@ template <int D>
 __global__ void __launch_bounds__(kProjThreads) k_project(const float* __restrict__ params, int64_t n,
                                                           const steepgs_camera* __restrict__ cams, int V,
                                                           steepgs_opts opt, steepgs_splat* __restrict__ out,
-                                                          uint32_t* __restrict__ tiles) {
+                                                          uint32_t* __restrict__ tiles, uint32_t* __restrict__ dkeys) {
   constexpr int NS = 3 * (D + 1) * (D + 1);
   __shared__ float s_sh[NS * kProjThreads];  // [coefficient][thread]
   const int tid = threadIdx.x;
@@ -49,7 +48,7 @@ __global__ void __launch_bounds__(kProjThreads) k_project(const float* __restric
       s.depth = (float)pv.pc[2];
       s.rect_lo = (uint32_t)pv.rect[0] | ((uint32_t)pv.rect[1] << 16);
       s.rect_hi = (uint32_t)pv.rect[2] | ((uint32_t)pv.rect[3] << 16);
-      // the rectangle's area for now; k_count_tiles keeps the tiles that meet the footprint
+      // the rectangle's area: the sort's emission keeps the tiles that meet the footprint
       count = (uint32_t)((pv.rect[2] - pv.rect[0] + 1) * (pv.rect[3] - pv.rect[1] + 1));
     } else {
       s.mean_x = s.mean_y = 0.f;
@@ -67,40 +66,9 @@ __global__ void __launch_bounds__(kProjThreads) k_project(const float* __restric
     dst[1] = src[1];
     dst[2] = src[2];
     tiles[r] = count;
-  }
-}
-
-// Exact footprint tile count of every record: a tile counts when its box of
-// pixel centres meets the cut-off ellipse (tile_hit, the test the instance
-// emission applies).  Each wavefront takes 64 consecutive records and walks
-// their rectangles together (rect_walk), so large rectangles do not serialise
-// on one lane.  A record none of whose tiles meets the ellipse gets 0
-// (culled).  With dkeys, also the key the depth sort orders the records by:
-// the float bits of the depth (positive), all ones for a culled record.
-__global__ void __launch_bounds__(256) k_count_tiles(const steepgs_splat* __restrict__ splats,
-                                                     uint32_t* __restrict__ tiles, int64_t m, steepgs_opts opt,
-                                                     uint32_t* __restrict__ dkeys) {
-  __shared__ RectWalkLds s_walk[4];
-  __shared__ uint32_t s_cnt[256];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  uint32_t* const cnt = s_cnt + (tid - lane);
-  for (int64_t base = (int64_t)blockIdx.x * 256; base < m; base += (int64_t)gridDim.x * 256) {
-    const int64_t r = base + tid;
-    uint32_t area = 0;
-    RectRec me = {};
-    me.wdt = 1;
-    const bool live = r < m && tiles[r];
-    if (live) area = walk_rect(splats[r], opt, me);
-    s_cnt[tid] = 0u;
-    rect_walk(s_walk[wave], lane, area, me, opt, [&](int owner, const RectRec&, int, int, bool hit) {
-      if (hit) atomicAdd(&cnt[owner], 1u);
-    });
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (live) tiles[r] = s_cnt[tid];
-    if (dkeys && r < m) dkeys[r] = (live && s_cnt[tid]) ? __float_as_uint(splats[r].depth) : 0xFFFFFFFFu;
-    __builtin_amdgcn_wave_barrier();
+    // the key of the sort's depth order: the float bits of the (positive)
+    // depth, all ones for a culled record
+    if (dkeys) dkeys[r] = count ? __float_as_uint(s.depth) : 0xFFFFFFFFu;
   }
 }
 
@@ -120,14 +88,11 @@ extern "C" steepgs_status steepgs_project(const float* d_params, int64_t n, int3
   const dim3 pg((unsigned)ceil_div(n, kProjThreads)), pb(kProjThreads);
   hipStream_t st = as_stream(stream);
   switch (sh_degree) {
-    case 0: hipLaunchKernelGGL(k_project<0>, pg, pb, 0, st, d_params, n, d_cams, V, *opts, d_splats, d_tiles_touched); break;
-    case 1: hipLaunchKernelGGL(k_project<1>, pg, pb, 0, st, d_params, n, d_cams, V, *opts, d_splats, d_tiles_touched); break;
-    case 2: hipLaunchKernelGGL(k_project<2>, pg, pb, 0, st, d_params, n, d_cams, V, *opts, d_splats, d_tiles_touched); break;
-    default: hipLaunchKernelGGL(k_project<3>, pg, pb, 0, st, d_params, n, d_cams, V, *opts, d_splats, d_tiles_touched); break;
+    case 0: hipLaunchKernelGGL(k_project<0>, pg, pb, 0, st, d_params, n, d_cams, V, *opts, d_splats, d_tiles_touched, d_depth_keys); break;
+    case 1: hipLaunchKernelGGL(k_project<1>, pg, pb, 0, st, d_params, n, d_cams, V, *opts, d_splats, d_tiles_touched, d_depth_keys); break;
+    case 2: hipLaunchKernelGGL(k_project<2>, pg, pb, 0, st, d_params, n, d_cams, V, *opts, d_splats, d_tiles_touched, d_depth_keys); break;
+    default: hipLaunchKernelGGL(k_project<3>, pg, pb, 0, st, d_params, n, d_cams, V, *opts, d_splats, d_tiles_touched, d_depth_keys); break;
   }
-  const int64_t m = (int64_t)V * n;
-  hipLaunchKernelGGL(k_count_tiles, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, as_stream(stream), d_splats,
-                     d_tiles_touched, m, *opts, d_depth_keys);
   timer_end(STEEPGS_TIMER_PROJECT, as_stream(stream));
   SG_TRY_LAUNCH();
   return STEEPGS_OK;

@@ -76,11 +76,10 @@ struct RectWalkLds {
   int at[64];
 };
 
-// `visit(owner_lane, rec, tx, ty, hit)` is called once per chunk with every
-// lane active (hit false beyond the last position).  Returns the total area.
-template <class Visit>
-SG_DEV uint32_t rect_walk(RectWalkLds& L, int lane, uint32_t area, const RectRec& mine, const steepgs_opts& opt,
-                          Visit&& visit) {
+// Sets up a wavefront's walk: the records go to the wavefront's LDS slice,
+// each lane gets the start of its own run (aoff).  Returns the total area
+// (uniform over the wavefront).
+SG_DEV uint32_t rect_walk_begin(RectWalkLds& L, int lane, uint32_t area, const RectRec& mine, uint32_t& aoff) {
   uint32_t incl = area;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
@@ -88,50 +87,72 @@ SG_DEV uint32_t rect_walk(RectWalkLds& L, int lane, uint32_t area, const RectRec
     if (lane >= d) incl += t;
   }
   const uint32_t atotal = __shfl(incl, 63, 64);
-  const uint32_t aoff = incl - area;
+  aoff = incl - area;
   RectRec me = mine;
   me.aoff = aoff;
   me.ia = 1.f / me.a;
   me.ic = 1.f / me.c;
   me.iw = 1.f / (float)me.wdt;
   L.rec[lane] = me;
+  return atotal;
+}
+
+// Position j0 + lane of the walk (area, aoff: the lane's own record): returns
+// the owner lane, i.e. the lane whose record's run holds the position, and
+// its tile (tx, ty).  `carry` is the owner of the previous chunk's last
+// position (0 before the first chunk).  Every lane of the wavefront takes part.
+SG_DEV int rect_walk_locate(RectWalkLds& L, int lane, uint32_t area, uint32_t aoff, uint32_t j0, int& carry, int& tx,
+                            int& ty) {
+  // starts of the records inside this chunk
+  L.at[lane] = -1;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  if (area > 0 && aoff >= j0 && aoff - j0 < 64u) L.at[aoff - j0] = lane;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const uint64_t starts = ballot(L.at[lane] >= 0);
+  const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+  const uint64_t below = starts & upto;
+  const int owner = below ? L.at[63 - __builtin_clzll(below)] : carry;
+  carry = __builtin_amdgcn_readlane(owner, 63);
+  const RectRec& R = L.rec[owner];
+  const uint32_t q = j0 + (uint32_t)lane - R.aoff;
+  // q / width without an integer division: the float quotient is off by at
+  // most one for q < 2^24, fixed up exactly below (larger q: integer path)
+  int row, col;
+  if (q < (1u << 24)) {
+    row = (int)((float)q * R.iw);
+    col = (int)q - row * (int)R.wdt;
+    if (col < 0) {
+      --row;
+      col += (int)R.wdt;
+    } else if (col >= (int)R.wdt) {
+      ++row;
+      col -= (int)R.wdt;
+    }
+  } else {
+    row = (int)(q / R.wdt);
+    col = (int)(q % R.wdt);
+  }
+  tx = (int)(R.xy0 & 0xFFFFu) + col;
+  ty = (int)(R.xy0 >> 16) + row;
+  return owner;
+}
+
+// `visit(owner_lane, rec, tx, ty, hit)` is called once per chunk with every
+// lane active (hit false beyond the last position).  Returns the total area.
+template <class Visit>
+SG_DEV uint32_t rect_walk(RectWalkLds& L, int lane, uint32_t area, const RectRec& mine, const steepgs_opts& opt,
+                          Visit&& visit) {
+  uint32_t aoff;
+  const uint32_t atotal = rect_walk_begin(L, lane, area, mine, aoff);
   int carry = 0;
   for (uint32_t j0 = 0; j0 < atotal; j0 += 64) {
-    // starts of the records inside this chunk
-    L.at[lane] = -1;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    if (area > 0 && aoff >= j0 && aoff - j0 < 64u) L.at[aoff - j0] = lane;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const uint64_t starts = ballot(L.at[lane] >= 0);
-    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-    const uint64_t below = starts & upto;
-    const int owner = below ? L.at[63 - __builtin_clzll(below)] : carry;
-    carry = __builtin_amdgcn_readlane(owner, 63);
+    int tx, ty;
+    const int owner = rect_walk_locate(L, lane, area, aoff, j0, carry, tx, ty);
     const RectRec& R = L.rec[owner];
-    const uint32_t j = j0 + (uint32_t)lane;
-    const uint32_t q = j - R.aoff;
-    // q / width without an integer division: the float quotient is off by at
-    // most one for q < 2^24, fixed up exactly below (larger q: integer path)
-    int row, col;
-    if (q < (1u << 24)) {
-      row = (int)((float)q * R.iw);
-      col = (int)q - row * (int)R.wdt;
-      if (col < 0) {
-        --row;
-        col += (int)R.wdt;
-      } else if (col >= (int)R.wdt) {
-        ++row;
-        col -= (int)R.wdt;
-      }
-    } else {
-      row = (int)(q / R.wdt);
-      col = (int)(q % R.wdt);
-    }
-    const int tx = (int)(R.xy0 & 0xFFFFu) + col, ty = (int)(R.xy0 >> 16) + row;
-    const bool hit = j < atotal && tile_hit_rcp(R.mx, R.my, R.a, R.b, R.c, R.ia, R.ic, opt, tx, ty);
+    const bool hit = j0 + (uint32_t)lane < atotal && tile_hit_rcp(R.mx, R.my, R.a, R.b, R.c, R.ia, R.ic, opt, tx, ty);
     visit(owner, R, tx, ty, hit);
     __builtin_amdgcn_wave_barrier();
   }

@@ -99,8 +99,7 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const uint32_t* __res
                                                            uint32_t* __restrict__ vals_out,
                                                            const uint64_t* __restrict__ d_count,
                                                            const uint64_t* __restrict__ d_cap, int shift, int bits,
-                                                           const uint32_t* __restrict__ hist_scanned,
-                                                           const uint32_t* __restrict__ gather) {
+                                                           const uint32_t* __restrict__ hist_scanned) {
   constexpr int DIG = 1 << BITS;
   constexpr int PER = DIG / kRsThreads > 0 ? DIG / kRsThreads : 1;  // digits per thread in the tile scan
   __shared__ uint32_t s_key[kRsTile], s_val[kRsTile];
@@ -193,10 +192,8 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const uint32_t* __res
         const uint32_t key = s_key[i];
         const uint32_t d = (key >> shift) & mask;
         const uint32_t g = s_run[d] + ((uint32_t)i - s_start[d]);
-        const uint32_t val = s_val[i];
-        // a last pass may write gather[value] instead of the key
-        keys_out[g] = gather ? gather[val] : key;
-        vals_out[g] = val;
+        keys_out[g] = key;
+        vals_out[g] = s_val[i];
       }
     }
     __syncthreads();
@@ -213,7 +210,7 @@ struct LoadU32 {
 template <int BITS>
 static void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, const uint64_t* d_count,
                        const uint64_t* d_cap, int shift, int b, uint32_t* hist, uint32_t* hist_partials,
-                       const uint32_t* gather, hipStream_t st, hipError_t& err) {
+                       hipStream_t st, hipError_t& err) {
   // as many workgroups as are resident together (LDS and registers), capped
   // at kRsGrid, so that no second partial round follows the first
   static int per_cu = 0;  // same code object on every device
@@ -229,19 +226,18 @@ static void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
   err = exclusive_scan<LoadU32, uint32_t, uint32_t>(LoadU32{hist}, hn, hist, hist_partials, st);
   if (err != hipSuccess) return;
   hipLaunchKernelGGL(k_rs_scatter<BITS>, dim3(grid), dim3(kRsThreads), 0, st, kin, vin, kout, vout, d_count, d_cap,
-                     shift, b, hist, gather);
+                     shift, b, hist);
 }
 
 // sorts (keys, vals) of `count` (device) elements on bits [0, total_bits),
 // ping-ponging between buffer pair 0 = (k0, v0) and 1 = (k1, v1); the input is
-// in pair `start`; returns the pair holding the result.  With gather_last,
-// the last pass writes gather_last[value] in place of each sorted key.  With
+// in pair `start`; returns the pair holding the result.  With
 // first_keys, the first pass reads its keys there (not from pair `start`)
 // and takes the element indices as values.
 static int radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int start,
                             const uint64_t* d_count, const uint64_t* d_cap, int total_bits, uint32_t* hist,
                             uint32_t* hist_partials, hipStream_t st, hipError_t& err,
-                            const uint32_t* gather_last = nullptr, const uint32_t* first_keys = nullptr) {
+                            const uint32_t* first_keys = nullptr) {
   const int npass = (total_bits + kRsMaxBits - 1) / kRsMaxBits;
   const int bits = (total_bits + npass - 1) / npass;
   int cur = start;
@@ -257,11 +253,10 @@ static int radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* 
     }
     uint32_t* kout = cur ? k0 : k1;
     uint32_t* vout = cur ? v0 : v1;
-    const uint32_t* gather = p + 1 == npass ? gather_last : nullptr;
     if (b <= 8)
-      radix_pass<8>(kin, vin, kout, vout, d_count, d_cap, shift, b, hist, hist_partials, gather, st, err);
+      radix_pass<8>(kin, vin, kout, vout, d_count, d_cap, shift, b, hist, hist_partials, st, err);
     else
-      radix_pass<9>(kin, vin, kout, vout, d_count, d_cap, shift, b, hist, hist_partials, gather, st, err);
+      radix_pass<9>(kin, vin, kout, vout, d_count, d_cap, shift, b, hist, hist_partials, st, err);
     if (err != hipSuccess) return cur;
     cur ^= 1;
     shift += b;
@@ -288,55 +283,158 @@ __global__ void k_depth_keys(const steepgs_splat* __restrict__ splats, const uin
   }
 }
 
-__global__ void k_instance_total(const uint64_t* __restrict__ total, uint64_t capacity,
-                                 uint64_t* __restrict__ d_num, int32_t* __restrict__ d_status, uint64_t* cap_out) {
-  const uint64_t K = *total;
-  *d_num = K;
-  *d_status = (K > capacity) ? (int32_t)STEEPGS_ERR_CAPACITY : (int32_t)STEEPGS_OK;
-  *cap_out = capacity;
+// ---------------------------------------------------------------------------
+// Instance emission in depth order with a decoupled look-back for the output
+// offsets.  Each wavefront takes the next chunk of 64 consecutive records of
+// the depth order (a global counter hands out chunk ids in launch order), walks
+// their tile rectangles together (rect_walk_begin / rect_walk_locate), tests
+// every tile against the footprint ellipse and counts the hits.  It publishes
+// that count, looks back over the chunks before it for the sum of their
+// counts, publishes its own inclusive prefix, and then writes its instances
+// (global tile id, record id) from that offset, replaying the walk with the
+// hit ballots kept in LDS (positions beyond the LDS ring are tested again).
+// A chunk waits only on chunks handed out before it, whose wavefronts are
+// already running, so the wait ends.  Status word per chunk: bits 62-63 flag
+// (0 empty, 1 aggregate, 2 inclusive prefix), bits 0-61 the count.
+
+constexpr int kEmitRing = 32;  // hit ballots kept per wavefront: 2048 rectangle positions
+constexpr uint64_t kLbAgg = 1ull << 62, kLbPre = 2ull << 62, kLbVal = kLbAgg - 1ull;
+
+SG_DEV uint64_t lb_load(const uint64_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+SG_DEV void lb_store(uint64_t* p, uint64_t v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
+SG_DEV uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const uint32_t lo = __shfl_xor((uint32_t)v, off, 64), hi = __shfl_xor((uint32_t)(v >> 32), off, 64);
+    v += ((uint64_t)hi << 32) | (uint64_t)lo;
+  }
+  return v;
 }
 
-// Each wavefront takes 64 consecutive records of the depth order; their
-// instances are contiguous in the output, so the lanes walk the group's tile
-// rectangles together (rect_walk), keep the tiles that meet the footprint
-// ellipse and append them in order with ballots.  Stores are coalesced.
+// exclusive prefix of chunk c's count `total` over chunks 0 .. c-1 (uniform)
+SG_DEV uint64_t lookback(uint64_t* status, uint32_t c, uint64_t total, int lane) {
+  if (c == 0) {
+    if (lane == 0) lb_store(status, kLbPre | total);
+    return 0;
+  }
+  if (lane == 0) lb_store(status + c, kLbAgg | total);
+  uint64_t excl = 0;
+  int64_t j = (int64_t)c - 1;
+  for (;;) {
+    const int64_t idx = j - lane;
+    // before chunk 0: an inclusive prefix of zero (the load stays in bounds)
+    const uint64_t got = lb_load(status + (idx >= 0 ? idx : 0));
+    const uint64_t w = idx >= 0 ? got : kLbPre;
+    const uint32_t flag = (uint32_t)(w >> 62);
+    const uint64_t pre = ballot(flag == 2u);
+    const int lim = pre ? __builtin_ctzll(pre) : 63;
+    const uint64_t need = lim == 63 ? ~0ull : ((2ull << lim) - 1ull);
+    if (ballot(flag == 0u) & need) {  // a chunk in the window has not published yet
+      __builtin_amdgcn_s_sleep(2);
+      continue;
+    }
+    excl += wave_sum_u64(lane <= lim ? (w & kLbVal) : 0ull);
+    if (pre) break;
+    j -= 64;
+  }
+  if (lane == 0) lb_store(status + c, kLbPre | (excl + total));
+  return excl;
+}
+
 __global__ void __launch_bounds__(256) k_emit(const steepgs_splat* __restrict__ splats,
-                                              const uint32_t* __restrict__ counts, const uint32_t* __restrict__ order,
-                                              const uint64_t* __restrict__ offs, int64_t m, int64_t n,
-                                              const steepgs_camera* __restrict__ cams, steepgs_opts opt,
-                                              const uint64_t* __restrict__ d_num, uint64_t capacity,
-                                              uint32_t* __restrict__ tkeys, uint32_t* __restrict__ ivals) {
+                                              const uint32_t* __restrict__ skeys, const uint32_t* __restrict__ order,
+                                              int64_t m, int64_t n, const steepgs_camera* __restrict__ cams,
+                                              steepgs_opts opt, uint64_t capacity, uint64_t* __restrict__ lb,
+                                              uint32_t* __restrict__ tkeys, uint32_t* __restrict__ ivals,
+                                              uint32_t* __restrict__ counts, uint64_t* __restrict__ d_num,
+                                              int32_t* __restrict__ d_status) {
   __shared__ RectWalkLds s_walk[4];
-  if (*d_num > capacity) return;
+  __shared__ uint64_t s_hit[4][kEmitRing];
+  __shared__ uint32_t s_cnt[256];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  RectWalkLds& L = s_walk[wave];
+  uint64_t* const ring = s_hit[wave];
+  uint32_t* const cnt = s_cnt + wave * 64;
   const uint64_t lt = lanemask_lt();
-  for (int64_t s0 = (int64_t)blockIdx.x * 256 + wave * 64; s0 < m; s0 += (int64_t)gridDim.x * 256) {
-    // s0: first record of this wavefront's group (wave-uniform)
-    const int64_t s = s0 + lane;
-    uint32_t area = 0;
+  // lb[0]: chunk counter; lb[1 ..]: chunk status words
+  uint32_t* const chunk_ctr = reinterpret_cast<uint32_t*>(lb);
+  uint64_t* const status = lb + 1;
+  const uint32_t nchunks = (uint32_t)((m + 63) / 64);
+  for (;;) {
+    __builtin_amdgcn_wave_barrier();
+    uint32_t c = 0;
+    if (lane == 0) c = atomicAdd(chunk_ctr, 1u);
+    c = (uint32_t)__builtin_amdgcn_readfirstlane((int)c);
+    if (c >= nchunks) break;
+    const int64_t s = (int64_t)c * 64 + lane;
+    uint32_t area = 0, r = 0xFFFFFFFFu;
     RectRec me = {};
     me.wdt = 1;
-    // counts: tile counts already gathered into depth order (contiguous)
-    if (s < m && counts[s]) {
-      const uint32_t r = order[s];
-      area = walk_rect(splats[r], opt, me);
-      const int v = (int)(r / (uint64_t)n);
-      me.tag0 = r;
-      me.tag1 = (uint32_t)cams[v].tile_offset;
-      me.pad0 = (uint32_t)cams[v].tiles_x;
-    }
-    // the group's instances are contiguous from the first record's offset
-    uint64_t cursor = offs[s0];
-    rect_walk(s_walk[wave], lane, area, me, opt, [&](int, const RectRec& R, int tx, int ty, bool hit) {
-      const uint64_t hits = ballot(hit);
-      if (hit) {
-        const uint64_t o = cursor + (uint64_t)__popcll(hits & lt);
-        tkeys[o] = R.tag1 + (uint32_t)ty * R.pad0 + (uint32_t)tx;
-        ivals[o] = R.tag0;
+    me.a = me.c = 1.f;
+    if (s < m) {
+      if (skeys[s] != 0xFFFFFFFFu) {  // culled records sort last
+        r = order[s];
+        area = walk_rect(splats[r], opt, me);
+        const int v = (int)(r / (uint64_t)n);
+        me.tag0 = r;
+        me.tag1 = (uint32_t)cams[v].tile_offset;
+        me.pad0 = (uint32_t)cams[v].tiles_x;
+      } else if (counts) {
+        r = order[s];
       }
-      cursor += (uint64_t)__popcll(hits);
-    });
+    }
+    cnt[lane] = 0u;
+    uint32_t aoff;
+    const uint32_t atotal = rect_walk_begin(L, lane, area, me, aoff);
+    // walk 1: test the tiles, count the hits, keep the ballots
+    uint64_t hits = 0;
+    int carry = 0;
+    uint32_t k = 0;
+    for (uint32_t j0 = 0; j0 < atotal; j0 += 64, ++k) {
+      int tx, ty;
+      const int owner = rect_walk_locate(L, lane, area, aoff, j0, carry, tx, ty);
+      const RectRec& R = L.rec[owner];
+      const bool hit = j0 + (uint32_t)lane < atotal && tile_hit_rcp(R.mx, R.my, R.a, R.b, R.c, R.ia, R.ic, opt, tx, ty);
+      const uint64_t b = ballot(hit);
+      if (k < (uint32_t)kEmitRing && lane == 0) ring[k] = b;
+      hits += (uint64_t)__popcll(b);
+      if (counts && hit) atomicAdd(&cnt[owner], 1u);
+      __builtin_amdgcn_wave_barrier();
+    }
+    const uint64_t excl = lookback(status, c, hits, lane);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (counts && r != 0xFFFFFFFFu) counts[r] = cnt[lane];
+    // walk 2: write the instances from the chunk's offset
+    uint64_t cursor = excl;
+    carry = 0;
+    k = 0;
+    for (uint32_t j0 = 0; j0 < atotal; j0 += 64, ++k) {
+      int tx, ty;
+      const int owner = rect_walk_locate(L, lane, area, aoff, j0, carry, tx, ty);
+      const RectRec& R = L.rec[owner];
+      uint64_t b;
+      if (k < (uint32_t)kEmitRing) {
+        b = ring[k];
+      } else {
+        b = ballot(j0 + (uint32_t)lane < atotal && tile_hit_rcp(R.mx, R.my, R.a, R.b, R.c, R.ia, R.ic, opt, tx, ty));
+      }
+      if ((b >> lane) & 1ull) {
+        const uint64_t o = cursor + (uint64_t)__popcll(b & lt);
+        if (o < capacity) {
+          tkeys[o] = R.tag1 + (uint32_t)ty * R.pad0 + (uint32_t)tx;
+          ivals[o] = R.tag0;
+        }
+      }
+      cursor += (uint64_t)__popcll(b);
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (c == nchunks - 1 && lane == 0) {
+      *d_num = cursor;
+      *d_status = cursor > capacity ? (int32_t)STEEPGS_ERR_CAPACITY : (int32_t)STEEPGS_OK;
+    }
   }
 }
 
@@ -387,8 +485,7 @@ __global__ void k_keys64(const uint32_t* __restrict__ tkeys, const uint32_t* __r
 
 struct SortWs {
   uint32_t *dkA, *dvA, *dkB, *dvB;
-  uint64_t* offs;
-  uint64_t* partials64;
+  uint64_t* lb;  // emission chunk counter and look-back status words
   uint32_t *tkA, *tkB, *ivB;
   uint32_t* hist;
   uint32_t* hist_partials;
@@ -401,8 +498,7 @@ static size_t sort_layout(void* base, int64_t m, uint64_t cap, SortWs& w) {
   w.dvA = c.take<uint32_t>(m);
   w.dkB = c.take<uint32_t>(m);
   w.dvB = c.take<uint32_t>(m);
-  w.offs = c.take<uint64_t>(m);
-  w.partials64 = c.take<uint64_t>(scan_partials_count(m) + 1);
+  w.lb = c.take<uint64_t>(1 + (size_t)ceil_div(m, 64));
   w.tkA = c.take<uint32_t>(cap);
   w.tkB = c.take<uint32_t>(cap);
   w.ivB = c.take<uint32_t>(cap);
@@ -425,8 +521,8 @@ extern "C" steepgs_status steepgs_sort(const steepgs_splat* d_splats, const uint
                                        const uint32_t* d_depth_keys, int64_t n,
                                        int32_t V, const steepgs_camera* d_cams, const steepgs_opts* opts,
                                        int32_t total_tiles, uint64_t* d_keys, uint32_t* d_vals, uint64_t capacity,
-                                       uint32_t* d_tile_ranges, uint64_t* d_num_instances, int32_t* d_status,
-                                       void* d_ws, size_t ws_bytes, void* stream) {
+                                       uint32_t* d_tile_ranges, uint32_t* d_counts, uint64_t* d_num_instances,
+                                       int32_t* d_status, void* d_ws, size_t ws_bytes, void* stream) {
   if (n < 0 || V <= 0 || total_tiles <= 0 || !opts) return STEEPGS_ERR_INVALID_ARG;
   if (!d_tile_ranges || !d_num_instances || !d_status || !d_cams) return STEEPGS_ERR_INVALID_ARG;
   if (capacity > 0xFFFFFFFFull) return STEEPGS_ERR_INVALID_ARG;
@@ -454,29 +550,28 @@ extern "C" steepgs_status steepgs_sort(const steepgs_splat* d_splats, const uint
     hipLaunchKernelGGL(k_depth_keys, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, d_splats, d_tiles_touched,
                        m, w.dkA, w.dvA);
   hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, w.counters, (uint64_t)m);
-  // (its last pass writes each record's tile count in place of the sorted
-  // depth key, so the counts come out in depth order, read contiguously below)
-  int where = radix_sort_pairs(w.dkA, w.dvA, w.dkB, w.dvB, 0, w.counters, nullptr, 32, w.hist, w.hist_partials, st,
-                               err, d_tiles_touched, d_depth_keys);
+  hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, w.counters + 1, (uint64_t)capacity);
+  const int where = radix_sort_pairs(w.dkA, w.dvA, w.dkB, w.dvB, 0, w.counters, nullptr, 32, w.hist, w.hist_partials,
+                                     st, err, d_depth_keys);
   if (err != hipSuccess) return STEEPGS_ERR_HIP;
   const uint32_t* order = where ? w.dvB : w.dvA;
-  uint32_t* counts = where ? w.dkB : w.dkA;
-  // 2. instance offsets in depth order; K and the capacity check
-  err = exclusive_scan<LoadU32, uint64_t, uint64_t>(LoadU32{counts}, m, w.offs, w.partials64, st);
-  if (err != hipSuccess) return STEEPGS_ERR_HIP;
-  uint64_t* total = w.partials64 + scan_partials_count(m);
-  hipLaunchKernelGGL(k_instance_total, dim3(1), dim3(1), 0, st, total, capacity, d_num_instances, d_status,
-                     w.counters + 1);
-  // 3. emit instances (tile id, record) in depth order, then stable sort by tile
+  const uint32_t* skeys = where ? w.dkB : w.dkA;
+  // 2. emit instances (tile id, record) in depth order, with their offsets
+  // from the look-back; K, the capacity check and the optional exact counts
   int tile_bits = 1;
   while (tile_bits < 32 && ((uint64_t)1 << tile_bits) < (uint64_t)total_tiles) ++tile_bits;
   const int npass = (tile_bits + kRsMaxBits - 1) / kRsMaxBits;
   const int start = npass & 1;
   uint32_t* ek = start ? w.tkB : w.tkA;
   uint32_t* ev = start ? w.ivB : d_vals;
+  const int64_t nchunks = ceil_div(m, 64);
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)ceil_div(2 * (1 + nchunks), 256)), dim3(256), 0, st,
+                     reinterpret_cast<uint32_t*>(w.lb), 0u, 2 * (1 + nchunks));
+  const int egrid = (int)std::min<int64_t>(ceil_div(nchunks, 4), (int64_t)device_cu_count() * 8);
+  hipLaunchKernelGGL(k_emit, dim3(egrid), dim3(256), 0, st, d_splats, skeys, order, m, n, d_cams, *opts, capacity,
+                     w.lb, ek, ev, d_counts, d_num_instances, d_status);
   if (capacity > 0) {
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, d_splats, counts, order,
-                       w.offs, m, n, d_cams, *opts, d_num_instances, capacity, ek, ev);
+    // 3. stable sort by tile (equal tiles keep the depth order)
     int fin = radix_sort_pairs(w.tkA, d_vals, w.tkB, w.ivB, start, d_num_instances, w.counters + 1, tile_bits, w.hist,
                                w.hist_partials, st, err);
     if (err != hipSuccess) return STEEPGS_ERR_HIP;

@@ -80,7 +80,7 @@ class Rasterizer:
         self.dev = cams.dev.device
         self.capacity = int(capacity)
         self.n = -1
-        self.splats = self.tiles = self.vals = self.keys = None
+        self.splats = self.tiles = self.vals = self.keys = self.counts = None
         self.ranges = torch.empty(2 * cams.total_tiles, dtype=torch.int32, device=self.dev)
         self.num = torch.zeros(1, dtype=torch.int64, device=self.dev)
         self.status = torch.zeros(1, dtype=torch.int32, device=self.dev)
@@ -120,10 +120,15 @@ class Rasterizer:
         L.steepgs_project(params, n, self.sh_degree, self.cams.dev, self.cams.V, self.cams.opts, self.splats,
                           self.tiles, depth_keys=self.dkeys)
 
-    def sort(self, want_keys: bool = False) -> int:
+    def sort(self, want_keys: bool = False, want_counts: bool = False) -> int:
         """Instance list; grows the capacity and retries on overflow (reads
-        the instance count back to the host)."""
+        the instance count back to the host).  want_counts: each record's
+        exact instance count into ``self.counts``."""
         n, V = self.n, self.cams.V
+        counts = None
+        if want_counts:
+            self.counts = _grow(self.counts, max(V * n, 1), torch.int32, self.dev)
+            counts = self.counts
         for _ in range(3):
             keys = None
             if want_keys:
@@ -131,7 +136,7 @@ class Rasterizer:
                 keys = self.keys
             L.steepgs_sort(self.splats, self.tiles, n, V, self.cams.dev, self.cams.opts, self.cams.total_tiles, keys,
                            self.vals, self.capacity, self.ranges, self.num, self.status, self.ws_sort,
-                           depth_keys=self.dkeys)
+                           depth_keys=self.dkeys, counts=counts)
             K = int(self.num.item())
             if int(self.status.item()) == L.OK:
                 return K
@@ -147,9 +152,9 @@ class Rasterizer:
                              self.loss if target is not None else None, self.ws_fwd)
 
     def forward(self, params: torch.Tensor, target: torch.Tensor | None = None, want_keys=False,
-                count_used=False) -> ForwardState:
+                count_used=False, want_counts=False) -> ForwardState:
         self.project(params)
-        K = self.sort(want_keys)
+        K = self.sort(want_keys, want_counts)
         self.render(target, count_used)
         return ForwardState(K, self.image, self.T_final, self.n_contrib, self.loss if target is not None else None)
 

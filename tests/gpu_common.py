@@ -17,10 +17,11 @@ def run_gpu(params, sh_degree, cams, opts, target=None, backward=True, want_keys
     ras = pipeline.Rasterizer(cb, sh_degree, capacity=1024)
     P = torch.from_numpy(np.ascontiguousarray(params)).to(dev)
     tg = None if target is None else torch.from_numpy(np.ascontiguousarray(target)).to(dev)
-    fs = ras.forward(P, tg, want_keys=want_keys, count_used=True)
+    fs = ras.forward(P, tg, want_keys=want_keys, count_used=True, want_counts=True)
     out = dict(K=fs.K, image=fs.image.cpu().numpy().astype(np.float64), T_final=fs.T_final.cpu().numpy(),
                n_contrib=fs.n_contrib.cpu().numpy(), n_used=ras.n_used.cpu().numpy(), splats=ras.splats.cpu().numpy(),
-               tiles=ras.tiles.cpu().numpy().view(np.uint32), vals=ras.vals[: fs.K].cpu().numpy().view(np.uint32),
+               tiles=ras.counts[: cams.V * P.shape[1]].cpu().numpy().view(np.uint32),
+               rect_tiles=ras.tiles.cpu().numpy().view(np.uint32), vals=ras.vals[: fs.K].cpu().numpy().view(np.uint32),
                ranges=ras.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2))
     if want_keys:
         out["keys"] = ras.keys[: fs.K].cpu().numpy().view(np.uint64)

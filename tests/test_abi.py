@@ -59,8 +59,8 @@ def test_bad_arguments_rejected_on_host():
     assert lib.steepgs_project(None, 10, 0, None, 1, C.byref(o), None, None, None, None) == L.ERR_INVALID_ARG
     bad = L.make_opts(scenes.opts("3dgs", tile_w=12))
     assert lib.steepgs_project(None, 10, 0, None, 1, C.byref(bad), None, None, None, None) == L.ERR_INVALID_ARG
-    assert lib.steepgs_sort(None, None, None, 10, 1, None, C.byref(o), 0, None, None, 0, None, None, None, None, 0,
-                            None) == L.ERR_INVALID_ARG
+    assert lib.steepgs_sort(None, None, None, 10, 1, None, C.byref(o), 0, None, None, 0, None, None, None, None,
+                            None, 0, None) == L.ERR_INVALID_ARG
     fake = C.c_void_p(0x1000)
     assert lib.steepgs_render_fwd(fake, 10, fake, fake, fake, 1, C.byref(o), 4, 64, None, fake, fake, fake, None,
                                   None, None, 0, None) == L.ERR_WORKSPACE

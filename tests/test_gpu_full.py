@@ -153,7 +153,8 @@ def test_batched_16_full(oracle):
     K = int(r.num.item())
     vals = r.vals[:K].cpu().numpy().view(np.uint32)
     ranges = r.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2)
-    tiles = r.tiles.cpu().numpy().view(np.uint32)
+    assert r.sort(want_counts=True) == K  # the exact per-record instance counts
+    tiles = r.counts[: scene.cams.V * scene.n].cpu().numpy().view(np.uint32)
     sp = r.splats.cpu().numpy()
     # invariants over the whole list: ranges partition [0, K); every record
     # appears once per covered tile; inside a tile depth is non-decreasing and

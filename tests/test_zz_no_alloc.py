@@ -1,7 +1,8 @@
 """The allocation-free forward entry point (scratch in the library's own
 device array) against steepgs_render_fwd (scratch in the caller's
 workspace), through the C ABI: two calls in a row, the second on a smaller
-problem, each bit-identical to the workspace form on the same inputs."""
+problem; image, transmittance and counts bit-identical to the workspace form
+on the same inputs, the loss equal up to the order of its float sums."""
 import numpy as np
 import pytest
 import torch
@@ -47,7 +48,12 @@ def test_noalloc_forward_matches_workspace_forward():
             a = ref[name].cpu().numpy()
             b = got[name].cpu().numpy()
             assert a.shape == b.shape, name
-            np.testing.assert_array_equal(a.view(np.uint32), b.view(np.uint32), err_msg=name)
+            if name == "loss":
+                # per-view sums of per-tile float32 partials added atomically
+                # in the order the tiles finish: equal up to that order
+                np.testing.assert_allclose(b, a, rtol=1e-6, atol=0)
+            else:
+                np.testing.assert_array_equal(a.view(np.uint32), b.view(np.uint32), err_msg=name)
         sizes.append(ref["T_final"].numel())
     assert sizes[1] < sizes[0]
 
