@@ -284,111 +284,61 @@ __global__ void k_depth_keys(const steepgs_splat* __restrict__ splats, const uin
 }
 
 // ---------------------------------------------------------------------------
-// Instance emission in depth order with a decoupled look-back for the output
-// offsets.  Each wavefront takes the next chunk of 64 consecutive records of
-// the depth order (a global counter hands out chunk ids in launch order), walks
-// their tile rectangles together (rect_walk_begin / rect_walk_locate), tests
-// every tile against the footprint ellipse and counts the hits.  It publishes
-// that count, looks back over the chunks before it for the sum of their
-// counts, publishes its own inclusive prefix, and then writes its instances
-// (global tile id, record id) from that offset, replaying the walk with the
-// hit ballots kept in LDS (positions beyond the LDS ring are tested again).
-// A chunk waits only on chunks handed out before it, whose wavefronts are
-// already running, so the wait ends.  Status word per chunk: bits 62-63 flag
-// (0 empty, 1 aggregate, 2 inclusive prefix), bits 0-61 the count.
+// Instance emission in depth order, walking every tile rectangle once.
+//
+// k_walk: each wavefront takes a chunk of 64 consecutive records of the depth
+// order, walks their tile rectangles together (rect_walk_begin /
+// rect_walk_locate), tests every tile against the footprint ellipse and
+// keeps the hit ballots of the first kWalkKeep walk steps in global memory,
+// with each record's walk rectangle (contiguous, in depth order) and the
+// chunk's hit count.  An exclusive scan of the chunk counts gives each
+// chunk's output offset.  k_emit replays the walk from the kept ballots and
+// rectangles -- no gather of the projected records, no second ellipse test
+// (steps beyond the kept ones are tested again) -- and writes the instances
+// (global tile id, record id) from the chunk's offset.
 
-constexpr int kEmitRing = 32;  // hit ballots kept per wavefront: 2048 rectangle positions
-constexpr uint64_t kLbAgg = 1ull << 62, kLbPre = 2ull << 62, kLbVal = kLbAgg - 1ull;
+constexpr int kWalkKeep = 16;  // ballots kept per chunk: 1024 rectangle positions
 
-SG_DEV uint64_t lb_load(const uint64_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
-SG_DEV void lb_store(uint64_t* p, uint64_t v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+struct WalkRect {
+  uint32_t xy0;  // x0 | y0 << 16
+  uint32_t wh;   // width | height << 16 (0: nothing to walk)
+};
 
-SG_DEV uint64_t wave_sum_u64(uint64_t v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const uint32_t lo = __shfl_xor((uint32_t)v, off, 64), hi = __shfl_xor((uint32_t)(v >> 32), off, 64);
-    v += ((uint64_t)hi << 32) | (uint64_t)lo;
-  }
-  return v;
+SG_DEV void walk_record(const steepgs_splat* __restrict__ splats, const steepgs_camera* __restrict__ cams,
+                        int64_t n, uint32_t r, const steepgs_opts& opt, RectRec& me, uint32_t& area) {
+  area = walk_rect(splats[r], opt, me);
+  const int v = (int)(r / (uint64_t)n);
+  me.tag0 = r;
+  me.tag1 = (uint32_t)cams[v].tile_offset;
+  me.pad0 = (uint32_t)cams[v].tiles_x;
 }
 
-// exclusive prefix of chunk c's count `total` over chunks 0 .. c-1 (uniform)
-SG_DEV uint64_t lookback(uint64_t* status, uint32_t c, uint64_t total, int lane) {
-  if (c == 0) {
-    if (lane == 0) lb_store(status, kLbPre | total);
-    return 0;
-  }
-  if (lane == 0) lb_store(status + c, kLbAgg | total);
-  uint64_t excl = 0;
-  int64_t j = (int64_t)c - 1;
-  for (;;) {
-    const int64_t idx = j - lane;
-    // before chunk 0: an inclusive prefix of zero (the load stays in bounds)
-    const uint64_t got = lb_load(status + (idx >= 0 ? idx : 0));
-    const uint64_t w = idx >= 0 ? got : kLbPre;
-    const uint32_t flag = (uint32_t)(w >> 62);
-    const uint64_t pre = ballot(flag == 2u);
-    const int lim = pre ? __builtin_ctzll(pre) : 63;
-    const uint64_t need = lim == 63 ? ~0ull : ((2ull << lim) - 1ull);
-    if (ballot(flag == 0u) & need) {  // a chunk in the window has not published yet
-      __builtin_amdgcn_s_sleep(2);
-      continue;
-    }
-    excl += wave_sum_u64(lane <= lim ? (w & kLbVal) : 0ull);
-    if (pre) break;
-    j -= 64;
-  }
-  if (lane == 0) lb_store(status + c, kLbPre | (excl + total));
-  return excl;
-}
-
-__global__ void __launch_bounds__(256) k_emit(const steepgs_splat* __restrict__ splats,
+__global__ void __launch_bounds__(256) k_walk(const steepgs_splat* __restrict__ splats,
                                               const uint32_t* __restrict__ skeys, const uint32_t* __restrict__ order,
                                               int64_t m, int64_t n, const steepgs_camera* __restrict__ cams,
-                                              steepgs_opts opt, uint64_t capacity, uint64_t* __restrict__ lb,
-                                              uint32_t* __restrict__ tkeys, uint32_t* __restrict__ ivals,
-                                              uint32_t* __restrict__ counts, uint64_t* __restrict__ d_num,
-                                              int32_t* __restrict__ d_status) {
+                                              steepgs_opts opt, WalkRect* __restrict__ rects,
+                                              uint64_t* __restrict__ kept, uint32_t* __restrict__ chunk_hits,
+                                              uint32_t* __restrict__ counts) {
   __shared__ RectWalkLds s_walk[4];
-  __shared__ uint64_t s_hit[4][kEmitRing];
   __shared__ uint32_t s_cnt[256];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   RectWalkLds& L = s_walk[wave];
-  uint64_t* const ring = s_hit[wave];
   uint32_t* const cnt = s_cnt + wave * 64;
-  const uint64_t lt = lanemask_lt();
-  // lb[0]: chunk counter; lb[1 ..]: chunk status words
-  uint32_t* const chunk_ctr = reinterpret_cast<uint32_t*>(lb);
-  uint64_t* const status = lb + 1;
-  const uint32_t nchunks = (uint32_t)((m + 63) / 64);
-  for (;;) {
-    __builtin_amdgcn_wave_barrier();
-    uint32_t c = 0;
-    if (lane == 0) c = atomicAdd(chunk_ctr, 1u);
-    c = (uint32_t)__builtin_amdgcn_readfirstlane((int)c);
-    if (c >= nchunks) break;
-    const int64_t s = (int64_t)c * 64 + lane;
+  const int64_t nchunks = (m + 63) / 64;
+  for (int64_t c = (int64_t)blockIdx.x * 4 + wave; c < nchunks; c += (int64_t)gridDim.x * 4) {
+    const int64_t s = c * 64 + lane;
     uint32_t area = 0, r = 0xFFFFFFFFu;
     RectRec me = {};
     me.wdt = 1;
     me.a = me.c = 1.f;
-    if (s < m) {
-      if (skeys[s] != 0xFFFFFFFFu) {  // culled records sort last
-        r = order[s];
-        area = walk_rect(splats[r], opt, me);
-        const int v = (int)(r / (uint64_t)n);
-        me.tag0 = r;
-        me.tag1 = (uint32_t)cams[v].tile_offset;
-        me.pad0 = (uint32_t)cams[v].tiles_x;
-      } else if (counts) {
-        r = order[s];
-      }
-    }
+    if (s < m && (skeys[s] != 0xFFFFFFFFu || counts)) r = order[s];
+    if (s < m && skeys[s] != 0xFFFFFFFFu) walk_record(splats, cams, n, r, opt, me, area);  // culled records sort last
+    if (s < m) rects[s] = WalkRect{me.xy0, area ? (me.wdt | ((area / me.wdt) << 16)) : 0u};
     cnt[lane] = 0u;
     uint32_t aoff;
     const uint32_t atotal = rect_walk_begin(L, lane, area, me, aoff);
-    // walk 1: test the tiles, count the hits, keep the ballots
-    uint64_t hits = 0;
+    uint32_t hits = 0;
+    uint64_t mine = 0;  // lane k keeps the ballot of step k
     int carry = 0;
     uint32_t k = 0;
     for (uint32_t j0 = 0; j0 < atotal; j0 += 64, ++k) {
@@ -397,45 +347,96 @@ __global__ void __launch_bounds__(256) k_emit(const steepgs_splat* __restrict__ 
       const RectRec& R = L.rec[owner];
       const bool hit = j0 + (uint32_t)lane < atotal && tile_hit_rcp(R.mx, R.my, R.a, R.b, R.c, R.ia, R.ic, opt, tx, ty);
       const uint64_t b = ballot(hit);
-      if (k < (uint32_t)kEmitRing && lane == 0) ring[k] = b;
-      hits += (uint64_t)__popcll(b);
+      if ((uint32_t)lane == k) mine = b;
+      hits += (uint32_t)__popcll(b);
       if (counts && hit) atomicAdd(&cnt[owner], 1u);
       __builtin_amdgcn_wave_barrier();
     }
-    const uint64_t excl = lookback(status, c, hits, lane);
+    if ((uint32_t)lane < k && lane < kWalkKeep) kept[c * kWalkKeep + lane] = mine;
+    if (lane == 0) chunk_hits[c] = hits;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (counts && r != 0xFFFFFFFFu) counts[r] = cnt[lane];
-    // walk 2: write the instances from the chunk's offset
-    uint64_t cursor = excl;
-    carry = 0;
-    k = 0;
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+__global__ void __launch_bounds__(256) k_emit(const steepgs_splat* __restrict__ splats,
+                                              const uint32_t* __restrict__ order, const WalkRect* __restrict__ rects,
+                                              const uint64_t* __restrict__ kept,
+                                              const uint64_t* __restrict__ chunk_off, int64_t m, int64_t n,
+                                              const steepgs_camera* __restrict__ cams, steepgs_opts opt,
+                                              const uint64_t* __restrict__ d_num, uint64_t capacity,
+                                              uint32_t* __restrict__ tkeys, uint32_t* __restrict__ ivals) {
+  __shared__ RectWalkLds s_walk[4];
+  if (*d_num > capacity) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  RectWalkLds& L = s_walk[wave];
+  const uint64_t lt = lanemask_lt();
+  const int64_t nchunks = (m + 63) / 64;
+  for (int64_t c = (int64_t)blockIdx.x * 4 + wave; c < nchunks; c += (int64_t)gridDim.x * 4) {
+    const int64_t s = c * 64 + lane;
+    const WalkRect wr = s < m ? rects[s] : WalkRect{0u, 0u};
+    uint32_t area = (wr.wh & 0xFFFFu) * (wr.wh >> 16);
+    const uint32_t r = area ? order[s] : 0u;
+    RectRec me = {};
+    me.a = me.c = 1.f;
+    me.xy0 = wr.xy0;
+    me.wdt = area ? (wr.wh & 0xFFFFu) : 1u;
+    if (area) {
+      const int v = (int)(r / (uint64_t)n);
+      me.tag0 = r;
+      me.tag1 = (uint32_t)cams[v].tile_offset;
+      me.pad0 = (uint32_t)cams[v].tiles_x;
+    }
+    // total area beyond the kept ballots: those steps test their tiles again,
+    // which needs the records' conics
+    uint32_t incl = area;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t t = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += t;
+    }
+    const bool retest = __shfl(incl, 63, 64) > 64u * kWalkKeep;
+    if (retest && area) {
+      uint32_t a2;
+      walk_record(splats, cams, n, r, opt, me, a2);
+    }
+    uint32_t aoff;
+    const uint32_t atotal = rect_walk_begin(L, lane, area, me, aoff);
+    const uint64_t mine = lane < kWalkKeep ? kept[c * kWalkKeep + lane] : 0ull;
+    uint64_t cursor = chunk_off[c];
+    int carry = 0;
+    uint32_t k = 0;
     for (uint32_t j0 = 0; j0 < atotal; j0 += 64, ++k) {
       int tx, ty;
       const int owner = rect_walk_locate(L, lane, area, aoff, j0, carry, tx, ty);
       const RectRec& R = L.rec[owner];
       uint64_t b;
-      if (k < (uint32_t)kEmitRing) {
-        b = ring[k];
+      if (k < (uint32_t)kWalkKeep) {
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mine, (int)k);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(mine >> 32), (int)k);
+        b = ((uint64_t)hi << 32) | lo;
       } else {
         b = ballot(j0 + (uint32_t)lane < atotal && tile_hit_rcp(R.mx, R.my, R.a, R.b, R.c, R.ia, R.ic, opt, tx, ty));
       }
       if ((b >> lane) & 1ull) {
         const uint64_t o = cursor + (uint64_t)__popcll(b & lt);
-        if (o < capacity) {
-          tkeys[o] = R.tag1 + (uint32_t)ty * R.pad0 + (uint32_t)tx;
-          ivals[o] = R.tag0;
-        }
+        tkeys[o] = R.tag1 + (uint32_t)ty * R.pad0 + (uint32_t)tx;
+        ivals[o] = R.tag0;
       }
       cursor += (uint64_t)__popcll(b);
       __builtin_amdgcn_wave_barrier();
     }
-    if (c == nchunks - 1 && lane == 0) {
-      *d_num = cursor;
-      *d_status = cursor > capacity ? (int32_t)STEEPGS_ERR_CAPACITY : (int32_t)STEEPGS_OK;
-    }
   }
+}
+
+__global__ void k_instance_total(const uint64_t* __restrict__ total, uint64_t capacity,
+                                 uint64_t* __restrict__ d_num, int32_t* __restrict__ d_status) {
+  const uint64_t K = *total;
+  *d_num = K;
+  *d_status = (K > capacity) ? (int32_t)STEEPGS_ERR_CAPACITY : (int32_t)STEEPGS_OK;
 }
 
 // per-tile [begin, end) of the sorted list: four consecutive entries per
@@ -485,7 +486,11 @@ __global__ void k_keys64(const uint32_t* __restrict__ tkeys, const uint32_t* __r
 
 struct SortWs {
   uint32_t *dkA, *dvA, *dkB, *dvB;
-  uint64_t* lb;  // emission chunk counter and look-back status words
+  WalkRect* rects;        // walk rectangle per record, depth order
+  uint64_t* kept;         // kept hit ballots per chunk
+  uint32_t* chunk_hits;   // instances per chunk of 64 records
+  uint64_t* chunk_off;    // their exclusive scan
+  uint64_t* partials64;
   uint32_t *tkA, *tkB, *ivB;
   uint32_t* hist;
   uint32_t* hist_partials;
@@ -498,7 +503,12 @@ static size_t sort_layout(void* base, int64_t m, uint64_t cap, SortWs& w) {
   w.dvA = c.take<uint32_t>(m);
   w.dkB = c.take<uint32_t>(m);
   w.dvB = c.take<uint32_t>(m);
-  w.lb = c.take<uint64_t>(1 + (size_t)ceil_div(m, 64));
+  const int64_t nchunks = ceil_div(m, 64);
+  w.rects = c.take<WalkRect>(m);
+  w.kept = c.take<uint64_t>((size_t)nchunks * kWalkKeep);
+  w.chunk_hits = c.take<uint32_t>(nchunks);
+  w.chunk_off = c.take<uint64_t>(nchunks);
+  w.partials64 = c.take<uint64_t>(scan_partials_count(nchunks) + 1);
   w.tkA = c.take<uint32_t>(cap);
   w.tkB = c.take<uint32_t>(cap);
   w.ivB = c.take<uint32_t>(cap);
@@ -556,8 +566,9 @@ extern "C" steepgs_status steepgs_sort(const steepgs_splat* d_splats, const uint
   if (err != hipSuccess) return STEEPGS_ERR_HIP;
   const uint32_t* order = where ? w.dvB : w.dvA;
   const uint32_t* skeys = where ? w.dkB : w.dkA;
-  // 2. emit instances (tile id, record) in depth order, with their offsets
-  // from the look-back; K, the capacity check and the optional exact counts
+  // 2. walk the tile rectangles in depth order (hits per chunk of 64
+  // records, optional exact counts), offsets of the chunks, K and the
+  // capacity check, then the instances (tile id, record) in depth order
   int tile_bits = 1;
   while (tile_bits < 32 && ((uint64_t)1 << tile_bits) < (uint64_t)total_tiles) ++tile_bits;
   const int npass = (tile_bits + kRsMaxBits - 1) / kRsMaxBits;
@@ -565,11 +576,16 @@ extern "C" steepgs_status steepgs_sort(const steepgs_splat* d_splats, const uint
   uint32_t* ek = start ? w.tkB : w.tkA;
   uint32_t* ev = start ? w.ivB : d_vals;
   const int64_t nchunks = ceil_div(m, 64);
-  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)ceil_div(2 * (1 + nchunks), 256)), dim3(256), 0, st,
-                     reinterpret_cast<uint32_t*>(w.lb), 0u, 2 * (1 + nchunks));
-  const int egrid = (int)std::min<int64_t>(ceil_div(nchunks, 4), (int64_t)device_cu_count() * 8);
-  hipLaunchKernelGGL(k_emit, dim3(egrid), dim3(256), 0, st, d_splats, skeys, order, m, n, d_cams, *opts, capacity,
-                     w.lb, ek, ev, d_counts, d_num_instances, d_status);
+  const int egrid = (int)std::min<int64_t>(ceil_div(nchunks, 4), (int64_t)device_cu_count() * 16);
+  hipLaunchKernelGGL(k_walk, dim3(egrid), dim3(256), 0, st, d_splats, skeys, order, m, n, d_cams, *opts, w.rects,
+                     w.kept, w.chunk_hits, d_counts);
+  err = exclusive_scan<LoadU32, uint64_t, uint64_t>(LoadU32{w.chunk_hits}, nchunks, w.chunk_off, w.partials64, st);
+  if (err != hipSuccess) return STEEPGS_ERR_HIP;
+  hipLaunchKernelGGL(k_instance_total, dim3(1), dim3(1), 0, st, w.partials64 + scan_partials_count(nchunks), capacity,
+                     d_num_instances, d_status);
+  if (capacity > 0)
+    hipLaunchKernelGGL(k_emit, dim3(egrid), dim3(256), 0, st, d_splats, order, w.rects, w.kept, w.chunk_off, m, n,
+                       d_cams, *opts, d_num_instances, capacity, ek, ev);
   if (capacity > 0) {
     // 3. stable sort by tile (equal tiles keep the depth order)
     int fin = radix_sort_pairs(w.tkA, d_vals, w.tkB, w.ivB, start, d_num_instances, w.counters + 1, tile_bits, w.hist,
