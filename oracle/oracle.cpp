@@ -616,13 +616,21 @@ struct Contrib {
   bool clamped;
 };
 
+// A cut-off decision of the blend taken within reach of float32 rounding of
+// its threshold: either outcome is a correct result of an implementation
+// that evaluates the record in float32.
+enum DecisionKind { kDecFootprint = 0, kDecAlphaMax = 1, kDecAlphaMin = 2, kDecTmin = 3 };
+
 struct Pixel {
   double C[3];
   double T_final;
   std::vector<Contrib> list;
   int listed;  // how many entries of the tile list were examined (incl. the stopping one)
-  bool ambig;  // a cut-off decision within the ambiguity band
+  bool ambig;  // a cut-off decision within the ambiguity band, or an uncertain alpha
   std::vector<int> amb_ids;  // entries whose own cut-off decision is within the band
+  int ndec;    // decisions within their band (in the order the blend meets them)
+  int dec_kind[4];  // kinds of the first four of them
+  bool valunc;  // an entry's alpha is uncertain in float32 by more than kAlphaValue
 };
 
 constexpr double kAlphaBand = 1e-5;  // relative band around alpha_min / alpha_max
@@ -631,11 +639,15 @@ constexpr double kTBand = 5e-5;      // relative band around t_min (fp32 transmi
 // A float32 evaluation of q = d^T A d on float32 record values is only good to
 // about 2^-24 of the magnitude of its terms, |A00| dx^2 + 2|A01 dx dy| + |A11| dy^2,
 // which exceeds q by orders of magnitude for a thin Gaussian seen far along its
-// long axis.  The bands widen with that bound, and a pair whose alpha is
-// uncertain by more than kAlphaValue (alpha * bound / 2) marks its pixel as well.
+// long axis.  The bands widen with that bound, and a pair whose alpha error
+// (alpha * bound / 2) can move the colour by more than kAlphaValue marks its
+// pixel as well.
 constexpr double kAlphaValue = 1e-5;
 
-void blend_pixel(const View& view, int u, int v, Pixel& px) {
+// Blend one pixel (Eq. alpha_blend, front to back).  flip >= 0 takes the
+// other outcome of the flip-th decision within its band (counted as the
+// blend meets them), the alternative result of a float32 implementation.
+void blend_pixel(const View& view, int u, int v, Pixel& px, int flip = -1) {
   const Cam& cam = *view.cam;
   const Opts& opt = *view.opt;
   const std::vector<int>& lst = view.tiles[(size_t)(v / opt.th) * cam.tiles_x + (u / opt.tw)];
@@ -644,8 +656,19 @@ void blend_pixel(const View& view, int u, int v, Pixel& px) {
   px.list.clear();
   px.amb_ids.clear();
   px.ambig = false;
+  px.valunc = false;
+  px.ndec = 0;
   px.listed = (int)lst.size();
   const double k2 = opt.radius_sigmas * opt.radius_sigmas;
+  // records a decision within its band; true when this one is to be flipped
+  auto decide = [&](int kind, int g) {
+    if (px.ndec < 4) px.dec_kind[px.ndec] = kind;
+    const bool f = px.ndec == flip;
+    ++px.ndec;
+    px.ambig = true;
+    px.amb_ids.push_back(g);
+    return f;
+  };
   for (size_t j = 0; j < lst.size(); ++j) {
     const Proj<double>& g = view.rec[lst[j]];
     // footprint: only pixels within radius_sigmas (Mahalanobis) of the mean
@@ -654,34 +677,32 @@ void blend_pixel(const View& view, int u, int v, Pixel& px) {
     const double terms =
         std::fabs(g.A00) * dxu * dxu + 2.0 * std::fabs(g.A01 * dxu * dyv) + std::fabs(g.A11) * dyv * dyv;
     const double eq = std::ldexp(terms, -23);  // float32 bound on q, with a factor 2 of margin
-    bool amb = std::fabs(q - k2) <= std::max(kQBand * k2, eq);
-    if (amb) {
-      px.ambig = true;
-      px.amb_ids.push_back(lst[j]);
-    }
-    if (q > k2) continue;
+    bool outside = q > k2;
+    if (std::fabs(q - k2) <= std::max(kQBand * k2, eq) && decide(kDecFootprint, lst[j])) outside = !outside;
+    if (outside) continue;
     double a = alpha_raw(g.mx, g.my, g.A00, g.A01, g.A11, g.o, (double)u, (double)v);
     const double aband = std::max(kAlphaBand, 0.5 * eq);  // relative: d alpha / alpha = dq / 2
-    bool clamped = false;
-    amb = false;
-    if (opt.alpha_max < 1.0 && std::fabs(a - opt.alpha_max) <= aband * opt.alpha_max) amb = true;
-    if (a > opt.alpha_max) {
-      a = opt.alpha_max;
-      clamped = true;
-    }
-    if (opt.alpha_min > 0.0 && std::fabs(a - opt.alpha_min) <= aband * opt.alpha_min) amb = true;
-    if (a >= opt.alpha_min && a * std::ldexp(terms, -25) > kAlphaValue) amb = true;
-    if (amb) {
+    bool clamped = a > opt.alpha_max;
+    if (opt.alpha_max < 1.0 && std::fabs(a - opt.alpha_max) <= aband * opt.alpha_max &&
+        decide(kDecAlphaMax, lst[j]))
+      clamped = !clamped;
+    if (clamped) a = opt.alpha_max;
+    bool skip = a < opt.alpha_min;
+    if (opt.alpha_min > 0.0 && std::fabs(a - opt.alpha_min) <= aband * opt.alpha_min &&
+        decide(kDecAlphaMin, lst[j]))
+      skip = !skip;
+    // an alpha error da moves the colour by T da (c_i - mean colour behind
+    // the entry, background included): at most T da for colours in [0, 1]
+    if (!skip && T * a * std::ldexp(terms, -25) > kAlphaValue) {
+      px.valunc = true;
       px.ambig = true;
       px.amb_ids.push_back(lst[j]);
     }
-    if (a < opt.alpha_min) continue;
+    if (skip) continue;
     double Tn = T * (1.0 - a);
-    if (opt.t_min > 0.0 && std::fabs(Tn - opt.t_min) <= kTBand * opt.t_min) {
-      px.ambig = true;
-      px.amb_ids.push_back(lst[j]);
-    }
-    if (Tn < opt.t_min) {
+    bool stop = Tn < opt.t_min;
+    if (opt.t_min > 0.0 && std::fabs(Tn - opt.t_min) <= kTBand * opt.t_min && decide(kDecTmin, lst[j])) stop = !stop;
+    if (stop) {
       px.listed = (int)j + 1;
       break;
     }
@@ -1044,13 +1065,17 @@ int orc_sort(const float* params, int64_t n, int deg, const float* cam_f, const 
 //   pix_ambig [Px], loss [V] (needs target), grads [F][n] (+=), S [9][n] (+=),
 //   g2d [V*n][9] and H2d [V*n][3] per-view accumulators, gauss_ambig [n],
 //   grads_abs [F][n] and S_abs [9][n] (+=): the gross magnitudes of the terms
-//   the gradients and S are sums of (see lift).
+//   the gradients and S are sums of (see lift);
+//   pix_ndec [Px]: cut-off decisions within their float32 band, pix_valunc
+//   [Px]: an entry's alpha uncertain beyond kAlphaValue, pix_signamb [Px]:
+//   bit c set when |C_c - target_c| < sign_band.
 // sign_band: |C - target| below it marks the pixel ambiguous.
 int orc_forward_backward(const float* params, int64_t n, int deg, const float* cam_f, const int32_t* cam_i, int V,
                          const double* opts, const float* target, const double* dLdimage, double sign_band,
                          double* image, double* T_final,
                          int32_t* n_used, uint8_t* pix_ambig, double* loss, double* grads, double* S, double* g2d,
-                         double* H2d, uint8_t* gauss_ambig, double* grads_abs, double* S_abs) {
+                         double* H2d, uint8_t* gauss_ambig, double* grads_abs, double* S_abs, int32_t* pix_ndec,
+                         uint8_t* pix_valunc, uint8_t* pix_signamb) {
   if (n < 0 || V <= 0 || deg < 0 || deg > 3) return 1;
   Opts opt = read_opts(opts);
   std::vector<Cam> cams = read_cams(cam_f, cam_i, V, opt);
@@ -1074,6 +1099,9 @@ int orc_forward_backward(const float* params, int64_t n, int deg, const float* c
           for (int ch = 0; ch < 3; ++ch) image[3 * cam.pixel_offset + (int64_t)ch * cam.W * cam.H + (int64_t)y * cam.W + x] = px.C[ch];
         if (T_final) T_final[pid] = px.T_final;
         if (n_used) n_used[pid] = (int32_t)px.list.size();
+        if (pix_ndec) pix_ndec[pid] = px.ndec;
+        if (pix_valunc) pix_valunc[pid] = px.valunc ? 1 : 0;
+        if (pix_signamb) pix_signamb[pid] = 0;
         bool amb = px.ambig;
         if (!target && !dLdimage) {
           if (pix_ambig) pix_ambig[pid] = amb;
@@ -1089,7 +1117,10 @@ int orc_forward_backward(const float* params, int64_t n, int deg, const float* c
           double diff = px.C[ch] - target[e];
           lsum += std::fabs(diff);
           dLdC[ch] = sgn(diff) * inv;
-          if (std::fabs(diff) < sign_band) amb = true;
+          if (std::fabs(diff) < sign_band) {
+            amb = true;
+            if (pix_signamb) pix_signamb[pid] |= (uint8_t)(1u << ch);
+          }
         }
         if (pix_ambig) pix_ambig[pid] = amb;
         if (amb && gauss_ambig) mark_affected(px, gauss_ambig);
@@ -1125,6 +1156,85 @@ int orc_forward_backward(const float* params, int64_t n, int deg, const float* c
     }
   }
   (void)F;
+  return 0;
+}
+
+// The contribution of single pixels to the gradients and splitting matrices,
+// under a chosen outcome of their in-band decisions and a chosen loss sign:
+// variant k is pixel pix[k] (global packed id), blended with decision
+// flip[k] flipped (-1: none), with dL/dC_c = sgnv[3k+c] / (3 H W) where
+// sgnv[3k+c] is -1, 0 or 1, or (2) the sign of C_c - target_c of the
+// variant's own colour; with dLdimage (packed image layout) dL/dC comes from
+// there instead.  Out: rgb [nv][3], T_final [nv], used [nv] (entries
+// blended), ndec [nv], and the Gaussians whose gradient or S the pixel
+// changes, in CSR form: count [nv]; with gid != nullptr also gid [sum count]
+// (Gaussian index), grad [sum count][F], S [sum count][9] (the pixel's term
+// of Theorem 1's sum, lifted with the Gaussian's own Jacobian) and, when
+// non-null, S6 [sum count][21] (its term of the dim-6 S).  Call once with
+// gid == nullptr for the counts.
+int orc_pixel_variants(const float* params, int64_t n, int deg, const float* cam_f, const int32_t* cam_i, int V,
+                       const double* opts, const float* target, const double* dLdimage, int64_t nv,
+                       const int64_t* pix, const int32_t* flip, const int32_t* sgnv, double* rgb, double* T_final,
+                       int32_t* used, int32_t* ndec, int64_t* count, int64_t* gid, double* grad, double* S,
+                       double* S6) {
+  if (n < 0 || V <= 0 || deg < 0 || deg > 3 || (!target && !dLdimage)) return 1;
+  Opts opt = read_opts(opts);
+  std::vector<Cam> cams = read_cams(cam_f, cam_i, V, opt);
+  const int F = num_params(deg);
+  int64_t cursor = 0;
+  std::vector<int64_t> start(nv + 1, 0);
+  if (gid) {
+    for (int64_t k = 0; k < nv; ++k) start[k + 1] = start[k] + count[k];
+  }
+  std::vector<Grad2D> acc(n);
+  for (auto& a : acc) std::memset(&a, 0, sizeof(a));
+  for (int v = 0; v < V; ++v) {
+    const Cam& cam = cams[v];
+    bool any = false;
+    for (int64_t k = 0; k < nv; ++k)
+      any |= (pix[k] >= cam.pixel_offset && pix[k] < cam.pixel_offset + (int64_t)cam.W * cam.H);
+    if (!any) continue;
+    View view;
+    build_view(params, n, deg, cam, opt, view);
+    const double inv = 1.0 / (3.0 * cam.W * cam.H);
+    Pixel px;
+    for (int64_t k = 0; k < nv; ++k) {
+      const int64_t local = pix[k] - cam.pixel_offset;
+      if (local < 0 || local >= (int64_t)cam.W * cam.H) continue;
+      const int x = (int)(local % cam.W), y = (int)(local / cam.W);
+      blend_pixel(view, x, y, px, flip[k]);
+      for (int ch = 0; ch < 3; ++ch) rgb[3 * k + ch] = px.C[ch];
+      T_final[k] = px.T_final;
+      used[k] = (int32_t)px.list.size();
+      ndec[k] = px.ndec;
+      double dLdC[3];
+      for (int ch = 0; ch < 3; ++ch) {
+        const int64_t e = 3 * cam.pixel_offset + (int64_t)ch * cam.W * cam.H + (int64_t)y * cam.W + x;
+        const int sg = sgnv[3 * k + ch];
+        dLdC[ch] = dLdimage ? dLdimage[e] : (sg == 2 ? sgn(px.C[ch] - target[e]) : (double)sg) * inv;
+      }
+      backward_pixel(view, x, y, px, dLdC, acc, nullptr, S6 != nullptr);
+      // the contributors, in blend order (each once)
+      int64_t c = 0;
+      for (const Contrib& ct : px.list) {
+        const int g = ct.g;
+        if (gid) {
+          const int64_t o = start[k] + c;
+          gid[o] = g;
+          for (int f = 0; f < F; ++f) grad[o * F + f] = 0.0;
+          for (int q = 0; q < 9; ++q) S[o * 9 + q] = 0.0;
+          lift(params, n, deg, g, cam, opt, acc[g], grad + o * F, 1, S + o * 9, 1);
+          if (S6)
+            for (int q = 0; q < kH6; ++q) S6[o * kH6 + q] = acc[g].H6[q];
+        }
+        ++c;
+      }
+      for (const Contrib& ct : px.list) std::memset(&acc[ct.g], 0, sizeof(Grad2D));
+      if (!gid) count[k] = c;
+      cursor += c;
+    }
+  }
+  (void)cursor;
   return 0;
 }
 

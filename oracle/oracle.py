@@ -51,7 +51,7 @@ def lib():
         L.orc_project.restype = C.c_int
         L.orc_sort.argtypes = common + [C.POINTER(C.c_uint64), C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_sort.restype = C.c_int
-        L.orc_forward_backward.argtypes = common + [C.c_void_p, C.c_void_p, C.c_double] + [C.c_void_p] * 12
+        L.orc_forward_backward.argtypes = common + [C.c_void_p, C.c_void_p, C.c_double] + [C.c_void_p] * 15
         L.orc_forward_backward.restype = C.c_int
         L.orc_loss.argtypes = common + [_c_f32]
         L.orc_loss.restype = C.c_double
@@ -83,6 +83,9 @@ def lib():
         L.orc_densify6.restype = C.c_int64
         L.orc_eigh_n.argtypes = [_c_f64, C.c_int64, C.c_int, _c_f64, _c_f64]
         L.orc_eigh_n.restype = None
+        L.orc_pixel_variants.argtypes = common + [C.c_void_p, C.c_void_p, C.c_int64, _c_i64, _c_i32, _c_i32] + \
+            [C.c_void_p] * 9
+        L.orc_pixel_variants.restype = C.c_int
         L.orc_tile_lists.argtypes = common + [_c_i64, C.c_int64, _c_i64, C.c_void_p]
         L.orc_tile_lists.restype = C.c_int
         L.orc_num_params.argtypes = [C.c_int]
@@ -171,6 +174,9 @@ def forward_backward(params, sh_degree, cams, opts, target=None, sign_band=1e-5,
     T = np.zeros(Px, np.float64)
     used = np.zeros(Px, np.int32)
     pamb = np.zeros(Px, np.uint8)
+    ndec = np.zeros(Px, np.int32)
+    valunc = np.zeros(Px, np.uint8)
+    signamb = np.zeros(Px, np.uint8)
     out = dict(image=image, T_final=T, n_used=used, pix_ambig=pamb)
     tgt = None if target is None else np.ascontiguousarray(target, np.float32)
     dld = None if dl_dimage is None else np.ascontiguousarray(dl_dimage, np.float64)
@@ -187,9 +193,12 @@ def forward_backward(params, sh_degree, cams, opts, target=None, sign_band=1e-5,
             H2d = np.zeros((cams.V * n, 3), np.float64)
     rc = lib().orc_forward_backward(*args, _ptr(tgt), _ptr(dld), float(sign_band), _ptr(image), _ptr(T), _ptr(used),
                                     _ptr(pamb), _ptr(loss), _ptr(grads), _ptr(S), _ptr(g2d), _ptr(H2d), _ptr(gamb),
-                                    _ptr(gabs), _ptr(Sabs))
+                                    _ptr(gabs), _ptr(Sabs), _ptr(ndec), _ptr(valunc), _ptr(signamb))
     assert rc == 0
     out["pix_ambig"] = pamb.astype(bool)
+    # per pixel: cut-off decisions within their float32 band, an entry's alpha
+    # uncertain in float32 beyond 1e-5, channels with |C - target| < sign_band
+    out.update(pix_ndec=ndec, pix_valunc=valunc.astype(bool), pix_signamb=signamb)
     if tgt is not None or dld is not None:
         # grads_abs / S_abs: gross magnitudes of the summed per-pixel terms
         # (the scale of an order-dependent float32 summation error)
@@ -197,6 +206,45 @@ def forward_backward(params, sh_degree, cams, opts, target=None, sign_band=1e-5,
         if per_view:
             out.update(g2d=g2d, H2d=H2d)
     return out
+
+
+def pixel_variants(params, sh_degree, cams, opts, target, pix, flip, signs, dl_dimage=None, with_s6=False):
+    """Single pixels under a chosen outcome of their in-band decisions:
+    pix [nv] global packed ids, flip [nv] the decision to flip (-1 none),
+    signs [nv][3] the loss sign per channel (-1, 0, 1; 2: from the variant's
+    own colour; ignored with ``dl_dimage``, an upstream gradient of the packed
+    image).  Returns per variant the colour, final transmittance, blended
+    count and number of in-band decisions, and the pixel's terms of the
+    gradients and S as lists of (Gaussian ids, grads [k][F], S [k][9]
+    (, S6 [k][21] with ``with_s6``))."""
+    args = _common(params, sh_degree, cams, opts)
+    F = params.shape[0]
+    tgt = None if target is None else np.ascontiguousarray(target, np.float32)
+    dld = None if dl_dimage is None else np.ascontiguousarray(dl_dimage, np.float64)
+    pix = np.ascontiguousarray(pix, np.int64)
+    flip = np.ascontiguousarray(flip, np.int32)
+    sg = np.ascontiguousarray(signs, np.int32).reshape(-1)
+    nv = len(pix)
+    rgb = np.zeros((nv, 3), np.float64)
+    T = np.zeros(nv, np.float64)
+    used = np.zeros(nv, np.int32)
+    nd = np.zeros(nv, np.int32)
+    cnt = np.zeros(nv, np.int64)
+    rc = lib().orc_pixel_variants(*args, _ptr(tgt), _ptr(dld), nv, pix, flip, sg, _ptr(rgb), _ptr(T), _ptr(used),
+                                  _ptr(nd), _ptr(cnt), None, None, None, None)
+    assert rc == 0
+    tot = int(cnt.sum())
+    gid = np.zeros(max(tot, 1), np.int64)
+    gr = np.zeros((max(tot, 1), F), np.float64)
+    Sv = np.zeros((max(tot, 1), 9), np.float64)
+    S6 = np.zeros((max(tot, 1), 21), np.float64) if with_s6 else None
+    rc = lib().orc_pixel_variants(*args, _ptr(tgt), _ptr(dld), nv, pix, flip, sg, _ptr(rgb), _ptr(T), _ptr(used),
+                                  _ptr(nd), _ptr(cnt), _ptr(gid), _ptr(gr), _ptr(Sv), _ptr(S6))
+    assert rc == 0
+    off = np.concatenate([[0], np.cumsum(cnt)])
+    terms = [(gid[off[k]:off[k + 1]], gr[off[k]:off[k + 1]], Sv[off[k]:off[k + 1]])
+             + ((S6[off[k]:off[k + 1]],) if with_s6 else ()) for k in range(nv)]
+    return dict(rgb=rgb, T_final=T, n_used=used, ndec=nd, terms=terms)
 
 
 def loss(params, sh_degree, cams, opts, target):

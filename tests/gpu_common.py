@@ -166,3 +166,234 @@ def scene_small(kind, seed=0):
         cams = scenes.make_cameras([(0.0, 1.0, 4.0)], [(72, 72)], model=1, ortho_scale=24.0)
         return P, 0, cams, scenes.uniform_target(rng, cams)
     raise KeyError(kind)
+
+
+def packed_index(cams, pix):
+    """[len(pix)][3] indices into the packed image of global pixel ids"""
+    offs = np.asarray(cams.pixel_offsets(), np.int64)
+    wh = (np.asarray(cams.width, np.int64) * np.asarray(cams.height, np.int64))
+    v = np.searchsorted(offs, pix, side="right") - 1
+    local = pix - offs[v]
+    return 3 * offs[v][:, None] + np.arange(3)[None, :] * wh[v][:, None] + local[:, None]
+
+
+def checked_reference(oracle, P, deg, cams, opts, g, target=None, dl_dimage=None, with_s6=False):
+    """The oracle's reference for one GPU run, with every decision that float32
+    can take either way resolved instead of excluded.
+
+    A pixel whose blend takes a cut-off decision within float32 reach of its
+    threshold (footprint, alpha_max, alpha_min, t_min), or whose L1 sign is
+    within reach of zero, has more than one correct result.  The oracle
+    computes the pixel under each outcome (colour, transmittance, blended
+    count, and its terms of every Gaussian's gradient and S); the GPU's colour
+    and blended count must match one of them, and the reference takes that
+    outcome's terms in place of the default ones.  The loss sign the GPU used
+    is its own float32 sign of C - target.  Outcomes the image cannot tell
+    apart (a clamp at alpha ~ alpha_max changes the gradient, not the colour)
+    are both accepted per Gaussian (every combination, up to four such pixels
+    per Gaussian; beyond that the Gaussian is left out).  Pixels with two or more such decisions
+    are excluded with the Gaussians they touch; pixels whose alpha float32
+    cannot evaluate to the image bar (thin footprints seen along their long
+    axis, pix_valunc) are checked, and their deviations counted, not failed.
+
+    Returns dict(image, T_final, n_used, grads, S, [S6], pix_excl, gauss_excl,
+    gauss_either, pix_soft, gauss_soft, stats)."""
+    ref = oracle.forward_backward(P, deg, cams, opts, target, dl_dimage=dl_dimage)
+    n = P.shape[1]
+    out = dict(image=ref["image"].copy(), T_final=ref["T_final"].copy(), n_used=ref["n_used"].copy(),
+               grads=ref["grads"].copy(), S=ref["S"].copy(), loss=ref.get("loss"))
+    if with_s6:
+        out["S6"] = oracle.split6(P, deg, cams, opts, target, dl_dimage=dl_dimage).copy()
+    nd, vu, sa = ref["pix_ndec"], ref["pix_valunc"], ref["pix_signamb"]
+    multi = nd >= 2
+    flagged = np.nonzero(((nd == 1) | ((sa > 0) & (dl_dimage is None))) & ~multi)[0]
+    pix_excl = multi.copy()
+    gauss_excl = np.zeros(n, bool)
+    gauss_either = {}  # Gaussian -> list of (grad delta, S delta) alternatives
+    stats = dict(flagged=len(flagged), multi=int(multi.sum()), gpu_flipped=0, either=0, valunc=int(vu.sum()))
+    img_g = g["image"]
+    if len(flagged):
+        e = packed_index(cams, flagged)
+        if dl_dimage is None:
+            d32 = img_g[e].astype(np.float32) - np.asarray(target, np.float32)[e]
+            sg = np.sign(d32).astype(np.int32)
+        else:
+            sg = np.zeros((len(flagged), 3), np.int32)
+        pix_l, flip_l, sgn_l, role = [], [], [], []
+        for k, p in enumerate(flagged):
+            pix_l += [p, p]
+            flip_l += [-1, -1]
+            sgn_l += [[2, 2, 2], list(sg[k])]
+            role += [(k, "D"), (k, "A")]
+            if nd[p] == 1:
+                pix_l.append(p)
+                flip_l.append(0)
+                sgn_l.append(list(sg[k]))
+                role.append((k, "B"))
+        var = oracle.pixel_variants(P, deg, cams, opts, target, np.array(pix_l), np.array(flip_l), np.array(sgn_l),
+                                    dl_dimage=dl_dimage, with_s6=with_s6)
+        by = {}
+        for j, (k, r) in enumerate(role):
+            by.setdefault(k, {})[r] = j
+        for k, p in enumerate(flagged):
+            got = img_g[e[k]]
+            cand = []
+            for r in ("A", "B"):
+                if r not in by[k]:
+                    continue
+                j = by[k][r]
+                ok = (np.abs(got - var["rgb"][j]) <= 1e-5 + 1e-4 * np.abs(var["rgb"][j])).all()
+                ok &= int(g["n_used"][p]) == int(var["n_used"][j])
+                if ok:
+                    cand.append(j)
+            if not cand:
+                raise AssertionError(f"pixel {p}: the GPU's colour {got} / count {g['n_used'][p]} matches no outcome "
+                                     f"of its in-band decision: " +
+                                     ", ".join(f"{r}: {var['rgb'][by[k][r]]} / {var['n_used'][by[k][r]]}"
+                                               for r in ("A", "B") if r in by[k]))
+            jd = by[k]["D"]
+
+            def delta(j):
+                dg = {}
+                for gid, gr, Sv, *rest in (var["terms"][j],):
+                    for t, i in enumerate(gid):
+                        a = dg.setdefault(int(i), [np.zeros(P.shape[0]), np.zeros(9), np.zeros(21)])
+                        a[0] += gr[t]
+                        a[1] += Sv[t]
+                        if rest:
+                            a[2] += rest[0][t]
+                gid, gr, Sv, *rest = var["terms"][jd]
+                for t, i in enumerate(gid):
+                    a = dg.setdefault(int(i), [np.zeros(P.shape[0]), np.zeros(9), np.zeros(21)])
+                    a[0] -= gr[t]
+                    a[1] -= Sv[t]
+                    if rest:
+                        a[2] -= rest[0][t]
+                return dg
+
+            j = cand[0]
+            out["image"][e[k]] = var["rgb"][j]
+            out["T_final"][p] = var["T_final"][j]
+            out["n_used"][p] = var["n_used"][j]
+            if by[k].get("B") == j:
+                stats["gpu_flipped"] += 1
+            dg = delta(j)
+            for i, (dgr, dS, dS6) in dg.items():
+                out["grads"][:, i] += dgr
+                out["S"][:, i] += dS
+                if with_s6:
+                    out["S6"][:, i] += dS6
+            if len(cand) == 2:  # both outcomes fit the image: either is a correct gradient
+                stats["either"] += 1
+                d2 = delta(cand[1])
+                for i in set(dg) | set(d2):
+                    a = dg.get(i, [np.zeros(P.shape[0]), np.zeros(9), np.zeros(21)])
+                    b = d2.get(i, [np.zeros(P.shape[0]), np.zeros(9), np.zeros(21)])
+                    gauss_either.setdefault(i, []).append((b[0] - a[0], b[1] - a[1], b[2] - a[2]))
+    # Gaussians touched by excluded pixels (every outcome's contributors)
+    if multi.any():
+        mp = np.nonzero(multi)[0]
+        pl, fl = [], []
+        for p in mp:
+            for f in range(-1, int(nd[p])):
+                pl.append(p)
+                fl.append(f)
+        var = oracle.pixel_variants(P, deg, cams, opts, target, np.array(pl), np.array(fl),
+                                    np.full((len(pl), 3), 2), dl_dimage=dl_dimage)
+        for gid, *_ in var["terms"]:
+            gauss_excl[gid] = True
+    pix_soft = vu & ~pix_excl
+    gauss_soft = np.zeros(n, bool)
+    if pix_soft.any():
+        sp = np.nonzero(pix_soft)[0]
+        var = oracle.pixel_variants(P, deg, cams, opts, target, sp, -np.ones(len(sp), np.int32),
+                                    np.full((len(sp), 3), 2), dl_dimage=dl_dimage)
+        for gid, *_ in var["terms"]:
+            gauss_soft[gid] = True
+    out.update(pix_excl=pix_excl, gauss_excl=gauss_excl, gauss_either=gauss_either, pix_soft=pix_soft,
+               gauss_soft=gauss_soft & ~gauss_excl, stats=stats)
+    return out
+
+
+def check_against(g, vref, cams, what, grads_key="grads", S_key="S6", rel=1e-3, abs_frac=1e-6):
+    """Image, transmittance, blended counts, gradients and S of a GPU run
+    against checked_reference at the plain bars.  Pixels and Gaussians of
+    pix_soft / gauss_soft may deviate (counted); pix_excl / gauss_excl are
+    left out.  Prints and returns the fractions."""
+    excl_rgb = expand_pixel_mask(vref["pix_excl"], cams)
+    soft_rgb = expand_pixel_mask(vref["pix_soft"], cams)
+    ok = image_close(g["image"], vref["image"])
+    bad = ~ok & ~excl_rgb
+    assert not (bad & ~soft_rgb).any(), f"{what}: {(bad & ~soft_rgb).sum()} image values out of tolerance"
+    soft_dev = (bad & soft_rgb).reshape(-1)
+    pix_soft_dev = np.zeros(len(vref["pix_excl"]), bool)
+    if soft_dev.any():
+        idx = np.nonzero(soft_dev)[0]
+        for v in range(cams.V):
+            o = 3 * cams.pixel_offsets()[v]
+            wh = int(cams.width[v] * cams.height[v])
+            sel = idx[(idx >= o) & (idx < o + 3 * wh)] - o
+            pix_soft_dev[cams.pixel_offsets()[v] + (sel % wh)] = True
+    keep_px = ~vref["pix_excl"] & ~vref["pix_soft"]
+    okT = np.abs(g["T_final"] - vref["T_final"]) <= 1e-5 + 1e-4 * vref["T_final"]
+    assert okT[keep_px].all(), f"{what}: transmittance"
+    np.testing.assert_array_equal(g["n_used"][keep_px], vref["n_used"][keep_px])
+    n = g[grads_key].shape[1]
+    # per Gaussian: the plain bar against the reference, or against the
+    # reference with the other outcome of a pixel both outcomes of which fit
+    G, R = g[grads_key], vref["grads"]
+    S9 = vref["S"]
+    excl = vref["gauss_excl"].copy()
+    either = vref["gauss_either"]
+    for i, alts in either.items():
+        if len(alts) > 4:
+            excl[i] = True
+    fails = _group_fails(G, R, ~excl, rel, abs_frac) | _S_fails(g[S_key], S9, ~excl, rel, abs_frac)
+    for i in list(np.nonzero(fails)[0]):
+        alts = either.get(int(i), [])
+        if not alts or len(alts) > 4:
+            continue
+        one = np.zeros(n, bool)
+        one[i] = True
+        # every combination of the pixels' outcomes
+        for mask in range(1, 1 << len(alts)):
+            R2 = R.copy()
+            S2 = S9.copy()
+            for b, alt in enumerate(alts):
+                if (mask >> b) & 1:
+                    R2[:, i] += alt[0]
+                    S2[:, i] += alt[1]
+            if not (_group_fails(G, R2, one, rel, abs_frac, scale_from=R)[i] or
+                    _S_fails(g[S_key], S2, one, rel, abs_frac, scale_from=S9)[i]):
+                fails[i] = False
+                break
+    soft = vref["gauss_soft"]
+    hard = fails & ~soft
+    assert not hard.any(), (f"{what}: {hard.sum()} Gaussians out of tolerance, e.g. {np.nonzero(hard)[0][:8]}")
+    st = dict(vref["stats"], pix_excl=float(vref["pix_excl"].mean()), gauss_excl=float(excl.mean()),
+              pix_soft_dev=float(pix_soft_dev.mean()), gauss_soft_dev=float((fails & soft).mean()))
+    print(f"[checked] {what}: {st}", flush=True)
+    return st
+
+
+def _group_fails(got, ref, keep, rel, abs_frac, scale_from=None):
+    scale = ref if scale_from is None else scale_from
+    fails = np.zeros(got.shape[1], bool)
+    for name, sl in GROUPS.items():
+        dn = np.linalg.norm(got[sl] - ref[sl], axis=0)
+        rn = np.linalg.norm(ref[sl], axis=0)
+        top = np.linalg.norm(scale[sl], axis=0)
+        tol = rel * rn + abs_frac * (top[keep].max() if keep.any() else 0.0)
+        fails |= keep & (dn > tol)
+    return fails
+
+
+def _S_fails(S6_gpu, S9_ref, keep, rel, abs_frac, scale_from=None):
+    M_g = s6_to_mats(S6_gpu)
+    M_r = s6_to_mats(s9_to_s6(S9_ref))
+    M_s = M_r if scale_from is None else s6_to_mats(s9_to_s6(scale_from))
+    dn = np.linalg.norm((M_g - M_r).reshape(len(M_g), -1), axis=1)
+    rn = np.linalg.norm(M_r.reshape(len(M_r), -1), axis=1)
+    top = np.linalg.norm(M_s.reshape(len(M_s), -1), axis=1)
+    tol = rel * rn + abs_frac * (top[keep].max() if keep.any() else 0.0)
+    return keep & (dn > tol)

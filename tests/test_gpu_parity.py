@@ -5,18 +5,18 @@ Bars: projected records within fp32 rounding of the oracle's fp64 values, and
 culling / rectangles / depth bits bit-exact; instance keys, values and tile
 ranges bit-exact; image within 1e-5 abs + 1e-4 rel; gradients and S_i within
 1e-3 of the reference norm per Gaussian and parameter group plus 1e-6 of the
-largest; lambda_min signs equal where |lambda_min| > 1e-4 |S_i|.  Pixels and
-Gaussians whose result hinges on a cut-off decision within its fp32 band
-(alpha_min, alpha_max, t_min, sign of C - target) are excluded, as the oracle
-flags them.
+largest; lambda_min signs equal where |lambda_min| > 1e-4 |S_i|.  Where a
+cut-off decision (footprint, alpha_min, alpha_max, t_min) or the L1 sign lies
+within float32 reach of its threshold, the oracle computes every outcome and
+the GPU must match one of them (gpu_common.checked_reference).
 """
 import numpy as np
 import pytest
 import torch
 
 from paper_2505_05587_amd import scenes
-from tests.gpu_common import (assert_group_close, assert_S_close, expand_pixel_mask, image_close,
-                              run_gpu, scene_small)
+from tests.gpu_common import (assert_group_close, assert_S_close, check_against, checked_reference,
+                              expand_pixel_mask, image_close, run_gpu, scene_small)
 
 pytestmark = pytest.mark.gpu
 
@@ -65,23 +65,12 @@ def test_forward_backward(oracle, kind, mode):
     opts = scenes.opts(mode)
     print(f"\n[case] fwd+bwd kind={kind} mode={mode} n={P.shape[1]} V={cams.V}", flush=True)
     g = run_gpu(P, deg, cams, opts, target=target)
-    ref = oracle.forward_backward(P, deg, cams, opts, target)
-    pix_amb = ref["pix_ambig"]
-    # excluded fractions: the extreme scene's needles, seen far along their
-    # long axis, carry pairs whose float32 quadratic form is ill-conditioned
-    # (the oracle flags them from the bound 2^-24 (|a| dx^2 + 2|b dx dy| + |c| dy^2))
-    lim_pix, lim_g = (0.02, 0.15) if kind.startswith("extreme") else (1e-3 if mode == "smooth" else 5e-3, 0.1)
-    assert pix_amb.mean() < lim_pix
-    ok = image_close(g["image"], ref["image"], expand_pixel_mask(pix_amb, cams))
-    assert ok.all(), f"{(~ok).sum()} image values out of tolerance"
-    okT = np.abs(g["T_final"] - ref["T_final"]) <= 1e-5 + 1e-4 * ref["T_final"]
-    assert (okT | pix_amb).all()
-    np.testing.assert_array_equal(g["n_used"][~pix_amb], ref["n_used"][~pix_amb])
-    np.testing.assert_allclose(g["loss"], ref["loss"], rtol=1e-4)
-    gamb = ref["gauss_ambig"]
-    assert gamb.mean() < lim_g
-    assert_group_close(g["grads"], ref["grads"], gamb, what=f"{kind}/{mode}", gross=ref["grads_abs"])
-    assert_S_close(g["S6"], ref["S"], gamb, gross=ref["S_abs"], what=f"{kind}/{mode}")
+    vref = checked_reference(oracle, P, deg, cams, opts, g, target=target)
+    st = check_against(g, vref, cams, f"{kind}/{mode}")
+    # excluded or deviating: under 1e-3 of the pixels, under 1 % of the Gaussians
+    assert st["pix_excl"] + st["pix_soft_dev"] < 1e-3
+    assert st["gauss_excl"] + st["gauss_soft_dev"] < 1e-2
+    np.testing.assert_allclose(g["loss"], vref["loss"], rtol=1e-4)
 
 
 @pytest.mark.parametrize("kind", ["multiview", "sh3_pinhole"])
@@ -225,24 +214,24 @@ def test_empty_set_and_tiny_views(oracle, n):
     ras = pipeline.Rasterizer(cb, 0, capacity=64)
     Pt = torch.from_numpy(np.ascontiguousarray(P)).to(dev)
     tg = torch.from_numpy(target).to(dev)
-    fs = ras.forward(Pt, tg)
+    fs = ras.forward(Pt, tg, count_used=True)
     grads = torch.zeros_like(Pt)
     S = torch.zeros((6, n), dtype=torch.float32, device=dev)
     ras.backward(Pt, grads, S, target=tg)
     d = pipeline.densify(Pt, 0, S, 1.0, 0.01, -1e-6)
     torch.cuda.synchronize()
-    ref = oracle.forward_backward(P, 0, cams, opts, target)
-    ok = image_close(fs.image.cpu().numpy().astype(np.float64), ref["image"], expand_pixel_mask(ref["pix_ambig"], cams))
-    assert ok.all()
     assert d["status"] == L.OK and d["n_out"] >= n
+    g = dict(image=fs.image.cpu().numpy().astype(np.float64), T_final=fs.T_final.cpu().numpy(),
+             n_used=ras.n_used.cpu().numpy(), grads=grads.cpu().numpy().astype(np.float64),
+             S6=S.cpu().numpy().astype(np.float64))
     if n == 0:
+        ref = oracle.forward_backward(P, 0, cams, opts)
+        assert image_close(g["image"], ref["image"]).all()
         assert fs.K == 0 and d["n_out"] == 0
         return
     assert fs.K > 0
-    gamb = ref["gauss_ambig"]
-    assert_group_close(grads.cpu().numpy().astype(np.float64), ref["grads"], gamb, what=f"tiny/{n}",
-                       gross=ref["grads_abs"])
-    assert_S_close(S.cpu().numpy().astype(np.float64), ref["S"], gamb, gross=ref["S_abs"])
+    vref = checked_reference(oracle, P, 0, cams, opts, g, target=target)
+    check_against(g, vref, cams, f"tiny/{n}")
 
 
 @pytest.mark.parametrize("kind", ["extreme_rand", "multiview"])

@@ -8,8 +8,7 @@ import torch
 
 from paper_2505_05587_amd import scenes
 from paper_2505_05587_amd.autotune import tune
-from tests.gpu_common import (assert_group_close, assert_S_close, expand_pixel_mask, image_close,
-                              run_gpu, scene_small)
+from tests.gpu_common import check_against, checked_reference, run_gpu, scene_small
 
 pytestmark = pytest.mark.gpu
 
@@ -26,12 +25,10 @@ def test_tile_shape_parity(oracle, kind, tile):
     np.testing.assert_array_equal(g["keys"], keys)
     np.testing.assert_array_equal(g["vals"], vals)
     np.testing.assert_array_equal(g["ranges"], ranges)
-    ref = oracle.forward_backward(P, deg, cams, opts, target)
-    ok = image_close(g["image"], ref["image"], expand_pixel_mask(ref["pix_ambig"], cams))
-    assert ok.all()
-    assert_group_close(g["grads"], ref["grads"], ref["gauss_ambig"], what=f"tile {tile} {kind}",
-                       gross=ref["grads_abs"])
-    assert_S_close(g["S6"], ref["S"], ref["gauss_ambig"], gross=ref["S_abs"], what=f"tile {tile} {kind}")
+    vref = checked_reference(oracle, P, deg, cams, opts, g, target=target)
+    st = check_against(g, vref, cams, f"tile {tile} {kind}")
+    assert st["pix_excl"] + st["pix_soft_dev"] < 1e-3
+    assert st["gauss_excl"] + st["gauss_soft_dev"] < 1e-2
     # the image does not depend on the tiling
     g16 = run_gpu(P, deg, cams, scenes.opts("3dgs"), target=target)
     np.testing.assert_array_equal(g["image"], g16["image"])
