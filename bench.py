@@ -30,9 +30,19 @@ if ROOT not in sys.path:
 
 METRIC = "ms per fwd+bwd+split step, 1M Gaussians×16 views; batched vs per-view speedup"
 PEAK_HBM_GBS = 8000.0
-# fp32 vector peak without packed-FP32 instructions: 256 CU x 4 SIMD x 16 lanes
-# x 2 flop (FMA) x 2.4 GHz
+# published fp32 vector peak of MI355X (packed FP32)
+PEAK_FP32_TFLOPS = 157.3
+# the same without packed-FP32 instructions (this library compiles without
+# them): 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 PEAK_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# algorithmic fp32 work of the raster kernels: flops per examined (pixel,
+# entry) pair and per contributing pair (quadratic form, exponential and
+# tests per examined pair; blend or gradient, moments and sums per
+# contributing pair)
+FLOP_EXAMINED = 10
+FLOP_CONTRIB_FWD = 20
+FLOP_CONTRIB_BWD = 60
+FLOP_CONTRIB_BWD6 = 83  # + the third and fourth moments of the dim-6 backward
 
 
 def say(msg):
@@ -135,6 +145,36 @@ def measured_traffic(stage):
                float(rec["write_kib"]) * float(rec["write_scale"]) * 1024)
 
 
+def host_cpu():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def valu_calibration(torch, L, dev):
+    """Achievable fp32 VALU rate of plain FMAs (TFLOP/s), best of three
+    launches of the library's FMA-loop kernel, timed with events."""
+    blocks, iters = torch.cuda.get_device_properties(dev).multi_processor_count * 8, 20000
+    out = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
+    L.steepgs_calibrate_valu(out, blocks, 100)
+    best = None
+    for _ in range(3):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        L.steepgs_calibrate_valu(out, blocks, iters)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    return blocks * 256 * iters * 16 / (best * 1e-3) / 1e12
+
+
 def cpu_baseline(scene, opts):
     """The oracle as it stands on one view of the workload (full Gaussian set),
     scaled to the 16-view step, plus its densification over all Gaussians."""
@@ -152,7 +192,8 @@ def cpu_baseline(scene, opts):
     O.densify(scene.params, scene.sh_degree, r["S"], 1.0, 1e-3, -1e-6)
     t_dens = time.perf_counter() - t0
     ms = (t_view * px.sum() / px[v] + t_dens) * 1e3
-    return {"value": round(ms, 1), "unit": "ms/step", "cores": 1, "kind": "oracle",
+    return {"value": round(ms, 1), "unit": "ms/step", "cores": 1, "kind": "oracle", "host_cpu": host_cpu(),
+            "host_nproc": os.cpu_count(),
             "sample": f"view {v} ({int(scene.cams.width[v])}x{int(scene.cams.height[v])}) of {V}, all "
                       f"{scene.n} Gaussians, fwd+bwd+S in {t_view:.1f} s scaled by total/view pixels "
                       f"({px.sum() / px[v]:.2f}x), plus densification of all Gaussians ({t_dens:.1f} s)"}
@@ -248,35 +289,42 @@ def main():
         del pv
         torch.cuda.empty_cache()
 
-    # roofline of the dominant kernel
+    # roofline of the dominant kernel (the raster backward): algorithmic flops
+    # per launch / its event-timed duration, against the published fp32 peak,
+    # with the non-packed ceiling and the measured FMA-loop rate beside it
     n, V, F = scene.n, scene.cams.V, scene.params.shape[0]
     Px = cams.total_pixels
-    dom = max((k for k in stages if k != "sort"), key=lambda k: stages[k])
-    models = {
-        # fp32 flops per examined (pixel, entry) pair and per contributing pair
-        "render_fwd": ("alu", pairs * 15 + contrib * 10),
-        # (the dim-6 backward also sums the third and fourth moments of the
-        # contributing pairs: 4 + 5 more products and sums, about 23 flops)
-        "render_bwd": ("alu", pairs * 15 + contrib * (50 if args.theta_dim == 3 else 73)),
-        # compulsory HBM bytes
-        "project": ("hbm", n * 4 * F + V * n * 52),
-        "proj_bwd": ("hbm", n * 4 * F + V * n * (4 + 36) + n * 4 * F * 2 + n * 24 * 2),
-        "densify": ("hbm", n * 24 + n * 4 * 5),
+    valu = valu_calibration(torch, L, dev)
+    say(f"FMA-loop VALU rate {valu:.1f} TFLOP/s")
+    flops = {
+        "render_fwd": pairs * FLOP_EXAMINED + contrib * FLOP_CONTRIB_FWD,
+        "render_bwd": pairs * FLOP_EXAMINED + contrib * (FLOP_CONTRIB_BWD if args.theta_dim == 3 else FLOP_CONTRIB_BWD6),
     }
-    bound, work = models[dom]
-    t_s = stages[dom] * 1e-3
-    if bound == "hbm":
-        achieved = work / t_s / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None}
-    else:
-        achieved = work / t_s / 1e12
-        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_NONPACKED_TFLOPS, 1),
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4), "traffic": None}
-    # the counter passes profile the default (dim-3) kernels only
-    roof["traffic"] = measured_traffic(dom) if args.theta_dim == 3 else None
-    roof["kernel"] = dom
-    roof["ms"] = round(stages[dom], 4)
+    dom = max(flops, key=lambda k: stages[k])
+    achieved = flops[dom] / (stages[dom] * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+            # the counter passes profile the default (dim-3) kernels only
+            "traffic": measured_traffic(dom) if args.theta_dim == 3 else None,
+            "kernel": dom, "ms": round(stages[dom], 4), "flop_per_launch": flops[dom],
+            "peak_nonpacked": round(PEAK_FP32_NONPACKED_TFLOPS, 1),
+            "frac_nonpacked": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4),
+            "valu_fma_loop_measured": round(valu, 1), "frac_of_measured": round(achieved / valu, 4)}
+    other = [k for k in flops if k != dom][0]
+    roof["other_raster"] = {"kernel": other, "achieved": round(flops[other] / (stages[other] * 1e-3) / 1e12, 3),
+                            "frac": round(flops[other] / (stages[other] * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4)}
+    # HBM fraction of the memory-bound stages: compulsory bytes (each array
+    # read or written once per stage) / event-timed stage duration / 8 TB/s
+    Tt = cams.total_tiles
+    Nv = visible
+    B = {
+        "project": n * 4 * F + Nv * 52,
+        "sort": Nv * 16 + K * 24 + K * 8 + K * 12 + Tt * 8,
+        "proj_bwd": n * 4 * F + Nv * (36 + 52) + n * 4 * F + n * 24 + n * 24,
+        "densify": n * (4 * F + 24) + n * 17 + n_out * 4 * F,
+    }
+    hbm = {k: {"bytes": int(b), "GB/s": round(b / (stages[k] * 1e-3) / 1e9, 1),
+               "frac": round(b / (stages[k] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)} for k, b in B.items()}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -309,6 +357,7 @@ def main():
         "counts": {"instances": K, "visible_pairs": visible, "examined_pairs": pairs, "contributing_pairs": contrib,
                    "n_out": n_out, "loss": round(loss, 6)},
         "roofline": roof,
+        "hbm_frac": hbm,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -352,10 +352,18 @@ steepgs_status steepgs_split_remap(const float* d_src, int32_t rows, int64_t n, 
 #define STEEPGS_TIMER_RENDER_FWD 2 /* forward raster kernel */
 #define STEEPGS_TIMER_RENDER_BWD 3 /* backward raster kernel */
 #define STEEPGS_TIMER_PROJ_BWD 4   /* projection backward + splitting-matrix lift */
-#define STEEPGS_TIMER_DENSIFY 5    /* eigensolve kernel of densification */
+#define STEEPGS_TIMER_DENSIFY 5    /* whole densification stage */
 #define STEEPGS_TIMER_COUNT 6
 steepgs_status steepgs_set_kernel_timer(int32_t which, void* const* start_events, void* const* stop_events,
                                         int32_t count);
+
+/* Measurement support: the achievable fp32 vector-ALU rate.  Launches
+ * `blocks` workgroups of 256 threads; every thread runs 8 independent fp32
+ * fused multiply-add chains for `iters` steps (plain, not packed, FMA: the
+ * instruction mix of the library's kernels) and writes one float to
+ * d_out[blocks * 256].  flops = blocks * 256 * iters * 16.  Errors:
+ * INVALID_ARG for a null d_out or a non-positive size. */
+steepgs_status steepgs_calibrate_valu(float* d_out, int32_t blocks, int32_t iters, void* stream);
 
 const char* steepgs_status_string(steepgs_status s);
 const char* steepgs_version(void);

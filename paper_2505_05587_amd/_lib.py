@@ -76,6 +76,8 @@ def lib():
                                          vp, vp, sz, vp]
         L.steepgs_render_fwd_noalloc.argtypes = [vp, i64, vp, vp, vp, i32, C.POINTER(Opts), i32, i64, vp, vp, vp,
                                                  vp, vp, vp, vp]
+        L.steepgs_calibrate_valu.argtypes = [vp, i32, i32, vp]
+        L.steepgs_calibrate_valu.restype = C.c_int
         L.steepgs_set_kernel_timer.argtypes = [i32, vp, vp, i32]
         L.steepgs_set_kernel_timer.restype = C.c_int
         L.steepgs_render_bwd_split.argtypes = [vp, i64, i32, vp, i32, C.POINTER(Opts), vp, vp, vp, vp, i32, i64,
@@ -170,6 +172,10 @@ def steepgs_render_fwd_noalloc(splats, n, vals, tile_ranges, d_cams, V, opts, to
            lib().steepgs_render_fwd_noalloc(_p(splats), n, _p(vals), _p(tile_ranges), _p(d_cams), V, C.byref(opts),
                                             total_tiles, total_pixels, _p(target), _p(image), _p(T_final),
                                             _p(n_contrib), _p(n_used), _p(loss), _stream(stream)))
+
+
+def steepgs_calibrate_valu(out, blocks, iters, stream=None):
+    _check("steepgs_calibrate_valu", lib().steepgs_calibrate_valu(_p(out), blocks, iters, _stream(stream)))
 
 
 TIMER_PROJECT, TIMER_SORT, TIMER_RENDER_FWD, TIMER_RENDER_BWD, TIMER_PROJ_BWD, TIMER_DENSIFY = range(6)

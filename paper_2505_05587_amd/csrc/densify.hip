@@ -451,7 +451,6 @@ extern "C" steepgs_status steepgs_densify(const float* d_params, int64_t n, int3
   timer_begin(STEEPGS_TIMER_DENSIFY, st);
   hipLaunchKernelGGL(k_densify_eig, dim3(nb), dim3(256), 0, st, d_S, n, s_scale, eps_split, G, g_scale, eps_grad,
                      Gabs, adc_tau, w.lam, w.vmin, w.flag, budget > 0 ? w.key : nullptr);
-  timer_end(STEEPGS_TIMER_DENSIFY, st);
   if (budget > 0) {
     const unsigned hb = (unsigned)std::min<int64_t>(ceil_div(n, 256), 2048);
     hipLaunchKernelGGL(k_select_init, dim3(1), dim3(256), 0, st, w.state, w.hist, budget);
@@ -474,6 +473,7 @@ extern "C" steepgs_status steepgs_densify(const float* d_params, int64_t n, int3
   if (d_lambda_min) hipLaunchKernelGGL(k_copy_f32, dim3(nb), dim3(256), 0, st, w.lam, d_lambda_min, n);
   if (d_vmin) hipLaunchKernelGGL(k_copy_f32, dim3((unsigned)ceil_div(3 * n, 256)), dim3(256), 0, st, w.vmin, d_vmin, 3 * n);
   if (d_split) hipLaunchKernelGGL(k_flag_u8, dim3(nb), dim3(256), 0, st, w.flag, d_split, n);
+  timer_end(STEEPGS_TIMER_DENSIFY, st);
   SG_TRY_LAUNCH();
   return STEEPGS_OK;
 }
@@ -502,7 +502,6 @@ extern "C" steepgs_status steepgs_densify6(const float* d_params, int64_t n, int
   timer_begin(STEEPGS_TIMER_DENSIFY, st);
   hipLaunchKernelGGL(k_densify6_eig, dim3((unsigned)ceil_div(n, 128)), dim3(128), 0, st, d_S6, n, s_scale, eps_split,
                      w.lam, w.vmin, w.flag);
-  timer_end(STEEPGS_TIMER_DENSIFY, st);
   if (exclusive_scan<LoadFlags, uint32_t, uint32_t>(LoadFlags{w.flag}, n, w.before, w.partials, st) != hipSuccess)
     return STEEPGS_ERR_HIP;
   hipLaunchKernelGGL(k_densify_total, dim3(1), dim3(1), 0, st, w.partials + scan_partials_count(n), n, out_capacity,
@@ -513,6 +512,7 @@ extern "C" steepgs_status steepgs_densify6(const float* d_params, int64_t n, int
   if (d_lambda_min) hipLaunchKernelGGL(k_copy_f32, dim3(nb), dim3(256), 0, st, w.lam, d_lambda_min, n);
   if (d_vmin) hipLaunchKernelGGL(k_copy_f32, dim3((unsigned)ceil_div(6 * n, 256)), dim3(256), 0, st, w.vmin, d_vmin, 6 * n);
   if (d_split) hipLaunchKernelGGL(k_flag_u8, dim3(nb), dim3(256), 0, st, w.flag, d_split, n);
+  timer_end(STEEPGS_TIMER_DENSIFY, st);
   SG_TRY_LAUNCH();
   return STEEPGS_OK;
 }
