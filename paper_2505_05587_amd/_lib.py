@@ -13,7 +13,8 @@ import os
 import torch  # loads the HIP runtime the library binds to
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsteepgs.so")
+# STEEPGS_LIB: another build of the same library (A/B timing of build variants)
+LIB_PATH = os.environ.get("STEEPGS_LIB") or os.path.join(_HERE, "libsteepgs.so")
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "output capacity exceeded", 3: "HIP runtime error",
           4: "workspace too small"}

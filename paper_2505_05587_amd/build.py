@@ -27,27 +27,30 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *HIP_FLAGS, "-c", src, "-o", obj]
+def _compile(src, bdir=BUILD, extra=()):
+    obj = os.path.join(bdir, os.path.basename(src) + ".o")
+    cmd = [HIPCC, *HIP_FLAGS, *extra, "-c", src, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{res.stderr}")
     return obj
 
 
-def build_library(jobs: int = 8) -> str:
-    """Compile every HIP source and link the shared library (always rebuilds)."""
-    os.makedirs(BUILD, exist_ok=True)
+def build_library(jobs: int = 8, out: str = LIB, defines=()) -> str:
+    """Compile every HIP source and link the shared library (always rebuilds);
+    `defines` (-D flags) and `out` build a variant elsewhere."""
+    bdir = BUILD if out == LIB else out + ".build"
+    os.makedirs(bdir, exist_ok=True)
+    flags = [f"-D{d}" for d in defines]
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, sources()))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda src: _compile(src, bdir, flags), sources()))
+    tmp = out + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

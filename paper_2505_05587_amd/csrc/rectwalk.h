@@ -70,10 +70,24 @@ SG_DEV uint32_t walk_rect(const steepgs_splat& sp, const steepgs_opts& opt, Rect
   return me.wdt * (uint32_t)(y1 - y0 + 1);
 }
 
-// LDS per wavefront: RectRec[64] + int[64]  (RectRec is 64 bytes)
+// LDS per wavefront: the 64 records field by field (one array per field, so
+// that lanes reading different records hit different banks; a 64-byte record
+// per lane put records two apart on the same banks) and the start table.
 struct RectWalkLds {
-  RectRec rec[64];
+  float mx[64], my[64], a[64], b[64], c[64], ia[64], ic[64], iw[64];
+  uint32_t xy0[64], wdt[64], aoff[64], tag0[64], tag1[64], pad0[64];
   int at[64];
+  SG_DEV void put(int k, const RectRec& r) {
+    mx[k] = r.mx; my[k] = r.my; a[k] = r.a; b[k] = r.b; c[k] = r.c; ia[k] = r.ia; ic[k] = r.ic; iw[k] = r.iw;
+    xy0[k] = r.xy0; wdt[k] = r.wdt; aoff[k] = r.aoff; tag0[k] = r.tag0; tag1[k] = r.tag1; pad0[k] = r.pad0;
+  }
+  SG_DEV RectRec get(int k) const {
+    RectRec r;
+    r.mx = mx[k]; r.my = my[k]; r.a = a[k]; r.b = b[k]; r.c = c[k]; r.ia = ia[k]; r.ic = ic[k]; r.iw = iw[k];
+    r.xy0 = xy0[k]; r.wdt = wdt[k]; r.aoff = aoff[k]; r.tag0 = tag0[k]; r.tag1 = tag1[k]; r.pad0 = pad0[k];
+    r.pad1 = 0u; r.pad2 = 0.f;
+    return r;
+  }
 };
 
 // Sets up a wavefront's walk: the records go to the wavefront's LDS slice,
@@ -93,7 +107,7 @@ SG_DEV uint32_t rect_walk_begin(RectWalkLds& L, int lane, uint32_t area, const R
   me.ia = 1.f / me.a;
   me.ic = 1.f / me.c;
   me.iw = 1.f / (float)me.wdt;
-  L.rec[lane] = me;
+  L.put(lane, me);
   return atotal;
 }
 
@@ -116,27 +130,28 @@ SG_DEV int rect_walk_locate(RectWalkLds& L, int lane, uint32_t area, uint32_t ao
   const uint64_t below = starts & upto;
   const int owner = below ? L.at[63 - __builtin_clzll(below)] : carry;
   carry = __builtin_amdgcn_readlane(owner, 63);
-  const RectRec& R = L.rec[owner];
-  const uint32_t q = j0 + (uint32_t)lane - R.aoff;
+  const uint32_t q = j0 + (uint32_t)lane - L.aoff[owner];
+  const uint32_t wdt = L.wdt[owner], xy0 = L.xy0[owner];
+  const float iw = L.iw[owner];
   // q / width without an integer division: the float quotient is off by at
   // most one for q < 2^24, fixed up exactly below (larger q: integer path)
   int row, col;
   if (q < (1u << 24)) {
-    row = (int)((float)q * R.iw);
-    col = (int)q - row * (int)R.wdt;
+    row = (int)((float)q * iw);
+    col = (int)q - row * (int)wdt;
     if (col < 0) {
       --row;
-      col += (int)R.wdt;
-    } else if (col >= (int)R.wdt) {
+      col += (int)wdt;
+    } else if (col >= (int)wdt) {
       ++row;
-      col -= (int)R.wdt;
+      col -= (int)wdt;
     }
   } else {
-    row = (int)(q / R.wdt);
-    col = (int)(q % R.wdt);
+    row = (int)(q / wdt);
+    col = (int)(q % wdt);
   }
-  tx = (int)(R.xy0 & 0xFFFFu) + col;
-  ty = (int)(R.xy0 >> 16) + row;
+  tx = (int)(xy0 & 0xFFFFu) + col;
+  ty = (int)(xy0 >> 16) + row;
   return owner;
 }
 
@@ -151,7 +166,7 @@ SG_DEV uint32_t rect_walk(RectWalkLds& L, int lane, uint32_t area, const RectRec
   for (uint32_t j0 = 0; j0 < atotal; j0 += 64) {
     int tx, ty;
     const int owner = rect_walk_locate(L, lane, area, aoff, j0, carry, tx, ty);
-    const RectRec& R = L.rec[owner];
+    const RectRec R = L.get(owner);
     const bool hit = j0 + (uint32_t)lane < atotal && tile_hit_rcp(R.mx, R.my, R.a, R.b, R.c, R.ia, R.ic, opt, tx, ty);
     visit(owner, R, tx, ty, hit);
     __builtin_amdgcn_wave_barrier();

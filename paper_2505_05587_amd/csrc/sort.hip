@@ -31,7 +31,10 @@ namespace sg {
 
 constexpr int kRsThreads = 256;
 constexpr int kRsWaves = kRsThreads / 64;
-constexpr int kRsItems = 16;                     // elements per lane per tile
+#ifndef SG_RS_ITEMS
+#define SG_RS_ITEMS 16
+#endif
+constexpr int kRsItems = SG_RS_ITEMS;            // elements per lane per tile
 constexpr int kRsTile = kRsThreads * kRsItems;   // 4096 elements per tile
 constexpr int kRsWaveSpan = 64 * kRsItems;       // contiguous elements per wavefront
 constexpr int kRsGrid = 1024;  // largest grid (sizes the digit-count table)
@@ -61,13 +64,16 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_hist(const uint32_t* __restri
                                                         uint32_t* __restrict__ hist) {
   constexpr int DIG = 1 << BITS;
   // several counter copies per wavefront (by lane), so that lanes holding
-  // equal digits -- common in clustered keys -- rarely update one address
+  // equal digits -- common in clustered keys -- rarely update one address;
+  // each copy's row is one word longer than the digit count, so that equal
+  // digits of different copies fall in different LDS banks
   constexpr int SUB = BITS <= 8 ? 8 : 4;
   constexpr int COPIES = kRsWaves * SUB;
-  __shared__ uint32_t h[COPIES][DIG];
+  constexpr int ROW = DIG + 1;
+  __shared__ uint32_t h[COPIES][ROW];
   const int tid = threadIdx.x, wave = tid >> 6;
   const int copy = wave * SUB + (tid & (SUB - 1));
-  for (int d = tid; d < COPIES * DIG; d += kRsThreads) (&h[0][0])[d] = 0u;
+  for (int d = tid; d < COPIES * ROW; d += kRsThreads) (&h[0][0])[d] = 0u;
   __syncthreads();
   uint64_t b, e;
   rs_range(rs_count(d_count, d_cap), b, e);
@@ -344,7 +350,7 @@ __global__ void __launch_bounds__(256) k_walk(const steepgs_splat* __restrict__ 
     for (uint32_t j0 = 0; j0 < atotal; j0 += 64, ++k) {
       int tx, ty;
       const int owner = rect_walk_locate(L, lane, area, aoff, j0, carry, tx, ty);
-      const RectRec& R = L.rec[owner];
+      const RectRec R = L.get(owner);
       const bool hit = j0 + (uint32_t)lane < atotal && tile_hit_rcp(R.mx, R.my, R.a, R.b, R.c, R.ia, R.ic, opt, tx, ty);
       const uint64_t b = ballot(hit);
       if ((uint32_t)lane == k) mine = b;
@@ -412,7 +418,7 @@ __global__ void __launch_bounds__(256) k_emit(const steepgs_splat* __restrict__ 
     for (uint32_t j0 = 0; j0 < atotal; j0 += 64, ++k) {
       int tx, ty;
       const int owner = rect_walk_locate(L, lane, area, aoff, j0, carry, tx, ty);
-      const RectRec& R = L.rec[owner];
+      const RectRec R = L.get(owner);
       uint64_t b;
       if (k < (uint32_t)kWalkKeep) {
         const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mine, (int)k);
