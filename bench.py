@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--eps", type=float, default=1e-3)
     ap.add_argument("--theta-dim", type=int, choices=(3, 6), default=3,
                     help="splitting matrix over the position (3, the paper's) or position and log-scales (6)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="default launch shape instead of the autotuner's (cached per device and shape class)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration under a profiler)")
     return ap.parse_args()
@@ -231,6 +233,22 @@ def main():
         del src, dst
     P = torch.from_numpy(scene.params).to(dev)
     target = torch.from_numpy(scene.target).to(dev)
+    # tile and launch shape from the autotuner: its cache entry for this
+    # device and shape class, else a tuning pass now (every view in one
+    # launch: the batched step is the measured configuration)
+    launch = {"source": "default"}
+    if not args.no_tune:
+        from paper_2505_05587_amd import autotune as AT
+        key = AT.cache_key(dev, scene.n, scene.cams.V, scene.cams.total_pixels(), scene.sh_degree)
+        tuned = AT.load(key)
+        launch = {"source": f"cache {key}"}
+        if tuned is None or tuned.views_per_launch != scene.cams.V:
+            say(f"tuning the launch shape ({key})")
+            tuned = AT.tune(P, scene.sh_degree, scene.cams, opts, target, eps=args.eps, groups=[scene.cams.V])
+            launch = {"source": "tuned in this run"}
+        opts = tuned.opts(opts)
+        launch.update(tuned.config())
+        say(f"launch shape: {launch}")
     cams = CameraBatch(scene.cams, opts, dev)
 
     step = BatchedStep(P, scene.sh_degree, cams, target, eps=args.eps, eps_split=-1e-6, theta_dim=args.theta_dim)
@@ -348,7 +366,7 @@ def main():
         "config": {"workload": args.workload, "gaussians": n, "views": V, "pixels": Px, "sh_degree": scene.sh_degree,
                    "resolutions": [f"{w}x{h}" for w, h in zip(cams.widths, cams.heights)],
                    "tile": f"{opts['tile_w']}x{opts['tile_h']}", "graph": use_graph, "eps_split": -1e-6,
-                   "theta_dim": args.theta_dim},
+                   "theta_dim": args.theta_dim, "launch": launch},
         "step_ms_p10_p50_p90": [round(float(x), 4) for x in pct],
         "peak_allocated_gib": round(peak_gb, 3),
         "per_view_ms_per_step": None if per_view is None else round(per_view, 4),

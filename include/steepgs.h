@@ -92,7 +92,9 @@ typedef struct {
 } steepgs_camera;
 
 /* Raster conventions (host struct, read at call time).  alpha_min = 0,
- * alpha_max = 1, t_min = 0 gives the cut-off free "smooth" blend.
+ * alpha_max = 1, t_min = 0 gives the cut-off free "smooth" blend; alpha is
+ * capped at 1 - 2^-24 (the largest float below one) even then, so that
+ * 1 - alpha never vanishes for a saturated opacity.
  *   alpha = min(alpha_max, o * exp(-1/2 d^T A d)); entries with alpha < alpha_min
  *   are skipped; a pixel stops before the entry that would take its
  *   transmittance below t_min.
@@ -108,6 +110,12 @@ typedef struct {
   float frustum_guard;
   float alpha_min, alpha_max, t_min;
   float bg[3];
+  /* launch shape of the persistent raster kernels (results do not depend on
+   * it): workgroups per compute unit (0: 8; 1..64) and wavefronts per
+   * workgroup (0: 4; 2, 4 or 8), each wavefront working on a tile of its
+   * own; chosen by the autotuner */
+  int32_t raster_wgs_per_cu;
+  int32_t raster_waves_per_wg;
 } steepgs_opts;
 
 /* Projected record of one (view, Gaussian) pair, 48 bytes.  Index r = v*n + i.

@@ -74,7 +74,11 @@ Opts read_opts(const double* o) {
   r.dilation = o[4];
   r.guard = o[5];
   r.alpha_min = o[6];
-  r.alpha_max = o[7];
+  // alpha stays below one even where alpha_max = 1 (smooth mode): capped at
+  // the largest float below one, 1 - 2^-24, so that 1 - alpha (the
+  // transmittance factor and the divisor of the blend's derivative) never
+  // vanishes for a saturated opacity
+  r.alpha_max = std::min(o[7], 1.0 - std::ldexp(1.0, -24));
   r.t_min = o[8];
   r.bg[0] = o[9];
   r.bg[1] = o[10];

@@ -33,7 +33,7 @@ class Opts(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("near_z", C.c_float),
                 ("radius_sigmas", C.c_float), ("dilation", C.c_float), ("frustum_guard", C.c_float),
                 ("alpha_min", C.c_float), ("alpha_max", C.c_float), ("t_min", C.c_float),
-                ("bg", C.c_float * 3)]
+                ("bg", C.c_float * 3), ("raster_wgs_per_cu", C.c_int32), ("raster_waves_per_wg", C.c_int32)]
 
 
 class SplitSelect(C.Structure):
@@ -129,6 +129,8 @@ def make_opts(d: dict) -> Opts:
     o.frustum_guard, o.alpha_min, o.alpha_max, o.t_min = d["frustum_guard"], d["alpha_min"], d["alpha_max"], d["t_min"]
     for k in range(3):
         o.bg[k] = d["bg"][k]
+    o.raster_wgs_per_cu = int(d.get("raster_wgs_per_cu", 0))
+    o.raster_waves_per_wg = int(d.get("raster_waves_per_wg", 0))
     return o
 
 

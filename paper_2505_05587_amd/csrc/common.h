@@ -29,8 +29,35 @@ inline bool opts_ok(const steepgs_opts* o) {
   if (!o) return false;
   const bool tile_ok = (o->tile_w == 16 && o->tile_h == 16) || (o->tile_w == 16 && o->tile_h == 8) ||
                        (o->tile_w == 8 && o->tile_h == 8);
-  return tile_ok && o->radius_sigmas > 0.f && o->alpha_max > 0.f && o->alpha_max <= 1.f && o->alpha_min >= 0.f &&
-         o->t_min >= 0.f && o->t_min < 1.f && o->near_z > 0.f && o->dilation >= 0.f && o->alpha_max >= o->alpha_min;
+  const bool launch_ok = o->raster_wgs_per_cu >= 0 && o->raster_wgs_per_cu <= 64 &&
+                         (o->raster_waves_per_wg == 0 || o->raster_waves_per_wg == 2 || o->raster_waves_per_wg == 4 ||
+                          o->raster_waves_per_wg == 8);
+  return tile_ok && launch_ok && o->radius_sigmas > 0.f && o->alpha_max > 0.f && o->alpha_max <= 1.f &&
+         o->alpha_min >= 0.f && o->t_min >= 0.f && o->t_min < 1.f && o->near_z > 0.f && o->dilation >= 0.f &&
+         o->alpha_max >= o->alpha_min;
+}
+
+// launch shape of the persistent raster kernels: waves per workgroup and the
+// grid (never more workgroups than tiles need)
+inline int raster_waves(const steepgs_opts& o) { return o.raster_waves_per_wg > 0 ? o.raster_waves_per_wg : 4; }
+int device_cu_count();
+inline int raster_grid(const steepgs_opts& o, int total_tiles) {
+  const int waves = raster_waves(o);
+  const int per_cu = o.raster_wgs_per_cu > 0 ? o.raster_wgs_per_cu : 8;
+  const int64_t need = ((int64_t)total_tiles + waves - 1) / waves;
+  const int64_t cap = (int64_t)device_cu_count() * per_cu;
+  return (int)(need < cap ? need : cap);
+}
+
+// The options as the raster kernels take them: alpha capped at 1 - 2^-24, the
+// largest float below one, even where alpha_max = 1 (smooth mode), so that
+// 1 - alpha never vanishes for a saturated opacity (the blend's factor and the
+// divisor of its derivative).
+inline steepgs_opts raster_opts(const steepgs_opts& o) {
+  steepgs_opts r = o;
+  const float cap = 1.f - 5.9604645e-8f;  // 1 - 2^-24
+  if (r.alpha_max > cap) r.alpha_max = cap;
+  return r;
 }
 
 // compute units of the current device (cached per device id)

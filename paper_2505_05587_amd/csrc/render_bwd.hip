@@ -33,7 +33,6 @@
 
 namespace sg {
 
-constexpr int kBwdWaves = 4;    // wavefronts per workgroup, each on a tile of its own
 // The backward's per-record accumulators (fp64 sums of the per-tile float32
 // partials): slot [m][9] = (m1_x, m1_y, m2_xx, m2_xy, m2_yy, dL/do, dL/dr,
 // dL/dg, dL/db), one 72-byte block per record so that the nine atomics of a
@@ -51,9 +50,10 @@ constexpr int kSlot = 9, kH6 = 9;
 constexpr int kGrad2dOut = 12;
 
 // H6: also the moments the dim-6 splitting matrix needs (third and fourth
-// order in d), summed like the others
-template <int TW, int TH, bool H6>
-__global__ void __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_per_eu(H6 ? 4 : 6))) k_render_bwd(const steepgs_splat* __restrict__ splats,
+// order in d), summed like the others; WAVES wavefronts per workgroup, each
+// on a tile of its own
+template <int TW, int TH, bool H6, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(H6 ? 4 : 6))) k_render_bwd(const steepgs_splat* __restrict__ splats,
                                                                const uint32_t* __restrict__ vals,
                                                                const uint32_t* __restrict__ ranges,
                                                                const steepgs_camera* __restrict__ cams, int V,
@@ -67,9 +67,9 @@ __global__ void __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_pe
                                                                uint32_t* __restrict__ queue) {
   constexpr int NQ = TW * TH / 64;  // 8x8 quadrants of the tile = pixels per lane
   constexpr int QX = TW / 8;
-  __shared__ float4 s_a[kBwdWaves][64];  // mean x, mean y, conic a, conic b
-  __shared__ float4 s_c[kBwdWaves][64];  // conic c, opacity, red, green
-  __shared__ float2 s_e[kBwdWaves][64];  // blue, record id (bits)
+  __shared__ float4 s_a[WAVES][64];  // mean x, mean y, conic a, conic b
+  __shared__ float4 s_c[WAVES][64];  // conic c, opacity, red, green
+  __shared__ float2 s_e[WAVES][64];  // blue, record id (bits)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lx = lane & 7, ly = lane >> 3;
   const int red_idx = reduce9_index(lane);
@@ -201,8 +201,9 @@ __global__ void __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_pe
           if (!cm) continue;
           took |= cm;
           // transmittance in front of this entry, T_i = T_{i+1} / (1 - alpha_i),
-          // with the hardware reciprocal (within 1 ulp); alpha <= alpha_max < 1
-          // on every lane, so the lanes that do not take the entry stay finite
+          // with the hardware reciprocal (within 1 ulp); alpha <= 1 - 2^-24 on
+          // every lane (the host caps alpha_max below one), so the lanes that
+          // do not take the entry stay finite
           const float inv_om = __builtin_amdgcn_rcpf(1.f - alpha);
           const float Ti = T[q] * inv_om;
           // g = dL/dalpha_i = sum_c dL/dC_c (c_c T_i - R_c / (1 - alpha_i))
@@ -811,8 +812,12 @@ static void launch_bwd(int grid, hipStream_t st, const steepgs_splat* splats, co
                        const uint32_t* ranges, const steepgs_camera* cams, int V, const steepgs_opts& opt,
                        int total_tiles, const float* image, const float* T_final, const uint32_t* n_contrib,
                        const float* dL_dimage, const float* target, Slots g2d, int64_t m, uint32_t* queue) {
-  hipLaunchKernelGGL((k_render_bwd<TW, TH, H6>), dim3(grid), dim3(64 * kBwdWaves), 0, st, splats, vals, ranges, cams, V, opt,
-                     total_tiles, image, T_final, n_contrib, dL_dimage, target, g2d, m, queue);
+#define SG_BWD(WAVES)                                                                                              \
+  hipLaunchKernelGGL((k_render_bwd<TW, TH, H6, WAVES>), dim3(grid), dim3(64 * WAVES), 0, st, splats, vals, ranges,  \
+                     cams, V, opt, total_tiles, image, T_final, n_contrib, dL_dimage, target, g2d, m, queue)
+  const int w = raster_waves(opt);
+  if (w == 2) SG_BWD(2); else if (w == 8) SG_BWD(8); else SG_BWD(4);
+#undef SG_BWD
 }
 
 }  // namespace sg
@@ -843,8 +848,8 @@ static steepgs_status bwd_impl(const float* d_params, int64_t n, int32_t sh_degr
   hipStream_t st = as_stream(stream);
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, reinterpret_cast<float*>(queue), (int64_t)1);
   hipLaunchKernelGGL(k_zero64, dim3(stride_grid(per_record * m, 256)), dim3(256), 0, st, g2d.slot, per_record * m);
-  const int grid = (int)std::min<int64_t>(ceil_div(total_tiles, kBwdWaves), (int64_t)device_cu_count() * 8);
-  const steepgs_opts& o = *opts;
+  const steepgs_opts o = raster_opts(*opts);
+  const int grid = raster_grid(o, total_tiles);
   timer_begin(STEEPGS_TIMER_RENDER_BWD, st);
 #define SG_LAUNCH_BWD(TW, TH)                                                                                        \
   (h6 ? launch_bwd<TW, TH, true>(grid, st, d_splats, d_vals, d_tile_ranges, d_cams, V, o, total_tiles, d_image,       \

@@ -17,11 +17,10 @@
 
 namespace sg {
 
-constexpr int kFwdWaves = 4;  // wavefronts per workgroup, each on a tile of its own
-
-// COUNT: also count each pixel's contributors (the optional n_used output)
-template <int TW, int TH, bool COUNT>
-__global__ void __launch_bounds__(64 * kFwdWaves) __attribute__((amdgpu_waves_per_eu(7))) k_render_fwd(const steepgs_splat* __restrict__ splats,
+// COUNT: also count each pixel's contributors (the optional n_used output);
+// WAVES wavefronts per workgroup, each on a tile of its own
+template <int TW, int TH, bool COUNT, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(7))) k_render_fwd(const steepgs_splat* __restrict__ splats,
                                                                const uint32_t* __restrict__ vals,
                                                                const uint32_t* __restrict__ ranges,
                                                                const steepgs_camera* __restrict__ cams, int V,
@@ -33,9 +32,9 @@ __global__ void __launch_bounds__(64 * kFwdWaves) __attribute__((amdgpu_waves_pe
                                                                uint32_t* __restrict__ queue) {
   constexpr int NQ = TW * TH / 64;  // 8x8 quadrants of the tile = pixels per lane
   constexpr int QX = TW / 8;
-  __shared__ float4 s_a[kFwdWaves][64];  // mean x, mean y, conic a, conic b
-  __shared__ float4 s_c[kFwdWaves][64];  // conic c, opacity, red, green
-  __shared__ float s_b[kFwdWaves][64];   // blue
+  __shared__ float4 s_a[WAVES][64];  // mean x, mean y, conic a, conic b
+  __shared__ float4 s_c[WAVES][64];  // conic c, opacity, red, green
+  __shared__ float s_b[WAVES][64];   // blue
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lx = lane & 7, ly = lane >> 3;
   float4* const A = s_a[wave];
@@ -181,17 +180,30 @@ __global__ void k_zero_u32(uint32_t* __restrict__ p, int64_t count) {
 
 size_t render_fwd_workspace() { return 256; }
 
+template <int TW, int TH, bool COUNT, int WAVES>
+static void launch_fwd1(int grid, hipStream_t st, const steepgs_splat* splats, const uint32_t* vals,
+                        const uint32_t* ranges, const steepgs_camera* cams, int V, const steepgs_opts& opt,
+                        int total_tiles, const float* target, float* image, float* T_final, uint32_t* n_contrib,
+                        uint32_t* n_used, float* loss, uint32_t* queue) {
+  hipLaunchKernelGGL((k_render_fwd<TW, TH, COUNT, WAVES>), dim3(grid), dim3(64 * WAVES), 0, st, splats, vals, ranges,
+                     cams, V, opt, total_tiles, target, image, T_final, n_contrib, n_used, loss, queue);
+}
+
 template <int TW, int TH>
 static void launch_fwd(int grid, hipStream_t st, const steepgs_splat* splats, const uint32_t* vals,
                        const uint32_t* ranges, const steepgs_camera* cams, int V, const steepgs_opts& opt,
                        int total_tiles, const float* target, float* image, float* T_final, uint32_t* n_contrib,
                        uint32_t* n_used, float* loss, uint32_t* queue) {
-  if (n_used)
-    hipLaunchKernelGGL((k_render_fwd<TW, TH, true>), dim3(grid), dim3(64 * kFwdWaves), 0, st, splats, vals, ranges, cams,
-                       V, opt, total_tiles, target, image, T_final, n_contrib, n_used, loss, queue);
-  else
-    hipLaunchKernelGGL((k_render_fwd<TW, TH, false>), dim3(grid), dim3(64 * kFwdWaves), 0, st, splats, vals, ranges,
-                       cams, V, opt, total_tiles, target, image, T_final, n_contrib, n_used, loss, queue);
+#define SG_FWD(COUNT, WAVES)                                                                                       \
+  launch_fwd1<TW, TH, COUNT, WAVES>(grid, st, splats, vals, ranges, cams, V, opt, total_tiles, target, image,     \
+                                    T_final, n_contrib, n_used, loss, queue)
+  const int w = raster_waves(opt);
+  if (n_used) {
+    if (w == 2) SG_FWD(true, 2); else if (w == 8) SG_FWD(true, 8); else SG_FWD(true, 4);
+  } else {
+    if (w == 2) SG_FWD(false, 2); else if (w == 8) SG_FWD(false, 8); else SG_FWD(false, 4);
+  }
+#undef SG_FWD
 }
 
 }  // namespace sg
@@ -216,7 +228,7 @@ static steepgs_status fwd_launch(const steepgs_splat* d_splats, const uint32_t* 
                                  uint32_t* d_n_used, float* d_loss, uint32_t* queue, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, queue, (int64_t)1);
   if (d_target) hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)ceil_div(V, 64)), dim3(64), 0, st, d_loss, (int64_t)V);
-  const int grid = (int)std::min<int64_t>(ceil_div(total_tiles, kFwdWaves), (int64_t)device_cu_count() * 8);
+  const int grid = raster_grid(o, total_tiles);
   timer_begin(STEEPGS_TIMER_RENDER_FWD, st);
   if (o.tile_w == 16 && o.tile_h == 16)
     launch_fwd<16, 16>(grid, st, d_splats, d_vals, d_tile_ranges, d_cams, V, o, total_tiles, d_target, d_image,
@@ -243,8 +255,8 @@ extern "C" steepgs_status steepgs_render_fwd(const steepgs_splat* d_splats, int6
                                        d_image, d_T_final, d_n_contrib, d_loss);
   if (chk != STEEPGS_OK) return chk;
   if (!d_ws || ws_bytes < render_fwd_workspace()) return STEEPGS_ERR_WORKSPACE;
-  return fwd_launch(d_splats, d_vals, d_tile_ranges, d_cams, V, *opts, total_tiles, d_target, d_image, d_T_final,
-                    d_n_contrib, d_n_used, d_loss, static_cast<uint32_t*>(d_ws), as_stream(stream));
+  return fwd_launch(d_splats, d_vals, d_tile_ranges, d_cams, V, raster_opts(*opts), total_tiles, d_target, d_image,
+                    d_T_final, d_n_contrib, d_n_used, d_loss, static_cast<uint32_t*>(d_ws), as_stream(stream));
 }
 
 // ---------------------------------------------------------------------------
@@ -292,6 +304,6 @@ extern "C" steepgs_status steepgs_render_fwd_noalloc(const steepgs_splat* d_spla
   uint32_t* queue = nullptr;
   const steepgs_status st = noalloc_scratch(&queue);
   if (st != STEEPGS_OK) return st;
-  return fwd_launch(d_splats, d_vals, d_tile_ranges, d_cams, V, *opts, total_tiles, d_target, d_image, d_T_final,
-                    d_n_contrib, d_n_used, d_loss, queue, as_stream(stream));
+  return fwd_launch(d_splats, d_vals, d_tile_ranges, d_cams, V, raster_opts(*opts), total_tiles, d_target, d_image,
+                    d_T_final, d_n_contrib, d_n_used, d_loss, queue, as_stream(stream));
 }

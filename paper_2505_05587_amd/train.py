@@ -96,11 +96,18 @@ class SteepGSTrainer:
                             G=self.G, Gabs=self.Gabs if self.adc_tau > 0 else None)
         self.acc_steps += 1
 
+    def window_scale(self) -> float:
+        """1 / (accumulated steps x views): a step's loss sums the V per-view
+        means, each view one image of Algorithm 1's gradient steps, so S, G and
+        the gradient-norm sum average over images as the algorithm's interval
+        average does, and eps_split applies per image."""
+        return 1.0 / (max(self.acc_steps, 1) * self.cams.V)
+
     def densify_step(self):
         n = self.n
-        k = max(self.acc_steps, 1)
-        out = densify(self.params, self.sh_degree, self.S, 1.0 / k, self.eps, self.eps_split,
-                      G=self.G if self.eps_grad > 0 else None, g_scale=1.0 / k, eps_grad=self.eps_grad,
+        sc = self.window_scale()
+        out = densify(self.params, self.sh_degree, self.S, sc, self.eps, self.eps_split,
+                      G=self.G if self.eps_grad > 0 else None, g_scale=sc, eps_grad=self.eps_grad,
                       budget=self.budget, Gabs=self.Gabs if self.adc_tau > 0 else None, adc_tau=self.adc_tau)
         if out["status"] != L.OK:
             raise RuntimeError("densification output capacity exceeded")

@@ -31,7 +31,7 @@ def test_header_symbols_exported():
 
 def test_struct_sizes_match_header():
     assert C.sizeof(L.Camera) == 96
-    assert C.sizeof(L.Opts) == 48
+    assert C.sizeof(L.Opts) == 56
     assert C.sizeof(L.SplitSelect) == 40
 
 

@@ -259,3 +259,16 @@ def test_backward_bitwise_repeatable(kind):
     for g, s in outs[1:]:
         np.testing.assert_array_equal(g, outs[0][0])
         np.testing.assert_array_equal(s, outs[0][1])
+
+
+def test_saturated_opacity(oracle):
+    # an opacity logit of 40 in smooth mode (alpha_max = 1): alpha is capped
+    # below one on both sides, gradients and S finite and at the bars
+    from tests.test_oracle_blend import saturated_scene
+    P, cams, target = saturated_scene()
+    opts = scenes.opts("smooth")
+    print("\n[case] saturated opacity", flush=True)
+    g = run_gpu(P, 0, cams, opts, target=target)
+    assert np.isfinite(g["grads"]).all() and np.isfinite(g["S6"]).all()
+    vref = checked_reference(oracle, P, 0, cams, opts, g, target=target)
+    check_against(g, vref, cams, "saturated")

@@ -85,24 +85,26 @@ def test_training_loop_follows_oracle(oracle, eps_grad, budget, adc):
     G32 = tr.G.cpu().numpy()
     Gabs32 = tr.Gabs.cpu().numpy()
     tau = 0.0
+    sc = 1.0 / (k * s.cams.V)  # the window average per image
+    assert sc == tr.window_scale()
     if adc:
-        lam_pre = oracle.densify(tr.params.cpu().numpy(), s.sh_degree, S9, 1.0 / k, 0.01, -1e-6)["lambda_min"]
+        lam_pre = oracle.densify(tr.params.cpu().numpy(), s.sh_degree, S9, sc, 0.01, -1e-6)["lambda_min"]
         cand = (lam_pre < -1e-6) & ~amb_any
-        tau = float(np.median(Gabs32[cand].astype(np.float64) / k))
+        tau = float(np.median(Gabs32[cand].astype(np.float64) * sc))
         tr.adc_tau = tau
     m_old, v_old = _np(tr.m), _np(tr.v)
     theta = tr.params.cpu().numpy()
     out = tr.iterate()
     torch.cuda.synchronize()
     assert out is not None and tr.history and tr.history[-1].accumulated_steps == k
-    dref = oracle.densify(theta, s.sh_degree, S9, 1.0 / k, 0.01, -1e-6, G=G32 if eps_grad > 0 else None,
-                          g_scale=1.0 / k, eps_grad=eps_grad, budget=budget, Gabs=Gabs32 if adc else None,
+    dref = oracle.densify(theta, s.sh_degree, S9, sc, 0.01, -1e-6, G=G32 if eps_grad > 0 else None,
+                          g_scale=sc, eps_grad=eps_grad, budget=budget, Gabs=Gabs32 if adc else None,
                           adc_tau=tau)
     split = out["split"].cpu().numpy().astype(bool)
-    Sn = np.linalg.norm(S9, axis=0) / k
+    Sn = np.linalg.norm(S9, axis=0) * sc
     sure = np.abs(dref["lambda_min"] + 1e-6) > 1e-4 * Sn
     if adc:
-        sure &= np.abs(Gabs32.astype(np.float64) / k - tau) > 1e-6 * tau
+        sure &= np.abs(Gabs32.astype(np.float64) * sc - tau) > 1e-6 * tau
         assert 0 < dref["split"].sum() < (dref["lambda_min"] < -1e-6).sum()
     if budget and dref["split"].sum() == budget:
         thr = np.sort(dref["lambda_min"][dref["split"]])[-1]

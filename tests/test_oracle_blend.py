@@ -143,3 +143,33 @@ def test_sampled_pixels_match_full_render(oracle):
     img = full["image"].reshape(3, -1)
     np.testing.assert_array_equal(rgb, img[:, pix].T)
     np.testing.assert_array_equal(T, full["T_final"][pix])
+
+
+def saturated_scene():
+    """two Gaussians on an orthographic 32x32 view, the front one with an
+    opacity logit of 40 (sigmoid rounds to one in float32 and to within 1e-17
+    of it in fp64)"""
+    from tests.helpers import pack_params
+    P = pack_params([[0.0, 0.0, 0.3], [0.1, -0.05, 0.0]], [[-1.2, -1.3, -1.4], [-1.0, -1.1, -1.2]],
+                    [[1.0, 0.0, 0.0, 0.0], [0.9, 0.1, 0.2, -0.1]], [40.0, 0.5],
+                    [[0.3, 0.2, 0.1], [0.1, 0.4, -0.2]], 0)
+    cams = ortho_camera(32, scale=10.0)
+    target = scenes.uniform_target(np.random.default_rng(5), cams)
+    return P, cams, target
+
+
+def test_saturated_opacity_stays_finite(oracle):
+    # smooth mode (alpha_max = 1): alpha is capped at 1 - 2^-24, so the
+    # transmittance behind a saturated Gaussian and the blend's derivative,
+    # which divides by 1 - alpha, stay finite; the capped alpha is constant,
+    # so such pixels add nothing to its mean, conic and opacity gradients
+    P, cams, target = saturated_scene()
+    opts = scenes.opts("smooth")
+    ref = oracle.forward_backward(P, 0, cams, opts, target)
+    assert np.isfinite(ref["image"]).all() and np.isfinite(ref["grads"]).all() and np.isfinite(ref["S"]).all()
+    assert 0.0 < ref["T_final"].min() < 1e-6  # the centre is saturated, and light still passes
+    # the cap is the clamp of Eq. (alpha_blend) at 1 - 2^-24: the same image as
+    # an explicit alpha_max of that value
+    ref2 = oracle.forward_backward(P, 0, cams, dict(opts, alpha_max=1.0 - 2.0 ** -24), target)
+    np.testing.assert_array_equal(ref["image"], ref2["image"])
+    np.testing.assert_array_equal(ref["grads"], ref2["grads"])
