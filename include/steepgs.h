@@ -118,20 +118,36 @@ typedef struct {
   int32_t raster_waves_per_wg;
 } steepgs_opts;
 
-/* Projected record of one (view, Gaussian) pair, 48 bytes.  Index r = v*n + i.
+/* Projected record of one (view, Gaussian) pair, 64 bytes.  Index r = v*n + i.
+ * mean = the projected mean rounded to float32; mean_lo packs what that
+ * rounding dropped, mean_x_exact - mean_x in the low 16 bits and
+ * mean_y_exact - mean_y in the high 16 bits, each an IEEE binary16 (the
+ * blend evaluates pixel offsets from the mean to ~2^-24 of the offset rather
+ * than of the pixel coordinate).  The depth of a record is not stored here:
+ * steepgs_project writes it to the depth-key array.
  * conic = (a, b, c) with A = [[a, b], [b, c]] = Pi(Sigma)^-1.  rect packs the
  * inclusive tile rectangle: rect_lo = x0 | y0 << 16, rect_hi = x1 | y1 << 16.
  * A pair is culled when tiles_touched is 0; a pair culled by the projection
  * itself (near plane, degenerate conic, empty rectangle) also has opacity 0.
  * The fields the footprint walk reads (mean, conic, opacity, rect) come first,
- * in one 32-byte block: the instance emission gathers records in depth order. */
+ * in one 32-byte block: the instance emission gathers records in depth order.
+ * The last block is the conic in eigen form, from which the blend evaluates
+ * alpha: (axis_x, axis_y) the unit long axis of the footprint ellipse,
+ * e_long, e_short = -log2(e)/2 times the conic's eigenvalues along the long
+ * and the short axis, so that -1/2 d^T A d = ln 2 * (e_long (axis . d)^2 +
+ * e_short (axis_perp . d)^2), axis_perp = (-axis_y, axis_x).  (A sum of two
+ * non-negative terms: in float32 its error grows with the square root of the
+ * ellipse's aspect ratio, not with the aspect ratio as a, b, c's terms do.)
+ * All computed in fp64 from Pi(Sigma) and rounded once. */
 typedef struct {
   float mean_x, mean_y;
   float conic_a, conic_b;
   float conic_c, opacity;
   uint32_t rect_lo, rect_hi;
   float rgb[3];
-  float depth; /* camera-space z */
+  uint32_t mean_lo; /* binary16 remainders of the mean, x | y << 16 */
+  float axis_x, axis_y;
+  float e_long, e_short;
 } steepgs_splat;
 
 /* Fill tiles_x/tiles_y/tile_offset/pixel_offset of V host cameras for the
@@ -152,9 +168,9 @@ size_t steepgs_workspace_size(int32_t stage, int64_t n, int32_t V, uint64_t capa
  *      count is an output of steepgs_sort), 0 if culled.  Discrete outcomes
  *      (culling, rectangle, depth) are computed in fp64 in a fixed operation
  *      order.
- *      d_depth_keys (nullable) [V*n]: the keys of steepgs_sort's depth order,
- *      the float bits of each record's depth, 0xFFFFFFFF for a culled one
- *      (pass them to steepgs_sort, which need not form them again). */
+ *      d_depth_keys [V*n]: the keys of steepgs_sort's depth order, the
+ *      float bits of each record's camera-space depth (rounded once from
+ *      fp64), 0xFFFFFFFF for a culled record (steepgs_sort takes them). */
 steepgs_status steepgs_project(const float* d_params, int64_t n, int32_t sh_degree, const steepgs_camera* d_cams,
                                int32_t V, const steepgs_opts* opts, steepgs_splat* d_splats,
                                uint32_t* d_tiles_touched, uint32_t* d_depth_keys, void* stream);
@@ -172,9 +188,8 @@ steepgs_status steepgs_project(const float* d_params, int64_t n, int32_t sh_degr
  *      *d_num_instances holds K and the outputs other than d_counts are not
  *      written.  *d_status is set to 0 otherwise.
  * d_tiles_touched [V*n]: as steepgs_project wrote it (0: culled).
- * d_depth_keys (nullable) [V*n]: the depth keys steepgs_project wrote for
- *      these same records; when null they are formed here from d_splats and
- *      d_tiles_touched (same result, one more pass over the records). */
+ * d_depth_keys [V*n]: the depth keys steepgs_project wrote for these same
+ *      records (required; read only). */
 steepgs_status steepgs_sort(const steepgs_splat* d_splats, const uint32_t* d_tiles_touched,
                             const uint32_t* d_depth_keys, int64_t n, int32_t V,
                             const steepgs_camera* d_cams, const steepgs_opts* opts, int32_t total_tiles,

@@ -640,12 +640,19 @@ struct Pixel {
 constexpr double kAlphaBand = 1e-5;  // relative band around alpha_min / alpha_max
 constexpr double kQBand = 1e-5;      // relative band around the footprint cut-off radius_sigmas^2
 constexpr double kTBand = 5e-5;      // relative band around t_min (fp32 transmittance after ~400 factors)
-// A float32 evaluation of q = d^T A d on float32 record values is only good to
-// about 2^-24 of the magnitude of its terms, |A00| dx^2 + 2|A01 dx dy| + |A11| dy^2,
-// which exceeds q by orders of magnitude for a thin Gaussian seen far along its
-// long axis.  The bands widen with that bound, and a pair whose alpha error
-// (alpha * bound / 2) can move the colour by more than kAlphaValue marks its
-// pixel as well.
+// A float32 evaluation of q = d^T A d as a sum of two non-negative terms
+// along the footprint ellipse's axes (lambda_1 (e_1 . d)^2 + lambda_2
+// (e_2 . d)^2, from float32 axes and eigenvalues) is good to about
+// 2^-24 (3 q + 2 sqrt(lambda_max q) e_d) when the projections of d on the
+// axes are known to 2^-24 e_d: the larger eigenvalue weighs a change of the
+// projections by sqrt(lambda_max q).  The offsets are taken from the float32
+// mean, the remainder of its rounding (stored as binary16) folded into the
+// projections: e_d = 5 |d| + 2^-11 |mean| + 1/2 covers the float32 roundings
+// of the offsets, the axes and the projections, and the remainder's binary16
+// rounding.  For a thin Gaussian seen far along its long axis this exceeds
+// 2^-24 q by the square root of the ellipse's aspect ratio.  The bands widen
+// with that bound, and a pair whose alpha error (alpha * bound / 2) can move
+// the colour by more than kAlphaValue marks its pixel as well.
 constexpr double kAlphaValue = 1e-5;
 
 // Blend one pixel (Eq. alpha_blend, front to back).  flip >= 0 takes the
@@ -678,9 +685,11 @@ void blend_pixel(const View& view, int u, int v, Pixel& px, int flip = -1) {
     // footprint: only pixels within radius_sigmas (Mahalanobis) of the mean
     double dxu = u - g.mx, dyv = v - g.my;
     double q = g.A00 * dxu * dxu + 2.0 * g.A01 * dxu * dyv + g.A11 * dyv * dyv;
-    const double terms =
-        std::fabs(g.A00) * dxu * dxu + 2.0 * std::fabs(g.A01 * dxu * dyv) + std::fabs(g.A11) * dyv * dyv;
-    const double eq = std::ldexp(terms, -23);  // float32 bound on q, with a factor 2 of margin
+    const double lmax = 0.5 * (g.A00 + g.A11) + std::sqrt(0.25 * (g.A00 - g.A11) * (g.A00 - g.A11) + g.A01 * g.A01);
+    const double e_d = 5.0 * std::sqrt(dxu * dxu + dyv * dyv) + std::ldexp(std::sqrt(g.mx * g.mx + g.my * g.my), -11) +
+                       0.5;
+    const double err = std::ldexp(3.0 * std::fabs(q) + 2.0 * std::sqrt(lmax * std::max(q, 0.0)) * e_d, -24);
+    const double eq = 2.0 * err;  // float32 bound on q, with a factor 2 of margin
     bool outside = q > k2;
     if (std::fabs(q - k2) <= std::max(kQBand * k2, eq) && decide(kDecFootprint, lst[j])) outside = !outside;
     if (outside) continue;
@@ -697,7 +706,7 @@ void blend_pixel(const View& view, int u, int v, Pixel& px, int flip = -1) {
       skip = !skip;
     // an alpha error da moves the colour by T da (c_i - mean colour behind
     // the entry, background included): at most T da for colours in [0, 1]
-    if (!skip && T * a * std::ldexp(terms, -25) > kAlphaValue) {
+    if (!skip && T * a * 0.5 * err > kAlphaValue) {
       px.valunc = true;
       px.ambig = true;
       px.amb_ids.push_back(lst[j]);
@@ -1170,7 +1179,8 @@ int orc_forward_backward(const float* params, int64_t n, int deg, const float* c
 // sgnv[3k+c] is -1, 0 or 1, or (2) the sign of C_c - target_c of the
 // variant's own colour; with dLdimage (packed image layout) dL/dC comes from
 // there instead.  Out: rgb [nv][3], T_final [nv], used [nv] (entries
-// blended), ndec [nv], and the Gaussians whose gradient or S the pixel
+// blended), ndec [nv], valunc [nv] (nullable: an entry's alpha uncertain in
+// float32 beyond kAlphaValue), and the Gaussians whose gradient or S the pixel
 // changes, in CSR form: count [nv]; with gid != nullptr also gid [sum count]
 // (Gaussian index), grad [sum count][F], S [sum count][9] (the pixel's term
 // of Theorem 1's sum, lifted with the Gaussian's own Jacobian) and, when
@@ -1179,19 +1189,19 @@ int orc_forward_backward(const float* params, int64_t n, int deg, const float* c
 int orc_pixel_variants(const float* params, int64_t n, int deg, const float* cam_f, const int32_t* cam_i, int V,
                        const double* opts, const float* target, const double* dLdimage, int64_t nv,
                        const int64_t* pix, const int32_t* flip, const int32_t* sgnv, double* rgb, double* T_final,
-                       int32_t* used, int32_t* ndec, int64_t* count, int64_t* gid, double* grad, double* S,
-                       double* S6) {
+                       int32_t* used, int32_t* ndec, uint8_t* valunc, int64_t* count, int64_t* gid, double* grad,
+                       double* S, double* S6) {
   if (n < 0 || V <= 0 || deg < 0 || deg > 3 || (!target && !dLdimage)) return 1;
   Opts opt = read_opts(opts);
   std::vector<Cam> cams = read_cams(cam_f, cam_i, V, opt);
   const int F = num_params(deg);
-  int64_t cursor = 0;
   std::vector<int64_t> start(nv + 1, 0);
   if (gid) {
     for (int64_t k = 0; k < nv; ++k) start[k + 1] = start[k] + count[k];
   }
-  std::vector<Grad2D> acc(n);
-  for (auto& a : acc) std::memset(&a, 0, sizeof(a));
+  // views are independent (every variant belongs to one view and writes only
+  // its own outputs): processed on their own, in parallel with OpenMP
+#pragma omp parallel for schedule(dynamic, 1)
   for (int v = 0; v < V; ++v) {
     const Cam& cam = cams[v];
     bool any = false;
@@ -1200,6 +1210,8 @@ int orc_pixel_variants(const float* params, int64_t n, int deg, const float* cam
     if (!any) continue;
     View view;
     build_view(params, n, deg, cam, opt, view);
+    std::vector<Grad2D> acc(n);
+    for (auto& a : acc) std::memset(&a, 0, sizeof(a));
     const double inv = 1.0 / (3.0 * cam.W * cam.H);
     Pixel px;
     for (int64_t k = 0; k < nv; ++k) {
@@ -1211,6 +1223,7 @@ int orc_pixel_variants(const float* params, int64_t n, int deg, const float* cam
       T_final[k] = px.T_final;
       used[k] = (int32_t)px.list.size();
       ndec[k] = px.ndec;
+      if (valunc) valunc[k] = px.valunc ? 1 : 0;
       double dLdC[3];
       for (int ch = 0; ch < 3; ++ch) {
         const int64_t e = 3 * cam.pixel_offset + (int64_t)ch * cam.W * cam.H + (int64_t)y * cam.W + x;
@@ -1235,10 +1248,8 @@ int orc_pixel_variants(const float* params, int64_t n, int deg, const float* cam
       }
       for (const Contrib& ct : px.list) std::memset(&acc[ct.g], 0, sizeof(Grad2D));
       if (!gid) count[k] = c;
-      cursor += c;
     }
   }
-  (void)cursor;
   return 0;
 }
 
@@ -1347,21 +1358,27 @@ int orc_render_pixels(const float* params, int64_t n, int deg, const float* cam_
 // Gradients and splitting matrices of sampled Gaussians only: every pixel of
 // every tile the sampled Gaussian touches is blended in full, its L1
 // gradient formed, and the reverse sweep credited to the sampled Gaussians.
-// grads [ns][F], S [ns][9], ambig [ns].
+// grads [ns][F], S [ns][9], ambig [ns]; flagged (nullable, capacity
+// flag_cap): the global ids of the pixels with an in-band decision, an
+// uncertain alpha or an L1 sign within sign_band of zero that touch a sampled
+// Gaussian, their number in *nflagged (returns 2 when they do not fit).
 int orc_grads_sampled(const float* params, int64_t n, int deg, const float* cam_f, const int32_t* cam_i, int V,
                       const double* opts, const float* target, double sign_band, const int64_t* gids, int64_t ns,
-                      double* grads, double* S, uint8_t* ambig) {
+                      double* grads, double* S, uint8_t* ambig, int64_t* flagged, int64_t flag_cap,
+                      int64_t* nflagged) {
   Opts opt = read_opts(opts);
   std::vector<Cam> cams = read_cams(cam_f, cam_i, V, opt);
   int F = num_params(deg);
   std::vector<uint8_t> want(n, 0);
   for (int64_t k = 0; k < ns; ++k) want[gids[k]] = 1;
-  for (int64_t k = 0; k < ns; ++k) {
-    ambig[k] = 0;
-    for (int f = 0; f < F; ++f) grads[k * F + f] = 0.0;
-    for (int q = 0; q < 9; ++q) S[k * 9 + q] = 0.0;
-  }
-  std::vector<uint8_t> gamb(n, 0);
+  // views are independent: each is processed on its own (in parallel when
+  // the library is built with OpenMP) into its own buffers, and the buffers
+  // are summed in view order afterwards, so the result does not depend on
+  // the number of threads
+  std::vector<std::vector<double>> vg(V, std::vector<double>(ns * F, 0.0)), vS(V, std::vector<double>(ns * 9, 0.0));
+  std::vector<std::vector<int64_t>> vflag(V);
+  std::vector<std::vector<uint8_t>> vamb(V);
+#pragma omp parallel for schedule(dynamic, 1)
   for (int v = 0; v < V; ++v) {
     const Cam& cam = cams[v];
     View view;
@@ -1375,6 +1392,7 @@ int orc_grads_sampled(const float* params, int64_t n, int deg, const float* cam_
     }
     std::vector<Grad2D> acc(n);
     for (auto& a : acc) std::memset(&a, 0, sizeof(a));
+    std::vector<uint8_t> gamb(n, 0);
     double inv = 1.0 / (3.0 * cam.W * cam.H);
     Pixel px;
     for (int ty = 0; ty < cam.tiles_y; ++ty)
@@ -1391,18 +1409,41 @@ int orc_grads_sampled(const float* params, int64_t n, int deg, const float* cam_
               dLdC[ch] = sgn(diff) * inv;
               if (std::fabs(diff) < sign_band) amb = true;
             }
-            if (amb) mark_affected(px, gamb.data());
+            if (amb) {
+              mark_affected(px, gamb.data());
+              bool touches = false;
+              for (const Contrib& c : px.list) touches |= want[c.g] != 0;
+              for (int g : px.amb_ids) touches |= want[g] != 0;
+              if (touches) vflag[v].push_back(cam.pixel_offset + (int64_t)y * cam.W + x);
+            }
             backward_pixel(view, x, y, px, dLdC, acc, &want);
           }
       }
     for (int64_t k = 0; k < ns; ++k) {
       int64_t i = gids[k];
       if (!view.rec[i].visible) continue;
-      lift(params, n, deg, i, cam, opt, acc[i], grads + k * F, 1, S + k * 9, 1);
+      lift(params, n, deg, i, cam, opt, acc[i], vg[v].data() + k * F, 1, vS[v].data() + k * 9, 1);
+    }
+    vamb[v].assign(ns, 0);
+    for (int64_t k = 0; k < ns; ++k) vamb[v][k] = gamb[gids[k]];
+  }
+  for (int64_t k = 0; k < ns; ++k) {
+    ambig[k] = 0;
+    for (int f = 0; f < F; ++f) grads[k * F + f] = 0.0;
+    for (int q = 0; q < 9; ++q) S[k * 9 + q] = 0.0;
+  }
+  int64_t nf = 0;
+  for (int v = 0; v < V; ++v) {
+    for (int64_t k = 0; k < ns * F; ++k) grads[k] += vg[v][k];
+    for (int64_t k = 0; k < ns * 9; ++k) S[k] += vS[v][k];
+    for (int64_t k = 0; k < ns; ++k) ambig[k] |= vamb[v][k];
+    for (int64_t p : vflag[v]) {
+      if (flagged && nf < flag_cap) flagged[nf] = p;
+      ++nf;
     }
   }
-  for (int64_t k = 0; k < ns; ++k) ambig[k] = gamb[gids[k]];
-  return 0;
+  if (nflagged) *nflagged = nf;
+  return (nflagged && nf > flag_cap) ? 2 : 0;
 }
 
 // Loss after splitting Gaussian i into two offspring at p +/- eps*delta with

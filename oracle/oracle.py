@@ -32,8 +32,11 @@ def build(force: bool = True) -> str:
     """Compile the oracle with g++ (plain FP64, no FMA contraction)."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
+        # -fopenmp: the sampled-gradient and pixel-variant entry points run
+        # their (independent) views in parallel; every other entry point is
+        # single-threaded
         subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
-                               "-fno-fast-math", "-o", tmp, SRC])
+                               "-fno-fast-math", "-fopenmp", "-o", tmp, SRC])
         os.replace(tmp, LIB)
     return LIB
 
@@ -57,7 +60,8 @@ def lib():
         L.orc_loss.restype = C.c_double
         L.orc_render_pixels.argtypes = common + [_c_i64, C.c_int64, _c_f64, _c_f64, _c_u8]
         L.orc_render_pixels.restype = C.c_int
-        L.orc_grads_sampled.argtypes = common + [_c_f32, C.c_double, _c_i64, C.c_int64, _c_f64, _c_f64, _c_u8]
+        L.orc_grads_sampled.argtypes = common + [_c_f32, C.c_double, _c_i64, C.c_int64, _c_f64, _c_f64, _c_u8,
+                                                 C.c_void_p, C.c_int64, C.c_void_p]
         L.orc_grads_sampled.restype = C.c_int
         L.orc_loss_merged_split.argtypes = common + [_c_f32, C.c_int64, _c_f64, C.c_double]
         L.orc_loss_merged_split.restype = C.c_double
@@ -84,7 +88,7 @@ def lib():
         L.orc_eigh_n.argtypes = [_c_f64, C.c_int64, C.c_int, _c_f64, _c_f64]
         L.orc_eigh_n.restype = None
         L.orc_pixel_variants.argtypes = common + [C.c_void_p, C.c_void_p, C.c_int64, _c_i64, _c_i32, _c_i32] + \
-            [C.c_void_p] * 9
+            [C.c_void_p] * 10
         L.orc_pixel_variants.restype = C.c_int
         L.orc_tile_lists.argtypes = common + [_c_i64, C.c_int64, _c_i64, C.c_void_p]
         L.orc_tile_lists.restype = C.c_int
@@ -230,8 +234,9 @@ def pixel_variants(params, sh_degree, cams, opts, target, pix, flip, signs, dl_d
     used = np.zeros(nv, np.int32)
     nd = np.zeros(nv, np.int32)
     cnt = np.zeros(nv, np.int64)
+    vu = np.zeros(nv, np.uint8)
     rc = lib().orc_pixel_variants(*args, _ptr(tgt), _ptr(dld), nv, pix, flip, sg, _ptr(rgb), _ptr(T), _ptr(used),
-                                  _ptr(nd), _ptr(cnt), None, None, None, None)
+                                  _ptr(nd), _ptr(vu), _ptr(cnt), None, None, None, None)
     assert rc == 0
     tot = int(cnt.sum())
     gid = np.zeros(max(tot, 1), np.int64)
@@ -239,12 +244,12 @@ def pixel_variants(params, sh_degree, cams, opts, target, pix, flip, signs, dl_d
     Sv = np.zeros((max(tot, 1), 9), np.float64)
     S6 = np.zeros((max(tot, 1), 21), np.float64) if with_s6 else None
     rc = lib().orc_pixel_variants(*args, _ptr(tgt), _ptr(dld), nv, pix, flip, sg, _ptr(rgb), _ptr(T), _ptr(used),
-                                  _ptr(nd), _ptr(cnt), _ptr(gid), _ptr(gr), _ptr(Sv), _ptr(S6))
+                                  _ptr(nd), _ptr(vu), _ptr(cnt), _ptr(gid), _ptr(gr), _ptr(Sv), _ptr(S6))
     assert rc == 0
     off = np.concatenate([[0], np.cumsum(cnt)])
     terms = [(gid[off[k]:off[k + 1]], gr[off[k]:off[k + 1]], Sv[off[k]:off[k + 1]])
              + ((S6[off[k]:off[k + 1]],) if with_s6 else ()) for k in range(nv)]
-    return dict(rgb=rgb, T_final=T, n_used=used, ndec=nd, terms=terms)
+    return dict(rgb=rgb, T_final=T, n_used=used, ndec=nd, valunc=vu.astype(bool), terms=terms)
 
 
 def loss(params, sh_degree, cams, opts, target):
@@ -262,16 +267,25 @@ def render_pixels(params, sh_degree, cams, opts, pixel_ids):
     return rgb, T, amb.astype(bool)
 
 
-def grads_sampled(params, sh_degree, cams, opts, target, gids, sign_band=1e-5):
+def grads_sampled(params, sh_degree, cams, opts, target, gids, sign_band=1e-5, flagged=False):
+    """Gradients [ns][F] and S [ns][9] of the sampled Gaussians (every pixel of
+    every tile they touch blended in full), their ambiguity flags, and with
+    ``flagged`` the global ids of the pixels with an in-band decision, an
+    uncertain alpha or an L1 sign near zero that touch a sampled Gaussian."""
     args = _common(params, sh_degree, cams, opts)
     g = np.ascontiguousarray(gids, np.int64)
     F = params.shape[0]
     grads = np.zeros((len(g), F), np.float64)
     S = np.zeros((len(g), 9), np.float64)
     amb = np.zeros(len(g), np.uint8)
+    cap = 1 << 16
+    fl = np.zeros(cap, np.int64) if flagged else None
+    nf = C.c_int64(0)
     rc = lib().orc_grads_sampled(*args, np.ascontiguousarray(target, np.float32), float(sign_band), g, len(g),
-                                 grads, S, amb)
-    assert rc == 0
+                                 grads, S, amb, _ptr(fl), cap if flagged else 0, C.byref(nf) if flagged else None)
+    assert rc == 0, "more flagged pixels than the buffer holds"
+    if flagged:
+        return grads, S, amb.astype(bool), fl[: nf.value].copy()
     return grads, S, amb.astype(bool)
 
 

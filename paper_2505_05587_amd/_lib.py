@@ -46,7 +46,7 @@ class AdamOpts(C.Structure):
 
 
 assert C.sizeof(Camera) == 96
-SPLAT_FLOATS = 12  # 48-byte record
+SPLAT_FLOATS = 16  # 64-byte record
 
 
 class SteepGSError(RuntimeError):

@@ -136,21 +136,57 @@ SG_DEV int view_of_tile(const steepgs_camera* __restrict__ cams, int V, int tile
   return v;
 }
 
+// IEEE binary16 bits of x (nearest even) and the float value of the low 16
+// bits of b: the record keeps the remainders of its float32 mean in this form
+SG_DEV uint32_t half_bits(float x) { return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)x); }
+SG_DEV float half_value(uint32_t b) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(b & 0xFFFFu)); }
+
+// The remainder rem = exact mean - float32 mean of a record
+SG_DEV float2 mean_rem(const steepgs_splat& sp) {
+  return make_float2(half_value(sp.mean_lo), half_value(sp.mean_lo >> 16));
+}
+
 // ---------------------------------------------------------------------------
 // Per-pixel opacity of a projected Gaussian (Eq. sigma_2D):
-//   alpha = min(alpha_max, o * exp(-1/2 d^T A d)),  d = x - mean.
-// The forward and backward raster kernels evaluate it with this one routine
-// so that both see bit-identical values.
-SG_DEV float splat_power(float dx, float dy, float a, float b, float c) {
+//   alpha = min(alpha_max, o * exp(-1/2 d^T A d)),  d = x - mean,
+// with the exponent in base 2 from the conic's eigen form (record fields
+// axis, e_long, e_short): -1/2 d^T A d * log2(e) = e_long (axis . d)^2 +
+// e_short (axis_perp . d)^2, axis_perp = (-axis_y, axis_x).  Two
+// non-negative terms, so float32 loses no digits to cancellation when a thin
+// footprint is seen along its long axis (the terms a dx^2, 2 b dx dy, c dy^2
+// of the conic would).
+// The offsets come from the float32 mean, d0 = x - mean_f = d + rem, which
+// depends on the pixel only (not on the tile that holds it); the remainder
+// enters through the entry's constants cl = axis . rem, cs = axis_perp . rem
+// (rem_axes): axis . d = axis . d0 - cl, at no cost per pixel.  The forward
+// and backward raster kernels evaluate it with this one routine, so that
+// both see bit-identical values.
+SG_DEV float splat_power2_axes(float dx0, float dy0, float ax, float ay, float cl, float cs, float el, float es,
+                               float& pl, float& ps) {
   // explicit fused operations: one fixed rounding sequence in every kernel
-  const float quad = __builtin_fmaf(dx, a * dx, dy * (c * dy));
-  return __builtin_fmaf(quad, -0.5f, -(dy * (b * dx)));
+  pl = __builtin_fmaf(ax, dx0, __builtin_fmaf(ay, dy0, -cl));
+  ps = __builtin_fmaf(ax, dy0, __builtin_fmaf(-ay, dx0, -cs));
+  return __builtin_fmaf(pl, el * pl, ps * (es * ps));
+}
+
+// the same, without the projections on the axes (pl = axis . d, ps = axis_perp . d)
+SG_DEV float splat_power2(float dx0, float dy0, float ax, float ay, float cl, float cs, float el, float es) {
+  float pl, ps;
+  return splat_power2_axes(dx0, dy0, ax, ay, cl, cs, el, es, pl, ps);
+}
+
+// (cl, cs) of a record, see splat_power2
+SG_DEV float2 rem_axes(const steepgs_splat& sp) {
+  const float2 r = mean_rem(sp);
+  return make_float2(__builtin_fmaf(sp.axis_x, r.x, sp.axis_y * r.y), __builtin_fmaf(sp.axis_x, r.y, -(sp.axis_y * r.x)));
 }
 
 // A pixel takes part in a Gaussian's blend only inside its footprint,
-// d^T A d <= radius_sigmas^2, i.e. power = -1/2 d^T A d >= this value.  The
-// forward and backward raster kernels both test against it.
-SG_DEV float footprint_power_cut(const steepgs_opts& opt) { return -0.5f * opt.radius_sigmas * opt.radius_sigmas; }
+// d^T A d <= radius_sigmas^2, i.e. power2 = -1/2 d^T A d log2(e) >= this
+// value.  The forward and backward raster kernels both test against it.
+SG_DEV float footprint_power2_cut(const steepgs_opts& opt) {
+  return -0.72134752044448170368f * opt.radius_sigmas * opt.radius_sigmas;
+}
 
 // Half-extents of the region where a pixel can contribute: inside the
 // footprint and alpha >= alpha_min, the ellipse d^T A d <= t with

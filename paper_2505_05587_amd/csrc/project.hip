@@ -33,11 +33,13 @@ __global__ void __launch_bounds__(kProjThreads) k_project(const float* __restric
     const int64_t r = (int64_t)v * n + i;
     steepgs_splat s;
     uint32_t count = 0;
+    float depth = 0.f;
     if (project_view(g, cam, opt, pv)) {
       double rgb[3];
       view_colour<D>(g, cam, sh, kProjThreads, rgb);
       s.mean_x = (float)pv.mx;
       s.mean_y = (float)pv.my;
+      s.mean_lo = half_bits((float)(pv.mx - (double)s.mean_x)) | (half_bits((float)(pv.my - (double)s.mean_y)) << 16);
       s.conic_a = (float)pv.A00;
       s.conic_b = (float)pv.A01;
       s.conic_c = (float)pv.A11;
@@ -45,7 +47,11 @@ __global__ void __launch_bounds__(kProjThreads) k_project(const float* __restric
       s.rgb[0] = (float)rgb[0];
       s.rgb[1] = (float)rgb[1];
       s.rgb[2] = (float)rgb[2];
-      s.depth = (float)pv.pc[2];
+      depth = (float)pv.pc[2];
+      s.axis_x = (float)pv.ax;
+      s.axis_y = (float)pv.ay;
+      s.e_long = (float)(-0.72134752044448170368 * pv.lam_long);   // -log2(e) / 2
+      s.e_short = (float)(-0.72134752044448170368 * pv.lam_short);
       s.rect_lo = (uint32_t)pv.rect[0] | ((uint32_t)pv.rect[1] << 16);
       s.rect_hi = (uint32_t)pv.rect[2] | ((uint32_t)pv.rect[3] << 16);
       // the rectangle's area: the sort's emission keeps the tiles that meet the footprint
@@ -55,20 +61,24 @@ __global__ void __launch_bounds__(kProjThreads) k_project(const float* __restric
       s.conic_a = s.conic_b = s.conic_c = 0.f;
       s.opacity = 0.f;
       s.rgb[0] = s.rgb[1] = s.rgb[2] = 0.f;
-      s.depth = 0.f;
+      s.mean_lo = 0u;
+      s.axis_x = 1.f;
+      s.axis_y = 0.f;
+      s.e_long = s.e_short = 0.f;
       s.rect_lo = 1u;  // x0 = 1 > x1 = 0: empty
       s.rect_hi = 0u;
     }
-    // three 16-byte stores
+    // four 16-byte stores
     float4* dst = reinterpret_cast<float4*>(out + r);
     const float4* src = reinterpret_cast<const float4*>(&s);
     dst[0] = src[0];
     dst[1] = src[1];
     dst[2] = src[2];
+    dst[3] = src[3];
     tiles[r] = count;
     // the key of the sort's depth order: the float bits of the (positive)
     // depth, all ones for a culled record
-    if (dkeys) dkeys[r] = count ? __float_as_uint(s.depth) : 0xFFFFFFFFu;
+    dkeys[r] = count ? __float_as_uint(depth) : 0xFFFFFFFFu;
   }
 }
 
@@ -82,7 +92,7 @@ extern "C" steepgs_status steepgs_project(const float* d_params, int64_t n, int3
                                           uint32_t* d_depth_keys, void* stream) {
   if (n < 0 || V <= 0 || sh_degree < 0 || sh_degree > 3 || !opts_ok(opts)) return STEEPGS_ERR_INVALID_ARG;
   if (n == 0) return STEEPGS_OK;
-  if (!d_params || !d_cams || !d_splats || !d_tiles_touched) return STEEPGS_ERR_INVALID_ARG;
+  if (!d_params || !d_cams || !d_splats || !d_tiles_touched || !d_depth_keys) return STEEPGS_ERR_INVALID_ARG;
   if ((int64_t)V * n >= (int64_t)UINT32_MAX) return STEEPGS_ERR_INVALID_ARG;  // record ids are 32-bit
   timer_begin(STEEPGS_TIMER_PROJECT, as_stream(stream));
   const dim3 pg((unsigned)ceil_div(n, kProjThreads)), pb(kProjThreads);

@@ -261,6 +261,8 @@ struct ViewProj {
   double S2[2][2];        // Pi(Sigma) + dilation
   double det;
   double A00, A01, A11;  // conic
+  double ax, ay;          // unit long axis of the footprint ellipse
+  double lam_long, lam_short;  // the conic's eigenvalues along it and across it
   int rect[4];
 };
 
@@ -322,7 +324,28 @@ SG_DEV bool project_view(const Gauss& g, const CamD& cam, const steepgs_opts& op
 
   const double a = v.S2[0][0], b = v.S2[0][1], c = v.S2[1][1];
   const double half = 0.5 * (a - c);
-  const double lam = 0.5 * (a + c) + sqrt(half * half + b * b);
+  const double rt = sqrt(half * half + b * b);
+  const double lam = 0.5 * (a + c) + rt;
+  // eigen form of the conic: the long axis is the eigenvector of Pi(Sigma)'s
+  // larger eigenvalue lam (the cancellation-free one of the two textbook
+  // forms), the conic's eigenvalues are 1 / lam along it and lam / det across
+  {
+    double ex = half + rt, ey = b;
+    if (half < 0.0) {
+      ex = b;
+      ey = rt - half;
+    }
+    const double en = sqrt(ex * ex + ey * ey);
+    if (en > 0.0) {
+      v.ax = ex / en;
+      v.ay = ey / en;
+    } else {
+      v.ax = 1.0;
+      v.ay = 0.0;
+    }
+    v.lam_long = 1.0 / lam;
+    v.lam_short = lam / v.det;
+  }
   const double r = ceil((double)opt.radius_sigmas * sqrt(lam));
   const double tw = opt.tile_w, th = opt.tile_h;
   double x0 = floor((v.mx - r) / tw), x1 = floor((v.mx + r) / tw);

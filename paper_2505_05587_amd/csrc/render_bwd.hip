@@ -52,8 +52,14 @@ constexpr int kGrad2dOut = 12;
 // H6: also the moments the dim-6 splitting matrix needs (third and fourth
 // order in d), summed like the others; WAVES wavefronts per workgroup, each
 // on a tile of its own
+// Occupancy target of the blend kernel without the split6 moments
+// (wavefronts per SIMD; a build option, it sets the register budget)
+#ifndef SG_BWD_WAVES_PER_EU
+#define SG_BWD_WAVES_PER_EU 6
+#endif
+
 template <int TW, int TH, bool H6, int WAVES>
-__global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(H6 ? 4 : 6))) k_render_bwd(const steepgs_splat* __restrict__ splats,
+__global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(H6 ? 4 : SG_BWD_WAVES_PER_EU))) k_render_bwd(const steepgs_splat* __restrict__ splats,
                                                                const uint32_t* __restrict__ vals,
                                                                const uint32_t* __restrict__ ranges,
                                                                const steepgs_camera* __restrict__ cams, int V,
@@ -67,16 +73,18 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
                                                                uint32_t* __restrict__ queue) {
   constexpr int NQ = TW * TH / 64;  // 8x8 quadrants of the tile = pixels per lane
   constexpr int QX = TW / 8;
-  __shared__ float4 s_a[WAVES][64];  // mean x, mean y, conic a, conic b
-  __shared__ float4 s_c[WAVES][64];  // conic c, opacity, red, green
-  __shared__ float2 s_e[WAVES][64];  // blue, record id (bits)
+  __shared__ float4 s_a[WAVES][64];  // float32 mean x, y, long axis x, y
+  __shared__ float4 s_c[WAVES][64];  // e_long, e_short, opacity, red
+  __shared__ float4 s_e[WAVES][64];  // green, blue, remainder constants cl, cs
+  __shared__ uint32_t s_id[WAVES][64];  // record id
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lx = lane & 7, ly = lane >> 3;
   const int red_idx = reduce9_index(lane);
   float4* const A = s_a[wave];
   float4* const Cq = s_c[wave];
-  float2* const E = s_e[wave];
-  const float cut = footprint_power_cut(opt);
+  float4* const E = s_e[wave];
+  uint32_t* const Id = s_id[wave];
+  const float cut = footprint_power2_cut(opt);
   for (;;) {
     // the wave barrier keeps the lane-0 fetch inside the loop
     __builtin_amdgcn_wave_barrier();
@@ -143,9 +151,11 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
         cutoff_extent(sp.conic_a, sp.conic_b, sp.conic_c, sp.opacity, opt, ex, ey);
         const float lev = cutoff_level(sp.opacity, opt);
         const float ia = __builtin_amdgcn_rcpf(sp.conic_a), ic = __builtin_amdgcn_rcpf(sp.conic_c);
-        A[lane] = make_float4(sp.mean_x, sp.mean_y, sp.conic_a, sp.conic_b);
-        Cq[lane] = make_float4(sp.conic_c, sp.opacity, sp.rgb[0], sp.rgb[1]);
-        E[lane] = make_float2(sp.rgb[2], __uint_as_float(id));
+        const float2 rc = rem_axes(sp);
+        A[lane] = make_float4(sp.mean_x, sp.mean_y, sp.axis_x, sp.axis_y);
+        Cq[lane] = make_float4(sp.e_long, sp.e_short, sp.opacity, sp.rgb[0]);
+        E[lane] = make_float4(sp.rgb[1], sp.rgb[2], rc.x, rc.y);
+        Id[lane] = id;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
           const float x0 = (float)(tx0 + (q % QX) * 8), y0 = (float)(ty0 + (q / QX) * 8);
@@ -175,9 +185,13 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
         const float4 a = A[j];
         const float4 cq = Cq[j];
         const uint32_t pos = (uint32_t)(b_start + j);
-        const float blue = E[j].x;
-        // moments of g alpha d over the tile's pixels (the mean and conic
-        // gradients are linear in them), opacity and colour gradients.  The
+        const float4 ej = E[j];  // green, blue, cl, cs
+        // moments of g alpha d over the tile's pixels, in the frame of the
+        // footprint's axes (pl = axis . d, ps = axis_perp . d, d the offset
+        // from the exact mean: for a thin footprint the moments across it
+        // would cancel to nothing in pixel coordinates; the lift turns them
+        // into pixel coordinates in fp64; the mean and conic gradients are
+        // linear in them), opacity and colour gradients.  The
         // per-pixel work is predicated (selects, no divergent branch), so the
         // sums are updated in place; a quadrant is skipped as a whole when
         // the entry is outside its reach or no pixel of it takes the entry.
@@ -189,9 +203,11 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
           if (!((qm[q] >> j) & 1ull)) continue;  // wave-uniform
           const float dx = (float)(tx0 + (q % QX) * 8 + lx) - a.x;
           const float dy = (float)(ty0 + (q / QX) * 8 + ly) - a.y;
-          const float power = splat_power(dx, dy, a.z, a.w, cq.x);
-          const float G = __expf(power);
-          const float raw = cq.y * G;
+          // offsets from the exact mean along and across the footprint's axis
+          float pl, ps;
+          const float power = splat_power2_axes(dx, dy, a.z, a.w, ej.z, ej.w, cq.x, cq.y, pl, ps);
+          const float G = __builtin_amdgcn_exp2f(power);
+          const float raw = cq.z * G;
           const bool clamped = raw > opt.alpha_max;
           const float alpha = fminf(opt.alpha_max, raw);
           // entries at or past the pixel's last contributor (or outside the
@@ -207,7 +223,7 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
           const float inv_om = __builtin_amdgcn_rcpf(1.f - alpha);
           const float Ti = T[q] * inv_om;
           // g = dL/dalpha_i = sum_c dL/dC_c (c_c T_i - R_c / (1 - alpha_i))
-          const float x = dC[q][0] * cq.z + dC[q][1] * cq.w + dC[q][2] * blue;
+          const float x = dC[q][0] * cq.w + dC[q][1] * ej.x + dC[q][2] * ej.y;
           const float g = Ti * x - D[q] * inv_om;
           const float w = c ? alpha * Ti : 0.f;
           T[q] = c ? Ti : T[q];
@@ -218,20 +234,20 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
           // the clamped alpha does not depend on the mean, conic or opacity
           const bool lin = c && !clamped;
           const float gaw = lin ? g * alpha : 0.f;
-          const float tx = gaw * dx, ty = gaw * dy;
+          const float tx = gaw * pl, ty = gaw * ps;
           mx += tx;
           my += ty;
-          mxx += tx * dx;
-          mxy += tx * dy;
-          myy += ty * dy;
+          mxx += tx * pl;
+          mxy += tx * ps;
+          myy += ty * ps;
           go += lin ? g * G : 0.f;
           if (H6) {
-            const float txx = tx * dx, tyy = ty * dy;
-            h3[0] += txx * dx;
-            h3[1] += txx * dy;
-            h3[2] += tyy * dx;
-            h3[3] += tyy * dy;
-            const float dxx = dx * dx, dxy = dx * dy, dyy = dy * dy;
+            const float txx = tx * pl, tyy = ty * ps;
+            h3[0] += txx * pl;
+            h3[1] += txx * ps;
+            h3[2] += tyy * pl;
+            h3[3] += tyy * ps;
+            const float dxx = pl * pl, dxy = pl * ps, dyy = ps * ps;
             h4[0] += txx * dxx;
             h4[1] += txx * dxy;
             h4[2] += txx * dyy;
@@ -246,7 +262,7 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
           // hardware-chosen order leaves the float32 results unchanged
           const float part[9] = {mx, my, mxx, mxy, myy, go, gr, gg, gbl};
           const float tot = reduce9(part);
-          const int64_t rid = (int64_t)__float_as_uint(E[j].y);
+          const int64_t rid = (int64_t)Id[j];
           if (red_idx >= 0) unsafeAtomicAdd(g2d.slot + rid * kSlot + red_idx, (double)tot);
           if (H6) {
             const float part2[9] = {h3[0], h3[1], h3[2], h3[3], h4[0], h4[1], h4[2], h4[3], h4[4]};
@@ -257,6 +273,63 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
       }
     }
   }
+}
+
+// The blend takes its moments in the frame of the footprint's float32 axis
+// a (pl = a . d, ps = a_perp . d, a_perp = (-a_y, a_x)); with
+// d = (pl a + ps a_perp) / |a|^2 they become moments of the pixel offsets:
+// mom[i][j] = sum w pl^i ps^j on entry, sum w dx^i dy^j on return (i + j <= K),
+// expanded in fp64 (a thin footprint's moments across its axis survive the
+// cancellation there)
+template <int K>
+SG_DEV void axis_to_pixel_moments(double (&mom)[K + 1][K + 1], float axf, float ayf) {
+  const double ax = axf, ay = ayf, n2 = ax * ax + ay * ay;
+  // dx = xl pl + xs ps, dy = yl pl + ys ps
+  const double xl = ax / n2, xs = -ay / n2, yl = ay / n2, ys = ax / n2;
+  double out[K + 1][K + 1];
+#pragma unroll
+  for (int a = 0; a <= K; ++a)
+#pragma unroll
+    for (int b = 0; b <= K - a; ++b) {
+      // coefficients of pl^(a+b-k) ps^k in (xl pl + xs ps)^a (yl pl + ys ps)^b
+      double c[K + 1];
+      c[0] = 1.0;
+#pragma unroll
+      for (int k = 1; k <= K; ++k) c[k] = 0.0;
+#pragma unroll
+      for (int t = 0; t < a + b; ++t) {
+        const double u = t < a ? xl : yl, v = t < a ? xs : ys;
+#pragma unroll
+        for (int k = K; k >= 1; --k) c[k] = c[k] * u + c[k - 1] * v;
+        c[0] *= u;
+      }
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k <= a + b; ++k) s += c[k] * mom[a + b - k][k];
+      out[a][b] = s;
+    }
+#pragma unroll
+  for (int a = 0; a <= K; ++a)
+#pragma unroll
+    for (int b = 0; b <= K - a; ++b) mom[a][b] = out[a][b];
+}
+
+// The second-order case written out (m1 and m2 of the lift):
+// m1 = (m1l, m1s), m2 = (m2ll, m2ls, m2ss) in the axis frame on entry,
+// (x, y) and (xx, xy, yy) on return
+SG_DEV void axis_to_pixel_moments2(double& m1l, double& m1s, double& m2ll, double& m2ls, double& m2ss, float axf,
+                                   float ayf) {
+  const double ax = axf, ay = ayf, n2 = ax * ax + ay * ay;
+  const double xl = ax / n2, xs = -ay / n2, yl = ay / n2, ys = ax / n2;
+  const double x = xl * m1l + xs * m1s, y = yl * m1l + ys * m1s;
+  const double xx = xl * xl * m2ll + 2.0 * xl * xs * m2ls + xs * xs * m2ss;
+  const double xy = xl * yl * m2ll + (xl * ys + xs * yl) * m2ls + xs * ys * m2ss;
+  const double yy = yl * yl * m2ll + 2.0 * yl * ys * m2ls + ys * ys * m2ss;
+  m1l = x;
+  m1s = y;
+  m2ll = xx;
+  m2ls = xy;
+  m2ss = yy;
 }
 
 // ---------------------------------------------------------------------------
@@ -325,7 +398,9 @@ SG_DEV uint32_t visible_views(const uint32_t* __restrict__ tiles, int64_t n, int
 template <int D>
 __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) k_proj_bwd(const float* __restrict__ params, int64_t n,
                                                   const steepgs_camera* __restrict__ cams, int V, steepgs_opts opt,
-                                                  const uint32_t* __restrict__ tiles, const double* __restrict__ g2d,
+                                                  const uint32_t* __restrict__ tiles,
+                                                  const steepgs_splat* __restrict__ splats,
+                                                  const double* __restrict__ g2d,
                                                   float* __restrict__ grads, float* __restrict__ S) {
   constexpr int NB = (D + 1) * (D + 1);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -419,9 +494,12 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) k
       if (!((vis >> k) & 1u)) continue;
       const int v = v0 + k;
       const double* slot = g2d + ((int64_t)v * n + i) * kSlot;
-      const double m1x = slot[0], m1y = slot[1], m2xx = slot[2], m2xy = slot[3], m2yy = slot[4], go = slot[5];
+      const double go = slot[5];
+      double m1x = slot[0], m1y = slot[1], m2xx = slot[2], m2xy = slot[3], m2yy = slot[4];
       if (m1x == 0.0 && m1y == 0.0 && m2xx == 0.0 && m2xy == 0.0 && m2yy == 0.0 && go == 0.0) continue;
       any = true;
+      axis_to_pixel_moments2(m1x, m1y, m2xx, m2xy, m2yy, splats[(int64_t)v * n + i].axis_x,
+                             splats[(int64_t)v * n + i].axis_y);
       const steepgs_camera& cam = cams[v];
       double W[9];
 #pragma unroll
@@ -618,7 +696,9 @@ SG_DEV void sq_coef(const double a[2], double c[3]) {
 
 __global__ void __launch_bounds__(128) k_split6_lift(const float* __restrict__ params, int64_t n,
                                                      const steepgs_camera* __restrict__ cams, int V, steepgs_opts opt,
-                                                     const uint32_t* __restrict__ tiles, const double* __restrict__ g2d,
+                                                     const uint32_t* __restrict__ tiles,
+                                                     const steepgs_splat* __restrict__ splats,
+                                                     const double* __restrict__ g2d,
                                                      const double* __restrict__ h6, float* __restrict__ S6) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -640,12 +720,19 @@ __global__ void __launch_bounds__(128) k_split6_lift(const float* __restrict__ p
     if (tiles[r] == 0) continue;
     const double* slot = g2d + r * kSlot;
     const double* hs = h6 + r * kH6;
-    const double m1[2] = {slot[0], slot[1]};
-    const double m2[3] = {slot[2], slot[3], slot[4]};  // xx, xy, yy
     const double go = slot[5];
-    const double m3[4] = {hs[0], hs[1], hs[2], hs[3]};  // xxx, xxy, xyy, yyy
-    const double m4[5] = {hs[4], hs[5], hs[6], hs[7], hs[8]};  // xxxx .. yyyy
-    if (m1[0] == 0.0 && m1[1] == 0.0 && m2[0] == 0.0 && m2[1] == 0.0 && m2[2] == 0.0 && go == 0.0) continue;
+    if (slot[0] == 0.0 && slot[1] == 0.0 && slot[2] == 0.0 && slot[3] == 0.0 && slot[4] == 0.0 && go == 0.0) continue;
+    // mom[a][b] = sum g alpha dx^a dy^b, from the moments along and across the axis
+    double mom[5][5] = {{o * go, slot[1], slot[4], hs[3], hs[8]},
+                        {slot[0], slot[3], hs[2], hs[7], 0.0},
+                        {slot[2], hs[1], hs[6], 0.0, 0.0},
+                        {hs[0], hs[5], 0.0, 0.0, 0.0},
+                        {hs[4], 0.0, 0.0, 0.0, 0.0}};
+    axis_to_pixel_moments<4>(mom, splats[r].axis_x, splats[r].axis_y);
+    const double m1[2] = {mom[1][0], mom[0][1]};
+    const double m2[3] = {mom[2][0], mom[1][1], mom[0][2]};  // xx, xy, yy
+    const double m3[4] = {mom[3][0], mom[2][1], mom[1][2], mom[0][3]};  // xxx, xxy, xyy, yyy
+    const double m4[5] = {mom[4][0], mom[3][1], mom[2][2], mom[1][3], mom[0][4]};  // xxxx .. yyyy
     const steepgs_camera& cam = cams[v];
     // camera space (fp64 for the guard decision, as the forward)
     double pcd[3];
@@ -760,13 +847,14 @@ __global__ void k_export2d(const steepgs_splat* __restrict__ splats, const uint3
     for (int k = 0; k < kGrad2dOut; ++k) v[k] = 0.f;
     if (tiles[r] != 0) {
       const double* slot = g2d + r * kSlot;
-      const double m1x = slot[0], m1y = slot[1];
+      double m1x = slot[0], m1y = slot[1], m2xx = slot[2], m2xy = slot[3], m2yy = slot[4];
+      axis_to_pixel_moments2(m1x, m1y, m2xx, m2xy, m2yy, splats[r].axis_x, splats[r].axis_y);
       const double a = splats[r].conic_a, b = splats[r].conic_b, c = splats[r].conic_c;
       v[0] = (float)(a * m1x + b * m1y);
       v[1] = (float)(b * m1x + c * m1y);
-      v[2] = (float)(-0.5 * slot[2]);
-      v[3] = (float)(-slot[3]);
-      v[4] = (float)(-0.5 * slot[4]);
+      v[2] = (float)(-0.5 * m2xx);
+      v[3] = (float)(-m2xy);
+      v[4] = (float)(-0.5 * m2yy);
 #pragma unroll
       for (int k = 5; k < 9; ++k) v[k] = (float)slot[k];
     }
@@ -867,13 +955,13 @@ static steepgs_status bwd_impl(const float* d_params, int64_t n, int32_t sh_degr
   timer_begin(STEEPGS_TIMER_PROJ_BWD, st);
   const dim3 pg((unsigned)ceil_div(n, 128));
   switch (sh_degree) {
-    case 0: hipLaunchKernelGGL(k_proj_bwd<0>, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d.slot, d_grads, d_S); break;
-    case 1: hipLaunchKernelGGL(k_proj_bwd<1>, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d.slot, d_grads, d_S); break;
-    case 2: hipLaunchKernelGGL(k_proj_bwd<2>, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d.slot, d_grads, d_S); break;
-    default: hipLaunchKernelGGL(k_proj_bwd<3>, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d.slot, d_grads, d_S); break;
+    case 0: hipLaunchKernelGGL(k_proj_bwd<0>, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, d_splats, g2d.slot, d_grads, d_S); break;
+    case 1: hipLaunchKernelGGL(k_proj_bwd<1>, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, d_splats, g2d.slot, d_grads, d_S); break;
+    case 2: hipLaunchKernelGGL(k_proj_bwd<2>, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, d_splats, g2d.slot, d_grads, d_S); break;
+    default: hipLaunchKernelGGL(k_proj_bwd<3>, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, d_splats, g2d.slot, d_grads, d_S); break;
   }
   if (h6)
-    hipLaunchKernelGGL(k_split6_lift, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, g2d.slot,
+    hipLaunchKernelGGL(k_split6_lift, pg, dim3(128), 0, st, d_params, n, d_cams, V, o, d_tiles_touched, d_splats, g2d.slot,
                        g2d.h6, d_S6);
   timer_end(STEEPGS_TIMER_PROJ_BWD, st);
   if (d_grad2d && !h6)

@@ -19,8 +19,14 @@ namespace sg {
 
 // COUNT: also count each pixel's contributors (the optional n_used output);
 // WAVES wavefronts per workgroup, each on a tile of its own
+// Occupancy target of the blend kernels (wavefronts per SIMD), which sets
+// their register budget (a build option: 512 / target registers per lane)
+#ifndef SG_FWD_WAVES_PER_EU
+#define SG_FWD_WAVES_PER_EU 7
+#endif
+
 template <int TW, int TH, bool COUNT, int WAVES>
-__global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(7))) k_render_fwd(const steepgs_splat* __restrict__ splats,
+__global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(SG_FWD_WAVES_PER_EU))) k_render_fwd(const steepgs_splat* __restrict__ splats,
                                                                const uint32_t* __restrict__ vals,
                                                                const uint32_t* __restrict__ ranges,
                                                                const steepgs_camera* __restrict__ cams, int V,
@@ -32,15 +38,15 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
                                                                uint32_t* __restrict__ queue) {
   constexpr int NQ = TW * TH / 64;  // 8x8 quadrants of the tile = pixels per lane
   constexpr int QX = TW / 8;
-  __shared__ float4 s_a[WAVES][64];  // mean x, mean y, conic a, conic b
-  __shared__ float4 s_c[WAVES][64];  // conic c, opacity, red, green
-  __shared__ float s_b[WAVES][64];   // blue
+  __shared__ float4 s_a[WAVES][64];  // float32 mean x, y, long axis x, y
+  __shared__ float4 s_c[WAVES][64];  // e_long, e_short, opacity, red
+  __shared__ float4 s_b[WAVES][64];  // green, blue, remainder constants cl, cs
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lx = lane & 7, ly = lane >> 3;
   float4* const A = s_a[wave];
   float4* const Cq = s_c[wave];
-  float* const Bl = s_b[wave];
-  const float cut = footprint_power_cut(opt);
+  float4* const Bl = s_b[wave];
+  const float cut = footprint_power2_cut(opt);
   for (;;) {
     // the wave barrier keeps the lane-0 fetch inside the loop
     __builtin_amdgcn_wave_barrier();
@@ -86,9 +92,10 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
         cutoff_extent(sp.conic_a, sp.conic_b, sp.conic_c, sp.opacity, opt, ex, ey);
         const float lev = cutoff_level(sp.opacity, opt);
         const float ia = __builtin_amdgcn_rcpf(sp.conic_a), ic = __builtin_amdgcn_rcpf(sp.conic_c);
-        A[lane] = make_float4(sp.mean_x, sp.mean_y, sp.conic_a, sp.conic_b);
-        Cq[lane] = make_float4(sp.conic_c, sp.opacity, sp.rgb[0], sp.rgb[1]);
-        Bl[lane] = sp.rgb[2];
+        const float2 rc = rem_axes(sp);
+        A[lane] = make_float4(sp.mean_x, sp.mean_y, sp.axis_x, sp.axis_y);
+        Cq[lane] = make_float4(sp.e_long, sp.e_short, sp.opacity, sp.rgb[0]);
+        Bl[lane] = make_float4(sp.rgb[1], sp.rgb[2], rc.x, rc.y);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
           const float x0 = (float)(tx0 + (q % QX) * 8), y0 = (float)(ty0 + (q / QX) * 8);
@@ -113,7 +120,7 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
         any_q &= any_q - 1ull;
         const float4 a = A[j];
         const float4 cq = Cq[j];
-        const float blue = Bl[j];
+        const float4 gb = Bl[j];  // green, blue, cl, cs
         const uint32_t pos1 = b0 - begin + (uint32_t)j + 1u;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
@@ -121,8 +128,8 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
           // per pixel: predicated, no divergent branch
           const float dx = (float)(tx0 + (q % QX) * 8 + lx) - a.x;
           const float dy = (float)(ty0 + (q / QX) * 8 + ly) - a.y;
-          const float power = splat_power(dx, dy, a.z, a.w, cq.x);
-          const float alpha = fminf(opt.alpha_max, cq.y * __expf(power));
+          const float power = splat_power2(dx, dy, a.z, a.w, gb.z, gb.w, cq.x, cq.y);
+          const float alpha = fminf(opt.alpha_max, cq.z * __builtin_amdgcn_exp2f(power));
           bool c = !done[q] && power >= cut && alpha >= opt.alpha_min;
           const float Tn = T[q] * (1.f - alpha);
           const bool stop = c && Tn < opt.t_min;  // would cross the cut-off: excluded, pixel done
@@ -131,9 +138,9 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
           // the weight is zero for a pixel that does not take the entry, so
           // the colour sums need no select (fma(colour, 0, C) = C)
           const float w = c ? alpha * T[q] : 0.f;
-          C[q][0] += cq.z * w;
-          C[q][1] += cq.w * w;
-          C[q][2] += blue * w;
+          C[q][0] += cq.w * w;
+          C[q][1] += gb.x * w;
+          C[q][2] += gb.y * w;
           T[q] = c ? Tn : T[q];
           last[q] = c ? pos1 : last[q];
           if (COUNT) used[q] += c ? 1u : 0u;

@@ -281,14 +281,6 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int64_t count) 
 
 __global__ void k_set_u64(uint64_t* __restrict__ p, uint64_t v) { *p = v; }
 
-__global__ void k_depth_keys(const steepgs_splat* __restrict__ splats, const uint32_t* __restrict__ tiles,
-                             int64_t m, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x) {
-    keys[r] = tiles[r] ? __float_as_uint(splats[r].depth) : 0xFFFFFFFFu;  // culled records sort last
-    vals[r] = (uint32_t)r;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Instance emission in depth order, walking every tile rectangle once.
 //
@@ -482,12 +474,12 @@ __global__ void k_ranges(const uint32_t* __restrict__ tkeys, const uint64_t* __r
 }
 
 __global__ void k_keys64(const uint32_t* __restrict__ tkeys, const uint32_t* __restrict__ vals,
-                         const steepgs_splat* __restrict__ splats, const uint64_t* __restrict__ d_num,
+                         const uint32_t* __restrict__ dkeys, const uint64_t* __restrict__ d_num,
                          uint64_t capacity, uint64_t* __restrict__ keys) {
   const uint64_t K = *d_num;
   if (K > capacity) return;
   for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < K; s += (uint64_t)gridDim.x * blockDim.x)
-    keys[s] = ((uint64_t)tkeys[s] << 32) | (uint64_t)__float_as_uint(splats[vals[s]].depth);
+    keys[s] = ((uint64_t)tkeys[s] << 32) | (uint64_t)dkeys[vals[s]];
 }
 
 struct SortWs {
@@ -558,13 +550,9 @@ extern "C" steepgs_status steepgs_sort(const steepgs_splat* d_splats, const uint
     SG_TRY_LAUNCH();
     return STEEPGS_OK;
   }
-  if (!d_splats || !d_tiles_touched || (capacity > 0 && !d_vals)) return STEEPGS_ERR_INVALID_ARG;
+  if (!d_splats || !d_tiles_touched || !d_depth_keys || (capacity > 0 && !d_vals)) return STEEPGS_ERR_INVALID_ARG;
   hipError_t err = hipSuccess;
-  // 1. depth order of the records (culled last); the keys come from the
-  // projection stage when it wrote them, else they are formed here
-  if (!d_depth_keys)
-    hipLaunchKernelGGL(k_depth_keys, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, d_splats, d_tiles_touched,
-                       m, w.dkA, w.dvA);
+  // 1. depth order of the records (culled last), on the projection's keys
   hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, w.counters, (uint64_t)m);
   hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, w.counters + 1, (uint64_t)capacity);
   const int where = radix_sort_pairs(w.dkA, w.dvA, w.dkB, w.dvB, 0, w.counters, nullptr, 32, w.hist, w.hist_partials,
@@ -602,7 +590,7 @@ extern "C" steepgs_status steepgs_sort(const steepgs_splat* d_splats, const uint
     hipLaunchKernelGGL(k_ranges, dim3((unsigned)ceil_div((int64_t)capacity, 256 * kRangesPer)), dim3(256), 0, st, w.tkA,
                        d_num_instances, capacity, d_tile_ranges);
     if (d_keys)
-      hipLaunchKernelGGL(k_keys64, dim3(2048), dim3(256), 0, st, w.tkA, d_vals, d_splats, d_num_instances, capacity,
+      hipLaunchKernelGGL(k_keys64, dim3(2048), dim3(256), 0, st, w.tkA, d_vals, d_depth_keys, d_num_instances, capacity,
                          d_keys);
   }
   timer_end(STEEPGS_TIMER_SORT, st);

@@ -20,6 +20,7 @@ def run_gpu(params, sh_degree, cams, opts, target=None, backward=True, want_keys
     fs = ras.forward(P, tg, want_keys=want_keys, count_used=True, want_counts=True)
     out = dict(K=fs.K, image=fs.image.cpu().numpy().astype(np.float64), T_final=fs.T_final.cpu().numpy(),
                n_contrib=fs.n_contrib.cpu().numpy(), n_used=ras.n_used.cpu().numpy(), splats=ras.splats.cpu().numpy(),
+               dkeys=ras.dkeys.cpu().numpy().view(np.uint32),
                tiles=ras.counts[: cams.V * P.shape[1]].cpu().numpy().view(np.uint32),
                rect_tiles=ras.tiles.cpu().numpy().view(np.uint32), vals=ras.vals[: fs.K].cpu().numpy().view(np.uint32),
                ranges=ras.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2))
@@ -177,21 +178,127 @@ def packed_index(cams, pix):
     return 3 * offs[v][:, None] + np.arange(3)[None, :] * wh[v][:, None] + local[:, None]
 
 
+def resolve_pixels(oracle, P, deg, cams, opts, target, pix, g_image, g_used, dl_dimage=None, with_s6=False):
+    """The outcome the GPU took at each of the pixels `pix` whose blend takes a
+    decision within float32 reach of its threshold (or whose L1 sign is within
+    reach of zero).  The oracle computes every outcome of the pixel; the GPU's
+    colour and blended count must match one of them.  Returns the chosen
+    outcome per pixel and, per Gaussian, the change of its gradient and S
+    terms from the oracle's default outcome (``delta``), the alternatives where
+    both outcomes fit the image (``either``), the Gaussians touched by pixels
+    with two or more such decisions (``excl``) or an alpha that float32 cannot
+    evaluate to the image bar (``soft``), and counts."""
+    F = P.shape[0]
+    pix = np.asarray(pix, np.int64)
+    out = dict(rgb={}, T={}, used={}, delta={}, either={}, excl=set(), soft=set(), excl_pix=set(), soft_pix=set(),
+               stats=dict(flagged=len(pix), multi=0, gpu_flipped=0, either=0, valunc=0))
+    if len(pix) == 0:
+        return out
+    e = packed_index(cams, pix)
+    n3 = np.full((len(pix), 3), 2)
+    D = oracle.pixel_variants(P, deg, cams, opts, target, pix, -np.ones(len(pix), np.int32), n3, dl_dimage=dl_dimage,
+                              with_s6=with_s6)
+    if dl_dimage is None:
+        d32 = g_image[e].astype(np.float32) - np.asarray(target, np.float32)[e]
+        sg = np.sign(d32).astype(np.int32)
+    else:
+        sg = np.zeros((len(pix), 3), np.int32)
+    pl, fl, sl, role = [], [], [], []
+    for k, p in enumerate(pix):
+        nd = int(D["ndec"][k])
+        if D["valunc"][k]:
+            out["stats"]["valunc"] += 1
+            out["soft_pix"].add(int(p))
+            out["soft"].update(int(i) for i in D["terms"][k][0])
+            continue
+        if nd >= 2:
+            out["stats"]["multi"] += 1
+            out["excl_pix"].add(int(p))
+            for f in range(-1, nd):
+                pl.append(p)
+                fl.append(f)
+                sl.append([2, 2, 2])
+                role.append((k, "X"))
+            continue
+        pl += [p]
+        fl += [-1]
+        sl += [list(sg[k])]
+        role += [(k, "A")]
+        if nd == 1:
+            pl.append(p)
+            fl.append(0)
+            sl.append(list(sg[k]))
+            role.append((k, "B"))
+    if not pl:
+        return out
+    var = oracle.pixel_variants(P, deg, cams, opts, target, np.array(pl), np.array(fl), np.array(sl),
+                                dl_dimage=dl_dimage, with_s6=with_s6)
+    by = {}
+    for j, (k, r) in enumerate(role):
+        by.setdefault(k, {}).setdefault(r, []).append(j)
+    zero = lambda: [np.zeros(F), np.zeros(9), np.zeros(21)]  # noqa: E731
+
+    def terms_of(v, j, sign, acc):
+        gid, gr, Sv, *rest = v["terms"][j]
+        for t, i in enumerate(gid):
+            a = acc.setdefault(int(i), zero())
+            a[0] += sign * gr[t]
+            a[1] += sign * Sv[t]
+            if rest:
+                a[2] += sign * rest[0][t]
+        return acc
+
+    for k, p in enumerate(pix):
+        rk = by.get(k, {})
+        if "X" in rk:
+            for j in rk["X"]:
+                out["excl"].update(int(i) for i in var["terms"][j][0])
+            continue
+        if "A" not in rk:
+            continue
+        got = g_image[e[k]]
+        cand = []
+        for r in ("A", "B"):
+            if r not in rk:
+                continue
+            j = rk[r][0]
+            ok = (np.abs(got - var["rgb"][j]) <= 1e-5 + 1e-4 * np.abs(var["rgb"][j])).all()
+            ok &= int(g_used[p]) == int(var["n_used"][j])
+            if ok:
+                cand.append((r, j))
+        if not cand:
+            raise AssertionError(f"pixel {p}: the GPU's colour {got} / count {g_used[p]} matches no outcome of its "
+                                 "in-band decision: " + ", ".join(f"{r}: {var['rgb'][rk[r][0]]} / "
+                                                                  f"{var['n_used'][rk[r][0]]}"
+                                                                  for r in ("A", "B") if r in rk))
+        r, j = cand[0]
+        out["rgb"][int(p)] = var["rgb"][j]
+        out["T"][int(p)] = var["T_final"][j]
+        out["used"][int(p)] = int(var["n_used"][j])
+        if r == "B":
+            out["stats"]["gpu_flipped"] += 1
+        dg = terms_of(D, k, -1.0, terms_of(var, j, 1.0, {}))
+        for i, a in dg.items():
+            b = out["delta"].setdefault(i, zero())
+            for t in range(3):
+                b[t] += a[t]
+        if len(cand) == 2:  # both outcomes fit the image: either is a correct gradient
+            out["stats"]["either"] += 1
+            d2 = terms_of(var, j, -1.0, terms_of(var, cand[1][1], 1.0, {}))
+            for i, a in d2.items():
+                out["either"].setdefault(i, []).append(tuple(a))
+    return out
+
+
 def checked_reference(oracle, P, deg, cams, opts, g, target=None, dl_dimage=None, with_s6=False):
     """The oracle's reference for one GPU run, with every decision that float32
-    can take either way resolved instead of excluded.
-
-    A pixel whose blend takes a cut-off decision within float32 reach of its
-    threshold (footprint, alpha_max, alpha_min, t_min), or whose L1 sign is
-    within reach of zero, has more than one correct result.  The oracle
-    computes the pixel under each outcome (colour, transmittance, blended
-    count, and its terms of every Gaussian's gradient and S); the GPU's colour
-    and blended count must match one of them, and the reference takes that
-    outcome's terms in place of the default ones.  The loss sign the GPU used
-    is its own float32 sign of C - target.  Outcomes the image cannot tell
-    apart (a clamp at alpha ~ alpha_max changes the gradient, not the colour)
-    are both accepted per Gaussian (every combination, up to four such pixels
-    per Gaussian; beyond that the Gaussian is left out).  Pixels with two or more such decisions
+    can take either way resolved instead of excluded (resolve_pixels): the
+    reference takes, at each such pixel, the outcome whose colour and blended
+    count the GPU's match.  The loss sign the GPU used is its own float32 sign
+    of C - target.  Outcomes the image cannot tell apart (a clamp at alpha ~
+    alpha_max changes the gradient, not the colour) are both accepted per
+    Gaussian (every combination, up to four such pixels per Gaussian; beyond
+    that the Gaussian is left out).  Pixels with two or more such decisions
     are excluded with the Gaussians they touch; pixels whose alpha float32
     cannot evaluate to the image bar (thin footprints seen along their long
     axis, pix_valunc) are checked, and their deviations counted, not failed.
@@ -205,113 +312,29 @@ def checked_reference(oracle, P, deg, cams, opts, g, target=None, dl_dimage=None
     if with_s6:
         out["S6"] = oracle.split6(P, deg, cams, opts, target, dl_dimage=dl_dimage).copy()
     nd, vu, sa = ref["pix_ndec"], ref["pix_valunc"], ref["pix_signamb"]
-    multi = nd >= 2
-    flagged = np.nonzero(((nd == 1) | ((sa > 0) & (dl_dimage is None))) & ~multi)[0]
-    pix_excl = multi.copy()
+    flagged = np.nonzero((nd >= 1) | vu | ((sa > 0) & (dl_dimage is None)))[0]
+    res = resolve_pixels(oracle, P, deg, cams, opts, target, flagged, g["image"], g["n_used"], dl_dimage=dl_dimage,
+                         with_s6=with_s6)
+    for p in res["rgb"]:
+        e = packed_index(cams, np.array([p]))[0]
+        out["image"][e] = res["rgb"][p]
+        out["T_final"][p] = res["T"][p]
+        out["n_used"][p] = res["used"][p]
+    for i, (dg, dS, dS6) in res["delta"].items():
+        out["grads"][:, i] += dg
+        out["S"][:, i] += dS
+        if with_s6:
+            out["S6"][:, i] += dS6
+    pix_excl = np.zeros(len(nd), bool)
+    pix_excl[list(res["excl_pix"])] = True
+    pix_soft = np.zeros(len(nd), bool)
+    pix_soft[list(res["soft_pix"])] = True
     gauss_excl = np.zeros(n, bool)
-    gauss_either = {}  # Gaussian -> list of (grad delta, S delta) alternatives
-    stats = dict(flagged=len(flagged), multi=int(multi.sum()), gpu_flipped=0, either=0, valunc=int(vu.sum()))
-    img_g = g["image"]
-    if len(flagged):
-        e = packed_index(cams, flagged)
-        if dl_dimage is None:
-            d32 = img_g[e].astype(np.float32) - np.asarray(target, np.float32)[e]
-            sg = np.sign(d32).astype(np.int32)
-        else:
-            sg = np.zeros((len(flagged), 3), np.int32)
-        pix_l, flip_l, sgn_l, role = [], [], [], []
-        for k, p in enumerate(flagged):
-            pix_l += [p, p]
-            flip_l += [-1, -1]
-            sgn_l += [[2, 2, 2], list(sg[k])]
-            role += [(k, "D"), (k, "A")]
-            if nd[p] == 1:
-                pix_l.append(p)
-                flip_l.append(0)
-                sgn_l.append(list(sg[k]))
-                role.append((k, "B"))
-        var = oracle.pixel_variants(P, deg, cams, opts, target, np.array(pix_l), np.array(flip_l), np.array(sgn_l),
-                                    dl_dimage=dl_dimage, with_s6=with_s6)
-        by = {}
-        for j, (k, r) in enumerate(role):
-            by.setdefault(k, {})[r] = j
-        for k, p in enumerate(flagged):
-            got = img_g[e[k]]
-            cand = []
-            for r in ("A", "B"):
-                if r not in by[k]:
-                    continue
-                j = by[k][r]
-                ok = (np.abs(got - var["rgb"][j]) <= 1e-5 + 1e-4 * np.abs(var["rgb"][j])).all()
-                ok &= int(g["n_used"][p]) == int(var["n_used"][j])
-                if ok:
-                    cand.append(j)
-            if not cand:
-                raise AssertionError(f"pixel {p}: the GPU's colour {got} / count {g['n_used'][p]} matches no outcome "
-                                     f"of its in-band decision: " +
-                                     ", ".join(f"{r}: {var['rgb'][by[k][r]]} / {var['n_used'][by[k][r]]}"
-                                               for r in ("A", "B") if r in by[k]))
-            jd = by[k]["D"]
-
-            def delta(j):
-                dg = {}
-                for gid, gr, Sv, *rest in (var["terms"][j],):
-                    for t, i in enumerate(gid):
-                        a = dg.setdefault(int(i), [np.zeros(P.shape[0]), np.zeros(9), np.zeros(21)])
-                        a[0] += gr[t]
-                        a[1] += Sv[t]
-                        if rest:
-                            a[2] += rest[0][t]
-                gid, gr, Sv, *rest = var["terms"][jd]
-                for t, i in enumerate(gid):
-                    a = dg.setdefault(int(i), [np.zeros(P.shape[0]), np.zeros(9), np.zeros(21)])
-                    a[0] -= gr[t]
-                    a[1] -= Sv[t]
-                    if rest:
-                        a[2] -= rest[0][t]
-                return dg
-
-            j = cand[0]
-            out["image"][e[k]] = var["rgb"][j]
-            out["T_final"][p] = var["T_final"][j]
-            out["n_used"][p] = var["n_used"][j]
-            if by[k].get("B") == j:
-                stats["gpu_flipped"] += 1
-            dg = delta(j)
-            for i, (dgr, dS, dS6) in dg.items():
-                out["grads"][:, i] += dgr
-                out["S"][:, i] += dS
-                if with_s6:
-                    out["S6"][:, i] += dS6
-            if len(cand) == 2:  # both outcomes fit the image: either is a correct gradient
-                stats["either"] += 1
-                d2 = delta(cand[1])
-                for i in set(dg) | set(d2):
-                    a = dg.get(i, [np.zeros(P.shape[0]), np.zeros(9), np.zeros(21)])
-                    b = d2.get(i, [np.zeros(P.shape[0]), np.zeros(9), np.zeros(21)])
-                    gauss_either.setdefault(i, []).append((b[0] - a[0], b[1] - a[1], b[2] - a[2]))
-    # Gaussians touched by excluded pixels (every outcome's contributors)
-    if multi.any():
-        mp = np.nonzero(multi)[0]
-        pl, fl = [], []
-        for p in mp:
-            for f in range(-1, int(nd[p])):
-                pl.append(p)
-                fl.append(f)
-        var = oracle.pixel_variants(P, deg, cams, opts, target, np.array(pl), np.array(fl),
-                                    np.full((len(pl), 3), 2), dl_dimage=dl_dimage)
-        for gid, *_ in var["terms"]:
-            gauss_excl[gid] = True
-    pix_soft = vu & ~pix_excl
+    gauss_excl[list(res["excl"])] = True
     gauss_soft = np.zeros(n, bool)
-    if pix_soft.any():
-        sp = np.nonzero(pix_soft)[0]
-        var = oracle.pixel_variants(P, deg, cams, opts, target, sp, -np.ones(len(sp), np.int32),
-                                    np.full((len(sp), 3), 2), dl_dimage=dl_dimage)
-        for gid, *_ in var["terms"]:
-            gauss_soft[gid] = True
-    out.update(pix_excl=pix_excl, gauss_excl=gauss_excl, gauss_either=gauss_either, pix_soft=pix_soft,
-               gauss_soft=gauss_soft & ~gauss_excl, stats=stats)
+    gauss_soft[list(res["soft"])] = True
+    out.update(pix_excl=pix_excl, gauss_excl=gauss_excl, gauss_either=res["either"], pix_soft=pix_soft & ~pix_excl,
+               gauss_soft=gauss_soft & ~gauss_excl, stats=res["stats"])
     return out
 
 
@@ -397,3 +420,108 @@ def _S_fails(S6_gpu, S9_ref, keep, rel, abs_frac, scale_from=None):
     top = np.linalg.norm(M_s.reshape(len(M_s), -1), axis=1)
     tol = rel * rn + abs_frac * (top[keep].max() if keep.any() else 0.0)
     return keep & (dn > tol)
+
+
+def _deviations(G, Rg, S6g, S9, keep, k, rel, abs_frac):
+    """(name, |d|, |ref|, tol) per parameter group and for S of sampled Gaussian k"""
+    out = []
+    for name, sl in GROUPS.items():
+        rn = np.linalg.norm(Rg[sl, k])
+        out.append((name, np.linalg.norm(G[sl, k] - Rg[sl, k]), rn,
+                    rel * rn + abs_frac * np.linalg.norm(Rg[sl][:, keep], axis=0).max()))
+    M_g = s6_to_mats(S6g)
+    M_r = s6_to_mats(s9_to_s6(S9))
+    rn = np.linalg.norm(M_r[k])
+    out.append(("S", np.linalg.norm(M_g[k] - M_r[k]), rn,
+                rel * rn + abs_frac * np.linalg.norm(M_r[keep].reshape(int(keep.sum()), -1), axis=1).max()))
+    return out
+
+
+def _fail_detail(G, Rg, S6g, S9, keep, k, rel, abs_frac):
+    """|d| / tol per parameter group and for S of sampled Gaussian k"""
+    return f"#{k}: " + ", ".join(f"{name} |d|={dn:.3e} |ref|={rn:.3e} tol={tol:.3e}"
+                                 for name, dn, rn, tol in _deviations(G, Rg, S6g, S9, keep, k, rel, abs_frac)
+                                 if dn > tol)
+
+
+def sampled_check(oracle, scene, opts, g_image, g_used, grads, S6, gids, what, rel=1e-3, abs_frac=1e-6):
+    """Gradients and S of sampled Gaussians of a full-size run against the
+    oracle's (every pixel of every tile they touch blended in full), with the
+    in-band decisions of those pixels resolved as in checked_reference.
+    grads [F][n], S6 [6][n] of the GPU.  Returns the fraction of the sample
+    left out (pixels with two or more in-band decisions) and the stats."""
+    gids = np.asarray(gids, np.int64)
+    g_ref, S_ref, _, flagged = oracle.grads_sampled(scene.params, scene.sh_degree, scene.cams, opts, scene.target,
+                                                    gids, flagged=True)
+    res = resolve_pixels(oracle, scene.params, scene.sh_degree, scene.cams, opts, scene.target, flagged, g_image,
+                         g_used)
+    pos = {int(i): k for k, i in enumerate(gids)}
+    for i, (dg, dS, _) in res["delta"].items():
+        if i in pos:
+            g_ref[pos[i]] += dg
+            S_ref[pos[i]] += dS
+    excl = np.array([int(i) in res["excl"] for i in gids])
+    soft = np.array([int(i) in res["soft"] for i in gids]) & ~excl
+    G = grads[:, gids]
+    Rg = g_ref.T.copy()
+    S9 = S_ref.T.copy()
+    keep = ~excl
+    fails = _group_fails(G, Rg, keep, rel, abs_frac) | _S_fails(S6[:, gids], S9, keep, rel, abs_frac)
+    for k in list(np.nonzero(fails)[0]):
+        alts = res["either"].get(int(gids[k]), [])
+        if not alts or len(alts) > 4:
+            continue
+        one = np.zeros(len(gids), bool)
+        one[k] = True
+        for mask in range(1, 1 << len(alts)):
+            R2, S2 = Rg.copy(), S9.copy()
+            for b, alt in enumerate(alts):
+                if (mask >> b) & 1:
+                    R2[:, k] += alt[0]
+                    S2[:, k] += alt[1]
+            if not (_group_fails(G, R2, one, rel, abs_frac, scale_from=Rg)[k] or
+                    _S_fails(S6[:, gids], S2, one, rel, abs_frac, scale_from=S9)[k]):
+                fails[k] = False
+                break
+    hard = fails & ~soft
+    assert not hard.any(), (f"{what}: sampled Gaussians {gids[hard]} out of tolerance: "
+                            + "; ".join(_fail_detail(G, Rg, S6[:, gids], S9, keep, k, rel, abs_frac)
+                                        for k in np.nonzero(hard)[0][:4]))
+    # the largest |d| / tol of the Gaussians whose deviation is left unchecked
+    # (pixels whose alpha float32 cannot evaluate to the image bar)
+    soft_worst = max([max(dn / tol for _, dn, _, tol in _deviations(G, Rg, S6[:, gids], S9, keep, k, rel, abs_frac))
+                      for k in np.nonzero(fails & soft)[0]], default=0.0)
+    st = dict(res["stats"], sampled=len(gids), excluded=float(excl.mean()), soft_dev=float((fails & soft).mean()),
+              soft_worst=round(float(soft_worst), 2), flagged_pixels=len(flagged))
+    print(f"[sampled] {what}: {st}", flush=True)
+    return st
+
+
+def sample_gaussians(oracle, scene, opts, rng, heavy_tiles=4, per_tile=4, needles=8, random=48, max_tiles=400):
+    """Gaussians to check at full size: members of the longest tile lists,
+    the most elongated footprints (largest condition number of the projected
+    covariance over the views), and random visible ones, all with at most
+    `max_tiles` tiles over all views (the oracle blends every pixel of them)"""
+    pr = oracle.project(scene.params, scene.sh_degree, scene.cams, opts)
+    V, n = scene.cams.V, scene.n
+    tiles = pr["tiles"].reshape(V, n).astype(np.int64)
+    tot = tiles.sum(0)
+    ok = (tot > 0) & (tot <= max_tiles)
+    a, b, c = pr["conic"][:, 0], pr["conic"][:, 1], pr["conic"][:, 2]
+    hi = 0.5 * (a + c) + np.sqrt(0.25 * (a - c) ** 2 + b * b)
+    lo = (a * c - b * b) / np.where(hi > 0, hi, 1.0)
+    kappa = np.where(pr["visible"] & (lo > 0), hi / np.where(lo > 0, lo, 1.0), 0.0).reshape(V, n).max(0)
+    picks = []
+    ln = np.zeros(1, np.int64)
+    if heavy_tiles > 0:
+        _, vals, ranges = oracle.sort(scene.params, scene.sh_degree, scene.cams, opts)
+        ln = ranges[:, 1].astype(np.int64) - ranges[:, 0].astype(np.int64)
+    for t in np.argsort(-ln)[:heavy_tiles]:
+        ids = np.unique(vals[ranges[t, 0]:ranges[t, 1]].astype(np.int64) % n)
+        ids = ids[ok[ids]]
+        picks += list(rng.choice(ids, size=min(per_tile, len(ids)), replace=False))
+    picks += list(np.argsort(-np.where(ok, kappa, 0.0))[:needles])
+    pool = np.setdiff1d(np.nonzero(ok)[0], picks)
+    picks += list(rng.choice(pool, size=min(random, len(pool)), replace=False))
+    return np.unique(np.asarray(picks, np.int64)), dict(heavy_tile_lengths=ln[np.argsort(-ln)[:heavy_tiles]].tolist(),
+                                                         max_kappa=float(kappa[ok].max()))

@@ -46,8 +46,20 @@ def test_project_and_sort(oracle, kind, mode):
     rect_hi = sp[:, 7].view(np.uint32)
     rect = np.stack([rect_lo & 0xFFFF, rect_lo >> 16, rect_hi & 0xFFFF, rect_hi >> 16], 1).astype(np.int32)
     np.testing.assert_array_equal(rect[vis], pr["rect"][vis])
-    np.testing.assert_array_equal(sp[vis, 11].view(np.uint32), pr["depth_bits"][vis])
+    # depth keys: the depth's float bits for a record with a non-empty tile
+    # rectangle, all ones for a culled one
+    dk = g["dkeys"][: len(vis)]
+    np.testing.assert_array_equal(dk[vis], pr["depth_bits"][vis])
+    assert ((dk == 0xFFFFFFFF) == (g["rect_tiles"][: len(vis)] == 0)).all()
     np.testing.assert_allclose(sp[vis, 0:2], pr["mean"][vis], rtol=2e-7, atol=1e-5)
+    # float32 mean + binary16 remainder: the projected mean to 2^-35 relative
+    lo = sp[:, 11].view(np.uint32)
+    rem = np.stack([(lo & 0xFFFF).astype(np.uint16).view(np.float16), (lo >> 16).astype(np.uint16).view(np.float16)],
+                   1).astype(np.float64)
+    full = sp[:, 0:2].astype(np.float64) + rem
+    m = pr["mean"][vis]
+    assert (np.abs(full[vis] - m) <= 2.0 ** -35 * np.abs(m) + 2.0 ** -24).all()
+    assert (np.abs(rem[vis]) <= 2.0 ** -24 * np.abs(m) + 1e-30).all()
     np.testing.assert_allclose(sp[vis, 2:5], pr["conic"][vis], rtol=2e-6, atol=1e-12)
     np.testing.assert_allclose(sp[vis, 5], pr["opacity"][vis], rtol=2e-7)
     np.testing.assert_allclose(sp[vis, 8:11], pr["rgb"][vis], rtol=2e-6, atol=1e-7)
@@ -169,33 +181,34 @@ def test_all_culled_and_empty(oracle):
 
 
 @pytest.mark.parametrize("kind", ["multiview", "extreme"])
-def test_sort_with_projected_depth_keys_matches_own_keys(oracle, kind):
-    # the depth keys written by the projection stage and the ones the sort
-    # forms itself order the records identically
+def test_sort_keys_match_oracle(oracle, kind):
+    # the optional 64-bit keys (tile << 32 | depth bits, from the projection's
+    # depth keys) and the values equal the oracle's; the sort refuses to run
+    # without the depth keys
     P, deg, cams, target = scene_small(kind)
     opts = scenes.opts("3dgs")
-    print(f"\n[case] sort with / without projected depth keys kind={kind}", flush=True)
+    print(f"\n[case] sort keys kind={kind}", flush=True)
     from paper_2505_05587_amd import _lib as L, pipeline
     dev = torch.device("cuda", 0)
     cb = pipeline.CameraBatch(cams, opts, dev)
     ras = pipeline.Rasterizer(cb, deg, capacity=1 << 16)
     ras.project(torch.from_numpy(P).to(dev))
-    outs = []
-    for dk in (ras.dkeys, None):
-        vals = torch.full((ras.capacity,), -1, dtype=torch.int32, device=dev)
-        ranges = torch.full_like(ras.ranges, -1)
-        keys = torch.zeros(ras.capacity, dtype=torch.int64, device=dev)
+    vals = torch.full((ras.capacity,), -1, dtype=torch.int32, device=dev)
+    ranges = torch.full_like(ras.ranges, -1)
+    keys = torch.zeros(ras.capacity, dtype=torch.int64, device=dev)
+    with pytest.raises(L.SteepGSError):
         L.steepgs_sort(ras.splats, ras.tiles, ras.n, cams.V, cb.dev, cb.opts, cb.total_tiles, keys, vals,
-                       ras.capacity, ranges, ras.num, ras.status, ras.ws_sort, depth_keys=dk)
-        torch.cuda.synchronize()
-        assert int(ras.status.item()) == L.OK
-        K = int(ras.num.item())
-        outs.append((K, vals[:K].cpu().numpy(), keys[:K].cpu().numpy(), ranges.cpu().numpy()))
-    assert outs[0][0] == outs[1][0] > 0
-    for a, b in zip(outs[0][1:], outs[1][1:]):
-        np.testing.assert_array_equal(a, b)
-    keys_ref, vals_ref, _ = oracle.sort(P, deg, cams, opts)
-    np.testing.assert_array_equal(outs[0][1].view(np.uint32), vals_ref)
+                       ras.capacity, ranges, ras.num, ras.status, ras.ws_sort, depth_keys=None)
+    L.steepgs_sort(ras.splats, ras.tiles, ras.n, cams.V, cb.dev, cb.opts, cb.total_tiles, keys, vals,
+                   ras.capacity, ranges, ras.num, ras.status, ras.ws_sort, depth_keys=ras.dkeys)
+    torch.cuda.synchronize()
+    assert int(ras.status.item()) == L.OK
+    K = int(ras.num.item())
+    keys_ref, vals_ref, ranges_ref = oracle.sort(P, deg, cams, opts)
+    assert K == len(keys_ref) > 0
+    np.testing.assert_array_equal(vals[:K].cpu().numpy().view(np.uint32), vals_ref)
+    np.testing.assert_array_equal(keys[:K].cpu().numpy().view(np.uint64), keys_ref)
+    np.testing.assert_array_equal(ranges.cpu().numpy().view(np.uint32).reshape(-1, 2), ranges_ref)
 
 
 @pytest.mark.parametrize("n", [0, 40])
