@@ -388,7 +388,9 @@ steepgs_status steepgs_set_kernel_timer(int32_t which, void* const* start_events
  * INVALID_ARG for a null d_out or a non-positive size. */
 steepgs_status steepgs_calibrate_valu(float* d_out, int32_t blocks, int32_t iters, void* stream);
 
-const char* steepgs_status_string(steepgs_status s);
+/* A static string naming status code `status` (any value: codes outside
+ * steepgs_status give "unknown status"). */
+const char* steepgs_status_string(int32_t status);
 const char* steepgs_version(void);
 
 #ifdef __cplusplus

@@ -17,7 +17,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "oracle.cpp")
-LIB = os.path.join(HERE, "liboracle.so")
+# STEEPGS_ORACLE_LIB: another build of oracle.cpp (the sanitizer test's), loaded as is
+LIB_OVERRIDE = os.environ.get("STEEPGS_ORACLE_LIB")
+LIB = LIB_OVERRIDE or os.path.join(HERE, "liboracle.so")
 
 _c_f32 = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
 _c_f64 = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
@@ -47,7 +49,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        build(force=False)
+        if not LIB_OVERRIDE:
+            build(force=False)
         L = C.CDLL(LIB)
         common = [_c_f32, C.c_int64, C.c_int, _c_f32, _c_i32, C.c_int, _c_f64]
         L.orc_project.argtypes = common + [_c_f64, _c_i32, _c_u32, _c_u32, _c_u8]

@@ -129,8 +129,8 @@ extern "C" steepgs_status steepgs_layout_cameras(steepgs_camera* cams, int32_t V
   return STEEPGS_OK;
 }
 
-extern "C" const char* steepgs_status_string(steepgs_status s) {
-  switch (s) {
+extern "C" const char* steepgs_status_string(int32_t status) {
+  switch (status) {
     case STEEPGS_OK: return "ok";
     case STEEPGS_ERR_INVALID_ARG: return "invalid argument";
     case STEEPGS_ERR_CAPACITY: return "output capacity exceeded";

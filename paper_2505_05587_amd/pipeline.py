@@ -110,7 +110,8 @@ class Rasterizer:
             self.capacity = max(capacity, self.capacity, 1)
             self.vals = torch.empty(self.capacity, dtype=torch.int32, device=self.dev)
             self.ws_sort = torch.empty(
-                L.steepgs_workspace_size(L.STAGE_SORT, n, V, self.capacity) // 4 + 64, dtype=torch.int32,
+                L.steepgs_workspace_size(L.STAGE_SORT, n, V, self.capacity, self.cams.total_tiles) // 4 + 64,
+                dtype=torch.int32,
                 device=self.dev)
 
     # -- stages -------------------------------------------------------------
