@@ -188,6 +188,15 @@ SG_DEV float footprint_power2_cut(const steepgs_opts& opt) {
   return -0.72134752044448170368f * opt.radius_sigmas * opt.radius_sigmas;
 }
 
+// The two per-pixel tests of an entry in one: inside the footprint and
+// alpha = o 2^power >= alpha_min (alpha_max > alpha_min does not change the
+// second), i.e. power >= max(cut, log2(alpha_min / o)).  The log2 form moves
+// the alpha_min decision only within float32 rounding of alpha.  The forward
+// and backward raster kernels take this one per-entry value.
+SG_DEV float entry_power2_min(float o, float cut, const steepgs_opts& opt) {
+  return opt.alpha_min > 0.f ? fmaxf(cut, __log2f(opt.alpha_min) - __log2f(o)) : cut;
+}
+
 // Half-extents of the region where a pixel can contribute: inside the
 // footprint and alpha >= alpha_min, the ellipse d^T A d <= t with
 // t = min(radius_sigmas^2, 2 ln(o / alpha_min)); its x half-width is

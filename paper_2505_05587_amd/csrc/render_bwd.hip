@@ -34,13 +34,16 @@
 namespace sg {
 
 // The backward's per-record accumulators (fp64 sums of the per-tile float32
-// partials): slot [m][9] = (m1_x, m1_y, m2_xx, m2_xy, m2_yy, dL/do, dL/dr,
-// dL/dg, dL/db), one 72-byte block per record so that the nine atomics of a
+// partials): slot [m][9] = (m1_l, m1_s, m2_ll, m2_ls, m2_ss, m0, dL/dr,
+// dL/dg, dL/db) -- the first moments and second moments of g alpha d in the
+// frame of the footprint's axis (l along it, s across), m0 = sum g alpha
+// = o dL/do over the unclamped pixels -- one 72-byte block per record so that the nine atomics of a
 // (tile, entry) touch one or two cache lines (planar geometry and colour
 // arrays were measured 0.1 ms slower in the raster backward on the 16-view
 // workload).  With the splitting matrix over theta = (p, log-scales) a
-// second array h6 [m][9] holds the third and fourth moments (m3_xxx, m3_xxy,
-// m3_xyy, m3_yyy, m4_xxxx, m4_xxxy, m4_xxyy, m4_xyyy, m4_yyyy).
+// second array h6 [m][9] holds the third and fourth moments in the same
+// frame (m3_lll, m3_lls, m3_lss, m3_sss, m4_llll, m4_llls, m4_llss, m4_lsss,
+// m4_ssss).
 struct Slots {
   double* slot;
   double* h6;
@@ -76,6 +79,7 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
   __shared__ float4 s_a[WAVES][64];  // float32 mean x, y, long axis x, y
   __shared__ float4 s_c[WAVES][64];  // e_long, e_short, opacity, red
   __shared__ float4 s_e[WAVES][64];  // green, blue, remainder constants cl, cs
+  __shared__ float s_t[WAVES][64];   // smallest power2 taken (entry_power2_min)
   __shared__ uint32_t s_id[WAVES][64];  // record id
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lx = lane & 7, ly = lane >> 3;
@@ -84,6 +88,7 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
   float4* const Cq = s_c[wave];
   float4* const E = s_e[wave];
   uint32_t* const Id = s_id[wave];
+  float* const Th = s_t[wave];
   const float cut = footprint_power2_cut(opt);
   for (;;) {
     // the wave barrier keeps the lane-0 fetch inside the loop
@@ -155,6 +160,7 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
         A[lane] = make_float4(sp.mean_x, sp.mean_y, sp.axis_x, sp.axis_y);
         Cq[lane] = make_float4(sp.e_long, sp.e_short, sp.opacity, sp.rgb[0]);
         E[lane] = make_float4(sp.rgb[1], sp.rgb[2], rc.x, rc.y);
+        Th[lane] = entry_power2_min(sp.opacity, cut, opt);
         Id[lane] = id;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
@@ -186,16 +192,18 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
         const float4 cq = Cq[j];
         const uint32_t pos = (uint32_t)(b_start + j);
         const float4 ej = E[j];  // green, blue, cl, cs
+        const float pmin = Th[j];
         // moments of g alpha d over the tile's pixels, in the frame of the
         // footprint's axes (pl = axis . d, ps = axis_perp . d, d the offset
         // from the exact mean: for a thin footprint the moments across it
         // would cancel to nothing in pixel coordinates; the lift turns them
         // into pixel coordinates in fp64; the mean and conic gradients are
-        // linear in them), opacity and colour gradients.  The
+        // linear in them), sum of g alpha (the opacity gradient times o) and
+        // colour gradients.  The
         // per-pixel work is predicated (selects, no divergent branch), so the
         // sums are updated in place; a quadrant is skipped as a whole when
         // the entry is outside its reach or no pixel of it takes the entry.
-        float mx = 0.f, my = 0.f, mxx = 0.f, mxy = 0.f, myy = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
+        float mx = 0.f, my = 0.f, mxx = 0.f, mxy = 0.f, myy = 0.f, s0 = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
         float h3[4] = {0.f, 0.f, 0.f, 0.f}, h4[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
         uint64_t took = 0;
 #pragma unroll
@@ -206,41 +214,39 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
           // offsets from the exact mean along and across the footprint's axis
           float pl, ps;
           const float power = splat_power2_axes(dx, dy, a.z, a.w, ej.z, ej.w, cq.x, cq.y, pl, ps);
-          const float G = __builtin_amdgcn_exp2f(power);
-          const float raw = cq.z * G;
+          const float raw = cq.z * __builtin_amdgcn_exp2f(power);
           const bool clamped = raw > opt.alpha_max;
-          const float alpha = fminf(opt.alpha_max, raw);
+          const float alpha = clamped ? opt.alpha_max : raw;  // min(alpha_max, raw): raw is finite
           // entries at or past the pixel's last contributor (or outside the
-          // image) and those below the cut-off were skipped by the forward
-          const bool c = pos < last[q] && power >= cut && alpha >= opt.alpha_min;
-          const uint64_t cm = __builtin_amdgcn_ballot_w64(c);
+          // image) and those below the cut-offs were skipped by the forward
+          const uint64_t cm = ballot(pos < last[q]) & ballot(power >= pmin);
           if (!cm) continue;
           took |= cm;
+          // the rest runs under the taking lanes' mask
+          if (!__builtin_amdgcn_inverse_ballot_w64(cm)) continue;
           // transmittance in front of this entry, T_i = T_{i+1} / (1 - alpha_i),
-          // with the hardware reciprocal (within 1 ulp); alpha <= 1 - 2^-24 on
-          // every lane (the host caps alpha_max below one), so the lanes that
-          // do not take the entry stay finite
+          // with the hardware reciprocal (within 1 ulp); alpha <= 1 - 2^-24
+          // (the host caps alpha_max below one)
           const float inv_om = __builtin_amdgcn_rcpf(1.f - alpha);
           const float Ti = T[q] * inv_om;
           // g = dL/dalpha_i = sum_c dL/dC_c (c_c T_i - R_c / (1 - alpha_i))
           const float x = dC[q][0] * cq.w + dC[q][1] * ej.x + dC[q][2] * ej.y;
           const float g = Ti * x - D[q] * inv_om;
-          const float w = c ? alpha * Ti : 0.f;
-          T[q] = c ? Ti : T[q];
+          const float w = alpha * Ti;
+          T[q] = Ti;
           D[q] += x * w;
           gr += w * dC[q][0];
           gg += w * dC[q][1];
           gbl += w * dC[q][2];
           // the clamped alpha does not depend on the mean, conic or opacity
-          const bool lin = c && !clamped;
-          const float gaw = lin ? g * alpha : 0.f;
+          const float gaw = clamped ? 0.f : g * alpha;
           const float tx = gaw * pl, ty = gaw * ps;
           mx += tx;
           my += ty;
           mxx += tx * pl;
           mxy += tx * ps;
           myy += ty * ps;
-          go += lin ? g * G : 0.f;
+          s0 += gaw;  // dL/do = sum g G = s0 / o
           if (H6) {
             const float txx = tx * pl, tyy = ty * ps;
             h3[0] += txx * pl;
@@ -260,7 +266,7 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
           // nine-lane fp64 atomic into the record's slot: the sums over the
           // tiles of a footprint are exact up to fp64 rounding, so their
           // hardware-chosen order leaves the float32 results unchanged
-          const float part[9] = {mx, my, mxx, mxy, myy, go, gr, gg, gbl};
+          const float part[9] = {mx, my, mxx, mxy, myy, s0, gr, gg, gbl};
           const float tot = reduce9(part);
           const int64_t rid = (int64_t)Id[j];
           if (red_idx >= 0) unsafeAtomicAdd(g2d.slot + rid * kSlot + red_idx, (double)tot);
@@ -494,9 +500,9 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) k
       if (!((vis >> k) & 1u)) continue;
       const int v = v0 + k;
       const double* slot = g2d + ((int64_t)v * n + i) * kSlot;
-      const double go = slot[5];
+      const double m0 = slot[5];  // sum g alpha = o dL/do
       double m1x = slot[0], m1y = slot[1], m2xx = slot[2], m2xy = slot[3], m2yy = slot[4];
-      if (m1x == 0.0 && m1y == 0.0 && m2xx == 0.0 && m2xy == 0.0 && m2yy == 0.0 && go == 0.0) continue;
+      if (m1x == 0.0 && m1y == 0.0 && m2xx == 0.0 && m2xy == 0.0 && m2yy == 0.0 && m0 == 0.0) continue;
       any = true;
       axis_to_pixel_moments2(m1x, m1y, m2xx, m2xy, m2yy, splats[(int64_t)v * n + i].axis_x,
                              splats[(int64_t)v * n + i].axis_y);
@@ -607,14 +613,13 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) k
           for (int c = 0; c < 3; ++c) Pe[a][c] = P[a][c];
       }
       for (int c = 0; c < 3; ++c) dp[c] += W[c] * dpc[0] + W[3 + c] * dpc[1] + W[6 + c] * dpc[2];
-      dop += go;
+      dop += m0 / o;
 
-      // splitting matrix: S2D = A M A - m0 A, M = m2, m0 = o * go
+      // splitting matrix: S2D = A M A - m0 A, M = m2
       const double M[2][2] = {{m2xx, m2xy}, {m2xy, m2yy}};
       double AM[2][2], S2D[2][2];
       for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) AM[a][b] = A[a][0] * M[0][b] + A[a][1] * M[1][b];
-      const double m0 = o * go;
       for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) S2D[a][b] = AM[a][0] * A[0][b] + AM[a][1] * A[1][b] - m0 * A[a][b];
       double SP[2][3];
@@ -720,10 +725,10 @@ __global__ void __launch_bounds__(128) k_split6_lift(const float* __restrict__ p
     if (tiles[r] == 0) continue;
     const double* slot = g2d + r * kSlot;
     const double* hs = h6 + r * kH6;
-    const double go = slot[5];
-    if (slot[0] == 0.0 && slot[1] == 0.0 && slot[2] == 0.0 && slot[3] == 0.0 && slot[4] == 0.0 && go == 0.0) continue;
+    const double m0 = slot[5];  // sum g alpha
+    if (slot[0] == 0.0 && slot[1] == 0.0 && slot[2] == 0.0 && slot[3] == 0.0 && slot[4] == 0.0 && m0 == 0.0) continue;
     // mom[a][b] = sum g alpha dx^a dy^b, from the moments along and across the axis
-    double mom[5][5] = {{o * go, slot[1], slot[4], hs[3], hs[8]},
+    double mom[5][5] = {{m0, slot[1], slot[4], hs[3], hs[8]},
                         {slot[0], slot[3], hs[2], hs[7], 0.0},
                         {slot[2], hs[1], hs[6], 0.0, 0.0},
                         {hs[0], hs[5], 0.0, 0.0, 0.0},
@@ -781,7 +786,6 @@ __global__ void __launch_bounds__(128) k_split6_lift(const float* __restrict__ p
     }
     const double idet = 1.0 / (c00 * c11 - c01 * c01);
     const double A[2][2] = {{c11 * idet, -c01 * idet}, {-c01 * idet, c00 * idet}};
-    const double m0 = o * go;
     double ak[3][2];
     for (int k = 0; k < 3; ++k)
       for (int a = 0; a < 2; ++a) ak[k][a] = A[a][0] * wv[k][0] + A[a][1] * wv[k][1];
@@ -855,8 +859,11 @@ __global__ void k_export2d(const steepgs_splat* __restrict__ splats, const uint3
       v[2] = (float)(-0.5 * m2xx);
       v[3] = (float)(-m2xy);
       v[4] = (float)(-0.5 * m2yy);
+      // slot[5] = sum g alpha = o dL/do
+      const double o = splats[r].opacity;
+      v[5] = o > 0.0 ? (float)(slot[5] / o) : 0.f;
 #pragma unroll
-      for (int k = 5; k < 9; ++k) v[k] = (float)slot[k];
+      for (int k = 6; k < 9; ++k) v[k] = (float)slot[k];
     }
 #pragma unroll
     for (int k = 0; k < kGrad2dOut; ++k) o[k] = v[k];

@@ -22,7 +22,7 @@ namespace sg {
 // Occupancy target of the blend kernels (wavefronts per SIMD), which sets
 // their register budget (a build option: 512 / target registers per lane)
 #ifndef SG_FWD_WAVES_PER_EU
-#define SG_FWD_WAVES_PER_EU 7
+#define SG_FWD_WAVES_PER_EU 6
 #endif
 
 template <int TW, int TH, bool COUNT, int WAVES>
@@ -41,12 +41,15 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
   __shared__ float4 s_a[WAVES][64];  // float32 mean x, y, long axis x, y
   __shared__ float4 s_c[WAVES][64];  // e_long, e_short, opacity, red
   __shared__ float4 s_b[WAVES][64];  // green, blue, remainder constants cl, cs
+  __shared__ float s_t[WAVES][64];   // smallest power2 taken (entry_power2_min)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lx = lane & 7, ly = lane >> 3;
   float4* const A = s_a[wave];
   float4* const Cq = s_c[wave];
   float4* const Bl = s_b[wave];
+  float* const Th = s_t[wave];
   const float cut = footprint_power2_cut(opt);
+  const int tmin_bits = __float_as_int(opt.t_min);
   for (;;) {
     // the wave barrier keeps the lane-0 fetch inside the loop
     __builtin_amdgcn_wave_barrier();
@@ -62,20 +65,22 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
     const uint32_t begin = ranges[2 * tile], end = ranges[2 * tile + 1];
     float T[NQ], C[NQ][3];
     uint32_t last[NQ], used[NQ];
-    bool done[NQ];
+    // per quadrant, the lanes whose pixel is finished (outside the image, or
+    // stopped at the transmittance cut-off): wave-uniform lane masks
+    uint64_t done[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int px = tx0 + (q % QX) * 8 + lx, py = ty0 + (q / QX) * 8 + ly;
       T[q] = 1.f;
       C[q][0] = C[q][1] = C[q][2] = 0.f;
       last[q] = used[q] = 0;
-      done[q] = !(px < W && py < H);
+      done[q] = ballot(!(px < W && py < H));
     }
     for (uint32_t b0 = begin; b0 < end; b0 += 64) {
       // quadrants with a pixel still open (wave-uniform)
       uint32_t alive = 0;
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) alive |= ballot(!done[q]) ? (1u << q) : 0u;
+      for (int q = 0; q < NQ; ++q) alive |= ~done[q] ? (1u << q) : 0u;
       alive = __builtin_amdgcn_readfirstlane(alive);
       if (!alive) break;
       // stage one batch of 64 entries in the wave's LDS slice; the loading
@@ -96,6 +101,7 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
         A[lane] = make_float4(sp.mean_x, sp.mean_y, sp.axis_x, sp.axis_y);
         Cq[lane] = make_float4(sp.e_long, sp.e_short, sp.opacity, sp.rgb[0]);
         Bl[lane] = make_float4(sp.rgb[1], sp.rgb[2], rc.x, rc.y);
+        Th[lane] = entry_power2_min(sp.opacity, cut, opt);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
           const float x0 = (float)(tx0 + (q % QX) * 8), y0 = (float)(ty0 + (q / QX) * 8);
@@ -121,7 +127,11 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
         const float4 a = A[j];
         const float4 cq = Cq[j];
         const float4 gb = Bl[j];  // green, blue, cl, cs
-        const uint32_t pos1 = b0 - begin + (uint32_t)j + 1u;
+        const float pmin = Th[j];
+        // the entry's 1-based position in the tile's list, in a vector
+        // register once for all quadrants
+        uint32_t pos1;
+        asm volatile("v_mov_b32 %0, %1" : "=v"(pos1) : "s"(b0 - begin + (uint32_t)j + 1u));
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
           if (!((qm[q] >> j) & 1ull)) continue;  // wave-uniform
@@ -130,14 +140,18 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
           const float dy = (float)(ty0 + (q / QX) * 8 + ly) - a.y;
           const float power = splat_power2(dx, dy, a.z, a.w, gb.z, gb.w, cq.x, cq.y);
           const float alpha = fminf(opt.alpha_max, cq.z * __builtin_amdgcn_exp2f(power));
-          bool c = !done[q] && power >= cut && alpha >= opt.alpha_min;
-          const float Tn = T[q] * (1.f - alpha);
-          const bool stop = c && Tn < opt.t_min;  // would cross the cut-off: excluded, pixel done
-          done[q] = done[q] || stop;
-          c = c && !stop;
+          const uint64_t in = ballot(power >= pmin) & ~done[q];
+          // T after the entry: T - alpha T (the weight alpha T is needed anyway)
+          const float wt = alpha * T[q];
+          const float Tn = T[q] - wt;
+          // else: would cross the cut-off, excluded, pixel done (Tn, t_min >= 0:
+          // their float bits order as integers)
+          const uint64_t keep = ballot(__float_as_int(Tn) >= tmin_bits);
+          done[q] |= in & ~keep;
+          const bool c = __builtin_amdgcn_inverse_ballot_w64(in & keep);
           // the weight is zero for a pixel that does not take the entry, so
           // the colour sums need no select (fma(colour, 0, C) = C)
-          const float w = c ? alpha * T[q] : 0.f;
+          const float w = c ? wt : 0.f;
           C[q][0] += cq.w * w;
           C[q][1] += gb.x * w;
           C[q][2] += gb.y * w;
