@@ -83,6 +83,49 @@ def test_pinhole_covariance_uses_local_affine_map(oracle):
                                                      cams.fy[0] * pc[1] / pc[2] + cams.cy[0]], rtol=1e-14)
 
 
+def test_frustum_guard_clamps_the_local_affine_map(oracle):
+    # Gaussians seen far off-axis: the local affine map J is taken at the
+    # projected direction clamped to guard * (half image size / focal length)
+    # per axis, while the mean still projects exactly.  Built here from the
+    # camera pose with the clamp written out, and without the guard from the
+    # unclamped direction (the two differ: the clamp is active).
+    rng = np.random.default_rng(12)
+    cams = pinhole_camera(64, pos=(0.0, 0.0, 3.0))
+    Rc, t = cams.R[0].astype(np.float64), cams.t[0].astype(np.float64)
+    fx, fy, W, H = float(cams.fx[0]), float(cams.fy[0]), int(cams.width[0]), int(cams.height[0])
+    # camera-space centres well beyond the guard on x, on y and on both
+    pcs = np.array([[1.3, 0.05, 1.5], [-0.1, -1.4, 1.7], [1.6, 1.5, 2.0], [-1.8, 0.2, 2.2], [0.2, 0.1, 2.0]])
+    n = len(pcs)
+    means = (Rc.T @ (pcs - t).T).T
+    g = _rand_gauss(rng, n)
+    ls = np.full((n, 3), np.log(0.35))  # large enough that the footprint reaches the image
+    P = pack_params(means, ls, g[2], g[3], g[4], 0)
+    dil = 0.3
+    for guard in (1.3, 0.0):
+        opts = scenes.opts("smooth", dilation=dil, radius_sigmas=1e3, frustum_guard=guard)
+        pr = oracle.project(P, 0, cams, opts)
+        for i in range(n):
+            pc = Rc @ P[0:3, i].astype(np.float64) + t
+            gx, gy = pc[0] / pc[2], pc[1] / pc[2]
+            if guard > 0:
+                g32 = float(np.float32(guard))  # the options are float32
+                lx, ly = g32 * (0.5 * W / fx), g32 * (0.5 * H / fy)
+                gx, gy = min(max(gx, -lx), lx), min(max(gy, -ly), ly)
+            J = np.array([[fx / pc[2], 0.0, -fx * gx / pc[2]], [0.0, fy / pc[2], -fy * gy / pc[2]]])
+            Pm = J @ Rc
+            expect = Pm @ _covariance_scipy(P, i) @ Pm.T + float(np.float32(dil)) * np.eye(2)
+            np.testing.assert_allclose(_sigma2d_from_conic(pr, i), expect, rtol=1e-9)
+            np.testing.assert_allclose(pr["mean"][i], [fx * pc[0] / pc[2] + cams.cx[0], fy * pc[1] / pc[2] + cams.cy[0]],
+                                       rtol=1e-13)
+        if guard > 0:
+            guarded = [_sigma2d_from_conic(pr, i) for i in range(n)]
+        else:
+            # the last centre is inside the guard: the same with and without it
+            for i in range(n):
+                d = np.abs(_sigma2d_from_conic(pr, i) - guarded[i]).max()
+                assert (d == 0.0) if i == n - 1 else (d > 1e-3 * np.abs(guarded[i]).max())
+
+
 def test_opacity_and_dc_colour(oracle):
     rng = np.random.default_rng(12)
     g = _rand_gauss(rng, 10)
