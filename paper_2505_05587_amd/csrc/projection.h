@@ -127,8 +127,9 @@ SG_DEV double box_min_q(double a, double b, double c, double mx, double my, doub
 
 // A tile belongs to a Gaussian's footprint when its box of pixel centres
 // meets the ellipse q <= radius_sigmas^2 (1e-6 relative slack).  Evaluated on
-// the stored float32 mean and conic, so the projection (which counts the
-// tiles) and the instance emission (which lists them) take the same decision.
+// the stored float32 mean and conic, so that any consumer of the record (the
+// sort's walk and emission here, the oracle's tile lists) takes the same
+// decision.
 SG_DEV bool tile_hit_fp64(float mx, float my, float a, float b, float c, const steepgs_opts& opt, int tx, int ty) {
 #pragma clang fp contract(off)
   const double k2 = (double)opt.radius_sigmas * (double)opt.radius_sigmas;
@@ -149,16 +150,9 @@ SG_DEV bool tile_hit_fp64(float mx, float my, float a, float b, float c, const s
 // below the threshold the tile is hit; when every evaluated face's estimate
 // minus that bound is above it the tile is missed; otherwise the fp64 rule
 // decides.  Mean inside the box: hit (the same comparisons either way).
-// Result identical to tile_hit_fp64.
-SG_DEV bool tile_hit_rcp(float mx, float my, float a, float b, float c, float ia, float ic, const steepgs_opts& opt,
-                         int tx, int ty);
-SG_DEV bool tile_hit(float mx, float my, float a, float b, float c, const steepgs_opts& opt, int tx, int ty) {
-  return tile_hit_rcp(mx, my, a, b, c, 1.f / a, 1.f / c, opt, tx, ty);
-}
-
-// tile_hit with the reciprocals 1/a and 1/c supplied (the edge minimiser is
-// a product instead of a division; its rounding enters the edge value only
-// at second order, inside the certified bound)
+// Result identical to tile_hit_fp64.  ia, ic: the reciprocals 1/a and 1/c
+// (the edge minimiser is a product instead of a division; its rounding
+// enters the edge value only at second order, inside the certified bound).
 SG_DEV bool tile_hit_rcp(float mx, float my, float a, float b, float c, float ia, float ic, const steepgs_opts& opt,
                          int tx, int ty) {
   const float x0 = (float)(tx * opt.tile_w), x1 = (float)(tx * opt.tile_w + opt.tile_w - 1);

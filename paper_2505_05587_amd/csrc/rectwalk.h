@@ -1,6 +1,6 @@
 // Cooperative walk of one wavefront over the tile rectangles of 64
-// consecutive records, shared by the footprint tile count (projection) and the
-// instance emission (sort).
+// consecutive records (the footprint walk and the instance emission of the
+// sort).
 //
 // The rectangles are laid end to end (exclusive prefix `aoff` of their
 // areas); chunk j0 .. j0+63 of that sequence goes to lanes 0..63.  The owner
@@ -9,8 +9,8 @@
 // ballot over the table marks the starts, and a lane takes the nearest start
 // at or below its position (or the record carried over from the previous
 // chunk).  The owner's record is read from the wavefront's LDS slice.  Each
-// position's tile is tested against the footprint ellipse (tile_hit) and
-// handed to the caller's visitor in order.
+// position's tile is then tested against the footprint ellipse
+// (tile_hit_rcp) by the caller.
 #pragma once
 
 #include "projection.h"
@@ -32,7 +32,7 @@ struct RectRec {
 // The rectangle a record's walk covers: its stored tile rectangle (a square
 // of radius 3 sqrt(lambda_max) around the mean) cut down to the tiles whose
 // boxes of pixel centres meet the bounding box of the footprint ellipse
-// d^T A d <= radius_sigmas^2 (1 + 1e-6) -- the only tiles tile_hit can
+// d^T A d <= radius_sigmas^2 (1 + 1e-6) -- the only tiles tile_hit_rcp can
 // accept.  The half-widths sqrt(t A^-1_xx), sqrt(t A^-1_yy) come from the
 // stored float conic (determinant in fp64, then fp32) and are widened by
 // 1e-4 relative and 1e-2 px, far above their rounding.  Fills the record's
@@ -153,25 +153,6 @@ SG_DEV int rect_walk_locate(RectWalkLds& L, int lane, uint32_t area, uint32_t ao
   tx = (int)(xy0 & 0xFFFFu) + col;
   ty = (int)(xy0 >> 16) + row;
   return owner;
-}
-
-// `visit(owner_lane, rec, tx, ty, hit)` is called once per chunk with every
-// lane active (hit false beyond the last position).  Returns the total area.
-template <class Visit>
-SG_DEV uint32_t rect_walk(RectWalkLds& L, int lane, uint32_t area, const RectRec& mine, const steepgs_opts& opt,
-                          Visit&& visit) {
-  uint32_t aoff;
-  const uint32_t atotal = rect_walk_begin(L, lane, area, mine, aoff);
-  int carry = 0;
-  for (uint32_t j0 = 0; j0 < atotal; j0 += 64) {
-    int tx, ty;
-    const int owner = rect_walk_locate(L, lane, area, aoff, j0, carry, tx, ty);
-    const RectRec R = L.get(owner);
-    const bool hit = j0 + (uint32_t)lane < atotal && tile_hit_rcp(R.mx, R.my, R.a, R.b, R.c, R.ia, R.ic, opt, tx, ty);
-    visit(owner, R, tx, ty, hit);
-    __builtin_amdgcn_wave_barrier();
-  }
-  return atotal;
 }
 
 }  // namespace sg
