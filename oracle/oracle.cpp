@@ -333,12 +333,13 @@ void project(const T* th, int deg, const Cam& cam, const Opts& opt, Proj<T>& out
       gx = clamp_(gx, -limx, limx);
       gy = clamp_(gy, -limy, limy);
     }
-    J[0][0] = cam.fx / pc[2];
+    const T iz = 1.0 / pc[2];
+    J[0][0] = cam.fx * iz;
     J[0][1] = T(0.0);
-    J[0][2] = -(cam.fx * gx) / pc[2];
+    J[0][2] = -(cam.fx * gx) * iz;
     J[1][0] = T(0.0);
-    J[1][1] = cam.fy / pc[2];
-    J[1][2] = -(cam.fy * gy) / pc[2];
+    J[1][1] = cam.fy * iz;
+    J[1][2] = -(cam.fy * gy) * iz;
   } else {
     out.mx = cam.fx * pc[0] + cam.cx;
     out.my = cam.fy * pc[1] + cam.cy;
@@ -369,21 +370,24 @@ void project(const T* th, int deg, const Cam& cam, const Opts& opt, Proj<T>& out
         out.Pe[a][c] = Je[a][0] * cam.R[0 + c] + Je[a][1] * cam.R[3 + c] + Je[a][2] * cam.R[6 + c];
       }
   }
-  T S2[2][2];
+  // (P Sigma) P^T; the matrix is symmetric, so its lower entry is the upper one
+  T PS[2][3];
   for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) {
-      T acc(0.0);
-      for (int c = 0; c < 3; ++c)
-        for (int d = 0; d < 3; ++d) acc = acc + P[a][c] * Sig[c][d] * P[b][d];
-      S2[a][b] = acc;
-    }
+    for (int d = 0; d < 3; ++d) PS[a][d] = P[a][0] * Sig[0][d] + P[a][1] * Sig[1][d] + P[a][2] * Sig[2][d];
+  T S2[2][2];
+  S2[0][0] = PS[0][0] * P[0][0] + PS[0][1] * P[0][1] + PS[0][2] * P[0][2];
+  S2[0][1] = PS[0][0] * P[1][0] + PS[0][1] * P[1][1] + PS[0][2] * P[1][2];
+  S2[1][1] = PS[1][0] * P[1][0] + PS[1][1] * P[1][1] + PS[1][2] * P[1][2];
+  S2[1][0] = S2[0][1];
   S2[0][0] = S2[0][0] + opt.dilation;
   S2[1][1] = S2[1][1] + opt.dilation;
   T det = S2[0][0] * S2[1][1] - S2[0][1] * S2[1][0];
   if (!(val(det) > 0.0)) return;
-  out.A00 = S2[1][1] / det;
-  out.A01 = -S2[0][1] / det;
-  out.A11 = S2[0][0] / det;
+  // the conic A = Pi(Sigma)^-1 through one reciprocal of the determinant
+  const T idet = 1.0 / det;
+  out.A00 = S2[1][1] * idet;
+  out.A01 = -S2[0][1] * idet;
+  out.A11 = S2[0][0] * idet;
 
   // footprint: radius_sigmas standard deviations along the major axis, in
   // whole pixels; tiles whose pixel span meets [m - r, m + r]

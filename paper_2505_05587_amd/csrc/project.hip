@@ -8,8 +8,10 @@ namespace sg {
 
 // One thread per Gaussian loops over the views; the Gaussian's SH
 // coefficients are staged once in the thread's own LDS column, so every view
-// reads them from LDS instead of HBM.
+// reads them from LDS instead of HBM.  The per-view camera constants (centre,
+// guard limits) are computed once per workgroup for a chunk of views.
 constexpr int kProjThreads = 128;
+constexpr int kCamChunk = 8;
 
 template <int D>
 __global__ void __launch_bounds__(kProjThreads) k_project(const float* __restrict__ params, int64_t n,
@@ -18,67 +20,93 @@ __global__ void __launch_bounds__(kProjThreads) k_project(const float* __restric
                                                           uint32_t* __restrict__ tiles, uint32_t* __restrict__ dkeys) {
   constexpr int NS = 3 * (D + 1) * (D + 1);
   __shared__ float s_sh[NS * kProjThreads];  // [coefficient][thread]
+  __shared__ double s_cc[kCamChunk * kCamConsts];
   const int tid = threadIdx.x;
   const int64_t i = (int64_t)blockIdx.x * kProjThreads + tid;
-  if (i >= n) return;  // no barrier below: each thread touches only its own column
+  const bool active = i < n;
   float* const sh = s_sh + tid;
-#pragma unroll
-  for (int k = 0; k < NS; ++k) sh[k * kProjThreads] = params[(STEEPGS_ROW_SH + k) * n + i];
   Gauss g;
-  load_gauss(params, n, i, g);
-  for (int v = 0; v < V; ++v) {
-    CamD cam;
-    load_cam(cams[v], cam);
-    ViewProj pv;
-    const int64_t r = (int64_t)v * n + i;
-    steepgs_splat s;
-    uint32_t count = 0;
-    float depth = 0.f;
-    if (project_view(g, cam, opt, pv)) {
-      double rgb[3];
-      view_colour<D>(g, cam, sh, kProjThreads, rgb);
-      s.mean_x = (float)pv.mx;
-      s.mean_y = (float)pv.my;
-      s.mean_lo = half_bits((float)(pv.mx - (double)s.mean_x)) | (half_bits((float)(pv.my - (double)s.mean_y)) << 16);
-      s.conic_a = (float)pv.A00;
-      s.conic_b = (float)pv.A01;
-      s.conic_c = (float)pv.A11;
-      s.opacity = (float)g.o;
-      s.rgb[0] = (float)rgb[0];
-      s.rgb[1] = (float)rgb[1];
-      s.rgb[2] = (float)rgb[2];
-      depth = (float)pv.pc[2];
-      s.axis_x = (float)pv.ax;
-      s.axis_y = (float)pv.ay;
-      s.e_long = (float)(-0.72134752044448170368 * pv.lam_long);   // -log2(e) / 2
-      s.e_short = (float)(-0.72134752044448170368 * pv.lam_short);
-      s.rect_lo = (uint32_t)pv.rect[0] | ((uint32_t)pv.rect[1] << 16);
-      s.rect_hi = (uint32_t)pv.rect[2] | ((uint32_t)pv.rect[3] << 16);
-      // the rectangle's area: the sort's emission keeps the tiles that meet the footprint
-      count = (uint32_t)((pv.rect[2] - pv.rect[0] + 1) * (pv.rect[3] - pv.rect[1] + 1));
-    } else {
-      s.mean_x = s.mean_y = 0.f;
-      s.conic_a = s.conic_b = s.conic_c = 0.f;
-      s.opacity = 0.f;
-      s.rgb[0] = s.rgb[1] = s.rgb[2] = 0.f;
-      s.mean_lo = 0u;
-      s.axis_x = 1.f;
-      s.axis_y = 0.f;
-      s.e_long = s.e_short = 0.f;
-      s.rect_lo = 1u;  // x0 = 1 > x1 = 0: empty
-      s.rect_hi = 0u;
+  if (active) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) sh[k * kProjThreads] = params[(STEEPGS_ROW_SH + k) * n + i];
+    load_gauss(params, n, i, g);
+  }
+  for (int v0 = 0; v0 < V; v0 += kCamChunk) {
+    const int nv = min(kCamChunk, V - v0);
+    __syncthreads();  // the previous chunk's constants are read by now
+    if (tid < nv) camera_constants(cams[v0 + tid], opt, s_cc + tid * kCamConsts);
+    __syncthreads();
+    if (!active) continue;
+    uint64_t near = 0;  // channels (3 per view of the chunk) within 1e-5 of the colour clamp
+    for (int k = 0; k < nv; ++k) {
+      const int v = v0 + k;
+      const double* cc = s_cc + k * kCamConsts;
+      CamD cam;
+      load_cam(cc, cams[v], cam);
+      ViewProj pv;
+      const int64_t r = (int64_t)v * n + i;
+      steepgs_splat s;
+      uint32_t count = 0;
+      float depth = 0.f;
+      const double lim[2] = {cc[kCamLim], cc[kCamLim + 1]};
+      if (project_view(g, cam, opt, lim, pv)) {
+        const double campos[3] = {cc[kCamCentre], cc[kCamCentre + 1], cc[kCamCentre + 2]};
+        const float pf[3] = {(float)g.p[0], (float)g.p[1], (float)g.p[2]};
+        float rgb[3];
+        near |= (uint64_t)view_colour<D>(pf, campos, sh, kProjThreads, rgb) << (3 * k);
+        s.mean_x = (float)pv.mx;
+        s.mean_y = (float)pv.my;
+        s.mean_lo =
+            half_bits((float)(pv.mx - (double)s.mean_x)) | (half_bits((float)(pv.my - (double)s.mean_y)) << 16);
+        s.conic_a = (float)pv.A00;
+        s.conic_b = (float)pv.A01;
+        s.conic_c = (float)pv.A11;
+        s.opacity = (float)g.o;
+        s.rgb[0] = rgb[0];
+        s.rgb[1] = rgb[1];
+        s.rgb[2] = rgb[2];
+        depth = (float)pv.pc[2];
+        s.axis_x = (float)pv.ax;
+        s.axis_y = (float)pv.ay;
+        s.e_long = (float)(-0.72134752044448170368 * pv.lam_long);  // -log2(e) / 2
+        s.e_short = (float)(-0.72134752044448170368 * pv.lam_short);
+        s.rect_lo = (uint32_t)pv.rect[0] | ((uint32_t)pv.rect[1] << 16);
+        s.rect_hi = (uint32_t)pv.rect[2] | ((uint32_t)pv.rect[3] << 16);
+        // the rectangle's area: the sort's emission keeps the tiles that meet the footprint
+        count = (uint32_t)((pv.rect[2] - pv.rect[0] + 1) * (pv.rect[3] - pv.rect[1] + 1));
+      } else {
+        s.mean_x = s.mean_y = 0.f;
+        s.conic_a = s.conic_b = s.conic_c = 0.f;
+        s.opacity = 0.f;
+        s.rgb[0] = s.rgb[1] = s.rgb[2] = 0.f;
+        s.mean_lo = 0u;
+        s.axis_x = 1.f;
+        s.axis_y = 0.f;
+        s.e_long = s.e_short = 0.f;
+        s.rect_lo = 1u;  // x0 = 1 > x1 = 0: empty
+        s.rect_hi = 0u;
+      }
+      // four 16-byte stores
+      float4* dst = reinterpret_cast<float4*>(out + r);
+      const float4* src = reinterpret_cast<const float4*>(&s);
+      dst[0] = src[0];
+      dst[1] = src[1];
+      dst[2] = src[2];
+      dst[3] = src[3];
+      tiles[r] = count;
+      // the key of the sort's depth order: the float bits of the (positive)
+      // depth, all ones for a culled record
+      dkeys[r] = count ? __float_as_uint(depth) : 0xFFFFFFFFu;
     }
-    // four 16-byte stores
-    float4* dst = reinterpret_cast<float4*>(out + r);
-    const float4* src = reinterpret_cast<const float4*>(&s);
-    dst[0] = src[0];
-    dst[1] = src[1];
-    dst[2] = src[2];
-    dst[3] = src[3];
-    tiles[r] = count;
-    // the key of the sort's depth order: the float bits of the (positive)
-    // depth, all ones for a culled record
-    dkeys[r] = count ? __float_as_uint(depth) : 0xFFFFFFFFu;
+    // the channels too close to the clamp to call in fp32: fp64 in the
+    // reference order decides and gives the value (rare; one call site)
+    while (near) {
+      const int b = __builtin_ctzll(near);
+      near &= near - 1;
+      const int k = b / 3, ch = b - 3 * k;
+      const double c = colour_channel_fp64(params, n, i, D, s_cc + k * kCamConsts + kCamCentre, ch);
+      out[(int64_t)(v0 + k) * n + i].rgb[ch] = c < 0.0 ? 0.f : (float)c;
+    }
   }
 }
 

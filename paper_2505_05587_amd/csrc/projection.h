@@ -230,20 +230,6 @@ struct CamD {
   int W, H, model, tiles_x, tiles_y;
 };
 
-SG_DEV void load_cam(const steepgs_camera& c, CamD& d) {
-  for (int k = 0; k < 9; ++k) d.R[k] = c.R[k];
-  for (int k = 0; k < 3; ++k) d.t[k] = c.t[k];
-  d.fx = c.fx;
-  d.fy = c.fy;
-  d.cx = c.cx;
-  d.cy = c.cy;
-  d.W = c.width;
-  d.H = c.height;
-  d.model = c.model;
-  d.tiles_x = c.tiles_x;
-  d.tiles_y = c.tiles_y;
-}
-
 // per (Gaussian, view) quantities
 struct ViewProj {
   double pc[3];
@@ -260,33 +246,83 @@ struct ViewProj {
   int rect[4];
 };
 
-// Geometry of one view; returns false when culled.
-SG_DEV bool project_view(const Gauss& g, const CamD& cam, const steepgs_opts& opt, ViewProj& v) {
+// Per-view constants of the projection and the colour, the same for every
+// Gaussian, in fp64: the camera centre -R^T t, the frustum-guard limits on
+// x/z and y/z, then R, t, fx, fy, cx, cy.  Computed once per workgroup and
+// view.
+constexpr int kCamCentre = 0, kCamLim = 3, kCamR = 5, kCamT = 14, kCamF = 17;
+constexpr int kCamConsts = 21;
+
+SG_DEV void camera_centre(const steepgs_camera& c, double out[3]) {
+#pragma clang fp contract(off)
+  double R[9], t[3];
+  for (int k = 0; k < 9; ++k) R[k] = c.R[k];
+  for (int k = 0; k < 3; ++k) t[k] = c.t[k];
+  for (int k = 0; k < 3; ++k) out[k] = -(R[0 + k] * t[0] + R[3 + k] * t[1] + R[6 + k] * t[2]);
+}
+
+SG_DEV void camera_constants(const steepgs_camera& c, const steepgs_opts& opt, double out[kCamConsts]) {
+#pragma clang fp contract(off)
+  camera_centre(c, out + kCamCentre);
+  const double guard = opt.frustum_guard;
+  out[kCamLim + 0] = guard * (0.5 * c.width / (double)c.fx);
+  out[kCamLim + 1] = guard * (0.5 * c.height / (double)c.fy);
+  for (int k = 0; k < 9; ++k) out[kCamR + k] = c.R[k];
+  for (int k = 0; k < 3; ++k) out[kCamT + k] = c.t[k];
+  out[kCamF + 0] = c.fx;
+  out[kCamF + 1] = c.fy;
+  out[kCamF + 2] = c.cx;
+  out[kCamF + 3] = c.cy;
+}
+
+// the camera of one view from its constants (fp64 part) and the record
+SG_DEV void load_cam(const double* cc, const steepgs_camera& c, CamD& d) {
+  for (int k = 0; k < 9; ++k) d.R[k] = cc[kCamR + k];
+  for (int k = 0; k < 3; ++k) d.t[k] = cc[kCamT + k];
+  d.fx = cc[kCamF + 0];
+  d.fy = cc[kCamF + 1];
+  d.cx = cc[kCamF + 2];
+  d.cy = cc[kCamF + 3];
+  d.W = c.width;
+  d.H = c.height;
+  d.model = c.model;
+  d.tiles_x = c.tiles_x;
+  d.tiles_y = c.tiles_y;
+}
+
+// Geometry of one view; returns false when culled.  lim: the frustum-guard
+// limits of camera_constants.  Operation order as written, no contraction:
+// the tile rectangle and the culling decisions are reproducible from the
+// fp32 inputs.  The structural zeros of J (and of the orthographic map) are
+// left out of P = J W: the sums they would join are unchanged by them.
+SG_DEV bool project_view(const Gauss& g, const CamD& cam, const steepgs_opts& opt, const double lim[2], ViewProj& v) {
 #pragma clang fp contract(off)
   for (int r = 0; r < 3; ++r)
     v.pc[r] = cam.R[3 * r + 0] * g.p[0] + cam.R[3 * r + 1] * g.p[1] + cam.R[3 * r + 2] * g.p[2] + cam.t[r];
   if (!(v.pc[2] > (double)opt.near_z)) return false;
   if (cam.model == 0) {
-    v.mx = cam.fx * (v.pc[0] / v.pc[2]) + cam.cx;
-    v.my = cam.fy * (v.pc[1] / v.pc[2]) + cam.cy;
     v.gx = v.pc[0] / v.pc[2];
     v.gy = v.pc[1] / v.pc[2];
+    v.mx = cam.fx * v.gx + cam.cx;
+    v.my = cam.fy * v.gy + cam.cy;
     v.gx_free = v.gy_free = true;
-    const double guard = opt.frustum_guard;
-    if (guard > 0.0) {
-      const double limx = guard * (0.5 * cam.W / cam.fx);
-      const double limy = guard * (0.5 * cam.H / cam.fy);
-      if (v.gx < -limx) { v.gx = -limx; v.gx_free = false; }
-      if (v.gx > limx) { v.gx = limx; v.gx_free = false; }
-      if (v.gy < -limy) { v.gy = -limy; v.gy_free = false; }
-      if (v.gy > limy) { v.gy = limy; v.gy_free = false; }
+    if (opt.frustum_guard > 0.f) {
+      if (v.gx < -lim[0]) { v.gx = -lim[0]; v.gx_free = false; }
+      if (v.gx > lim[0]) { v.gx = lim[0]; v.gx_free = false; }
+      if (v.gy < -lim[1]) { v.gy = -lim[1]; v.gy_free = false; }
+      if (v.gy > lim[1]) { v.gy = lim[1]; v.gy_free = false; }
     }
-    v.J[0][0] = cam.fx / v.pc[2];
+    const double iz = 1.0 / v.pc[2];
+    v.J[0][0] = cam.fx * iz;
     v.J[0][1] = 0.0;
-    v.J[0][2] = -(cam.fx * v.gx) / v.pc[2];
+    v.J[0][2] = -(cam.fx * v.gx) * iz;
     v.J[1][0] = 0.0;
-    v.J[1][1] = cam.fy / v.pc[2];
-    v.J[1][2] = -(cam.fy * v.gy) / v.pc[2];
+    v.J[1][1] = cam.fy * iz;
+    v.J[1][2] = -(cam.fy * v.gy) * iz;
+    for (int c = 0; c < 3; ++c) {
+      v.P[0][c] = v.J[0][0] * cam.R[0 + c] + v.J[0][2] * cam.R[6 + c];
+      v.P[1][c] = v.J[1][1] * cam.R[3 + c] + v.J[1][2] * cam.R[6 + c];
+    }
   } else {
     v.mx = cam.fx * v.pc[0] + cam.cx;
     v.my = cam.fy * v.pc[1] + cam.cy;
@@ -298,23 +334,27 @@ SG_DEV bool project_view(const Gauss& g, const CamD& cam, const steepgs_opts& op
     v.J[1][0] = 0.0;
     v.J[1][1] = cam.fy;
     v.J[1][2] = 0.0;
-  }
-  for (int a = 0; a < 2; ++a)
-    for (int c = 0; c < 3; ++c) v.P[a][c] = v.J[a][0] * cam.R[0 + c] + v.J[a][1] * cam.R[3 + c] + v.J[a][2] * cam.R[6 + c];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) {
-      double acc = 0.0;
-      for (int c = 0; c < 3; ++c)
-        for (int d = 0; d < 3; ++d) acc = acc + v.P[a][c] * g.Sig[c][d] * v.P[b][d];
-      v.S2[a][b] = acc;
+    for (int c = 0; c < 3; ++c) {
+      v.P[0][c] = cam.fx * cam.R[0 + c];
+      v.P[1][c] = cam.fy * cam.R[3 + c];
     }
+  }
+  // Pi(Sigma) = (P Sigma) P^T, its lower entry the mirror of the upper one
+  double PS[2][3];
+  for (int a = 0; a < 2; ++a)
+    for (int d = 0; d < 3; ++d) PS[a][d] = v.P[a][0] * g.Sig[0][d] + v.P[a][1] * g.Sig[1][d] + v.P[a][2] * g.Sig[2][d];
+  v.S2[0][0] = PS[0][0] * v.P[0][0] + PS[0][1] * v.P[0][1] + PS[0][2] * v.P[0][2];
+  v.S2[0][1] = PS[0][0] * v.P[1][0] + PS[0][1] * v.P[1][1] + PS[0][2] * v.P[1][2];
+  v.S2[1][1] = PS[1][0] * v.P[1][0] + PS[1][1] * v.P[1][1] + PS[1][2] * v.P[1][2];
+  v.S2[1][0] = v.S2[0][1];
   v.S2[0][0] = v.S2[0][0] + (double)opt.dilation;
   v.S2[1][1] = v.S2[1][1] + (double)opt.dilation;
   v.det = v.S2[0][0] * v.S2[1][1] - v.S2[0][1] * v.S2[1][0];
   if (!(v.det > 0.0)) return false;
-  v.A00 = v.S2[1][1] / v.det;
-  v.A01 = -v.S2[0][1] / v.det;
-  v.A11 = v.S2[0][0] / v.det;
+  const double idet = 1.0 / v.det;
+  v.A00 = v.S2[1][1] * idet;
+  v.A01 = -v.S2[0][1] * idet;
+  v.A11 = v.S2[0][0] * idet;
 
   const double a = v.S2[0][0], b = v.S2[0][1], c = v.S2[1][1];
   const double half = 0.5 * (a - c);
@@ -331,19 +371,21 @@ SG_DEV bool project_view(const Gauss& g, const CamD& cam, const steepgs_opts& op
     }
     const double en = sqrt(ex * ex + ey * ey);
     if (en > 0.0) {
-      v.ax = ex / en;
-      v.ay = ey / en;
+      const double ien = 1.0 / en;
+      v.ax = ex * ien;
+      v.ay = ey * ien;
     } else {
       v.ax = 1.0;
       v.ay = 0.0;
     }
     v.lam_long = 1.0 / lam;
-    v.lam_short = lam / v.det;
+    v.lam_short = lam * idet;
   }
   const double r = ceil((double)opt.radius_sigmas * sqrt(lam));
-  const double tw = opt.tile_w, th = opt.tile_h;
-  double x0 = floor((v.mx - r) / tw), x1 = floor((v.mx + r) / tw);
-  double y0 = floor((v.my - r) / th), y1 = floor((v.my + r) / th);
+  // tile sizes are powers of two: the products below equal the quotients
+  const double itw = 1.0 / opt.tile_w, ith = 1.0 / opt.tile_h;
+  double x0 = floor((v.mx - r) * itw), x1 = floor((v.mx + r) * itw);
+  double y0 = floor((v.my - r) * ith), y1 = floor((v.my + r) * ith);
   x0 = fmax(x0, 0.0);
   y0 = fmax(y0, 0.0);
   x1 = fmin(x1, (double)(cam.tiles_x - 1));
@@ -357,28 +399,45 @@ SG_DEV bool project_view(const Gauss& g, const CamD& cam, const steepgs_opts& op
   return true;
 }
 
-// SH colour of one view (Sec. 3: colour stored as SH coefficients), fp64:
-// max(0, sum_k sh_k Y_k(dir) + 1/2), dir the unit vector from the camera
-// centre to the mean.  sh[(3 k + ch) * stride] holds coefficient k of
-// channel ch.
-template <int D>
-SG_DEV void view_colour(const Gauss& g, const CamD& cam, const float* sh, int stride, double rgb[3]) {
+// fp64 colour of one channel in the reference operation order (no
+// contraction, the direction divided by its length): the value that decides
+// the clamp max(0, .) when a faster evaluation lands within 1e-5 of zero.
+SG_DEV double colour_channel_fp64(const float* __restrict__ params, int64_t n, int64_t i, int deg,
+                                  const double campos[3], int ch) {
 #pragma clang fp contract(off)
-  constexpr int NB = (D + 1) * (D + 1);
-  double campos[3];
-  for (int k = 0; k < 3; ++k) campos[k] = -(cam.R[0 + k] * cam.t[0] + cam.R[3 + k] * cam.t[1] + cam.R[6 + k] * cam.t[2]);
-  double d[3] = {g.p[0] - campos[0], g.p[1] - campos[1], g.p[2] - campos[2]};
+  double d[3];
+  for (int k = 0; k < 3; ++k) d[k] = (double)params[(STEEPGS_ROW_MEAN + k) * n + i] - campos[k];
   const double len = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
   double Y[16];
-  sh_eval<double>(D, d[0] / len, d[1] / len, d[2] / len, Y);
+  sh_eval<double>(deg, d[0] / len, d[1] / len, d[2] / len, Y);
+  double acc = 0.0;
+  for (int k = 0; k < (deg + 1) * (deg + 1); ++k) acc = acc + (double)params[(STEEPGS_ROW_SH + 3 * k + ch) * n + i] * Y[k];
+  return acc + 0.5;
+}
+
+// SH colour of one view (Sec. 3: colour stored as SH coefficients):
+// max(0, sum_k sh_k Y_k(dir) + 1/2), dir the unit vector from the camera
+// centre to the mean.  sh[(3 k + ch) * stride] holds coefficient k of
+// channel ch.  Evaluated in fp32 (error ~1e-7 of the terms' magnitude);
+// returns a bit per channel that lies within 1e-5 of the clamp, whose
+// decision and value the caller takes from colour_channel_fp64 instead.
+template <int D>
+SG_DEV uint32_t view_colour(const float p[3], const double campos[3], const float* sh, int stride, float rgb[3]) {
+  constexpr int NB = (D + 1) * (D + 1);
+  const float d0 = p[0] - (float)campos[0], d1 = p[1] - (float)campos[1], d2 = p[2] - (float)campos[2];
+  const float il = 1.f / sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+  float Y[16];
+  sh_eval<float>(D, d0 * il, d1 * il, d2 * il, Y);
+  uint32_t near = 0;
 #pragma unroll
   for (int ch = 0; ch < 3; ++ch) {
-    double acc = 0.0;
+    float acc = 0.5f;
 #pragma unroll
-    for (int k = 0; k < NB; ++k) acc = acc + (double)sh[(3 * k + ch) * stride] * Y[k];
-    acc = acc + 0.5;
-    rgb[ch] = acc < 0.0 ? 0.0 : acc;
+    for (int k = 0; k < NB; ++k) acc = fmaf(sh[(3 * k + ch) * stride], Y[k], acc);
+    near |= (fabsf(acc) < 1e-5f ? 1u : 0u) << ch;
+    rgb[ch] = acc < 0.f ? 0.f : acc;
   }
+  return near;
 }
 
 }  // namespace sg

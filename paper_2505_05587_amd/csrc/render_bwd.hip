@@ -349,20 +349,9 @@ SG_DEV void axis_to_pixel_moments2(double& m1l, double& m1s, double& m2ll, doubl
 // fp64 colour of one channel, for a clamp decision too close to call in fp32
 __device__ __noinline__ bool colour_clamped_fp64(const float* __restrict__ params, int64_t n, int64_t i, int deg,
                                                   const steepgs_camera& cam, int ch) {
-#pragma clang fp contract(off)
-  double R[9], t[3];
-  for (int k = 0; k < 9; ++k) R[k] = cam.R[k];
-  for (int k = 0; k < 3; ++k) t[k] = cam.t[k];
-  double campos[3], d[3];
-  for (int k = 0; k < 3; ++k) campos[k] = -(R[0 + k] * t[0] + R[3 + k] * t[1] + R[6 + k] * t[2]);
-  for (int k = 0; k < 3; ++k) d[k] = (double)params[(STEEPGS_ROW_MEAN + k) * n + i] - campos[k];
-  const double len = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-  double Y[16];
-  sh_eval<double>(deg, d[0] / len, d[1] / len, d[2] / len, Y);
-  double acc = 0.0;
-  for (int k = 0; k < (deg + 1) * (deg + 1); ++k) acc = acc + (double)params[(STEEPGS_ROW_SH + 3 * k + ch) * n + i] * Y[k];
-  acc = acc + 0.5;
-  return acc < 0.0;
+  double campos[3];
+  camera_centre(cam, campos);
+  return colour_channel_fp64(params, n, i, deg, campos, ch) < 0.0;
 }
 
 // fp64 rotation of the normalised quaternion qh = q / |q| and the scales
