@@ -388,8 +388,10 @@ SG_DEV uint32_t visible_views(const uint32_t* __restrict__ tiles, int64_t n, int
 // (quaternion, scale) -- and the splitting-matrix lift in fp64 (the conic of a
 // thin footprint, condition number kappa, loses ~kappa ulps when inverted or
 // differentiated in fp32).  The passes keep the SH coefficients and the
-// fp64 geometry out of each other's live range.  The view index stays
-// uniform over the wavefront, so camera data are scalar loads.
+// fp64 geometry out of each other's live range (as two kernels they ran
+// slower than as one).  The view index stays uniform over the wavefront, so
+// camera data are scalar loads; each pass loads the next view's slot while
+// it processes the current one.
 template <int D>
 __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) k_proj_bwd(const float* __restrict__ params, int64_t n,
                                                   const steepgs_camera* __restrict__ cams, int V, steepgs_opts opt,
@@ -417,11 +419,20 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) k
     for (int v0 = 0; v0 < V; v0 += 32) {
       const int nv = min(32, V - v0);
       const uint32_t vis = visible_views(tiles, n, i, v0, nv);
+      // the next view's colour gradient is loaded while this one is processed
+      double nc[3] = {0.0, 0.0, 0.0};
+      auto fetch = [&](int k) {
+        if ((vis >> k) & 1u) {
+          const double* slot = g2d + ((int64_t)(v0 + k) * n + i) * kSlot;
+          for (int e = 0; e < 3; ++e) nc[e] = slot[6 + e];
+        }
+      };
+      fetch(0);
       for (int k = 0; k < nv; ++k) {
+        const float gcol[3] = {(float)nc[0], (float)nc[1], (float)nc[2]};
+        if (k + 1 < nv) fetch(k + 1);
         if (!((vis >> k) & 1u)) continue;
         const int v = v0 + k;
-        const double* slot = g2d + ((int64_t)v * n + i) * kSlot;
-        const float gcol[3] = {(float)slot[6], (float)slot[7], (float)slot[8]};
         if (gcol[0] == 0.f && gcol[1] == 0.f && gcol[2] == 0.f) continue;
         any = true;
         const steepgs_camera& cam = cams[v];
@@ -485,16 +496,32 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) k
   for (int v0 = 0; v0 < V; v0 += 32) {
     const int nv = min(32, V - v0);
     const uint32_t vis = visible_views(tiles, n, i, v0, nv);
+    // the next view's moments and footprint axis are loaded while this one
+    // is processed
+    double nm[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    float nax = 1.f, nay = 0.f;
+    auto fetch = [&](int k) {
+      if ((vis >> k) & 1u) {
+        const int64_t r = (int64_t)(v0 + k) * n + i;
+        const double* slot = g2d + r * kSlot;
+        for (int e = 0; e < 6; ++e) nm[e] = slot[e];
+        nax = splats[r].axis_x;
+        nay = splats[r].axis_y;
+      }
+    };
+    fetch(0);
     for (int k = 0; k < nv; ++k) {
+      double cm[6];
+      for (int e = 0; e < 6; ++e) cm[e] = nm[e];
+      const float cax = nax, cay = nay;
+      if (k + 1 < nv) fetch(k + 1);
       if (!((vis >> k) & 1u)) continue;
       const int v = v0 + k;
-      const double* slot = g2d + ((int64_t)v * n + i) * kSlot;
-      const double m0 = slot[5];  // sum g alpha = o dL/do
-      double m1x = slot[0], m1y = slot[1], m2xx = slot[2], m2xy = slot[3], m2yy = slot[4];
+      const double m0 = cm[5];  // sum g alpha = o dL/do
+      double m1x = cm[0], m1y = cm[1], m2xx = cm[2], m2xy = cm[3], m2yy = cm[4];
       if (m1x == 0.0 && m1y == 0.0 && m2xx == 0.0 && m2xy == 0.0 && m2yy == 0.0 && m0 == 0.0) continue;
       any = true;
-      axis_to_pixel_moments2(m1x, m1y, m2xx, m2xy, m2yy, splats[(int64_t)v * n + i].axis_x,
-                             splats[(int64_t)v * n + i].axis_y);
+      axis_to_pixel_moments2(m1x, m1y, m2xx, m2xy, m2yy, cax, cay);
       const steepgs_camera& cam = cams[v];
       double W[9];
 #pragma unroll
