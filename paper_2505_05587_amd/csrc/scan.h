@@ -12,8 +12,8 @@ constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;  // elements per block
 
 // exclusive scan over the 256 threads of a block; returns the block total
-template <class T>
-SG_DEV T block_exclusive_scan(T x, T* lds /*[kScanThreads/64 + 1]*/, T& total) {
+template <class T, int kThreads = kScanThreads>
+SG_DEV T block_exclusive_scan(T x, T* lds /*[kThreads/64 + 1]*/, T& total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   T inc = x;
 #pragma unroll
@@ -24,7 +24,7 @@ SG_DEV T block_exclusive_scan(T x, T* lds /*[kScanThreads/64 + 1]*/, T& total) {
   if (lane == 63) lds[wave] = inc;
   __syncthreads();
   T wave_off = 0, tot = 0;
-  for (int w = 0; w < kScanThreads / 64; ++w) {
+  for (int w = 0; w < kThreads / 64; ++w) {
     if (w < wave) wave_off += lds[w];
     tot += lds[w];
   }
