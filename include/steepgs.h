@@ -254,6 +254,31 @@ steepgs_status steepgs_render_bwd_split(const float* d_params, int64_t n, int32_
                                         const float* d_target, float* d_grads, float* d_S, float* d_grad2d,
                                         void* d_ws, size_t ws_bytes, void* stream);
 
+/* The backward's first step, on its own: clears the fp64 moment slots of a
+ * stage-3 workspace (steepgs_workspace_size(3, n, V, ...) bytes, laid out for
+ * n and V), which steepgs_render_bwd_split accumulates into.  With
+ * steepgs_render_bwd_split_cleared it lets a caller run the clear earlier,
+ * on another stream -- e.g. beside the forward blend, which leaves most of
+ * the HBM bandwidth unused.  The workspace is the caller's; n = 0 does
+ * nothing.  STEEPGS_ERR_INVALID_ARG for n < 0, V <= 0 or a null workspace,
+ * STEEPGS_ERR_WORKSPACE if ws_bytes is too small. */
+steepgs_status steepgs_render_bwd_clear(int64_t n, int32_t V, void* d_ws, size_t ws_bytes, void* stream);
+
+/* steepgs_render_bwd_split without its own clear of the workspace's moment
+ * slots (same arguments, results and errors): the caller has cleared them
+ * with steepgs_render_bwd_clear for the same n and V, ordered before this
+ * call (same stream, or an event), and nothing else has written the
+ * workspace since.  Slots left uncleared add into the results. */
+steepgs_status steepgs_render_bwd_split_cleared(const float* d_params, int64_t n, int32_t sh_degree,
+                                                const steepgs_camera* d_cams, int32_t V, const steepgs_opts* opts,
+                                                const steepgs_splat* d_splats, const uint32_t* d_tiles_touched,
+                                                const uint32_t* d_vals, const uint32_t* d_tile_ranges,
+                                                int32_t total_tiles, int64_t total_pixels, const float* d_image,
+                                                const float* d_T_final, const uint32_t* d_n_contrib,
+                                                const float* d_dL_dimage, const float* d_target, float* d_grads,
+                                                float* d_S, float* d_grad2d, void* d_ws, size_t ws_bytes,
+                                                void* stream);
+
 /* Stage 4 over theta = (p, log-scales) (dim 6; Sec. 4.4 defines S_i over the
  * parameters the Hessian is taken in, the paper's experiments use p alone):
  * as steepgs_render_bwd_split, and in addition

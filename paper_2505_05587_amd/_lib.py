@@ -86,13 +86,16 @@ def lib():
         L.steepgs_densify.argtypes = [vp, i64, i32, vp, f32, f32, f32, C.POINTER(SplitSelect), vp, i64, vp, vp, vp,
                                       vp, vp, vp, sz, vp]
         L.steepgs_render_bwd_split6.argtypes = L.steepgs_render_bwd_split.argtypes
+        L.steepgs_render_bwd_split_cleared.argtypes = L.steepgs_render_bwd_split.argtypes
+        L.steepgs_render_bwd_clear.argtypes = [i64, i32, vp, sz, vp]
         L.steepgs_densify6.argtypes = [vp, i64, i32, vp, f32, f32, f32, vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]
         L.steepgs_adam_step.argtypes = [vp, vp, vp, vp, i64, i32, C.POINTER(AdamOpts), vp, vp, vp, vp]
         L.steepgs_split_remap.argtypes = [vp, i32, i64, vp, vp, i64, vp, sz, vp]
         for fn in ("steepgs_layout_cameras", "steepgs_project", "steepgs_sort", "steepgs_render_fwd",
                    "steepgs_render_fwd_noalloc",
                    "steepgs_render_bwd_split", "steepgs_densify", "steepgs_adam_step", "steepgs_split_remap",
-                   "steepgs_render_bwd_split6", "steepgs_densify6"):
+                   "steepgs_render_bwd_split6", "steepgs_densify6", "steepgs_render_bwd_split_cleared",
+                   "steepgs_render_bwd_clear"):
             getattr(L, fn).restype = C.c_int
         L.steepgs_status_string.argtypes = [C.c_int]
         L.steepgs_status_string.restype = C.c_char_p
@@ -205,6 +208,23 @@ def steepgs_render_bwd_split(params, n, sh_degree, d_cams, V, opts, splats, tile
                                           _p(image), _p(T_final), _p(n_contrib), _p(dL_dimage), _p(target),
                                           _p(grads), _p(S), _p(grad2d), _p(ws), ws.numel() * ws.element_size(),
                                           _stream(stream)))
+
+
+def steepgs_render_bwd_split_cleared(params, n, sh_degree, d_cams, V, opts, splats, tiles_touched, vals, tile_ranges,
+                                     total_tiles, total_pixels, image, T_final, n_contrib, dL_dimage, target, grads,
+                                     S, grad2d, ws, stream=None):
+    """steepgs_render_bwd_split on a workspace cleared by steepgs_render_bwd_clear."""
+    _check("steepgs_render_bwd_split_cleared",
+           lib().steepgs_render_bwd_split_cleared(_p(params), n, sh_degree, _p(d_cams), V, C.byref(opts), _p(splats),
+                                                  _p(tiles_touched), _p(vals), _p(tile_ranges), total_tiles,
+                                                  total_pixels, _p(image), _p(T_final), _p(n_contrib),
+                                                  _p(dL_dimage), _p(target), _p(grads), _p(S), _p(grad2d), _p(ws),
+                                                  ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def steepgs_render_bwd_clear(n, V, ws, stream=None):
+    _check("steepgs_render_bwd_clear",
+           lib().steepgs_render_bwd_clear(n, V, _p(ws), ws.numel() * ws.element_size(), _stream(stream)))
 
 
 def steepgs_render_bwd_split6(params, n, sh_degree, d_cams, V, opts, splats, tiles_touched, vals, tile_ranges,

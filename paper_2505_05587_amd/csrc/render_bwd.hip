@@ -941,7 +941,8 @@ static steepgs_status bwd_impl(const float* d_params, int64_t n, int32_t sh_degr
                                const uint32_t* d_tile_ranges, int32_t total_tiles, int64_t total_pixels,
                                const float* d_image, const float* d_T_final, const uint32_t* d_n_contrib,
                                const float* d_dL_dimage, const float* d_target, float* d_grads, float* d_S,
-                               float* d_S6, float* d_grad2d, void* d_ws, size_t ws_bytes, void* stream) {
+                               float* d_S6, float* d_grad2d, void* d_ws, size_t ws_bytes, void* stream,
+                               bool clear = true) {
   const bool h6 = d_S6 != nullptr;
   if (n < 0 || V <= 0 || sh_degree < 0 || sh_degree > 3 || total_tiles <= 0 || total_pixels <= 0 || !opts_ok(opts))
     return STEEPGS_ERR_INVALID_ARG;
@@ -958,7 +959,8 @@ static steepgs_status bwd_impl(const float* d_params, int64_t n, int32_t sh_degr
   bwd_layout(d_ws, m, h6, &g2d, &queue);
   hipStream_t st = as_stream(stream);
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, reinterpret_cast<float*>(queue), (int64_t)1);
-  hipLaunchKernelGGL(k_zero64, dim3(stride_grid(per_record * m, 256)), dim3(256), 0, st, g2d.slot, per_record * m);
+  if (clear)
+    hipLaunchKernelGGL(k_zero64, dim3(stride_grid(per_record * m, 256)), dim3(256), 0, st, g2d.slot, per_record * m);
   const steepgs_opts o = raster_opts(*opts);
   const int grid = raster_grid(o, total_tiles);
   timer_begin(STEEPGS_TIMER_RENDER_BWD, st);
@@ -1008,6 +1010,31 @@ extern "C" steepgs_status steepgs_render_bwd_split(const float* d_params, int64_
   return bwd_impl(d_params, n, sh_degree, d_cams, V, opts, d_splats, d_tiles_touched, d_vals, d_tile_ranges,
                   total_tiles, total_pixels, d_image, d_T_final, d_n_contrib, d_dL_dimage, d_target, d_grads, d_S,
                   nullptr, d_grad2d, d_ws, ws_bytes, stream);
+}
+
+extern "C" steepgs_status steepgs_render_bwd_clear(int64_t n, int32_t V, void* d_ws, size_t ws_bytes, void* stream) {
+  if (n < 0 || V <= 0 || !d_ws) return STEEPGS_ERR_INVALID_ARG;
+  if (n == 0) return STEEPGS_OK;
+  const int64_t m = (int64_t)V * n;
+  Slots g2d;
+  uint32_t* queue;
+  if (ws_bytes < bwd_layout(nullptr, m, false, &g2d, &queue)) return STEEPGS_ERR_WORKSPACE;
+  bwd_layout(d_ws, m, false, &g2d, &queue);
+  hipLaunchKernelGGL(k_zero64, dim3(stride_grid(kSlot * m, 256)), dim3(256), 0, as_stream(stream), g2d.slot,
+                     kSlot * m);
+  SG_TRY_LAUNCH();
+  return STEEPGS_OK;
+}
+
+extern "C" steepgs_status steepgs_render_bwd_split_cleared(
+    const float* d_params, int64_t n, int32_t sh_degree, const steepgs_camera* d_cams, int32_t V,
+    const steepgs_opts* opts, const steepgs_splat* d_splats, const uint32_t* d_tiles_touched, const uint32_t* d_vals,
+    const uint32_t* d_tile_ranges, int32_t total_tiles, int64_t total_pixels, const float* d_image,
+    const float* d_T_final, const uint32_t* d_n_contrib, const float* d_dL_dimage, const float* d_target,
+    float* d_grads, float* d_S, float* d_grad2d, void* d_ws, size_t ws_bytes, void* stream) {
+  return bwd_impl(d_params, n, sh_degree, d_cams, V, opts, d_splats, d_tiles_touched, d_vals, d_tile_ranges,
+                  total_tiles, total_pixels, d_image, d_T_final, d_n_contrib, d_dL_dimage, d_target, d_grads, d_S,
+                  nullptr, d_grad2d, d_ws, ws_bytes, stream, false);
 }
 
 extern "C" steepgs_status steepgs_render_bwd_split6(const float* d_params, int64_t n, int32_t sh_degree,

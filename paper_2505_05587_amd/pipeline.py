@@ -159,17 +159,23 @@ class Rasterizer:
         self.render(target, count_used)
         return ForwardState(K, self.image, self.T_final, self.n_contrib, self.loss if target is not None else None)
 
+    def clear_backward(self):
+        """Clear the backward's moment slots ahead of ``backward(cleared=True)``
+        (on the current stream, which may differ from the backward's)."""
+        L.steepgs_render_bwd_clear(self.n, self.cams.V, self.ws_bwd)
+
     def backward(self, params: torch.Tensor, grads: torch.Tensor, S: torch.Tensor, target=None, dL_dimage=None,
-                 keep_grad2d=False):
-        """grads [F, n] and S [6, n] accumulate (+=)."""
+                 keep_grad2d=False, cleared=False):
+        """grads [F, n] and S [6, n] accumulate (+=).  cleared: the slots were
+        cleared by ``clear_backward`` (ordered before this call)."""
         g2d = None
         if keep_grad2d:
             self.grad2d = _grow(self.grad2d, 12 * self.cams.V * self.n, torch.float32, self.dev)
             g2d = self.grad2d
-        L.steepgs_render_bwd_split(params, self.n, self.sh_degree, self.cams.dev, self.cams.V, self.cams.opts,
-                                   self.splats, self.tiles, self.vals, self.ranges, self.cams.total_tiles,
-                                   self.cams.total_pixels, self.image, self.T_final, self.n_contrib, dL_dimage,
-                                   target, grads, S, g2d, self.ws_bwd)
+        fn = L.steepgs_render_bwd_split_cleared if cleared else L.steepgs_render_bwd_split
+        fn(params, self.n, self.sh_degree, self.cams.dev, self.cams.V, self.cams.opts, self.splats, self.tiles,
+           self.vals, self.ranges, self.cams.total_tiles, self.cams.total_pixels, self.image, self.T_final,
+           self.n_contrib, dL_dimage, target, grads, S, g2d, self.ws_bwd)
 
     def backward6(self, params: torch.Tensor, grads: torch.Tensor, S6: torch.Tensor, S: torch.Tensor | None = None,
                   target=None, dL_dimage=None):

@@ -59,6 +59,7 @@ class BatchedStep:
         self.grads = torch.zeros((F, n), dtype=torch.float32, device=dev)
         self.S = torch.zeros((6 if theta_dim == 3 else 21, n), dtype=torch.float32, device=dev)
         self.dens = _Densify(F, n, dev, theta_dim)
+        self.side = torch.cuda.Stream(device=dev)  # default priority
         self.graph = None
 
     def prepare(self, headroom: float = 1.1) -> int:
@@ -70,16 +71,25 @@ class BatchedStep:
 
     def run(self):
         r = self.ras
+        main = torch.cuda.current_stream()
         r.project(self.params)
         L.steepgs_sort(r.splats, r.tiles, r.n, self.cams.V, self.cams.dev, self.cams.opts, self.cams.total_tiles,
                        None, r.vals, r.capacity, r.ranges, r.num, r.status, r.ws_sort, depth_keys=r.dkeys)
+        # the clears of the backward's accumulators read nothing: they run on a
+        # second stream beside the forward blend (VALU-bound, most of the HBM
+        # bandwidth free) and join before the backward
+        self.side.wait_stream(main)
+        with torch.cuda.stream(self.side):
+            self.grads.zero_()
+            self.S.zero_()
+            if self.theta_dim == 3:
+                r.clear_backward()
         r.render(self.target)
-        self.grads.zero_()
-        self.S.zero_()
+        main.wait_stream(self.side)
         if self.theta_dim == 6:
             r.backward6(self.params, self.grads, self.S, target=self.target)
         else:
-            r.backward(self.params, self.grads, self.S, target=self.target)
+            r.backward(self.params, self.grads, self.S, target=self.target, cleared=True)
         self.dens.run(self.params, self.sh_degree, self.S, self.s_scale, self.eps, self.eps_split)
 
     def capture(self):

@@ -2,7 +2,8 @@
 every replay, with unrelated eager work and synchronisations between the
 replays: instance list and image bit-identical, loss, gradients and S within
 the reordering of float atomics, the same split decisions where lambda_min is
-clear of the threshold."""
+clear of the threshold.  The backward run on slots cleared ahead of it (on
+another stream) equals the backward that clears them itself."""
 import numpy as np
 import pytest
 import torch
@@ -47,6 +48,7 @@ def test_graph_replays_match_eager(kind):
         (a @ a).sum().item()
         step.S.fill_(123.0)
         step.grads.fill_(-7.0)
+        step.ras.ws_bwd.fill_(0x3FF00000)  # the backward's moment slots: nonzero doubles
         step.replay()
         torch.cuda.synchronize()
         got = _snapshot(step)
@@ -107,3 +109,43 @@ def test_per_view_form_matches_batched():
     lam_b = bat.dens.lam[:n].cpu().numpy().astype(np.float64)
     sure = np.abs(lam_b + 1e-6) > 1e-4 * r + 1e-12
     np.testing.assert_array_equal(pv.dens.split[:n].cpu().numpy()[sure], bat.dens.split[:n].cpu().numpy()[sure])
+
+
+@pytest.mark.parametrize("side", [False, True])
+def test_backward_on_cleared_slots_matches_split(side):
+    # steepgs_render_bwd_clear (same stream, or a second stream joined by an
+    # event) then steepgs_render_bwd_split_cleared: gradients, S and the
+    # per-pair 2D gradients bit-identical to steepgs_render_bwd_split, with
+    # the slots poisoned before the clear
+    from paper_2505_05587_amd.pipeline import Rasterizer
+    P0, deg, cams, target = scene_small("multiview")
+    print(f"\n[case] backward on cleared slots, side stream={side}", flush=True)
+    dev = torch.device("cuda", 0)
+    opts = scenes.opts("3dgs")
+    cb = CameraBatch(cams, opts, dev)
+    P = torch.from_numpy(P0).to(dev)
+    tg = torch.from_numpy(target).to(dev)
+    r = Rasterizer(cb, deg)
+    r.forward(P, target=tg)
+    F, n = P.shape
+    out = []
+    for cleared in (False, True):
+        grads = torch.zeros((F, n), dtype=torch.float32, device=dev)
+        S = torch.zeros((6, n), dtype=torch.float32, device=dev)
+        r.ws_bwd.fill_(0x3FF00000)
+        if cleared:
+            if side:
+                other = torch.cuda.Stream(device=dev)
+                other.wait_stream(torch.cuda.current_stream())
+                with torch.cuda.stream(other):
+                    r.clear_backward()
+                torch.cuda.current_stream().wait_stream(other)
+            else:
+                r.clear_backward()
+        r.backward(P, grads, S, target=tg, keep_grad2d=True, cleared=cleared)
+        torch.cuda.synchronize()
+        out.append((grads.cpu().numpy(), S.cpu().numpy(), r.grad2d.cpu().numpy().copy()))
+    for a, b in zip(out[0], out[1]):
+        np.testing.assert_array_equal(a, b)
+    assert np.abs(out[0][1]).max() > 0
+
