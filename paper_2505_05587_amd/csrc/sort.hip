@@ -29,17 +29,19 @@ namespace sg {
 // offsets, scatters the tile into LDS in sorted order and writes it out so
 // that consecutive lanes write consecutive addresses of one digit's run.
 
-// 16 wavefronts of 8 elements per lane: one workgroup fills a CU (4 waves
-// per SIMD at <= 128 VGPRs) and a tile of 8192 elements gives digit runs long
-// enough for mostly whole-line writes.  Measured on 59 M instances and 16 M
-// records: 256 x 16 -> 1024 x 8 took the sort stage from 2.34 to 2.22 ms.
+// 16 wavefronts of 6 elements per lane: one workgroup fills a CU (4 waves
+// per SIMD at <= 128 VGPRs, the next tile's elements in flight) and a tile of
+// 6144 elements gives digit runs long enough for mostly whole-line writes.
+// Sort stage on 59 M instances and 16 M records: 256 x 16 2.34 ms, 1024 x 8
+// 2.22 ms; in a later run 1024 x 8 2.250 ms against 2.233 ms for 1024 x 6
+// with the next tile loaded ahead (at 1024 x 8 that load spills: 2.79 ms).
 #ifndef SG_RS_THREADS
 #define SG_RS_THREADS 1024
 #endif
 constexpr int kRsThreads = SG_RS_THREADS;
 constexpr int kRsWaves = kRsThreads / 64;
 #ifndef SG_RS_ITEMS
-#define SG_RS_ITEMS 8
+#define SG_RS_ITEMS 6
 #endif
 constexpr int kRsItems = SG_RS_ITEMS;            // elements per lane per tile
 constexpr int kRsTile = kRsThreads * kRsItems;   // elements per workgroup tile
@@ -125,19 +127,31 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const uint32_t* __res
   for (int d = tid; d < DIG; d += kRsThreads) s_run[d] = hist_scanned[(size_t)d * gridDim.x + blockIdx.x];
   uint64_t b, e;
   rs_range(rs_count(d_count, d_cap), b, e);
-  for (uint64_t base = b; base < e; base += kRsTile) {
+  // a tile's keys and values, loaded while the previous tile is ranked and
+  // written (one workgroup fills the CU, so nothing else would overlap them)
+  uint32_t nk[kRsItems], nv[kRsItems];
+  auto load_tile = [&](uint64_t base) {
     const int n_tile = (int)((e - base) < (uint64_t)kRsTile ? (e - base) : (uint64_t)kRsTile);
-    for (int d = lane; d < DIG; d += 64) s_wc[wave][d] = 0u;
-    uint32_t k[kRsItems], v[kRsItems], rank[kRsItems];
-    // all of the tile's loads first (kept in flight together), then the ranks
 #pragma unroll
     for (int it = 0; it < kRsItems; ++it) {
       const int idx = wave * kRsWaveSpan + it * 64 + lane;
       const bool valid = idx < n_tile;
-      k[it] = valid ? keys_in[base + idx] : 0u;
+      nk[it] = valid ? keys_in[base + idx] : 0u;
       // no value array: the values are the element indices
-      v[it] = valid ? (vals_in ? vals_in[base + idx] : (uint32_t)(base + idx)) : 0u;
+      nv[it] = valid ? (vals_in ? vals_in[base + idx] : (uint32_t)(base + idx)) : 0u;
     }
+  };
+  if (b < e) load_tile(b);
+  for (uint64_t base = b; base < e; base += kRsTile) {
+    const int n_tile = (int)((e - base) < (uint64_t)kRsTile ? (e - base) : (uint64_t)kRsTile);
+    for (int d = lane; d < DIG; d += 64) s_wc[wave][d] = 0u;
+    uint32_t k[kRsItems], v[kRsItems], rank[kRsItems];
+#pragma unroll
+    for (int it = 0; it < kRsItems; ++it) {
+      k[it] = nk[it];
+      v[it] = nv[it];
+    }
+    if (base + kRsTile < e) load_tile(base + kRsTile);
 #pragma unroll
     for (int it = 0; it < kRsItems; ++it) {
       const int idx = wave * kRsWaveSpan + it * 64 + lane;
