@@ -332,6 +332,34 @@ SG_DEV void walk_record(const steepgs_splat* __restrict__ splats, const steepgs_
   me.pad0 = (uint32_t)cams[v].tiles_x;
 }
 
+// One lane's input of the walk: the depth key and record id at its position
+// of the depth order, and the record's first 32 bytes (mean, conic, opacity,
+// tile rectangle).  Loaded two chunks (order) and one chunk (record) ahead.
+struct WalkIn {
+  uint32_t key, r;
+  float4 lo, hi;  // (mean_x, mean_y, conic_a, conic_b), (conic_c, opacity, rect_lo, rect_hi)
+};
+
+SG_DEV void walk_in_order(const uint32_t* __restrict__ skeys, const uint32_t* __restrict__ order, int64_t m,
+                          int64_t c, int lane, WalkIn& w) {
+  // both loads unconditional (no wait on the key before the order load)
+  const int64_t s = c * 64 + lane;
+  w.key = 0xFFFFFFFFu;
+  w.r = 0xFFFFFFFFu;
+  if (s < m) {
+    w.key = skeys[s];
+    w.r = order[s];
+  }
+}
+
+SG_DEV void walk_in_record(const steepgs_splat* __restrict__ splats, WalkIn& w) {
+  if (w.key != 0xFFFFFFFFu) {
+    const float4* p = reinterpret_cast<const float4*>(splats + w.r);
+    w.lo = p[0];
+    w.hi = p[1];
+  }
+}
+
 __global__ void __launch_bounds__(256) k_walk(const steepgs_splat* __restrict__ splats,
                                               const uint32_t* __restrict__ skeys, const uint32_t* __restrict__ order,
                                               int64_t m, int64_t n, const steepgs_camera* __restrict__ cams,
@@ -344,18 +372,47 @@ __global__ void __launch_bounds__(256) k_walk(const steepgs_splat* __restrict__ 
   RectWalkLds& L = s_walk[wave];
   uint32_t* const cnt = s_cnt + wave * 64;
   const int64_t nchunks = (m + 63) / 64;
-  for (int64_t c = (int64_t)blockIdx.x * 4 + wave; c < nchunks; c += (int64_t)gridDim.x * 4) {
+  const int64_t stride = (int64_t)gridDim.x * 4;
+  // the chunk's records gathered while the previous chunk walks, its depth
+  // order positions one chunk earlier still
+  WalkIn cur = {}, nxt = {};
+  int64_t c = (int64_t)blockIdx.x * 4 + wave;
+  walk_in_order(skeys, order, m, c, lane, cur);
+  walk_in_record(splats, cur);
+  walk_in_order(skeys, order, m, c + stride, lane, nxt);
+  for (; c < nchunks; c += stride) {
+    const WalkIn w = cur;
     const int64_t s = c * 64 + lane;
-    uint32_t area = 0, r = 0xFFFFFFFFu;
+    uint32_t area = 0;
+    const uint32_t r = w.r;
     RectRec me = {};
     me.wdt = 1;
     me.a = me.c = 1.f;
-    if (s < m && (skeys[s] != 0xFFFFFFFFu || counts)) r = order[s];
-    if (s < m && skeys[s] != 0xFFFFFFFFu) walk_record(splats, cams, n, r, opt, me, area);  // culled records sort last
-    if (s < m) rects[s] = WalkRect{me.xy0, area ? (me.wdt | ((area / me.wdt) << 16)) : 0u};
-    cnt[lane] = 0u;
+    if (w.key != 0xFFFFFFFFu) {  // culled records sort last
+      steepgs_splat sp;
+      sp.mean_x = w.lo.x;
+      sp.mean_y = w.lo.y;
+      sp.conic_a = w.lo.z;
+      sp.conic_b = w.lo.w;
+      sp.conic_c = w.hi.x;
+      sp.opacity = w.hi.y;
+      sp.rect_lo = __float_as_uint(w.hi.z);
+      sp.rect_hi = __float_as_uint(w.hi.w);
+      area = walk_rect(sp, opt, me);
+      const int v = (int)(r / (uint64_t)n);
+      me.tag0 = r;
+      me.tag1 = (uint32_t)cams[v].tile_offset;
+      me.pad0 = (uint32_t)cams[v].tiles_x;
+    }
     uint32_t aoff;
     const uint32_t atotal = rect_walk_begin(L, lane, area, me, aoff);
+    // the next chunks' loads go out after this chunk's last one (the camera
+    // fields above), so that no wait on this chunk's data waits on them
+    cur = nxt;
+    walk_in_record(splats, cur);
+    walk_in_order(skeys, order, m, c + 2 * stride, lane, nxt);
+    if (s < m) rects[s] = WalkRect{me.xy0, area ? (me.wdt | ((area / me.wdt) << 16)) : 0u};
+    cnt[lane] = 0u;
     uint32_t hits = 0;
     uint64_t mine = 0;  // lane k keeps the ballot of step k
     int carry = 0;
@@ -376,7 +433,7 @@ __global__ void __launch_bounds__(256) k_walk(const steepgs_splat* __restrict__ 
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (counts && r != 0xFFFFFFFFu) counts[r] = cnt[lane];
+    if (counts && s < m) counts[r] = cnt[lane];
     __builtin_amdgcn_wave_barrier();
   }
 }
