@@ -354,6 +354,14 @@ __device__ __noinline__ bool colour_clamped_fp64(const float* __restrict__ param
   return colour_channel_fp64(params, n, i, deg, campos, ch) < 0.0;
 }
 
+// lane k's double, for every lane of the wavefront (k uniform)
+SG_DEV double lane_double(double x, int k) {
+  const uint64_t b = __double_as_longlong(x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, k);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), k);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // fp64 rotation of the normalised quaternion qh = q / |q| and the scales
 // exp(log_scale) of Gaussian i
 SG_DEV void rotation_scales(const float* __restrict__ params, int64_t n, int64_t i, double Rq[3][3], double sc[3],
@@ -400,8 +408,12 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) k
                                                   const double* __restrict__ g2d,
                                                   float* __restrict__ grads, float* __restrict__ S) {
   constexpr int NB = (D + 1) * (D + 1);
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  // threads past n stay (with no visible view) so that every lane of a
+  // wavefront takes part in the per-view lane tables below
+  const int64_t i_raw = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = i_raw < n;
+  const int64_t i = live ? i_raw : n - 1;
+  const int lane = threadIdx.x & 63;
   float pf[3];
   for (int k = 0; k < 3; ++k) pf[k] = params[(STEEPGS_ROW_MEAN + k) * n + i];
   double dp[3] = {0.0, 0.0, 0.0};
@@ -418,7 +430,14 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) k
     for (int k = 0; k < 3 * NB; ++k) dsh[k] = 0.f;
     for (int v0 = 0; v0 < V; v0 += 32) {
       const int nv = min(32, V - v0);
-      const uint32_t vis = visible_views(tiles, n, i, v0, nv);
+      const uint32_t vis = live ? visible_views(tiles, n, i, v0, nv) : 0u;
+      // lane k holds the camera centre of view v0 + k (read per view by readlane)
+      float centre_k[3];
+      {
+        const steepgs_camera& ck = cams[v0 + (lane < nv ? lane : 0)];
+        for (int e = 0; e < 3; ++e)
+          centre_k[e] = -(ck.R[0 + e] * ck.t[0] + ck.R[3 + e] * ck.t[1] + ck.R[6 + e] * ck.t[2]);
+      }
       // the next view's colour gradient is loaded while this one is processed
       double nc[3] = {0.0, 0.0, 0.0};
       auto fetch = [&](int k) {
@@ -437,11 +456,11 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) k
         any = true;
         const steepgs_camera& cam = cams[v];
         float campos[3];
-        for (int e = 0; e < 3; ++e)
-          campos[e] = -(cam.R[0 + e] * cam.t[0] + cam.R[3 + e] * cam.t[1] + cam.R[6 + e] * cam.t[2]);
+        for (int e = 0; e < 3; ++e) campos[e] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(centre_k[e]), k));
         const float dv[3] = {pf[0] - campos[0], pf[1] - campos[1], pf[2] - campos[2]};
-        const float dlen = sqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
-        const float idl = 1.f / dlen;
+        // 1 / |p - c| by the hardware reciprocal square root (1 ulp): the
+        // direction enters the gradients only
+        const float idl = __builtin_amdgcn_rsqf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
         const float dir[3] = {dv[0] * idl, dv[1] * idl, dv[2] * idl};
         float Y[NB];
         sh_eval<float>(D, dir[0], dir[1], dir[2], Y);
@@ -495,7 +514,15 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) k
   double S3[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int v0 = 0; v0 < V; v0 += 32) {
     const int nv = min(32, V - v0);
-    const uint32_t vis = visible_views(tiles, n, i, v0, nv);
+    const uint32_t vis = live ? visible_views(tiles, n, i, v0, nv) : 0u;
+    // lane k holds the frustum-guard limits of view v0 + k (the projection's
+    // expression, so the clamp decisions match); read per view by readlane
+    double lim_k[2] = {0.0, 0.0};
+    if (opt.frustum_guard > 0.f) {
+      const steepgs_camera& ck = cams[v0 + (lane < nv ? lane : 0)];
+      lim_k[0] = (double)opt.frustum_guard * (0.5 * ck.width / (double)ck.fx);
+      lim_k[1] = (double)opt.frustum_guard * (0.5 * ck.height / (double)ck.fy);
+    }
     // the next view's moments and footprint axis are loaded while this one
     // is processed
     double nm[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -544,8 +571,7 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) k
         gy = pcd[1] / pcd[2];
         gx_free = gy_free = true;
         if (opt.frustum_guard > 0.f) {
-          const double limx = (double)opt.frustum_guard * (0.5 * cam.width / (double)cam.fx);
-          const double limy = (double)opt.frustum_guard * (0.5 * cam.height / (double)cam.fy);
+          const double limx = lane_double(lim_k[0], k), limy = lane_double(lim_k[1], k);
           if (gx < -limx) { gx = -limx; gx_free = false; }
           if (gx > limx) { gx = limx; gx_free = false; }
           if (gy < -limy) { gy = -limy; gy_free = false; }
@@ -559,8 +585,11 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) k
         J[1][0] = 0.0; J[1][1] = fy; J[1][2] = 0.0;
       }
       double P[2][3];
-      for (int a = 0; a < 2; ++a)
-        for (int c = 0; c < 3; ++c) P[a][c] = J[a][0] * W[c] + J[a][1] * W[3 + c] + J[a][2] * W[6 + c];
+      // P = J W without the products by J's structural zeros (J01 = J10 = 0)
+      for (int c = 0; c < 3; ++c) {
+        P[0][c] = J[0][0] * W[c] + J[0][2] * W[6 + c];
+        P[1][c] = J[1][1] * W[3 + c] + J[1][2] * W[6 + c];
+      }
       const double Sig[3][3] = {{Sg[0], Sg[1], Sg[2]}, {Sg[1], Sg[3], Sg[4]}, {Sg[2], Sg[4], Sg[5]}};
       // Pi(Sigma) and its inverse (the conic)
       double PS[2][3];
@@ -619,9 +648,12 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) k
           dpc[1] -= GJ[1][2] * fy * iz2;
           dpc[2] += GJ[1][2] * fy * pcy * iz2 * iz;
         }
-        const double Je[2][3] = {{fx * iz, 0.0, -fx * pcx * iz2}, {0.0, fy * iz, -fy * pcy * iz2}};
-        for (int a = 0; a < 2; ++a)
-          for (int c = 0; c < 3; ++c) Pe[a][c] = Je[a][0] * W[c] + Je[a][2] * W[6 + c] + Je[a][1] * W[3 + c];
+        // exact Jacobian of the projected mean times W (its zeros left out)
+        const double je00 = fx * iz, je02 = -fx * pcx * iz2, je11 = fy * iz, je12 = -fy * pcy * iz2;
+        for (int c = 0; c < 3; ++c) {
+          Pe[0][c] = je00 * W[c] + je02 * W[6 + c];
+          Pe[1][c] = je11 * W[3 + c] + je12 * W[6 + c];
+        }
       } else {
         dpc[0] += gmx * fx;
         dpc[1] += gmy * fy;
@@ -629,7 +661,7 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) k
           for (int c = 0; c < 3; ++c) Pe[a][c] = P[a][c];
       }
       for (int c = 0; c < 3; ++c) dp[c] += W[c] * dpc[0] + W[3 + c] * dpc[1] + W[6 + c] * dpc[2];
-      dop += m0 / o;
+      dop += m0;  // sum over views of o dL/do, divided by o once
 
       // splitting matrix: S2D = A M A - m0 A, M = m2
       const double M[2][2] = {{m2xx, m2xy}, {m2xy, m2yy}};
@@ -679,7 +711,7 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) k
   for (int k = 0; k < 3; ++k) gp[(STEEPGS_ROW_MEAN + k) * n] += (float)dp[k];
   for (int k = 0; k < 3; ++k) gp[(STEEPGS_ROW_LOG_SCALE + k) * n] += (float)dls[k];
   for (int k = 0; k < 4; ++k) gp[(STEEPGS_ROW_QUAT + k) * n] += (float)((dq[k] - qh[k] * qd) / qn);
-  gp[STEEPGS_ROW_OPACITY * n] += (float)(dop * o * (1.0 - o));
+  gp[STEEPGS_ROW_OPACITY * n] += (float)(dop * (1.0 - o));  // dL/do o (1 - o), dL/do = dop / o
   if (S)
     for (int k = 0; k < 6; ++k) S[k * n + i] += (float)S3[k];
 }
