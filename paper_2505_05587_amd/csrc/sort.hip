@@ -236,8 +236,8 @@ struct LoadU32 {
 
 template <int BITS>
 static void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, const uint64_t* d_count,
-                       const uint64_t* d_cap, int shift, int b, uint32_t* hist, uint32_t* hist_partials,
-                       hipStream_t st, hipError_t& err) {
+                       const uint64_t* d_cap, uint64_t max_count, int shift, int b, uint32_t* hist,
+                       uint32_t* hist_partials, hipStream_t st, hipError_t& err) {
   // as many workgroups as are resident together (LDS and registers), capped
   // at kRsGrid, so that no second partial round follows the first
   static int per_cu = 0;  // same code object on every device
@@ -248,6 +248,10 @@ static void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
   }
   int grid = device_cu_count() * per_cu;
   if (grid > kRsGrid) grid = kRsGrid;
+  // no more workgroups than tiles of the largest possible input (small
+  // inputs: fewer histogram rows to clear and scan)
+  const uint64_t tiles = (max_count + kRsTile - 1) / kRsTile;
+  if ((uint64_t)grid > tiles) grid = tiles > 0 ? (int)tiles : 1;
   hipLaunchKernelGGL(k_rs_hist<BITS>, dim3(grid), dim3(kRsThreads), 0, st, kin, d_count, d_cap, shift, b, hist);
   const int64_t hn = (int64_t)(1 << BITS) * grid;
   err = exclusive_scan<LoadU32, uint32_t, uint32_t>(LoadU32{hist}, hn, hist, hist_partials, st);
@@ -262,8 +266,8 @@ static void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
 // first_keys, the first pass reads its keys there (not from pair `start`)
 // and takes the element indices as values.
 static int radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int start,
-                            const uint64_t* d_count, const uint64_t* d_cap, int total_bits, uint32_t* hist,
-                            uint32_t* hist_partials, hipStream_t st, hipError_t& err,
+                            const uint64_t* d_count, const uint64_t* d_cap, uint64_t max_count, int total_bits,
+                            uint32_t* hist, uint32_t* hist_partials, hipStream_t st, hipError_t& err,
                             const uint32_t* first_keys = nullptr) {
   const int npass = (total_bits + kRsMaxBits - 1) / kRsMaxBits;
   const int bits = (total_bits + npass - 1) / npass;
@@ -281,9 +285,9 @@ static int radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* 
     uint32_t* kout = cur ? k0 : k1;
     uint32_t* vout = cur ? v0 : v1;
     if (b <= 8)
-      radix_pass<8>(kin, vin, kout, vout, d_count, d_cap, shift, b, hist, hist_partials, st, err);
+      radix_pass<8>(kin, vin, kout, vout, d_count, d_cap, max_count, shift, b, hist, hist_partials, st, err);
     else
-      radix_pass<9>(kin, vin, kout, vout, d_count, d_cap, shift, b, hist, hist_partials, st, err);
+      radix_pass<9>(kin, vin, kout, vout, d_count, d_cap, max_count, shift, b, hist, hist_partials, st, err);
     if (err != hipSuccess) return cur;
     cur ^= 1;
     shift += b;
@@ -643,8 +647,8 @@ extern "C" steepgs_status steepgs_sort(const steepgs_splat* d_splats, const uint
   // 1. depth order of the records (culled last), on the projection's keys
   hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, w.counters, (uint64_t)m);
   hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, w.counters + 1, (uint64_t)capacity);
-  const int where = radix_sort_pairs(w.dkA, w.dvA, w.dkB, w.dvB, 0, w.counters, nullptr, 32, w.hist, w.hist_partials,
-                                     st, err, d_depth_keys);
+  const int where = radix_sort_pairs(w.dkA, w.dvA, w.dkB, w.dvB, 0, w.counters, nullptr, (uint64_t)m, 32, w.hist,
+                                     w.hist_partials, st, err, d_depth_keys);
   if (err != hipSuccess) return STEEPGS_ERR_HIP;
   const uint32_t* order = where ? w.dvB : w.dvA;
   const uint32_t* skeys = where ? w.dkB : w.dkA;
@@ -670,8 +674,8 @@ extern "C" steepgs_status steepgs_sort(const steepgs_splat* d_splats, const uint
                        d_cams, *opts, d_num_instances, capacity, ek, ev);
   if (capacity > 0) {
     // 3. stable sort by tile (equal tiles keep the depth order)
-    int fin = radix_sort_pairs(w.tkA, d_vals, w.tkB, w.ivB, start, d_num_instances, w.counters + 1, tile_bits, w.hist,
-                               w.hist_partials, st, err);
+    int fin = radix_sort_pairs(w.tkA, d_vals, w.tkB, w.ivB, start, d_num_instances, w.counters + 1, capacity,
+                               tile_bits, w.hist, w.hist_partials, st, err);
     if (err != hipSuccess) return STEEPGS_ERR_HIP;
     if (fin != 0) return STEEPGS_ERR_HIP;  // cannot happen: start chosen so the result lands in d_vals
     // 4. per-tile ranges and the optional 64-bit keys

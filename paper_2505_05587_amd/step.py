@@ -42,6 +42,9 @@ class _Densify:
         return self.out[:, :n_out]
 
 
+FORK_CLEARS_RECORDS = 1 << 22
+
+
 class BatchedStep:
     """theta_dim 3: the splitting matrix over the position (the paper's);
     6: over (position, log-scales), S [21, n] and the dim-6 split."""
@@ -60,6 +63,9 @@ class BatchedStep:
         self.S = torch.zeros((6 if theta_dim == 3 else 21, n), dtype=torch.float32, device=dev)
         self.dens = _Densify(F, n, dev, theta_dim)
         self.side = torch.cuda.Stream(device=dev)  # default priority
+        # side-stream clears from 2^22 records (a 300 MB slot clear) on: below
+        # that, the graph's cross-stream dependencies cost more than they hide
+        self.fork_clears = cams.V * n >= FORK_CLEARS_RECORDS
         self.graph = None
 
     def prepare(self, headroom: float = 1.1) -> int:
@@ -75,21 +81,27 @@ class BatchedStep:
         r.project(self.params)
         L.steepgs_sort(r.splats, r.tiles, r.n, self.cams.V, self.cams.dev, self.cams.opts, self.cams.total_tiles,
                        None, r.vals, r.capacity, r.ranges, r.num, r.status, r.ws_sort, depth_keys=r.dkeys)
-        # the clears of the backward's accumulators read nothing: they run on a
-        # second stream beside the forward blend (VALU-bound, most of the HBM
-        # bandwidth free) and join before the backward
-        self.side.wait_stream(main)
-        with torch.cuda.stream(self.side):
+        # the clears of the backward's accumulators read nothing: on large
+        # batches they run on a second stream beside the forward blend
+        # (VALU-bound, most of the HBM bandwidth free) and join before the
+        # backward; on small ones the fork and join cost more than they hide
+        if self.fork_clears:
+            self.side.wait_stream(main)
+            with torch.cuda.stream(self.side):
+                self.grads.zero_()
+                self.S.zero_()
+                if self.theta_dim == 3:
+                    r.clear_backward()
+        r.render(self.target)
+        if self.fork_clears:
+            main.wait_stream(self.side)
+        else:
             self.grads.zero_()
             self.S.zero_()
-            if self.theta_dim == 3:
-                r.clear_backward()
-        r.render(self.target)
-        main.wait_stream(self.side)
         if self.theta_dim == 6:
             r.backward6(self.params, self.grads, self.S, target=self.target)
         else:
-            r.backward(self.params, self.grads, self.S, target=self.target, cleared=True)
+            r.backward(self.params, self.grads, self.S, target=self.target, cleared=self.fork_clears)
         self.dens.run(self.params, self.sh_degree, self.S, self.s_scale, self.eps, self.eps_split)
 
     def capture(self):

@@ -27,14 +27,18 @@ def _snapshot(step):
                 new=new.cpu().numpy().copy())
 
 
+@pytest.mark.parametrize("fork", [False, True])
 @pytest.mark.parametrize("kind", ["multiview", "sh3_pinhole"])
-def test_graph_replays_match_eager(kind):
+def test_graph_replays_match_eager(kind, fork):
+    # fork: the accumulators cleared on a second stream beside the forward
+    # blend (the large-batch path), forced on this small scene
     P0, deg, cams, target = scene_small(kind)
-    print(f"\n[case] graph replay kind={kind}", flush=True)
+    print(f"\n[case] graph replay kind={kind} fork={fork}", flush=True)
     dev = torch.device("cuda", 0)
     opts = scenes.opts("3dgs")
     step = BatchedStep(torch.from_numpy(P0).to(dev), deg, CameraBatch(cams, opts, dev),
                        torch.from_numpy(target).to(dev), eps=1e-3, eps_split=-1e-6)
+    step.fork_clears = fork
     step.prepare()
     step.run()
     torch.cuda.synchronize()
