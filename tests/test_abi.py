@@ -87,6 +87,18 @@ def test_bad_arguments_rejected_on_host():
                                 None) == L.ERR_INVALID_ARG
     assert lib.steepgs_densify6(fake, 10, 0, fake, 1.0, 0.01, 0.0, fake, 20, fake, None, None, None, fake, None, 0,
                                 None) == L.ERR_WORKSPACE
+    # the backward's clear on its own, and the backward that skips it
+    assert lib.steepgs_render_bwd_clear(-1, 1, fake, 1 << 20, None) == L.ERR_INVALID_ARG
+    assert lib.steepgs_render_bwd_clear(10, 0, fake, 1 << 20, None) == L.ERR_INVALID_ARG
+    assert lib.steepgs_render_bwd_clear(10, 1, None, 1 << 20, None) == L.ERR_INVALID_ARG
+    assert lib.steepgs_render_bwd_clear(10, 1, fake, 16, None) == L.ERR_WORKSPACE
+    assert lib.steepgs_render_bwd_clear(0, 1, fake, 0, None) == L.OK  # nothing to clear
+    assert lib.steepgs_render_bwd_split_cleared(fake, 10, 0, fake, 1, C.byref(o), fake, fake, fake, fake, 4, 64, fake,
+                                                fake, fake, None, fake, fake, fake, None, fake, 16,
+                                                None) == L.ERR_WORKSPACE
+    assert lib.steepgs_render_bwd_split_cleared(fake, 10, 4, fake, 1, C.byref(o), fake, fake, fake, fake, 4, 64, fake,
+                                                fake, fake, None, fake, fake, fake, None, fake, 1 << 30,
+                                                None) == L.ERR_INVALID_ARG
     assert lib.steepgs_status_string(2) == b"output capacity exceeded"
 
 

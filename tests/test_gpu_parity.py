@@ -298,3 +298,42 @@ def test_saturated_opacity(oracle):
     assert np.isfinite(g["grads"]).all() and np.isfinite(g["S6"]).all()
     vref = checked_reference(oracle, P, 0, cams, opts, g, target=target)
     check_against(g, vref, cams, "saturated")
+
+
+def test_colour_clamp_band(oracle):
+    # colour channels placed within the 1e-5 band around the clamp max(0, .)
+    # (the DC coefficient chosen so that 1/2 + sum sh_k Y_k lands at +-delta):
+    # the projection's fp32 colour flags them and its fp64 evaluation decides
+    # and values them, the projection backward re-takes the same fp64
+    # decision.  Records: a channel is 0 exactly where the oracle clamps it,
+    # else within 1e-7 of the oracle's value; gradients and S at the plain bar.
+    P, deg, cams, target = scene_small("sh3_pinhole")
+    P = P.copy()
+    n, NB = P.shape[1], (deg + 1) ** 2
+    print(f"\n[case] colour clamp band n={n} deg={deg}", flush=True)
+    centre = -(cams.R[0].astype(np.float64).T @ cams.t[0].astype(np.float64))
+    d = P[0:3].T.astype(np.float64) - centre
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    Y = oracle.sh_basis(deg, d)
+    rng = np.random.default_rng(7)
+    idx = rng.choice(n, 96, replace=False)
+    deltas = [2e-6, -2e-6, 5e-8, -5e-8, 0.0, 8e-6, -8e-6, 1e-9]
+    for j, i in enumerate(idx):
+        for ch in range(3):
+            delta = deltas[(j + ch) % len(deltas)]
+            rest = 0.5 + sum(float(P[11 + 3 * k + ch, i]) * Y[i, k] for k in range(1, NB))
+            P[11 + ch, i] = np.float32((delta - rest) / Y[i, 0])
+    opts = scenes.opts("3dgs")
+    g = run_gpu(P, deg, cams, opts, target=target)
+    pr = oracle.project(P, deg, cams, opts)
+    vis = pr["visible"][idx]
+    raw = pr["rgb_raw"][idx][vis]
+    assert (np.abs(raw) < 1e-5).sum() >= 100, "too few channels inside the band"
+    got = g["splats"][idx][vis][:, 8:11].astype(np.float64)
+    want = pr["rgb"][idx][vis]
+    np.testing.assert_array_equal(got == 0, want == 0)
+    assert (np.abs(got - want) <= 1e-7).all()
+    vref = checked_reference(oracle, P, deg, cams, opts, g, target=target)
+    st = check_against(g, vref, cams, "colour clamp band")
+    assert st["pix_excl"] + st["pix_soft_dev"] < 1e-3
+    assert st["gauss_excl"] + st["gauss_soft_dev"] < 1e-2
