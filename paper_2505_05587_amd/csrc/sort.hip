@@ -114,7 +114,8 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const uint32_t* __res
                                                            uint32_t* __restrict__ vals_out,
                                                            const uint64_t* __restrict__ d_count,
                                                            const uint64_t* __restrict__ d_cap, int shift, int bits,
-                                                           const uint32_t* __restrict__ hist_scanned) {
+                                                           const uint32_t* __restrict__ hist_scanned,
+                                                           uint32_t* __restrict__ ranges) {
   constexpr int DIG = 1 << BITS;
   constexpr int PER = DIG / kRsThreads > 0 ? DIG / kRsThreads : 1;  // digits per thread in the tile scan
   __shared__ uint32_t s_key[kRsTile], s_val[kRsTile];
@@ -219,8 +220,17 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const uint32_t* __res
         const uint32_t key = s_key[i];
         const uint32_t d = (key >> shift) & mask;
         const uint32_t g = s_run[d] + ((uint32_t)i - s_start[d]);
-        keys_out[g] = key;
+        if (keys_out) keys_out[g] = key;
         vals_out[g] = s_val[i];
+        if (ranges) {
+          // last pass: the key's [begin, end) from the boundaries of its run
+          // in this tile; at the ends of a digit run the neighbour lies in
+          // another tile, so every boundary is an atomic maximum (begin
+          // stored complemented: the largest ~g is the smallest g)
+          const uint32_t rs = s_start[d], re = rs + s_cnt[d];
+          if ((uint32_t)i == rs || s_key[i - 1] != key) atomicMax(&ranges[2 * (size_t)key], ~g);
+          if ((uint32_t)i + 1 == re || s_key[i + 1] != key) atomicMax(&ranges[2 * (size_t)key + 1], g + 1u);
+        }
       }
     }
     __syncthreads();
@@ -237,7 +247,7 @@ struct LoadU32 {
 template <int BITS>
 static void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, const uint64_t* d_count,
                        const uint64_t* d_cap, uint64_t max_count, int shift, int b, uint32_t* hist,
-                       uint32_t* hist_partials, hipStream_t st, hipError_t& err) {
+                       uint32_t* hist_partials, hipStream_t st, hipError_t& err, uint32_t* ranges) {
   // as many workgroups as are resident together (LDS and registers), capped
   // at kRsGrid, so that no second partial round follows the first
   static int per_cu = 0;  // same code object on every device
@@ -257,7 +267,7 @@ static void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
   err = exclusive_scan<LoadU32, uint32_t, uint32_t>(LoadU32{hist}, hn, hist, hist_partials, st);
   if (err != hipSuccess) return;
   hipLaunchKernelGGL(k_rs_scatter<BITS>, dim3(grid), dim3(kRsThreads), 0, st, kin, vin, kout, vout, d_count, d_cap,
-                     shift, b, hist);
+                     shift, b, hist, ranges);
 }
 
 // sorts (keys, vals) of `count` (device) elements on bits [0, total_bits),
@@ -268,7 +278,8 @@ static void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
 static int radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int start,
                             const uint64_t* d_count, const uint64_t* d_cap, uint64_t max_count, int total_bits,
                             uint32_t* hist, uint32_t* hist_partials, hipStream_t st, hipError_t& err,
-                            const uint32_t* first_keys = nullptr) {
+                            const uint32_t* first_keys = nullptr, uint32_t* ranges = nullptr,
+                            bool last_keys = true) {
   const int npass = (total_bits + kRsMaxBits - 1) / kRsMaxBits;
   const int bits = (total_bits + npass - 1) / npass;
   int cur = start;
@@ -284,10 +295,14 @@ static int radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* 
     }
     uint32_t* kout = cur ? k0 : k1;
     uint32_t* vout = cur ? v0 : v1;
+    // the last pass may record the key ranges and skip writing the keys
+    const bool last = p + 1 == npass;
+    uint32_t* rng = last ? ranges : nullptr;
+    if (last && !last_keys) kout = nullptr;
     if (b <= 8)
-      radix_pass<8>(kin, vin, kout, vout, d_count, d_cap, max_count, shift, b, hist, hist_partials, st, err);
+      radix_pass<8>(kin, vin, kout, vout, d_count, d_cap, max_count, shift, b, hist, hist_partials, st, err, rng);
     else
-      radix_pass<9>(kin, vin, kout, vout, d_count, d_cap, max_count, shift, b, hist, hist_partials, st, err);
+      radix_pass<9>(kin, vin, kout, vout, d_count, d_cap, max_count, shift, b, hist, hist_partials, st, err, rng);
     if (err != hipSuccess) return cur;
     cur ^= 1;
     shift += b;
@@ -529,39 +544,14 @@ __global__ void k_instance_total(const uint64_t* __restrict__ total, uint64_t ca
   *d_status = (K > capacity) ? (int32_t)STEEPGS_ERR_CAPACITY : (int32_t)STEEPGS_OK;
 }
 
-// per-tile [begin, end) of the sorted list: four consecutive entries per
-// thread (one 16-byte load) and their two neighbours
-constexpr int kRangesPer = 4;
-__global__ void k_ranges(const uint32_t* __restrict__ tkeys, const uint64_t* __restrict__ d_num, uint64_t capacity,
-                         uint32_t* __restrict__ ranges) {
-  const uint64_t K = *d_num;
-  if (K > capacity) return;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * kRangesPer;
-  for (uint64_t s0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRangesPer; s0 < K; s0 += stride) {
-    uint32_t t[kRangesPer];
-    if (s0 + kRangesPer <= K) {
-      const uint4 q = *reinterpret_cast<const uint4*>(tkeys + s0);
-      t[0] = q.x;
-      t[1] = q.y;
-      t[2] = q.z;
-      t[3] = q.w;
-    } else {
-#pragma unroll
-      for (int j = 0; j < kRangesPer; ++j) t[j] = s0 + j < K ? tkeys[s0 + j] : 0u;
-    }
-    const bool has_prev = s0 > 0;
-    const uint32_t prev = has_prev ? tkeys[s0 - 1] : 0u;
-    const bool has_next = s0 + kRangesPer < K;
-    const uint32_t next = has_next ? tkeys[s0 + kRangesPer] : 0u;
-#pragma unroll
-    for (int j = 0; j < kRangesPer; ++j) {
-      const uint64_t s = s0 + j;
-      if (s >= K) break;
-      const bool first = j == 0 ? (!has_prev || prev != t[0]) : t[j - 1] != t[j];
-      const bool last = j == kRangesPer - 1 ? (!has_next || next != t[j]) : (s + 1 == K || t[j + 1] != t[j]);
-      if (first) ranges[2 * (size_t)t[j]] = (uint32_t)s;
-      if (last) ranges[2 * (size_t)t[j] + 1] = (uint32_t)(s + 1);
-    }
+// per-tile [begin, end) of the sorted list: the last tile pass leaves
+// (~begin, end) for every tile it saw (~begin >= 1, as begin < 2^32 - 1) and
+// the zero fill (0, 0) for the others
+__global__ void k_ranges_fix(uint32_t* __restrict__ ranges, int64_t tiles) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < tiles) {
+    const uint32_t b = ranges[2 * t];
+    ranges[2 * t] = b ? ~b : 0u;
   }
 }
 
@@ -674,13 +664,15 @@ extern "C" steepgs_status steepgs_sort(const steepgs_splat* d_splats, const uint
                        d_cams, *opts, d_num_instances, capacity, ek, ev);
   if (capacity > 0) {
     // 3. stable sort by tile (equal tiles keep the depth order)
+    // (the last pass records each tile's range; the sorted tile ids are
+    // written only for the optional 64-bit keys)
     int fin = radix_sort_pairs(w.tkA, d_vals, w.tkB, w.ivB, start, d_num_instances, w.counters + 1, capacity,
-                               tile_bits, w.hist, w.hist_partials, st, err);
+                               tile_bits, w.hist, w.hist_partials, st, err, nullptr, d_tile_ranges, d_keys != nullptr);
     if (err != hipSuccess) return STEEPGS_ERR_HIP;
     if (fin != 0) return STEEPGS_ERR_HIP;  // cannot happen: start chosen so the result lands in d_vals
-    // 4. per-tile ranges and the optional 64-bit keys
-    hipLaunchKernelGGL(k_ranges, dim3((unsigned)ceil_div((int64_t)capacity, 256 * kRangesPer)), dim3(256), 0, st, w.tkA,
-                       d_num_instances, capacity, d_tile_ranges);
+    // 4. per-tile ranges from the last pass's (~begin, end), and the optional 64-bit keys
+    hipLaunchKernelGGL(k_ranges_fix, dim3((unsigned)ceil_div((int64_t)total_tiles, 256)), dim3(256), 0, st,
+                       d_tile_ranges, (int64_t)total_tiles);
     if (d_keys)
       hipLaunchKernelGGL(k_keys64, dim3(2048), dim3(256), 0, st, w.tkA, d_vals, d_depth_keys, d_num_instances, capacity,
                          d_keys);
